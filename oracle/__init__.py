@@ -1,0 +1,271 @@
+"""FP64 CPU oracle (test infrastructure only).
+
+Only the tests, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` may import this
+package.  It loads ``liboracle`` (built from ``ffrt_oracle.cpp`` by :func:`build`) and exposes numpy-level
+wrappers.  It does not import the HIP package: a problem is any object with the attribute layout of
+``Problem`` (lens / source / detector / options groups), read here by name.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ffrt_oracle.cpp")
+_LIB = os.path.join(_HERE, "libffrt_oracle.so")
+
+HIT, MISS_ENTRY, SIDE_WALL, TIR, OFF_SCREEN = 0, 1, 2, 3, 4
+
+
+def build():
+    """Compile the oracle with the host C++ compiler (no GPU code)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-o", _LIB, _SRC]
+    subprocess.run(cmd, check=True, cwd=_HERE)
+
+
+class OrcProblem(ctypes.Structure):
+    _fields_ = [
+        ("n_lens", ctypes.c_double), ("r_x", ctypes.c_double), ("r_y", ctypes.c_double),
+        ("z_in", ctypes.c_double), ("delta_min", ctypes.c_double),
+        ("p", ctypes.c_int32), ("q", ctypes.c_int32), ("n_u", ctypes.c_int32), ("n_v", ctypes.c_int32),
+        ("kind", ctypes.c_int32), ("grid_u", ctypes.c_int32), ("grid_v", ctypes.c_int32),
+        ("jitter", ctypes.c_int32),
+        ("pos_x", ctypes.c_double), ("pos_y", ctypes.c_double), ("pos_z", ctypes.c_double),
+        ("half_angle", ctypes.c_double),
+        ("emit_nx", ctypes.c_int32), ("emit_ny", ctypes.c_int32),
+        ("emit_wx", ctypes.c_double), ("emit_wy", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("n_x", ctypes.c_int32), ("n_y", ctypes.c_int32),
+        ("R_x", ctypes.c_double), ("R_y", ctypes.c_double), ("z_screen", ctypes.c_double),
+        ("alpha", ctypes.c_double),
+        ("nu_x", ctypes.c_int32), ("nu_y", ctypes.c_int32), ("ghost", ctypes.c_int32),
+        ("fresnel", ctypes.c_int32), ("pad_", ctypes.c_int32),
+    ]
+
+
+class OrcStats(ctypes.Structure):
+    _fields_ = [("flux_on_screen", ctypes.c_double)] + [
+        (n, ctypes.c_int64) for n in
+        ("n_rays", "n_hit", "n_miss_entry", "n_side_wall", "n_tir", "n_off_screen", "n_marginal")
+    ]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER
+        dp, i64p = P(ctypes.c_double), P(ctypes.c_int64)
+        pp = P(OrcProblem)
+        sig = {
+            "orc_num_rays": (ctypes.c_int64, [pp]),
+            "orc_image_size": (None, [pp, P(ctypes.c_int32), P(ctypes.c_int32)]),
+            "orc_knots": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, dp]),
+            "orc_basis_all": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, dp]),
+            "orc_surface": (ctypes.c_int, [pp, dp, ctypes.c_double, ctypes.c_double, dp]),
+            "orc_samples": (ctypes.c_int, [pp, i64p, ctypes.c_int64, dp]),
+            "orc_refract": (ctypes.c_int, [dp, dp, ctypes.c_double, dp]),
+            "orc_schlick": (ctypes.c_double, [ctypes.c_double, ctypes.c_double]),
+            "orc_splat_one": (ctypes.c_int, [pp, ctypes.c_double, ctypes.c_double, dp]),
+            "orc_trace_rays": (ctypes.c_int, [pp, dp, i64p, ctypes.c_int64, dp]),
+            "orc_forward": (ctypes.c_int, [pp, dp, dp, P(OrcStats), dp, ctypes.c_int32]),
+            "orc_loss": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, dp, dp, dp, dp]),
+            "orc_grad": (ctypes.c_int, [pp, dp, dp, dp, dp, dp, dp, ctypes.c_int32]),
+            "orc_grad_split": (ctypes.c_int, [pp, dp, dp, ctypes.c_double, dp, dp, dp, ctypes.c_int32]),
+            "orc_jvp": (ctypes.c_int, [pp, dp, dp, dp, ctypes.c_int32]),
+            "orc_adam": (ctypes.c_int, [ctypes.c_int64, dp, dp, dp, dp, ctypes.c_int64, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_double]),
+            "orc_rng": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def to_struct(prob):
+    """Convert a problem description (grouped attributes) to the oracle's flat struct."""
+    L, S, D, O = prob.lens, prob.source, prob.detector, prob.options
+    s = OrcProblem()
+    s.n_lens, s.r_x, s.r_y, s.z_in, s.delta_min = L.n_lens, L.r_x, L.r_y, L.z_in, L.delta_min
+    s.p, s.q, s.n_u, s.n_v = L.p, L.q, L.n_u, L.n_v
+    s.kind, s.grid_u, s.grid_v, s.jitter = S.kind, S.grid_u, S.grid_v, S.jitter
+    s.pos_x, s.pos_y, s.pos_z = S.pos
+    s.half_angle = S.half_angle
+    s.emit_nx, s.emit_ny, s.emit_wx, s.emit_wy = S.emit_nx, S.emit_ny, S.emit_wx, S.emit_wy
+    s.seed = S.seed
+    s.n_x, s.n_y, s.R_x, s.R_y = D.n_x, D.n_y, D.R_x, D.R_y
+    s.z_screen, s.alpha, s.nu_x, s.nu_y, s.ghost = D.z_screen, D.alpha, D.nu_x, D.nu_y, D.ghost
+    s.fresnel = O.fresnel
+    return s
+
+
+def num_rays(prob):
+    s = to_struct(prob)
+    n = lib().orc_num_rays(ctypes.byref(s))
+    if n < 0:
+        raise ValueError("invalid problem")
+    return n
+
+
+def image_size(prob):
+    s = to_struct(prob)
+    nx, ny = ctypes.c_int32(), ctypes.c_int32()
+    lib().orc_image_size(ctypes.byref(s), ctypes.byref(nx), ctypes.byref(ny))
+    return nx.value, ny.value
+
+
+def knots(p, n):
+    U = np.zeros(n + p + 1)
+    assert lib().orc_knots(p, n, _dp(U)) == 0
+    return U
+
+
+def basis_all(p, n, u, der=0):
+    out = np.zeros(n)
+    assert lib().orc_basis_all(p, n, float(u), der, _dp(out)) == 0
+    return out
+
+
+def surface(prob, Pz, x, y):
+    s = to_struct(prob)
+    P = _f64(Pz).ravel()
+    out = np.zeros(6)
+    assert lib().orc_surface(ctypes.byref(s), _dp(P), float(x), float(y), _dp(out)) == 0
+    return out
+
+
+def samples(prob, ids):
+    s = to_struct(prob)
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    out = np.zeros((len(ids), 4))
+    assert lib().orc_samples(ctypes.byref(s), ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                             len(ids), _dp(out)) == 0
+    return out
+
+
+def refract(d, nrm, eta):
+    d, nrm = _f64(d), _f64(nrm)
+    out = np.zeros(3)
+    tir = lib().orc_refract(_dp(d), _dp(nrm), float(eta), _dp(out))
+    return None if tir else out
+
+
+def schlick(c, n_lens):
+    return lib().orc_schlick(float(c), float(n_lens))
+
+
+def splat_one(prob, X, Y):
+    s = to_struct(prob)
+    nx, ny = image_size(prob)
+    img = np.zeros((nx, ny))
+    assert lib().orc_splat_one(ctypes.byref(s), float(X), float(Y), _dp(img)) == 0
+    return img
+
+
+def trace_rays(prob, Pz, ids):
+    """Per-ray {status, X, Y, w, u, v, t, marginal} as an (n, 8) array."""
+    s = to_struct(prob)
+    P = _f64(Pz).ravel()
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    out = np.zeros((len(ids), 8))
+    assert lib().orc_trace_rays(ctypes.byref(s), _dp(P), ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                len(ids), _dp(out)) == 0
+    return out
+
+
+def forward(prob, Pz, threads=0, with_mask=False):
+    """Irradiance image (n_x, n_y), stats dict, and (optionally) the marginal-ray pixel mask."""
+    s = to_struct(prob)
+    P = _f64(Pz).ravel()
+    nx, ny = image_size(prob)
+    img = np.zeros((nx, ny))
+    st = OrcStats()
+    mask = np.zeros((nx, ny)) if with_mask else None
+    rc = lib().orc_forward(ctypes.byref(s), _dp(P), _dp(img), ctypes.byref(st),
+                           _dp(mask) if with_mask else None, threads)
+    if rc:
+        raise RuntimeError(f"orc_forward failed: {rc}")
+    if with_mask:
+        return img, st.as_dict(), mask.astype(bool)
+    return img, st.as_dict()
+
+
+def loss(irr, target):
+    irr, target = _f64(irr), _f64(target)
+    nx, ny = irr.shape
+    L = ctypes.c_double()
+    g = np.zeros_like(irr)
+    rc = lib().orc_loss(nx, ny, _dp(irr), _dp(target), ctypes.byref(L), _dp(g))
+    if rc:
+        raise RuntimeError(f"orc_loss failed: {rc}")
+    return L.value, g
+
+
+def grad(prob, Pz, target, threads=0):
+    """(loss, dL/dP [n_u, n_v], irradiance, dL/dI)."""
+    s = to_struct(prob)
+    P = _f64(Pz)
+    T = _f64(target)
+    nx, ny = image_size(prob)
+    g = np.zeros(P.shape)
+    irr = np.zeros((nx, ny))
+    G = np.zeros((nx, ny))
+    L = ctypes.c_double()
+    rc = lib().orc_grad(ctypes.byref(s), _dp(P), _dp(T), ctypes.byref(L), _dp(g), _dp(irr), _dp(G), threads)
+    if rc:
+        raise RuntimeError(f"orc_grad failed: {rc}")
+    return L.value, g, irr, G
+
+
+def grad_split(prob, Pz, target, k_min, threads=0):
+    """(loss, dL/dP from well-conditioned rays, dL/dP from rays with |Snell discriminant| < k_min)."""
+    s = to_struct(prob)
+    P, T = _f64(Pz), _f64(target)
+    g = np.zeros(P.shape)
+    gi = np.zeros(P.shape)
+    L = ctypes.c_double()
+    rc = lib().orc_grad_split(ctypes.byref(s), _dp(P), _dp(T), float(k_min), ctypes.byref(L), _dp(g),
+                              _dp(gi), threads)
+    if rc:
+        raise RuntimeError(f"orc_grad_split failed: {rc}")
+    return L.value, g, gi
+
+
+def jvp(prob, Pz, v, threads=0):
+    s = to_struct(prob)
+    P, V = _f64(Pz), _f64(v)
+    nx, ny = image_size(prob)
+    dI = np.zeros((nx, ny))
+    assert lib().orc_jvp(ctypes.byref(s), _dp(P), _dp(V), _dp(dI), threads) == 0
+    return dI
+
+
+def adam(P, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step in place on float64 arrays (t = new step count)."""
+    for a in (P, g, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    assert lib().orc_adam(P.size, _dp(P), _dp(g), _dp(m), _dp(v), t, lr, beta1, beta2, eps) == 0
+
+
+def rng(seed, stream, index):
+    return lib().orc_rng(seed, stream, index)

@@ -1,0 +1,933 @@
+// FP64 CPU oracle for differentiable non-sequential ray tracing through a plano-freeform B-spline lens.
+//
+// TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the CPU-baseline leg of the benchmark.
+// It shares no code with the HIP library.  Every step follows the paper (de Koning et al. 2023) in its
+// order and notation; where the paper is silent or garbled the reading taken is stated at the step.
+//
+// Structure of one ray (sec. 2.2 - 2.3):
+//   sample (sec. 2.2.1) -> [point sources: flat entry face, refraction air->glass]
+//   -> freeform hit (collimated: sampled on the surface; point: smallest root of f(t), sec. 2.2.1 eq. for f)
+//   -> exit refraction glass->air, TIR dropped (sec. 2.2), Schlick weight (sec. 2.3)
+//   -> screen plane (sec. 2.3) -> Gaussian reconstruction filter (sec. 2.3, eq. for f_i^x)
+// The gradient (sec. 2.5, back-propagated in the paper) is the same pathwise derivative computed here in
+// forward mode: the ray is re-evaluated with dual numbers whose tangents are the control points of the hit
+// knot-span product.  At a point-source hit the root t is differentiated by Newton steps taken in dual
+// arithmetic from the converged root (implicit function theorem).
+#include "oracle.h"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <thread>
+#include <vector>
+
+namespace {
+
+constexpr int MAXDEG = 5;
+constexpr int MAXT = (MAXDEG + 1) * (MAXDEG + 1);
+
+// ---------------------------------------------------------------------------------------------------
+// Dual numbers: value plus tl_nt tangents (tl_nt is fixed for the duration of one ray).
+// ---------------------------------------------------------------------------------------------------
+thread_local int tl_nt = 0;
+
+struct NoInit {};
+
+struct Dual {
+    double v;
+    double d[MAXT];
+    Dual() : v(0.0) { for (int k = 0; k < tl_nt; ++k) d[k] = 0.0; }
+    Dual(double x) : v(x) { for (int k = 0; k < tl_nt; ++k) d[k] = 0.0; }
+    Dual(double x, NoInit) : v(x) {}
+};
+
+inline Dual operator+(const Dual& a, const Dual& b) { Dual r(a.v + b.v, NoInit{}); for (int k = 0; k < tl_nt; ++k) r.d[k] = a.d[k] + b.d[k]; return r; }
+inline Dual operator-(const Dual& a, const Dual& b) { Dual r(a.v - b.v, NoInit{}); for (int k = 0; k < tl_nt; ++k) r.d[k] = a.d[k] - b.d[k]; return r; }
+inline Dual operator-(const Dual& a) { Dual r(-a.v, NoInit{}); for (int k = 0; k < tl_nt; ++k) r.d[k] = -a.d[k]; return r; }
+inline Dual operator*(const Dual& a, const Dual& b) { Dual r(a.v * b.v, NoInit{}); for (int k = 0; k < tl_nt; ++k) r.d[k] = a.d[k] * b.v + a.v * b.d[k]; return r; }
+inline Dual operator/(const Dual& a, const Dual& b) { Dual r(a.v / b.v, NoInit{}); for (int k = 0; k < tl_nt; ++k) r.d[k] = (a.d[k] * b.v - a.v * b.d[k]) / (b.v * b.v); return r; }
+inline Dual operator+(const Dual& a, double b) { Dual r(a.v + b, NoInit{}); for (int k = 0; k < tl_nt; ++k) r.d[k] = a.d[k]; return r; }
+inline Dual operator+(double a, const Dual& b) { return b + a; }
+inline Dual operator-(const Dual& a, double b) { return a + (-b); }
+inline Dual operator-(double a, const Dual& b) { Dual r(a - b.v, NoInit{}); for (int k = 0; k < tl_nt; ++k) r.d[k] = -b.d[k]; return r; }
+inline Dual operator*(const Dual& a, double b) { Dual r(a.v * b, NoInit{}); for (int k = 0; k < tl_nt; ++k) r.d[k] = a.d[k] * b; return r; }
+inline Dual operator*(double a, const Dual& b) { return b * a; }
+inline Dual operator/(const Dual& a, double b) { return a * (1.0 / b); }
+inline Dual operator/(double a, const Dual& b) { Dual r(a / b.v, NoInit{}); for (int k = 0; k < tl_nt; ++k) r.d[k] = -a * b.d[k] / (b.v * b.v); return r; }
+inline Dual& operator+=(Dual& a, const Dual& b) { a = a + b; return a; }
+inline Dual sqrt(const Dual& a) { double s = std::sqrt(a.v); Dual r(s, NoInit{}); for (int k = 0; k < tl_nt; ++k) r.d[k] = a.d[k] / (2.0 * s); return r; }
+inline Dual exp(const Dual& a) { double e = std::exp(a.v); Dual r(e, NoInit{}); for (int k = 0; k < tl_nt; ++k) r.d[k] = a.d[k] * e; return r; }
+
+inline double val(double x) { return x; }
+inline double val(const Dual& x) { return x.v; }
+using std::exp;
+using std::sqrt;
+
+// ---------------------------------------------------------------------------------------------------
+// B-spline basis (sec. 2.1)
+// ---------------------------------------------------------------------------------------------------
+
+// Clamped knot vector with p+1 zeros, p+1 ones and equispaced interior knots u_i = (i-p)/(n-p), where n is
+// the number of control points (the paper's n_1 + 1), length n + p + 1.
+std::vector<double> make_knots(int p, int n) {
+    std::vector<double> U(n + p + 1);
+    for (int i = 0; i < n + p + 1; ++i) {
+        if (i <= p) U[i] = 0.0;
+        else if (i >= n) U[i] = 1.0;
+        else U[i] = double(i - p) / double(n - p);
+    }
+    return U;
+}
+
+// Knot span s with U[s] <= u < U[s+1]; u = 1 belongs to the last span s = n-1 so that N_{n-1,p}(1) = 1.
+int find_span(int p, int n, double u) {
+    int s = p + int(std::floor(u * double(n - p)));
+    if (s < p) s = p;
+    if (s > n - 1) s = n - 1;
+    return s;
+}
+
+// Degree-k derivative-type combination used by the textbook derivative formula:
+//   D_{i,k} = k * ( X_{i,k-1} / (U[i+k]-U[i]) - X_{i+1,k-1} / (U[i+k+1]-U[i+1]) ),  0/0 := 0,
+// where X holds the k nonzero degree-(k-1) entries of span s (index m <-> function s-k+1+m).
+template <class S>
+void deriv_step(int k, const double* U, int s, const S* X, S* D) {
+    for (int m = 0; m <= k; ++m) {
+        int i = s - k + m;
+        S acc = 0.0;
+        double d1 = U[i + k] - U[i];
+        double d2 = U[i + k + 1] - U[i + 1];
+        if (m >= 1 && d1 != 0.0) acc = acc + X[m - 1] / d1;
+        if (m <= k - 1 && d2 != 0.0) acc = acc - X[m] / d2;
+        D[m] = acc * double(k);
+    }
+}
+
+// Nonzero basis functions N_{s-p..s,p}(u) on span s, by the Cox-de Boor recursion (sec. 2.1; the second
+// denominator is read as u_{i+p+1} - u_{i+1}, and 0/0 := 0), with first and second u-derivatives.
+template <class S>
+void basis(int p, const double* U, int s, const S& u, S* N, S* dN, S* d2N) {
+    S T[MAXDEG + 1][MAXDEG + 1];  // T[k][m] = N_{s-k+m,k}(u)
+    T[0][0] = 1.0;
+    for (int k = 1; k <= p; ++k) {
+        for (int m = 0; m <= k; ++m) {
+            int i = s - k + m;
+            S acc = 0.0;
+            double d1 = U[i + k] - U[i];
+            double d2 = U[i + k + 1] - U[i + 1];
+            if (m >= 1 && d1 != 0.0) acc = acc + (u - U[i]) / d1 * T[k - 1][m - 1];
+            if (m <= k - 1 && d2 != 0.0) acc = acc + (U[i + k + 1] - u) / d2 * T[k - 1][m];
+            T[k][m] = acc;
+        }
+    }
+    for (int m = 0; m <= p; ++m) N[m] = T[p][m];
+    if (dN) deriv_step(p, U, s, T[p - 1], dN);
+    if (d2N) {
+        if (p >= 2) {
+            S D1[MAXDEG + 1];
+            deriv_step(p - 1, U, s, T[p - 2], D1);
+            deriv_step(p, U, s, D1, d2N);
+        } else {
+            for (int m = 0; m <= p; ++m) d2N[m] = 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------------
+// Problem geometry
+// ---------------------------------------------------------------------------------------------------
+struct Geo {
+    orc_problem pr;
+    int p, q, nu, nv;
+    std::vector<double> U, V;
+    double zmin, zmax;      // global convex-hull bounds of P^z (sec. 2.2.2, whole-surface test)
+    double Gx, Gy;          // bounds of |h_x|, |h_y| from the derivative control points
+    int nxe, nye;           // effective detector resolution
+    double Rxe, Rye, wx, wy;
+    double R0;              // Schlick reflectance at normal incidence
+    int64_t nrays;
+    double w0;              // initial ray weight
+};
+
+bool valid_problem(const orc_problem* pr) {
+    if (!pr) return false;
+    if (pr->p < 1 || pr->q < 1 || pr->p > MAXDEG || pr->q > MAXDEG) return false;
+    if (pr->n_u <= pr->p || pr->n_v <= pr->q) return false;
+    if (!(pr->n_lens > 1.0) || !(pr->r_x > 0) || !(pr->r_y > 0)) return false;
+    if (pr->grid_u < 1 || pr->grid_v < 1 || pr->n_x < 1 || pr->n_y < 1) return false;
+    if (pr->nu_x < 1 || pr->nu_y < 1 || pr->nu_x % 2 == 0 || pr->nu_y % 2 == 0) return false;
+    if (!(pr->R_x > 0) || !(pr->R_y > 0) || !(pr->alpha > 0)) return false;
+    if (pr->kind < 0 || pr->kind > 2) return false;
+    if (pr->kind != 0) {
+        if (!(pr->pos_z < pr->z_in)) return false;
+        if (!(pr->half_angle >= 0.0 && pr->half_angle < M_PI / 2)) return false;
+        if (pr->kind == 2 && (pr->emit_nx < 1 || pr->emit_ny < 1)) return false;
+    }
+    return true;
+}
+
+Geo make_geo(const orc_problem* pr, const double* Pz) {
+    Geo g;
+    g.pr = *pr;
+    g.p = pr->p; g.q = pr->q; g.nu = pr->n_u; g.nv = pr->n_v;
+    g.U = make_knots(g.p, g.nu);
+    g.V = make_knots(g.q, g.nv);
+    g.zmin = Pz ? Pz[0] : 0.0; g.zmax = g.zmin;
+    g.Gx = 0.0; g.Gy = 0.0;
+    if (Pz) {
+        for (int i = 0; i < g.nu * g.nv; ++i) { g.zmin = std::min(g.zmin, Pz[i]); g.zmax = std::max(g.zmax, Pz[i]); }
+        // Derivative control points: Z_u = sum N_{i,p-1} N_{j,q} p (P_{i+1,j} - P_{i,j}) / (U[i+p+1] - U[i+1]).
+        for (int i = 0; i + 1 < g.nu; ++i)
+            for (int j = 0; j < g.nv; ++j) {
+                double den = g.U[i + g.p + 1] - g.U[i + 1];
+                double Q = g.p * (Pz[(i + 1) * g.nv + j] - Pz[i * g.nv + j]) / den;
+                g.Gx = std::max(g.Gx, std::fabs(Q) / (2.0 * pr->r_x));
+            }
+        for (int i = 0; i < g.nu; ++i)
+            for (int j = 0; j + 1 < g.nv; ++j) {
+                double den = g.V[j + g.q + 1] - g.V[j + 1];
+                double Q = g.q * (Pz[i * g.nv + j + 1] - Pz[i * g.nv + j]) / den;
+                g.Gy = std::max(g.Gy, std::fabs(Q) / (2.0 * pr->r_y));
+            }
+    }
+    double wx = 2.0 * pr->R_x / pr->n_x, wy = 2.0 * pr->R_y / pr->n_y;
+    g.wx = wx; g.wy = wy;
+    if (pr->ghost) {  // ghost pixels (sec. 2.3): R* = R + (nu-1)/2 w, resolution n + nu - 1
+        g.nxe = pr->n_x + pr->nu_x - 1; g.nye = pr->n_y + pr->nu_y - 1;
+        g.Rxe = pr->R_x + 0.5 * (pr->nu_x - 1) * wx; g.Rye = pr->R_y + 0.5 * (pr->nu_y - 1) * wy;
+    } else {
+        g.nxe = pr->n_x; g.nye = pr->n_y; g.Rxe = pr->R_x; g.Rye = pr->R_y;
+    }
+    double r0 = (pr->n_lens - 1.0) / (pr->n_lens + 1.0);
+    g.R0 = r0 * r0;
+    int64_t per = int64_t(pr->grid_u) * pr->grid_v;
+    if (pr->kind == 2) per *= int64_t(pr->emit_nx) * pr->emit_ny;
+    g.nrays = per;
+    g.w0 = 1.0 / double(per);
+    return g;
+}
+
+// Surface derivatives at (u, v) on span (su, sv) with local control points Pl[(a)*(q+1)+b] =
+// P^z_{su-p+a, sv-q+b}.  Returns h and its x/y derivatives (X = (2u-1) r_x, so d/dx = d/du / (2 r_x)).
+template <class S>
+struct Surf { S h, hx, hy, hxx, hxy, hyy; };
+
+template <class S>
+Surf<S> eval_surface(const Geo& g, const S* Pl, int su, int sv, const S& u, const S& v, bool second) {
+    S Nu[MAXDEG + 1], dNu[MAXDEG + 1], d2Nu[MAXDEG + 1];
+    S Nv[MAXDEG + 1], dNv[MAXDEG + 1], d2Nv[MAXDEG + 1];
+    basis(g.p, g.U.data(), su, u, Nu, dNu, second ? d2Nu : nullptr);
+    basis(g.q, g.V.data(), sv, v, Nv, dNv, second ? d2Nv : nullptr);
+    // S(u,v) = sum_i sum_j N_i(u) N_j(v) P_ij (sec. 2.1, tensor-product surface)
+    S h = 0.0, hu = 0.0, hv = 0.0, huu = 0.0, huv = 0.0, hvv = 0.0;
+    for (int a = 0; a <= g.p; ++a)
+        for (int b = 0; b <= g.q; ++b) {
+            const S& P = Pl[a * (g.q + 1) + b];
+            h = h + Nu[a] * Nv[b] * P;
+            hu = hu + dNu[a] * Nv[b] * P;
+            hv = hv + Nu[a] * dNv[b] * P;
+            if (second) {
+                huu = huu + d2Nu[a] * Nv[b] * P;
+                huv = huv + dNu[a] * dNv[b] * P;
+                hvv = hvv + Nu[a] * d2Nv[b] * P;
+            }
+        }
+    Surf<S> r;
+    double sx = 1.0 / (2.0 * g.pr.r_x), sy = 1.0 / (2.0 * g.pr.r_y);
+    r.h = h; r.hx = hu * sx; r.hy = hv * sy;
+    r.hxx = huu * (sx * sx); r.hxy = huv * (sx * sy); r.hyy = hvv * (sy * sy);
+    return r;
+}
+
+// Local control points of the span product containing (u, v), as doubles.
+void local_cps(const Geo& g, const double* Pz, int su, int sv, double* Pl) {
+    for (int a = 0; a <= g.p; ++a)
+        for (int b = 0; b <= g.q; ++b)
+            Pl[a * (g.q + 1) + b] = Pz[(su - g.p + a) * g.nv + (sv - g.q + b)];
+}
+
+// h(x, y) and derivatives in double precision from the full control net.
+Surf<double> surface_at(const Geo& g, const double* Pz, double x, double y, bool second) {
+    double u = 0.5 * (x / g.pr.r_x + 1.0), v = 0.5 * (y / g.pr.r_y + 1.0);  // X^{-1}, Y^{-1} (sec. 2.1.1)
+    int su = find_span(g.p, g.nu, u), sv = find_span(g.q, g.nv, v);
+    double Pl[MAXT];
+    local_cps(g, Pz, su, sv, Pl);
+    return eval_surface<double>(g, Pl, su, sv, u, v, second);
+}
+
+// ---------------------------------------------------------------------------------------------------
+// Random numbers: counter-based SplitMix64 (Steele, Lea, Flood 2014).  Output i of the SplitMix64 sequence
+// whose state starts at mix(seed + stream * gamma).
+// ---------------------------------------------------------------------------------------------------
+constexpr uint64_t GOLDEN_GAMMA = 0x9E3779B97F4A7C15ull;
+uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+uint64_t rng_at(uint64_t seed, uint64_t stream, uint64_t index) {
+    uint64_t state = mix64(seed + stream * GOLDEN_GAMMA);
+    return mix64(state + (index + 1) * GOLDEN_GAMMA);
+}
+constexpr uint64_t RAY_STREAM = 2;
+
+// Two 24-bit uniforms in [0,1) from one output.
+void two_uniforms(uint64_t h, double* a, double* b) {
+    *a = double(h >> 40) * (1.0 / 16777216.0);
+    *b = double((h >> 16) & 0xFFFFFFull) * (1.0 / 16777216.0);
+}
+
+// ---------------------------------------------------------------------------------------------------
+// Sources (sec. 2.2.1; grid of point sources, sec. 3.3)
+// ---------------------------------------------------------------------------------------------------
+// Collimated: rays sampled on a square grid of [0,1]^2 directly on the B-spline surface.  Reading: samples
+// are cell-centred (k + 1/2)/N, or (k + xi)/N when jittered.  Ray id = k_u * N_v + k_v.
+void sample_collimated(const Geo& g, int64_t id, double* u, double* v) {
+    int64_t ku = id / g.pr.grid_v, kv = id % g.pr.grid_v;
+    double xu = 0.5, xv = 0.5;
+    if (g.pr.jitter) two_uniforms(rng_at(g.pr.seed, RAY_STREAM, uint64_t(id)), &xu, &xv);
+    *u = (double(ku) + xu) / double(g.pr.grid_u);
+    *v = (double(kv) + xv) / double(g.pr.grid_v);
+}
+
+// Point source: theta uniform in [0, 2 pi), a uniform in [0,1], phi = arccos(1 - (1 - cos phi_max) a)
+// (uniform in solid angle).  Reading: the "uniform" draws are stratified, k_theta and k_a being the strata.
+// Ray id = e * (S_theta S_a) + k_theta * S_a + k_a for emitter e (kind 2: grid of emitters, endpoints
+// included, row-major in (x, y)).
+void sample_point(const Geo& g, int64_t id, double* theta, double* a, double* ex, double* ey) {
+    int64_t per = int64_t(g.pr.grid_u) * g.pr.grid_v;
+    int64_t e = id / per, r = id % per;
+    int64_t kt = r / g.pr.grid_v, ka = r % g.pr.grid_v;
+    double x1 = 0.5, x2 = 0.5;
+    if (g.pr.jitter) two_uniforms(rng_at(g.pr.seed, RAY_STREAM, uint64_t(id)), &x1, &x2);
+    *theta = 2.0 * M_PI * (double(kt) + x1) / double(g.pr.grid_u);
+    *a = (double(ka) + x2) / double(g.pr.grid_v);
+    *ex = g.pr.pos_x; *ey = g.pr.pos_y;
+    if (g.pr.kind == 2) {
+        int64_t ix = e / g.pr.emit_ny, iy = e % g.pr.emit_ny;
+        if (g.pr.emit_nx > 1) *ex += -0.5 * g.pr.emit_wx + double(ix) * g.pr.emit_wx / double(g.pr.emit_nx - 1);
+        if (g.pr.emit_ny > 1) *ey += -0.5 * g.pr.emit_wy + double(iy) * g.pr.emit_wy / double(g.pr.emit_ny - 1);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------------
+// Optics
+// ---------------------------------------------------------------------------------------------------
+// Schlick's approximation, R = R0 + (1 - R0)(1 - c)^5.  Reading: c is the cosine on the air side.
+template <class S>
+S schlick(const S& c, double R0) {
+    S m = 1.0 - c;
+    S m2 = m * m;
+    return R0 + (1.0 - R0) * (m2 * m2 * m);
+}
+
+// Vector Snell law (the paper does not print it; textbook form): n_hat on the transmitted side,
+// eta = n_i / n_t, c = d . n_hat, k = 1 - eta^2 (1 - c^2); k < 0 is TIR; d_t = eta d + (sqrt(k) - eta c) n_hat.
+// ---------------------------------------------------------------------------------------------------
+
+struct Entry {          // P-independent part of a ray: origin/direction inside the glass and weight
+    int status;         // ORC_HIT (continues) or ORC_MISS_ENTRY
+    double o[3], d[3], w;
+    bool collimated;
+    double u, v;        // collimated: the sample on the surface
+    double margin;      // distance of the entry point to the aperture edge (point sources)
+};
+
+Entry ray_entry(const Geo& g, int64_t id) {
+    Entry E;
+    E.status = ORC_HIT;
+    E.margin = 1e300;
+    const orc_problem& pr = g.pr;
+    if (pr.kind == 0) {
+        // Collimated bundle: the path to the freeform is parallel to z, rays start on the surface with
+        // d = (0,0,1).  They cross the flat face at normal incidence: Schlick weight 1 - R0.
+        E.collimated = true;
+        sample_collimated(g, id, &E.u, &E.v);
+        E.o[0] = (2.0 * E.u - 1.0) * pr.r_x;
+        E.o[1] = (2.0 * E.v - 1.0) * pr.r_y;
+        E.o[2] = pr.z_in;
+        E.d[0] = 0.0; E.d[1] = 0.0; E.d[2] = 1.0;
+        E.w = g.w0 * (pr.fresnel ? 1.0 - g.R0 : 1.0);
+        return E;
+    }
+    E.collimated = false;
+    double theta, a, ex, ey;
+    sample_point(g, id, &theta, &a, &ex, &ey);
+    double cphi = 1.0 - (1.0 - std::cos(pr.half_angle)) * a;
+    double sphi = std::sqrt(std::max(0.0, 1.0 - cphi * cphi));
+    double d0[3] = {std::cos(theta) * sphi, std::sin(theta) * sphi, cphi};
+    // Flat entry face z = z_in over the aperture; rays outside it are dropped (other paths ignored, sec 2.2).
+    double t0 = (pr.z_in - pr.pos_z) / d0[2];
+    double p0[3] = {ex + t0 * d0[0], ey + t0 * d0[1], pr.z_in};
+    E.margin = std::min(pr.r_x - std::fabs(p0[0]), pr.r_y - std::fabs(p0[1]));
+    if (std::fabs(p0[0]) > pr.r_x || std::fabs(p0[1]) > pr.r_y) { E.status = ORC_MISS_ENTRY; return E; }
+    // Refraction air -> glass at normal (0,0,1), eta = 1/n.
+    double eta = 1.0 / pr.n_lens;
+    double c = d0[2];
+    double k = 1.0 - eta * eta * (1.0 - c * c);
+    double sk = std::sqrt(k);
+    for (int i = 0; i < 3; ++i) E.d[i] = eta * d0[i] + (i == 2 ? (sk - eta * c) : 0.0);
+    for (int i = 0; i < 3; ++i) E.o[i] = p0[i];
+    E.w = g.w0 * (pr.fresnel ? 1.0 - schlick(c, g.R0) : 1.0);  // air-side cosine is the incidence cosine
+    return E;
+}
+
+// f(t) = h(o_xy + t d_xy) - o_z - t d_z  (sec. 2.2.1, the root problem, written in x,y instead of u,v).
+double f_of_t(const Geo& g, const double* Pz, const Entry& E, double t) {
+    double x = E.o[0] + t * E.d[0], y = E.o[1] + t * E.d[1];
+    return surface_at(g, Pz, x, y, false).h - E.o[2] - t * E.d[2];
+}
+
+struct Root { int status; double t; double margin; };
+
+// Smallest positive root of f whose point lies in the lens aperture.  Exact in double precision:
+// the bracket comes from the global convex-hull bounds (sec. 2.2.2); when the derivative bound proves f
+// strictly decreasing the root is unique and found by bisection, otherwise the bracket is scanned in steps
+// of 1/64 of a projected knot span for the first sign change.  Newton steps polish the root.
+Root find_root(const Geo& g, const double* Pz, const Entry& E) {
+    Root R; R.status = ORC_HIT; R.t = 0.0; R.margin = 1e300;
+    const double* o = E.o; const double* d = E.d;
+    // Bracket widened by a rounding margin so that f(t_lo) > 0 > f(t_hi) also for a flat surface.
+    double pad = 1e-9 * (1.0 + std::fabs(g.zmax - o[2])) / d[2];
+    double t_lo = std::max(0.0, (g.zmin - o[2]) / d[2] - pad);
+    double t_hi = (g.zmax - o[2]) / d[2] + pad;
+    double t_ap = std::numeric_limits<double>::infinity();
+    const double r[2] = {g.pr.r_x, g.pr.r_y};
+    for (int ax = 0; ax < 2; ++ax) {
+        if (d[ax] > 0) t_ap = std::min(t_ap, (r[ax] - o[ax]) / d[ax]);
+        else if (d[ax] < 0) t_ap = std::min(t_ap, (-r[ax] - o[ax]) / d[ax]);
+    }
+    double t_end = std::min(t_hi, t_ap);
+    if (t_end < t_lo) { R.status = ORC_SIDE_WALL; R.margin = (t_lo - t_end) * d[2]; return R; }
+    double f_end = f_of_t(g, Pz, E, t_end);
+    if (t_ap <= t_hi) R.margin = std::fabs(f_end);
+    if (f_end > 0.0) { R.status = ORC_SIDE_WALL; return R; }
+    double a = t_lo, b = t_end;
+    bool monotone = g.Gx * std::fabs(d[0]) + g.Gy * std::fabs(d[1]) < d[2];
+    if (!monotone) {
+        double du = std::fabs(d[0]) * (t_end - t_lo) / (2.0 * g.pr.r_x) * (g.nu - g.p);
+        double dv = std::fabs(d[1]) * (t_end - t_lo) / (2.0 * g.pr.r_y) * (g.nv - g.q);
+        int64_t M = std::max<int64_t>(64, int64_t(std::ceil(64.0 * (du + dv))) + 1);
+        double prev = t_lo;
+        for (int64_t k = 1; k <= M; ++k) {
+            double t = t_lo + (t_end - t_lo) * double(k) / double(M);
+            if (f_of_t(g, Pz, E, t) <= 0.0) { a = prev; b = t; break; }
+            prev = t;
+        }
+    }
+    // Bisection: f(a) > 0 >= f(b).
+    for (int it = 0; it < 200 && (b - a) > 1e-11 * (1.0 + b); ++it) {
+        double m = 0.5 * (a + b);
+        if (f_of_t(g, Pz, E, m) > 0.0) a = m; else b = m;
+    }
+    double t = 0.5 * (a + b);
+    double slack = b - a;              // the root may sit on a bracket end up to rounding of f
+    for (int it = 0; it < 6; ++it) {  // guarded Newton polish
+        double x = o[0] + t * d[0], y = o[1] + t * d[1];
+        Surf<double> s = surface_at(g, Pz, x, y, false);
+        double f = s.h - o[2] - t * d[2];
+        double fp = s.hx * d[0] + s.hy * d[1] - d[2];
+        if (fp == 0.0) break;
+        double tn = t - f / fp;
+        if (!(tn >= a - slack && tn <= b + slack)) break;
+        bool done = std::fabs(tn - t) <= 1e-15 * (1.0 + std::fabs(t));
+        t = tn;
+        if (done) break;
+    }
+    R.t = t;
+    return R;
+}
+
+// Result of the P-dependent part of a ray (templated: double for values, Dual for derivatives).
+template <class S>
+struct Exit {
+    int status;
+    S X, Y, w;
+    double k;        // Snell discriminant at the exit face (TIR margin)
+};
+
+// Exit refraction at the freeform, Schlick weight, propagation to the screen.
+template <class S>
+Exit<S> exit_and_screen(const Geo& g, const S* q, const double* d, const S& hx, const S& hy, double w_in,
+                        bool ignore_tir) {
+    Exit<S> X;
+    X.status = ORC_HIT;
+    // Outward unit normal of z = h(x,y): (-h_x, -h_y, 1) / |.|
+    S m0 = -hx, m1 = -hy;
+    S nn = sqrt(m0 * m0 + m1 * m1 + 1.0);
+    S n0 = m0 / nn, n1 = m1 / nn, n2 = 1.0 / nn;
+    double eta = g.pr.n_lens;  // glass -> air
+    S c = n0 * d[0] + n1 * d[1] + n2 * d[2];
+    S k = 1.0 - eta * eta * (1.0 - c * c);
+    X.k = val(k);
+    if (val(k) < 0.0) {
+        if (!ignore_tir) { X.status = ORC_TIR; return X; }
+        k = S(0.0);
+    }
+    S sk = sqrt(k);
+    S beta = sk - eta * c;
+    S e0 = eta * d[0] + beta * n0, e1 = eta * d[1] + beta * n1, e2 = eta * d[2] + beta * n2;
+    S T = g.pr.fresnel ? 1.0 - schlick(sk, g.R0) : S(1.0);
+    X.w = T * w_in;
+    if (!(val(e2) > 0.0)) { X.status = ORC_OFF_SCREEN; return X; }
+    S tau = (g.pr.z_screen - q[2]) / e2;
+    X.X = q[0] + tau * e0;
+    X.Y = q[1] + tau * e1;
+    if (!(val(X.X) >= -g.Rxe && val(X.X) < g.Rxe && val(X.Y) >= -g.Rye && val(X.Y) < g.Rye))
+        X.status = ORC_OFF_SCREEN;
+    return X;
+}
+
+// Gaussian reconstruction filter (sec. 2.3):
+//   f_i(x) = exp(-alpha (x - c_i)^2) - exp(-alpha (nu w / 2)^2) if |x - c_i| < nu w / 2, else 0,
+//   c_i = (i + 1/2) w - R*, F_ij = f_i g_j / sum_{i',j'} f_i' g_j'.
+// Reading: distances in pixel widths (alpha per pixel^2); pixel i is [i w - R*, (i+1) w - R*) (0-based);
+// the sum runs over the pixels of the grid.  Window = the nu pixels centred on the landing pixel, which
+// holds the whole support.  Fills idx[] with pixel indices and F[] with the normalised weights.
+template <class S>
+int filter_axis(int n, double R, double w, int nu, double alpha, const S& X, int* idx, S* F) {
+    int i0 = int(std::floor((val(X) + R) / w));
+    if (i0 < 0) i0 = 0;
+    if (i0 > n - 1) i0 = n - 1;
+    int h = (nu - 1) / 2;
+    double edge = std::exp(-alpha * (0.5 * nu) * (0.5 * nu));
+    S sum = 0.0;
+    int cnt = 0;
+    for (int a = -h; a <= h; ++a) {
+        int i = i0 + a;
+        if (i < 0 || i >= n) continue;
+        double c = (i + 0.5) * w - R;
+        S dx = (X - c) / w;
+        S f = 0.0;
+        if (std::fabs(val(dx)) < 0.5 * nu) f = exp(-alpha * dx * dx) - edge;
+        idx[cnt] = i;
+        F[cnt] = f;
+        sum = sum + f;
+        ++cnt;
+    }
+    for (int m = 0; m < cnt; ++m) F[m] = F[m] / sum;
+    return cnt;
+}
+
+constexpr int MAXNU = 64;
+
+// Splat: calls fn(pixel_index, weight) for every pixel of the window of a ray landing at (X, Y).
+template <class S, class Fn>
+void splat(const Geo& g, const S& X, const S& Y, const S& w, Fn fn) {
+    int ix[MAXNU], iy[MAXNU];
+    S Fx[MAXNU], Fy[MAXNU];
+    int cx = filter_axis(g.nxe, g.Rxe, g.wx, g.pr.nu_x, g.pr.alpha, X, ix, Fx);
+    int cy = filter_axis(g.nye, g.Rye, g.wy, g.pr.nu_y, g.pr.alpha, Y, iy, Fy);
+    for (int a = 0; a < cx; ++a)
+        for (int b = 0; b < cy; ++b) fn(int64_t(ix[a]) * g.nye + iy[b], w * Fx[a] * Fy[b]);
+}
+
+// ---------------------------------------------------------------------------------------------------
+// One ray, values only.
+// ---------------------------------------------------------------------------------------------------
+struct RayOut {
+    int status;
+    double X, Y, w;
+    double u, v, t;      // hit parameters
+    int su, sv;          // hit span product
+    bool marginal;
+    double k;
+    Entry E;
+};
+
+// Rounding-distance thresholds for "marginal" rays whose discrete state may differ in single precision.
+constexpr double EPS_APERTURE = 1e-4;  // mm
+constexpr double EPS_SIDE = 1e-5;      // mm, |f| at the aperture exit
+constexpr double EPS_TIR = 1e-5;       // Snell discriminant
+constexpr double EPS_SCREEN = 1e-4;    // relative to the screen radius
+
+RayOut trace_value(const Geo& g, const double* Pz, int64_t id) {
+    RayOut R;
+    R.marginal = false; R.X = R.Y = R.w = 0.0; R.u = R.v = R.t = 0.0; R.su = R.sv = 0; R.k = 1.0;
+    R.E = ray_entry(g, id);
+    const Entry& E = R.E;
+    if (std::fabs(E.margin) < EPS_APERTURE) R.marginal = true;
+    if (E.status != ORC_HIT) { R.status = E.status; return R; }
+    double q[3];
+    if (E.collimated) {
+        R.t = 0.0;
+        q[0] = E.o[0]; q[1] = E.o[1];
+        R.u = E.u; R.v = E.v;
+    } else {
+        Root rt = find_root(g, Pz, E);
+        if (rt.margin < EPS_SIDE) R.marginal = true;
+        if (rt.status != ORC_HIT) { R.status = rt.status; return R; }
+        R.t = rt.t;
+        q[0] = E.o[0] + rt.t * E.d[0]; q[1] = E.o[1] + rt.t * E.d[1];
+        R.u = 0.5 * (q[0] / g.pr.r_x + 1.0); R.v = 0.5 * (q[1] / g.pr.r_y + 1.0);
+    }
+    R.su = find_span(g.p, g.nu, R.u); R.sv = find_span(g.q, g.nv, R.v);
+    double Pl[MAXT];
+    local_cps(g, Pz, R.su, R.sv, Pl);
+    Surf<double> s = eval_surface<double>(g, Pl, R.su, R.sv, R.u, R.v, false);
+    q[2] = E.collimated ? s.h : E.o[2] + R.t * E.d[2];
+    Exit<double> X = exit_and_screen<double>(g, q, E.d, s.hx, s.hy, E.w, false);
+    R.k = X.k;
+    if (std::fabs(X.k) < EPS_TIR) {
+        R.marginal = true;
+        if (X.status == ORC_TIR) {  // landing the ray would have had: for the mask only
+            Exit<double> Y = exit_and_screen<double>(g, q, E.d, s.hx, s.hy, E.w, true);
+            R.X = Y.X; R.Y = Y.Y;
+        }
+    }
+    R.status = X.status;
+    if (X.status == ORC_TIR) return R;
+    R.X = X.X; R.Y = X.Y; R.w = X.w;
+    if (std::fabs(g.Rxe - std::fabs(X.X)) < EPS_SCREEN * g.Rxe || std::fabs(g.Rye - std::fabs(X.Y)) < EPS_SCREEN * g.Rye)
+        R.marginal = true;
+    return R;
+}
+
+// ---------------------------------------------------------------------------------------------------
+// One ray with dual numbers: tangents are the (p+1)(q+1) control points of the hit span product.
+// Calls sink(local_cp_index, derivative) with d(sum_ij G_ij w F_ij)/dP for each local control point, or
+// accumulates the image JVP when G is null.
+// ---------------------------------------------------------------------------------------------------
+Exit<Dual> trace_dual(const Geo& g, const double* Pz, const RayOut& R, Dual* Xo, Dual* Yo) {
+    const Entry& E = R.E;
+    int nt = (g.p + 1) * (g.q + 1);
+    tl_nt = nt;
+    Dual Pl[MAXT];
+    for (int a = 0; a <= g.p; ++a)
+        for (int b = 0; b <= g.q; ++b) {
+            int l = a * (g.q + 1) + b;
+            Pl[l] = Dual(Pz[(R.su - g.p + a) * g.nv + (R.sv - g.q + b)]);
+            Pl[l].d[l] = 1.0;
+        }
+    Dual q[3];
+    Surf<Dual> s;
+    if (E.collimated) {
+        Dual u(R.u), v(R.v);
+        s = eval_surface<Dual>(g, Pl, R.su, R.sv, u, v, false);
+        q[0] = Dual(E.o[0]); q[1] = Dual(E.o[1]); q[2] = s.h;
+    } else {
+        // Differentiate the root: two Newton steps in dual arithmetic from the converged root.
+        Dual t(R.t);
+        for (int it = 0; it < 2; ++it) {
+            Dual x = E.o[0] + t * E.d[0], y = E.o[1] + t * E.d[1];
+            Dual u = 0.5 * (x / g.pr.r_x + 1.0), v = 0.5 * (y / g.pr.r_y + 1.0);
+            Surf<Dual> sn = eval_surface<Dual>(g, Pl, R.su, R.sv, u, v, false);
+            Dual f = sn.h - E.o[2] - t * E.d[2];
+            Dual fp = sn.hx * E.d[0] + sn.hy * E.d[1] - E.d[2];
+            t = t - f / fp;
+        }
+        for (int i = 0; i < 3; ++i) q[i] = E.o[i] + t * E.d[i];
+        Dual u = 0.5 * (q[0] / g.pr.r_x + 1.0), v = 0.5 * (q[1] / g.pr.r_y + 1.0);
+        s = eval_surface<Dual>(g, Pl, R.su, R.sv, u, v, false);
+    }
+    Exit<Dual> X = exit_and_screen<Dual>(g, q, E.d, s.hx, s.hy, E.w, false);
+    *Xo = X.X; *Yo = X.Y;
+    return X;
+}
+
+int64_t cp_index(const Geo& g, const RayOut& R, int l) {
+    int a = l / (g.q + 1), b = l % (g.q + 1);
+    return int64_t(R.su - g.p + a) * g.nv + (R.sv - g.q + b);
+}
+
+// ---------------------------------------------------------------------------------------------------
+// Parallel loop over rays: blocks of 4096 rays, block b handled by thread b mod T (static, so results are
+// summed in a fixed order and are reproducible).
+// ---------------------------------------------------------------------------------------------------
+template <class Fn>
+void parallel_rays(int64_t n, int threads, Fn fn) {
+    if (threads <= 0) threads = int(std::max(1u, std::thread::hardware_concurrency()));
+    const int64_t B = 4096;
+    int64_t nb = (n + B - 1) / B;
+    if (threads > nb) threads = int(std::max<int64_t>(1, nb));
+    std::vector<std::thread> pool;
+    for (int t = 0; t < threads; ++t) {
+        pool.emplace_back([=, &fn]() {
+            for (int64_t b = t; b < nb; b += threads) {
+                int64_t lo = b * B, hi = std::min(n, lo + B);
+                for (int64_t id = lo; id < hi; ++id) fn(t, id);
+            }
+        });
+    }
+    for (auto& th : pool) th.join();
+}
+
+int nthreads(int t, int64_t n) {
+    if (t <= 0) t = int(std::max(1u, std::thread::hardware_concurrency()));
+    int64_t nb = (n + 4095) / 4096;
+    return int(std::max<int64_t>(1, std::min<int64_t>(t, nb)));
+}
+
+void mark_window(const Geo& g, double X, double Y, double* mask) {
+    splat<double>(g, X, Y, 1.0, [&](int64_t pix, double) { mask[pix] = 1.0; });
+}
+
+}  // namespace
+
+// ===================================================================================================
+// C ABI
+// ===================================================================================================
+extern "C" {
+
+int64_t orc_num_rays(const orc_problem* pr) {
+    if (!valid_problem(pr)) return -1;
+    return make_geo(pr, nullptr).nrays;
+}
+
+void orc_image_size(const orc_problem* pr, int32_t* nx, int32_t* ny) {
+    Geo g = make_geo(pr, nullptr);
+    *nx = g.nxe; *ny = g.nye;
+}
+
+int orc_knots(int32_t p, int32_t n, double* U) {
+    if (p < 1 || n <= p) return ORC_E_ARG;
+    std::vector<double> k = make_knots(p, n);
+    std::copy(k.begin(), k.end(), U);
+    return ORC_OK;
+}
+
+int orc_basis_all(int32_t p, int32_t n, double u, int32_t der, double* out) {
+    if (p < 1 || p > MAXDEG || n <= p || der < 0 || der > 2) return ORC_E_ARG;
+    std::vector<double> U = make_knots(p, n);
+    int s = find_span(p, n, u);
+    double N[MAXDEG + 1], dN[MAXDEG + 1], d2N[MAXDEG + 1];
+    basis<double>(p, U.data(), s, u, N, dN, d2N);
+    for (int i = 0; i < n; ++i) out[i] = 0.0;
+    const double* src = der == 0 ? N : (der == 1 ? dN : d2N);
+    for (int m = 0; m <= p; ++m) out[s - p + m] = src[m];
+    return ORC_OK;
+}
+
+int orc_surface(const orc_problem* pr, const double* Pz, double x, double y, double* out) {
+    if (!valid_problem(pr)) return ORC_E_ARG;
+    Geo g = make_geo(pr, Pz);
+    Surf<double> s = surface_at(g, Pz, x, y, true);
+    out[0] = s.h; out[1] = s.hx; out[2] = s.hy; out[3] = s.hxx; out[4] = s.hxy; out[5] = s.hyy;
+    return ORC_OK;
+}
+
+int orc_samples(const orc_problem* pr, const int64_t* ids, int64_t n, double* out4) {
+    if (!valid_problem(pr)) return ORC_E_ARG;
+    Geo g = make_geo(pr, nullptr);
+    for (int64_t r = 0; r < n; ++r) {
+        double* o = out4 + 4 * r;
+        if (pr->kind == 0) { sample_collimated(g, ids[r], &o[0], &o[1]); o[2] = o[3] = 0.0; }
+        else sample_point(g, ids[r], &o[0], &o[1], &o[2], &o[3]);
+    }
+    return ORC_OK;
+}
+
+int orc_refract(const double* d, const double* nrm, double eta, double* out) {
+    double c = d[0] * nrm[0] + d[1] * nrm[1] + d[2] * nrm[2];
+    double k = 1.0 - eta * eta * (1.0 - c * c);
+    if (k < 0.0) return 1;
+    double sk = std::sqrt(k);
+    for (int i = 0; i < 3; ++i) out[i] = eta * d[i] + (sk - eta * c) * nrm[i];
+    return 0;
+}
+
+double orc_schlick(double c, double n_lens) {
+    double r0 = (n_lens - 1.0) / (n_lens + 1.0);
+    return schlick(c, r0 * r0);
+}
+
+int orc_splat_one(const orc_problem* pr, double X, double Y, double* img) {
+    if (!valid_problem(pr)) return ORC_E_ARG;
+    Geo g = make_geo(pr, nullptr);
+    if (!(X >= -g.Rxe && X < g.Rxe && Y >= -g.Rye && Y < g.Rye)) return ORC_OK;
+    splat<double>(g, X, Y, 1.0, [&](int64_t pix, double F) { img[pix] += F; });
+    return ORC_OK;
+}
+
+int orc_trace_rays(const orc_problem* pr, const double* Pz, const int64_t* ids, int64_t n, double* out8) {
+    if (!valid_problem(pr)) return ORC_E_ARG;
+    Geo g = make_geo(pr, Pz);
+    for (int64_t r = 0; r < n; ++r) {
+        RayOut R = trace_value(g, Pz, ids[r]);
+        double* o = out8 + 8 * r;
+        o[0] = R.status; o[1] = R.X; o[2] = R.Y; o[3] = R.status == ORC_HIT ? R.w : 0.0;
+        o[4] = R.u; o[5] = R.v; o[6] = R.t; o[7] = R.marginal ? 1.0 : 0.0;
+    }
+    return ORC_OK;
+}
+
+int orc_forward(const orc_problem* pr, const double* Pz, double* irr, orc_stats* st, double* mask,
+                int32_t threads) {
+    if (!valid_problem(pr) || !Pz || !irr) return ORC_E_ARG;
+    Geo g = make_geo(pr, Pz);
+    int64_t npix = int64_t(g.nxe) * g.nye;
+    int T = nthreads(threads, g.nrays);
+    std::vector<std::vector<double>> img(T, std::vector<double>(npix, 0.0));
+    std::vector<std::vector<double>> msk(mask ? T : 0, std::vector<double>(npix, 0.0));
+    std::vector<orc_stats> sts(T);
+    for (auto& s : sts) std::memset(&s, 0, sizeof(s));
+    parallel_rays(g.nrays, T, [&](int t, int64_t id) {
+        RayOut R = trace_value(g, Pz, id);
+        orc_stats& s = sts[t];
+        s.n_rays++;
+        if (R.marginal) {
+            s.n_marginal++;
+            if (mask && (R.status == ORC_HIT || R.status == ORC_OFF_SCREEN || R.status == ORC_TIR)) {
+                double X = std::min(std::max(R.X, -g.Rxe), std::nextafter(g.Rxe, 0.0));
+                double Y = std::min(std::max(R.Y, -g.Rye), std::nextafter(g.Rye, 0.0));
+                if (std::isfinite(X) && std::isfinite(Y)) mark_window(g, X, Y, msk[t].data());
+            }
+        }
+        switch (R.status) {
+            case ORC_HIT: s.n_hit++; break;
+            case ORC_MISS_ENTRY: s.n_miss_entry++; break;
+            case ORC_SIDE_WALL: s.n_side_wall++; break;
+            case ORC_TIR: s.n_tir++; break;
+            default: s.n_off_screen++; break;
+        }
+        if (R.status != ORC_HIT) return;
+        s.flux_on_screen += R.w;
+        double* I = img[t].data();
+        splat<double>(g, R.X, R.Y, R.w, [&](int64_t pix, double v) { I[pix] += v; });
+    });
+    for (int64_t i = 0; i < npix; ++i) {
+        double acc = 0.0;
+        for (int t = 0; t < T; ++t) acc += img[t][i];
+        irr[i] = acc;
+        if (mask) {
+            double m = 0.0;
+            for (int t = 0; t < T; ++t) m = std::max(m, msk[t][i]);
+            mask[i] = m;
+        }
+    }
+    if (st) {
+        std::memset(st, 0, sizeof(*st));
+        for (int t = 0; t < T; ++t) {
+            st->flux_on_screen += sts[t].flux_on_screen;
+            st->n_rays += sts[t].n_rays; st->n_hit += sts[t].n_hit; st->n_miss_entry += sts[t].n_miss_entry;
+            st->n_side_wall += sts[t].n_side_wall; st->n_tir += sts[t].n_tir;
+            st->n_off_screen += sts[t].n_off_screen; st->n_marginal += sts[t].n_marginal;
+        }
+    }
+    return ORC_OK;
+}
+
+// Loss (sec. 2.5): I_hat = I / sum I, I_ref_hat likewise, L = ||I_hat - I_ref_hat||_F / sqrt(n_x n_y).
+// dL/dI_kl = (D_kl - sum_ij D_ij I_hat_ij) / (s sqrt(n_x n_y) ||D||), with D = I_hat - I_ref_hat, s = sum I;
+// reading: dL/dI = 0 where ||D|| = 0.
+int orc_loss(int32_t nx, int32_t ny, const double* irr, const double* target, double* loss, double* dL_dI) {
+    int64_t n = int64_t(nx) * ny;
+    double s = 0.0, sT = 0.0;
+    for (int64_t i = 0; i < n; ++i) { s += irr[i]; sT += target[i]; }
+    if (!(sT > 0.0)) return ORC_E_ARG;
+    if (!(s > 0.0)) return ORC_E_NOFLUX;
+    double d2 = 0.0, dot = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double D = irr[i] / s - target[i] / sT;
+        d2 += D * D;
+        dot += D * irr[i] / s;
+    }
+    double nrm = std::sqrt(d2), rn = std::sqrt(double(n));
+    *loss = nrm / rn;
+    if (dL_dI) {
+        for (int64_t i = 0; i < n; ++i) {
+            double D = irr[i] / s - target[i] / sT;
+            dL_dI[i] = nrm > 0.0 ? (D - dot) / (s * rn * nrm) : 0.0;
+        }
+    }
+    return ORC_OK;
+}
+
+static int grad_impl(const orc_problem* pr, const double* Pz, const double* target, double k_min,
+                     double* loss, double* dL_dP, double* dL_dP_ill, double* irr_out, double* dLdI_out,
+                     int32_t threads) {
+    if (!valid_problem(pr) || !Pz || !target || !dL_dP) return ORC_E_ARG;
+    Geo g = make_geo(pr, Pz);
+    int64_t npix = int64_t(g.nxe) * g.nye;
+    std::vector<double> irr(npix), G(npix);
+    int rc = orc_forward(pr, Pz, irr.data(), nullptr, nullptr, threads);
+    if (rc) return rc;
+    double L = 0.0;
+    rc = orc_loss(g.nxe, g.nye, irr.data(), target, &L, G.data());
+    if (rc) return rc;
+    if (loss) *loss = L;
+    if (irr_out) std::copy(irr.begin(), irr.end(), irr_out);
+    if (dLdI_out) std::copy(G.begin(), G.end(), dLdI_out);
+    int64_t K = int64_t(g.nu) * g.nv;
+    int T = nthreads(threads, g.nrays);
+    std::vector<std::vector<double>> gr(T, std::vector<double>(K, 0.0));
+    std::vector<std::vector<double>> gi(T, std::vector<double>(K, 0.0));
+    parallel_rays(g.nrays, T, [&](int t, int64_t id) {
+        RayOut R = trace_value(g, Pz, id);
+        if (R.status != ORC_HIT) return;
+        Dual X, Y;
+        Exit<Dual> E = trace_dual(g, Pz, R, &X, &Y);
+        Dual acc = 0.0;
+        splat<Dual>(g, X, Y, E.w, [&](int64_t pix, const Dual& v) { acc = acc + v * G[pix]; });
+        bool ill = dL_dP_ill && std::fabs(R.k) < k_min;
+        double* dst = ill ? gi[t].data() : gr[t].data();
+        int nt = (g.p + 1) * (g.q + 1);
+        for (int l = 0; l < nt; ++l) dst[cp_index(g, R, l)] += acc.d[l];
+        tl_nt = 0;
+    });
+    for (int64_t k = 0; k < K; ++k) {
+        double a = 0.0, b = 0.0;
+        for (int t = 0; t < T; ++t) { a += gr[t][k]; b += gi[t][k]; }
+        dL_dP[k] = a;
+        if (dL_dP_ill) dL_dP_ill[k] = b;
+    }
+    return ORC_OK;
+}
+
+int orc_grad(const orc_problem* pr, const double* Pz, const double* target, double* loss, double* dL_dP,
+             double* irr, double* dL_dI, int32_t threads) {
+    return grad_impl(pr, Pz, target, 0.0, loss, dL_dP, nullptr, irr, dL_dI, threads);
+}
+
+int orc_grad_split(const orc_problem* pr, const double* Pz, const double* target, double k_min,
+                   double* loss, double* dL_dP, double* dL_dP_ill, int32_t threads) {
+    return grad_impl(pr, Pz, target, k_min, loss, dL_dP, dL_dP_ill, nullptr, nullptr, threads);
+}
+
+int orc_jvp(const orc_problem* pr, const double* Pz, const double* vdir, double* dI, int32_t threads) {
+    if (!valid_problem(pr) || !Pz || !vdir || !dI) return ORC_E_ARG;
+    Geo g = make_geo(pr, Pz);
+    int64_t npix = int64_t(g.nxe) * g.nye;
+    int T = nthreads(threads, g.nrays);
+    std::vector<std::vector<double>> acc(T, std::vector<double>(npix, 0.0));
+    parallel_rays(g.nrays, T, [&](int t, int64_t id) {
+        RayOut R = trace_value(g, Pz, id);
+        if (R.status != ORC_HIT) return;
+        Dual X, Y;
+        Exit<Dual> E = trace_dual(g, Pz, R, &X, &Y);
+        int nt = (g.p + 1) * (g.q + 1);
+        double* A = acc[t].data();
+        splat<Dual>(g, X, Y, E.w, [&](int64_t pix, const Dual& v) {
+            double s = 0.0;
+            for (int l = 0; l < nt; ++l) s += v.d[l] * vdir[cp_index(g, R, l)];
+            A[pix] += s;
+        });
+        tl_nt = 0;
+    });
+    for (int64_t i = 0; i < npix; ++i) {
+        double s = 0.0;
+        for (int t = 0; t < T; ++t) s += acc[t][i];
+        dI[i] = s;
+    }
+    return ORC_OK;
+}
+
+// Adam (Kingma & Ba): m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+// P -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+int orc_adam(int64_t n, double* P, const double* g, double* m, double* v, int64_t t, double lr,
+             double beta1, double beta2, double eps) {
+    if (t < 1) return ORC_E_ARG;
+    double bc1 = 1.0 - std::pow(beta1, double(t)), bc2 = 1.0 - std::pow(beta2, double(t));
+    for (int64_t i = 0; i < n; ++i) {
+        m[i] = beta1 * m[i] + (1.0 - beta1) * g[i];
+        v[i] = beta2 * v[i] + (1.0 - beta2) * g[i] * g[i];
+        P[i] -= lr * (m[i] / bc1) / (std::sqrt(v[i] / bc2) + eps);
+    }
+    return ORC_OK;
+}
+
+uint64_t orc_rng(uint64_t seed, uint64_t stream, uint64_t index) { return rng_at(seed, stream, index); }
+
+}  // extern "C"
