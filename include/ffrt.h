@@ -1,0 +1,206 @@
+/*
+ * ffrt - differentiable freeform-lens ray tracing on AMD Instinct MI355X (gfx950).
+ *
+ * The calls follow the design problem of de Koning, Heemels, Adam, Moller (2023), "Gradient descent-based
+ * freeform optics design using algorithmic differentiable non-sequential ray tracing":
+ *   sec. 2 (problem)          min over P of L(P; I_ref), solved by gradient descent
+ *   sec. 2.1, 2.1.1, 2.1.2    plano-freeform lens: flat entry face z = z_in, exit face a clamped uniform
+ *                             B-spline height field; X, Y linear (Greville), only P^z free; P^z >= z_in + delta
+ *   sec. 2.2.1                collimated bundle, point source uniform in solid angle; sec. 3.3 grid of
+ *                             point sources approximating an extended source
+ *   sec. 2.2, 2.2.2           smallest positive root of the ray/height-field equation; refraction at both
+ *                             faces; total internal reflection dropped
+ *   sec. 2.3                  detector grid, Schlick weights, normalised Gaussian reconstruction filter,
+ *                             optional ghost pixels
+ *   sec. 2.5                  normalised images, RMS Frobenius loss, Adam on the control points
+ *
+ * Conventions for every call:
+ *  - Lengths in mm, angles in radians.  Device arrays are float32 unless stated.
+ *  - The caller owns every buffer.  A plan holds host metadata only; its device workspace is caller
+ *    allocated (ffrt_plan_workspace_size) and handed over once (ffrt_plan_set_workspace).  The compute
+ *    calls never allocate.
+ *  - A plan holds one or more designs.  Their buffers are packed back to back at the offsets given by
+ *    ffrt_plan_layout: control points P^z[i][j] row-major with i along u / x (sec. 2.1); images I[i][j]
+ *    row-major with i along x (sec. 2.3).  Ghost pixels, when enabled, enlarge the stored image.
+ *  - Compute calls are asynchronous on the given HIP stream (hipStream_t passed as void*, NULL = default
+ *    stream).  Argument and shape errors are reported at plan creation or by the call's return code;
+ *    data-dependent conditions (constraint violation, no flux, NaN, Newton non-convergence) are counted on
+ *    the device in ffrt_stats.  Nothing crosses the ABI as an exception.
+ *  - ffrt_last_error() returns a thread-local message for the last failing call.
+ */
+#ifndef FFRT_H
+#define FFRT_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FFRT_OK = 0,
+    FFRT_E_ARG = 1,          /* invalid argument or shape */
+    FFRT_E_CONSTRAINT = 2,   /* lens constraint violated (host-side check of given values) */
+    FFRT_E_NOFLUX = 3,       /* no ray reached the screen */
+    FFRT_E_HIP = 4,          /* HIP runtime error (message in ffrt_last_error) */
+    FFRT_E_OOM = 5,          /* workspace too small */
+    FFRT_E_UNSUPPORTED = 6,  /* valid but not compiled for (degree / filter-size combination) */
+    FFRT_E_STATE = 7         /* call order (e.g. no workspace set, no graph captured) */
+} ffrt_status;
+
+/* Lens (sec. 2.1 - 2.1.2).  n_u = n_1 + 1 and n_v = n_2 + 1 control points, degrees p, q.  The aperture is
+ * [-r_x, r_x] x [-r_y, r_y]; the flat entry face is z = z_in; delta_min is the minimal thickness used by
+ * the constraint count (P^z >= z_in + delta_min). */
+typedef struct {
+    double n_lens, r_x, r_y, z_in, delta_min;
+    int32_t p, q, n_u, n_v;
+} ffrt_lens;
+
+/* Source (sec. 2.2.1, sec. 3.3).
+ * kind 0: collimated bundle along +z sampled on a grid_u x grid_v grid of [0,1]^2 directly on the
+ *         freeform; ray id = k_u * grid_v + k_v.
+ * kind 1: point source at pos, cone half angle half_angle; (theta, a) stratified grid_u x grid_v;
+ *         ray id = k_theta * grid_v + k_a.
+ * kind 2: emit_nx x emit_ny point sources evenly spaced (endpoints included) over emit_wx x emit_wy around
+ *         pos, each sampled as kind 1; ray id = e * grid_u * grid_v + (per-emitter id), e = ix * emit_ny + iy.
+ * jitter 0 places samples at cell centres; 1 jitters them with 24-bit uniforms from a counter-based
+ * SplitMix64 keyed by (seed, stream 2, ray id). */
+typedef struct {
+    int32_t kind, grid_u, grid_v, jitter;
+    double pos[3];
+    double half_angle;
+    int32_t emit_nx, emit_ny;
+    double emit_wx, emit_wy;
+    uint64_t seed;
+} ffrt_source;
+
+/* Detector (sec. 2.3): n_x x n_y pixels on [-R_x, R_x) x [-R_y, R_y) at z = z_screen.  Filter
+ * f(x) = exp(-alpha ((x - c)/w)^2) - exp(-alpha (nu/2)^2) inside nu pixels (alpha per pixel width^2),
+ * normalised over the grid.  ghost = 1 adds (nu-1)/2 ghost pixels on each side. */
+typedef struct {
+    int32_t n_x, n_y;
+    double R_x, R_y, z_screen, alpha;
+    int32_t nu_x, nu_y, ghost;
+} ffrt_detector;
+
+/* fresnel: 1 applies Schlick's approximation at both faces (cosine taken on the air side), 0 does not.
+ * newton_max_iter: iteration cap of the freeform intersection (point sources), 1..32. */
+typedef struct {
+    int32_t fresnel, newton_max_iter;
+} ffrt_options;
+
+typedef struct {
+    ffrt_lens lens;
+    ffrt_source src;
+    ffrt_detector det;
+    ffrt_options opt;
+} ffrt_problem;
+
+typedef struct ffrt_plan ffrt_plan;
+
+/* Per-design counters written by ffrt_forward (device memory, one per design, zeroed by the call). */
+typedef struct {
+    float flux_on_screen;         /* sum of final weights of accepted rays (initial weight 1/N) */
+    uint32_t n_traced, n_hit, n_miss_entry, n_side_wall, n_tir, n_off_screen;
+    uint32_t n_newton_fail;       /* roots not converged within newton_max_iter */
+    uint32_t n_fp64_refined;      /* grazing hits whose residual was re-checked in double precision */
+    uint32_t n_nonmonotone;       /* rays whose root needed the bracket scan */
+    uint32_t n_constraint_viol;   /* control points below z_in + delta_min (sec. 2.1.2) */
+    uint32_t n_nan;               /* non-finite control points */
+} ffrt_stats;
+
+typedef struct {
+    float lr, beta1, beta2, eps;
+} ffrt_adam_hparams;
+
+/* ---- plan ------------------------------------------------------------------------------------------ */
+
+/* Validate n_designs problems and build a plan (host only, no HIP call).  All designs of a plan share the
+ * degrees (p, q) and filter sizes (nu_x, nu_y).  Supported: p, q in {2,3,5} pairs (3,3), (5,3), (2,2) and
+ * nu in {3, 5, 11} with nu_x = nu_y; other valid values return FFRT_E_UNSUPPORTED.  Returns FFRT_E_ARG
+ * with a message for invalid problems. */
+ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_plan** out);
+ffrt_status ffrt_plan_destroy(ffrt_plan* plan);
+
+/* Device workspace bytes the plan needs (design descriptors, knot tables, bounds, loss flags). */
+ffrt_status ffrt_plan_workspace_size(const ffrt_plan* plan, size_t* bytes);
+
+/* Hand over caller-allocated device workspace (>= the size above, 256-byte aligned) on the current
+ * device; uploads the plan's descriptors with a synchronous copy.  Must precede every compute call. */
+ffrt_status ffrt_plan_set_workspace(ffrt_plan* plan, void* dev_ptr, size_t bytes);
+
+/* Packed layout: cp_offsets[n_designs + 1] and img_offsets[n_designs + 1] (prefix sums, in elements);
+ * either may be NULL. */
+ffrt_status ffrt_plan_layout(const ffrt_plan* plan, int64_t* cp_offsets, int64_t* img_offsets);
+ffrt_status ffrt_plan_num_designs(const ffrt_plan* plan, int32_t* n);
+ffrt_status ffrt_plan_num_rays(const ffrt_plan* plan, int64_t* n);
+
+/* ---- the hot path ---------------------------------------------------------------------------------- */
+
+/* Irradiance of every design (sec. 2.3): zeroes irr and stats, traces all rays and splats them.
+ * Pz: packed control heights; irr: packed images (output); stats: n_designs ffrt_stats or NULL. */
+ffrt_status ffrt_forward(ffrt_plan* plan, const float* Pz, float* irr, ffrt_stats* stats, void* stream);
+
+/* Loss of sec. 2.5 per design and dL/dI.  loss: n_designs floats (NaN for a design without flux, whose
+ * dL/dI is then zero and whose next Adam update is skipped); dL_dI: packed like irr. */
+ffrt_status ffrt_loss(ffrt_plan* plan, const float* irr, const float* target, float* loss, float* dL_dI,
+                      void* stream);
+
+/* Pathwise gradient dL/dP^z (packed like Pz) of sum_ij dL_dI_ij I_ij: re-traces every ray (nothing per ray
+ * is stored) and back-propagates through splat, screen, refraction and the root (implicit function
+ * theorem).  Zeroes dL_dP first. */
+ffrt_status ffrt_adjoint(ffrt_plan* plan, const float* Pz, const float* dL_dI, float* dL_dP, void* stream);
+
+/* Adam on P^z in place (Kingma & Ba; bias-corrected).  m, v: packed like Pz; t: n_designs step counters
+ * in device memory, incremented by the call.  A design whose last ffrt_loss found no flux is skipped. */
+ffrt_status ffrt_adam(ffrt_plan* plan, float* Pz, const float* dL_dP, float* m, float* v, int32_t* t,
+                      const ffrt_adam_hparams* hp, void* stream);
+
+/* One optimisation step: forward, loss, adjoint, Adam (all device-side, no host synchronisation). */
+ffrt_status ffrt_step(ffrt_plan* plan, float* Pz, const float* target, float* irr, float* loss,
+                      float* dL_dI, float* dL_dP, float* m, float* v, int32_t* t, ffrt_stats* stats,
+                      const ffrt_adam_hparams* hp, void* stream);
+
+/* Capture `steps` consecutive ffrt_step calls into a HIP graph owned by the plan (stream must not be the
+ * NULL stream).  The arguments are bound at capture.  ffrt_graph_launch replays it on `stream`.
+ * timed = 1 also records HIP events immediately around every step's forward and adjoint trace kernel
+ * (event nodes of the graph, on the capturing stream); ffrt_graph_kernel_times then reports their mean
+ * durations over the steps of the last replay, once the caller has synchronised with it. */
+ffrt_status ffrt_graph_capture(ffrt_plan* plan, int32_t steps, float* Pz, const float* target, float* irr,
+                               float* loss, float* dL_dI, float* dL_dP, float* m, float* v, int32_t* t,
+                               ffrt_stats* stats, const ffrt_adam_hparams* hp, int32_t timed, void* stream);
+ffrt_status ffrt_graph_launch(ffrt_plan* plan, void* stream);
+ffrt_status ffrt_graph_kernel_times(ffrt_plan* plan, float* fwd_ms, float* adj_ms);
+
+/* ---- kernel shapes (autotuner) ------------------------------------------------------------------- */
+
+/* Number of candidate shapes for the forward (which = 0) or adjoint (which = 1) kernel, and selection. */
+ffrt_status ffrt_num_configs(int32_t which, int32_t* n);
+ffrt_status ffrt_config_name(int32_t which, int32_t index, char* buf, int32_t buflen);
+ffrt_status ffrt_plan_set_config(ffrt_plan* plan, int32_t which, int32_t index);
+ffrt_status ffrt_plan_get_config(const ffrt_plan* plan, int32_t which, int32_t* index);
+
+/* Time every candidate shape on the caller's buffers (reps launches each, HIP events, synchronises the
+ * stream) and keep the fastest for each kernel.  irr and dL_dP are overwritten. */
+ffrt_status ffrt_plan_autotune(ffrt_plan* plan, const float* Pz, float* irr, const float* dL_dI,
+                               float* dL_dP, int32_t reps, void* stream);
+
+/* ---- inspection ------------------------------------------------------------------------------------ */
+
+/* Trace individual rays of one design.  ray_ids: n int64 (device); out8: n x 8 floats (device) =
+ * {status, X, Y, w, u_hit, v_hit, t_hit, newton_iterations}; status 0 hit, 1 missed the entry face,
+ * 2 left through the side wall, 3 TIR, 4 off screen. */
+ffrt_status ffrt_trace_rays(ffrt_plan* plan, int32_t design, const float* Pz, const int64_t* ray_ids,
+                            int64_t n, float* out8, void* stream);
+
+/* The ray-sampling random numbers: out[i] = SplitMix64 output for (seed, stream, first + i) (device). */
+ffrt_status ffrt_rng(uint64_t seed, uint64_t stream_id, uint64_t first, int64_t n, uint64_t* out,
+                     void* stream);
+
+const char* ffrt_status_string(ffrt_status s);
+const char* ffrt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

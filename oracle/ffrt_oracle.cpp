@@ -386,7 +386,7 @@ struct Root { int status; double t; double margin; };
 // the bracket comes from the global convex-hull bounds (sec. 2.2.2); when the derivative bound proves f
 // strictly decreasing the root is unique and found by bisection, otherwise the bracket is scanned in steps
 // of 1/64 of a projected knot span for the first sign change.  Newton steps polish the root.
-Root find_root(const Geo& g, const double* Pz, const Entry& E) {
+Root find_root(const Geo& g, const double* Pz, const Entry& E, bool ignore_aperture = false) {
     Root R; R.status = ORC_HIT; R.t = 0.0; R.margin = 1e300;
     const double* o = E.o; const double* d = E.d;
     // Bracket widened by a rounding margin so that f(t_lo) > 0 > f(t_hi) also for a flat surface.
@@ -399,6 +399,7 @@ Root find_root(const Geo& g, const double* Pz, const Entry& E) {
         if (d[ax] > 0) t_ap = std::min(t_ap, (r[ax] - o[ax]) / d[ax]);
         else if (d[ax] < 0) t_ap = std::min(t_ap, (-r[ax] - o[ax]) / d[ax]);
     }
+    if (ignore_aperture) t_ap = std::numeric_limits<double>::infinity();
     double t_end = std::min(t_hi, t_ap);
     if (t_end < t_lo) { R.status = ORC_SIDE_WALL; R.margin = (t_lo - t_end) * d[2]; return R; }
     double f_end = f_of_t(g, Pz, E, t_end);
@@ -537,18 +538,34 @@ struct RayOut {
     Entry E;
 };
 
-// Rounding-distance thresholds for "marginal" rays whose discrete state may differ in single precision.
-constexpr double EPS_APERTURE = 1e-4;  // mm
-constexpr double EPS_SIDE = 1e-5;      // mm, |f| at the aperture exit
-constexpr double EPS_TIR = 1e-5;       // Snell discriminant
-constexpr double EPS_SCREEN = 1e-4;    // relative to the screen radius
+// Rounding-distance thresholds for "marginal" rays whose discrete state may differ in single precision
+// (about ten times the single-precision error of each quantity).
+constexpr double EPS_APERTURE = 3e-5;  // mm, entry point to the aperture edge
+constexpr double EPS_SIDE = 5e-6;      // mm, |f| at the aperture exit
+constexpr double EPS_TIR = 3e-6;       // Snell discriminant k
+constexpr double EPS_SCREEN = 3e-5;    // landing to the screen edge, relative to the screen radius
 
-RayOut trace_value(const Geo& g, const double* Pz, int64_t id) {
+// force = true ignores the entry aperture and the side wall: used only to locate, for the pixel mask, where
+// a marginal ray would land if single precision took the other side of such a decision.
+RayOut trace_value(const Geo& g, const double* Pz, int64_t id, bool force = false) {
     RayOut R;
     R.marginal = false; R.X = R.Y = R.w = 0.0; R.u = R.v = R.t = 0.0; R.su = R.sv = 0; R.k = 1.0;
     R.E = ray_entry(g, id);
-    const Entry& E = R.E;
+    Entry& E = R.E;
     if (std::fabs(E.margin) < EPS_APERTURE) R.marginal = true;
+    if (force && E.status == ORC_MISS_ENTRY) {  // continue as if the entry face were large enough
+        double theta, a, ex, ey;
+        sample_point(g, id, &theta, &a, &ex, &ey);
+        double cphi = 1.0 - (1.0 - std::cos(g.pr.half_angle)) * a;
+        double sphi = std::sqrt(std::max(0.0, 1.0 - cphi * cphi));
+        double d0[3] = {std::cos(theta) * sphi, std::sin(theta) * sphi, cphi};
+        double t0 = (g.pr.z_in - g.pr.pos_z) / d0[2];
+        double eta = 1.0 / g.pr.n_lens, k = 1.0 - eta * eta * (1.0 - cphi * cphi);
+        E.o[0] = ex + t0 * d0[0]; E.o[1] = ey + t0 * d0[1]; E.o[2] = g.pr.z_in;
+        for (int i = 0; i < 3; ++i) E.d[i] = eta * d0[i] + (i == 2 ? std::sqrt(k) - eta * cphi : 0.0);
+        E.w = g.w0;
+        E.status = ORC_HIT;
+    }
     if (E.status != ORC_HIT) { R.status = E.status; return R; }
     double q[3];
     if (E.collimated) {
@@ -556,7 +573,7 @@ RayOut trace_value(const Geo& g, const double* Pz, int64_t id) {
         q[0] = E.o[0]; q[1] = E.o[1];
         R.u = E.u; R.v = E.v;
     } else {
-        Root rt = find_root(g, Pz, E);
+        Root rt = find_root(g, Pz, E, force);
         if (rt.margin < EPS_SIDE) R.marginal = true;
         if (rt.status != ORC_HIT) { R.status = rt.status; return R; }
         R.t = rt.t;
@@ -769,10 +786,15 @@ int orc_forward(const orc_problem* pr, const double* Pz, double* irr, orc_stats*
         s.n_rays++;
         if (R.marginal) {
             s.n_marginal++;
-            if (mask && (R.status == ORC_HIT || R.status == ORC_OFF_SCREEN || R.status == ORC_TIR)) {
-                double X = std::min(std::max(R.X, -g.Rxe), std::nextafter(g.Rxe, 0.0));
-                double Y = std::min(std::max(R.Y, -g.Rye), std::nextafter(g.Rye, 0.0));
-                if (std::isfinite(X) && std::isfinite(Y)) mark_window(g, X, Y, msk[t].data());
+            if (mask) {
+                RayOut F = (R.status == ORC_MISS_ENTRY || R.status == ORC_SIDE_WALL) ? trace_value(g, Pz, id, true) : R;
+                bool landed = F.status == ORC_HIT || F.status == ORC_OFF_SCREEN ||
+                              (F.status == ORC_TIR && std::fabs(F.k) < EPS_TIR);
+                if (landed) {
+                    double X = std::min(std::max(F.X, -g.Rxe), std::nextafter(g.Rxe, 0.0));
+                    double Y = std::min(std::max(F.Y, -g.Rye), std::nextafter(g.Rye, 0.0));
+                    if (std::isfinite(X) && std::isfinite(Y)) mark_window(g, X, Y, msk[t].data());
+                }
             }
         }
         switch (R.status) {

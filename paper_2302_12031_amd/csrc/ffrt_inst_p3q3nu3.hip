@@ -1,0 +1,6 @@
+// Trace kernels compiled for degrees (p, q) = (3, 3) and filter size nu = 3.
+#include "trace.hpp"
+
+namespace ffrt {
+const KernelSet* kernel_set_p3q3nu3() { return KernelsFor<3, 3, 3>::get(); }
+}  // namespace ffrt

@@ -1,0 +1,127 @@
+// Internal descriptors shared by the host runtime and the gfx950 kernels of libffrt.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ffrt.h"
+
+namespace ffrt {
+
+constexpr int WG = 256;               // threads per workgroup: 4 wave64s
+constexpr int TILE_CAP = 6144;        // floats in the LDS irradiance tile of the forward kernel
+constexpr int MAX_DEG = 5;
+constexpr int N_SHAPES = 5;           // block shapes: rays per thread 1, 2, 4, 8, 16
+constexpr int RPT_OF_SHAPE[N_SHAPES] = {1, 2, 4, 8, 16};
+
+// Ray status codes (same meaning as the public ffrt_trace_rays status).
+enum : int { ST_HIT = 0, ST_MISS_ENTRY = 1, ST_SIDE_WALL = 2, ST_TIR = 3, ST_OFF_SCREEN = 4 };
+
+// Per-axis knot table stride (floats) for degree p: 2p local knots + p(p+1)/2 reciprocals, padded to 4.
+__host__ __device__ constexpr int kt_stride(int p) { return ((2 * p + p * (p + 1) / 2) + 3) / 4 * 4; }
+
+// One design, as the kernels see it (all float32 except layout and seed).
+struct DesignDev {
+    // lens
+    float r_x, r_y, z_in, n_lens;
+    float sxu, syv;          // d(ubar)/dx = (n_u - p) / (2 r_x), d(vbar)/dy: knot units per mm
+    float ubar0, vbar0;      // ubar at x = 0: (n_u - p) / 2
+    int32_t n_u, n_v, nsu, nsv;     // control points and knot spans per axis
+    float zmin_allowed;      // z_in + delta_min
+    // source
+    int32_t kind, grid_u, grid_v, jitter;
+    float pos_x, pos_y, pos_z, omc;  // omc = 1 - cos(phi_max)
+    int32_t emit_nx, emit_ny;
+    float ex0, edx, ey0, edy;        // emitter grid: pos + (ex0 + ix * edx, ey0 + iy * edy)
+    float inv_gu, inv_gv;            // 1 / grid_u, 1 / grid_v
+    uint64_t rng_state0;             // SplitMix64 state for (seed, stream 2)
+    // detector (effective grid, ghost pixels included)
+    int32_t nx, ny;
+    float Rx, Ry, wx, wy, inv_wx, inv_wy, z_screen, alpha, edge_x, edge_y;  // edge = exp(-alpha (nu/2)^2)
+    // options
+    int32_t fresnel, newton_max;
+    float R0, w0;                    // Schlick R0, initial ray weight 1/N
+    // layout
+    int64_t cp_off, img_off, n_rays;
+    int32_t kt_u, kt_v;              // float offsets of the knot tables (workspace)
+    int32_t per_emitter_u, pad_;     // unused padding
+};
+
+// Per-design bounds computed on the device each call (sec. 2.2.2: global convex-hull box).
+struct BoundsDev {
+    float zmin, zmax, gx, gy;        // gx, gy: bounds of |dh/dx|, |dh/dy| from derivative control points
+    float zref;                      // reference height subtracted from P^z in LDS: (zmin + zmax) / 2
+    float pad_[3];
+};
+
+// Block map of one design for one block shape.
+struct BlockMap {
+    int64_t first;                   // first logical block of the design
+    int32_t nbv, per_emitter;        // blocks along v; blocks per emitter
+};
+
+struct TraceArgs {
+    const DesignDev* designs;
+    const BoundsDev* bounds;
+    const float* knots;
+    const BlockMap* bmap;            // n_designs entries for the launch's block shape
+    int32_t n_designs;
+    int64_t n_blocks;
+    int32_t lds_cp;                  // floats of the LDS control-point array (max over designs)
+    int32_t lds_kt;                  // floats of the LDS knot tables
+    const float* Pz;
+    float* irr;                      // forward output
+    ffrt_stats* stats;               // forward stats (may be null)
+    const float* dLdI;               // adjoint input
+    float* dLdP;                     // adjoint output
+    int32_t use_tile;                // forward: LDS footprint tile
+    int32_t butterfly;               // adjoint: wave-level reduce-scatter of control-point gradients
+};
+
+struct FwdCfg { int shape; int tile; int persistent; const char* name; };
+struct AdjCfg { int shape; int butterfly; int persistent; const char* name; };
+
+constexpr FwdCfg FWD_CFGS[] = {
+    {2, 1, 0, "fwd rpt4 lds-tile"},
+    {1, 1, 0, "fwd rpt2 lds-tile"},
+    {3, 1, 0, "fwd rpt8 lds-tile"},
+    {2, 0, 0, "fwd rpt4 global-atomics"},
+    {0, 0, 0, "fwd rpt1 global-atomics"},
+    {3, 1, 1, "fwd rpt8 lds-tile persistent"},
+};
+constexpr AdjCfg ADJ_CFGS[] = {
+    {2, 1, 0, "adj rpt4 butterfly"},
+    {1, 1, 0, "adj rpt2 butterfly"},
+    {3, 1, 0, "adj rpt8 butterfly"},
+    {2, 0, 0, "adj rpt4 lds-atomics"},
+    {4, 1, 0, "adj rpt16 butterfly"},
+    {3, 1, 1, "adj rpt8 butterfly persistent"},
+};
+constexpr int N_FWD_CFGS = sizeof(FWD_CFGS) / sizeof(FWD_CFGS[0]);
+constexpr int N_ADJ_CFGS = sizeof(ADJ_CFGS) / sizeof(ADJ_CFGS[0]);
+
+// Launchers of the templated trace kernels, one set per compiled (P, Q, NU).
+struct KernelSet {
+    hipError_t (*forward)(const TraceArgs&, int shape, int grid, hipStream_t);
+    hipError_t (*adjoint)(const TraceArgs&, int shape, int grid, hipStream_t);
+    hipError_t (*trace_rays)(const TraceArgs&, int design, const int64_t* ids, int64_t n, float* out8,
+                             hipStream_t);
+};
+
+// Returns null when (P, Q, NU) is not compiled.
+const KernelSet* kernel_set(int P, int Q, int NU);
+
+// Kernels that do not depend on the degrees (ffrt_common.hip).
+hipError_t launch_zero(float* a, int64_t n, ffrt_stats* stats, int n_stats, hipStream_t s);
+hipError_t launch_bounds(const DesignDev* designs, int n_designs, const float* Pz, int p, int q,
+                         BoundsDev* bounds, ffrt_stats* stats, hipStream_t s);
+hipError_t launch_loss(const DesignDev* designs, int n_designs, const float* irr, const float* target,
+                       float* loss, float* dLdI, int32_t* valid, hipStream_t s);
+hipError_t launch_adam(const DesignDev* designs, int n_designs, float* Pz, const float* g, float* m,
+                       float* v, int32_t* t, const int32_t* valid, ffrt_adam_hparams hp, hipStream_t s);
+hipError_t launch_rng(uint64_t seed, uint64_t stream_id, uint64_t first, int64_t n, uint64_t* out,
+                      hipStream_t s);
+
+// Host-side SplitMix64 state (same published definition as the device generator).
+uint64_t splitmix_state0(uint64_t seed, uint64_t stream_id);
+
+}  // namespace ffrt

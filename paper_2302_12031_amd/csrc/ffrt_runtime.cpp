@@ -1,0 +1,634 @@
+// Host runtime of libffrt: plan validation, workspace layout, launches, HIP graph capture and the kernel
+// shape autotuner.  Implements the C ABI declared in include/ffrt.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ffrt_internal.h"
+
+namespace ffrt {
+const KernelSet* kernel_set_p3q3nu3();
+const KernelSet* kernel_set_p3q3nu5();
+const KernelSet* kernel_set_p3q3nu11();
+const KernelSet* kernel_set_p5q3nu3();
+const KernelSet* kernel_set_p2q2nu3();
+
+const KernelSet* kernel_set(int P, int Q, int NU) {
+    if (P == 3 && Q == 3 && NU == 3) return kernel_set_p3q3nu3();
+    if (P == 3 && Q == 3 && NU == 5) return kernel_set_p3q3nu5();
+    if (P == 3 && Q == 3 && NU == 11) return kernel_set_p3q3nu11();
+    if (P == 5 && Q == 3 && NU == 3) return kernel_set_p5q3nu3();
+    if (P == 2 && Q == 2 && NU == 3) return kernel_set_p2q2nu3();
+    return nullptr;
+}
+}  // namespace ffrt
+
+using namespace ffrt;
+
+namespace {
+
+thread_local std::string g_err;
+
+ffrt_status fail(ffrt_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+ffrt_status hip_fail(hipError_t e, const char* where) {
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return FFRT_E_HIP;
+}
+
+#define HIP_TRY(expr)                                      \
+    do {                                                   \
+        hipError_t _e = (expr);                            \
+        if (_e != hipSuccess) return hip_fail(_e, #expr);  \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct ShapeDims { int BU, BV; };
+ShapeDims shape_dims(int shape) {
+    int rpt = RPT_OF_SHAPE[shape];
+    int PU = (shape == 0) ? 2 : (shape <= 2 ? 4 : 8);
+    int PV = 4 * rpt / PU;
+    return {8 * PU, 8 * PV};
+}
+
+}  // namespace
+
+struct ffrt_plan {
+    std::vector<ffrt_problem> probs;
+    int nd = 0, P = 3, Q = 3, NU = 3;
+    const KernelSet* ks = nullptr;
+    std::vector<DesignDev> dd;
+    std::vector<int64_t> cp_off, img_off;
+    int64_t total_cp = 0, total_img = 0, total_rays = 0;
+    int max_cp = 0, max_kt = 0;
+    std::vector<float> knots;
+    std::vector<BlockMap> bmaps[N_SHAPES];
+    int64_t nblocks[N_SHAPES] = {};
+    // workspace
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t off_designs = 0, off_bounds = 0, off_valid = 0, off_knots = 0, off_bmap = 0, need = 0;
+    int num_cu = 256;
+    int fwd_cfg = 0, adj_cfg = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<hipEvent_t> gev;      // timed graphs: 4 events per step (fwd start/stop, adj start/stop)
+    int gsteps = 0;
+
+    DesignDev* d_designs() const { return reinterpret_cast<DesignDev*>(ws + off_designs); }
+    BoundsDev* d_bounds() const { return reinterpret_cast<BoundsDev*>(ws + off_bounds); }
+    int32_t* d_valid() const { return reinterpret_cast<int32_t*>(ws + off_valid); }
+    float* d_knots() const { return reinterpret_cast<float*>(ws + off_knots); }
+    BlockMap* d_bmap(int shape) const {
+        return reinterpret_cast<BlockMap*>(ws + off_bmap) + (size_t)shape * nd;
+    }
+};
+
+namespace {
+
+bool odd3(int v) { return v >= 3 && (v % 2) == 1; }
+
+ffrt_status validate(const ffrt_problem& pr, int idx) {
+    char b[256];
+    auto bad = [&](const char* what) {
+        snprintf(b, sizeof b, "design %d: %s", idx, what);
+        return fail(FFRT_E_ARG, b);
+    };
+    const ffrt_lens& L = pr.lens;
+    const ffrt_source& S = pr.src;
+    const ffrt_detector& D = pr.det;
+    if (L.p < 1 || L.q < 1 || L.p > MAX_DEG || L.q > MAX_DEG) return bad("degrees must be in [1, 5]");
+    if (L.n_u <= L.p || L.n_v <= L.q) return bad("need more control points than the degree");
+    if ((int64_t)L.n_u * L.n_v > 4096 || L.n_u - L.p > 64 || L.n_v - L.q > 64)
+        return bad("control net larger than 64 x 64");
+    if (!(L.n_lens > 1.0) || !std::isfinite(L.n_lens)) return bad("n_lens must be > 1");
+    if (!(L.r_x > 0) || !(L.r_y > 0)) return bad("aperture half widths must be > 0");
+    if (!(L.delta_min >= 0)) return bad("delta_min must be >= 0");
+    if (S.kind < 0 || S.kind > 2) return bad("source kind must be 0, 1 or 2");
+    if (S.grid_u < 1 || S.grid_v < 1 || S.grid_u > (1 << 24) || S.grid_v > (1 << 24)) return bad("bad sample grid");
+    if (S.jitter != 0 && S.jitter != 1) return bad("jitter must be 0 or 1");
+    if (S.kind != 0) {
+        if (!(S.pos[2] < L.z_in)) return bad("point source must lie below the entry face");
+        if (!(S.half_angle >= 0 && S.half_angle < M_PI / 2)) return bad("half angle must be in [0, pi/2)");
+        if (S.kind == 2 && (S.emit_nx < 1 || S.emit_ny < 1 || !(S.emit_wx >= 0) || !(S.emit_wy >= 0)))
+            return bad("bad emitter grid");
+    }
+    if (D.n_x < 1 || D.n_y < 1 || D.n_x > 8192 || D.n_y > 8192) return bad("bad detector resolution");
+    if (!(D.R_x > 0) || !(D.R_y > 0)) return bad("screen radii must be > 0");
+    if (!(D.alpha > 0)) return bad("alpha must be > 0");
+    if (!odd3(D.nu_x) || !odd3(D.nu_y)) return bad("filter sizes must be odd and >= 3");
+    if (D.ghost != 0 && D.ghost != 1) return bad("ghost must be 0 or 1");
+    if (!(D.z_screen > L.z_in)) return bad("screen must lie above the entry face");
+    if (pr.opt.fresnel != 0 && pr.opt.fresnel != 1) return bad("fresnel must be 0 or 1");
+    if (pr.opt.newton_max_iter < 1 || pr.opt.newton_max_iter > 32) return bad("newton_max_iter in [1, 32]");
+    int64_t n = (int64_t)S.grid_u * S.grid_v * (S.kind == 2 ? (int64_t)S.emit_nx * S.emit_ny : 1);
+    if (n > ((int64_t)1 << 40)) return bad("too many rays");
+    return FFRT_OK;
+}
+
+// Knot table of one axis (see span_basis): for span k, local knots kap(o) = clamp(o, -k, nspan - k) for
+// o = 1-p..p, then 1 / (kap(j) - kap(j - deg)) for deg = 1..p, j = 1..deg (0 for zero-length intervals).
+void build_knot_table(int p, int nspan, std::vector<float>& out) {
+    const int st = kt_stride(p);
+    for (int k = 0; k < nspan; ++k) {
+        std::vector<float> row(st, 0.0f);
+        auto kap = [&](int o) { return std::min(std::max(o, -k), nspan - k); };
+        for (int o = 1 - p; o <= p; ++o) row[o + p - 1] = (float)kap(o);
+        int idx = 2 * p;
+        for (int deg = 1; deg <= p; ++deg)
+            for (int j = 1; j <= deg; ++j) {
+                int diff = kap(j) - kap(j - deg);
+                row[idx++] = diff > 0 ? (float)(1.0 / diff) : 0.0f;
+            }
+        out.insert(out.end(), row.begin(), row.end());
+    }
+}
+
+DesignDev make_design(const ffrt_problem& pr, int64_t cp_off, int64_t img_off, int kt_u, int kt_v) {
+    DesignDev d;
+    std::memset(&d, 0, sizeof d);
+    const ffrt_lens& L = pr.lens;
+    const ffrt_source& S = pr.src;
+    const ffrt_detector& D = pr.det;
+    d.r_x = (float)L.r_x;
+    d.r_y = (float)L.r_y;
+    d.z_in = (float)L.z_in;
+    d.n_lens = (float)L.n_lens;
+    d.n_u = L.n_u;
+    d.n_v = L.n_v;
+    d.nsu = L.n_u - L.p;
+    d.nsv = L.n_v - L.q;
+    d.sxu = (float)(d.nsu / (2.0 * L.r_x));
+    d.syv = (float)(d.nsv / (2.0 * L.r_y));
+    d.ubar0 = 0.5f * (float)d.nsu;
+    d.vbar0 = 0.5f * (float)d.nsv;
+    d.zmin_allowed = (float)(L.z_in + L.delta_min);
+    d.kind = S.kind;
+    d.grid_u = S.grid_u;
+    d.grid_v = S.grid_v;
+    d.jitter = S.jitter;
+    d.pos_x = (float)S.pos[0];
+    d.pos_y = (float)S.pos[1];
+    d.pos_z = (float)S.pos[2];
+    d.omc = (float)(1.0 - std::cos(S.half_angle));
+    d.emit_nx = S.kind == 2 ? S.emit_nx : 1;
+    d.emit_ny = S.kind == 2 ? S.emit_ny : 1;
+    d.ex0 = (S.kind == 2 && S.emit_nx > 1) ? (float)(-0.5 * S.emit_wx) : 0.0f;
+    d.edx = (S.kind == 2 && S.emit_nx > 1) ? (float)(S.emit_wx / (S.emit_nx - 1)) : 0.0f;
+    d.ey0 = (S.kind == 2 && S.emit_ny > 1) ? (float)(-0.5 * S.emit_wy) : 0.0f;
+    d.edy = (S.kind == 2 && S.emit_ny > 1) ? (float)(S.emit_wy / (S.emit_ny - 1)) : 0.0f;
+    d.inv_gu = (float)(1.0 / S.grid_u);
+    d.inv_gv = (float)(1.0 / S.grid_v);
+    d.rng_state0 = splitmix_state0(S.seed, 2);
+    double wx = 2.0 * D.R_x / D.n_x, wy = 2.0 * D.R_y / D.n_y;
+    if (D.ghost) {
+        d.nx = D.n_x + D.nu_x - 1;
+        d.ny = D.n_y + D.nu_y - 1;
+        d.Rx = (float)(D.R_x + 0.5 * (D.nu_x - 1) * wx);
+        d.Ry = (float)(D.R_y + 0.5 * (D.nu_y - 1) * wy);
+    } else {
+        d.nx = D.n_x;
+        d.ny = D.n_y;
+        d.Rx = (float)D.R_x;
+        d.Ry = (float)D.R_y;
+    }
+    d.wx = (float)wx;
+    d.wy = (float)wy;
+    d.inv_wx = (float)(1.0 / wx);
+    d.inv_wy = (float)(1.0 / wy);
+    d.z_screen = (float)D.z_screen;
+    d.alpha = (float)D.alpha;
+    d.edge_x = (float)std::exp(-D.alpha * 0.25 * D.nu_x * D.nu_x);
+    d.edge_y = (float)std::exp(-D.alpha * 0.25 * D.nu_y * D.nu_y);
+    d.fresnel = pr.opt.fresnel;
+    d.newton_max = pr.opt.newton_max_iter;
+    double r0 = (L.n_lens - 1.0) / (L.n_lens + 1.0);
+    d.R0 = (float)(r0 * r0);
+    int64_t n = (int64_t)S.grid_u * S.grid_v * d.emit_nx * d.emit_ny;
+    d.n_rays = n;
+    d.w0 = (float)(1.0 / (double)n);
+    d.cp_off = cp_off;
+    d.img_off = img_off;
+    d.kt_u = kt_u;
+    d.kt_v = kt_v;
+    return d;
+}
+
+bool ready(ffrt_plan* p) { return p && p->ws; }
+
+void free_graph_events(ffrt_plan* p) {
+    for (auto e : p->gev)
+        if (e) (void)hipEventDestroy(e);
+    p->gev.clear();
+    p->gsteps = 0;
+}
+
+TraceArgs make_args(ffrt_plan* pl, int shape) {
+    TraceArgs A;
+    std::memset(&A, 0, sizeof A);
+    A.designs = pl->d_designs();
+    A.bounds = pl->d_bounds();
+    A.knots = pl->d_knots();
+    A.bmap = pl->d_bmap(shape);
+    A.n_designs = pl->nd;
+    A.n_blocks = pl->nblocks[shape];
+    A.lds_cp = (pl->max_cp + 3) / 4 * 4;
+    A.lds_kt = (pl->max_kt + 3) / 4 * 4;
+    return A;
+}
+
+int grid_for(ffrt_plan* pl, int shape, int persistent) {
+    int64_t nb = pl->nblocks[shape];
+    int64_t g = nb;
+    if (persistent) g = std::min<int64_t>(nb, (int64_t)pl->num_cu * 4);
+    if (g > 0x7FFFFFFF) g = 0x7FFFFFFF;
+    return (int)std::max<int64_t>(g, 1);
+}
+
+// ev: optional pair of events recorded immediately around the trace kernel.
+ffrt_status run_forward(ffrt_plan* pl, const float* Pz, float* irr, ffrt_stats* stats, hipStream_t s,
+                        hipEvent_t* ev = nullptr) {
+    HIP_TRY(launch_zero(irr, pl->total_img, stats, stats ? pl->nd : 0, s));
+    HIP_TRY(launch_bounds(pl->d_designs(), pl->nd, Pz, pl->P, pl->Q, pl->d_bounds(), stats, s));
+    const FwdCfg& c = FWD_CFGS[pl->fwd_cfg];
+    TraceArgs A = make_args(pl, c.shape);
+    A.Pz = Pz;
+    A.irr = irr;
+    A.stats = stats;
+    A.use_tile = c.tile;
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(pl->ks->forward(A, c.shape, grid_for(pl, c.shape, c.persistent), s));
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    return FFRT_OK;
+}
+
+ffrt_status run_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, float* dLdP, bool need_bounds,
+                        hipStream_t s, hipEvent_t* ev = nullptr) {
+    HIP_TRY(launch_zero(dLdP, pl->total_cp, nullptr, 0, s));
+    if (need_bounds) HIP_TRY(launch_bounds(pl->d_designs(), pl->nd, Pz, pl->P, pl->Q, pl->d_bounds(), nullptr, s));
+    const AdjCfg& c = ADJ_CFGS[pl->adj_cfg];
+    TraceArgs A = make_args(pl, c.shape);
+    A.Pz = Pz;
+    A.dLdI = dLdI;
+    A.dLdP = dLdP;
+    A.butterfly = c.butterfly;
+    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(pl->ks->adjoint(A, c.shape, grid_for(pl, c.shape, c.persistent), s));
+    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
+    return FFRT_OK;
+}
+
+ffrt_status run_step(ffrt_plan* pl, float* Pz, const float* target, float* irr, float* loss, float* dLdI,
+                     float* dLdP, float* m, float* v, int32_t* t, ffrt_stats* stats, const ffrt_adam_hparams& hp,
+                     hipStream_t s, hipEvent_t* ev = nullptr) {
+    ffrt_status st = run_forward(pl, Pz, irr, stats, s, ev);
+    if (st) return st;
+    HIP_TRY(launch_loss(pl->d_designs(), pl->nd, irr, target, loss, dLdI, pl->d_valid(), s));
+    st = run_adjoint(pl, Pz, dLdI, dLdP, false, s, ev ? ev + 2 : nullptr);
+    if (st) return st;
+    HIP_TRY(launch_adam(pl->d_designs(), pl->nd, Pz, dLdP, m, v, t, pl->d_valid(), hp, s));
+    return FFRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ffrt_status_string(ffrt_status s) {
+    switch (s) {
+        case FFRT_OK: return "ok";
+        case FFRT_E_ARG: return "invalid argument";
+        case FFRT_E_CONSTRAINT: return "lens constraint violated";
+        case FFRT_E_NOFLUX: return "no flux on the screen";
+        case FFRT_E_HIP: return "HIP error";
+        case FFRT_E_OOM: return "workspace too small";
+        case FFRT_E_UNSUPPORTED: return "unsupported configuration";
+        case FFRT_E_STATE: return "invalid call order";
+    }
+    return "unknown status";
+}
+
+const char* ffrt_last_error(void) { return g_err.c_str(); }
+
+ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_plan** out) {
+    if (!out) return fail(FFRT_E_ARG, "out is null");
+    *out = nullptr;
+    if (!probs || n_designs < 1) return fail(FFRT_E_ARG, "need at least one design");
+    for (int i = 0; i < n_designs; ++i) {
+        ffrt_status s = validate(probs[i], i);
+        if (s) return s;
+    }
+    const ffrt_problem& p0 = probs[0];
+    for (int i = 1; i < n_designs; ++i) {
+        const ffrt_problem& pi = probs[i];
+        if (pi.lens.p != p0.lens.p || pi.lens.q != p0.lens.q || pi.det.nu_x != p0.det.nu_x ||
+            pi.det.nu_y != p0.det.nu_y)
+            return fail(FFRT_E_ARG, "all designs of a plan must share degrees and filter sizes");
+    }
+    if (p0.det.nu_x != p0.det.nu_y) return fail(FFRT_E_UNSUPPORTED, "nu_x != nu_y is not compiled");
+    const KernelSet* ks = kernel_set(p0.lens.p, p0.lens.q, p0.det.nu_x);
+    if (!ks) return fail(FFRT_E_UNSUPPORTED, "(p, q, nu) combination not compiled");
+    ffrt_plan* pl = new ffrt_plan();
+    pl->probs.assign(probs, probs + n_designs);
+    pl->nd = n_designs;
+    pl->P = p0.lens.p;
+    pl->Q = p0.lens.q;
+    pl->NU = p0.det.nu_x;
+    pl->ks = ks;
+    int64_t cp = 0, img = 0;
+    for (int i = 0; i < n_designs; ++i) {
+        const ffrt_problem& pr = probs[i];
+        int kt_u = (int)pl->knots.size();
+        build_knot_table(pr.lens.p, pr.lens.n_u - pr.lens.p, pl->knots);
+        int kt_v = (int)pl->knots.size();
+        build_knot_table(pr.lens.q, pr.lens.n_v - pr.lens.q, pl->knots);
+        DesignDev d = make_design(pr, cp, img, kt_u, kt_v);
+        pl->dd.push_back(d);
+        pl->cp_off.push_back(cp);
+        pl->img_off.push_back(img);
+        cp += (int64_t)d.n_u * d.n_v;
+        img += (int64_t)d.nx * d.ny;
+        pl->total_rays += d.n_rays;
+        pl->max_cp = std::max(pl->max_cp, d.n_u * d.n_v);
+        pl->max_kt = std::max(pl->max_kt, d.nsu * kt_stride(pl->P) + d.nsv * kt_stride(pl->Q));
+    }
+    pl->cp_off.push_back(cp);
+    pl->img_off.push_back(img);
+    pl->total_cp = cp;
+    pl->total_img = img;
+    for (int sh = 0; sh < N_SHAPES; ++sh) {
+        ShapeDims sd = shape_dims(sh);
+        int64_t first = 0;
+        for (int i = 0; i < n_designs; ++i) {
+            const DesignDev& d = pl->dd[i];
+            int nbu = (d.grid_u + sd.BU - 1) / sd.BU, nbv = (d.grid_v + sd.BV - 1) / sd.BV;
+            BlockMap bm;
+            bm.first = first;
+            bm.nbv = nbv;
+            bm.per_emitter = nbu * nbv;
+            pl->bmaps[sh].push_back(bm);
+            first += (int64_t)bm.per_emitter * d.emit_nx * d.emit_ny;
+        }
+        pl->nblocks[sh] = first;
+    }
+    size_t off = 0;
+    pl->off_designs = off;
+    off = align256(off + sizeof(DesignDev) * n_designs);
+    pl->off_bounds = off;
+    off = align256(off + sizeof(BoundsDev) * n_designs);
+    pl->off_valid = off;
+    off = align256(off + sizeof(int32_t) * n_designs);
+    pl->off_knots = off;
+    off = align256(off + sizeof(float) * pl->knots.size());
+    pl->off_bmap = off;
+    off = align256(off + sizeof(BlockMap) * N_SHAPES * n_designs);
+    pl->need = off;
+    *out = pl;
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_plan_destroy(ffrt_plan* plan) {
+    if (!plan) return FFRT_OK;
+    free_graph_events(plan);
+    if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    delete plan;
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_plan_workspace_size(const ffrt_plan* plan, size_t* bytes) {
+    if (!plan || !bytes) return fail(FFRT_E_ARG, "null argument");
+    *bytes = plan->need;
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_plan_set_workspace(ffrt_plan* plan, void* dev_ptr, size_t bytes) {
+    if (!plan || !dev_ptr) return fail(FFRT_E_ARG, "null argument");
+    if (bytes < plan->need) return fail(FFRT_E_OOM, "workspace smaller than ffrt_plan_workspace_size");
+    if (reinterpret_cast<uintptr_t>(dev_ptr) % 256) return fail(FFRT_E_ARG, "workspace must be 256-byte aligned");
+    plan->ws = static_cast<char*>(dev_ptr);
+    plan->ws_bytes = bytes;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    int ncu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    plan->num_cu = ncu > 0 ? ncu : 256;
+    HIP_TRY(hipMemcpy(plan->d_designs(), plan->dd.data(), sizeof(DesignDev) * plan->nd, hipMemcpyHostToDevice));
+    std::vector<int32_t> ones(plan->nd, 1);
+    HIP_TRY(hipMemcpy(plan->d_valid(), ones.data(), sizeof(int32_t) * plan->nd, hipMemcpyHostToDevice));
+    if (!plan->knots.empty())
+        HIP_TRY(hipMemcpy(plan->d_knots(), plan->knots.data(), sizeof(float) * plan->knots.size(),
+                          hipMemcpyHostToDevice));
+    for (int sh = 0; sh < N_SHAPES; ++sh)
+        HIP_TRY(hipMemcpy(plan->d_bmap(sh), plan->bmaps[sh].data(), sizeof(BlockMap) * plan->nd,
+                          hipMemcpyHostToDevice));
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_plan_layout(const ffrt_plan* plan, int64_t* cp_offsets, int64_t* img_offsets) {
+    if (!plan) return fail(FFRT_E_ARG, "null plan");
+    if (cp_offsets) std::copy(plan->cp_off.begin(), plan->cp_off.end(), cp_offsets);
+    if (img_offsets) std::copy(plan->img_off.begin(), plan->img_off.end(), img_offsets);
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_plan_num_designs(const ffrt_plan* plan, int32_t* n) {
+    if (!plan || !n) return fail(FFRT_E_ARG, "null argument");
+    *n = plan->nd;
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_plan_num_rays(const ffrt_plan* plan, int64_t* n) {
+    if (!plan || !n) return fail(FFRT_E_ARG, "null argument");
+    *n = plan->total_rays;
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_forward(ffrt_plan* plan, const float* Pz, float* irr, ffrt_stats* stats, void* stream) {
+    if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
+    if (!Pz || !irr) return fail(FFRT_E_ARG, "null buffer");
+    return run_forward(plan, Pz, irr, stats, (hipStream_t)stream);
+}
+
+ffrt_status ffrt_loss(ffrt_plan* plan, const float* irr, const float* target, float* loss, float* dL_dI,
+                      void* stream) {
+    if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
+    if (!irr || !target || !loss || !dL_dI) return fail(FFRT_E_ARG, "null buffer");
+    HIP_TRY(launch_loss(plan->d_designs(), plan->nd, irr, target, loss, dL_dI, plan->d_valid(), (hipStream_t)stream));
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_adjoint(ffrt_plan* plan, const float* Pz, const float* dL_dI, float* dL_dP, void* stream) {
+    if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
+    if (!Pz || !dL_dI || !dL_dP) return fail(FFRT_E_ARG, "null buffer");
+    return run_adjoint(plan, Pz, dL_dI, dL_dP, true, (hipStream_t)stream);
+}
+
+ffrt_status ffrt_adam(ffrt_plan* plan, float* Pz, const float* dL_dP, float* m, float* v, int32_t* t,
+                      const ffrt_adam_hparams* hp, void* stream) {
+    if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
+    if (!Pz || !dL_dP || !m || !v || !t || !hp) return fail(FFRT_E_ARG, "null buffer");
+    HIP_TRY(launch_adam(plan->d_designs(), plan->nd, Pz, dL_dP, m, v, t, plan->d_valid(), *hp, (hipStream_t)stream));
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_step(ffrt_plan* plan, float* Pz, const float* target, float* irr, float* loss, float* dL_dI,
+                      float* dL_dP, float* m, float* v, int32_t* t, ffrt_stats* stats, const ffrt_adam_hparams* hp,
+                      void* stream) {
+    if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
+    if (!Pz || !target || !irr || !loss || !dL_dI || !dL_dP || !m || !v || !t || !hp)
+        return fail(FFRT_E_ARG, "null buffer");
+    return run_step(plan, Pz, target, irr, loss, dL_dI, dL_dP, m, v, t, stats, *hp, (hipStream_t)stream);
+}
+
+ffrt_status ffrt_graph_capture(ffrt_plan* plan, int32_t steps, float* Pz, const float* target, float* irr,
+                               float* loss, float* dL_dI, float* dL_dP, float* m, float* v, int32_t* t,
+                               ffrt_stats* stats, const ffrt_adam_hparams* hp, int32_t timed, void* stream) {
+    if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
+    if (!stream) return fail(FFRT_E_ARG, "graph capture needs a non-default stream");
+    if (steps < 1) return fail(FFRT_E_ARG, "steps must be >= 1");
+    if (!Pz || !target || !irr || !loss || !dL_dI || !dL_dP || !m || !v || !t || !hp)
+        return fail(FFRT_E_ARG, "null buffer");
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->gexec) { (void)hipGraphExecDestroy(plan->gexec); plan->gexec = nullptr; }
+    if (plan->graph) { (void)hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+    free_graph_events(plan);
+    if (timed) {
+        plan->gev.resize((size_t)4 * steps, nullptr);
+        for (auto& e : plan->gev) HIP_TRY(hipEventCreate(&e));
+        plan->gsteps = steps;
+    }
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    ffrt_status st = FFRT_OK;
+    for (int i = 0; i < steps && st == FFRT_OK; ++i)
+        st = run_step(plan, Pz, target, irr, loss, dL_dI, dL_dP, m, v, t, stats, *hp, s,
+                      timed ? &plan->gev[(size_t)4 * i] : nullptr);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(e, "hipGraphInstantiate"); }
+    plan->graph = g;
+    plan->gexec = ge;
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_graph_launch(ffrt_plan* plan, void* stream) {
+    if (!plan || !plan->gexec) return fail(FFRT_E_STATE, "no graph captured");
+    HIP_TRY(hipGraphLaunch(plan->gexec, (hipStream_t)stream));
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_graph_kernel_times(ffrt_plan* plan, float* fwd_ms, float* adj_ms) {
+    if (!plan || !fwd_ms || !adj_ms) return fail(FFRT_E_ARG, "null argument");
+    if (!plan->gexec || plan->gev.empty()) return fail(FFRT_E_STATE, "no timed graph captured");
+    double f = 0.0, a = 0.0;
+    for (int i = 0; i < plan->gsteps; ++i) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, plan->gev[4 * i], plan->gev[4 * i + 1]));
+        f += ms;
+        HIP_TRY(hipEventElapsedTime(&ms, plan->gev[4 * i + 2], plan->gev[4 * i + 3]));
+        a += ms;
+    }
+    *fwd_ms = (float)(f / plan->gsteps);
+    *adj_ms = (float)(a / plan->gsteps);
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_num_configs(int32_t which, int32_t* n) {
+    if (!n || (which != 0 && which != 1)) return fail(FFRT_E_ARG, "which must be 0 or 1");
+    *n = which == 0 ? N_FWD_CFGS : N_ADJ_CFGS;
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_config_name(int32_t which, int32_t index, char* buf, int32_t buflen) {
+    int32_t n = 0;
+    if (ffrt_num_configs(which, &n)) return FFRT_E_ARG;
+    if (index < 0 || index >= n || !buf || buflen < 1) return fail(FFRT_E_ARG, "bad index or buffer");
+    const char* name = which == 0 ? FWD_CFGS[index].name : ADJ_CFGS[index].name;
+    snprintf(buf, (size_t)buflen, "%s", name);
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_plan_set_config(ffrt_plan* plan, int32_t which, int32_t index) {
+    int32_t n = 0;
+    if (!plan) return fail(FFRT_E_ARG, "null plan");
+    if (ffrt_num_configs(which, &n)) return FFRT_E_ARG;
+    if (index < 0 || index >= n) return fail(FFRT_E_ARG, "config index out of range");
+    if (which == 0) plan->fwd_cfg = index; else plan->adj_cfg = index;
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_plan_get_config(const ffrt_plan* plan, int32_t which, int32_t* index) {
+    if (!plan || !index || (which != 0 && which != 1)) return fail(FFRT_E_ARG, "bad argument");
+    *index = which == 0 ? plan->fwd_cfg : plan->adj_cfg;
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_plan_autotune(ffrt_plan* plan, const float* Pz, float* irr, const float* dL_dI, float* dL_dP,
+                               int32_t reps, void* stream) {
+    if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
+    if (!Pz || !irr || !dL_dI || !dL_dP || reps < 1) return fail(FFRT_E_ARG, "bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    ffrt_status st = FFRT_OK;
+    for (int which = 0; which < 2 && st == FFRT_OK; ++which) {
+        int n = which == 0 ? N_FWD_CFGS : N_ADJ_CFGS;
+        int best = 0;
+        float best_ms = 1e30f;
+        for (int c = 0; c < n && st == FFRT_OK; ++c) {
+            if (which == 0) plan->fwd_cfg = c; else plan->adj_cfg = c;
+            // one untimed launch, then reps timed
+            st = which == 0 ? run_forward(plan, Pz, irr, nullptr, s) : run_adjoint(plan, Pz, dL_dI, dL_dP, true, s);
+            if (st) break;
+            if (hipEventRecord(e0, s) != hipSuccess) { st = hip_fail(hipGetLastError(), "hipEventRecord"); break; }
+            for (int r = 0; r < reps && st == FFRT_OK; ++r)
+                st = which == 0 ? run_forward(plan, Pz, irr, nullptr, s) : run_adjoint(plan, Pz, dL_dI, dL_dP, true, s);
+            if (st) break;
+            hipError_t e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { st = hip_fail(e, "autotune timing"); break; }
+            if (ms < best_ms) { best_ms = ms; best = c; }
+        }
+        if (which == 0) plan->fwd_cfg = best; else plan->adj_cfg = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+ffrt_status ffrt_trace_rays(ffrt_plan* plan, int32_t design, const float* Pz, const int64_t* ray_ids, int64_t n,
+                            float* out8, void* stream) {
+    if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
+    if (design < 0 || design >= plan->nd || !Pz || (n > 0 && (!ray_ids || !out8)) || n < 0)
+        return fail(FFRT_E_ARG, "bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_bounds(plan->d_designs(), plan->nd, Pz, plan->P, plan->Q, plan->d_bounds(), nullptr, s));
+    TraceArgs A = make_args(plan, 0);
+    A.Pz = Pz;
+    HIP_TRY(plan->ks->trace_rays(A, design, ray_ids, n, out8, s));
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_rng(uint64_t seed, uint64_t stream_id, uint64_t first, int64_t n, uint64_t* out, void* stream) {
+    if (n < 0 || (n > 0 && !out)) return fail(FFRT_E_ARG, "bad argument");
+    HIP_TRY(launch_rng(seed, stream_id, first, n, out, (hipStream_t)stream));
+    return FFRT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1027 @@
+// gfx950 device code of the tracer: ray sampling, B-spline evaluation from LDS, freeform intersection,
+// refraction, splatting (forward) and the hand-written reverse sweep (adjoint).  Templated on the degrees
+// P, Q and the filter size NU; included by one translation unit per compiled combination.
+//
+// Layout of one workgroup (256 threads = 4 wave64s) working on a block of rays:
+//   - the block is a BU x BV patch of the source's sample grid (collimated: (u, v); point: (theta, a)),
+//     split in 8x8 sub-patches, one per wave and round, so the 64 lanes of a wave trace neighbouring rays;
+//   - the design's control heights and both knot tables are staged in LDS once per design;
+//   - forward: rays are traced into registers, the workgroup reduces the pixel footprint of the block and,
+//     when it fits, splats into a privatised LDS tile that is merged into HBM with one global atomic per
+//     touched pixel;
+//   - adjoint: every ray is re-traced, dL/dI is gathered over its filter window, the reverse sweep gives
+//     dL/dP for the (P+1)(Q+1) control points of the hit span, reduced across the wave when all its lanes
+//     share the span, and accumulated in a privatised LDS copy of the control net.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "ffrt_internal.h"
+
+namespace ffrt {
+
+// ------------------------------------------------------------------------------------------------
+// Scalar helpers
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcpd(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp_any(float x) { return rcpf(x); }
+__device__ __forceinline__ double rcp_any(double x) { return rcpd(x); }
+
+// SplitMix64 (Steele, Lea & Flood 2014) in counter form: output `index` of the sequence whose state starts
+// at state0 = mix(seed + stream * gamma).
+__device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ uint64_t splitmix_at(uint64_t state0, uint64_t index) {
+    return splitmix_mix(state0 + (index + 1) * 0x9E3779B97F4A7C15ull);
+}
+// Two 24-bit uniforms in [0, 1), exact in float.
+__device__ __forceinline__ void two_uniforms(uint64_t h, float& a, float& b) {
+    a = (float)(uint32_t)(h >> 40) * (1.0f / 16777216.0f);
+    b = (float)(uint32_t)((h >> 16) & 0xFFFFFFull) * (1.0f / 16777216.0f);
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+// ------------------------------------------------------------------------------------------------
+// B-spline basis from the LDS knot table of one span (sec. 2.1).
+// Knot units: ubar = u (n - p), so the clamped knots are the integers clamp(i - p, 0, n - p).  The table
+// of span k holds the local knots kap(o) = clamp(o, -k, nspan - k), o = 1-P..P, followed by the
+// reciprocals rec(deg, j) = 1 / (kap(j) - kap(j - deg)) (0 for a zero-length interval), deg = 1..P,
+// j = 1..deg.  The Cox-de Boor recursion then reads
+//   N_{m,deg}(t) = (t - kap(m-deg)) rec(deg,m) N_{m-1,deg-1} + (kap(m+1) - t) rec(deg,m+1) N_{m,deg-1}
+// for the nonzero functions m = 0..deg of the span, t = ubar - k in [0, 1].
+// Derivatives (d/d ubar): N'_{m,P} = P (rec(P,m) N_{m-1,P-1} - rec(P,m+1) N_{m,P-1}); second derivatives
+// apply the same rule to the degree P-1 derivatives.
+// ------------------------------------------------------------------------------------------------
+template <int P, bool D2, class T>
+__device__ __forceinline__ void span_basis(const float* __restrict__ kt, T t, T* N, T* dN, T* d2N) {
+    constexpr int NREC = P * (P + 1) / 2;
+    T kap[2 * P];
+    T rec[NREC];
+#pragma unroll
+    for (int i = 0; i < 2 * P; ++i) kap[i] = (T)kt[i];
+#pragma unroll
+    for (int i = 0; i < NREC; ++i) rec[i] = (T)kt[2 * P + i];
+#define KAP(o) kap[(o) + P - 1]
+#define REC(deg, j) rec[((deg) - 1) * (deg) / 2 + (j) - 1]
+    T tb[P + 1][P + 1];
+    tb[0][0] = (T)1;
+#pragma unroll
+    for (int deg = 1; deg <= P; ++deg) {
+#pragma unroll
+        for (int m = 0; m <= deg; ++m) {
+            T acc = (T)0;
+            if (m >= 1) acc += (t - KAP(m - deg)) * REC(deg, m) * tb[deg - 1][m - 1];
+            if (m <= deg - 1) acc += (KAP(m + 1) - t) * REC(deg, m + 1) * tb[deg - 1][m];
+            tb[deg][m] = acc;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m <= P; ++m) {
+        N[m] = tb[P][m];
+        T a = (m >= 1) ? REC(P, m) * tb[P - 1][m - 1] : (T)0;
+        T b = (m <= P - 1) ? REC(P, m + 1) * tb[P - 1][m] : (T)0;
+        dN[m] = (T)P * (a - b);
+    }
+    if constexpr (D2) {
+        if constexpr (P >= 2) {
+            T d1[P];
+#pragma unroll
+            for (int m = 0; m <= P - 1; ++m) {
+                T a = (m >= 1) ? REC(P - 1, m) * tb[P - 2][m - 1] : (T)0;
+                T b = (m <= P - 2) ? REC(P - 1, m + 1) * tb[P - 2][m] : (T)0;
+                d1[m] = (T)(P - 1) * (a - b);
+            }
+#pragma unroll
+            for (int m = 0; m <= P; ++m) {
+                T a = (m >= 1) ? REC(P, m) * d1[m - 1] : (T)0;
+                T b = (m <= P - 1) ? REC(P, m + 1) * d1[m] : (T)0;
+                d2N[m] = (T)P * (a - b);
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m <= P; ++m) d2N[m] = (T)0;
+        }
+    }
+#undef KAP
+#undef REC
+}
+
+// Surface h(x, y) = Z(X^-1(x), Y^-1(y)) and derivatives (sec. 2.1, 2.1.1) from LDS.  The LDS copy holds
+// P^z - zref (partition of unity: h = zref + sum N M (P - zref)), so h below is relative to zref and the
+// slopes do not lose digits to the mean lens height.
+template <int P, int Q, class T>
+struct SurfEval {
+    int ku, kv;
+    T Nu[P + 1], dNu[P + 1], d2Nu[P + 1];
+    T Nv[Q + 1], dNv[Q + 1], d2Nv[Q + 1];
+    T h, hx, hy, hxx, hxy, hyy;
+};
+
+template <int P, int Q, bool D2, class T>
+__device__ __forceinline__ void eval_surface(const DesignDev& D, const float* __restrict__ sP,
+                                             const float* __restrict__ sKu, const float* __restrict__ sKv, T x,
+                                             T y, SurfEval<P, Q, T>& S) {
+    T ub = x * (T)D.sxu + (T)D.ubar0;
+    T vb = y * (T)D.syv + (T)D.vbar0;
+    int ku = (int)floor(ub), kv = (int)floor(vb);
+    ku = min(max(ku, 0), D.nsu - 1);
+    kv = min(max(kv, 0), D.nsv - 1);
+    S.ku = ku;
+    S.kv = kv;
+    span_basis<P, D2, T>(sKu + ku * kt_stride(P), ub - (T)ku, S.Nu, S.dNu, S.d2Nu);
+    span_basis<Q, D2, T>(sKv + kv * kt_stride(Q), vb - (T)kv, S.Nv, S.dNv, S.d2Nv);
+    const float* row = sP + ku * D.n_v + kv;  // control point (ku + a, kv + b) of span product (ku, kv)
+    T h = 0, hu = 0, hv = 0, huu = 0, huv = 0, hvv = 0;
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        T r0 = 0, r1 = 0, r2 = 0;
+#pragma unroll
+        for (int b = 0; b <= Q; ++b) {
+            T pz = (T)row[a * D.n_v + b];
+            r0 += S.Nv[b] * pz;
+            r1 += S.dNv[b] * pz;
+            if constexpr (D2) r2 += S.d2Nv[b] * pz;
+        }
+        h += S.Nu[a] * r0;
+        hu += S.dNu[a] * r0;
+        hv += S.Nu[a] * r1;
+        if constexpr (D2) {
+            huu += S.d2Nu[a] * r0;
+            huv += S.dNu[a] * r1;
+            hvv += S.Nu[a] * r2;
+        }
+    }
+    T sx = (T)D.sxu, sy = (T)D.syv;
+    S.h = h;
+    S.hx = hu * sx;
+    S.hy = hv * sy;
+    if constexpr (D2) {
+        S.hxx = huu * sx * sx;
+        S.hxy = huv * sx * sy;
+        S.hyy = hvv * sy * sy;
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Sources (sec. 2.2.1) and the flat entry face (point sources).
+// ------------------------------------------------------------------------------------------------
+struct RayIn {
+    int status;
+    float ox, oy, oz;   // point on the entry plane (collimated: below the sample, on z = z_in)
+    float dx, dy, dz;   // unit direction in the glass
+    float w;            // weight after the entry face
+};
+
+__device__ __forceinline__ RayIn ray_entry(const DesignDev& D, int e, int ku, int kv, int64_t id) {
+    RayIn r;
+    r.status = ST_HIT;
+    float x1 = 0.5f, x2 = 0.5f;
+    if (D.jitter) two_uniforms(splitmix_at(D.rng_state0, (uint64_t)id), x1, x2);
+    if (D.kind == 0) {
+        // Collimated bundle: samples on the grid of [0,1]^2, mapped linearly to the aperture; the ray meets
+        // the flat face at normal incidence (Schlick weight 1 - R0) and travels along +z.
+        float u = ((float)ku + x1) * D.inv_gu;
+        float v = ((float)kv + x2) * D.inv_gv;
+        r.ox = (2.0f * u - 1.0f) * D.r_x;
+        r.oy = (2.0f * v - 1.0f) * D.r_y;
+        r.oz = D.z_in;
+        r.dx = 0.0f;
+        r.dy = 0.0f;
+        r.dz = 1.0f;
+        r.w = D.fresnel ? D.w0 * (1.0f - D.R0) : D.w0;
+        return r;
+    }
+    // Point source: theta = 2 pi (k + xi) / S_theta, cos(phi) = 1 - (1 - cos phi_max) a (uniform in solid
+    // angle), a = (k_a + xi) / S_a.  sin(phi) = sqrt(a' (2 - a')) with a' = (1 - cos phi_max) a avoids the
+    // cancellation of 1 - cos^2.
+    float sth, cth;
+    sincospif(2.0f * ((float)ku + x1) * D.inv_gu, &sth, &cth);
+    float a = ((float)kv + x2) * D.inv_gv;
+    float ao = a * D.omc;
+    float cphi = 1.0f - ao;
+    float sphi = sqrtf(ao * (2.0f - ao));
+    float px = D.pos_x, py = D.pos_y;
+    if (D.kind == 2) {
+        int ix = e / D.emit_ny, iy = e - ix * D.emit_ny;
+        px += D.ex0 + (float)ix * D.edx;
+        py += D.ey0 + (float)iy * D.edy;
+    }
+    float t0 = (D.z_in - D.pos_z) * rcpf(cphi);
+    r.ox = px + t0 * cth * sphi;
+    r.oy = py + t0 * sth * sphi;
+    r.oz = D.z_in;
+    if (fabsf(r.ox) > D.r_x || fabsf(r.oy) > D.r_y) {
+        r.status = ST_MISS_ENTRY;
+        return r;
+    }
+    // Refraction air -> glass at the normal (0,0,1): d1 = eta d0 + (sqrt(k) - eta cos) z, eta = 1/n, whose
+    // z component is sqrt(k) = sqrt(1 - eta^2 sin^2).
+    float eta = rcpf(D.n_lens);
+    float k = 1.0f - eta * eta * sphi * sphi;
+    r.dx = eta * cth * sphi;
+    r.dy = eta * sth * sphi;
+    r.dz = sqrtf(k);
+    float w = D.w0;
+    if (D.fresnel) {  // Schlick with the air-side cosine
+        float m = 1.0f - cphi, m2 = m * m;
+        w *= 1.0f - (D.R0 + (1.0f - D.R0) * m2 * m2 * m);
+    }
+    r.w = w;
+    return r;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Freeform intersection (sec. 2.2.1 root problem; sec. 2.2.2 bounding box).
+// f(t) = h(o_xy + t d_xy) - o_z - t d_z.  Bracket from the global convex-hull box [min P^z, max P^z]
+// intersected with the aperture; f > 0 below it and f < 0 above.  When the slope bound proves f strictly
+// decreasing the root is unique; otherwise the bracket is scanned for its first sign change.  Safeguarded
+// Newton (bisection when a step leaves the bracket), at most newton_max iterations.  Grazing hits
+// (|f'| small) get their residual re-evaluated in double precision and one double Newton correction.
+// ------------------------------------------------------------------------------------------------
+constexpr float GRAZING_FP = 0.05f;
+
+// oz_rel = o_z - zref (heights in LDS are relative to zref).
+template <int P, int Q>
+__device__ __forceinline__ float f_and_slope(const DesignDev& D, const float* sP, const float* sKu,
+                                             const float* sKv, const RayIn& r, float oz_rel, float t,
+                                             float& fp) {
+    SurfEval<P, Q, float> S;
+    eval_surface<P, Q, false, float>(D, sP, sKu, sKv, r.ox + t * r.dx, r.oy + t * r.dy, S);
+    fp = S.hx * r.dx + S.hy * r.dy - r.dz;
+    return S.h - oz_rel - t * r.dz;
+}
+
+struct RootOut {
+    int status;
+    float t;
+    int iters;
+    int failed, nonmono, refined;
+};
+
+template <int P, int Q>
+__device__ RootOut intersect(const DesignDev& D, const BoundsDev& B, const float* sP, const float* sKu,
+                             const float* sKv, const RayIn& r) {
+    RootOut R;
+    R.status = ST_HIT;
+    R.t = 0.0f;
+    R.iters = 0;
+    R.failed = R.nonmono = R.refined = 0;
+    float inv_dz = rcpf(r.dz);
+    float pad = 4e-6f * (1.0f + fabsf(B.zmax - r.oz)) * inv_dz;
+    float t_lo = fmaxf(0.0f, (B.zmin - r.oz) * inv_dz - pad);
+    float t_hi = (B.zmax - r.oz) * inv_dz + pad;
+    float t_ap = INFINITY;
+    if (r.dx > 0.0f) t_ap = fminf(t_ap, (D.r_x - r.ox) * rcpf(r.dx));
+    if (r.dx < 0.0f) t_ap = fminf(t_ap, (-D.r_x - r.ox) * rcpf(r.dx));
+    if (r.dy > 0.0f) t_ap = fminf(t_ap, (D.r_y - r.oy) * rcpf(r.dy));
+    if (r.dy < 0.0f) t_ap = fminf(t_ap, (-D.r_y - r.oy) * rcpf(r.dy));
+    float t_end = fminf(t_hi, t_ap);
+    if (t_end < t_lo) {
+        R.status = ST_SIDE_WALL;
+        return R;
+    }
+    const float ozr = r.oz - B.zref;
+    float a = t_lo, b = t_end, fp;
+    if (t_ap <= t_hi) {
+        // the aperture ends the search: the ray must be above the surface where it leaves the aperture
+        if (f_and_slope<P, Q>(D, sP, sKu, sKv, r, ozr, t_end, fp) > 0.0f) {
+            R.status = ST_SIDE_WALL;
+            return R;
+        }
+    }
+    bool mono = B.gx * fabsf(r.dx) + B.gy * fabsf(r.dy) < r.dz;
+    if (!mono) {
+        R.nonmono = 1;
+        constexpr int SCAN = 32;
+        float prev = a;
+        for (int s = 1; s <= SCAN; ++s) {
+            float ts = a + (t_end - a) * ((float)s * (1.0f / SCAN));
+            if (f_and_slope<P, Q>(D, sP, sKu, sKv, r, ozr, ts, fp) <= 0.0f) {
+                a = prev;
+                b = ts;
+                break;
+            }
+            prev = ts;
+        }
+    }
+    float t = 0.5f * (a + b);
+    bool done = false;
+    float f = 0.0f;
+    int it = 0;
+    for (; it < D.newton_max && !done; ++it) {
+        f = f_and_slope<P, Q>(D, sP, sKu, sKv, r, ozr, t, fp);
+        if (f > 0.0f) a = t; else b = t;
+        float tn = t - f * rcpf(fp);
+        if (!(tn >= a && tn <= b) || !(fp < 0.0f)) tn = 0.5f * (a + b);
+        done = fabsf(tn - t) <= 2e-6f * (1.0f + fabsf(t));
+        t = tn;
+    }
+    R.iters = it;
+    R.failed = done ? 0 : 1;
+    if (fabsf(fp) < GRAZING_FP) {
+        // double-precision residual at the root and one Newton correction
+        SurfEval<P, Q, double> S;
+        double td = (double)t;
+        eval_surface<P, Q, false, double>(D, sP, sKu, sKv, (double)r.ox + td * (double)r.dx,
+                                          (double)r.oy + td * (double)r.dy, S);
+        double fd = S.h - ((double)r.oz - (double)B.zref) - td * (double)r.dz;
+        double fpd = S.hx * (double)r.dx + S.hy * (double)r.dy - (double)r.dz;
+        if (fpd < 0.0) {
+            double tn = td - fd / fpd;
+            if (tn >= (double)a - 1e-6 && tn <= (double)b + 1e-6) t = (float)tn;
+        }
+        R.refined = 1;
+    }
+    R.t = t;
+    return R;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Exit face (sec. 2.2): vector Snell glass -> air at n_hat = (-h_x, -h_y, 1)/|.|, TIR dropped, Schlick
+// weight with the air-side cosine sqrt(k), propagation to the screen plane (sec. 2.3).
+// ------------------------------------------------------------------------------------------------
+struct ExitState {
+    int status;
+    float nxh, nyh, nzh, inv_m;   // unit normal and 1/|m|
+    float c, sk, beta;            // d.n_hat, sqrt(k), sqrt(k) - n c
+    float ex, ey, ez;             // direction in air
+    float tau, T;                 // screen distance parameter, Schlick transmittance
+    float X, Y, w;
+};
+
+__device__ __forceinline__ ExitState exit_face(const DesignDev& D, float qx, float qy, float qz, float dx,
+                                               float dy, float dz, float hx, float hy, float w1) {
+    ExitState E;
+    E.status = ST_HIT;
+    float inv = rsqrtf(hx * hx + hy * hy + 1.0f);
+    E.inv_m = inv;
+    E.nxh = -hx * inv;
+    E.nyh = -hy * inv;
+    E.nzh = inv;
+    E.c = dx * E.nxh + dy * E.nyh + dz * E.nzh;
+    // sin^2 of the incidence angle as |d x n_hat|^2 (no cancellation near normal incidence)
+    float cx = dy * E.nzh - dz * E.nyh, cy = dz * E.nxh - dx * E.nzh, cz = dx * E.nyh - dy * E.nxh;
+    float s2 = cx * cx + cy * cy + cz * cz;
+    float n = D.n_lens;
+    float k = 1.0f - n * n * s2;
+    if (!(k >= 0.0f)) {
+        E.status = ST_TIR;
+        return E;
+    }
+    E.sk = sqrtf(k);
+    E.beta = E.sk - n * E.c;
+    E.ex = n * dx + E.beta * E.nxh;
+    E.ey = n * dy + E.beta * E.nyh;
+    E.ez = n * dz + E.beta * E.nzh;
+    E.T = 1.0f;
+    if (D.fresnel) {
+        float m = 1.0f - E.sk, m2 = m * m;
+        E.T = 1.0f - (D.R0 + (1.0f - D.R0) * m2 * m2 * m);
+    }
+    E.w = w1 * E.T;
+    if (!(E.ez > 0.0f)) {
+        E.status = ST_OFF_SCREEN;
+        return E;
+    }
+    E.tau = (D.z_screen - qz) * rcpf(E.ez);
+    E.X = qx + E.tau * E.ex;
+    E.Y = qy + E.tau * E.ey;
+    if (!(E.X >= -D.Rx && E.X < D.Rx && E.Y >= -D.Ry && E.Y < D.Ry)) E.status = ST_OFF_SCREEN;
+    return E;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Gaussian reconstruction filter along one axis (sec. 2.3, filter eq.):
+//   f_i = exp(-alpha ((X - c_i)/w)^2) - exp(-alpha (nu/2)^2) inside the support, c_i = (i + 1/2) w - R,
+// window = the NU pixels centred on the landing pixel i0, pixels outside the grid excluded, normalised.
+// F[m] is the weight of pixel i0 - (NU-1)/2 + m; dF[m] = dF/dX.
+// ------------------------------------------------------------------------------------------------
+template <int NU, bool DERIV>
+__device__ __forceinline__ int filter_axis(float X, float R, float w, float inv_w, int n, float alpha,
+                                           float edge, float* F, float* dF) {
+    constexpr int H = (NU - 1) / 2;
+    int i0 = (int)floorf((X + R) * inv_w);
+    i0 = min(max(i0, 0), n - 1);
+    float c0 = ((float)i0 + 0.5f) * w - R;
+    float delta = (X - c0) * inv_w;  // offset from the centre of pixel i0, in pixel widths
+    float S = 0.0f, Sp = 0.0f;
+    float fp[NU];
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+        int i = i0 + m - H;
+        float dm = delta - (float)(m - H);
+        bool in = (i >= 0) && (i < n) && (fabsf(dm) < 0.5f * (float)NU);
+        float e = __expf(-alpha * dm * dm);
+        F[m] = in ? e - edge : 0.0f;
+        S += F[m];
+        if constexpr (DERIV) {
+            fp[m] = in ? -2.0f * alpha * dm * e * inv_w : 0.0f;
+            Sp += fp[m];
+        }
+    }
+    float invS = rcpf(S);
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+        F[m] *= invS;
+        if constexpr (DERIV) dF[m] = (fp[m] - F[m] * Sp) * invS;
+    }
+    return i0;
+}
+
+// ------------------------------------------------------------------------------------------------
+// One ray, forward.
+// ------------------------------------------------------------------------------------------------
+struct FwdRay {
+    int status;
+    float X, Y, w;
+    float t, u, v;
+    int iters, failed, nonmono, refined;
+};
+
+template <int P, int Q>
+__device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const BoundsDev& B, const float* sP,
+                                                const float* sKu, const float* sKv, int e, int ku, int kv,
+                                                int64_t id) {
+    FwdRay o;
+    o.iters = o.failed = o.nonmono = o.refined = 0;
+    o.X = o.Y = o.w = o.t = o.u = o.v = 0.0f;
+    RayIn r = ray_entry(D, e, ku, kv, id);
+    o.status = r.status;
+    if (r.status != ST_HIT) return o;
+    float t;
+    if (D.kind != 0) {
+        RootOut R = intersect<P, Q>(D, B, sP, sKu, sKv, r);
+        o.iters = R.iters;
+        o.failed = R.failed;
+        o.nonmono = R.nonmono;
+        o.refined = R.refined;
+        if (R.status != ST_HIT) {
+            o.status = R.status;
+            return o;
+        }
+        t = R.t;
+    } else {
+        t = 0.0f;
+    }
+    float qx = r.ox + t * r.dx, qy = r.oy + t * r.dy;
+    SurfEval<P, Q, float> S;
+    eval_surface<P, Q, false, float>(D, sP, sKu, sKv, qx, qy, S);
+    float qz = (D.kind == 0) ? S.h + B.zref : r.oz + t * r.dz;
+    if (D.kind == 0) t = qz - r.oz;
+    o.t = t;
+    o.u = qx * (0.5f / D.r_x) + 0.5f;
+    o.v = qy * (0.5f / D.r_y) + 0.5f;
+    ExitState E = exit_face(D, qx, qy, qz, r.dx, r.dy, r.dz, S.hx, S.hy, r.w);
+    o.status = E.status;
+    if (E.status == ST_TIR) return o;
+    o.X = E.X;
+    o.Y = E.Y;
+    o.w = E.w;
+    return o;
+}
+
+// ------------------------------------------------------------------------------------------------
+// One ray, adjoint: re-trace, gather dL/dI over the filter window, reverse sweep.  Returns false when the
+// ray does not reach the screen.  g[] receives dL/dP for control point (ku + a, kv + b) at a * (Q+1) + b.
+// ------------------------------------------------------------------------------------------------
+template <int P, int Q, int NU>
+__device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDev& B, const float* sP,
+                                              const float* sKu, const float* sKv, const float* __restrict__ G,
+                                              int e, int ku, int kv, int64_t id, int& cku, int& ckv,
+                                              float* g) {
+    RayIn r = ray_entry(D, e, ku, kv, id);
+    if (r.status != ST_HIT) return false;
+    float t = 0.0f;
+    const bool point = D.kind != 0;
+    if (point) {
+        RootOut R = intersect<P, Q>(D, B, sP, sKu, sKv, r);
+        if (R.status != ST_HIT) return false;
+        t = R.t;
+    }
+    float qx = r.ox + t * r.dx, qy = r.oy + t * r.dy;
+    SurfEval<P, Q, float> S;
+    if (point) {
+        eval_surface<P, Q, true, float>(D, sP, sKu, sKv, qx, qy, S);
+    } else {
+        // the hit of a collimated ray does not move with P: no second derivatives needed
+        eval_surface<P, Q, false, float>(D, sP, sKu, sKv, qx, qy, S);
+    }
+    float qz = point ? r.oz + t * r.dz : S.h + B.zref;
+    ExitState E = exit_face(D, qx, qy, qz, r.dx, r.dy, r.dz, S.hx, S.hy, r.w);
+    if (E.status != ST_HIT) return false;
+
+    // ---- splat, reverse: I_ij += w Fx_i Fy_j
+    float Fx[NU], dFx[NU], Fy[NU], dFy[NU];
+    int i0 = filter_axis<NU, true>(E.X, D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, dFx);
+    int j0 = filter_axis<NU, true>(E.Y, D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, dFy);
+    constexpr int H = (NU - 1) / 2;
+    float wbar = 0.0f, Xbar = 0.0f, Ybar = 0.0f;
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+        int i = min(max(i0 + a - H, 0), D.nx - 1);
+        float gb = 0.0f, gbp = 0.0f;
+#pragma unroll
+        for (int b = 0; b < NU; ++b) {
+            int j = min(max(j0 + b - H, 0), D.ny - 1);
+            float Gij = G[(int64_t)i * D.ny + j];
+            gb += Gij * Fy[b];
+            gbp += Gij * dFy[b];
+        }
+        wbar += Fx[a] * gb;
+        Xbar += dFx[a] * gb;
+        Ybar += Fx[a] * gbp;
+    }
+    Xbar *= E.w;
+    Ybar *= E.w;
+
+    // ---- screen: X = q_x + tau e_x, Y = q_y + tau e_y, tau = (z_s - q_z) / e_z
+    float qxb = Xbar, qyb = Ybar;
+    float taub = Xbar * E.ex + Ybar * E.ey;
+    float inv_ez = rcpf(E.ez);
+    float exb = Xbar * E.tau, eyb = Ybar * E.tau, ezb = -taub * E.tau * inv_ez;
+    float qzb = -taub * inv_ez;
+    // ---- Schlick: w = w1 T(sk)
+    float skb = 0.0f;
+    if (D.fresnel) {
+        float m = 1.0f - E.sk, m2 = m * m;
+        skb = wbar * r.w * 5.0f * (1.0f - D.R0) * m2 * m2;
+    }
+    // ---- refraction: e = n d + beta n_hat, beta = sk - n c, sk = sqrt(k), k = 1 - n^2 (1 - c^2), c = d.n_hat
+    float n = D.n_lens;
+    float betab = exb * E.nxh + eyb * E.nyh + ezb * E.nzh;
+    float nxb = E.beta * exb, nyb = E.beta * eyb, nzb = E.beta * ezb;
+    skb += betab;
+    float cb = -n * betab;
+    float kb = skb * 0.5f * rcpf(fmaxf(E.sk, 1e-30f));
+    cb += 2.0f * n * n * E.c * kb;
+    nxb += cb * r.dx;
+    nyb += cb * r.dy;
+    nzb += cb * r.dz;
+    // ---- n_hat = m / |m|, m = (-h_x, -h_y, 1)
+    float ndot = nxb * E.nxh + nyb * E.nyh + nzb * E.nzh;
+    float mxb = (nxb - ndot * E.nxh) * E.inv_m;
+    float myb = (nyb - ndot * E.nyh) * E.inv_m;
+    float hxb = -mxb, hyb = -myb;
+    // ---- hit point: coefficient of N_a M_b in dL/dP
+    float g0;
+    if (point) {
+        // q = o + t d; t moves with P through f(t, P) = 0: dt/dP_ab = -N_a M_b / f'(t)
+        float tb = qxb * r.dx + qyb * r.dy + qzb * r.dz + hxb * (S.hxx * r.dx + S.hxy * r.dy) +
+                   hyb * (S.hxy * r.dx + S.hyy * r.dy);
+        float fp = S.hx * r.dx + S.hy * r.dy - r.dz;
+        g0 = -tb * rcpf(fp);
+    } else {
+        g0 = qzb;  // q_z = h(x, y)
+    }
+    // h_x = sum dN_a/du M_b P_ab * sxu, h_y = sum N_a dM_b/dv P_ab * syv
+    float gx = hxb * D.sxu, gy = hyb * D.syv;
+    float cv[Q + 1];
+#pragma unroll
+    for (int b = 0; b <= Q; ++b) cv[b] = g0 * S.Nv[b] + gy * S.dNv[b];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        float du = gx * S.dNu[a];
+#pragma unroll
+        for (int b = 0; b <= Q; ++b) g[a * (Q + 1) + b] = S.Nu[a] * cv[b] + du * S.Nv[b];
+    }
+    cku = S.ku;
+    ckv = S.kv;
+    return true;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Block decoding
+// ------------------------------------------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip; give each XCD a contiguous range of
+// logical blocks so that its L2 sees neighbouring rays (same control points, same pixels).
+__device__ __forceinline__ int64_t xcd_remap(int64_t pb, int64_t nblocks) {
+    constexpr int NX = 8;
+    int64_t per = nblocks / NX, rem = nblocks % NX;
+    int64_t x = pb % NX, slot = pb / NX;
+    return x * per + min(x, rem) + slot;
+}
+
+__device__ __forceinline__ int find_design(const BlockMap* bm, int n, int64_t b) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (bm[mid].first <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int SHAPE>
+struct Shape {
+    static constexpr int RPT = (SHAPE == 0) ? 1 : (SHAPE == 1) ? 2 : (SHAPE == 2) ? 4 : (SHAPE == 3) ? 8 : 16;
+    static constexpr int PU = (SHAPE == 0) ? 2 : (SHAPE == 1) ? 4 : (SHAPE == 2) ? 4 : 8;
+    static constexpr int PV = 4 * RPT / PU;
+    static constexpr int BU = 8 * PU, BV = 8 * PV;
+};
+
+// Load the design's control heights (relative to zref) and knot tables into LDS.
+__device__ __forceinline__ void stage_design(const TraceArgs& A, const DesignDev& D, float zref, float* sP,
+                                             float* sK, int p, int q) {
+    const float* P = A.Pz + D.cp_off;
+    int ncp = D.n_u * D.n_v;
+    for (int i = threadIdx.x; i < ncp; i += WG) sP[i] = P[i] - zref;
+    int nku = D.nsu * kt_stride(p), nkv = D.nsv * kt_stride(q);
+    const float* ku = A.knots + D.kt_u;
+    const float* kv = A.knots + D.kt_v;
+    for (int i = threadIdx.x; i < nku; i += WG) sK[i] = ku[i];
+    for (int i = threadIdx.x; i < nkv; i += WG) sK[nku + i] = kv[i];
+}
+
+// ------------------------------------------------------------------------------------------------
+// Forward kernel
+// ------------------------------------------------------------------------------------------------
+template <int P, int Q, int NU, int SHAPE>
+__global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
+    using SH = Shape<SHAPE>;
+    constexpr int RPT = SH::RPT;
+    constexpr int H = (NU - 1) / 2;
+    extern __shared__ float smem[];
+    float* sP = smem;
+    float* sK = sP + A.lds_cp;
+    float* tile = sK + A.lds_kt;
+    __shared__ int s_box[4][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int cur = -1;
+    for (int64_t pb = blockIdx.x; pb < A.n_blocks; pb += gridDim.x) {
+        const int64_t b = xcd_remap(pb, A.n_blocks);
+        const int d = find_design(A.bmap, A.n_designs, b);
+        const DesignDev& D = A.designs[d];
+        const BoundsDev B = A.bounds[d];
+        if (d != cur) {
+            __syncthreads();
+            stage_design(A, D, B.zref, sP, sK, P, Q);
+            __syncthreads();
+            cur = d;
+        }
+        const float* sKu = sK;
+        const float* sKv = sK + D.nsu * kt_stride(P);
+        const BlockMap bm = A.bmap[d];
+        int64_t local = b - bm.first;
+        int e = (int)(local / bm.per_emitter);
+        int rb = (int)(local - (int64_t)e * bm.per_emitter);
+        int bu = rb / bm.nbv, bv = rb - (rb / bm.nbv) * bm.nbv;
+        int64_t ebase = (int64_t)e * D.grid_u * D.grid_v;
+
+        float X[RPT], Y[RPT], W[RPT];
+        uint32_t c_hit = 0, c_miss = 0, c_side = 0, c_tir = 0, c_off = 0, c_fail = 0, c_ref = 0, c_nm = 0,
+                 c_tr = 0;
+        float flux = 0.0f;
+        int imin = 1 << 30, imax = -1, jmin = 1 << 30, jmax = -1;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            int patch = r * 4 + wave;
+            int pu = patch / SH::PV, pv = patch - (patch / SH::PV) * SH::PV;
+            int ku = bu * SH::BU + pu * 8 + (lane >> 3);
+            int kv = bv * SH::BV + pv * 8 + (lane & 7);
+            W[r] = 0.0f;
+            X[r] = 0.0f;
+            Y[r] = 0.0f;
+            if (ku < D.grid_u && kv < D.grid_v) {
+                int64_t id = ebase + (int64_t)ku * D.grid_v + kv;
+                FwdRay o = trace_forward<P, Q>(D, B, sP, sKu, sKv, e, ku, kv, id);
+                c_tr++;
+                c_fail += o.failed;
+                c_ref += o.refined;
+                c_nm += o.nonmono;
+                switch (o.status) {
+                    case ST_HIT: c_hit++; break;
+                    case ST_MISS_ENTRY: c_miss++; break;
+                    case ST_SIDE_WALL: c_side++; break;
+                    case ST_TIR: c_tir++; break;
+                    default: c_off++; break;
+                }
+                if (o.status == ST_HIT) {
+                    X[r] = o.X;
+                    Y[r] = o.Y;
+                    W[r] = o.w;
+                    flux += o.w;
+                    int i0 = min(max((int)floorf((o.X + D.Rx) * D.inv_wx), 0), D.nx - 1);
+                    int j0 = min(max((int)floorf((o.Y + D.Ry) * D.inv_wy), 0), D.ny - 1);
+                    imin = min(imin, i0);
+                    imax = max(imax, i0);
+                    jmin = min(jmin, j0);
+                    jmax = max(jmax, j0);
+                }
+            }
+        }
+        // ---- statistics: one atomic per wave and counter
+        if (A.stats) {
+            ffrt_stats* st = A.stats + d;
+            uint32_t v0 = wave_sum(c_tr), v1 = wave_sum(c_hit), v2 = wave_sum(c_miss), v3 = wave_sum(c_side),
+                     v4 = wave_sum(c_tir), v5 = wave_sum(c_off), v6 = wave_sum(c_fail), v7 = wave_sum(c_ref),
+                     v8 = wave_sum(c_nm);
+            float fl = wave_sum(flux);
+            if (lane == 0) {
+                atomicAdd(&st->n_traced, v0);
+                if (v1) atomicAdd(&st->n_hit, v1);
+                if (v2) atomicAdd(&st->n_miss_entry, v2);
+                if (v3) atomicAdd(&st->n_side_wall, v3);
+                if (v4) atomicAdd(&st->n_tir, v4);
+                if (v5) atomicAdd(&st->n_off_screen, v5);
+                if (v6) atomicAdd(&st->n_newton_fail, v6);
+                if (v7) atomicAdd(&st->n_fp64_refined, v7);
+                if (v8) atomicAdd(&st->n_nonmonotone, v8);
+                if (fl != 0.0f) atomicAdd(&st->flux_on_screen, fl);
+            }
+        }
+        // ---- footprint of the block (landing pixels widened by the filter half-width)
+        float* img = A.irr + D.img_off;
+        bool use_tile = false;
+        int ilo = 0, jlo = 0, tw = 0, area = 0;
+        if (A.use_tile) {
+            int a0 = wave_min(imin), a1 = wave_max(imax), b0 = wave_min(jmin), b1 = wave_max(jmax);
+            if (lane == 0) {
+                s_box[wave][0] = a0;
+                s_box[wave][1] = a1;
+                s_box[wave][2] = b0;
+                s_box[wave][3] = b1;
+            }
+            __syncthreads();
+            a0 = min(min(s_box[0][0], s_box[1][0]), min(s_box[2][0], s_box[3][0]));
+            a1 = max(max(s_box[0][1], s_box[1][1]), max(s_box[2][1], s_box[3][1]));
+            b0 = min(min(s_box[0][2], s_box[1][2]), min(s_box[2][2], s_box[3][2]));
+            b1 = max(max(s_box[0][3], s_box[1][3]), max(s_box[2][3], s_box[3][3]));
+            __syncthreads();
+            if (a1 < 0) continue;  // no ray of the block reached the screen
+            ilo = max(a0 - H, 0);
+            int ihi = min(a1 + H, D.nx - 1);
+            jlo = max(b0 - H, 0);
+            int jhi = min(b1 + H, D.ny - 1);
+            tw = jhi - jlo + 1;
+            area = (ihi - ilo + 1) * tw;
+            use_tile = area <= TILE_CAP;
+            if (use_tile) {
+                for (int i = threadIdx.x; i < area; i += WG) tile[i] = 0.0f;
+                __syncthreads();
+            }
+        }
+        // ---- splat
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            if (W[r] == 0.0f) continue;
+            float Fx[NU], Fy[NU];
+            int i0 = filter_axis<NU, false>(X[r], D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr);
+            int j0 = filter_axis<NU, false>(Y[r], D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr);
+#pragma unroll
+            for (int a = 0; a < NU; ++a) {
+                int i = i0 + a - H;
+                if (i < 0 || i >= D.nx) continue;
+                float wa = W[r] * Fx[a];
+#pragma unroll
+                for (int bb = 0; bb < NU; ++bb) {
+                    int j = j0 + bb - H;
+                    if (j < 0 || j >= D.ny) continue;
+                    float val = wa * Fy[bb];
+                    if (use_tile) atomicAdd(&tile[(i - ilo) * tw + (j - jlo)], val);
+                    else atomicAdd(&img[(int64_t)i * D.ny + j], val);
+                }
+            }
+        }
+        if (use_tile) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < area; i += WG) {
+                float v = tile[i];
+                int ti = i / tw;
+                if (v != 0.0f) atomicAdd(&img[(int64_t)(ilo + ti) * D.ny + jlo + (i - ti * tw)], v);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Adjoint kernel
+// ------------------------------------------------------------------------------------------------
+// Reduce-scatter of NV per-lane values across the wave.  Each halving step at lane offset OFF keeps one
+// half of the values (the upper half on lanes whose OFF bit is set) and adds the partner's copy of it, so
+// after log2(NV) steps lane l holds a partial sum of value index l >> (6 - log2 NV); the remaining
+// xor-steps complete it.  Lanes whose low 6 - log2(NV) bits are zero hold the wave totals.
+template <int HALF, int OFF>
+__device__ __forceinline__ void halve(float* v, int lane) {
+    const bool upper = (lane & OFF) != 0;
+#pragma unroll
+    for (int j = 0; j < HALF; ++j) {
+        float lo = v[j], hi = v[j + HALF];
+        float send = upper ? lo : hi;
+        float keep = upper ? hi : lo;
+        v[j] = keep + __shfl_xor(send, OFF);
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ float wave_reduce_scatter(float* v, int lane) {
+    static_assert(NV == 16 || NV == 32 || NV == 64, "NV");
+    float s;
+    if constexpr (NV == 16) {
+        halve<8, 32>(v, lane); halve<4, 16>(v, lane); halve<2, 8>(v, lane); halve<1, 4>(v, lane);
+        s = v[0];
+        s += __shfl_xor(s, 2);
+        s += __shfl_xor(s, 1);
+    } else if constexpr (NV == 32) {
+        halve<16, 32>(v, lane); halve<8, 16>(v, lane); halve<4, 8>(v, lane); halve<2, 4>(v, lane);
+        halve<1, 2>(v, lane);
+        s = v[0];
+        s += __shfl_xor(s, 1);
+    } else {
+        halve<32, 32>(v, lane); halve<16, 16>(v, lane); halve<8, 8>(v, lane); halve<4, 4>(v, lane);
+        halve<2, 2>(v, lane); halve<1, 1>(v, lane);
+        s = v[0];
+    }
+    return s;
+}
+
+template <int P, int Q, int NU>
+__global__ __launch_bounds__(WG) void k_adjoint(TraceArgs A, int shape) {
+    constexpr int NT = (P + 1) * (Q + 1);
+    constexpr int NV = NT <= 16 ? 16 : (NT <= 32 ? 32 : 64);
+    constexpr int LOG_NV = NV == 16 ? 4 : (NV == 32 ? 5 : 6);
+    extern __shared__ float smem[];
+    float* sP = smem;
+    float* sK = sP + A.lds_cp;
+    float* sG = sK + A.lds_kt;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rpt = RPT_OF_SHAPE[shape];
+    const int PU = (shape == 0) ? 2 : (shape <= 2 ? 4 : 8);
+    const int PV = 4 * rpt / PU;
+    const int BU = 8 * PU, BV = 8 * PV;
+    int cur = -1;
+    for (int64_t pb = blockIdx.x; pb < A.n_blocks; pb += gridDim.x) {
+        const int64_t b = xcd_remap(pb, A.n_blocks);
+        const int d = find_design(A.bmap, A.n_designs, b);
+        const DesignDev& D = A.designs[d];
+        const int ncp = D.n_u * D.n_v;
+        if (d != cur) {
+            __syncthreads();
+            if (cur >= 0) {  // flush the previous design's accumulator
+                const DesignDev& Dc = A.designs[cur];
+                for (int i = threadIdx.x; i < Dc.n_u * Dc.n_v; i += WG) {
+                    float v = sG[i];
+                    if (v != 0.0f) atomicAdd(&A.dLdP[Dc.cp_off + i], v);
+                }
+                __syncthreads();
+            }
+            stage_design(A, D, A.bounds[d].zref, sP, sK, P, Q);
+            for (int i = threadIdx.x; i < ncp; i += WG) sG[i] = 0.0f;
+            __syncthreads();
+            cur = d;
+        }
+        const BoundsDev B = A.bounds[d];
+        const float* sKu = sK;
+        const float* sKv = sK + D.nsu * kt_stride(P);
+        const float* G = A.dLdI + D.img_off;
+        const BlockMap bm = A.bmap[d];
+        int64_t local = b - bm.first;
+        int e = (int)(local / bm.per_emitter);
+        int rb = (int)(local - (int64_t)e * bm.per_emitter);
+        int bu = rb / bm.nbv, bv = rb - (rb / bm.nbv) * bm.nbv;
+        int64_t ebase = (int64_t)e * D.grid_u * D.grid_v;
+        for (int r = 0; r < rpt; ++r) {
+            int patch = r * 4 + wave;
+            int pu = patch / PV, pv = patch - (patch / PV) * PV;
+            int ku = bu * BU + pu * 8 + (lane >> 3);
+            int kv = bv * BV + pv * 8 + (lane & 7);
+            float g[NV];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) g[i] = 0.0f;
+            int cku = -1, ckv = -1;
+            bool ok = false;
+            if (ku < D.grid_u && kv < D.grid_v) {
+                int64_t id = ebase + (int64_t)ku * D.grid_v + kv;
+                ok = trace_adjoint<P, Q, NU>(D, B, sP, sKu, sKv, G, e, ku, kv, id, cku, ckv, g);
+            }
+            uint64_t okmask = __ballot(ok);
+            if (okmask == 0) continue;
+            int leader = __ffsll((unsigned long long)okmask) - 1;
+            int key = ok ? (cku << 16) | ckv : -1;
+            int lkey = __shfl(key, leader);
+            bool uniform = A.butterfly && __all(!ok || key == lkey);
+            if (uniform) {
+                if (!ok) {
+#pragma unroll
+                    for (int i = 0; i < NV; ++i) g[i] = 0.0f;
+                }
+                float s = wave_reduce_scatter<NV>(g, lane);
+                int idx = lane >> (6 - LOG_NV);
+                if ((lane & ((1 << (6 - LOG_NV)) - 1)) == 0 && idx < NT) {
+                    int a = idx / (Q + 1), bb = idx - (idx / (Q + 1)) * (Q + 1);
+                    int lku = lkey >> 16, lkv = lkey & 0xFFFF;
+                    atomicAdd(&sG[(lku + a) * D.n_v + lkv + bb], s);
+                }
+            } else if (ok) {
+#pragma unroll
+                for (int a = 0; a <= P; ++a)
+#pragma unroll
+                    for (int bb = 0; bb <= Q; ++bb) atomicAdd(&sG[(cku + a) * D.n_v + ckv + bb], g[a * (Q + 1) + bb]);
+            }
+        }
+    }
+    // flush the last design's accumulator
+    __syncthreads();
+    if (cur >= 0) {
+        const DesignDev& Dc = A.designs[cur];
+        for (int i = threadIdx.x; i < Dc.n_u * Dc.n_v; i += WG) {
+            float v = sG[i];
+            if (v != 0.0f) atomicAdd(&A.dLdP[Dc.cp_off + i], v);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Individual rays (inspection)
+// ------------------------------------------------------------------------------------------------
+template <int P, int Q>
+__global__ __launch_bounds__(WG) void k_trace_rays(TraceArgs A, int design, const int64_t* ids, int64_t n,
+                                                   float* out8) {
+    extern __shared__ float smem[];
+    float* sP = smem;
+    float* sK = sP + A.lds_cp;
+    const DesignDev& D = A.designs[design];
+    stage_design(A, D, A.bounds[design].zref, sP, sK, P, Q);
+    __syncthreads();
+    int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
+    if (i >= n) return;
+    int64_t id = ids[i];
+    int64_t per = (int64_t)D.grid_u * D.grid_v;
+    int e = (int)(id / per);
+    int64_t rr = id - (int64_t)e * per;
+    int ku = (int)(rr / D.grid_v), kv = (int)(rr - (rr / D.grid_v) * D.grid_v);
+    FwdRay o = trace_forward<P, Q>(D, A.bounds[design], sP, sK, sK + D.nsu * kt_stride(P), e, ku, kv, id);
+    float* dst = out8 + 8 * i;
+    dst[0] = (float)o.status;
+    dst[1] = o.X;
+    dst[2] = o.Y;
+    dst[3] = o.status == ST_HIT ? o.w : 0.0f;
+    dst[4] = o.u;
+    dst[5] = o.v;
+    dst[6] = o.t;
+    dst[7] = (float)o.iters;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Launchers
+// ------------------------------------------------------------------------------------------------
+inline size_t trace_lds_bytes(const TraceArgs& A, int extra_floats) {
+    return sizeof(float) * (size_t)(A.lds_cp + A.lds_kt + extra_floats);
+}
+
+template <int P, int Q, int NU>
+struct KernelsFor {
+    template <int SHAPE>
+    static hipError_t fwd_shape(const TraceArgs& A, int grid, hipStream_t s) {
+        size_t lds = trace_lds_bytes(A, A.use_tile ? TILE_CAP : 0);
+        hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE>), dim3(grid), dim3(WG), lds, s, A);
+        return hipGetLastError();
+    }
+    static hipError_t forward(const TraceArgs& A, int shape, int grid, hipStream_t s) {
+        switch (shape) {
+            case 0: return fwd_shape<0>(A, grid, s);
+            case 1: return fwd_shape<1>(A, grid, s);
+            case 2: return fwd_shape<2>(A, grid, s);
+            case 3: return fwd_shape<3>(A, grid, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    static hipError_t adjoint(const TraceArgs& A, int shape, int grid, hipStream_t s) {
+        size_t lds = trace_lds_bytes(A, A.lds_cp);
+        hipLaunchKernelGGL((k_adjoint<P, Q, NU>), dim3(grid), dim3(WG), lds, s, A, shape);
+        return hipGetLastError();
+    }
+    static hipError_t trace_rays(const TraceArgs& A, int design, const int64_t* ids, int64_t n, float* out8,
+                                 hipStream_t s) {
+        if (n <= 0) return hipSuccess;
+        size_t lds = trace_lds_bytes(A, 0);
+        int grid = (int)((n + WG - 1) / WG);
+        hipLaunchKernelGGL((k_trace_rays<P, Q>), dim3(grid), dim3(WG), lds, s, A, design, ids, n, out8);
+        return hipGetLastError();
+    }
+    static const KernelSet* get() {
+        static const KernelSet ks = {&forward, &adjoint, &trace_rays};
+        return &ks;
+    }
+};
+
+}  // namespace ffrt

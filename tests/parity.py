@@ -1,0 +1,38 @@
+"""Shared helpers of the GPU-vs-oracle parity tests (tolerances stated here)."""
+import numpy as np
+
+# Irradiance: |I_gpu - I_64| <= 1e-4 * max(I_64[px], 0.01 * max I_64) at every pixel not touched by a
+# marginal ray (a ray whose discrete state sits within rounding distance of flipping).
+IRR_REL = 1e-4
+IRR_FLOOR = 0.01
+# Gradient: ||g_gpu - g_64||_inf <= 1e-3 ||g_64||_inf.
+GRAD_REL = 1e-3
+
+
+def irradiance_errors(I_gpu, I_64, mask=None):
+    tol = IRR_REL * np.maximum(I_64, IRR_FLOOR * I_64.max())
+    err = np.abs(I_gpu - I_64)
+    ok = err <= tol
+    if mask is not None:
+        ok |= mask
+    big = I_64 >= IRR_FLOOR * I_64.max()
+    if mask is not None:
+        big &= ~mask
+    rel_big = (err[big] / I_64[big]).max() if big.any() else 0.0
+    return ok, float((err / np.maximum(tol, 1e-300)).max()), float(rel_big)
+
+
+def assert_irradiance(I_gpu, I_64, mask=None, max_masked_frac=0.02, what=""):
+    ok, worst, rel_big = irradiance_errors(I_gpu, I_64, mask)
+    n_mask = int(mask.sum()) if mask is not None else 0
+    assert n_mask <= max_masked_frac * I_64.size + 9, f"{what}: {n_mask} masked pixels"
+    bad = np.argwhere(~ok)
+    assert ok.all(), (f"{what}: {len(bad)} pixels out of tolerance, first {bad[:5].tolist()}, "
+                      f"worst err/tol {worst:.3g}, max rel on bright pixels {rel_big:.3g}")
+    return worst, rel_big
+
+
+def assert_gradient(g_gpu, g_64, rel=GRAD_REL, what=""):
+    e = np.abs(g_gpu - g_64).max() / np.abs(g_64).max()
+    assert e <= rel, f"{what}: gradient error {e:.3g} of max |g| (tolerance {rel})"
+    return e

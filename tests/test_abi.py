@@ -1,0 +1,100 @@
+"""The C-ABI library loads, exports what include/ffrt.h declares, and validates plans (no GPU needed)."""
+import ctypes
+import os
+import re
+from dataclasses import replace
+
+import pytest
+
+from paper_2302_12031_amd import ffrt
+from paper_2302_12031_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "ffrt.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ffrt_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_functions():
+    assert _declared() == sorted(ffrt.HEADER_FUNCTIONS)
+
+
+def test_library_exports_every_declared_symbol():
+    L = ffrt.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_struct_layout_matches_header():
+    # sizes from the header's struct definitions (x86-64 / gfx950 share the layout)
+    assert ctypes.sizeof(ffrt.CProblem) == 200
+    assert ffrt.CProblem.det.offset == 136 and ffrt.CProblem.opt.offset == 192
+    assert ffrt.STATS_BYTES == 48 and ctypes.sizeof(ffrt.CAdam) == 16
+
+
+def test_status_strings():
+    L = ffrt.lib()
+    for s in range(8):
+        assert L.ffrt_status_string(s)
+
+
+def _bad(p, match):
+    with pytest.raises(ffrt.FfrtError, match=match):
+        ffrt.create_plan_handle([p])
+
+
+def test_plan_validation_rejects_bad_problems():
+    p = W.c1().problems[0]
+    _bad(replace(p, lens=replace(p.lens, n_u=3)), "invalid argument")
+    _bad(replace(p, lens=replace(p.lens, n_lens=1.0)), "n_lens")
+    _bad(replace(p, detector=replace(p.detector, nu_x=4, nu_y=4)), "odd")
+    _bad(replace(p, detector=replace(p.detector, alpha=0.0)), "alpha")
+    _bad(replace(p, source=replace(p.source, kind=1, pos=(0.0, 0.0, 1.0), half_angle=0.3)), "below")
+    _bad(replace(p, source=replace(p.source, kind=1, half_angle=1.6)), "half angle")
+    _bad(replace(p, options=replace(p.options, newton_max_iter=0)), "newton")
+    _bad(replace(p, detector=replace(p.detector, z_screen=-1.0)), "screen")
+    with pytest.raises(ffrt.FfrtError, match="unsupported"):
+        ffrt.create_plan_handle([replace(p, lens=replace(p.lens, p=4, q=4))])
+    q = replace(p, lens=replace(p.lens, p=5, q=3, n_u=10))
+    with pytest.raises(ffrt.FfrtError, match="share"):
+        ffrt.create_plan_handle([p, q])
+
+
+def test_plan_accepts_all_workloads_and_reports_layout():
+    for wl in (W.c1(), W.c2(), W.c3(), W.c4(), W.c5()):
+        h = ffrt.create_plan_handle(wl.problems)
+        L = ffrt.lib()
+        n = len(wl.problems)
+        cp = (ctypes.c_int64 * (n + 1))()
+        im = (ctypes.c_int64 * (n + 1))()
+        assert L.ffrt_plan_layout(h, cp, im) == 0
+        assert cp[n] == sum(p.lens.n_u * p.lens.n_v for p in wl.problems)
+        assert im[n] == sum(p.image_shape()[0] * p.image_shape()[1] for p in wl.problems)
+        nr = ctypes.c_int64()
+        assert L.ffrt_plan_num_rays(h, ctypes.byref(nr)) == 0 and nr.value == wl.num_rays
+        sz = ctypes.c_size_t()
+        assert L.ffrt_plan_workspace_size(h, ctypes.byref(sz)) == 0 and sz.value > 0
+        # compute calls before a workspace is set fail cleanly
+        assert L.ffrt_forward(h, None, None, None, None) == 7
+        assert L.ffrt_plan_destroy(h) == 0
+
+
+def test_config_tables():
+    for which in (0, 1):
+        names = ffrt.Plan.config_names(which)
+        assert len(names) >= 4 and len(set(names)) == len(names)
+
+
+def test_workload_sizes_match_the_stated_configurations():
+    assert W.c1().num_rays == 256 * 256
+    assert W.c2().num_rays == 1024 * 1024
+    assert W.c3().num_rays == 2048 * 2048
+    assert W.c4().num_rays == 81 * 1024 * 1024
+    c5 = W.c5()
+    assert len(c5.problems) == 64
+    assert all(p.lens.n_u in (8, 16, 24, 32) for p in c5.problems)
+    for wl in (W.c1(), W.c2(), W.c3(64)):
+        assert abs(wl.targets[0].sum() - 1.0) < 1e-12 and (wl.targets[0] >= 0).all()
