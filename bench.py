@@ -6,7 +6,8 @@ plano-freeform lens with a 16 x 16 bicubic control net onto a 128 x 128 detector
 
   value       forward+adjoint rays per second of whole optimisation steps (inputs resident in HBM)
   roofline    the dominant trace kernel's algorithmic FP32 FLOP/s (per-ray operation counts below)
-              over its mean duration, measured with HIP events recorded around it inside the timed graph
+              over its mean duration, measured with HIP events on the same stream right after the timed
+              region (the kernel alone, launched back to back as many times as there are timed steps)
   fd          forward-only central finite-difference gradient over all control points on the same GPU:
               2K perturbed designs traced in one batched launch, and its agreement with the adjoint
   cpu_baseline  the FP64 oracle (forward + loss + forward-mode gradient) on the host cores
@@ -82,7 +83,20 @@ def main():
     ap.add_argument("--no-fd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--shapes", default=None,
+                    help="forward,adjoint kernel-shape indices to use instead of autotuning (e.g. 0,1)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy a 256 MiB buffer three times (reference kernel for HBM byte counters)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        src = torch.ones(64 << 20, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": src.numel() * 4}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the tracer runs on a single MI355X in this build "
               "(multi-GPU sharding is a design note, not implemented); use --gpus 1", file=sys.stderr)
@@ -102,8 +116,12 @@ def main():
     rays = wl.num_rays
     kinds = {("collimated" if p.source.kind == 0 else "point") for p in wl.problems}
 
-    # kernel shapes: autotuned on the initial design
-    if not args.no_autotune:
+    # kernel shapes: autotuned on the initial design, or given
+    if args.shapes:
+        f, a = (int(x) for x in args.shapes.split(","))
+        plan.set_config(0, f)
+        plan.set_config(1, a)
+    elif not args.no_autotune:
         irr = plan.forward(st["Pz"])
         _, dLdI = plan.loss(irr, T)
         plan.autotune(st["Pz"], irr, dLdI, st["dLdP"], reps=5)
@@ -120,7 +138,7 @@ def main():
     timed.set_config(0, plan.get_config(0))
     timed.set_config(1, plan.get_config(1))
     with torch.cuda.stream(stream):
-        timed.graph_capture(st, T, steps=args.steps, timed=True)
+        timed.graph_capture(st, T, steps=args.steps)
     torch.cuda.synchronize()
 
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -133,9 +151,14 @@ def main():
     t_wall = time.perf_counter() - t_wall
     ms_total = e0.elapsed_time(e1)
     ms_step = ms_total / args.steps
-    fwd_ms, adj_ms = timed.graph_kernel_times()
     stats = timed.decode_stats(st["stats"])
     loss_now = st["loss"].cpu().numpy()
+    # the trace kernels alone, on the same stream, right after the timed region (HIP events in the library)
+    with torch.cuda.stream(stream):
+        scratch_irr = torch.empty_like(st["irr"])
+        scratch_g = torch.empty_like(st["dLdP"])
+        fwd_ms, adj_ms = timed.time_kernels(st["Pz"], scratch_irr, st["dLdI"], scratch_g, reps=args.steps,
+                                            stream=stream)
 
     # ---- roofline of the dominant trace kernel
     iters = 0.0
@@ -179,12 +202,17 @@ def main():
 
     # ---- finite-difference baseline on the same GPU (single-design workloads)
     if not args.no_fd and len(wl.problems) == 1:
+        # at the initial design (the optimised one has rays parked on the screen edge by the target's dark
+        # border, whose discrete flips within +-h make any finite difference ill-defined)
         p = wl.problems[0]
         K = p.lens.n_u * p.lens.n_v
-        P = st["Pz"].clone()
+        P = plan.pack_cp(wl.Pz)
         irr = plan.forward(P)
         _, dLdI = plan.loss(irr, T)
         g_adj = plan.adjoint(P, dLdI).cpu().numpy()
+        # h = 1e-4 mm; the losses of the perturbed designs are reduced in double precision (their central
+        # difference is ~1e-5 of the loss itself).  A larger step is not an option: at 1e-3 mm the landing
+        # points move by ~0.1 pixel and the truncation error of the quotient reaches ~4e-3.
         h = 1e-4
         Pp = P.repeat(K, 1) + h * torch.eye(K, device=P.device)
         Pm = P.repeat(K, 1) - h * torch.eye(K, device=P.device)
@@ -194,29 +222,46 @@ def main():
         fdplan.set_config(0, plan.get_config(0))
         Tfd = T.repeat(2 * K)
         irr_fd = torch.empty(fdplan.total_img, device=P.device)
-        loss_fd = torch.empty(2 * K, device=P.device)
-        dLdI_fd = torch.empty(fdplan.total_img, device=P.device)
+        loss_fd = torch.empty(2 * K, dtype=torch.float64, device=P.device)
         fdplan.forward(Pfd, irr_fd)
-        fdplan.loss(irr_fd, Tfd, loss_fd, dLdI_fd)
+        fdplan.loss_f64(irr_fd, Tfd, loss_fd)
         torch.cuda.synchronize()
         reps = 3
         f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         f0.record()
         for _ in range(reps):
             fdplan.forward(Pfd, irr_fd)
-            fdplan.loss(irr_fd, Tfd, loss_fd, dLdI_fd)
+            fdplan.loss_f64(irr_fd, Tfd, loss_fd)
         f1.record()
         torch.cuda.synchronize()
         fd_ms = f0.elapsed_time(f1) / reps
         L = loss_fd.cpu().numpy().astype(np.float64)
         g_fd = (L[0::2] - L[1::2]) / denom
-        sel = np.random.default_rng(W.STREAM_FD).choice(K, 16, replace=False)
+        # control points where some ray changes its discrete state (screen edge, TIR, side wall) within +-h:
+        # there the difference quotient measures a jump the pathwise derivative leaves out by definition
+        st_fd, st0 = fdplan.new_stats(), plan.new_stats()
+        fdplan.forward(Pfd, irr_fd, stats=st_fd)
+        plan.forward(P, stats=st0)
+        S, S0 = fdplan.decode_stats(st_fd), plan.decode_stats(st0)[0]
+        keys = ("n_hit", "n_miss_entry", "n_side_wall", "n_tir", "n_off_screen")
+        flip = np.array([any(S[2 * k][c] != S0[c] or S[2 * k + 1][c] != S0[c] for c in keys) for k in range(K)])
+        clean = np.where(~flip)[0]
+        sel = np.random.default_rng(W.STREAM_FD).choice(clean, min(16, len(clean)), replace=False)
         gmax = np.abs(g_adj).max()
-        out["fd"] = {"h_mm": h, "control_points": K, "rays_per_gradient": 2 * K * rays,
-                     "ms_per_gradient": fd_ms, "speedup_of_step": fd_ms / ms_step,
-                     "max_rel_err_16cp": float(np.abs(g_fd[sel] - g_adj[sel]).max() / gmax),
-                     "max_rel_err_all": float(np.abs(g_fd - g_adj).max() / gmax),
-                     "note": "FP32 losses; error relative to max |dL/dP|"}
+        fd = {"h_mm": h, "control_points": K, "rays_per_gradient": 2 * K * rays,
+              "ms_per_gradient": fd_ms, "speedup_of_step": fd_ms / ms_step,
+              "max_rel_err_16cp": float(np.abs(g_fd[sel] - g_adj[sel]).max() / gmax),
+              "max_rel_err_all_flip_free": float(np.abs(g_fd[clean] - g_adj[clean]).max() / gmax),
+              "cps_with_state_flips": int(flip.sum()),
+              "note": "initial design; FP32 images, losses reduced in FP64; errors relative to max |dL/dP| "
+                      "over control points whose rays keep their discrete state within +-h"}
+        if not args.no_cpu:
+            import oracle
+            _, g64, _, _ = oracle.grad(p, wl.Pz[0], wl.targets[0], threads=min(16, len(os.sched_getaffinity(0))))
+            g64 = g64.ravel()
+            fd["adjoint_vs_oracle_fp64"] = float(np.abs(g_adj - g64).max() / np.abs(g64).max())
+            fd["fd_vs_oracle_fp64_16cp"] = float(np.abs(g_fd[sel] - g64[sel]).max() / np.abs(g64).max())
+        out["fd"] = fd
 
     if not args.no_cpu and len(wl.problems) == 1:
         out["cpu_baseline"] = cpu_baseline(wl)

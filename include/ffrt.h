@@ -146,6 +146,11 @@ ffrt_status ffrt_forward(ffrt_plan* plan, const float* Pz, float* irr, ffrt_stat
 ffrt_status ffrt_loss(ffrt_plan* plan, const float* irr, const float* target, float* loss, float* dL_dI,
                       void* stream);
 
+/* Loss value per design (n_designs doubles, device) with every reduction in double precision, no dL/dI.
+ * For finite-difference gradients: a central difference over h = 1e-4 mm changes the loss by ~1e-5 of
+ * itself, below what single-precision sums resolve.  Not used by the optimisation step. */
+ffrt_status ffrt_loss_f64(ffrt_plan* plan, const float* irr, const float* target, double* loss, void* stream);
+
 /* Pathwise gradient dL/dP^z (packed like Pz) of sum_ij dL_dI_ij I_ij: re-traces every ray (nothing per ray
  * is stored) and back-propagates through splat, screen, refraction and the root (implicit function
  * theorem).  Zeroes dL_dP first. */
@@ -162,15 +167,11 @@ ffrt_status ffrt_step(ffrt_plan* plan, float* Pz, const float* target, float* ir
                       const ffrt_adam_hparams* hp, void* stream);
 
 /* Capture `steps` consecutive ffrt_step calls into a HIP graph owned by the plan (stream must not be the
- * NULL stream).  The arguments are bound at capture.  ffrt_graph_launch replays it on `stream`.
- * timed = 1 also records HIP events immediately around every step's forward and adjoint trace kernel
- * (event nodes of the graph, on the capturing stream); ffrt_graph_kernel_times then reports their mean
- * durations over the steps of the last replay, once the caller has synchronised with it. */
+ * NULL stream).  The arguments are bound at capture.  ffrt_graph_launch replays it on `stream`. */
 ffrt_status ffrt_graph_capture(ffrt_plan* plan, int32_t steps, float* Pz, const float* target, float* irr,
                                float* loss, float* dL_dI, float* dL_dP, float* m, float* v, int32_t* t,
-                               ffrt_stats* stats, const ffrt_adam_hparams* hp, int32_t timed, void* stream);
+                               ffrt_stats* stats, const ffrt_adam_hparams* hp, void* stream);
 ffrt_status ffrt_graph_launch(ffrt_plan* plan, void* stream);
-ffrt_status ffrt_graph_kernel_times(ffrt_plan* plan, float* fwd_ms, float* adj_ms);
 
 /* ---- kernel shapes (autotuner) ------------------------------------------------------------------- */
 
@@ -179,6 +180,13 @@ ffrt_status ffrt_num_configs(int32_t which, int32_t* n);
 ffrt_status ffrt_config_name(int32_t which, int32_t index, char* buf, int32_t buflen);
 ffrt_status ffrt_plan_set_config(ffrt_plan* plan, int32_t which, int32_t index);
 ffrt_status ffrt_plan_get_config(const ffrt_plan* plan, int32_t which, int32_t* index);
+
+/* Mean duration (ms) of the forward and the adjoint trace kernel alone, each launched `reps` times back to
+ * back between two HIP events recorded on `stream` with the plan's current shapes (the zeroing and bounds
+ * kernels of the full calls run once before).  Synchronises the stream.  irr and dL_dP are overwritten
+ * (they accumulate over the repetitions). */
+ffrt_status ffrt_plan_time_kernels(ffrt_plan* plan, const float* Pz, float* irr, const float* dL_dI,
+                                   float* dL_dP, int32_t reps, float* fwd_ms, float* adj_ms, void* stream);
 
 /* Time every candidate shape on the caller's buffers (reps launches each, HIP events, synchronises the
  * stream) and keep the fastest for each kernel.  irr and dL_dP are overwritten. */

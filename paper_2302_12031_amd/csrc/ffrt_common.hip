@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "ffrt_internal.h"
 
 namespace ffrt {
@@ -16,6 +18,17 @@ __host__ __device__ inline uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
 }
+
+// Compensated (Neumaier) running sum: s + c carries the rounding error of the additions.
+struct CSum {
+    float s = 0.0f, c = 0.0f;
+    __device__ void add(float x) {
+        float t = s + x;
+        c += (fabsf(s) >= fabsf(x)) ? (s - t) + x : (x - t) + s;
+        s = t;
+    }
+    __device__ float value() const { return s + c; }
+};
 
 // Block-wide sum over blockDim.x threads (a multiple of 64, at most 1024).
 __device__ inline float block_sum(float v, float* sh) {
@@ -42,22 +55,21 @@ __device__ inline float block_max(float v, float* sh) {
     return s;
 }
 
-__global__ void k_zero(float* __restrict__ a, int64_t n, ffrt_stats* stats, int n_stats) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = i; k < n; k += stride) a[k] = 0.0f;
-    if (stats) {
-        uint32_t* s = reinterpret_cast<uint32_t*>(stats);
-        int64_t ns = (int64_t)n_stats * (sizeof(ffrt_stats) / 4);
-        for (int64_t k = i; k < ns; k += stride) s[k] = 0u;
+// Per design (blocks 0 .. n_designs-1): global bounds of P^z (sec. 2.2.2), slope bounds from the derivative
+// control points p (P_{i+1,j} - P_{i,j}) / (u_{i+p+1} - u_{i+1}) (textbook derivative of a B-spline), and the
+// lens checks of sec. 2.1.2 (P^z >= z_in + delta) and finiteness.  Every block also clears its share of the
+// arrays z0, z1, z2.
+__global__ __launch_bounds__(256) void k_prepare(const DesignDev* designs, int n_designs, const float* __restrict__ Pz,
+                                                 int p, int q, BoundsDev* bounds, float* z0, int64_t n0, float* z1,
+                                                 int64_t n1, float* z2, int64_t n2) {
+    {
+        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+        const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        if (z0) for (int64_t k = i0; k < n0; k += stride) z0[k] = 0.0f;
+        if (z1) for (int64_t k = i0; k < n1; k += stride) z1[k] = 0.0f;
+        if (z2) for (int64_t k = i0; k < n2; k += stride) z2[k] = 0.0f;
     }
-}
-
-// Per design: global bounds of P^z (sec. 2.2.2), slope bounds from the derivative control points
-// p (P_{i+1,j} - P_{i,j}) / (u_{i+p+1} - u_{i+1}) (textbook derivative of a B-spline), and the lens checks
-// of sec. 2.1.2 (P^z >= z_in + delta) and finiteness, counted into the stats.
-__global__ __launch_bounds__(256) void k_bounds(const DesignDev* designs, const float* __restrict__ Pz, int p,
-                                                int q, BoundsDev* bounds, ffrt_stats* stats) {
+    if (!Pz || (int)blockIdx.x >= n_designs) return;
     __shared__ float sh[16];
     const DesignDev& D = designs[blockIdx.x];
     const float* P = Pz + D.cp_off;
@@ -91,16 +103,40 @@ __global__ __launch_bounds__(256) void k_bounds(const DesignDev* designs, const 
         B.zmin = lo;
         B.zmax = hi;
         B.zref = 0.5f * (lo + hi);
-        B.pad_[0] = B.pad_[1] = B.pad_[2] = 0.0f;
         // d(ubar)/dx = sxu; a small relative margin keeps the bound conservative under rounding
         B.gx = gu * D.sxu * 1.0001f;
         B.gy = gv * D.syv * 1.0001f;
+        B.n_bad = (uint32_t)nbad;
+        B.n_nan = (uint32_t)nnan;
+        B.pad_ = 0.0f;
         bounds[blockIdx.x] = B;
-        if (stats) {
-            stats[blockIdx.x].n_constraint_viol = (uint32_t)nbad;
-            stats[blockIdx.x].n_nan = (uint32_t)nnan;
+    }
+}
+
+// Sum the NSLOT partial slots of design d into stats[d] (threads of one block).
+__device__ void reduce_slots(int d, const BoundsDev* bounds, const ffrt_stats* slots, ffrt_stats* stats) {
+    constexpr int NF = sizeof(ffrt_stats) / 4;
+    const ffrt_stats* sl = slots + (size_t)d * NSLOT;
+    for (int f = threadIdx.x; f < NF; f += blockDim.x) {
+        if (f == 0) {
+            float acc = 0.0f;
+            for (int k = 0; k < NSLOT; ++k) acc += sl[k].flux_on_screen;
+            stats[d].flux_on_screen = acc;
+        } else {
+            uint32_t acc = 0;
+            for (int k = 0; k < NSLOT; ++k) acc += reinterpret_cast<const uint32_t*>(sl + k)[f];
+            reinterpret_cast<uint32_t*>(stats + d)[f] = acc;
         }
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        stats[d].n_constraint_viol = bounds[d].n_bad;
+        stats[d].n_nan = bounds[d].n_nan;
+    }
+}
+
+__global__ void k_stats(const BoundsDev* bounds, const ffrt_stats* slots, ffrt_stats* stats) {
+    reduce_slots(blockIdx.x, bounds, slots, stats);
 }
 
 // Loss of sec. 2.5 per design: I_hat = I / sum I, I_ref_hat = T / sum T, D = I_hat - I_ref_hat,
@@ -108,20 +144,24 @@ __global__ __launch_bounds__(256) void k_bounds(const DesignDev* designs, const 
 // A design without flux gets L = NaN, dL/dI = 0 and valid = 0 (its Adam update is skipped).
 __global__ __launch_bounds__(1024) void k_loss(const DesignDev* designs, const float* __restrict__ irr,
                                                const float* __restrict__ target, float* loss, float* dLdI,
-                                               int32_t* valid) {
+                                               int32_t* valid, const BoundsDev* bounds, const ffrt_stats* slots,
+                                               ffrt_stats* stats) {
     __shared__ float sh[16];
+    if (stats) reduce_slots(blockIdx.x, bounds, slots, stats);
     const DesignDev& D = designs[blockIdx.x];
     const int64_t n = (int64_t)D.nx * D.ny;
     const float* I = irr + D.img_off;
     const float* T = target + D.img_off;
     float* G = dLdI + D.img_off;
-    float a = 0.0f, b = 0.0f;
+    // compensated per-thread sums: the loss is differenced by finite-difference checks, so its rounding
+    // has to stay near one ulp
+    CSum a, b;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        a += I[i];
-        b += T[i];
+        a.add(I[i]);
+        b.add(T[i]);
     }
-    float s = block_sum(a, sh);
-    float sT = block_sum(b, sh);
+    float s = block_sum(a.value(), sh);
+    float sT = block_sum(b.value(), sh);
     if (!(s > 0.0f) || !(sT > 0.0f)) {
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) G[i] = 0.0f;
         if (threadIdx.x == 0) {
@@ -131,15 +171,15 @@ __global__ __launch_bounds__(1024) void k_loss(const DesignDev* designs, const f
         return;
     }
     const float is = 1.0f / s, isT = 1.0f / sT;
-    float d2 = 0.0f, dot = 0.0f;
+    CSum cd2, cdot;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
         float ih = I[i] * is;
         float Dv = ih - T[i] * isT;
-        d2 += Dv * Dv;
-        dot += Dv * ih;
+        cd2.add(Dv * Dv);
+        cdot.add(Dv * ih);
     }
-    d2 = block_sum(d2, sh);
-    dot = block_sum(dot, sh);
+    float d2 = block_sum(cd2.value(), sh);
+    float dot = block_sum(cdot.value(), sh);
     const float nrm = sqrtf(d2), rn = sqrtf((float)n);
     const float coef = nrm > 0.0f ? 1.0f / (s * rn * nrm) : 0.0f;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
@@ -150,6 +190,45 @@ __global__ __launch_bounds__(1024) void k_loss(const DesignDev* designs, const f
         loss[blockIdx.x] = nrm / rn;
         valid[blockIdx.x] = 1;
     }
+}
+
+__device__ inline double block_sum_f64(double v, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[w];
+    return s;
+}
+
+// The loss value of sec. 2.5 with double-precision reductions (finite-difference checks only).
+__global__ __launch_bounds__(1024) void k_loss_f64(const DesignDev* designs, const float* __restrict__ irr,
+                                                   const float* __restrict__ target, double* loss) {
+    __shared__ double sh[16];
+    const DesignDev& D = designs[blockIdx.x];
+    const int64_t n = (int64_t)D.nx * D.ny;
+    const float* I = irr + D.img_off;
+    const float* T = target + D.img_off;
+    double a = 0.0, b = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        a += (double)I[i];
+        b += (double)T[i];
+    }
+    double s = block_sum_f64(a, sh), sT = block_sum_f64(b, sh);
+    if (!(s > 0.0) || !(sT > 0.0)) {
+        if (threadIdx.x == 0) loss[blockIdx.x] = NAN;
+        return;
+    }
+    double d2 = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        double Dv = (double)I[i] / s - (double)T[i] / sT;
+        d2 += Dv * Dv;
+    }
+    d2 = block_sum_f64(d2, sh);
+    if (threadIdx.x == 0) loss[blockIdx.x] = sqrt(d2 / (double)n);
 }
 
 // Adam (Kingma & Ba) per design; the step counter lives on the device so the update can be replayed from
@@ -187,24 +266,36 @@ __global__ void k_rng(uint64_t state0, uint64_t first, int64_t n, uint64_t* out)
 
 uint64_t splitmix_state0(uint64_t seed, uint64_t stream_id) { return mix64(seed + stream_id * GAMMA); }
 
-hipError_t launch_zero(float* a, int64_t n, ffrt_stats* stats, int n_stats, hipStream_t s) {
-    int64_t work = n > (int64_t)n_stats * 16 ? n : (int64_t)n_stats * 16;
-    int grid = (int)((work + 255) / 256);
-    if (grid > 4096) grid = 4096;
+hipError_t launch_prepare(const DesignDev* designs, int n_designs, const float* Pz, int p, int q,
+                          BoundsDev* bounds, float* z0, int64_t n0, float* z1, int64_t n1, float* z2, int64_t n2,
+                          hipStream_t s) {
+    int64_t work = std::max<int64_t>(std::max<int64_t>(z0 ? n0 : 0, z1 ? n1 : 0), z2 ? n2 : 0);
+    int64_t extra = (work + 255) / 256;
+    if (extra > 2048) extra = 2048;
+    int grid = (int)std::max<int64_t>(Pz ? n_designs : 0, extra);
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_zero, dim3(grid), dim3(256), 0, s, a, n, stats, n_stats);
+    hipLaunchKernelGGL(k_prepare, dim3(grid), dim3(256), 0, s, designs, n_designs, Pz, p, q, bounds, z0, n0, z1, n1,
+                       z2, n2);
     return hipGetLastError();
 }
 
-hipError_t launch_bounds(const DesignDev* designs, int n_designs, const float* Pz, int p, int q,
-                         BoundsDev* bounds, ffrt_stats* stats, hipStream_t s) {
-    hipLaunchKernelGGL(k_bounds, dim3(n_designs), dim3(256), 0, s, designs, Pz, p, q, bounds, stats);
+hipError_t launch_stats(int n_designs, const BoundsDev* bounds, const ffrt_stats* slots, ffrt_stats* stats,
+                        hipStream_t s) {
+    hipLaunchKernelGGL(k_stats, dim3(n_designs), dim3(64), 0, s, bounds, slots, stats);
     return hipGetLastError();
 }
 
 hipError_t launch_loss(const DesignDev* designs, int n_designs, const float* irr, const float* target,
-                       float* loss, float* dLdI, int32_t* valid, hipStream_t s) {
-    hipLaunchKernelGGL(k_loss, dim3(n_designs), dim3(1024), 0, s, designs, irr, target, loss, dLdI, valid);
+                       float* loss, float* dLdI, int32_t* valid, const BoundsDev* bounds, const ffrt_stats* slots,
+                       ffrt_stats* stats, hipStream_t s) {
+    hipLaunchKernelGGL(k_loss, dim3(n_designs), dim3(1024), 0, s, designs, irr, target, loss, dLdI, valid, bounds,
+                       slots, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_f64(const DesignDev* designs, int n_designs, const float* irr, const float* target,
+                           double* loss, hipStream_t s) {
+    hipLaunchKernelGGL(k_loss_f64, dim3(n_designs), dim3(1024), 0, s, designs, irr, target, loss);
     return hipGetLastError();
 }
 

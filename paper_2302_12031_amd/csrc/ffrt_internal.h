@@ -12,9 +12,15 @@ constexpr int TILE_CAP = 6144;        // floats in the LDS irradiance tile of th
 constexpr int MAX_DEG = 5;
 constexpr int N_SHAPES = 5;           // block shapes: rays per thread 1, 2, 4, 8, 16
 constexpr int RPT_OF_SHAPE[N_SHAPES] = {1, 2, 4, 8, 16};
+constexpr int NSLOT = 64;             // per-design partial-statistics slots (spreads the counter atomics)
 
 // Ray status codes (same meaning as the public ffrt_trace_rays status).
 enum : int { ST_HIT = 0, ST_MISS_ENTRY = 1, ST_SIDE_WALL = 2, ST_TIR = 3, ST_OFF_SCREEN = 4 };
+
+// Block shapes: every thread traces an MU x MV patch of adjacent samples (RPT = MU MV rays), a wave covers
+// 8 x 8 such patches and a workgroup 2 x 2 waves, so a block is (16 MU) x (16 MV) samples.
+__host__ __device__ constexpr int shape_mu(int s) { return s <= 1 ? 1 : (s <= 3 ? 2 : 4); }
+__host__ __device__ constexpr int shape_mv(int s) { return s == 0 ? 1 : (s <= 2 ? 2 : 4); }
 
 // Per-axis knot table stride (floats) for degree p: 2p local knots + p(p+1)/2 reciprocals, padded to 4.
 __host__ __device__ constexpr int kt_stride(int p) { return ((2 * p + p * (p + 1) / 2) + 3) / 4 * 4; }
@@ -50,7 +56,8 @@ struct DesignDev {
 struct BoundsDev {
     float zmin, zmax, gx, gy;        // gx, gy: bounds of |dh/dx|, |dh/dy| from derivative control points
     float zref;                      // reference height subtracted from P^z in LDS: (zmin + zmax) / 2
-    float pad_[3];
+    uint32_t n_bad, n_nan;           // control points below z_in + delta_min, non-finite control points
+    float pad_;
 };
 
 // Block map of one design for one block shape.
@@ -70,7 +77,7 @@ struct TraceArgs {
     int32_t lds_kt;                  // floats of the LDS knot tables
     const float* Pz;
     float* irr;                      // forward output
-    ffrt_stats* stats;               // forward stats (may be null)
+    ffrt_stats* slots;               // forward: NSLOT partial-statistics slots per design (may be null)
     const float* dLdI;               // adjoint input
     float* dLdP;                     // adjoint output
     int32_t use_tile;                // forward: LDS footprint tile
@@ -82,19 +89,19 @@ struct AdjCfg { int shape; int butterfly; int persistent; const char* name; };
 
 constexpr FwdCfg FWD_CFGS[] = {
     {2, 1, 0, "fwd rpt4 lds-tile"},
-    {1, 1, 0, "fwd rpt2 lds-tile"},
     {3, 1, 0, "fwd rpt8 lds-tile"},
-    {2, 0, 0, "fwd rpt4 global-atomics"},
-    {0, 0, 0, "fwd rpt1 global-atomics"},
+    {1, 1, 0, "fwd rpt2 lds-tile"},
+    {0, 1, 0, "fwd rpt1 lds-tile"},
     {3, 1, 1, "fwd rpt8 lds-tile persistent"},
+    {2, 0, 0, "fwd rpt4 global-atomics"},
 };
 constexpr AdjCfg ADJ_CFGS[] = {
     {2, 1, 0, "adj rpt4 butterfly"},
-    {1, 1, 0, "adj rpt2 butterfly"},
     {3, 1, 0, "adj rpt8 butterfly"},
-    {2, 0, 0, "adj rpt4 lds-atomics"},
     {4, 1, 0, "adj rpt16 butterfly"},
-    {3, 1, 1, "adj rpt8 butterfly persistent"},
+    {1, 1, 0, "adj rpt2 butterfly"},
+    {3, 0, 0, "adj rpt8 lds-atomics"},
+    {4, 1, 1, "adj rpt16 butterfly persistent"},
 };
 constexpr int N_FWD_CFGS = sizeof(FWD_CFGS) / sizeof(FWD_CFGS[0]);
 constexpr int N_ADJ_CFGS = sizeof(ADJ_CFGS) / sizeof(ADJ_CFGS[0]);
@@ -111,11 +118,20 @@ struct KernelSet {
 const KernelSet* kernel_set(int P, int Q, int NU);
 
 // Kernels that do not depend on the degrees (ffrt_common.hip).
-hipError_t launch_zero(float* a, int64_t n, ffrt_stats* stats, int n_stats, hipStream_t s);
-hipError_t launch_bounds(const DesignDev* designs, int n_designs, const float* Pz, int p, int q,
-                         BoundsDev* bounds, ffrt_stats* stats, hipStream_t s);
+// One launch per call: convex-hull bounds and lens checks per design (Pz may be null to skip them), and
+// zeroing of up to three float arrays (null arrays are skipped).
+hipError_t launch_prepare(const DesignDev* designs, int n_designs, const float* Pz, int p, int q,
+                          BoundsDev* bounds, float* z0, int64_t n0, float* z1, int64_t n1, float* z2, int64_t n2,
+                          hipStream_t s);
+// Sums the NSLOT partial-statistics slots of every design into stats (and the lens checks of bounds).
+hipError_t launch_stats(int n_designs, const BoundsDev* bounds, const ffrt_stats* slots, ffrt_stats* stats,
+                        hipStream_t s);
+// Loss and dL/dI; when stats is not null it also performs launch_stats' reduction.
 hipError_t launch_loss(const DesignDev* designs, int n_designs, const float* irr, const float* target,
-                       float* loss, float* dLdI, int32_t* valid, hipStream_t s);
+                       float* loss, float* dLdI, int32_t* valid, const BoundsDev* bounds,
+                       const ffrt_stats* slots, ffrt_stats* stats, hipStream_t s);
+hipError_t launch_loss_f64(const DesignDev* designs, int n_designs, const float* irr, const float* target,
+                           double* loss, hipStream_t s);
 hipError_t launch_adam(const DesignDev* designs, int n_designs, float* Pz, const float* g, float* m,
                        float* v, int32_t* t, const int32_t* valid, ffrt_adam_hparams hp, hipStream_t s);
 hipError_t launch_rng(uint64_t seed, uint64_t stream_id, uint64_t first, int64_t n, uint64_t* out,

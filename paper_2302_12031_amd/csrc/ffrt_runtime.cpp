@@ -53,12 +53,7 @@ ffrt_status hip_fail(hipError_t e, const char* where) {
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct ShapeDims { int BU, BV; };
-ShapeDims shape_dims(int shape) {
-    int rpt = RPT_OF_SHAPE[shape];
-    int PU = (shape == 0) ? 2 : (shape <= 2 ? 4 : 8);
-    int PV = 4 * rpt / PU;
-    return {8 * PU, 8 * PV};
-}
+ShapeDims shape_dims(int shape) { return {16 * shape_mu(shape), 16 * shape_mv(shape)}; }
 
 }  // namespace
 
@@ -76,13 +71,11 @@ struct ffrt_plan {
     // workspace
     char* ws = nullptr;
     size_t ws_bytes = 0;
-    size_t off_designs = 0, off_bounds = 0, off_valid = 0, off_knots = 0, off_bmap = 0, need = 0;
+    size_t off_designs = 0, off_bounds = 0, off_valid = 0, off_knots = 0, off_bmap = 0, off_slots = 0, need = 0;
     int num_cu = 256;
     int fwd_cfg = 0, adj_cfg = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    std::vector<hipEvent_t> gev;      // timed graphs: 4 events per step (fwd start/stop, adj start/stop)
-    int gsteps = 0;
 
     DesignDev* d_designs() const { return reinterpret_cast<DesignDev*>(ws + off_designs); }
     BoundsDev* d_bounds() const { return reinterpret_cast<BoundsDev*>(ws + off_bounds); }
@@ -91,6 +84,8 @@ struct ffrt_plan {
     BlockMap* d_bmap(int shape) const {
         return reinterpret_cast<BlockMap*>(ws + off_bmap) + (size_t)shape * nd;
     }
+    ffrt_stats* d_slots() const { return reinterpret_cast<ffrt_stats*>(ws + off_slots); }
+    int64_t slot_floats() const { return (int64_t)nd * NSLOT * (int64_t)(sizeof(ffrt_stats) / 4); }
 };
 
 namespace {
@@ -225,13 +220,6 @@ DesignDev make_design(const ffrt_problem& pr, int64_t cp_off, int64_t img_off, i
 
 bool ready(ffrt_plan* p) { return p && p->ws; }
 
-void free_graph_events(ffrt_plan* p) {
-    for (auto e : p->gev)
-        if (e) (void)hipEventDestroy(e);
-    p->gev.clear();
-    p->gsteps = 0;
-}
-
 TraceArgs make_args(ffrt_plan* pl, int shape) {
     TraceArgs A;
     std::memset(&A, 0, sizeof A);
@@ -250,50 +238,63 @@ int grid_for(ffrt_plan* pl, int shape, int persistent) {
     int64_t nb = pl->nblocks[shape];
     int64_t g = nb;
     if (persistent) g = std::min<int64_t>(nb, (int64_t)pl->num_cu * 4);
-    if (g > 0x7FFFFFFF) g = 0x7FFFFFFF;
+    // launches are limited to 2^31 work items; larger batches loop over blocks inside the kernel
+    if (g > ((int64_t)1 << 22)) g = (int64_t)1 << 22;
     return (int)std::max<int64_t>(g, 1);
 }
 
-// ev: optional pair of events recorded immediately around the trace kernel.
-ffrt_status run_forward(ffrt_plan* pl, const float* Pz, float* irr, ffrt_stats* stats, hipStream_t s,
-                        hipEvent_t* ev = nullptr) {
-    HIP_TRY(launch_zero(irr, pl->total_img, stats, stats ? pl->nd : 0, s));
-    HIP_TRY(launch_bounds(pl->d_designs(), pl->nd, Pz, pl->P, pl->Q, pl->d_bounds(), stats, s));
+// The forward trace kernel; partial statistics go to the plan's slots when `stats` is set.
+ffrt_status launch_forward(ffrt_plan* pl, const float* Pz, float* irr, bool stats, hipStream_t s) {
     const FwdCfg& c = FWD_CFGS[pl->fwd_cfg];
     TraceArgs A = make_args(pl, c.shape);
     A.Pz = Pz;
     A.irr = irr;
-    A.stats = stats;
+    A.slots = stats ? pl->d_slots() : nullptr;
     A.use_tile = c.tile;
-    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     HIP_TRY(pl->ks->forward(A, c.shape, grid_for(pl, c.shape, c.persistent), s));
-    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     return FFRT_OK;
 }
 
-ffrt_status run_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, float* dLdP, bool need_bounds,
-                        hipStream_t s, hipEvent_t* ev = nullptr) {
-    HIP_TRY(launch_zero(dLdP, pl->total_cp, nullptr, 0, s));
-    if (need_bounds) HIP_TRY(launch_bounds(pl->d_designs(), pl->nd, Pz, pl->P, pl->Q, pl->d_bounds(), nullptr, s));
+ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, float* dLdP, hipStream_t s) {
     const AdjCfg& c = ADJ_CFGS[pl->adj_cfg];
     TraceArgs A = make_args(pl, c.shape);
     A.Pz = Pz;
     A.dLdI = dLdI;
     A.dLdP = dLdP;
     A.butterfly = c.butterfly;
-    if (ev) HIP_TRY(hipEventRecord(ev[0], s));
     HIP_TRY(pl->ks->adjoint(A, c.shape, grid_for(pl, c.shape, c.persistent), s));
-    if (ev) HIP_TRY(hipEventRecord(ev[1], s));
     return FFRT_OK;
 }
 
+ffrt_status run_forward(ffrt_plan* pl, const float* Pz, float* irr, ffrt_stats* stats, hipStream_t s) {
+    HIP_TRY(launch_prepare(pl->d_designs(), pl->nd, Pz, pl->P, pl->Q, pl->d_bounds(), irr, pl->total_img,
+                           stats ? reinterpret_cast<float*>(pl->d_slots()) : nullptr, pl->slot_floats(), nullptr, 0,
+                           s));
+    ffrt_status st = launch_forward(pl, Pz, irr, stats != nullptr, s);
+    if (st) return st;
+    if (stats) HIP_TRY(launch_stats(pl->nd, pl->d_bounds(), pl->d_slots(), stats, s));
+    return FFRT_OK;
+}
+
+ffrt_status run_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, float* dLdP, hipStream_t s) {
+    HIP_TRY(launch_prepare(pl->d_designs(), pl->nd, Pz, pl->P, pl->Q, pl->d_bounds(), dLdP, pl->total_cp, nullptr,
+                           0, nullptr, 0, s));
+    return launch_adjoint(pl, Pz, dLdI, dLdP, s);
+}
+
+// One optimisation step in five kernels: prepare (bounds, clearing), forward, loss (+ statistics),
+// adjoint, Adam.
 ffrt_status run_step(ffrt_plan* pl, float* Pz, const float* target, float* irr, float* loss, float* dLdI,
                      float* dLdP, float* m, float* v, int32_t* t, ffrt_stats* stats, const ffrt_adam_hparams& hp,
-                     hipStream_t s, hipEvent_t* ev = nullptr) {
-    ffrt_status st = run_forward(pl, Pz, irr, stats, s, ev);
+                     hipStream_t s) {
+    HIP_TRY(launch_prepare(pl->d_designs(), pl->nd, Pz, pl->P, pl->Q, pl->d_bounds(), irr, pl->total_img, dLdP,
+                           pl->total_cp, stats ? reinterpret_cast<float*>(pl->d_slots()) : nullptr,
+                           pl->slot_floats(), s));
+    ffrt_status st = launch_forward(pl, Pz, irr, stats != nullptr, s);
     if (st) return st;
-    HIP_TRY(launch_loss(pl->d_designs(), pl->nd, irr, target, loss, dLdI, pl->d_valid(), s));
-    st = run_adjoint(pl, Pz, dLdI, dLdP, false, s, ev ? ev + 2 : nullptr);
+    HIP_TRY(launch_loss(pl->d_designs(), pl->nd, irr, target, loss, dLdI, pl->d_valid(), pl->d_bounds(),
+                        pl->d_slots(), stats, s));
+    st = launch_adjoint(pl, Pz, dLdI, dLdP, s);
     if (st) return st;
     HIP_TRY(launch_adam(pl->d_designs(), pl->nd, Pz, dLdP, m, v, t, pl->d_valid(), hp, s));
     return FFRT_OK;
@@ -391,6 +392,8 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
     off = align256(off + sizeof(float) * pl->knots.size());
     pl->off_bmap = off;
     off = align256(off + sizeof(BlockMap) * N_SHAPES * n_designs);
+    pl->off_slots = off;
+    off = align256(off + sizeof(ffrt_stats) * NSLOT * n_designs);
     pl->need = off;
     *out = pl;
     return FFRT_OK;
@@ -398,7 +401,6 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
 
 ffrt_status ffrt_plan_destroy(ffrt_plan* plan) {
     if (!plan) return FFRT_OK;
-    free_graph_events(plan);
     if (plan->gexec) (void)hipGraphExecDestroy(plan->gexec);
     if (plan->graph) (void)hipGraphDestroy(plan->graph);
     delete plan;
@@ -463,14 +465,22 @@ ffrt_status ffrt_loss(ffrt_plan* plan, const float* irr, const float* target, fl
                       void* stream) {
     if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
     if (!irr || !target || !loss || !dL_dI) return fail(FFRT_E_ARG, "null buffer");
-    HIP_TRY(launch_loss(plan->d_designs(), plan->nd, irr, target, loss, dL_dI, plan->d_valid(), (hipStream_t)stream));
+    HIP_TRY(launch_loss(plan->d_designs(), plan->nd, irr, target, loss, dL_dI, plan->d_valid(), plan->d_bounds(),
+                        plan->d_slots(), nullptr, (hipStream_t)stream));
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_loss_f64(ffrt_plan* plan, const float* irr, const float* target, double* loss, void* stream) {
+    if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
+    if (!irr || !target || !loss) return fail(FFRT_E_ARG, "null buffer");
+    HIP_TRY(launch_loss_f64(plan->d_designs(), plan->nd, irr, target, loss, (hipStream_t)stream));
     return FFRT_OK;
 }
 
 ffrt_status ffrt_adjoint(ffrt_plan* plan, const float* Pz, const float* dL_dI, float* dL_dP, void* stream) {
     if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
     if (!Pz || !dL_dI || !dL_dP) return fail(FFRT_E_ARG, "null buffer");
-    return run_adjoint(plan, Pz, dL_dI, dL_dP, true, (hipStream_t)stream);
+    return run_adjoint(plan, Pz, dL_dI, dL_dP, (hipStream_t)stream);
 }
 
 ffrt_status ffrt_adam(ffrt_plan* plan, float* Pz, const float* dL_dP, float* m, float* v, int32_t* t,
@@ -492,7 +502,7 @@ ffrt_status ffrt_step(ffrt_plan* plan, float* Pz, const float* target, float* ir
 
 ffrt_status ffrt_graph_capture(ffrt_plan* plan, int32_t steps, float* Pz, const float* target, float* irr,
                                float* loss, float* dL_dI, float* dL_dP, float* m, float* v, int32_t* t,
-                               ffrt_stats* stats, const ffrt_adam_hparams* hp, int32_t timed, void* stream) {
+                               ffrt_stats* stats, const ffrt_adam_hparams* hp, void* stream) {
     if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
     if (!stream) return fail(FFRT_E_ARG, "graph capture needs a non-default stream");
     if (steps < 1) return fail(FFRT_E_ARG, "steps must be >= 1");
@@ -501,17 +511,10 @@ ffrt_status ffrt_graph_capture(ffrt_plan* plan, int32_t steps, float* Pz, const 
     hipStream_t s = (hipStream_t)stream;
     if (plan->gexec) { (void)hipGraphExecDestroy(plan->gexec); plan->gexec = nullptr; }
     if (plan->graph) { (void)hipGraphDestroy(plan->graph); plan->graph = nullptr; }
-    free_graph_events(plan);
-    if (timed) {
-        plan->gev.resize((size_t)4 * steps, nullptr);
-        for (auto& e : plan->gev) HIP_TRY(hipEventCreate(&e));
-        plan->gsteps = steps;
-    }
     HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     ffrt_status st = FFRT_OK;
     for (int i = 0; i < steps && st == FFRT_OK; ++i)
-        st = run_step(plan, Pz, target, irr, loss, dL_dI, dL_dP, m, v, t, stats, *hp, s,
-                      timed ? &plan->gev[(size_t)4 * i] : nullptr);
+        st = run_step(plan, Pz, target, irr, loss, dL_dI, dL_dP, m, v, t, stats, *hp, s);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s, &g);
     if (st) { if (g) (void)hipGraphDestroy(g); return st; }
@@ -527,22 +530,6 @@ ffrt_status ffrt_graph_capture(ffrt_plan* plan, int32_t steps, float* Pz, const 
 ffrt_status ffrt_graph_launch(ffrt_plan* plan, void* stream) {
     if (!plan || !plan->gexec) return fail(FFRT_E_STATE, "no graph captured");
     HIP_TRY(hipGraphLaunch(plan->gexec, (hipStream_t)stream));
-    return FFRT_OK;
-}
-
-ffrt_status ffrt_graph_kernel_times(ffrt_plan* plan, float* fwd_ms, float* adj_ms) {
-    if (!plan || !fwd_ms || !adj_ms) return fail(FFRT_E_ARG, "null argument");
-    if (!plan->gexec || plan->gev.empty()) return fail(FFRT_E_STATE, "no timed graph captured");
-    double f = 0.0, a = 0.0;
-    for (int i = 0; i < plan->gsteps; ++i) {
-        float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, plan->gev[4 * i], plan->gev[4 * i + 1]));
-        f += ms;
-        HIP_TRY(hipEventElapsedTime(&ms, plan->gev[4 * i + 2], plan->gev[4 * i + 3]));
-        a += ms;
-    }
-    *fwd_ms = (float)(f / plan->gsteps);
-    *adj_ms = (float)(a / plan->gsteps);
     return FFRT_OK;
 }
 
@@ -592,11 +579,11 @@ ffrt_status ffrt_plan_autotune(ffrt_plan* plan, const float* Pz, float* irr, con
         for (int c = 0; c < n && st == FFRT_OK; ++c) {
             if (which == 0) plan->fwd_cfg = c; else plan->adj_cfg = c;
             // one untimed launch, then reps timed
-            st = which == 0 ? run_forward(plan, Pz, irr, nullptr, s) : run_adjoint(plan, Pz, dL_dI, dL_dP, true, s);
+            st = which == 0 ? run_forward(plan, Pz, irr, nullptr, s) : run_adjoint(plan, Pz, dL_dI, dL_dP, s);
             if (st) break;
             if (hipEventRecord(e0, s) != hipSuccess) { st = hip_fail(hipGetLastError(), "hipEventRecord"); break; }
             for (int r = 0; r < reps && st == FFRT_OK; ++r)
-                st = which == 0 ? run_forward(plan, Pz, irr, nullptr, s) : run_adjoint(plan, Pz, dL_dI, dL_dP, true, s);
+                st = which == 0 ? run_forward(plan, Pz, irr, nullptr, s) : run_adjoint(plan, Pz, dL_dI, dL_dP, s);
             if (st) break;
             hipError_t e = hipEventRecord(e1, s);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -612,13 +599,42 @@ ffrt_status ffrt_plan_autotune(ffrt_plan* plan, const float* Pz, float* irr, con
     return st;
 }
 
+ffrt_status ffrt_plan_time_kernels(ffrt_plan* plan, const float* Pz, float* irr, const float* dL_dI,
+                                   float* dL_dP, int32_t reps, float* fwd_ms, float* adj_ms, void* stream) {
+    if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
+    if (!Pz || !irr || !dL_dI || !dL_dP || reps < 1 || !fwd_ms || !adj_ms) return fail(FFRT_E_ARG, "bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev[4];
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    ffrt_status st = run_forward(plan, Pz, irr, nullptr, s);
+    if (!st) st = run_adjoint(plan, Pz, dL_dI, dL_dP, s);
+    hipError_t e = hipSuccess;
+    if (!st) e = hipEventRecord(ev[0], s);
+    for (int r = 0; r < reps && !st && e == hipSuccess; ++r) st = launch_forward(plan, Pz, irr, false, s);
+    if (!st && e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (!st && e == hipSuccess) e = hipEventRecord(ev[2], s);
+    for (int r = 0; r < reps && !st && e == hipSuccess; ++r) st = launch_adjoint(plan, Pz, dL_dI, dL_dP, s);
+    if (!st && e == hipSuccess) e = hipEventRecord(ev[3], s);
+    if (!st && e == hipSuccess) e = hipEventSynchronize(ev[3]);
+    float f = 0.0f, a = 0.0f;
+    if (!st && e == hipSuccess) e = hipEventElapsedTime(&f, ev[0], ev[1]);
+    if (!st && e == hipSuccess) e = hipEventElapsedTime(&a, ev[2], ev[3]);
+    for (auto x : ev) (void)hipEventDestroy(x);
+    if (st) return st;
+    if (e != hipSuccess) return hip_fail(e, "kernel timing");
+    *fwd_ms = f / reps;
+    *adj_ms = a / reps;
+    return FFRT_OK;
+}
+
 ffrt_status ffrt_trace_rays(ffrt_plan* plan, int32_t design, const float* Pz, const int64_t* ray_ids, int64_t n,
                             float* out8, void* stream) {
     if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
     if (design < 0 || design >= plan->nd || !Pz || (n > 0 && (!ray_ids || !out8)) || n < 0)
         return fail(FFRT_E_ARG, "bad argument");
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(launch_bounds(plan->d_designs(), plan->nd, Pz, plan->P, plan->Q, plan->d_bounds(), nullptr, s));
+    HIP_TRY(launch_prepare(plan->d_designs(), plan->nd, Pz, plan->P, plan->Q, plan->d_bounds(), nullptr, 0, nullptr,
+                           0, nullptr, 0, s));
     TraceArgs A = make_args(plan, 0);
     A.Pz = Pz;
     HIP_TRY(plan->ks->trace_rays(A, design, ray_ids, n, out8, s));

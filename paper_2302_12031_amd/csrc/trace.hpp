@@ -44,6 +44,18 @@ __device__ __forceinline__ void two_uniforms(uint64_t h, float& a, float& b) {
     b = (float)(uint32_t)((h >> 16) & 0xFFFFFFull) * (1.0f / 16777216.0f);
 }
 
+// Loads of per-design data through the constant address space: with a wave-uniform index they become
+// scalar loads into SGPRs instead of one vector load per lane (the data is read-only during a launch).
+#define FFRT_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ T load_uniform(const T* p, int i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return ((const FFRT_CONST T*)(p))[i];
+#else
+    return p[i];  // host pass of the single-source compile: never executed
+#endif
+}
+
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll
@@ -625,18 +637,10 @@ __device__ __forceinline__ int find_design(const BlockMap* bm, int n, int64_t b)
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (bm[mid].first <= b) lo = mid; else hi = mid - 1;
+        if (load_uniform(bm, mid).first <= b) lo = mid; else hi = mid - 1;
     }
-    return lo;
+    return __builtin_amdgcn_readfirstlane(lo);
 }
-
-template <int SHAPE>
-struct Shape {
-    static constexpr int RPT = (SHAPE == 0) ? 1 : (SHAPE == 1) ? 2 : (SHAPE == 2) ? 4 : (SHAPE == 3) ? 8 : 16;
-    static constexpr int PU = (SHAPE == 0) ? 2 : (SHAPE == 1) ? 4 : (SHAPE == 2) ? 4 : 8;
-    static constexpr int PV = 4 * RPT / PU;
-    static constexpr int BU = 8 * PU, BV = 8 * PV;
-};
 
 // Load the design's control heights (relative to zref) and knot tables into LDS.
 __device__ __forceinline__ void stage_design(const TraceArgs& A, const DesignDev& D, float zref, float* sP,
@@ -651,171 +655,6 @@ __device__ __forceinline__ void stage_design(const TraceArgs& A, const DesignDev
     for (int i = threadIdx.x; i < nkv; i += WG) sK[nku + i] = kv[i];
 }
 
-// ------------------------------------------------------------------------------------------------
-// Forward kernel
-// ------------------------------------------------------------------------------------------------
-template <int P, int Q, int NU, int SHAPE>
-__global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
-    using SH = Shape<SHAPE>;
-    constexpr int RPT = SH::RPT;
-    constexpr int H = (NU - 1) / 2;
-    extern __shared__ float smem[];
-    float* sP = smem;
-    float* sK = sP + A.lds_cp;
-    float* tile = sK + A.lds_kt;
-    __shared__ int s_box[4][4];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int cur = -1;
-    for (int64_t pb = blockIdx.x; pb < A.n_blocks; pb += gridDim.x) {
-        const int64_t b = xcd_remap(pb, A.n_blocks);
-        const int d = find_design(A.bmap, A.n_designs, b);
-        const DesignDev& D = A.designs[d];
-        const BoundsDev B = A.bounds[d];
-        if (d != cur) {
-            __syncthreads();
-            stage_design(A, D, B.zref, sP, sK, P, Q);
-            __syncthreads();
-            cur = d;
-        }
-        const float* sKu = sK;
-        const float* sKv = sK + D.nsu * kt_stride(P);
-        const BlockMap bm = A.bmap[d];
-        int64_t local = b - bm.first;
-        int e = (int)(local / bm.per_emitter);
-        int rb = (int)(local - (int64_t)e * bm.per_emitter);
-        int bu = rb / bm.nbv, bv = rb - (rb / bm.nbv) * bm.nbv;
-        int64_t ebase = (int64_t)e * D.grid_u * D.grid_v;
-
-        float X[RPT], Y[RPT], W[RPT];
-        uint32_t c_hit = 0, c_miss = 0, c_side = 0, c_tir = 0, c_off = 0, c_fail = 0, c_ref = 0, c_nm = 0,
-                 c_tr = 0;
-        float flux = 0.0f;
-        int imin = 1 << 30, imax = -1, jmin = 1 << 30, jmax = -1;
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            int patch = r * 4 + wave;
-            int pu = patch / SH::PV, pv = patch - (patch / SH::PV) * SH::PV;
-            int ku = bu * SH::BU + pu * 8 + (lane >> 3);
-            int kv = bv * SH::BV + pv * 8 + (lane & 7);
-            W[r] = 0.0f;
-            X[r] = 0.0f;
-            Y[r] = 0.0f;
-            if (ku < D.grid_u && kv < D.grid_v) {
-                int64_t id = ebase + (int64_t)ku * D.grid_v + kv;
-                FwdRay o = trace_forward<P, Q>(D, B, sP, sKu, sKv, e, ku, kv, id);
-                c_tr++;
-                c_fail += o.failed;
-                c_ref += o.refined;
-                c_nm += o.nonmono;
-                switch (o.status) {
-                    case ST_HIT: c_hit++; break;
-                    case ST_MISS_ENTRY: c_miss++; break;
-                    case ST_SIDE_WALL: c_side++; break;
-                    case ST_TIR: c_tir++; break;
-                    default: c_off++; break;
-                }
-                if (o.status == ST_HIT) {
-                    X[r] = o.X;
-                    Y[r] = o.Y;
-                    W[r] = o.w;
-                    flux += o.w;
-                    int i0 = min(max((int)floorf((o.X + D.Rx) * D.inv_wx), 0), D.nx - 1);
-                    int j0 = min(max((int)floorf((o.Y + D.Ry) * D.inv_wy), 0), D.ny - 1);
-                    imin = min(imin, i0);
-                    imax = max(imax, i0);
-                    jmin = min(jmin, j0);
-                    jmax = max(jmax, j0);
-                }
-            }
-        }
-        // ---- statistics: one atomic per wave and counter
-        if (A.stats) {
-            ffrt_stats* st = A.stats + d;
-            uint32_t v0 = wave_sum(c_tr), v1 = wave_sum(c_hit), v2 = wave_sum(c_miss), v3 = wave_sum(c_side),
-                     v4 = wave_sum(c_tir), v5 = wave_sum(c_off), v6 = wave_sum(c_fail), v7 = wave_sum(c_ref),
-                     v8 = wave_sum(c_nm);
-            float fl = wave_sum(flux);
-            if (lane == 0) {
-                atomicAdd(&st->n_traced, v0);
-                if (v1) atomicAdd(&st->n_hit, v1);
-                if (v2) atomicAdd(&st->n_miss_entry, v2);
-                if (v3) atomicAdd(&st->n_side_wall, v3);
-                if (v4) atomicAdd(&st->n_tir, v4);
-                if (v5) atomicAdd(&st->n_off_screen, v5);
-                if (v6) atomicAdd(&st->n_newton_fail, v6);
-                if (v7) atomicAdd(&st->n_fp64_refined, v7);
-                if (v8) atomicAdd(&st->n_nonmonotone, v8);
-                if (fl != 0.0f) atomicAdd(&st->flux_on_screen, fl);
-            }
-        }
-        // ---- footprint of the block (landing pixels widened by the filter half-width)
-        float* img = A.irr + D.img_off;
-        bool use_tile = false;
-        int ilo = 0, jlo = 0, tw = 0, area = 0;
-        if (A.use_tile) {
-            int a0 = wave_min(imin), a1 = wave_max(imax), b0 = wave_min(jmin), b1 = wave_max(jmax);
-            if (lane == 0) {
-                s_box[wave][0] = a0;
-                s_box[wave][1] = a1;
-                s_box[wave][2] = b0;
-                s_box[wave][3] = b1;
-            }
-            __syncthreads();
-            a0 = min(min(s_box[0][0], s_box[1][0]), min(s_box[2][0], s_box[3][0]));
-            a1 = max(max(s_box[0][1], s_box[1][1]), max(s_box[2][1], s_box[3][1]));
-            b0 = min(min(s_box[0][2], s_box[1][2]), min(s_box[2][2], s_box[3][2]));
-            b1 = max(max(s_box[0][3], s_box[1][3]), max(s_box[2][3], s_box[3][3]));
-            __syncthreads();
-            if (a1 < 0) continue;  // no ray of the block reached the screen
-            ilo = max(a0 - H, 0);
-            int ihi = min(a1 + H, D.nx - 1);
-            jlo = max(b0 - H, 0);
-            int jhi = min(b1 + H, D.ny - 1);
-            tw = jhi - jlo + 1;
-            area = (ihi - ilo + 1) * tw;
-            use_tile = area <= TILE_CAP;
-            if (use_tile) {
-                for (int i = threadIdx.x; i < area; i += WG) tile[i] = 0.0f;
-                __syncthreads();
-            }
-        }
-        // ---- splat
-#pragma unroll
-        for (int r = 0; r < RPT; ++r) {
-            if (W[r] == 0.0f) continue;
-            float Fx[NU], Fy[NU];
-            int i0 = filter_axis<NU, false>(X[r], D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr);
-            int j0 = filter_axis<NU, false>(Y[r], D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr);
-#pragma unroll
-            for (int a = 0; a < NU; ++a) {
-                int i = i0 + a - H;
-                if (i < 0 || i >= D.nx) continue;
-                float wa = W[r] * Fx[a];
-#pragma unroll
-                for (int bb = 0; bb < NU; ++bb) {
-                    int j = j0 + bb - H;
-                    if (j < 0 || j >= D.ny) continue;
-                    float val = wa * Fy[bb];
-                    if (use_tile) atomicAdd(&tile[(i - ilo) * tw + (j - jlo)], val);
-                    else atomicAdd(&img[(int64_t)i * D.ny + j], val);
-                }
-            }
-        }
-        if (use_tile) {
-            __syncthreads();
-            for (int i = threadIdx.x; i < area; i += WG) {
-                float v = tile[i];
-                int ti = i / tw;
-                if (v != 0.0f) atomicAdd(&img[(int64_t)(ilo + ti) * D.ny + jlo + (i - ti * tw)], v);
-            }
-            __syncthreads();
-        }
-    }
-}
-
-// ------------------------------------------------------------------------------------------------
-// Adjoint kernel
-// ------------------------------------------------------------------------------------------------
 // Reduce-scatter of NV per-lane values across the wave.  Each halving step at lane offset OFF keeps one
 // half of the values (the upper half on lanes whose OFF bit is set) and adds the partner's copy of it, so
 // after log2(NV) steps lane l holds a partial sum of value index l >> (6 - log2 NV); the remaining
@@ -854,6 +693,250 @@ __device__ __forceinline__ float wave_reduce_scatter(float* v, int lane) {
     return s;
 }
 
+// ------------------------------------------------------------------------------------------------
+// Forward kernel
+// ------------------------------------------------------------------------------------------------
+// Atomic add into the LDS tile or directly into the image.  The two scopes differ (workgroup vs device),
+// which keeps them separate instructions (ds_add vs global atomic) instead of one generic-address atomic.
+__device__ __forceinline__ void splat_add(bool to_tile, float* tile, int tile_ld, int ilo, int jlo, float* img,
+                                          int ny, int i, int j, float v) {
+    if (to_tile)
+        __hip_atomic_fetch_add(&tile[(i - ilo) * tile_ld + (j - jlo)], v, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+        __hip_atomic_fetch_add(&img[(int64_t)i * ny + j], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int P, int Q, int NU, int SHAPE>
+__global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
+    constexpr int MU = shape_mu(SHAPE), MV = shape_mv(SHAPE), RPT = MU * MV;
+    constexpr int BU = 16 * MU, BV = 16 * MV;
+    constexpr int H = (NU - 1) / 2;
+    // per-thread accumulation window of WN x WN pixels: the filter windows of a thread's neighbouring rays
+    // usually fall inside one such window, so most rays cost no atomic at all
+    constexpr bool ACCUM = NU <= 5;
+    constexpr int WN = NU + 1;
+    extern __shared__ float smem[];
+    float* sP = smem;
+    float* sK = sP + A.lds_cp;
+    float* tile = sK + A.lds_kt;
+    __shared__ int s_box[4][4];
+    __shared__ uint32_t s_cnt[4][9];
+    __shared__ float s_flux[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int cur = -1;
+    for (int64_t pb = blockIdx.x; pb < A.n_blocks; pb += gridDim.x) {
+        const int64_t b = xcd_remap(pb, A.n_blocks);
+        const int d = find_design(A.bmap, A.n_designs, b);
+        const DesignDev D = load_uniform(A.designs, d);
+        const BoundsDev B = load_uniform(A.bounds, d);
+        if (d != cur) {
+            __syncthreads();
+            stage_design(A, D, B.zref, sP, sK, P, Q);
+            __syncthreads();
+            cur = d;
+        }
+        const float* sKu = sK;
+        const float* sKv = sK + D.nsu * kt_stride(P);
+        const BlockMap bm = load_uniform(A.bmap, d);
+        int64_t local = b - bm.first;
+        int e = (int)(local / bm.per_emitter);
+        int rb = (int)(local - (int64_t)e * bm.per_emitter);
+        int bu = rb / bm.nbv, bv = rb - (rb / bm.nbv) * bm.nbv;
+        int64_t ebase = (int64_t)e * D.grid_u * D.grid_v;
+        const int ku0 = bu * BU + (wave >> 1) * 8 * MU + (lane >> 3) * MU;
+        const int kv0 = bv * BV + (wave & 1) * 8 * MV + (lane & 7) * MV;
+
+        float X[RPT], Y[RPT], W[RPT];
+        uint32_t c_hit = 0, c_miss = 0, c_side = 0, c_tir = 0, c_off = 0, c_fail = 0, c_ref = 0, c_nm = 0,
+                 c_tr = 0;
+        float flux = 0.0f;
+        int imin = 1 << 30, imax = -1, jmin = 1 << 30, jmax = -1;
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int ku = ku0 + r / MV, kv = kv0 + r % MV;
+            W[r] = 0.0f;
+            X[r] = 0.0f;
+            Y[r] = 0.0f;
+            if (ku < D.grid_u && kv < D.grid_v) {
+                int64_t id = ebase + (int64_t)ku * D.grid_v + kv;
+                FwdRay o = trace_forward<P, Q>(D, B, sP, sKu, sKv, e, ku, kv, id);
+                c_tr++;
+                c_fail += o.failed;
+                c_ref += o.refined;
+                c_nm += o.nonmono;
+                switch (o.status) {
+                    case ST_HIT: c_hit++; break;
+                    case ST_MISS_ENTRY: c_miss++; break;
+                    case ST_SIDE_WALL: c_side++; break;
+                    case ST_TIR: c_tir++; break;
+                    default: c_off++; break;
+                }
+                if (o.status == ST_HIT) {
+                    X[r] = o.X;
+                    Y[r] = o.Y;
+                    W[r] = o.w;
+                    flux += o.w;
+                    int i0 = min(max((int)floorf((o.X + D.Rx) * D.inv_wx), 0), D.nx - 1);
+                    int j0 = min(max((int)floorf((o.Y + D.Ry) * D.inv_wy), 0), D.ny - 1);
+                    imin = min(imin, i0);
+                    imax = max(imax, i0);
+                    jmin = min(jmin, j0);
+                    jmax = max(jmax, j0);
+                }
+            }
+        }
+        // ---- statistics: reduced over the workgroup, then one atomic per counter into one of NSLOT slots
+        if (A.slots) {
+            uint32_t v[9] = {c_tr, c_hit, c_miss, c_side, c_tir, c_off, c_fail, c_ref, c_nm};
+#pragma unroll
+            for (int k = 0; k < 9; ++k) v[k] = wave_sum(v[k]);
+            float fl = wave_sum(flux);
+            if (lane == 0) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) s_cnt[wave][k] = v[k];
+                s_flux[wave] = fl;
+            }
+            __syncthreads();
+            ffrt_stats* slot = A.slots + (size_t)d * NSLOT + (blockIdx.x % NSLOT);
+            if (threadIdx.x < 9) {
+                uint32_t tot = s_cnt[0][threadIdx.x] + s_cnt[1][threadIdx.x] + s_cnt[2][threadIdx.x] +
+                               s_cnt[3][threadIdx.x];
+                // fields n_traced .. n_nonmonotone follow flux_on_screen in ffrt_stats
+                if (tot) atomicAdd(reinterpret_cast<uint32_t*>(slot) + 1 + threadIdx.x, tot);
+            } else if (threadIdx.x == 9) {
+                float tot = s_flux[0] + s_flux[1] + s_flux[2] + s_flux[3];
+                if (tot != 0.0f) atomicAdd(&slot->flux_on_screen, tot);
+            }
+            __syncthreads();
+        }
+        // ---- footprint of the block (landing pixels widened by the filter half-width)
+        float* img = A.irr + D.img_off;
+        bool use_tile = false;
+        int ilo = 0, jlo = 0, tw = 0, area = 0;
+        if (A.use_tile) {
+            int a0 = wave_min(imin), a1 = wave_max(imax), b0 = wave_min(jmin), b1 = wave_max(jmax);
+            if (lane == 0) {
+                s_box[wave][0] = a0;
+                s_box[wave][1] = a1;
+                s_box[wave][2] = b0;
+                s_box[wave][3] = b1;
+            }
+            __syncthreads();
+            a0 = min(min(s_box[0][0], s_box[1][0]), min(s_box[2][0], s_box[3][0]));
+            a1 = max(max(s_box[0][1], s_box[1][1]), max(s_box[2][1], s_box[3][1]));
+            b0 = min(min(s_box[0][2], s_box[1][2]), min(s_box[2][2], s_box[3][2]));
+            b1 = max(max(s_box[0][3], s_box[1][3]), max(s_box[2][3], s_box[3][3]));
+            __syncthreads();
+            if (a1 < 0) continue;  // no ray of the block reached the screen
+            ilo = max(a0 - H, 0);
+            int ihi = min(a1 + H, D.nx - 1);
+            jlo = max(b0 - H, 0);
+            int jhi = min(b1 + H, D.ny - 1);
+            tw = jhi - jlo + 1;
+            area = (ihi - ilo + 1) * tw;
+            use_tile = area <= TILE_CAP;
+            if (use_tile) {
+                for (int i = threadIdx.x; i < area; i += WG) tile[i] = 0.0f;
+                __syncthreads();
+            }
+        }
+        // ---- splat
+        if constexpr (ACCUM) {
+            float acc[WN * WN];
+#pragma unroll
+            for (int k = 0; k < WN * WN; ++k) acc[k] = 0.0f;
+            int ai = 0, aj = 0;
+            bool anchored = false;
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                if (W[r] == 0.0f) continue;
+                float Fx[NU], Fy[NU];
+                int wi = filter_axis<NU, false>(X[r], D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr) - H;
+                int wj = filter_axis<NU, false>(Y[r], D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr) - H;
+                if (!anchored) {
+                    ai = wi;
+                    aj = wj;
+                    anchored = true;
+                }
+                int di = wi - ai, dj = wj - aj;
+                if (di < 0 || di > WN - NU || dj < 0 || dj > WN - NU) {
+                    // this ray's window leaves the accumulation window: flush and re-anchor
+#pragma unroll
+                    for (int k = 0; k < WN * WN; ++k) {
+                        if (acc[k] != 0.0f)
+                            splat_add(use_tile, tile, tw, ilo, jlo, img, D.ny, ai + k / WN, aj + k % WN, acc[k]);
+                        acc[k] = 0.0f;
+                    }
+                    ai = wi;
+                    aj = wj;
+                    di = dj = 0;
+                }
+                // add the NU x NU window at offset (di, dj) in {0, 1}^2 without indexing registers dynamically
+                float fx[WN], fy[WN];
+#pragma unroll
+                for (int k = 0; k < WN; ++k) {
+                    float a0 = k < NU ? Fx[k] : 0.0f, a1 = k > 0 ? Fx[k - 1] : 0.0f;
+                    float b0 = k < NU ? Fy[k] : 0.0f, b1 = k > 0 ? Fy[k - 1] : 0.0f;
+                    fx[k] = W[r] * (di == 0 ? a0 : a1);
+                    fy[k] = dj == 0 ? b0 : b1;
+                }
+#pragma unroll
+                for (int k = 0; k < WN * WN; ++k) acc[k] += fx[k / WN] * fy[k % WN];
+            }
+            if (anchored) {
+#pragma unroll
+                for (int k = 0; k < WN * WN; ++k)
+                    if (acc[k] != 0.0f)
+                        splat_add(use_tile, tile, tw, ilo, jlo, img, D.ny, ai + k / WN, aj + k % WN, acc[k]);
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                if (W[r] == 0.0f) continue;
+                float Fx[NU], Fy[NU];
+                int i0 = filter_axis<NU, false>(X[r], D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr);
+                int j0 = filter_axis<NU, false>(Y[r], D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr);
+#pragma unroll
+                for (int a = 0; a < NU; ++a) {
+                    int i = i0 + a - H;
+                    if (i < 0 || i >= D.nx) continue;
+#pragma unroll
+                    for (int bb = 0; bb < NU; ++bb) {
+                        int j = j0 + bb - H;
+                        if (j < 0 || j >= D.ny) continue;
+                        splat_add(use_tile, tile, tw, ilo, jlo, img, D.ny, i, j, W[r] * Fx[a] * Fy[bb]);
+                    }
+                }
+            }
+        }
+        if (use_tile) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < area; i += WG) {
+                float v = tile[i];
+                int ti = i / tw;
+                if (v != 0.0f) atomicAdd(&img[(int64_t)(ilo + ti) * D.ny + jlo + (i - ti * tw)], v);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Adjoint kernel
+// ------------------------------------------------------------------------------------------------
+// Add a thread's control-point accumulator (span product (ku, kv)) to the LDS copy of the control net.
+template <int P, int Q, int NV>
+__device__ __forceinline__ void cp_flush_lane(float* sG, int n_v, int ku, int kv, const float* acc) {
+#pragma unroll
+    for (int a = 0; a <= P; ++a)
+#pragma unroll
+        for (int b = 0; b <= Q; ++b) {
+            float v = acc[a * (Q + 1) + b];
+            if (v != 0.0f) atomicAdd(&sG[(ku + a) * n_v + kv + b], v);
+        }
+}
+
 template <int P, int Q, int NU>
 __global__ __launch_bounds__(WG) void k_adjoint(TraceArgs A, int shape) {
     constexpr int NT = (P + 1) * (Q + 1);
@@ -864,85 +947,88 @@ __global__ __launch_bounds__(WG) void k_adjoint(TraceArgs A, int shape) {
     float* sK = sP + A.lds_cp;
     float* sG = sK + A.lds_kt;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int rpt = RPT_OF_SHAPE[shape];
-    const int PU = (shape == 0) ? 2 : (shape <= 2 ? 4 : 8);
-    const int PV = 4 * rpt / PU;
-    const int BU = 8 * PU, BV = 8 * PV;
+    const int MU = shape_mu(shape), MV = shape_mv(shape), RPT = MU * MV;
+    const int BU = 16 * MU, BV = 16 * MV;
+    const int mv_shift = MV == 1 ? 0 : (MV == 2 ? 1 : 2);
     int cur = -1;
     for (int64_t pb = blockIdx.x; pb < A.n_blocks; pb += gridDim.x) {
         const int64_t b = xcd_remap(pb, A.n_blocks);
         const int d = find_design(A.bmap, A.n_designs, b);
-        const DesignDev& D = A.designs[d];
+        const DesignDev D = load_uniform(A.designs, d);
         const int ncp = D.n_u * D.n_v;
         if (d != cur) {
             __syncthreads();
             if (cur >= 0) {  // flush the previous design's accumulator
-                const DesignDev& Dc = A.designs[cur];
+                const DesignDev Dc = load_uniform(A.designs, cur);
                 for (int i = threadIdx.x; i < Dc.n_u * Dc.n_v; i += WG) {
                     float v = sG[i];
                     if (v != 0.0f) atomicAdd(&A.dLdP[Dc.cp_off + i], v);
                 }
                 __syncthreads();
             }
-            stage_design(A, D, A.bounds[d].zref, sP, sK, P, Q);
+            stage_design(A, D, load_uniform(A.bounds, d).zref, sP, sK, P, Q);
             for (int i = threadIdx.x; i < ncp; i += WG) sG[i] = 0.0f;
             __syncthreads();
             cur = d;
         }
-        const BoundsDev B = A.bounds[d];
+        const BoundsDev B = load_uniform(A.bounds, d);
         const float* sKu = sK;
         const float* sKv = sK + D.nsu * kt_stride(P);
         const float* G = A.dLdI + D.img_off;
-        const BlockMap bm = A.bmap[d];
+        const BlockMap bm = load_uniform(A.bmap, d);
         int64_t local = b - bm.first;
         int e = (int)(local / bm.per_emitter);
         int rb = (int)(local - (int64_t)e * bm.per_emitter);
         int bu = rb / bm.nbv, bv = rb - (rb / bm.nbv) * bm.nbv;
         int64_t ebase = (int64_t)e * D.grid_u * D.grid_v;
-        for (int r = 0; r < rpt; ++r) {
-            int patch = r * 4 + wave;
-            int pu = patch / PV, pv = patch - (patch / PV) * PV;
-            int ku = bu * BU + pu * 8 + (lane >> 3);
-            int kv = bv * BV + pv * 8 + (lane & 7);
-            float g[NV];
+        const int ku0 = bu * BU + (wave >> 1) * 8 * MU + (lane >> 3) * MU;
+        const int kv0 = bv * BV + (wave & 1) * 8 * MV + (lane & 7) * MV;
+        // per-thread accumulator of the span product its rays hit; flushed when the span changes
+        float acc[NV];
 #pragma unroll
-            for (int i = 0; i < NV; ++i) g[i] = 0.0f;
+        for (int i = 0; i < NV; ++i) acc[i] = 0.0f;
+        int aku = -1, akv = -1;
+        for (int r = 0; r < RPT; ++r) {
+            const int ku = ku0 + (r >> mv_shift), kv = kv0 + (r & (MV - 1));
+            if (ku >= D.grid_u || kv >= D.grid_v) continue;
+            float g[NT];
             int cku = -1, ckv = -1;
-            bool ok = false;
-            if (ku < D.grid_u && kv < D.grid_v) {
-                int64_t id = ebase + (int64_t)ku * D.grid_v + kv;
-                ok = trace_adjoint<P, Q, NU>(D, B, sP, sKu, sKv, G, e, ku, kv, id, cku, ckv, g);
+            int64_t id = ebase + (int64_t)ku * D.grid_v + kv;
+            if (!trace_adjoint<P, Q, NU>(D, B, sP, sKu, sKv, G, e, ku, kv, id, cku, ckv, g)) continue;
+            if (aku >= 0 && (cku != aku || ckv != akv)) {
+                cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc);
+#pragma unroll
+                for (int i = 0; i < NV; ++i) acc[i] = 0.0f;
             }
-            uint64_t okmask = __ballot(ok);
-            if (okmask == 0) continue;
-            int leader = __ffsll((unsigned long long)okmask) - 1;
-            int key = ok ? (cku << 16) | ckv : -1;
-            int lkey = __shfl(key, leader);
-            bool uniform = A.butterfly && __all(!ok || key == lkey);
-            if (uniform) {
-                if (!ok) {
+            aku = cku;
+            akv = ckv;
 #pragma unroll
-                    for (int i = 0; i < NV; ++i) g[i] = 0.0f;
-                }
-                float s = wave_reduce_scatter<NV>(g, lane);
-                int idx = lane >> (6 - LOG_NV);
-                if ((lane & ((1 << (6 - LOG_NV)) - 1)) == 0 && idx < NT) {
-                    int a = idx / (Q + 1), bb = idx - (idx / (Q + 1)) * (Q + 1);
-                    int lku = lkey >> 16, lkv = lkey & 0xFFFF;
-                    atomicAdd(&sG[(lku + a) * D.n_v + lkv + bb], s);
-                }
-            } else if (ok) {
-#pragma unroll
-                for (int a = 0; a <= P; ++a)
-#pragma unroll
-                    for (int bb = 0; bb <= Q; ++bb) atomicAdd(&sG[(cku + a) * D.n_v + ckv + bb], g[a * (Q + 1) + bb]);
+            for (int i = 0; i < NT; ++i) acc[i] += g[i];
+        }
+        // end of the block: reduce across the wave when every active lane holds the same span product
+        const bool ok = aku >= 0;
+        uint64_t okmask = __ballot(ok);
+        if (okmask == 0) continue;
+        int leader = __ffsll((unsigned long long)okmask) - 1;
+        int key = ok ? (aku << 16) | akv : -1;
+        int lkey = __shfl(key, leader);
+        bool uniform = A.butterfly && __all(!ok || key == lkey);
+        if (uniform) {
+            float s = wave_reduce_scatter<NV>(acc, lane);
+            int idx = lane >> (6 - LOG_NV);
+            if ((lane & ((1 << (6 - LOG_NV)) - 1)) == 0 && idx < NT && s != 0.0f) {
+                int a = idx / (Q + 1), bb = idx - (idx / (Q + 1)) * (Q + 1);
+                int lku = lkey >> 16, lkv = lkey & 0xFFFF;
+                atomicAdd(&sG[(lku + a) * D.n_v + lkv + bb], s);
             }
+        } else if (ok) {
+            cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc);
         }
     }
     // flush the last design's accumulator
     __syncthreads();
     if (cur >= 0) {
-        const DesignDev& Dc = A.designs[cur];
+        const DesignDev Dc = load_uniform(A.designs, cur);
         for (int i = threadIdx.x; i < Dc.n_u * Dc.n_v; i += WG) {
             float v = sG[i];
             if (v != 0.0f) atomicAdd(&A.dLdP[Dc.cp_off + i], v);
@@ -959,8 +1045,8 @@ __global__ __launch_bounds__(WG) void k_trace_rays(TraceArgs A, int design, cons
     extern __shared__ float smem[];
     float* sP = smem;
     float* sK = sP + A.lds_cp;
-    const DesignDev& D = A.designs[design];
-    stage_design(A, D, A.bounds[design].zref, sP, sK, P, Q);
+    const DesignDev D = load_uniform(A.designs, design);
+    stage_design(A, D, load_uniform(A.bounds, design).zref, sP, sK, P, Q);
     __syncthreads();
     int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (i >= n) return;
@@ -969,7 +1055,8 @@ __global__ __launch_bounds__(WG) void k_trace_rays(TraceArgs A, int design, cons
     int e = (int)(id / per);
     int64_t rr = id - (int64_t)e * per;
     int ku = (int)(rr / D.grid_v), kv = (int)(rr - (rr / D.grid_v) * D.grid_v);
-    FwdRay o = trace_forward<P, Q>(D, A.bounds[design], sP, sK, sK + D.nsu * kt_stride(P), e, ku, kv, id);
+    FwdRay o = trace_forward<P, Q>(D, load_uniform(A.bounds, design), sP, sK, sK + D.nsu * kt_stride(P), e, ku, kv,
+                                   id);
     float* dst = out8 + 8 * i;
     dst[0] = (float)o.status;
     dst[1] = o.X;

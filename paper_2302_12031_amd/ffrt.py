@@ -62,8 +62,9 @@ STATS_BYTES = STATS_DTYPE.itemsize
 HEADER_FUNCTIONS = [
     "ffrt_plan_create", "ffrt_plan_destroy", "ffrt_plan_workspace_size", "ffrt_plan_set_workspace",
     "ffrt_plan_layout", "ffrt_plan_num_designs", "ffrt_plan_num_rays", "ffrt_forward", "ffrt_loss",
+    "ffrt_loss_f64",
     "ffrt_adjoint", "ffrt_adam", "ffrt_step", "ffrt_graph_capture", "ffrt_graph_launch",
-    "ffrt_graph_kernel_times", "ffrt_num_configs",
+    "ffrt_plan_time_kernels", "ffrt_num_configs",
     "ffrt_config_name", "ffrt_plan_set_config", "ffrt_plan_get_config", "ffrt_plan_autotune",
     "ffrt_trace_rays", "ffrt_rng", "ffrt_status_string", "ffrt_last_error",
 ]
@@ -90,12 +91,13 @@ def lib():
             "ffrt_plan_num_rays": [vp, P(i64)],
             "ffrt_forward": [vp, vp, vp, vp, vp],
             "ffrt_loss": [vp, vp, vp, vp, vp, vp],
+            "ffrt_loss_f64": [vp, vp, vp, vp, vp],
             "ffrt_adjoint": [vp, vp, vp, vp, vp],
             "ffrt_adam": [vp, vp, vp, vp, vp, vp, P(CAdam), vp],
             "ffrt_step": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(CAdam), vp],
-            "ffrt_graph_capture": [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(CAdam), i32, vp],
+            "ffrt_graph_capture": [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, P(CAdam), vp],
             "ffrt_graph_launch": [vp, vp],
-            "ffrt_graph_kernel_times": [vp, P(ctypes.c_float), P(ctypes.c_float)],
+            "ffrt_plan_time_kernels": [vp, vp, vp, vp, vp, i32, P(ctypes.c_float), P(ctypes.c_float), vp],
             "ffrt_num_configs": [i32, P(i32)],
             "ffrt_config_name": [i32, i32, ctypes.c_char_p, i32],
             "ffrt_plan_set_config": [vp, i32, i32],
@@ -258,6 +260,15 @@ class Plan:
                "ffrt_loss")
         return loss, dLdI
 
+    def loss_f64(self, irr, target, loss=None, stream=None):
+        """Loss values with double-precision reductions (for finite differences)."""
+        self._f32(irr, self.total_img, "irr")
+        self._f32(target, self.total_img, "target")
+        if loss is None:
+            loss = torch.empty(self.n_designs, dtype=torch.float64, device=self.device)
+        _check(lib().ffrt_loss_f64(self.h, _ptr(irr), _ptr(target), _ptr(loss), _stream(stream)), "ffrt_loss_f64")
+        return loss
+
     def adjoint(self, Pz, dLdI, dLdP=None, stream=None):
         self._f32(Pz, self.total_cp, "Pz")
         self._f32(dLdI, self.total_img, "dLdI")
@@ -284,16 +295,17 @@ class Plan:
                                _ptr(st["dLdI"]), _ptr(st["dLdP"]), _ptr(st["m"]), _ptr(st["v"]), _ptr(st["t"]),
                                _ptr(st["stats"]), ctypes.byref(hp.c()), _stream(stream)), "ffrt_step")
 
-    def graph_capture(self, st, target, steps=1, hp=AdamHP(), timed=False, stream=None):
+    def graph_capture(self, st, target, steps=1, hp=AdamHP(), stream=None):
         _check(lib().ffrt_graph_capture(self.h, steps, _ptr(st["Pz"]), _ptr(target), _ptr(st["irr"]),
                                         _ptr(st["loss"]), _ptr(st["dLdI"]), _ptr(st["dLdP"]), _ptr(st["m"]),
                                         _ptr(st["v"]), _ptr(st["t"]), _ptr(st["stats"]), ctypes.byref(hp.c()),
-                                        1 if timed else 0, _stream(stream)), "ffrt_graph_capture")
+                                        _stream(stream)), "ffrt_graph_capture")
 
-    def graph_kernel_times(self):
-        """Mean (forward, adjoint) trace-kernel durations in ms over the steps of the last timed replay."""
+    def time_kernels(self, Pz, irr, dLdI, dLdP, reps=20, stream=None):
+        """Mean (forward, adjoint) trace-kernel durations in ms (HIP events on the stream)."""
         f, a = ctypes.c_float(), ctypes.c_float()
-        _check(lib().ffrt_graph_kernel_times(self.h, ctypes.byref(f), ctypes.byref(a)), "graph_kernel_times")
+        _check(lib().ffrt_plan_time_kernels(self.h, _ptr(Pz), _ptr(irr), _ptr(dLdI), _ptr(dLdP), reps,
+                                            ctypes.byref(f), ctypes.byref(a), _stream(stream)), "time_kernels")
         return f.value, a.value
 
     def graph_launch(self, stream=None):

@@ -5,6 +5,8 @@ import numpy as np
 # marginal ray (a ray whose discrete state sits within rounding distance of flipping).
 IRR_REL = 1e-4
 IRR_FLOOR = 0.01
+# Marginal rays (excluded through the mask) must stay rare: at most MAX_MARGINAL of all rays.
+MAX_MARGINAL = 2e-5
 # Gradient: ||g_gpu - g_64||_inf <= 1e-3 ||g_64||_inf.
 GRAD_REL = 1e-3
 
@@ -22,7 +24,7 @@ def irradiance_errors(I_gpu, I_64, mask=None):
     return ok, float((err / np.maximum(tol, 1e-300)).max()), float(rel_big)
 
 
-def assert_irradiance(I_gpu, I_64, mask=None, max_masked_frac=0.02, what=""):
+def assert_irradiance(I_gpu, I_64, mask=None, max_masked_frac=0.05, what=""):
     ok, worst, rel_big = irradiance_errors(I_gpu, I_64, mask)
     n_mask = int(mask.sum()) if mask is not None else 0
     assert n_mask <= max_masked_frac * I_64.size + 9, f"{what}: {n_mask} masked pixels"

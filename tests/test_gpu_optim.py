@@ -171,6 +171,15 @@ def test_device_error_counters_and_noflux_skip():
     assert s2["n_hit"] == 0 and s2["n_off_screen"] == p.num_rays()
 
 
+def test_kernel_timing_call():
+    wl = W.c2(512)
+    plan, st, T = _setup(wl)
+    irr = plan.forward(st["Pz"])
+    _, dLdI = plan.loss(irr, T)
+    f, a = plan.time_kernels(st["Pz"], torch.empty_like(irr), dLdI, torch.empty_like(st["dLdP"]), reps=5)
+    assert 0 < f < 1e3 and 0 < a < 1e3
+
+
 def test_autotune_picks_a_valid_shape_and_keeps_parity():
     wl = W.c3(1024)
     plan, st, T = _setup(wl)
