@@ -82,6 +82,7 @@ struct TraceArgs {
     float* dLdP;                     // adjoint output
     int32_t use_tile;                // forward: LDS footprint tile
     int32_t butterfly;               // adjoint: wave-level reduce-scatter of control-point gradients
+    int32_t kind_group;              // 0: collimated designs, 1: point-source designs (bmap covers only these)
 };
 
 struct FwdCfg { int shape; int tile; int persistent; const char* name; };

@@ -66,8 +66,9 @@ struct ffrt_plan {
     int64_t total_cp = 0, total_img = 0, total_rays = 0;
     int max_cp = 0, max_kt = 0;
     std::vector<float> knots;
-    std::vector<BlockMap> bmaps[N_SHAPES];
-    int64_t nblocks[N_SHAPES] = {};
+    // block maps per shape and source-kind group (designs of the other group get no blocks)
+    std::vector<BlockMap> bmaps[N_SHAPES][2];
+    int64_t nblocks[N_SHAPES][2] = {};
     // workspace
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -81,8 +82,8 @@ struct ffrt_plan {
     BoundsDev* d_bounds() const { return reinterpret_cast<BoundsDev*>(ws + off_bounds); }
     int32_t* d_valid() const { return reinterpret_cast<int32_t*>(ws + off_valid); }
     float* d_knots() const { return reinterpret_cast<float*>(ws + off_knots); }
-    BlockMap* d_bmap(int shape) const {
-        return reinterpret_cast<BlockMap*>(ws + off_bmap) + (size_t)shape * nd;
+    BlockMap* d_bmap(int shape, int kg) const {
+        return reinterpret_cast<BlockMap*>(ws + off_bmap) + ((size_t)shape * 2 + kg) * nd;
     }
     ffrt_stats* d_slots() const { return reinterpret_cast<ffrt_stats*>(ws + off_slots); }
     int64_t slot_floats() const { return (int64_t)nd * NSLOT * (int64_t)(sizeof(ffrt_stats) / 4); }
@@ -220,22 +221,23 @@ DesignDev make_design(const ffrt_problem& pr, int64_t cp_off, int64_t img_off, i
 
 bool ready(ffrt_plan* p) { return p && p->ws; }
 
-TraceArgs make_args(ffrt_plan* pl, int shape) {
+TraceArgs make_args(ffrt_plan* pl, int shape, int kg) {
     TraceArgs A;
     std::memset(&A, 0, sizeof A);
     A.designs = pl->d_designs();
     A.bounds = pl->d_bounds();
     A.knots = pl->d_knots();
-    A.bmap = pl->d_bmap(shape);
+    A.bmap = pl->d_bmap(shape, kg);
     A.n_designs = pl->nd;
-    A.n_blocks = pl->nblocks[shape];
+    A.n_blocks = pl->nblocks[shape][kg];
+    A.kind_group = kg;
     A.lds_cp = (pl->max_cp + 3) / 4 * 4;
     A.lds_kt = (pl->max_kt + 3) / 4 * 4;
     return A;
 }
 
-int grid_for(ffrt_plan* pl, int shape, int persistent) {
-    int64_t nb = pl->nblocks[shape];
+int grid_for(ffrt_plan* pl, int shape, int kg, int persistent) {
+    int64_t nb = pl->nblocks[shape][kg];
     int64_t g = nb;
     if (persistent) g = std::min<int64_t>(nb, (int64_t)pl->num_cu * 4);
     // launches are limited to 2^31 work items; larger batches loop over blocks inside the kernel
@@ -246,23 +248,29 @@ int grid_for(ffrt_plan* pl, int shape, int persistent) {
 // The forward trace kernel; partial statistics go to the plan's slots when `stats` is set.
 ffrt_status launch_forward(ffrt_plan* pl, const float* Pz, float* irr, bool stats, hipStream_t s) {
     const FwdCfg& c = FWD_CFGS[pl->fwd_cfg];
-    TraceArgs A = make_args(pl, c.shape);
-    A.Pz = Pz;
-    A.irr = irr;
-    A.slots = stats ? pl->d_slots() : nullptr;
-    A.use_tile = c.tile;
-    HIP_TRY(pl->ks->forward(A, c.shape, grid_for(pl, c.shape, c.persistent), s));
+    for (int kg = 0; kg < 2; ++kg) {
+        if (pl->nblocks[c.shape][kg] == 0) continue;
+        TraceArgs A = make_args(pl, c.shape, kg);
+        A.Pz = Pz;
+        A.irr = irr;
+        A.slots = stats ? pl->d_slots() : nullptr;
+        A.use_tile = c.tile;
+        HIP_TRY(pl->ks->forward(A, c.shape, grid_for(pl, c.shape, kg, c.persistent), s));
+    }
     return FFRT_OK;
 }
 
 ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, float* dLdP, hipStream_t s) {
     const AdjCfg& c = ADJ_CFGS[pl->adj_cfg];
-    TraceArgs A = make_args(pl, c.shape);
-    A.Pz = Pz;
-    A.dLdI = dLdI;
-    A.dLdP = dLdP;
-    A.butterfly = c.butterfly;
-    HIP_TRY(pl->ks->adjoint(A, c.shape, grid_for(pl, c.shape, c.persistent), s));
+    for (int kg = 0; kg < 2; ++kg) {
+        if (pl->nblocks[c.shape][kg] == 0) continue;
+        TraceArgs A = make_args(pl, c.shape, kg);
+        A.Pz = Pz;
+        A.dLdI = dLdI;
+        A.dLdP = dLdP;
+        A.butterfly = c.butterfly;
+        HIP_TRY(pl->ks->adjoint(A, c.shape, grid_for(pl, c.shape, kg, c.persistent), s));
+    }
     return FFRT_OK;
 }
 
@@ -368,18 +376,20 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
     pl->total_img = img;
     for (int sh = 0; sh < N_SHAPES; ++sh) {
         ShapeDims sd = shape_dims(sh);
-        int64_t first = 0;
-        for (int i = 0; i < n_designs; ++i) {
-            const DesignDev& d = pl->dd[i];
-            int nbu = (d.grid_u + sd.BU - 1) / sd.BU, nbv = (d.grid_v + sd.BV - 1) / sd.BV;
-            BlockMap bm;
-            bm.first = first;
-            bm.nbv = nbv;
-            bm.per_emitter = nbu * nbv;
-            pl->bmaps[sh].push_back(bm);
-            first += (int64_t)bm.per_emitter * d.emit_nx * d.emit_ny;
+        for (int kg = 0; kg < 2; ++kg) {
+            int64_t first = 0;
+            for (int i = 0; i < n_designs; ++i) {
+                const DesignDev& d = pl->dd[i];
+                int nbu = (d.grid_u + sd.BU - 1) / sd.BU, nbv = (d.grid_v + sd.BV - 1) / sd.BV;
+                BlockMap bm;
+                bm.first = first;
+                bm.nbv = nbv;
+                bm.per_emitter = nbu * nbv;
+                pl->bmaps[sh][kg].push_back(bm);
+                if ((d.kind == 0) == (kg == 0)) first += (int64_t)bm.per_emitter * d.emit_nx * d.emit_ny;
+            }
+            pl->nblocks[sh][kg] = first;
         }
-        pl->nblocks[sh] = first;
     }
     size_t off = 0;
     pl->off_designs = off;
@@ -391,7 +401,7 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
     pl->off_knots = off;
     off = align256(off + sizeof(float) * pl->knots.size());
     pl->off_bmap = off;
-    off = align256(off + sizeof(BlockMap) * N_SHAPES * n_designs);
+    off = align256(off + sizeof(BlockMap) * N_SHAPES * 2 * n_designs);
     pl->off_slots = off;
     off = align256(off + sizeof(ffrt_stats) * NSLOT * n_designs);
     pl->need = off;
@@ -431,8 +441,9 @@ ffrt_status ffrt_plan_set_workspace(ffrt_plan* plan, void* dev_ptr, size_t bytes
         HIP_TRY(hipMemcpy(plan->d_knots(), plan->knots.data(), sizeof(float) * plan->knots.size(),
                           hipMemcpyHostToDevice));
     for (int sh = 0; sh < N_SHAPES; ++sh)
-        HIP_TRY(hipMemcpy(plan->d_bmap(sh), plan->bmaps[sh].data(), sizeof(BlockMap) * plan->nd,
-                          hipMemcpyHostToDevice));
+        for (int kg = 0; kg < 2; ++kg)
+            HIP_TRY(hipMemcpy(plan->d_bmap(sh, kg), plan->bmaps[sh][kg].data(), sizeof(BlockMap) * plan->nd,
+                              hipMemcpyHostToDevice));
     return FFRT_OK;
 }
 
@@ -635,7 +646,7 @@ ffrt_status ffrt_trace_rays(ffrt_plan* plan, int32_t design, const float* Pz, co
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(launch_prepare(plan->d_designs(), plan->nd, Pz, plan->P, plan->Q, plan->d_bounds(), nullptr, 0, nullptr,
                            0, nullptr, 0, s));
-    TraceArgs A = make_args(plan, 0);
+    TraceArgs A = make_args(plan, 0, 0);
     A.Pz = Pz;
     HIP_TRY(plan->ks->trace_rays(A, design, ray_ids, n, out8, s));
     return FFRT_OK;

@@ -84,15 +84,26 @@ __device__ __forceinline__ int wave_max(int v) {
 // Derivatives (d/d ubar): N'_{m,P} = P (rec(P,m) N_{m-1,P-1} - rec(P,m+1) N_{m,P-1}); second derivatives
 // apply the same rule to the degree P-1 derivatives.
 // ------------------------------------------------------------------------------------------------
-template <int P, bool D2, class T>
+// INTERIOR: the span's 2P knots are unclamped, so kap(o) = o and rec(deg, j) = 1/deg are constants and
+// the recursion folds into the uniform (cardinal) B-spline without reading the table.
+template <int P, bool D2, bool INTERIOR, class T>
 __device__ __forceinline__ void span_basis(const float* __restrict__ kt, T t, T* N, T* dN, T* d2N) {
     constexpr int NREC = P * (P + 1) / 2;
     T kap[2 * P];
     T rec[NREC];
+    if constexpr (INTERIOR) {
 #pragma unroll
-    for (int i = 0; i < 2 * P; ++i) kap[i] = (T)kt[i];
+        for (int i = 0; i < 2 * P; ++i) kap[i] = (T)(i + 1 - P);
 #pragma unroll
-    for (int i = 0; i < NREC; ++i) rec[i] = (T)kt[2 * P + i];
+        for (int deg = 1; deg <= P; ++deg)
+#pragma unroll
+            for (int j = 1; j <= deg; ++j) rec[(deg - 1) * deg / 2 + j - 1] = (T)1 / (T)deg;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 2 * P; ++i) kap[i] = (T)kt[i];
+#pragma unroll
+        for (int i = 0; i < NREC; ++i) rec[i] = (T)kt[2 * P + i];
+    }
 #define KAP(o) kap[(o) + P - 1]
 #define REC(deg, j) rec[((deg) - 1) * (deg) / 2 + (j) - 1]
     T tb[P + 1][P + 1];
@@ -160,8 +171,15 @@ __device__ __forceinline__ void eval_surface(const DesignDev& D, const float* __
     kv = min(max(kv, 0), D.nsv - 1);
     S.ku = ku;
     S.kv = kv;
-    span_basis<P, D2, T>(sKu + ku * kt_stride(P), ub - (T)ku, S.Nu, S.dNu, S.d2Nu);
-    span_basis<Q, D2, T>(sKv + kv * kt_stride(Q), vb - (T)kv, S.Nv, S.dNv, S.d2Nv);
+    // spans k with P-1 <= k <= nspan-P see only unclamped knots
+    if (ku >= P - 1 && ku <= D.nsu - P)
+        span_basis<P, D2, true, T>(nullptr, ub - (T)ku, S.Nu, S.dNu, S.d2Nu);
+    else
+        span_basis<P, D2, false, T>(sKu + ku * kt_stride(P), ub - (T)ku, S.Nu, S.dNu, S.d2Nu);
+    if (kv >= Q - 1 && kv <= D.nsv - Q)
+        span_basis<Q, D2, true, T>(nullptr, vb - (T)kv, S.Nv, S.dNv, S.d2Nv);
+    else
+        span_basis<Q, D2, false, T>(sKv + kv * kt_stride(Q), vb - (T)kv, S.Nv, S.dNv, S.d2Nv);
     const float* row = sP + ku * D.n_v + kv;  // control point (ku + a, kv + b) of span product (ku, kv)
     T h = 0, hu = 0, hv = 0, huu = 0, huv = 0, hvv = 0;
 #pragma unroll
@@ -204,12 +222,14 @@ struct RayIn {
     float w;            // weight after the entry face
 };
 
+// KIND 0: collimated source; KIND 1: point source or grid of point sources (D.kind 1 or 2).
+template <int KIND>
 __device__ __forceinline__ RayIn ray_entry(const DesignDev& D, int e, int ku, int kv, int64_t id) {
     RayIn r;
     r.status = ST_HIT;
     float x1 = 0.5f, x2 = 0.5f;
     if (D.jitter) two_uniforms(splitmix_at(D.rng_state0, (uint64_t)id), x1, x2);
-    if (D.kind == 0) {
+    if constexpr (KIND == 0) {
         // Collimated bundle: samples on the grid of [0,1]^2, mapped linearly to the aperture; the ray meets
         // the flat face at normal incidence (Schlick weight 1 - R0) and travels along +z.
         float u = ((float)ku + x1) * D.inv_gu;
@@ -222,7 +242,7 @@ __device__ __forceinline__ RayIn ray_entry(const DesignDev& D, int e, int ku, in
         r.dz = 1.0f;
         r.w = D.fresnel ? D.w0 * (1.0f - D.R0) : D.w0;
         return r;
-    }
+    } else {
     // Point source: theta = 2 pi (k + xi) / S_theta, cos(phi) = 1 - (1 - cos phi_max) a (uniform in solid
     // angle), a = (k_a + xi) / S_a.  sin(phi) = sqrt(a' (2 - a')) with a' = (1 - cos phi_max) a avoids the
     // cancellation of 1 - cos^2.
@@ -260,6 +280,7 @@ __device__ __forceinline__ RayIn ray_entry(const DesignDev& D, int e, int ku, in
     }
     r.w = w;
     return r;
+    }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -470,18 +491,18 @@ struct FwdRay {
     int iters, failed, nonmono, refined;
 };
 
-template <int P, int Q>
+template <int P, int Q, int KIND>
 __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const BoundsDev& B, const float* sP,
                                                 const float* sKu, const float* sKv, int e, int ku, int kv,
                                                 int64_t id) {
     FwdRay o;
     o.iters = o.failed = o.nonmono = o.refined = 0;
     o.X = o.Y = o.w = o.t = o.u = o.v = 0.0f;
-    RayIn r = ray_entry(D, e, ku, kv, id);
+    RayIn r = ray_entry<KIND>(D, e, ku, kv, id);
     o.status = r.status;
     if (r.status != ST_HIT) return o;
     float t;
-    if (D.kind != 0) {
+    if constexpr (KIND != 0) {
         RootOut R = intersect<P, Q>(D, B, sP, sKu, sKv, r);
         o.iters = R.iters;
         o.failed = R.failed;
@@ -498,8 +519,8 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
     float qx = r.ox + t * r.dx, qy = r.oy + t * r.dy;
     SurfEval<P, Q, float> S;
     eval_surface<P, Q, false, float>(D, sP, sKu, sKv, qx, qy, S);
-    float qz = (D.kind == 0) ? S.h + B.zref : r.oz + t * r.dz;
-    if (D.kind == 0) t = qz - r.oz;
+    float qz = (KIND == 0) ? S.h + B.zref : r.oz + t * r.dz;
+    if constexpr (KIND == 0) t = qz - r.oz;
     o.t = t;
     o.u = qx * (0.5f / D.r_x) + 0.5f;
     o.v = qy * (0.5f / D.r_y) + 0.5f;
@@ -516,15 +537,15 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
 // One ray, adjoint: re-trace, gather dL/dI over the filter window, reverse sweep.  Returns false when the
 // ray does not reach the screen.  g[] receives dL/dP for control point (ku + a, kv + b) at a * (Q+1) + b.
 // ------------------------------------------------------------------------------------------------
-template <int P, int Q, int NU>
+template <int P, int Q, int NU, int KIND>
 __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDev& B, const float* sP,
                                               const float* sKu, const float* sKv, const float* __restrict__ G,
                                               int e, int ku, int kv, int64_t id, int& cku, int& ckv,
                                               float* g) {
-    RayIn r = ray_entry(D, e, ku, kv, id);
+    RayIn r = ray_entry<KIND>(D, e, ku, kv, id);
     if (r.status != ST_HIT) return false;
     float t = 0.0f;
-    const bool point = D.kind != 0;
+    constexpr bool point = KIND != 0;
     if (point) {
         RootOut R = intersect<P, Q>(D, B, sP, sKu, sKv, r);
         if (R.status != ST_HIT) return false;
@@ -707,7 +728,7 @@ __device__ __forceinline__ void splat_add(bool to_tile, float* tile, int tile_ld
         __hip_atomic_fetch_add(&img[(int64_t)i * ny + j], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int P, int Q, int NU, int SHAPE>
+template <int P, int Q, int NU, int SHAPE, int KIND>
 __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
     constexpr int MU = shape_mu(SHAPE), MV = shape_mv(SHAPE), RPT = MU * MV;
     constexpr int BU = 16 * MU, BV = 16 * MV;
@@ -760,7 +781,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
             Y[r] = 0.0f;
             if (ku < D.grid_u && kv < D.grid_v) {
                 int64_t id = ebase + (int64_t)ku * D.grid_v + kv;
-                FwdRay o = trace_forward<P, Q>(D, B, sP, sKu, sKv, e, ku, kv, id);
+                FwdRay o = trace_forward<P, Q, KIND>(D, B, sP, sKu, sKv, e, ku, kv, id);
                 c_tr++;
                 c_fail += o.failed;
                 c_ref += o.refined;
@@ -937,7 +958,7 @@ __device__ __forceinline__ void cp_flush_lane(float* sG, int n_v, int ku, int kv
         }
 }
 
-template <int P, int Q, int NU>
+template <int P, int Q, int NU, int KIND>
 __global__ __launch_bounds__(WG) void k_adjoint(TraceArgs A, int shape) {
     constexpr int NT = (P + 1) * (Q + 1);
     constexpr int NV = NT <= 16 ? 16 : (NT <= 32 ? 32 : 64);
@@ -994,7 +1015,7 @@ __global__ __launch_bounds__(WG) void k_adjoint(TraceArgs A, int shape) {
             float g[NT];
             int cku = -1, ckv = -1;
             int64_t id = ebase + (int64_t)ku * D.grid_v + kv;
-            if (!trace_adjoint<P, Q, NU>(D, B, sP, sKu, sKv, G, e, ku, kv, id, cku, ckv, g)) continue;
+            if (!trace_adjoint<P, Q, NU, KIND>(D, B, sP, sKu, sKv, G, e, ku, kv, id, cku, ckv, g)) continue;
             if (aku >= 0 && (cku != aku || ckv != akv)) {
                 cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc);
 #pragma unroll
@@ -1055,8 +1076,10 @@ __global__ __launch_bounds__(WG) void k_trace_rays(TraceArgs A, int design, cons
     int e = (int)(id / per);
     int64_t rr = id - (int64_t)e * per;
     int ku = (int)(rr / D.grid_v), kv = (int)(rr - (rr / D.grid_v) * D.grid_v);
-    FwdRay o = trace_forward<P, Q>(D, load_uniform(A.bounds, design), sP, sK, sK + D.nsu * kt_stride(P), e, ku, kv,
-                                   id);
+    const BoundsDev B = load_uniform(A.bounds, design);
+    const float* sKv = sK + D.nsu * kt_stride(P);
+    FwdRay o = D.kind == 0 ? trace_forward<P, Q, 0>(D, B, sP, sK, sKv, e, ku, kv, id)
+                           : trace_forward<P, Q, 1>(D, B, sP, sK, sKv, e, ku, kv, id);
     float* dst = out8 + 8 * i;
     dst[0] = (float)o.status;
     dst[1] = o.X;
@@ -1080,7 +1103,8 @@ struct KernelsFor {
     template <int SHAPE>
     static hipError_t fwd_shape(const TraceArgs& A, int grid, hipStream_t s) {
         size_t lds = trace_lds_bytes(A, A.use_tile ? TILE_CAP : 0);
-        hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE>), dim3(grid), dim3(WG), lds, s, A);
+        if (A.kind_group == 0) hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 0>), dim3(grid), dim3(WG), lds, s, A);
+        else hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 1>), dim3(grid), dim3(WG), lds, s, A);
         return hipGetLastError();
     }
     static hipError_t forward(const TraceArgs& A, int shape, int grid, hipStream_t s) {
@@ -1094,7 +1118,8 @@ struct KernelsFor {
     }
     static hipError_t adjoint(const TraceArgs& A, int shape, int grid, hipStream_t s) {
         size_t lds = trace_lds_bytes(A, A.lds_cp);
-        hipLaunchKernelGGL((k_adjoint<P, Q, NU>), dim3(grid), dim3(WG), lds, s, A, shape);
+        if (A.kind_group == 0) hipLaunchKernelGGL((k_adjoint<P, Q, NU, 0>), dim3(grid), dim3(WG), lds, s, A, shape);
+        else hipLaunchKernelGGL((k_adjoint<P, Q, NU, 1>), dim3(grid), dim3(WG), lds, s, A, shape);
         return hipGetLastError();
     }
     static hipError_t trace_rays(const TraceArgs& A, int design, const int64_t* ids, int64_t n, float* out8,
