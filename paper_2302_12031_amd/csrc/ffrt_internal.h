@@ -8,7 +8,7 @@
 namespace ffrt {
 
 constexpr int WG = 256;               // threads per workgroup: 4 wave64s
-constexpr int TILE_CAP = 6144;        // floats in the LDS irradiance tile of the forward kernel
+constexpr int TILE_CAP = 3072;        // int64 fixed-point pixels in the LDS irradiance tile of the forward kernel
 constexpr int MAX_DEG = 5;
 constexpr int N_SHAPES = 5;           // block shapes: rays per thread 1, 2, 4, 8, 16
 constexpr int RPT_OF_SHAPE[N_SHAPES] = {1, 2, 4, 8, 16};
@@ -49,7 +49,10 @@ struct DesignDev {
     // layout
     int64_t cp_off, img_off, n_rays;
     int32_t kt_u, kt_v;              // float offsets of the knot tables (workspace)
-    int32_t per_emitter_u, pad_;     // unused padding
+    // Fixed-point scale of the forward's LDS tile: a pixel contribution v (at most RPT w0) is added as the
+    // integer rint(v fx_scale), fx_scale = 2^26 / w0, so that one addend stays below 2^31 and a workgroup's
+    // sum for one pixel (at most 2^11 rays) below 2^37.
+    float fx_scale, fx_unscale;
 };
 
 // Per-design bounds computed on the device each call (sec. 2.2.2: global convex-hull box).

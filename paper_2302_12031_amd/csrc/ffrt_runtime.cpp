@@ -212,6 +212,8 @@ DesignDev make_design(const ffrt_problem& pr, int64_t cp_off, int64_t img_off, i
     int64_t n = (int64_t)S.grid_u * S.grid_v * d.emit_nx * d.emit_ny;
     d.n_rays = n;
     d.w0 = (float)(1.0 / (double)n);
+    d.fx_scale = (float)(std::ldexp(1.0, 26) / (double)d.w0);
+    d.fx_unscale = (float)((double)d.w0 * std::ldexp(1.0, -26));
     d.cp_off = cp_off;
     d.img_off = img_off;
     d.kt_u = kt_u;

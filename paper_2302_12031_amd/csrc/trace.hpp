@@ -56,21 +56,65 @@ __device__ __forceinline__ T load_uniform(const T* p, int i) {
 #endif
 }
 
+// ------------------------------------------------------------------------------------------------
+// Cross-lane exchanges that stay in the VALU (no LDS crossbar traffic): v_permlane32_swap and
+// v_permlane16_swap exchange the two 32-lane halves / neighbouring 16-lane rows of two registers, and DPP
+// reads the partner lane L ^ 15 (row_mirror), L ^ 7 (row_half_mirror), L ^ 2 and L ^ 1 (quad_perm).  The
+// six masks 32, 16, 15, 7, 2, 1 span all six lane bits, so reducing over them covers the whole wave.
+// ------------------------------------------------------------------------------------------------
+template <int M>
+__device__ __forceinline__ uint32_t dpp_xor(uint32_t v) {
+    static_assert(M == 15 || M == 7 || M == 2 || M == 1, "DPP partner mask");
+    constexpr int ctrl = M == 15 ? 0x140 : (M == 7 ? 0x141 : (M == 2 ? 0x4E : 0xB1));
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, 0xF, 0xF, false);
+}
+template <int M>
+__device__ __forceinline__ float dpp_xor(float v) {
+    return __builtin_bit_cast(float, dpp_xor<M>(__builtin_bit_cast(uint32_t, v)));
+}
+template <int M>
+__device__ __forceinline__ int dpp_xor(int v) {
+    return (int)dpp_xor<M>((uint32_t)v);
+}
+// (a, b) -> halves / rows swapped: for lanes whose bit log2(OFF) is clear, first = a[L], second =
+// a[L + OFF]; for the others, first = b[L - OFF], second = b[L].
+template <int OFF, class T>
+__device__ __forceinline__ void lane_swap(T a, T b, T& first, T& second) {
+    static_assert(OFF == 32 || OFF == 16, "permlane swap distance");
+    const uint32_t ua = __builtin_bit_cast(uint32_t, a), ub = __builtin_bit_cast(uint32_t, b);
+    if constexpr (OFF == 32) {
+        auto r = __builtin_amdgcn_permlane32_swap(ua, ub, false, false);
+        first = __builtin_bit_cast(T, (uint32_t)r[0]);
+        second = __builtin_bit_cast(T, (uint32_t)r[1]);
+    } else {
+        auto r = __builtin_amdgcn_permlane16_swap(ua, ub, false, false);
+        first = __builtin_bit_cast(T, (uint32_t)r[0]);
+        second = __builtin_bit_cast(T, (uint32_t)r[1]);
+    }
+}
+// Whole-wave reduction; every lane receives the result.
+template <class T, class Op>
+__device__ __forceinline__ T wave_reduce(T v, Op op) {
+    T x, y;
+    lane_swap<32>(v, v, x, y);
+    v = op(x, y);
+    lane_swap<16>(v, v, x, y);
+    v = op(x, y);
+    v = op(v, dpp_xor<15>(v));
+    v = op(v, dpp_xor<7>(v));
+    v = op(v, dpp_xor<2>(v));
+    v = op(v, dpp_xor<1>(v));
+    return v;
+}
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    return wave_reduce(v, [](T a, T b) { return a + b; });
 }
 __device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o));
-    return v;
+    return wave_reduce(v, [](int a, int b) { return min(a, b); });
 }
 __device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    return v;
+    return wave_reduce(v, [](int a, int b) { return max(a, b); });
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -680,18 +724,33 @@ __device__ __forceinline__ void stage_design(const TraceArgs& A, const DesignDev
 // half of the values (the upper half on lanes whose OFF bit is set) and adds the partner's copy of it, so
 // after log2(NV) steps lane l holds a partial sum of value index l >> (6 - log2 NV); the remaining
 // xor-steps complete it.  Lanes whose low 6 - log2(NV) bits are zero hold the wave totals.
+// One butterfly step of a wave reduce-scatter: lanes with bit OFF clear keep entries [0, HALF) and add the
+// partner's copy of them, the others keep [HALF, 2 HALF).  The partner differs in bit OFF (and, for the
+// DPP steps, in lower bits too, which the later steps pair up in turn).
 template <int HALF, int OFF>
 __device__ __forceinline__ void halve(float* v, int lane) {
-    const bool upper = (lane & OFF) != 0;
+    if constexpr (OFF == 32 || OFF == 16) {
 #pragma unroll
-    for (int j = 0; j < HALF; ++j) {
-        float lo = v[j], hi = v[j + HALF];
-        float send = upper ? lo : hi;
-        float keep = upper ? hi : lo;
-        v[j] = keep + __shfl_xor(send, OFF);
+        for (int j = 0; j < HALF; ++j) {
+            float x, y;
+            lane_swap<OFF>(v[j], v[j + HALF], x, y);
+            v[j] = x + y;
+        }
+    } else {
+        constexpr int M = OFF == 8 ? 15 : (OFF == 4 ? 7 : OFF);
+        const bool upper = (lane & OFF) != 0;
+#pragma unroll
+        for (int j = 0; j < HALF; ++j) {
+            float lo = v[j], hi = v[j + HALF];
+            float send = upper ? lo : hi;
+            float keep = upper ? hi : lo;
+            v[j] = keep + dpp_xor<M>(send);
+        }
     }
 }
 
+// Sum NV per-lane values over the wave; entry k of the total ends in the lanes with lane >> (6 - log2 NV)
+// == k (for NV < 64 every such lane holds it; the lane with the low bits clear is used).
 template <int NV>
 __device__ __forceinline__ float wave_reduce_scatter(float* v, int lane) {
     static_assert(NV == 16 || NV == 32 || NV == 64, "NV");
@@ -699,13 +758,13 @@ __device__ __forceinline__ float wave_reduce_scatter(float* v, int lane) {
     if constexpr (NV == 16) {
         halve<8, 32>(v, lane); halve<4, 16>(v, lane); halve<2, 8>(v, lane); halve<1, 4>(v, lane);
         s = v[0];
-        s += __shfl_xor(s, 2);
-        s += __shfl_xor(s, 1);
+        s += dpp_xor<2>(s);
+        s += dpp_xor<1>(s);
     } else if constexpr (NV == 32) {
         halve<16, 32>(v, lane); halve<8, 16>(v, lane); halve<4, 8>(v, lane); halve<2, 4>(v, lane);
         halve<1, 2>(v, lane);
         s = v[0];
-        s += __shfl_xor(s, 1);
+        s += dpp_xor<1>(s);
     } else {
         halve<32, 32>(v, lane); halve<16, 16>(v, lane); halve<8, 8>(v, lane); halve<4, 4>(v, lane);
         halve<2, 2>(v, lane); halve<1, 1>(v, lane);
@@ -717,15 +776,19 @@ __device__ __forceinline__ float wave_reduce_scatter(float* v, int lane) {
 // ------------------------------------------------------------------------------------------------
 // Forward kernel
 // ------------------------------------------------------------------------------------------------
-// Atomic add into the LDS tile or directly into the image.  The two scopes differ (workgroup vs device),
-// which keeps them separate instructions (ds_add vs global atomic) instead of one generic-address atomic.
-__device__ __forceinline__ void splat_add(bool to_tile, float* tile, int tile_ld, int ilo, int jlo, float* img,
-                                          int ny, int i, int j, float v) {
-    if (to_tile)
-        __hip_atomic_fetch_add(&tile[(i - ilo) * tile_ld + (j - jlo)], v, __ATOMIC_RELAXED,
+// Add a pixel contribution v >= 0 either to the workgroup's LDS tile, as the 64-bit fixed-point integer
+// rint(v scale) (integer LDS atomics are far cheaper than float ones on gfx950, and integer sums do not
+// depend on the order of the additions), or, when the block's footprint does not fit the tile, directly to
+// the float image with a device-scope atomic.
+__device__ __forceinline__ void splat_add(bool to_tile, unsigned long long* tile, int tile_ld, int ilo, int jlo,
+                                          float scale, float* img, int ny, int i, int j, float v) {
+    if (to_tile) {
+        const long long q = (long long)__float2int_rn(v * scale);
+        __hip_atomic_fetch_add(&tile[(i - ilo) * tile_ld + (j - jlo)], (unsigned long long)q, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
-    else
+    } else {
         __hip_atomic_fetch_add(&img[(int64_t)i * ny + j], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 template <int P, int Q, int NU, int SHAPE, int KIND>
@@ -740,10 +803,9 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
     extern __shared__ float smem[];
     float* sP = smem;
     float* sK = sP + A.lds_cp;
-    float* tile = sK + A.lds_kt;
+    unsigned long long* tile = reinterpret_cast<unsigned long long*>(sK + A.lds_kt);  // 16-byte aligned
     __shared__ int s_box[4][4];
-    __shared__ uint32_t s_cnt[4][9];
-    __shared__ float s_flux[4];
+    __shared__ float s_red[4][10];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int cur = -1;
     for (int64_t pb = blockIdx.x; pb < A.n_blocks; pb += gridDim.x) {
@@ -809,24 +871,21 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
         }
         // ---- statistics: reduced over the workgroup, then one atomic per counter into one of NSLOT slots
         if (A.slots) {
-            uint32_t v[9] = {c_tr, c_hit, c_miss, c_side, c_tir, c_off, c_fail, c_ref, c_nm};
-#pragma unroll
-            for (int k = 0; k < 9; ++k) v[k] = wave_sum(v[k]);
-            float fl = wave_sum(flux);
-            if (lane == 0) {
-#pragma unroll
-                for (int k = 0; k < 9; ++k) s_cnt[wave][k] = v[k];
-                s_flux[wave] = fl;
-            }
+            // the nine counters (exact in float: a wave traces at most 1024 rays) and the flux, summed over
+            // the wave by one reduce-scatter
+            float v[16] = {(float)c_tr, (float)c_hit, (float)c_miss, (float)c_side, (float)c_tir, (float)c_off,
+                           (float)c_fail, (float)c_ref, (float)c_nm, flux, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+            const float sum = wave_reduce_scatter<16>(v, lane);
+            if ((lane & 3) == 0 && (lane >> 2) < 10) s_red[wave][lane >> 2] = sum;
             __syncthreads();
             ffrt_stats* slot = A.slots + (size_t)d * NSLOT + (blockIdx.x % NSLOT);
             if (threadIdx.x < 9) {
-                uint32_t tot = s_cnt[0][threadIdx.x] + s_cnt[1][threadIdx.x] + s_cnt[2][threadIdx.x] +
-                               s_cnt[3][threadIdx.x];
+                uint32_t tot = (uint32_t)s_red[0][threadIdx.x] + (uint32_t)s_red[1][threadIdx.x] +
+                               (uint32_t)s_red[2][threadIdx.x] + (uint32_t)s_red[3][threadIdx.x];
                 // fields n_traced .. n_nonmonotone follow flux_on_screen in ffrt_stats
                 if (tot) atomicAdd(reinterpret_cast<uint32_t*>(slot) + 1 + threadIdx.x, tot);
             } else if (threadIdx.x == 9) {
-                float tot = s_flux[0] + s_flux[1] + s_flux[2] + s_flux[3];
+                float tot = s_red[0][9] + s_red[1][9] + s_red[2][9] + s_red[3][9];
                 if (tot != 0.0f) atomicAdd(&slot->flux_on_screen, tot);
             }
             __syncthreads();
@@ -858,40 +917,37 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
             area = (ihi - ilo + 1) * tw;
             use_tile = area <= TILE_CAP;
             if (use_tile) {
-                for (int i = threadIdx.x; i < area; i += WG) tile[i] = 0.0f;
+                for (int i = threadIdx.x; i < area; i += WG) tile[i] = 0ull;
                 __syncthreads();
             }
         }
         // ---- splat
         if constexpr (ACCUM) {
+            // The window is anchored at the thread's lowest landing pixel (imin, jmin); rays whose filter
+            // window starts at most one pixel further along each axis are summed in registers, the others
+            // are added directly.
+            const int ai = imin - H, aj = jmin - H;
             float acc[WN * WN];
 #pragma unroll
             for (int k = 0; k < WN * WN; ++k) acc[k] = 0.0f;
-            int ai = 0, aj = 0;
-            bool anchored = false;
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
                 if (W[r] == 0.0f) continue;
                 float Fx[NU], Fy[NU];
-                int wi = filter_axis<NU, false>(X[r], D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr) - H;
-                int wj = filter_axis<NU, false>(Y[r], D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr) - H;
-                if (!anchored) {
-                    ai = wi;
-                    aj = wj;
-                    anchored = true;
-                }
-                int di = wi - ai, dj = wj - aj;
-                if (di < 0 || di > WN - NU || dj < 0 || dj > WN - NU) {
-                    // this ray's window leaves the accumulation window: flush and re-anchor
+                const int di = filter_axis<NU, false>(X[r], D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr) - H - ai;
+                const int dj = filter_axis<NU, false>(Y[r], D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr) - H - aj;
+                if (di > WN - NU || dj > WN - NU) {
 #pragma unroll
-                    for (int k = 0; k < WN * WN; ++k) {
-                        if (acc[k] != 0.0f)
-                            splat_add(use_tile, tile, tw, ilo, jlo, img, D.ny, ai + k / WN, aj + k % WN, acc[k]);
-                        acc[k] = 0.0f;
+                    for (int a = 0; a < NU; ++a) {
+#pragma unroll
+                        for (int bb = 0; bb < NU; ++bb) {
+                            const float v = W[r] * Fx[a] * Fy[bb];
+                            if (v != 0.0f)
+                                splat_add(use_tile, tile, tw, ilo, jlo, D.fx_scale, img, D.ny, ai + di + a,
+                                          aj + dj + bb, v);
+                        }
                     }
-                    ai = wi;
-                    aj = wj;
-                    di = dj = 0;
+                    continue;
                 }
                 // add the NU x NU window at offset (di, dj) in {0, 1}^2 without indexing registers dynamically
                 float fx[WN], fy[WN];
@@ -905,12 +961,10 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
 #pragma unroll
                 for (int k = 0; k < WN * WN; ++k) acc[k] += fx[k / WN] * fy[k % WN];
             }
-            if (anchored) {
 #pragma unroll
-                for (int k = 0; k < WN * WN; ++k)
-                    if (acc[k] != 0.0f)
-                        splat_add(use_tile, tile, tw, ilo, jlo, img, D.ny, ai + k / WN, aj + k % WN, acc[k]);
-            }
+            for (int k = 0; k < WN * WN; ++k)
+                if (acc[k] != 0.0f)
+                    splat_add(use_tile, tile, tw, ilo, jlo, D.fx_scale, img, D.ny, ai + k / WN, aj + k % WN, acc[k]);
         } else {
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
@@ -926,7 +980,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
                     for (int bb = 0; bb < NU; ++bb) {
                         int j = j0 + bb - H;
                         if (j < 0 || j >= D.ny) continue;
-                        splat_add(use_tile, tile, tw, ilo, jlo, img, D.ny, i, j, W[r] * Fx[a] * Fy[bb]);
+                        splat_add(use_tile, tile, tw, ilo, jlo, D.fx_scale, img, D.ny, i, j, W[r] * Fx[a] * Fy[bb]);
                     }
                 }
             }
@@ -934,9 +988,10 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
         if (use_tile) {
             __syncthreads();
             for (int i = threadIdx.x; i < area; i += WG) {
-                float v = tile[i];
-                int ti = i / tw;
-                if (v != 0.0f) atomicAdd(&img[(int64_t)(ilo + ti) * D.ny + jlo + (i - ti * tw)], v);
+                const long long q = (long long)tile[i];
+                const int ti = i / tw;
+                if (q != 0)
+                    atomicAdd(&img[(int64_t)(ilo + ti) * D.ny + jlo + (i - ti * tw)], (float)q * D.fx_unscale);
             }
             __syncthreads();
         }
@@ -1026,23 +1081,26 @@ __global__ __launch_bounds__(WG) void k_adjoint(TraceArgs A, int shape) {
 #pragma unroll
             for (int i = 0; i < NT; ++i) acc[i] += g[i];
         }
-        // end of the block: reduce across the wave when every active lane holds the same span product
-        const bool ok = aku >= 0;
-        uint64_t okmask = __ballot(ok);
-        if (okmask == 0) continue;
-        int leader = __ffsll((unsigned long long)okmask) - 1;
-        int key = ok ? (aku << 16) | akv : -1;
-        int lkey = __shfl(key, leader);
-        bool uniform = A.butterfly && __all(!ok || key == lkey);
-        if (uniform) {
-            float s = wave_reduce_scatter<NV>(acc, lane);
-            int idx = lane >> (6 - LOG_NV);
-            if ((lane & ((1 << (6 - LOG_NV)) - 1)) == 0 && idx < NT && s != 0.0f) {
-                int a = idx / (Q + 1), bb = idx - (idx / (Q + 1)) * (Q + 1);
-                int lku = lkey >> 16, lkv = lkey & 0xFFFF;
-                atomicAdd(&sG[(lku + a) * D.n_v + lkv + bb], s);
+        // end of the block: one round per distinct span product held in the wave, in which the lanes of the
+        // leader's span product sum their accumulators with a butterfly (one LDS atomic per control point)
+        bool pend = aku >= 0;
+        if (A.butterfly) {
+            const int key = (aku << 16) | (akv & 0xFFFF);
+            for (uint64_t m = __ballot(pend); m != 0; m = __ballot(pend)) {
+                const int lkey = __builtin_amdgcn_readlane(key, __ffsll((unsigned long long)m) - 1);
+                const bool take = pend && key == lkey;
+                float v[NV];
+#pragma unroll
+                for (int i = 0; i < NV; ++i) v[i] = take ? acc[i] : 0.0f;
+                const float sum = wave_reduce_scatter<NV>(v, lane);
+                const int idx = lane >> (6 - LOG_NV);
+                if ((lane & ((1 << (6 - LOG_NV)) - 1)) == 0 && idx < NT && sum != 0.0f) {
+                    const int a = idx / (Q + 1), bb = idx - (idx / (Q + 1)) * (Q + 1);
+                    atomicAdd(&sG[((lkey >> 16) + a) * D.n_v + (lkey & 0xFFFF) + bb], sum);
+                }
+                pend = pend && !take;
             }
-        } else if (ok) {
+        } else if (pend) {
             cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc);
         }
     }
@@ -1102,7 +1160,7 @@ template <int P, int Q, int NU>
 struct KernelsFor {
     template <int SHAPE>
     static hipError_t fwd_shape(const TraceArgs& A, int grid, hipStream_t s) {
-        size_t lds = trace_lds_bytes(A, A.use_tile ? TILE_CAP : 0);
+        size_t lds = trace_lds_bytes(A, A.use_tile ? 2 * TILE_CAP : 0);
         if (A.kind_group == 0) hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 0>), dim3(grid), dim3(WG), lds, s, A);
         else hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 1>), dim3(grid), dim3(WG), lds, s, A);
         return hipGetLastError();
