@@ -18,7 +18,8 @@
  *  - Lengths in mm, angles in radians.  Device arrays are float32 unless stated.
  *  - The caller owns every buffer.  A plan holds host metadata only; its device workspace is caller
  *    allocated (ffrt_plan_workspace_size) and handed over once (ffrt_plan_set_workspace).  The compute
- *    calls never allocate.
+ *    calls never allocate.  Calls on one plan share that workspace (bounds, loss partial sums and their
+ *    arrival counters), so they must not overlap in time: issue them on one stream, or order the streams.
  *  - A plan holds one or more designs.  Their buffers are packed back to back at the offsets given by
  *    ffrt_plan_layout: control points P^z[i][j] row-major with i along u / x (sec. 2.1); images I[i][j]
  *    row-major with i along x (sec. 2.3).  Ghost pixels, when enabled, enlarge the stored image.
@@ -122,7 +123,9 @@ typedef struct {
 ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_plan** out);
 ffrt_status ffrt_plan_destroy(ffrt_plan* plan);
 
-/* Device workspace bytes the plan needs (design descriptors, knot tables, bounds, loss flags). */
+/* Device workspace bytes the plan needs: design descriptors, knot tables, bounds, loss flags and partial
+ * sums, and the accumulators of the trace kernels (a 64-bit fixed-point irradiance image and a gradient
+ * buffer, each kept at zero between calls). */
 ffrt_status ffrt_plan_workspace_size(const ffrt_plan* plan, size_t* bytes);
 
 /* Hand over caller-allocated device workspace (>= the size above, 256-byte aligned) on the current
@@ -137,8 +140,10 @@ ffrt_status ffrt_plan_num_rays(const ffrt_plan* plan, int64_t* n);
 
 /* ---- the hot path ---------------------------------------------------------------------------------- */
 
-/* Irradiance of every design (sec. 2.3): zeroes irr and stats, traces all rays and splats them.
- * Pz: packed control heights; irr: packed images (output); stats: n_designs ffrt_stats or NULL. */
+/* Irradiance of every design (sec. 2.3): traces all rays and splats them; irr and stats are overwritten.
+ * Pz: packed control heights; irr: packed images (output); stats: n_designs ffrt_stats or NULL.  Pixel
+ * sums are accumulated in 64-bit fixed point (unit 2^-26 w0, w0 = 1 / rays of the design), so the result
+ * does not depend on the order in which rays are added. */
 ffrt_status ffrt_forward(ffrt_plan* plan, const float* Pz, float* irr, ffrt_stats* stats, void* stream);
 
 /* Loss of sec. 2.5 per design and dL/dI.  loss: n_designs floats (NaN for a design without flux, whose
@@ -153,7 +158,7 @@ ffrt_status ffrt_loss_f64(ffrt_plan* plan, const float* irr, const float* target
 
 /* Pathwise gradient dL/dP^z (packed like Pz) of sum_ij dL_dI_ij I_ij: re-traces every ray (nothing per ray
  * is stored) and back-propagates through splat, screen, refraction and the root (implicit function
- * theorem).  Zeroes dL_dP first. */
+ * theorem).  dL_dP is overwritten. */
 ffrt_status ffrt_adjoint(ffrt_plan* plan, const float* Pz, const float* dL_dI, float* dL_dP, void* stream);
 
 /* Adam on P^z in place (Kingma & Ba; bias-corrected).  m, v: packed like Pz; t: n_designs step counters
@@ -161,13 +166,17 @@ ffrt_status ffrt_adjoint(ffrt_plan* plan, const float* Pz, const float* dL_dI, f
 ffrt_status ffrt_adam(ffrt_plan* plan, float* Pz, const float* dL_dP, float* m, float* v, int32_t* t,
                       const ffrt_adam_hparams* hp, void* stream);
 
-/* One optimisation step: forward, loss, adjoint, Adam (all device-side, no host synchronisation). */
+/* One optimisation step: forward, loss, adjoint, Adam (all device-side, no host synchronisation; three
+ * kernels).  irr, loss, dL_dP, stats (if not NULL) receive the step's values before the update; Pz, m, v,
+ * t are updated.  dL_dI may be NULL: the adjoint then forms dL/dI from irr, target and the loss on the fly
+ * instead of writing and reading it back (one kernel fewer). */
 ffrt_status ffrt_step(ffrt_plan* plan, float* Pz, const float* target, float* irr, float* loss,
                       float* dL_dI, float* dL_dP, float* m, float* v, int32_t* t, ffrt_stats* stats,
                       const ffrt_adam_hparams* hp, void* stream);
 
 /* Capture `steps` consecutive ffrt_step calls into a HIP graph owned by the plan (stream must not be the
- * NULL stream).  The arguments are bound at capture.  ffrt_graph_launch replays it on `stream`. */
+ * NULL stream; dL_dI may be NULL as for ffrt_step).  The arguments are bound at capture.
+ * ffrt_graph_launch replays it on `stream`. */
 ffrt_status ffrt_graph_capture(ffrt_plan* plan, int32_t steps, float* Pz, const float* target, float* irr,
                                float* loss, float* dL_dI, float* dL_dP, float* m, float* v, int32_t* t,
                                ffrt_stats* stats, const ffrt_adam_hparams* hp, void* stream);

@@ -1,11 +1,14 @@
-// Kernels of libffrt that do not depend on the B-spline degrees: clearing, convex-hull bounds and lens
-// checks, the loss of sec. 2.5 with dL/dI, Adam, and the ray-sampling generator.
+// Kernels of libffrt that do not depend on the B-spline degrees: resolving the fixed-point irradiance and
+// the ray statistics, the loss of sec. 2.5 with dL/dI, Adam, and the ray-sampling generator.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
 #include <algorithm>
 
 #include "ffrt_internal.h"
+#include "loss.hpp"
+#include "optim.hpp"
+#include "wave.hpp"
 
 namespace ffrt {
 
@@ -19,176 +22,44 @@ __host__ __device__ inline uint64_t mix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-// Compensated (Neumaier) running sum: s + c carries the rounding error of the additions.
-struct CSum {
-    float s = 0.0f, c = 0.0f;
-    __device__ void add(float x) {
-        float t = s + x;
-        c += (fabsf(s) >= fabsf(x)) ? (s - t) + x : (x - t) + s;
-        s = t;
-    }
-    __device__ float value() const { return s + c; }
-};
-
-// Block-wide sum over blockDim.x threads (a multiple of 64, at most 1024).
-__device__ inline float block_sum(float v, float* sh) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    __syncthreads();
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    float s = 0.0f;
-    for (int w = 0; w < nw; ++w) s += sh[w];
-    return s;
-}
-
-__device__ inline float block_max(float v, float* sh) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    __syncthreads();
-    if (lane == 0) sh[wave] = v;
-    __syncthreads();
-    float s = -INFINITY;
-    for (int w = 0; w < nw; ++w) s = fmaxf(s, sh[w]);
-    return s;
-}
-
-// Per design (blocks 0 .. n_designs-1): global bounds of P^z (sec. 2.2.2), slope bounds from the derivative
-// control points p (P_{i+1,j} - P_{i,j}) / (u_{i+p+1} - u_{i+1}) (textbook derivative of a B-spline), and the
-// lens checks of sec. 2.1.2 (P^z >= z_in + delta) and finiteness.  Every block also clears its share of the
-// arrays z0, z1, z2.
-__global__ __launch_bounds__(256) void k_prepare(const DesignDev* designs, int n_designs, const float* __restrict__ Pz,
-                                                 int p, int q, BoundsDev* bounds, float* z0, int64_t n0, float* z1,
-                                                 int64_t n1, float* z2, int64_t n2) {
-    {
-        const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-        const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-        if (z0) for (int64_t k = i0; k < n0; k += stride) z0[k] = 0.0f;
-        if (z1) for (int64_t k = i0; k < n1; k += stride) z1[k] = 0.0f;
-        if (z2) for (int64_t k = i0; k < n2; k += stride) z2[k] = 0.0f;
-    }
-    if (!Pz || (int)blockIdx.x >= n_designs) return;
-    __shared__ float sh[16];
-    const DesignDev& D = designs[blockIdx.x];
-    const float* P = Pz + D.cp_off;
-    const int n = D.n_u * D.n_v;
-    float lo = INFINITY, hi = -INFINITY, gu = 0.0f, gv = 0.0f;
-    float nbad = 0.0f, nnan = 0.0f;
-    for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
-        int i = idx / D.n_v, j = idx - (idx / D.n_v) * D.n_v;
-        float z = P[idx];
-        if (!isfinite(z)) nnan += 1.0f;
-        if (!(z >= D.zmin_allowed)) nbad += 1.0f;
-        lo = fminf(lo, z);
-        hi = fmaxf(hi, z);
-        if (i + 1 < D.n_u) {
-            int dk = min(i + 1, D.nsu) - max(i + 1 - p, 0);
-            gu = fmaxf(gu, fabsf((float)p * (P[idx + D.n_v] - z) / (float)dk));
-        }
-        if (j + 1 < D.n_v) {
-            int dk = min(j + 1, D.nsv) - max(j + 1 - q, 0);
-            gv = fmaxf(gv, fabsf((float)q * (P[idx + 1] - z) / (float)dk));
-        }
-    }
-    lo = -block_max(-lo, sh);
-    hi = block_max(hi, sh);
-    gu = block_max(gu, sh);
-    gv = block_max(gv, sh);
-    nbad = block_sum(nbad, sh);
-    nnan = block_sum(nnan, sh);
-    if (threadIdx.x == 0) {
-        BoundsDev B;
-        B.zmin = lo;
-        B.zmax = hi;
-        B.zref = 0.5f * (lo + hi);
-        // d(ubar)/dx = sxu; a small relative margin keeps the bound conservative under rounding
-        B.gx = gu * D.sxu * 1.0001f;
-        B.gy = gv * D.syv * 1.0001f;
-        B.n_bad = (uint32_t)nbad;
-        B.n_nan = (uint32_t)nnan;
-        B.pad_ = 0.0f;
-        bounds[blockIdx.x] = B;
-    }
-}
-
-// Sum the NSLOT partial slots of design d into stats[d] (threads of one block).
-__device__ void reduce_slots(int d, const BoundsDev* bounds, const ffrt_stats* slots, ffrt_stats* stats) {
+// Sum the NSLOT partial-statistics slots of design d into stats[d] and clear them (a 256-thread workgroup:
+// wave w sums fields w, w + 4, w + 8 across the 64 slots, one slot per lane), and count the lens checks of
+// sec. 2.1.2 (P^z >= z_in + delta_min, finite) over the design's control points.
+__device__ void reduce_slots(int d, const DesignDev& D, const float* Pz, ffrt_stats* slots, ffrt_stats* stats) {
     constexpr int NF = sizeof(ffrt_stats) / 4;
-    const ffrt_stats* sl = slots + (size_t)d * NSLOT;
-    for (int f = threadIdx.x; f < NF; f += blockDim.x) {
-        if (f == 0) {
-            float acc = 0.0f;
-            for (int k = 0; k < NSLOT; ++k) acc += sl[k].flux_on_screen;
-            stats[d].flux_on_screen = acc;
+    static_assert(NSLOT == 64 && NF == 12, "one slot per lane, three fields per wave");
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t* slot = reinterpret_cast<uint32_t*>(slots + (size_t)d * NSLOT + lane);
+    uint32_t* out = reinterpret_cast<uint32_t*>(stats + d);
+    for (int f = wave; f < NF - 2; f += 4) {  // the last two fields are the lens checks
+        const uint32_t x = slot[f];
+        slot[f] = 0u;
+        if (f == 0) {  // flux_on_screen (float)
+            const float sum = wave_sum(__builtin_bit_cast(float, x));
+            if (lane == 0) out[f] = __builtin_bit_cast(uint32_t, sum);
         } else {
-            uint32_t acc = 0;
-            for (int k = 0; k < NSLOT; ++k) acc += reinterpret_cast<const uint32_t*>(sl + k)[f];
-            reinterpret_cast<uint32_t*>(stats + d)[f] = acc;
+            const uint32_t sum = wave_sum(x);
+            if (lane == 0) out[f] = sum;
         }
+    }
+    __shared__ uint32_t s_chk[4][2];
+    uint32_t nbad = 0, nnan = 0;
+    const float* P = Pz + D.cp_off;
+    for (int i = threadIdx.x; i < D.n_u * D.n_v; i += blockDim.x) {
+        const float z = P[i];
+        nnan += isfinite(z) ? 0u : 1u;
+        nbad += (z >= D.zmin_allowed) ? 0u : 1u;
+    }
+    nbad = wave_sum(nbad);
+    nnan = wave_sum(nnan);
+    if (lane == 0) {
+        s_chk[wave][0] = nbad;
+        s_chk[wave][1] = nnan;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        stats[d].n_constraint_viol = bounds[d].n_bad;
-        stats[d].n_nan = bounds[d].n_nan;
-    }
-}
-
-__global__ void k_stats(const BoundsDev* bounds, const ffrt_stats* slots, ffrt_stats* stats) {
-    reduce_slots(blockIdx.x, bounds, slots, stats);
-}
-
-// Loss of sec. 2.5 per design: I_hat = I / sum I, I_ref_hat = T / sum T, D = I_hat - I_ref_hat,
-// L = ||D||_F / sqrt(n_x n_y), dL/dI = (D - sum(D I_hat)) / (sum(I) sqrt(n_x n_y) ||D||) (0 where ||D|| = 0).
-// A design without flux gets L = NaN, dL/dI = 0 and valid = 0 (its Adam update is skipped).
-__global__ __launch_bounds__(1024) void k_loss(const DesignDev* designs, const float* __restrict__ irr,
-                                               const float* __restrict__ target, float* loss, float* dLdI,
-                                               int32_t* valid, const BoundsDev* bounds, const ffrt_stats* slots,
-                                               ffrt_stats* stats) {
-    __shared__ float sh[16];
-    if (stats) reduce_slots(blockIdx.x, bounds, slots, stats);
-    const DesignDev& D = designs[blockIdx.x];
-    const int64_t n = (int64_t)D.nx * D.ny;
-    const float* I = irr + D.img_off;
-    const float* T = target + D.img_off;
-    float* G = dLdI + D.img_off;
-    // compensated per-thread sums: the loss is differenced by finite-difference checks, so its rounding
-    // has to stay near one ulp
-    CSum a, b;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        a.add(I[i]);
-        b.add(T[i]);
-    }
-    float s = block_sum(a.value(), sh);
-    float sT = block_sum(b.value(), sh);
-    if (!(s > 0.0f) || !(sT > 0.0f)) {
-        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) G[i] = 0.0f;
-        if (threadIdx.x == 0) {
-            loss[blockIdx.x] = NAN;
-            valid[blockIdx.x] = 0;
-        }
-        return;
-    }
-    const float is = 1.0f / s, isT = 1.0f / sT;
-    CSum cd2, cdot;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        float ih = I[i] * is;
-        float Dv = ih - T[i] * isT;
-        cd2.add(Dv * Dv);
-        cdot.add(Dv * ih);
-    }
-    float d2 = block_sum(cd2.value(), sh);
-    float dot = block_sum(cdot.value(), sh);
-    const float nrm = sqrtf(d2), rn = sqrtf((float)n);
-    const float coef = nrm > 0.0f ? 1.0f / (s * rn * nrm) : 0.0f;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        float Dv = I[i] * is - T[i] * isT;
-        G[i] = (Dv - dot) * coef;
-    }
-    if (threadIdx.x == 0) {
-        loss[blockIdx.x] = nrm / rn;
-        valid[blockIdx.x] = 1;
+        stats[d].n_constraint_viol = s_chk[0][0] + s_chk[1][0] + s_chk[2][0] + s_chk[3][0];
+        stats[d].n_nan = s_chk[0][1] + s_chk[1][1] + s_chk[2][1] + s_chk[3][1];
     }
 }
 
@@ -202,6 +73,176 @@ __device__ inline double block_sum_f64(double v, double* sh) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += sh[w];
     return s;
+}
+
+// Bounds of sec. 2.2.2 for design blockIdx.x: the global convex-hull box [min P^z, max P^z], zref at its
+// middle, and slope bounds from the derivative control points p (P_{i+1,j} - P_{i,j}) / (u_{i+p+1} - u_{i+1})
+// (the textbook derivative of a B-spline; knot units, so d(ubar)/dx = sxu converts them to mm).
+__global__ __launch_bounds__(256) void k_bounds(const DesignDev* designs, const float* __restrict__ Pz, int p, int q,
+                                                BoundsDev* bounds) {
+    __shared__ float s_b[4][4];
+    const int d = blockIdx.x;
+    const DesignDev& D = designs[d];
+    const float* P = Pz + D.cp_off;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float lo = INFINITY, hi = -INFINITY, gu = 0.0f, gv = 0.0f;
+    for (int i = wave; i < D.n_u; i += 4) {  // row i by wave, columns by lane
+        const float fu = (float)p / (float)(min(i + 1, D.nsu) - max(i + 1 - p, 0));
+        for (int j = lane; j < D.n_v; j += 64) {
+            const int idx = i * D.n_v + j;
+            const float z = P[idx];
+            lo = fminf(lo, z);
+            hi = fmaxf(hi, z);
+            if (i + 1 < D.n_u) gu = fmaxf(gu, fabsf(fu * (P[idx + D.n_v] - z)));
+            if (j + 1 < D.n_v) {
+                const float fv = (float)q / (float)(min(j + 1, D.nsv) - max(j + 1 - q, 0));
+                gv = fmaxf(gv, fabsf(fv * (P[idx + 1] - z)));
+            }
+        }
+    }
+    auto fmin_ = [](float a, float b) { return fminf(a, b); };
+    auto fmax_ = [](float a, float b) { return fmaxf(a, b); };
+    lo = wave_reduce(lo, fmin_);
+    hi = wave_reduce(hi, fmax_);
+    gu = wave_reduce(gu, fmax_);
+    gv = wave_reduce(gv, fmax_);
+    if (lane == 0) {
+        s_b[wave][0] = lo;
+        s_b[wave][1] = hi;
+        s_b[wave][2] = gu;
+        s_b[wave][3] = gv;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        BoundsDev B;
+        B.zmin = fminf(fminf(s_b[0][0], s_b[1][0]), fminf(s_b[2][0], s_b[3][0]));
+        B.zmax = fmaxf(fmaxf(s_b[0][1], s_b[1][1]), fmaxf(s_b[2][1], s_b[3][1]));
+        B.zref = 0.5f * (B.zmin + B.zmax);
+        // a small relative margin keeps the slope bounds conservative under rounding
+        B.gx = fmaxf(fmaxf(s_b[0][2], s_b[1][2]), fmaxf(s_b[2][2], s_b[3][2])) * D.sxu * 1.0001f;
+        B.gy = fmaxf(fmaxf(s_b[0][3], s_b[1][3]), fmaxf(s_b[2][3], s_b[3][3])) * D.syv * 1.0001f;
+        bounds[d] = B;
+    }
+}
+
+// Slice [lo, hi) of the image of design D handled by workgroup b of LB.
+__device__ inline void image_slice(const DesignDev& D, int LB, int b, int64_t& lo, int64_t& hi) {
+    const int64_t n = (int64_t)D.nx * D.ny;
+    const int64_t chunk = (n + LB - 1) / LB;
+    lo = min<int64_t>(n, (int64_t)b * chunk);
+    hi = min<int64_t>(n, lo + chunk);
+}
+
+// Fixed-point irradiance -> float (the forward accumulates rint(v fx_scale) per pixel), clearing img64 for
+// the next forward.  Workgroup 0 of each design also reduces the statistics.
+__global__ __launch_bounds__(256) void k_resolve(const DesignDev* designs, int LB, unsigned long long* img64,
+                                                 float* irr, const float* Pz, ffrt_stats* slots, ffrt_stats* stats) {
+    const int d = blockIdx.x / LB, b = blockIdx.x - d * LB;
+    const DesignDev& D = designs[d];
+    int64_t lo, hi;
+    image_slice(D, LB, b, lo, hi);
+    for (int64_t i = D.img_off + lo + threadIdx.x; i < D.img_off + hi; i += blockDim.x) {
+        irr[i] = (float)(long long)img64[i] * D.fx_unscale;
+        img64[i] = 0ull;
+    }
+    if (stats && b == 0) reduce_slots(d, D, Pz, slots, stats);
+}
+
+// Slice sums of the loss of sec. 2.5 (sum I, sum T, sum I^2, sum I T, sum T^2 in double precision) of
+// slice b of design d, resolving the fixed-point irradiance first when img64 is given.  No workgroup waits
+// for another: the consumers (k_loss_grad, the adjoint) each add up the LB slices themselves.
+__global__ __launch_bounds__(256) void k_loss_sums(const DesignDev* designs, int LB, unsigned long long* img64,
+                                                   float* irr, const float* __restrict__ target, const float* Pz,
+                                                   ffrt_stats* slots, ffrt_stats* stats, double* partial) {
+    __shared__ double sh[4][LOSS_Q];
+    const int d = blockIdx.x / LB, b = blockIdx.x - d * LB;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const DesignDev& D = designs[d];
+    int64_t lo, hi;
+    image_slice(D, LB, b, lo, hi);
+    double q[LOSS_Q] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = D.img_off + lo + threadIdx.x; i < D.img_off + hi; i += blockDim.x) {
+        float xf;
+        if (img64) {
+            xf = (float)(long long)img64[i] * D.fx_unscale;
+            irr[i] = xf;
+            img64[i] = 0ull;
+        } else {
+            xf = irr[i];
+        }
+        const double x = (double)xf, y = (double)target[i];
+        q[0] += x;
+        q[1] += y;
+        q[2] += x * x;
+        q[3] += x * y;
+        q[4] += y * y;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < LOSS_Q; ++k) q[k] += __shfl_xor(q[k], o);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < LOSS_Q; ++k) sh[wave][k] = q[k];
+    __syncthreads();
+    if (threadIdx.x < LOSS_Q) {
+        const int k = threadIdx.x;
+        partial[((size_t)d * LB + b) * LOSS_Q + k] = ((sh[0][k] + sh[1][k]) + sh[2][k]) + sh[3][k];
+    }
+    if (stats && b == 0) reduce_slots(d, D, Pz, slots, stats);
+}
+
+// dL/dI of slice b of design d; workgroup 0 also stores the loss value and the validity flag.
+__global__ __launch_bounds__(256) void k_loss_grad(const DesignDev* designs, int LB, const float* __restrict__ irr,
+                                                   const float* __restrict__ target, const double* partial,
+                                                   float* loss, int32_t* valid, float* dLdI) {
+    const int d = blockIdx.x / LB, b = blockIdx.x - d * LB;
+    const DesignDev& D = designs[d];
+    const LossOut R = loss_from_partials(partial, d, LB, D);
+    if (b == 0 && threadIdx.x == 0) {
+        loss[d] = R.loss;
+        valid[d] = R.valid;
+    }
+    int64_t lo, hi;
+    image_slice(D, LB, b, lo, hi);
+    for (int64_t i = D.img_off + lo + threadIdx.x; i < D.img_off + hi; i += blockDim.x) {
+        const float Dv = irr[i] * R.L.is - target[i] * R.L.isT;
+        dLdI[i] = (Dv - R.L.dot) * R.L.coef;
+    }
+}
+
+// One workgroup per design after the adjoint: dL/dP from the accumulator (which is cleared for the next
+// adjoint), the loss value and validity flag (from the slice sums, when lpart is given) and Adam.
+__global__ __launch_bounds__(256) void k_finish(const DesignDev* designs, float* gacc, float* dLdP,
+                                                const double* lpart, int LB, float* loss, int32_t* valid,
+                                                AdamArgs adam) {
+    const int d = blockIdx.x;
+    const DesignDev& D = designs[d];
+    int ok = 1;
+    if (lpart) {
+        const LossOut R = loss_from_partials(lpart, d, LB, D);
+        ok = R.valid;
+        if (threadIdx.x == 0) {
+            loss[d] = R.loss;
+            valid[d] = R.valid;
+        }
+    } else if (valid) {
+        ok = valid[d];
+    }
+    float* acc = gacc + D.cp_off;
+    float* out = dLdP + D.cp_off;
+    auto take = [acc, out](int i) {
+        const float g = acc[i];
+        acc[i] = 0.0f;
+        out[i] = g;
+        return g;
+    };
+    const int ncp = D.n_u * D.n_v;
+    if (adam.Pz && ok) {
+        adam_update(adam.Pz, adam.m, adam.v, adam.t + d, D.cp_off, ncp, adam.hp, take);
+    } else {
+        for (int i = threadIdx.x; i < ncp; i += blockDim.x) take(i);
+    }
 }
 
 // The loss value of sec. 2.5 with double-precision reductions (finite-difference checks only).
@@ -231,30 +272,15 @@ __global__ __launch_bounds__(1024) void k_loss_f64(const DesignDev* designs, con
     if (threadIdx.x == 0) loss[blockIdx.x] = sqrt(d2 / (double)n);
 }
 
-// Adam (Kingma & Ba) per design; the step counter lives on the device so the update can be replayed from
-// a graph.  P -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+// Adam per design; the step counter lives on the device so the update can be replayed from a graph.
 __global__ __launch_bounds__(256) void k_adam(const DesignDev* designs, float* Pz, const float* __restrict__ g,
                                               float* m, float* v, int32_t* t, const int32_t* valid,
                                               ffrt_adam_hparams hp) {
     const int d = blockIdx.x;
     if (valid && !valid[d]) return;
     const DesignDev& D = designs[d];
-    const int n = D.n_u * D.n_v;
-    const int tn = t[d] + 1;
-    const float bc1 = 1.0f - powf(hp.beta1, (float)tn);
-    const float bc2 = 1.0f - powf(hp.beta2, (float)tn);
-    const float step = hp.lr / bc1, rb2 = 1.0f / sqrtf(bc2);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        int64_t k = D.cp_off + i;
-        float gi = g[k];
-        float mi = hp.beta1 * m[k] + (1.0f - hp.beta1) * gi;
-        float vi = hp.beta2 * v[k] + (1.0f - hp.beta2) * gi * gi;
-        m[k] = mi;
-        v[k] = vi;
-        Pz[k] -= step * mi / (sqrtf(vi) * rb2 + hp.eps);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) t[d] = tn;
+    const float* gd = g + D.cp_off;
+    adam_update(Pz, m, v, t + d, D.cp_off, D.n_u * D.n_v, hp, [gd](int i) { return gd[i]; });
 }
 
 __global__ void k_rng(uint64_t state0, uint64_t first, int64_t n, uint64_t* out) {
@@ -266,30 +292,36 @@ __global__ void k_rng(uint64_t state0, uint64_t first, int64_t n, uint64_t* out)
 
 uint64_t splitmix_state0(uint64_t seed, uint64_t stream_id) { return mix64(seed + stream_id * GAMMA); }
 
-hipError_t launch_prepare(const DesignDev* designs, int n_designs, const float* Pz, int p, int q,
-                          BoundsDev* bounds, float* z0, int64_t n0, float* z1, int64_t n1, float* z2, int64_t n2,
-                          hipStream_t s) {
-    int64_t work = std::max<int64_t>(std::max<int64_t>(z0 ? n0 : 0, z1 ? n1 : 0), z2 ? n2 : 0);
-    int64_t extra = (work + 255) / 256;
-    if (extra > 2048) extra = 2048;
-    int grid = (int)std::max<int64_t>(Pz ? n_designs : 0, extra);
-    if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_prepare, dim3(grid), dim3(256), 0, s, designs, n_designs, Pz, p, q, bounds, z0, n0, z1, n1,
-                       z2, n2);
+hipError_t launch_bounds(const DesignDev* designs, int n_designs, const float* Pz, int p, int q, BoundsDev* bounds,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_bounds, dim3(n_designs), dim3(256), 0, s, designs, Pz, p, q, bounds);
     return hipGetLastError();
 }
 
-hipError_t launch_stats(int n_designs, const BoundsDev* bounds, const ffrt_stats* slots, ffrt_stats* stats,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(k_stats, dim3(n_designs), dim3(64), 0, s, bounds, slots, stats);
+int loss_blocks_per_design(int64_t max_pixels) {
+    return (int)std::min<int64_t>(64, std::max<int64_t>(1, (max_pixels + 1023) / 1024));
+}
+
+hipError_t launch_resolve(const DesignDev* designs, int n_designs, int LB, unsigned long long* img64, float* irr,
+                          const float* Pz, ffrt_stats* slots, ffrt_stats* stats, hipStream_t s) {
+    hipLaunchKernelGGL(k_resolve, dim3(n_designs * LB), dim3(256), 0, s, designs, LB, img64, irr, Pz, slots, stats);
     return hipGetLastError();
 }
 
-hipError_t launch_loss(const DesignDev* designs, int n_designs, const float* irr, const float* target,
-                       float* loss, float* dLdI, int32_t* valid, const BoundsDev* bounds, const ffrt_stats* slots,
-                       ffrt_stats* stats, hipStream_t s) {
-    hipLaunchKernelGGL(k_loss, dim3(n_designs), dim3(1024), 0, s, designs, irr, target, loss, dLdI, valid, bounds,
-                       slots, stats);
+hipError_t launch_loss(const DesignDev* designs, int n_designs, int LB, unsigned long long* img64, float* irr,
+                       const float* target, const float* Pz, ffrt_stats* slots, ffrt_stats* stats, double* partial,
+                       float* loss, float* dLdI, int32_t* valid, hipStream_t s) {
+    hipLaunchKernelGGL(k_loss_sums, dim3(n_designs * LB), dim3(256), 0, s, designs, LB, img64, irr, target, Pz, slots,
+                       stats, partial);
+    if (dLdI)
+        hipLaunchKernelGGL(k_loss_grad, dim3(n_designs * LB), dim3(256), 0, s, designs, LB, irr, target, partial, loss,
+                           valid, dLdI);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const DesignDev* designs, int n_designs, float* gacc, float* dLdP, const double* lpart,
+                         int LB, float* loss, int32_t* valid, const AdamArgs& adam, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(n_designs), dim3(256), 0, s, designs, gacc, dLdP, lpart, LB, loss, valid, adam);
     return hipGetLastError();
 }
 

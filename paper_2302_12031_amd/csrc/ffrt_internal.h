@@ -55,12 +55,11 @@ struct DesignDev {
     float fx_scale, fx_unscale;
 };
 
-// Per-design bounds computed on the device each call (sec. 2.2.2: global convex-hull box).
+// Per-design bounds of sec. 2.2.2 (global convex-hull box and slope bounds), formed by launch_bounds before
+// the trace kernels of designs whose rays need the root search (point and grid sources).
 struct BoundsDev {
     float zmin, zmax, gx, gy;        // gx, gy: bounds of |dh/dx|, |dh/dy| from derivative control points
-    float zref;                      // reference height subtracted from P^z in LDS: (zmin + zmax) / 2
-    uint32_t n_bad, n_nan;           // control points below z_in + delta_min, non-finite control points
-    float pad_;
+    float zref;                      // reference height subtracted from P^z in LDS
 };
 
 // Block map of one design for one block shape.
@@ -69,9 +68,23 @@ struct BlockMap {
     int32_t nbv, per_emitter;        // blocks along v; blocks per emitter
 };
 
+// Scalars of dL/dI for one design: dL/dI = ((I is - T isT) - dot) coef.
+struct LossScalars {
+    float is, isT, dot, coef;
+};
+
+// Adam applied by the finishing kernel after the adjoint (null Pz: plain gradient output).
+struct AdamArgs {
+    float* Pz;
+    float* m;
+    float* v;
+    int32_t* t;
+    ffrt_adam_hparams hp;
+};
+
 struct TraceArgs {
     const DesignDev* designs;
-    const BoundsDev* bounds;
+    const BoundsDev* bounds;         // of the current Pz, for point and grid sources
     const float* knots;
     const BlockMap* bmap;            // n_designs entries for the launch's block shape
     int32_t n_designs;
@@ -79,10 +92,15 @@ struct TraceArgs {
     int32_t lds_cp;                  // floats of the LDS control-point array (max over designs)
     int32_t lds_kt;                  // floats of the LDS knot tables
     const float* Pz;
-    float* irr;                      // forward output
+    unsigned long long* img64;       // forward: fixed-point irradiance accumulator (zero on entry)
     ffrt_stats* slots;               // forward: NSLOT partial-statistics slots per design (may be null)
-    const float* dLdI;               // adjoint input
-    float* dLdP;                     // adjoint output
+    // adjoint: dL/dI from the array dLdI, or (dLdI null) from irr, target and the loss's slice sums
+    const float* dLdI;
+    const float* irr;
+    const float* target;
+    const double* lpart;
+    int32_t loss_lb;
+    float* gacc;                     // adjoint: gradient accumulator (zero on entry; launch_finish clears it)
     int32_t use_tile;                // forward: LDS footprint tile
     int32_t butterfly;               // adjoint: wave-level reduce-scatter of control-point gradients
     int32_t kind_group;              // 0: collimated designs, 1: point-source designs (bmap covers only these)
@@ -122,18 +140,26 @@ struct KernelSet {
 const KernelSet* kernel_set(int P, int Q, int NU);
 
 // Kernels that do not depend on the degrees (ffrt_common.hip).
-// One launch per call: convex-hull bounds and lens checks per design (Pz may be null to skip them), and
-// zeroing of up to three float arrays (null arrays are skipped).
-hipError_t launch_prepare(const DesignDev* designs, int n_designs, const float* Pz, int p, int q,
-                          BoundsDev* bounds, float* z0, int64_t n0, float* z1, int64_t n1, float* z2, int64_t n2,
-                          hipStream_t s);
-// Sums the NSLOT partial-statistics slots of every design into stats (and the lens checks of bounds).
-hipError_t launch_stats(int n_designs, const BoundsDev* bounds, const ffrt_stats* slots, ffrt_stats* stats,
-                        hipStream_t s);
-// Loss and dL/dI; when stats is not null it also performs launch_stats' reduction.
-hipError_t launch_loss(const DesignDev* designs, int n_designs, const float* irr, const float* target,
-                       float* loss, float* dLdI, int32_t* valid, const BoundsDev* bounds,
-                       const ffrt_stats* slots, ffrt_stats* stats, hipStream_t s);
+// Bounds of sec. 2.2.2 of every design from Pz (one workgroup per design).
+hipError_t launch_bounds(const DesignDev* designs, int n_designs, const float* Pz, int p, int q, BoundsDev* bounds,
+                         hipStream_t s);
+// Image slices: LB = loss_blocks_per_design(largest image) workgroups per design, LB <= 64.
+int loss_blocks_per_design(int64_t max_pixels);
+// img64 -> irr (float), img64 cleared.  With stats, the partial-statistics slots are summed into stats and
+// cleared, and the lens checks of sec. 2.1.2 are counted from Pz.
+hipError_t launch_resolve(const DesignDev* designs, int n_designs, int LB, unsigned long long* img64, float* irr,
+                          const float* Pz, ffrt_stats* slots, ffrt_stats* stats, hipStream_t s);
+// Slice sums of the loss into partial (n_designs * LB * 5 doubles), resolving the irradiance from img64
+// first when img64 is not null (as launch_resolve, statistics included).  With dLdI not null a second kernel
+// writes dL/dI, loss and valid; otherwise the adjoint forms them from partial.
+hipError_t launch_loss(const DesignDev* designs, int n_designs, int LB, unsigned long long* img64, float* irr,
+                       const float* target, const float* Pz, ffrt_stats* slots, ffrt_stats* stats, double* partial,
+                       float* loss, float* dLdI, int32_t* valid, hipStream_t s);
+// After the adjoint: dL/dP = gacc, gacc cleared; with lpart not null the loss value and validity flag are
+// formed from the slice sums and stored, otherwise valid is read; with adam.Pz set, Adam updates the
+// designs whose loss found flux.
+hipError_t launch_finish(const DesignDev* designs, int n_designs, float* gacc, float* dLdP, const double* lpart,
+                         int LB, float* loss, int32_t* valid, const AdamArgs& adam, hipStream_t s);
 hipError_t launch_loss_f64(const DesignDev* designs, int n_designs, const float* irr, const float* target,
                            double* loss, hipStream_t s);
 hipError_t launch_adam(const DesignDev* designs, int n_designs, float* Pz, const float* g, float* m,

@@ -64,7 +64,9 @@ struct ffrt_plan {
     std::vector<DesignDev> dd;
     std::vector<int64_t> cp_off, img_off;
     int64_t total_cp = 0, total_img = 0, total_rays = 0;
-    int max_cp = 0, max_kt = 0;
+    int max_cp = 0, max_kt = 0, loss_lb = 1;
+    bool has_point = false;  // some design needs the root search (bounds kernel)
+    int64_t max_img = 0;
     std::vector<float> knots;
     // block maps per shape and source-kind group (designs of the other group get no blocks)
     std::vector<BlockMap> bmaps[N_SHAPES][2];
@@ -73,6 +75,7 @@ struct ffrt_plan {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     size_t off_designs = 0, off_bounds = 0, off_valid = 0, off_knots = 0, off_bmap = 0, off_slots = 0, need = 0;
+    size_t off_lpart = 0, off_img64 = 0, off_gacc = 0;
     int num_cu = 256;
     int fwd_cfg = 0, adj_cfg = 0;
     hipGraph_t graph = nullptr;
@@ -86,7 +89,9 @@ struct ffrt_plan {
         return reinterpret_cast<BlockMap*>(ws + off_bmap) + ((size_t)shape * 2 + kg) * nd;
     }
     ffrt_stats* d_slots() const { return reinterpret_cast<ffrt_stats*>(ws + off_slots); }
-    int64_t slot_floats() const { return (int64_t)nd * NSLOT * (int64_t)(sizeof(ffrt_stats) / 4); }
+    double* d_lpart() const { return reinterpret_cast<double*>(ws + off_lpart); }
+    unsigned long long* d_img64() const { return reinterpret_cast<unsigned long long*>(ws + off_img64); }
+    float* d_gacc() const { return reinterpret_cast<float*>(ws + off_gacc); }
 };
 
 namespace {
@@ -127,7 +132,8 @@ ffrt_status validate(const ffrt_problem& pr, int idx) {
     if (pr.opt.fresnel != 0 && pr.opt.fresnel != 1) return bad("fresnel must be 0 or 1");
     if (pr.opt.newton_max_iter < 1 || pr.opt.newton_max_iter > 32) return bad("newton_max_iter in [1, 32]");
     int64_t n = (int64_t)S.grid_u * S.grid_v * (S.kind == 2 ? (int64_t)S.emit_nx * S.emit_ny : 1);
-    if (n > ((int64_t)1 << 40)) return bad("too many rays");
+    // the forward's fixed-point pixel sums (at most 2^26 per ray) must stay below 2^63
+    if (n > ((int64_t)1 << 36)) return bad("too many rays in one design (at most 2^36)");
     return FFRT_OK;
 }
 
@@ -247,14 +253,15 @@ int grid_for(ffrt_plan* pl, int shape, int kg, int persistent) {
     return (int)std::max<int64_t>(g, 1);
 }
 
-// The forward trace kernel; partial statistics go to the plan's slots when `stats` is set.
-ffrt_status launch_forward(ffrt_plan* pl, const float* Pz, float* irr, bool stats, hipStream_t s) {
+// The forward trace kernel, into the plan's fixed-point image; partial statistics go to the plan's slots
+// when `stats` is set.  The image must be resolved (launch_resolve or the loss) before the next forward.
+ffrt_status launch_forward(ffrt_plan* pl, const float* Pz, bool stats, hipStream_t s) {
     const FwdCfg& c = FWD_CFGS[pl->fwd_cfg];
     for (int kg = 0; kg < 2; ++kg) {
         if (pl->nblocks[c.shape][kg] == 0) continue;
         TraceArgs A = make_args(pl, c.shape, kg);
         A.Pz = Pz;
-        A.irr = irr;
+        A.img64 = pl->d_img64();
         A.slots = stats ? pl->d_slots() : nullptr;
         A.use_tile = c.tile;
         HIP_TRY(pl->ks->forward(A, c.shape, grid_for(pl, c.shape, kg, c.persistent), s));
@@ -262,51 +269,78 @@ ffrt_status launch_forward(ffrt_plan* pl, const float* Pz, float* irr, bool stat
     return FFRT_OK;
 }
 
-ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, float* dLdP, hipStream_t s) {
+// The adjoint trace kernel, into the plan's gradient accumulator (launch_finish turns it into dL/dP).
+// dL/dI comes from dLdI, or, when dLdI is null, from irr, target and the slice sums of the last loss.
+ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, const float* irr,
+                           const float* target, hipStream_t s) {
     const AdjCfg& c = ADJ_CFGS[pl->adj_cfg];
     for (int kg = 0; kg < 2; ++kg) {
         if (pl->nblocks[c.shape][kg] == 0) continue;
         TraceArgs A = make_args(pl, c.shape, kg);
         A.Pz = Pz;
         A.dLdI = dLdI;
-        A.dLdP = dLdP;
+        A.irr = irr;
+        A.target = target;
+        A.lpart = pl->d_lpart();
+        A.loss_lb = pl->loss_lb;
+        A.gacc = pl->d_gacc();
         A.butterfly = c.butterfly;
         HIP_TRY(pl->ks->adjoint(A, c.shape, grid_for(pl, c.shape, kg, c.persistent), s));
     }
     return FFRT_OK;
 }
 
+AdamArgs no_adam() {
+    AdamArgs a;
+    std::memset(&a, 0, sizeof a);
+    return a;
+}
+
+// Bounds of sec. 2.2.2 for the current Pz (only plans with point or grid sources use them).
+ffrt_status run_bounds(ffrt_plan* pl, const float* Pz, hipStream_t s) {
+    if (pl->has_point) HIP_TRY(launch_bounds(pl->d_designs(), pl->nd, Pz, pl->P, pl->Q, pl->d_bounds(), s));
+    return FFRT_OK;
+}
+
 ffrt_status run_forward(ffrt_plan* pl, const float* Pz, float* irr, ffrt_stats* stats, hipStream_t s) {
-    HIP_TRY(launch_prepare(pl->d_designs(), pl->nd, Pz, pl->P, pl->Q, pl->d_bounds(), irr, pl->total_img,
-                           stats ? reinterpret_cast<float*>(pl->d_slots()) : nullptr, pl->slot_floats(), nullptr, 0,
-                           s));
-    ffrt_status st = launch_forward(pl, Pz, irr, stats != nullptr, s);
+    if (ffrt_status b = run_bounds(pl, Pz, s)) return b;
+    ffrt_status st = launch_forward(pl, Pz, stats != nullptr, s);
     if (st) return st;
-    if (stats) HIP_TRY(launch_stats(pl->nd, pl->d_bounds(), pl->d_slots(), stats, s));
+    HIP_TRY(launch_resolve(pl->d_designs(), pl->nd, pl->loss_lb, pl->d_img64(), irr, Pz, pl->d_slots(), stats, s));
     return FFRT_OK;
 }
 
 ffrt_status run_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, float* dLdP, hipStream_t s) {
-    HIP_TRY(launch_prepare(pl->d_designs(), pl->nd, Pz, pl->P, pl->Q, pl->d_bounds(), dLdP, pl->total_cp, nullptr,
-                           0, nullptr, 0, s));
-    return launch_adjoint(pl, Pz, dLdI, dLdP, s);
+    if (ffrt_status b = run_bounds(pl, Pz, s)) return b;
+    if (ffrt_status a = launch_adjoint(pl, Pz, dLdI, nullptr, nullptr, s)) return a;
+    HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), dLdP, nullptr, pl->loss_lb, nullptr, nullptr,
+                          no_adam(), s));
+    return FFRT_OK;
 }
 
-// One optimisation step in five kernels: prepare (bounds, clearing), forward, loss (+ statistics),
-// adjoint, Adam.
+// One optimisation step in four kernels (five with point or grid sources: their bounds of sec. 2.2.2
+// first): forward, loss slice sums (resolving the irradiance, statistics), adjoint (dL/dI formed on the
+// fly), finish (dL/dP, loss value, Adam).  With dLdI set, dL/dI is also written out (one more kernel) and
+// read back.
 ffrt_status run_step(ffrt_plan* pl, float* Pz, const float* target, float* irr, float* loss, float* dLdI,
                      float* dLdP, float* m, float* v, int32_t* t, ffrt_stats* stats, const ffrt_adam_hparams& hp,
                      hipStream_t s) {
-    HIP_TRY(launch_prepare(pl->d_designs(), pl->nd, Pz, pl->P, pl->Q, pl->d_bounds(), irr, pl->total_img, dLdP,
-                           pl->total_cp, stats ? reinterpret_cast<float*>(pl->d_slots()) : nullptr,
-                           pl->slot_floats(), s));
-    ffrt_status st = launch_forward(pl, Pz, irr, stats != nullptr, s);
+    if (ffrt_status b = run_bounds(pl, Pz, s)) return b;
+    ffrt_status st = launch_forward(pl, Pz, stats != nullptr, s);
     if (st) return st;
-    HIP_TRY(launch_loss(pl->d_designs(), pl->nd, irr, target, loss, dLdI, pl->d_valid(), pl->d_bounds(),
-                        pl->d_slots(), stats, s));
-    st = launch_adjoint(pl, Pz, dLdI, dLdP, s);
+    HIP_TRY(launch_loss(pl->d_designs(), pl->nd, pl->loss_lb, pl->d_img64(), irr, target, Pz, pl->d_slots(), stats,
+                        pl->d_lpart(), loss, dLdI, pl->d_valid(), s));
+    AdamArgs adam;
+    adam.Pz = Pz;
+    adam.m = m;
+    adam.v = v;
+    adam.t = t;
+    adam.hp = hp;
+    st = launch_adjoint(pl, Pz, dLdI, irr, target, s);
     if (st) return st;
-    HIP_TRY(launch_adam(pl->d_designs(), pl->nd, Pz, dLdP, m, v, t, pl->d_valid(), hp, s));
+    // with dLdI written, the dL/dI kernel already stored loss and valid
+    HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), dLdP, dLdI ? nullptr : pl->d_lpart(), pl->loss_lb,
+                          loss, pl->d_valid(), adam, s));
     return FFRT_OK;
 }
 
@@ -370,6 +404,8 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
         img += (int64_t)d.nx * d.ny;
         pl->total_rays += d.n_rays;
         pl->max_cp = std::max(pl->max_cp, d.n_u * d.n_v);
+        pl->max_img = std::max<int64_t>(pl->max_img, (int64_t)d.nx * d.ny);
+        if (d.kind != 0) pl->has_point = true;
         pl->max_kt = std::max(pl->max_kt, d.nsu * kt_stride(pl->P) + d.nsv * kt_stride(pl->Q));
     }
     pl->cp_off.push_back(cp);
@@ -406,6 +442,13 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
     off = align256(off + sizeof(BlockMap) * N_SHAPES * 2 * n_designs);
     pl->off_slots = off;
     off = align256(off + sizeof(ffrt_stats) * NSLOT * n_designs);
+    pl->loss_lb = loss_blocks_per_design(pl->max_img);
+    pl->off_lpart = off;
+    off = align256(off + sizeof(double) * 5 * pl->loss_lb * n_designs);
+    pl->off_img64 = off;
+    off = align256(off + sizeof(unsigned long long) * (size_t)pl->total_img);
+    pl->off_gacc = off;
+    off = align256(off + sizeof(float) * (size_t)pl->total_cp);
     pl->need = off;
     *out = pl;
     return FFRT_OK;
@@ -439,6 +482,10 @@ ffrt_status ffrt_plan_set_workspace(ffrt_plan* plan, void* dev_ptr, size_t bytes
     HIP_TRY(hipMemcpy(plan->d_designs(), plan->dd.data(), sizeof(DesignDev) * plan->nd, hipMemcpyHostToDevice));
     std::vector<int32_t> ones(plan->nd, 1);
     HIP_TRY(hipMemcpy(plan->d_valid(), ones.data(), sizeof(int32_t) * plan->nd, hipMemcpyHostToDevice));
+    // accumulators and counters that the kernels expect to be zero on entry (and leave zero on exit)
+    HIP_TRY(hipMemset(plan->d_slots(), 0, sizeof(ffrt_stats) * NSLOT * plan->nd));
+    HIP_TRY(hipMemset(plan->d_img64(), 0, sizeof(unsigned long long) * plan->total_img));
+    HIP_TRY(hipMemset(plan->d_gacc(), 0, sizeof(float) * plan->total_cp));
     if (!plan->knots.empty())
         HIP_TRY(hipMemcpy(plan->d_knots(), plan->knots.data(), sizeof(float) * plan->knots.size(),
                           hipMemcpyHostToDevice));
@@ -478,8 +525,8 @@ ffrt_status ffrt_loss(ffrt_plan* plan, const float* irr, const float* target, fl
                       void* stream) {
     if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
     if (!irr || !target || !loss || !dL_dI) return fail(FFRT_E_ARG, "null buffer");
-    HIP_TRY(launch_loss(plan->d_designs(), plan->nd, irr, target, loss, dL_dI, plan->d_valid(), plan->d_bounds(),
-                        plan->d_slots(), nullptr, (hipStream_t)stream));
+    HIP_TRY(launch_loss(plan->d_designs(), plan->nd, plan->loss_lb, nullptr, const_cast<float*>(irr), target, nullptr,
+                        plan->d_slots(), nullptr, plan->d_lpart(), loss, dL_dI, plan->d_valid(), (hipStream_t)stream));
     return FFRT_OK;
 }
 
@@ -508,7 +555,7 @@ ffrt_status ffrt_step(ffrt_plan* plan, float* Pz, const float* target, float* ir
                       float* dL_dP, float* m, float* v, int32_t* t, ffrt_stats* stats, const ffrt_adam_hparams* hp,
                       void* stream) {
     if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
-    if (!Pz || !target || !irr || !loss || !dL_dI || !dL_dP || !m || !v || !t || !hp)
+    if (!Pz || !target || !irr || !loss || !dL_dP || !m || !v || !t || !hp)
         return fail(FFRT_E_ARG, "null buffer");
     return run_step(plan, Pz, target, irr, loss, dL_dI, dL_dP, m, v, t, stats, *hp, (hipStream_t)stream);
 }
@@ -519,7 +566,7 @@ ffrt_status ffrt_graph_capture(ffrt_plan* plan, int32_t steps, float* Pz, const 
     if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
     if (!stream) return fail(FFRT_E_ARG, "graph capture needs a non-default stream");
     if (steps < 1) return fail(FFRT_E_ARG, "steps must be >= 1");
-    if (!Pz || !target || !irr || !loss || !dL_dI || !dL_dP || !m || !v || !t || !hp)
+    if (!Pz || !target || !irr || !loss || !dL_dP || !m || !v || !t || !hp)
         return fail(FFRT_E_ARG, "null buffer");
     hipStream_t s = (hipStream_t)stream;
     if (plan->gexec) { (void)hipGraphExecDestroy(plan->gexec); plan->gexec = nullptr; }
@@ -623,12 +670,19 @@ ffrt_status ffrt_plan_time_kernels(ffrt_plan* plan, const float* Pz, float* irr,
     if (!st) st = run_adjoint(plan, Pz, dL_dI, dL_dP, s);
     hipError_t e = hipSuccess;
     if (!st) e = hipEventRecord(ev[0], s);
-    for (int r = 0; r < reps && !st && e == hipSuccess; ++r) st = launch_forward(plan, Pz, irr, false, s);
+    for (int r = 0; r < reps && !st && e == hipSuccess; ++r) st = launch_forward(plan, Pz, false, s);
     if (!st && e == hipSuccess) e = hipEventRecord(ev[1], s);
     if (!st && e == hipSuccess) e = hipEventRecord(ev[2], s);
-    for (int r = 0; r < reps && !st && e == hipSuccess; ++r) st = launch_adjoint(plan, Pz, dL_dI, dL_dP, s);
+    for (int r = 0; r < reps && !st && e == hipSuccess; ++r)
+        st = launch_adjoint(plan, Pz, dL_dI, nullptr, nullptr, s);
     if (!st && e == hipSuccess) e = hipEventRecord(ev[3], s);
     if (!st && e == hipSuccess) e = hipEventSynchronize(ev[3]);
+    // the timed launches accumulated into the fixed-point image and the gradient accumulator without
+    // consuming them: clear both in any case
+    hipError_t ez = hipMemsetAsync(plan->d_img64(), 0, sizeof(unsigned long long) * plan->total_img, s);
+    if (ez == hipSuccess) ez = hipMemsetAsync(plan->d_gacc(), 0, sizeof(float) * plan->total_cp, s);
+    if (!st && e == hipSuccess) e = ez;
+    if (!st && e == hipSuccess) e = hipStreamSynchronize(s);
     float f = 0.0f, a = 0.0f;
     if (!st && e == hipSuccess) e = hipEventElapsedTime(&f, ev[0], ev[1]);
     if (!st && e == hipSuccess) e = hipEventElapsedTime(&a, ev[2], ev[3]);
@@ -646,8 +700,7 @@ ffrt_status ffrt_trace_rays(ffrt_plan* plan, int32_t design, const float* Pz, co
     if (design < 0 || design >= plan->nd || !Pz || (n > 0 && (!ray_ids || !out8)) || n < 0)
         return fail(FFRT_E_ARG, "bad argument");
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(launch_prepare(plan->d_designs(), plan->nd, Pz, plan->P, plan->Q, plan->d_bounds(), nullptr, 0, nullptr,
-                           0, nullptr, 0, s));
+    if (ffrt_status b = run_bounds(plan, Pz, s)) return b;
     TraceArgs A = make_args(plan, 0, 0);
     A.Pz = Pz;
     HIP_TRY(plan->ks->trace_rays(A, design, ray_ids, n, out8, s));

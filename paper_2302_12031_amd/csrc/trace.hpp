@@ -17,6 +17,8 @@
 #include <stdint.h>
 
 #include "ffrt_internal.h"
+#include "loss.hpp"
+#include "wave.hpp"
 
 namespace ffrt {
 
@@ -54,67 +56,6 @@ __device__ __forceinline__ T load_uniform(const T* p, int i) {
 #else
     return p[i];  // host pass of the single-source compile: never executed
 #endif
-}
-
-// ------------------------------------------------------------------------------------------------
-// Cross-lane exchanges that stay in the VALU (no LDS crossbar traffic): v_permlane32_swap and
-// v_permlane16_swap exchange the two 32-lane halves / neighbouring 16-lane rows of two registers, and DPP
-// reads the partner lane L ^ 15 (row_mirror), L ^ 7 (row_half_mirror), L ^ 2 and L ^ 1 (quad_perm).  The
-// six masks 32, 16, 15, 7, 2, 1 span all six lane bits, so reducing over them covers the whole wave.
-// ------------------------------------------------------------------------------------------------
-template <int M>
-__device__ __forceinline__ uint32_t dpp_xor(uint32_t v) {
-    static_assert(M == 15 || M == 7 || M == 2 || M == 1, "DPP partner mask");
-    constexpr int ctrl = M == 15 ? 0x140 : (M == 7 ? 0x141 : (M == 2 ? 0x4E : 0xB1));
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, ctrl, 0xF, 0xF, false);
-}
-template <int M>
-__device__ __forceinline__ float dpp_xor(float v) {
-    return __builtin_bit_cast(float, dpp_xor<M>(__builtin_bit_cast(uint32_t, v)));
-}
-template <int M>
-__device__ __forceinline__ int dpp_xor(int v) {
-    return (int)dpp_xor<M>((uint32_t)v);
-}
-// (a, b) -> halves / rows swapped: for lanes whose bit log2(OFF) is clear, first = a[L], second =
-// a[L + OFF]; for the others, first = b[L - OFF], second = b[L].
-template <int OFF, class T>
-__device__ __forceinline__ void lane_swap(T a, T b, T& first, T& second) {
-    static_assert(OFF == 32 || OFF == 16, "permlane swap distance");
-    const uint32_t ua = __builtin_bit_cast(uint32_t, a), ub = __builtin_bit_cast(uint32_t, b);
-    if constexpr (OFF == 32) {
-        auto r = __builtin_amdgcn_permlane32_swap(ua, ub, false, false);
-        first = __builtin_bit_cast(T, (uint32_t)r[0]);
-        second = __builtin_bit_cast(T, (uint32_t)r[1]);
-    } else {
-        auto r = __builtin_amdgcn_permlane16_swap(ua, ub, false, false);
-        first = __builtin_bit_cast(T, (uint32_t)r[0]);
-        second = __builtin_bit_cast(T, (uint32_t)r[1]);
-    }
-}
-// Whole-wave reduction; every lane receives the result.
-template <class T, class Op>
-__device__ __forceinline__ T wave_reduce(T v, Op op) {
-    T x, y;
-    lane_swap<32>(v, v, x, y);
-    v = op(x, y);
-    lane_swap<16>(v, v, x, y);
-    v = op(x, y);
-    v = op(v, dpp_xor<15>(v));
-    v = op(v, dpp_xor<7>(v));
-    v = op(v, dpp_xor<2>(v));
-    v = op(v, dpp_xor<1>(v));
-    return v;
-}
-template <class T>
-__device__ __forceinline__ T wave_sum(T v) {
-    return wave_reduce(v, [](T a, T b) { return a + b; });
-}
-__device__ __forceinline__ int wave_min(int v) {
-    return wave_reduce(v, [](int a, int b) { return min(a, b); });
-}
-__device__ __forceinline__ int wave_max(int v) {
-    return wave_reduce(v, [](int a, int b) { return max(a, b); });
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -581,9 +522,21 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
 // One ray, adjoint: re-trace, gather dL/dI over the filter window, reverse sweep.  Returns false when the
 // ray does not reach the screen.  g[] receives dL/dP for control point (ku + a, kv + b) at a * (Q+1) + b.
 // ------------------------------------------------------------------------------------------------
+// dL/dI of one design: read from an array, or formed from the irradiance, the target and the loss scalars.
+struct GradSrc {
+    const float* G;  // null: ((I is - T isT) - dot) coef
+    const float* I;
+    const float* T;
+    LossScalars L;
+    __device__ __forceinline__ float at(int64_t k) const {
+        if (G) return G[k];
+        return ((I[k] * L.is - T[k] * L.isT) - L.dot) * L.coef;
+    }
+};
+
 template <int P, int Q, int NU, int KIND>
 __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDev& B, const float* sP,
-                                              const float* sKu, const float* sKv, const float* __restrict__ G,
+                                              const float* sKu, const float* sKv, const GradSrc& G,
                                               int e, int ku, int kv, int64_t id, int& cku, int& ckv,
                                               float* g) {
     RayIn r = ray_entry<KIND>(D, e, ku, kv, id);
@@ -620,7 +573,7 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
 #pragma unroll
         for (int b = 0; b < NU; ++b) {
             int j = min(max(j0 + b - H, 0), D.ny - 1);
-            float Gij = G[(int64_t)i * D.ny + j];
+            float Gij = G.at((int64_t)i * D.ny + j);
             gb += Gij * Fy[b];
             gbp += Gij * dFy[b];
         }
@@ -707,88 +660,48 @@ __device__ __forceinline__ int find_design(const BlockMap* bm, int n, int64_t b)
     return __builtin_amdgcn_readfirstlane(lo);
 }
 
-// Load the design's control heights (relative to zref) and knot tables into LDS.
-__device__ __forceinline__ void stage_design(const TraceArgs& A, const DesignDev& D, float zref, float* sP,
-                                             float* sK, int p, int q) {
+// Stage design d in LDS: the knot tables, and P^z relative to a reference height zref inside the lens's
+// height range (single-precision sums of B-spline terms then cancel far less).  With `bracket` (sources
+// whose rays need the root search) the bounds of sec. 2.2.2 come from launch_bounds and zref is the middle of
+// the convex-hull box; otherwise (collimated rays meet the surface at a known (x, y)) zref is the height of
+// the middle control point and no bounds are used.  Every thread calls it; it ends with a barrier.
+__device__ BoundsDev stage_design(const TraceArgs& A, const DesignDev& D, int d, float* sP, float* sK, int p, int q,
+                                  bool bracket) {
     const float* P = A.Pz + D.cp_off;
-    int ncp = D.n_u * D.n_v;
-    for (int i = threadIdx.x; i < ncp; i += WG) sP[i] = P[i] - zref;
-    int nku = D.nsu * kt_stride(p), nkv = D.nsv * kt_stride(q);
+    const int ncp = D.n_u * D.n_v;
+    const int nku = D.nsu * kt_stride(p), nkv = D.nsv * kt_stride(q);
     const float* ku = A.knots + D.kt_u;
     const float* kv = A.knots + D.kt_v;
+    BoundsDev B;
+    if (bracket) {
+        B = load_uniform(A.bounds, d);
+    } else {
+        B.zmin = B.zmax = B.gx = B.gy = 0.0f;
+        const float zc = load_uniform(P, (D.n_u / 2) * D.n_v + D.n_v / 2);
+        B.zref = isfinite(zc) ? zc : D.zmin_allowed;
+    }
+    for (int i = threadIdx.x; i < ncp; i += WG) sP[i] = P[i] - B.zref;
     for (int i = threadIdx.x; i < nku; i += WG) sK[i] = ku[i];
     for (int i = threadIdx.x; i < nkv; i += WG) sK[nku + i] = kv[i];
-}
-
-// Reduce-scatter of NV per-lane values across the wave.  Each halving step at lane offset OFF keeps one
-// half of the values (the upper half on lanes whose OFF bit is set) and adds the partner's copy of it, so
-// after log2(NV) steps lane l holds a partial sum of value index l >> (6 - log2 NV); the remaining
-// xor-steps complete it.  Lanes whose low 6 - log2(NV) bits are zero hold the wave totals.
-// One butterfly step of a wave reduce-scatter: lanes with bit OFF clear keep entries [0, HALF) and add the
-// partner's copy of them, the others keep [HALF, 2 HALF).  The partner differs in bit OFF (and, for the
-// DPP steps, in lower bits too, which the later steps pair up in turn).
-template <int HALF, int OFF>
-__device__ __forceinline__ void halve(float* v, int lane) {
-    if constexpr (OFF == 32 || OFF == 16) {
-#pragma unroll
-        for (int j = 0; j < HALF; ++j) {
-            float x, y;
-            lane_swap<OFF>(v[j], v[j + HALF], x, y);
-            v[j] = x + y;
-        }
-    } else {
-        constexpr int M = OFF == 8 ? 15 : (OFF == 4 ? 7 : OFF);
-        const bool upper = (lane & OFF) != 0;
-#pragma unroll
-        for (int j = 0; j < HALF; ++j) {
-            float lo = v[j], hi = v[j + HALF];
-            float send = upper ? lo : hi;
-            float keep = upper ? hi : lo;
-            v[j] = keep + dpp_xor<M>(send);
-        }
-    }
-}
-
-// Sum NV per-lane values over the wave; entry k of the total ends in the lanes with lane >> (6 - log2 NV)
-// == k (for NV < 64 every such lane holds it; the lane with the low bits clear is used).
-template <int NV>
-__device__ __forceinline__ float wave_reduce_scatter(float* v, int lane) {
-    static_assert(NV == 16 || NV == 32 || NV == 64, "NV");
-    float s;
-    if constexpr (NV == 16) {
-        halve<8, 32>(v, lane); halve<4, 16>(v, lane); halve<2, 8>(v, lane); halve<1, 4>(v, lane);
-        s = v[0];
-        s += dpp_xor<2>(s);
-        s += dpp_xor<1>(s);
-    } else if constexpr (NV == 32) {
-        halve<16, 32>(v, lane); halve<8, 16>(v, lane); halve<4, 8>(v, lane); halve<2, 4>(v, lane);
-        halve<1, 2>(v, lane);
-        s = v[0];
-        s += dpp_xor<1>(s);
-    } else {
-        halve<32, 32>(v, lane); halve<16, 16>(v, lane); halve<8, 8>(v, lane); halve<4, 4>(v, lane);
-        halve<2, 2>(v, lane); halve<1, 1>(v, lane);
-        s = v[0];
-    }
-    return s;
+    __syncthreads();
+    return B;
 }
 
 // ------------------------------------------------------------------------------------------------
 // Forward kernel
 // ------------------------------------------------------------------------------------------------
-// Add a pixel contribution v >= 0 either to the workgroup's LDS tile, as the 64-bit fixed-point integer
-// rint(v scale) (integer LDS atomics are far cheaper than float ones on gfx950, and integer sums do not
-// depend on the order of the additions), or, when the block's footprint does not fit the tile, directly to
-// the float image with a device-scope atomic.
+// Add a pixel contribution v >= 0, as the 64-bit fixed-point integer rint(v scale), either to the
+// workgroup's LDS tile or, when the block's footprint does not fit the tile, directly to the device image.
+// Integer LDS atomics are far cheaper than float ones on gfx950, and integer sums do not depend on the
+// order of the additions, so the irradiance is reproducible bit for bit.
 __device__ __forceinline__ void splat_add(bool to_tile, unsigned long long* tile, int tile_ld, int ilo, int jlo,
-                                          float scale, float* img, int ny, int i, int j, float v) {
-    if (to_tile) {
-        const long long q = (long long)__float2int_rn(v * scale);
-        __hip_atomic_fetch_add(&tile[(i - ilo) * tile_ld + (j - jlo)], (unsigned long long)q, __ATOMIC_RELAXED,
+                                          float scale, unsigned long long* img, int ny, int i, int j, float v) {
+    const unsigned long long q = (unsigned long long)(long long)__float2int_rn(v * scale);
+    if (to_tile)
+        __hip_atomic_fetch_add(&tile[(i - ilo) * tile_ld + (j - jlo)], q, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
-    } else {
-        __hip_atomic_fetch_add(&img[(int64_t)i * ny + j], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    else
+        __hip_atomic_fetch_add(&img[(int64_t)i * ny + j], q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int P, int Q, int NU, int SHAPE, int KIND>
@@ -808,15 +721,14 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
     __shared__ float s_red[4][10];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int cur = -1;
+    BoundsDev B;
     for (int64_t pb = blockIdx.x; pb < A.n_blocks; pb += gridDim.x) {
         const int64_t b = xcd_remap(pb, A.n_blocks);
         const int d = find_design(A.bmap, A.n_designs, b);
         const DesignDev D = load_uniform(A.designs, d);
-        const BoundsDev B = load_uniform(A.bounds, d);
         if (d != cur) {
             __syncthreads();
-            stage_design(A, D, B.zref, sP, sK, P, Q);
-            __syncthreads();
+            B = stage_design(A, D, d, sP, sK, P, Q, KIND != 0);
             cur = d;
         }
         const float* sKu = sK;
@@ -891,7 +803,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
             __syncthreads();
         }
         // ---- footprint of the block (landing pixels widened by the filter half-width)
-        float* img = A.irr + D.img_off;
+        unsigned long long* img = A.img64 + D.img_off;
         bool use_tile = false;
         int ilo = 0, jlo = 0, tw = 0, area = 0;
         if (A.use_tile) {
@@ -988,10 +900,11 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
         if (use_tile) {
             __syncthreads();
             for (int i = threadIdx.x; i < area; i += WG) {
-                const long long q = (long long)tile[i];
+                const unsigned long long q = tile[i];
                 const int ti = i / tw;
-                if (q != 0)
-                    atomicAdd(&img[(int64_t)(ilo + ti) * D.ny + jlo + (i - ti * tw)], (float)q * D.fx_unscale);
+                if (q != 0ull)
+                    __hip_atomic_fetch_add(&img[(int64_t)(ilo + ti) * D.ny + jlo + (i - ti * tw)], q,
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             __syncthreads();
         }
@@ -1013,6 +926,18 @@ __device__ __forceinline__ void cp_flush_lane(float* sG, int n_v, int ku, int kv
         }
 }
 
+// End of a workgroup's run of blocks of design d: add its LDS control-net gradient to the device
+// accumulator (cleared again by the finishing kernel that reads it).
+__device__ void adjoint_flush(const TraceArgs& A, int d, const float* sG) {
+    __syncthreads();
+    const DesignDev D = load_uniform(A.designs, d);
+    float* acc = A.gacc + D.cp_off;
+    for (int i = threadIdx.x; i < D.n_u * D.n_v; i += WG) {
+        const float v = sG[i];
+        if (v != 0.0f) atomicAdd(&acc[i], v);
+    }
+}
+
 template <int P, int Q, int NU, int KIND>
 __global__ __launch_bounds__(WG) void k_adjoint(TraceArgs A, int shape) {
     constexpr int NT = (P + 1) * (Q + 1);
@@ -1027,32 +952,32 @@ __global__ __launch_bounds__(WG) void k_adjoint(TraceArgs A, int shape) {
     const int BU = 16 * MU, BV = 16 * MV;
     const int mv_shift = MV == 1 ? 0 : (MV == 2 ? 1 : 2);
     int cur = -1;
+    BoundsDev B;
+    GradSrc G;
     for (int64_t pb = blockIdx.x; pb < A.n_blocks; pb += gridDim.x) {
         const int64_t b = xcd_remap(pb, A.n_blocks);
         const int d = find_design(A.bmap, A.n_designs, b);
         const DesignDev D = load_uniform(A.designs, d);
-        const int ncp = D.n_u * D.n_v;
-        if (d != cur) {
-            __syncthreads();
-            if (cur >= 0) {  // flush the previous design's accumulator
-                const DesignDev Dc = load_uniform(A.designs, cur);
-                for (int i = threadIdx.x; i < Dc.n_u * Dc.n_v; i += WG) {
-                    float v = sG[i];
-                    if (v != 0.0f) atomicAdd(&A.dLdP[Dc.cp_off + i], v);
-                }
-                __syncthreads();
-            }
-            stage_design(A, D, load_uniform(A.bounds, d).zref, sP, sK, P, Q);
-            for (int i = threadIdx.x; i < ncp; i += WG) sG[i] = 0.0f;
-            __syncthreads();
-            cur = d;
-        }
-        const BoundsDev B = load_uniform(A.bounds, d);
-        const float* sKu = sK;
-        const float* sKv = sK + D.nsu * kt_stride(P);
-        const float* G = A.dLdI + D.img_off;
         const BlockMap bm = load_uniform(A.bmap, d);
         int64_t local = b - bm.first;
+        if (d != cur) {
+            if (cur >= 0) adjoint_flush(A, cur, sG);
+            __syncthreads();
+            for (int i = threadIdx.x; i < D.n_u * D.n_v; i += WG) sG[i] = 0.0f;
+            B = stage_design(A, D, d, sP, sK, P, Q, KIND != 0);
+            if (A.dLdI) {
+                G.G = A.dLdI + D.img_off;
+            } else {
+                // every wave forms the loss from the slice sums (same bits in every wave and workgroup)
+                G.G = nullptr;
+                G.I = A.irr + D.img_off;
+                G.T = A.target + D.img_off;
+                G.L = loss_from_partials(A.lpart, d, A.loss_lb, D).L;
+            }
+            cur = d;
+        }
+        const float* sKu = sK;
+        const float* sKv = sK + D.nsu * kt_stride(P);
         int e = (int)(local / bm.per_emitter);
         int rb = (int)(local - (int64_t)e * bm.per_emitter);
         int bu = rb / bm.nbv, bv = rb - (rb / bm.nbv) * bm.nbv;
@@ -1104,15 +1029,7 @@ __global__ __launch_bounds__(WG) void k_adjoint(TraceArgs A, int shape) {
             cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc);
         }
     }
-    // flush the last design's accumulator
-    __syncthreads();
-    if (cur >= 0) {
-        const DesignDev Dc = load_uniform(A.designs, cur);
-        for (int i = threadIdx.x; i < Dc.n_u * Dc.n_v; i += WG) {
-            float v = sG[i];
-            if (v != 0.0f) atomicAdd(&A.dLdP[Dc.cp_off + i], v);
-        }
-    }
+    if (cur >= 0) adjoint_flush(A, cur, sG);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1125,8 +1042,7 @@ __global__ __launch_bounds__(WG) void k_trace_rays(TraceArgs A, int design, cons
     float* sP = smem;
     float* sK = sP + A.lds_cp;
     const DesignDev D = load_uniform(A.designs, design);
-    stage_design(A, D, load_uniform(A.bounds, design).zref, sP, sK, P, Q);
-    __syncthreads();
+    const BoundsDev B = stage_design(A, D, design, sP, sK, P, Q, D.kind != 0);
     int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (i >= n) return;
     int64_t id = ids[i];
@@ -1134,7 +1050,6 @@ __global__ __launch_bounds__(WG) void k_trace_rays(TraceArgs A, int design, cons
     int e = (int)(id / per);
     int64_t rr = id - (int64_t)e * per;
     int ku = (int)(rr / D.grid_v), kv = (int)(rr - (rr / D.grid_v) * D.grid_v);
-    const BoundsDev B = load_uniform(A.bounds, design);
     const float* sKv = sK + D.nsu * kt_stride(P);
     FwdRay o = D.kind == 0 ? trace_forward<P, Q, 0>(D, B, sP, sK, sKv, e, ku, kv, id)
                            : trace_forward<P, Q, 1>(D, B, sP, sK, sKv, e, ku, kv, id);

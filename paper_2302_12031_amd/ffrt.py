@@ -281,23 +281,25 @@ class Plan:
         _check(lib().ffrt_adam(self.h, _ptr(Pz), _ptr(g), _ptr(m), _ptr(v), _ptr(t), ctypes.byref(hp.c()),
                                _stream(stream)), "ffrt_adam")
 
-    def new_state(self, Pz):
-        """Buffers of an optimisation loop for control heights Pz (packed)."""
+    def new_state(self, Pz, with_dLdI=False):
+        """Buffers of an optimisation loop for control heights Pz (packed).  Without with_dLdI the step does
+        not write dL/dI out (the adjoint forms it on the fly), which saves a kernel per step."""
         dev = self.device
         return dict(
             Pz=Pz, irr=torch.zeros(self.total_img, device=dev), loss=torch.zeros(self.n_designs, device=dev),
-            dLdI=torch.zeros(self.total_img, device=dev), dLdP=torch.zeros(self.total_cp, device=dev),
+            dLdI=torch.zeros(self.total_img, device=dev) if with_dLdI else None,
+            dLdP=torch.zeros(self.total_cp, device=dev),
             m=torch.zeros(self.total_cp, device=dev), v=torch.zeros(self.total_cp, device=dev),
             t=torch.zeros(self.n_designs, dtype=torch.int32, device=dev), stats=self.new_stats())
 
     def step(self, st, target, hp=AdamHP(), stream=None):
         _check(lib().ffrt_step(self.h, _ptr(st["Pz"]), _ptr(target), _ptr(st["irr"]), _ptr(st["loss"]),
-                               _ptr(st["dLdI"]), _ptr(st["dLdP"]), _ptr(st["m"]), _ptr(st["v"]), _ptr(st["t"]),
+                               _ptr(st.get("dLdI")), _ptr(st["dLdP"]), _ptr(st["m"]), _ptr(st["v"]), _ptr(st["t"]),
                                _ptr(st["stats"]), ctypes.byref(hp.c()), _stream(stream)), "ffrt_step")
 
     def graph_capture(self, st, target, steps=1, hp=AdamHP(), stream=None):
         _check(lib().ffrt_graph_capture(self.h, steps, _ptr(st["Pz"]), _ptr(target), _ptr(st["irr"]),
-                                        _ptr(st["loss"]), _ptr(st["dLdI"]), _ptr(st["dLdP"]), _ptr(st["m"]),
+                                        _ptr(st["loss"]), _ptr(st.get("dLdI")), _ptr(st["dLdP"]), _ptr(st["m"]),
                                         _ptr(st["v"]), _ptr(st["t"]), _ptr(st["stats"]), ctypes.byref(hp.c()),
                                         _stream(stream)), "ffrt_graph_capture")
 

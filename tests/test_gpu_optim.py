@@ -59,6 +59,27 @@ def test_step_equals_forward_loss_adjoint_adam():
     torch.testing.assert_close(st["Pz"], P1, rtol=1e-6, atol=1e-6)
 
 
+def test_step_with_and_without_written_dLdI_agree():
+    """The step forms dL/dI on the fly unless asked to write it; both paths give the same update."""
+    wl = W.c3(512)
+    plan_a = ffrt.Plan(wl.problems)
+    plan_b = ffrt.Plan(wl.problems)
+    P0 = plan_a.pack_cp(wl.Pz)
+    st_a = plan_a.new_state(P0.clone())
+    st_b = plan_b.new_state(P0.clone(), with_dLdI=True)
+    T = plan_a.pack_img(wl.targets)
+    for _ in range(3):
+        plan_a.step(st_a, T)
+        plan_b.step(st_b, T)
+    torch.cuda.synchronize()
+    torch.testing.assert_close(st_a["loss"], st_b["loss"], rtol=1e-6, atol=0)
+    torch.testing.assert_close(st_a["dLdP"], st_b["dLdP"], rtol=1e-4, atol=1e-5 * st_b["dLdP"].abs().max().item())
+    torch.testing.assert_close(st_a["Pz"], st_b["Pz"], rtol=0, atol=2e-6)
+    _, G = plan_b.loss(st_b["irr"], T)
+    torch.testing.assert_close(st_b["dLdI"], G, rtol=1e-6, atol=0)
+    assert int(st_a["t"][0]) == int(st_b["t"][0]) == 3
+
+
 @pytest.mark.parametrize("steps_per_graph", [1, 4])
 def test_graph_replay_matches_eager_steps(steps_per_graph):
     wl = W.c2(512)
