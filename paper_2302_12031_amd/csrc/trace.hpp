@@ -805,7 +805,8 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
         // ---- footprint of the block (landing pixels widened by the filter half-width)
         unsigned long long* img = A.img64 + D.img_off;
         bool use_tile = false;
-        int ilo = 0, jlo = 0, tw = 0, area = 0;
+        int ilo = 0, jlo = 0, tw = 0, area = 0, ncopy = 1;
+        unsigned long long* mytile = tile;
         if (A.use_tile) {
             int a0 = wave_min(imin), a1 = wave_max(imax), b0 = wave_min(jmin), b1 = wave_max(jmax);
             if (lane == 0) {
@@ -829,8 +830,13 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
             area = (ihi - ilo + 1) * tw;
             use_tile = area <= TILE_CAP;
             if (use_tile) {
-                for (int i = threadIdx.x; i < area; i += WG) tile[i] = 0ull;
+                // Neighbouring lanes usually add to the same pixels, and LDS atomics on one address serialise:
+                // when it fits, each of the four lanes of a 2 x 2 patch of the wave's 8 x 8 lane grid adds to
+                // its own copy of the tile, and the flush sums the copies.
+                ncopy = 4 * area <= TILE_CAP ? 4 : 1;
+                for (int i = threadIdx.x; i < ncopy * area; i += WG) tile[i] = 0ull;
                 __syncthreads();
+                mytile = tile + (ncopy == 4 ? ((lane & 1) | ((lane >> 2) & 2)) * area : 0);
             }
         }
         // ---- splat
@@ -855,7 +861,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
                         for (int bb = 0; bb < NU; ++bb) {
                             const float v = W[r] * Fx[a] * Fy[bb];
                             if (v != 0.0f)
-                                splat_add(use_tile, tile, tw, ilo, jlo, D.fx_scale, img, D.ny, ai + di + a,
+                                splat_add(use_tile, mytile, tw, ilo, jlo, D.fx_scale, img, D.ny, ai + di + a,
                                           aj + dj + bb, v);
                         }
                     }
@@ -876,7 +882,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
 #pragma unroll
             for (int k = 0; k < WN * WN; ++k)
                 if (acc[k] != 0.0f)
-                    splat_add(use_tile, tile, tw, ilo, jlo, D.fx_scale, img, D.ny, ai + k / WN, aj + k % WN, acc[k]);
+                    splat_add(use_tile, mytile, tw, ilo, jlo, D.fx_scale, img, D.ny, ai + k / WN, aj + k % WN, acc[k]);
         } else {
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
@@ -892,7 +898,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
                     for (int bb = 0; bb < NU; ++bb) {
                         int j = j0 + bb - H;
                         if (j < 0 || j >= D.ny) continue;
-                        splat_add(use_tile, tile, tw, ilo, jlo, D.fx_scale, img, D.ny, i, j, W[r] * Fx[a] * Fy[bb]);
+                        splat_add(use_tile, mytile, tw, ilo, jlo, D.fx_scale, img, D.ny, i, j, W[r] * Fx[a] * Fy[bb]);
                     }
                 }
             }
@@ -900,7 +906,8 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
         if (use_tile) {
             __syncthreads();
             for (int i = threadIdx.x; i < area; i += WG) {
-                const unsigned long long q = tile[i];
+                unsigned long long q = tile[i];
+                for (int c = 1; c < ncopy; ++c) q += tile[c * area + i];
                 const int ti = i / tw;
                 if (q != 0ull)
                     __hip_atomic_fetch_add(&img[(int64_t)(ilo + ti) * D.ny + jlo + (i - ti * tw)], q,
