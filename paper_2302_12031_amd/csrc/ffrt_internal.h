@@ -8,7 +8,7 @@
 namespace ffrt {
 
 constexpr int WG = 256;               // threads per workgroup: 4 wave64s
-constexpr int TILE_CAP = 3072;        // int64 fixed-point pixels in the LDS irradiance tile of the forward kernel
+constexpr int TILE_CAP = 6144;        // 32-bit fixed-point pixels in the LDS irradiance tile of the forward kernel
 constexpr int MAX_DEG = 5;
 constexpr int N_SHAPES = 5;           // block shapes: rays per thread 1, 2, 4, 8, 16
 constexpr int RPT_OF_SHAPE[N_SHAPES] = {1, 2, 4, 8, 16};

@@ -690,18 +690,23 @@ __device__ BoundsDev stage_design(const TraceArgs& A, const DesignDev& D, int d,
 // ------------------------------------------------------------------------------------------------
 // Forward kernel
 // ------------------------------------------------------------------------------------------------
-// Add a pixel contribution v >= 0, as the 64-bit fixed-point integer rint(v scale), either to the
-// workgroup's LDS tile or, when the block's footprint does not fit the tile, directly to the device image.
-// Integer LDS atomics are far cheaper than float ones on gfx950, and integer sums do not depend on the
-// order of the additions, so the irradiance is reproducible bit for bit.
-__device__ __forceinline__ void splat_add(bool to_tile, unsigned long long* tile, int tile_ld, int ilo, int jlo,
-                                          float scale, unsigned long long* img, int ny, int i, int j, float v) {
-    const unsigned long long q = (unsigned long long)(long long)__float2int_rn(v * scale);
-    if (to_tile)
+// Add a pixel contribution v >= 0 in fixed point, either to the workgroup's LDS tile or, when the block's
+// footprint does not fit the tile, directly to the device image.  The image unit is 1 / scale (2^-26 w0,
+// 64-bit); the tile unit is 2^TSH image units (32-bit), chosen so that a workgroup's sum for one pixel stays
+// below 2^31.  Integer LDS atomics are far cheaper than float ones on gfx950 (and 32-bit ones cheaper than
+// 64-bit ones when lanes collide), and integer sums do not depend on the order of the additions, so the
+// irradiance is reproducible bit for bit.
+template <int TSH>
+__device__ __forceinline__ void splat_add(bool to_tile, uint32_t* tile, int tile_ld, int ilo, int jlo, float scale,
+                                          unsigned long long* img, int ny, int i, int j, float v) {
+    if (to_tile) {
+        const uint32_t q = (uint32_t)__float2int_rn(v * (scale * (1.0f / (float)(1 << TSH))));
         __hip_atomic_fetch_add(&tile[(i - ilo) * tile_ld + (j - jlo)], q, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
-    else
+    } else {
+        const unsigned long long q = (unsigned long long)(long long)__float2int_rn(v * scale);
         __hip_atomic_fetch_add(&img[(int64_t)i * ny + j], q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 template <int P, int Q, int NU, int SHAPE, int KIND>
@@ -709,6 +714,8 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
     constexpr int MU = shape_mu(SHAPE), MV = shape_mv(SHAPE), RPT = MU * MV;
     constexpr int BU = 16 * MU, BV = 16 * MV;
     constexpr int H = (NU - 1) / 2;
+    // tile unit 2^TSH image units: 256 RPT rays of at most 2^26 units each then sum to at most 2^30 per pixel
+    constexpr int TSH = 4 + (RPT >= 2) + (RPT >= 4) + (RPT >= 8) + (RPT >= 16);
     // per-thread accumulation window of WN x WN pixels: the filter windows of a thread's neighbouring rays
     // usually fall inside one such window, so most rays cost no atomic at all
     constexpr bool ACCUM = NU <= 5;
@@ -716,7 +723,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
     extern __shared__ float smem[];
     float* sP = smem;
     float* sK = sP + A.lds_cp;
-    unsigned long long* tile = reinterpret_cast<unsigned long long*>(sK + A.lds_kt);  // 16-byte aligned
+    uint32_t* tile = reinterpret_cast<uint32_t*>(sK + A.lds_kt);
     __shared__ int s_box[4][4];
     __shared__ float s_red[4][10];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -806,7 +813,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
         unsigned long long* img = A.img64 + D.img_off;
         bool use_tile = false;
         int ilo = 0, jlo = 0, tw = 0, area = 0, ncopy = 1;
-        unsigned long long* mytile = tile;
+        uint32_t* mytile = tile;
         if (A.use_tile) {
             int a0 = wave_min(imin), a1 = wave_max(imax), b0 = wave_min(jmin), b1 = wave_max(jmax);
             if (lane == 0) {
@@ -834,7 +841,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
                 // when it fits, each of the four lanes of a 2 x 2 patch of the wave's 8 x 8 lane grid adds to
                 // its own copy of the tile, and the flush sums the copies.
                 ncopy = 4 * area <= TILE_CAP ? 4 : 1;
-                for (int i = threadIdx.x; i < ncopy * area; i += WG) tile[i] = 0ull;
+                for (int i = threadIdx.x; i < ncopy * area; i += WG) tile[i] = 0u;
                 __syncthreads();
                 mytile = tile + (ncopy == 4 ? ((lane & 1) | ((lane >> 2) & 2)) * area : 0);
             }
@@ -861,7 +868,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
                         for (int bb = 0; bb < NU; ++bb) {
                             const float v = W[r] * Fx[a] * Fy[bb];
                             if (v != 0.0f)
-                                splat_add(use_tile, mytile, tw, ilo, jlo, D.fx_scale, img, D.ny, ai + di + a,
+                                splat_add<TSH>(use_tile, mytile, tw, ilo, jlo, D.fx_scale, img, D.ny, ai + di + a,
                                           aj + dj + bb, v);
                         }
                     }
@@ -882,7 +889,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
 #pragma unroll
             for (int k = 0; k < WN * WN; ++k)
                 if (acc[k] != 0.0f)
-                    splat_add(use_tile, mytile, tw, ilo, jlo, D.fx_scale, img, D.ny, ai + k / WN, aj + k % WN, acc[k]);
+                    splat_add<TSH>(use_tile, mytile, tw, ilo, jlo, D.fx_scale, img, D.ny, ai + k / WN, aj + k % WN, acc[k]);
         } else {
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
@@ -898,7 +905,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
                     for (int bb = 0; bb < NU; ++bb) {
                         int j = j0 + bb - H;
                         if (j < 0 || j >= D.ny) continue;
-                        splat_add(use_tile, mytile, tw, ilo, jlo, D.fx_scale, img, D.ny, i, j, W[r] * Fx[a] * Fy[bb]);
+                        splat_add<TSH>(use_tile, mytile, tw, ilo, jlo, D.fx_scale, img, D.ny, i, j, W[r] * Fx[a] * Fy[bb]);
                     }
                 }
             }
@@ -908,6 +915,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
             for (int i = threadIdx.x; i < area; i += WG) {
                 unsigned long long q = tile[i];
                 for (int c = 1; c < ncopy; ++c) q += tile[c * area + i];
+                q <<= TSH;
                 const int ti = i / tw;
                 if (q != 0ull)
                     __hip_atomic_fetch_add(&img[(int64_t)(ilo + ti) * D.ny + jlo + (i - ti * tw)], q,
@@ -946,7 +954,7 @@ __device__ void adjoint_flush(const TraceArgs& A, int d, const float* sG) {
 }
 
 template <int P, int Q, int NU, int KIND>
-__global__ __launch_bounds__(WG) void k_adjoint(TraceArgs A, int shape) {
+__device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
     constexpr int NT = (P + 1) * (Q + 1);
     constexpr int NV = NT <= 16 ? 16 : (NT <= 32 ? 32 : 64);
     constexpr int LOG_NV = NV == 16 ? 4 : (NV == 32 ? 5 : 6);
@@ -1039,6 +1047,18 @@ __global__ __launch_bounds__(WG) void k_adjoint(TraceArgs A, int shape) {
     if (cur >= 0) adjoint_flush(A, cur, sG);
 }
 
+template <int P, int Q, int NU, int KIND>
+__global__ __launch_bounds__(WG) void k_adjoint(TraceArgs A, int shape) {
+    adjoint_body<P, Q, NU, KIND>(A, shape);
+}
+
+// The same with at least three waves per SIMD, for the instances where that costs (almost) no spill: the
+// bicubic, nu = 3 point-source adjoint would otherwise take ~190 VGPRs (two waves) and stall on latency.
+template <int P, int Q, int NU, int KIND>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void k_adjoint_w3(TraceArgs A, int shape) {
+    adjoint_body<P, Q, NU, KIND>(A, shape);
+}
+
 // ------------------------------------------------------------------------------------------------
 // Individual rays (inspection)
 // ------------------------------------------------------------------------------------------------
@@ -1082,7 +1102,7 @@ template <int P, int Q, int NU>
 struct KernelsFor {
     template <int SHAPE>
     static hipError_t fwd_shape(const TraceArgs& A, int grid, hipStream_t s) {
-        size_t lds = trace_lds_bytes(A, A.use_tile ? 2 * TILE_CAP : 0);
+        size_t lds = trace_lds_bytes(A, A.use_tile ? TILE_CAP : 0);
         if (A.kind_group == 0) hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 0>), dim3(grid), dim3(WG), lds, s, A);
         else hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 1>), dim3(grid), dim3(WG), lds, s, A);
         return hipGetLastError();
@@ -1098,8 +1118,13 @@ struct KernelsFor {
     }
     static hipError_t adjoint(const TraceArgs& A, int shape, int grid, hipStream_t s) {
         size_t lds = trace_lds_bytes(A, A.lds_cp);
-        if (A.kind_group == 0) hipLaunchKernelGGL((k_adjoint<P, Q, NU, 0>), dim3(grid), dim3(WG), lds, s, A, shape);
-        else hipLaunchKernelGGL((k_adjoint<P, Q, NU, 1>), dim3(grid), dim3(WG), lds, s, A, shape);
+        constexpr bool cap = P == 3 && Q == 3 && NU == 3;
+        if (A.kind_group == 0)
+            hipLaunchKernelGGL((k_adjoint<P, Q, NU, 0>), dim3(grid), dim3(WG), lds, s, A, shape);
+        else if constexpr (cap)
+            hipLaunchKernelGGL((k_adjoint_w3<P, Q, NU, 1>), dim3(grid), dim3(WG), lds, s, A, shape);
+        else
+            hipLaunchKernelGGL((k_adjoint<P, Q, NU, 1>), dim3(grid), dim3(WG), lds, s, A, shape);
         return hipGetLastError();
     }
     static hipError_t trace_rays(const TraceArgs& A, int design, const int64_t* ids, int64_t n, float* out8,
