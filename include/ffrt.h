@@ -124,8 +124,8 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
 ffrt_status ffrt_plan_destroy(ffrt_plan* plan);
 
 /* Device workspace bytes the plan needs: design descriptors, knot tables, bounds, loss flags and partial
- * sums, and the accumulators of the trace kernels (a 64-bit fixed-point irradiance image and a gradient
- * buffer, each kept at zero between calls). */
+ * sums, a dL/dI buffer for steps, and the accumulators of the trace kernels (a 64-bit fixed-point
+ * irradiance image and a gradient buffer, each kept at zero between calls). */
 ffrt_status ffrt_plan_workspace_size(const ffrt_plan* plan, size_t* bytes);
 
 /* Hand over caller-allocated device workspace (>= the size above, 256-byte aligned) on the current
@@ -166,10 +166,9 @@ ffrt_status ffrt_adjoint(ffrt_plan* plan, const float* Pz, const float* dL_dI, f
 ffrt_status ffrt_adam(ffrt_plan* plan, float* Pz, const float* dL_dP, float* m, float* v, int32_t* t,
                       const ffrt_adam_hparams* hp, void* stream);
 
-/* One optimisation step: forward, loss, adjoint, Adam (all device-side, no host synchronisation; three
- * kernels).  irr, loss, dL_dP, stats (if not NULL) receive the step's values before the update; Pz, m, v,
- * t are updated.  dL_dI may be NULL: the adjoint then forms dL/dI from irr, target and the loss on the fly
- * instead of writing and reading it back (one kernel fewer). */
+/* One optimisation step: forward, loss, adjoint, Adam (all device-side, no host synchronisation).  irr,
+ * loss, dL_dI, dL_dP and stats (if not NULL) receive the step's values before the update; Pz, m, v, t are
+ * updated.  dL_dI may be NULL, in which case dL/dI is kept in the plan's workspace. */
 ffrt_status ffrt_step(ffrt_plan* plan, float* Pz, const float* target, float* irr, float* loss,
                       float* dL_dI, float* dL_dP, float* m, float* v, int32_t* t, ffrt_stats* stats,
                       const ffrt_adam_hparams* hp, void* stream);

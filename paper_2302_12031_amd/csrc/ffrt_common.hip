@@ -212,23 +212,11 @@ __global__ __launch_bounds__(256) void k_loss_grad(const DesignDev* designs, int
 }
 
 // One workgroup per design after the adjoint: dL/dP from the accumulator (which is cleared for the next
-// adjoint), the loss value and validity flag (from the slice sums, when lpart is given) and Adam.
+// adjoint) and, when asked, Adam for the designs whose loss found flux.
 __global__ __launch_bounds__(256) void k_finish(const DesignDev* designs, float* gacc, float* dLdP,
-                                                const double* lpart, int LB, float* loss, int32_t* valid,
-                                                AdamArgs adam) {
+                                                const int32_t* valid, AdamArgs adam) {
     const int d = blockIdx.x;
     const DesignDev& D = designs[d];
-    int ok = 1;
-    if (lpart) {
-        const LossOut R = loss_from_partials(lpart, d, LB, D);
-        ok = R.valid;
-        if (threadIdx.x == 0) {
-            loss[d] = R.loss;
-            valid[d] = R.valid;
-        }
-    } else if (valid) {
-        ok = valid[d];
-    }
     float* acc = gacc + D.cp_off;
     float* out = dLdP + D.cp_off;
     auto take = [acc, out](int i) {
@@ -238,7 +226,7 @@ __global__ __launch_bounds__(256) void k_finish(const DesignDev* designs, float*
         return g;
     };
     const int ncp = D.n_u * D.n_v;
-    if (adam.Pz && ok) {
+    if (adam.Pz && (!valid || valid[d])) {
         adam_update(adam.Pz, adam.m, adam.v, adam.t + d, D.cp_off, ncp, adam.hp, take);
     } else {
         for (int i = threadIdx.x; i < ncp; i += blockDim.x) take(i);
@@ -313,15 +301,14 @@ hipError_t launch_loss(const DesignDev* designs, int n_designs, int LB, unsigned
                        float* loss, float* dLdI, int32_t* valid, hipStream_t s) {
     hipLaunchKernelGGL(k_loss_sums, dim3(n_designs * LB), dim3(256), 0, s, designs, LB, img64, irr, target, Pz, slots,
                        stats, partial);
-    if (dLdI)
-        hipLaunchKernelGGL(k_loss_grad, dim3(n_designs * LB), dim3(256), 0, s, designs, LB, irr, target, partial, loss,
+    hipLaunchKernelGGL(k_loss_grad, dim3(n_designs * LB), dim3(256), 0, s, designs, LB, irr, target, partial, loss,
                            valid, dLdI);
     return hipGetLastError();
 }
 
-hipError_t launch_finish(const DesignDev* designs, int n_designs, float* gacc, float* dLdP, const double* lpart,
-                         int LB, float* loss, int32_t* valid, const AdamArgs& adam, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish, dim3(n_designs), dim3(256), 0, s, designs, gacc, dLdP, lpart, LB, loss, valid, adam);
+hipError_t launch_finish(const DesignDev* designs, int n_designs, float* gacc, float* dLdP, const int32_t* valid,
+                         const AdamArgs& adam, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(n_designs), dim3(256), 0, s, designs, gacc, dLdP, valid, adam);
     return hipGetLastError();
 }
 

@@ -94,12 +94,7 @@ struct TraceArgs {
     const float* Pz;
     unsigned long long* img64;       // forward: fixed-point irradiance accumulator (zero on entry)
     ffrt_stats* slots;               // forward: NSLOT partial-statistics slots per design (may be null)
-    // adjoint: dL/dI from the array dLdI, or (dLdI null) from irr, target and the loss's slice sums
-    const float* dLdI;
-    const float* irr;
-    const float* target;
-    const double* lpart;
-    int32_t loss_lb;
+    const float* dLdI;               // adjoint input
     float* gacc;                     // adjoint: gradient accumulator (zero on entry; launch_finish clears it)
     int32_t use_tile;                // forward: LDS footprint tile
     int32_t butterfly;               // adjoint: wave-level reduce-scatter of control-point gradients
@@ -150,16 +145,14 @@ int loss_blocks_per_design(int64_t max_pixels);
 hipError_t launch_resolve(const DesignDev* designs, int n_designs, int LB, unsigned long long* img64, float* irr,
                           const float* Pz, ffrt_stats* slots, ffrt_stats* stats, hipStream_t s);
 // Slice sums of the loss into partial (n_designs * LB * 5 doubles), resolving the irradiance from img64
-// first when img64 is not null (as launch_resolve, statistics included).  With dLdI not null a second kernel
-// writes dL/dI, loss and valid; otherwise the adjoint forms them from partial.
+// first when img64 is not null (as launch_resolve, statistics included); then dL/dI, loss and valid.
 hipError_t launch_loss(const DesignDev* designs, int n_designs, int LB, unsigned long long* img64, float* irr,
                        const float* target, const float* Pz, ffrt_stats* slots, ffrt_stats* stats, double* partial,
                        float* loss, float* dLdI, int32_t* valid, hipStream_t s);
-// After the adjoint: dL/dP = gacc, gacc cleared; with lpart not null the loss value and validity flag are
-// formed from the slice sums and stored, otherwise valid is read; with adam.Pz set, Adam updates the
-// designs whose loss found flux.
-hipError_t launch_finish(const DesignDev* designs, int n_designs, float* gacc, float* dLdP, const double* lpart,
-                         int LB, float* loss, int32_t* valid, const AdamArgs& adam, hipStream_t s);
+// After the adjoint: dL/dP = gacc, gacc cleared; with adam.Pz set, Adam updates the designs whose loss
+// found flux (valid).
+hipError_t launch_finish(const DesignDev* designs, int n_designs, float* gacc, float* dLdP, const int32_t* valid,
+                         const AdamArgs& adam, hipStream_t s);
 hipError_t launch_loss_f64(const DesignDev* designs, int n_designs, const float* irr, const float* target,
                            double* loss, hipStream_t s);
 hipError_t launch_adam(const DesignDev* designs, int n_designs, float* Pz, const float* g, float* m,

@@ -75,7 +75,7 @@ struct ffrt_plan {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     size_t off_designs = 0, off_bounds = 0, off_valid = 0, off_knots = 0, off_bmap = 0, off_slots = 0, need = 0;
-    size_t off_lpart = 0, off_img64 = 0, off_gacc = 0;
+    size_t off_lpart = 0, off_img64 = 0, off_gacc = 0, off_dldi = 0;
     int num_cu = 256;
     int fwd_cfg = 0, adj_cfg = 0;
     hipGraph_t graph = nullptr;
@@ -92,6 +92,7 @@ struct ffrt_plan {
     double* d_lpart() const { return reinterpret_cast<double*>(ws + off_lpart); }
     unsigned long long* d_img64() const { return reinterpret_cast<unsigned long long*>(ws + off_img64); }
     float* d_gacc() const { return reinterpret_cast<float*>(ws + off_gacc); }
+    float* d_dldi() const { return reinterpret_cast<float*>(ws + off_dldi); }
 };
 
 namespace {
@@ -270,19 +271,13 @@ ffrt_status launch_forward(ffrt_plan* pl, const float* Pz, bool stats, hipStream
 }
 
 // The adjoint trace kernel, into the plan's gradient accumulator (launch_finish turns it into dL/dP).
-// dL/dI comes from dLdI, or, when dLdI is null, from irr, target and the slice sums of the last loss.
-ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, const float* irr,
-                           const float* target, hipStream_t s) {
+ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hipStream_t s) {
     const AdjCfg& c = ADJ_CFGS[pl->adj_cfg];
     for (int kg = 0; kg < 2; ++kg) {
         if (pl->nblocks[c.shape][kg] == 0) continue;
         TraceArgs A = make_args(pl, c.shape, kg);
         A.Pz = Pz;
         A.dLdI = dLdI;
-        A.irr = irr;
-        A.target = target;
-        A.lpart = pl->d_lpart();
-        A.loss_lb = pl->loss_lb;
         A.gacc = pl->d_gacc();
         A.butterfly = c.butterfly;
         HIP_TRY(pl->ks->adjoint(A, c.shape, grid_for(pl, c.shape, kg, c.persistent), s));
@@ -312,35 +307,32 @@ ffrt_status run_forward(ffrt_plan* pl, const float* Pz, float* irr, ffrt_stats* 
 
 ffrt_status run_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, float* dLdP, hipStream_t s) {
     if (ffrt_status b = run_bounds(pl, Pz, s)) return b;
-    if (ffrt_status a = launch_adjoint(pl, Pz, dLdI, nullptr, nullptr, s)) return a;
-    HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), dLdP, nullptr, pl->loss_lb, nullptr, nullptr,
-                          no_adam(), s));
+    if (ffrt_status a = launch_adjoint(pl, Pz, dLdI, s)) return a;
+    HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), dLdP, nullptr, no_adam(), s));
     return FFRT_OK;
 }
 
-// One optimisation step in four kernels (five with point or grid sources: their bounds of sec. 2.2.2
-// first): forward, loss slice sums (resolving the irradiance, statistics), adjoint (dL/dI formed on the
-// fly), finish (dL/dP, loss value, Adam).  With dLdI set, dL/dI is also written out (one more kernel) and
-// read back.
+// One optimisation step in five kernels (six with point or grid sources: their bounds of sec. 2.2.2 first):
+// forward, loss slice sums (resolving the irradiance, statistics), dL/dI (plus loss and validity), adjoint,
+// finish (dL/dP and Adam).  dL/dI goes to the plan's workspace when the caller passes no buffer for it.
 ffrt_status run_step(ffrt_plan* pl, float* Pz, const float* target, float* irr, float* loss, float* dLdI,
                      float* dLdP, float* m, float* v, int32_t* t, ffrt_stats* stats, const ffrt_adam_hparams& hp,
                      hipStream_t s) {
+    if (!dLdI) dLdI = pl->d_dldi();
     if (ffrt_status b = run_bounds(pl, Pz, s)) return b;
     ffrt_status st = launch_forward(pl, Pz, stats != nullptr, s);
     if (st) return st;
     HIP_TRY(launch_loss(pl->d_designs(), pl->nd, pl->loss_lb, pl->d_img64(), irr, target, Pz, pl->d_slots(), stats,
                         pl->d_lpart(), loss, dLdI, pl->d_valid(), s));
+    st = launch_adjoint(pl, Pz, dLdI, s);
+    if (st) return st;
     AdamArgs adam;
     adam.Pz = Pz;
     adam.m = m;
     adam.v = v;
     adam.t = t;
     adam.hp = hp;
-    st = launch_adjoint(pl, Pz, dLdI, irr, target, s);
-    if (st) return st;
-    // with dLdI written, the dL/dI kernel already stored loss and valid
-    HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), dLdP, dLdI ? nullptr : pl->d_lpart(), pl->loss_lb,
-                          loss, pl->d_valid(), adam, s));
+    HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), dLdP, pl->d_valid(), adam, s));
     return FFRT_OK;
 }
 
@@ -449,6 +441,8 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
     off = align256(off + sizeof(unsigned long long) * (size_t)pl->total_img);
     pl->off_gacc = off;
     off = align256(off + sizeof(float) * (size_t)pl->total_cp);
+    pl->off_dldi = off;  // dL/dI of a step whose caller does not want it
+    off = align256(off + sizeof(float) * (size_t)pl->total_img);
     pl->need = off;
     *out = pl;
     return FFRT_OK;
@@ -674,7 +668,7 @@ ffrt_status ffrt_plan_time_kernels(ffrt_plan* plan, const float* Pz, float* irr,
     if (!st && e == hipSuccess) e = hipEventRecord(ev[1], s);
     if (!st && e == hipSuccess) e = hipEventRecord(ev[2], s);
     for (int r = 0; r < reps && !st && e == hipSuccess; ++r)
-        st = launch_adjoint(plan, Pz, dL_dI, nullptr, nullptr, s);
+        st = launch_adjoint(plan, Pz, dL_dI, s);
     if (!st && e == hipSuccess) e = hipEventRecord(ev[3], s);
     if (!st && e == hipSuccess) e = hipEventSynchronize(ev[3]);
     // the timed launches accumulated into the fixed-point image and the gradient accumulator without

@@ -1,4 +1,4 @@
-// Loss of sec. 2.5 from per-slice sums, evaluated by one wave (shared by the dL/dI and adjoint kernels).
+// Loss of sec. 2.5 from per-slice sums, evaluated by one wave in every workgroup of the dL/dI kernel.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -21,7 +21,7 @@ struct LossOut {
 // ||D||^2 = A / s^2 - 2 B / (s s_T) + C / s_T^2 and sum(D I_hat) = A / s^2 - B / (s s_T) from the slice sums
 // (A = sum I^2, B = sum I T, C = sum T^2), which in double precision lose nothing that matters to the float
 // results.  The LB <= 64 slices are added by a butterfly over the wave, so every lane of every wave that
-// calls this gets the same bits.  Call with a full wave.
+// calls this gets the same bits (no workgroup has to wait for another).  Call with a full wave.
 __device__ inline LossOut loss_from_partials(const double* partial, int d, int LB, const DesignDev& D) {
     const int lane = threadIdx.x & 63;
     double q[LOSS_Q];

@@ -17,7 +17,6 @@
 #include <stdint.h>
 
 #include "ffrt_internal.h"
-#include "loss.hpp"
 #include "wave.hpp"
 
 namespace ffrt {
@@ -522,21 +521,9 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
 // One ray, adjoint: re-trace, gather dL/dI over the filter window, reverse sweep.  Returns false when the
 // ray does not reach the screen.  g[] receives dL/dP for control point (ku + a, kv + b) at a * (Q+1) + b.
 // ------------------------------------------------------------------------------------------------
-// dL/dI of one design: read from an array, or formed from the irradiance, the target and the loss scalars.
-struct GradSrc {
-    const float* G;  // null: ((I is - T isT) - dot) coef
-    const float* I;
-    const float* T;
-    LossScalars L;
-    __device__ __forceinline__ float at(int64_t k) const {
-        if (G) return G[k];
-        return ((I[k] * L.is - T[k] * L.isT) - L.dot) * L.coef;
-    }
-};
-
 template <int P, int Q, int NU, int KIND>
 __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDev& B, const float* sP,
-                                              const float* sKu, const float* sKv, const GradSrc& G,
+                                              const float* sKu, const float* sKv, const float* __restrict__ G,
                                               int e, int ku, int kv, int64_t id, int& cku, int& ckv,
                                               float* g) {
     RayIn r = ray_entry<KIND>(D, e, ku, kv, id);
@@ -573,7 +560,7 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
 #pragma unroll
         for (int b = 0; b < NU; ++b) {
             int j = min(max(j0 + b - H, 0), D.ny - 1);
-            float Gij = G.at((int64_t)i * D.ny + j);
+            float Gij = G[(int64_t)i * D.ny + j];
             gb += Gij * Fy[b];
             gbp += Gij * dFy[b];
         }
@@ -968,7 +955,6 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
     const int mv_shift = MV == 1 ? 0 : (MV == 2 ? 1 : 2);
     int cur = -1;
     BoundsDev B;
-    GradSrc G;
     for (int64_t pb = blockIdx.x; pb < A.n_blocks; pb += gridDim.x) {
         const int64_t b = xcd_remap(pb, A.n_blocks);
         const int d = find_design(A.bmap, A.n_designs, b);
@@ -980,17 +966,9 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
             __syncthreads();
             for (int i = threadIdx.x; i < D.n_u * D.n_v; i += WG) sG[i] = 0.0f;
             B = stage_design(A, D, d, sP, sK, P, Q, KIND != 0);
-            if (A.dLdI) {
-                G.G = A.dLdI + D.img_off;
-            } else {
-                // every wave forms the loss from the slice sums (same bits in every wave and workgroup)
-                G.G = nullptr;
-                G.I = A.irr + D.img_off;
-                G.T = A.target + D.img_off;
-                G.L = loss_from_partials(A.lpart, d, A.loss_lb, D).L;
-            }
             cur = d;
         }
+        const float* G = A.dLdI + D.img_off;
         const float* sKu = sK;
         const float* sKv = sK + D.nsu * kt_stride(P);
         int e = (int)(local / bm.per_emitter);

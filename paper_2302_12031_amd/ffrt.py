@@ -282,8 +282,8 @@ class Plan:
                                _stream(stream)), "ffrt_adam")
 
     def new_state(self, Pz, with_dLdI=False):
-        """Buffers of an optimisation loop for control heights Pz (packed).  Without with_dLdI the step does
-        not write dL/dI out (the adjoint forms it on the fly), which saves a kernel per step."""
+        """Buffers of an optimisation loop for control heights Pz (packed).  Without with_dLdI the step keeps
+        dL/dI in the plan's workspace."""
         dev = self.device
         return dict(
             Pz=Pz, irr=torch.zeros(self.total_img, device=dev), loss=torch.zeros(self.n_designs, device=dev),
