@@ -79,11 +79,39 @@ __device__ inline double block_sum_f64(double v, double* sh) {
 // middle, and slope bounds from the derivative control points p (P_{i+1,j} - P_{i,j}) / (u_{i+p+1} - u_{i+1})
 // (the textbook derivative of a B-spline; knot units, so d(ubar)/dx = sxu converts them to mm).
 __global__ __launch_bounds__(256) void k_bounds(const DesignDev* designs, const float* __restrict__ Pz, int p, int q,
-                                                BoundsDev* bounds) {
+                                                BoundsDev* bounds, SpanBounds* span_bounds) {
     __shared__ float s_b[4][4];
     const int d = blockIdx.x;
     const DesignDev& D = designs[d];
     const float* P = Pz + D.cp_off;
+    // per span product (su, sv): control points su..su+p x sv..sv+q; derivative control points along u are
+    // i = su..su+p-1 (times the factor of their knot interval), along v likewise
+    SpanBounds* sb = span_bounds + D.sb_off;
+    for (int s = threadIdx.x; s < D.nsu * D.nsv; s += blockDim.x) {
+        const int su = s / D.nsv, sv = s - (s / D.nsv) * D.nsv;
+        float lo = INFINITY, hi = -INFINITY, gu = 0.0f, gv = 0.0f;
+        for (int a = 0; a <= p; ++a) {
+            const int i = su + a;
+            const float fu = a < p ? (float)p / (float)(min(i + 1, D.nsu) - max(i + 1 - p, 0)) : 0.0f;
+            for (int b = 0; b <= q; ++b) {
+                const int j = sv + b;
+                const float z = P[i * D.n_v + j];
+                lo = fminf(lo, z);
+                hi = fmaxf(hi, z);
+                if (a < p) gu = fmaxf(gu, fabsf(fu * (P[(i + 1) * D.n_v + j] - z)));
+                if (b < q) {
+                    const float fv = (float)q / (float)(min(j + 1, D.nsv) - max(j + 1 - q, 0));
+                    gv = fmaxf(gv, fabsf(fv * (P[i * D.n_v + j + 1] - z)));
+                }
+            }
+        }
+        SpanBounds r;
+        r.zmin = lo;
+        r.zmax = hi;
+        r.gx = gu * D.sxu * 1.0001f;
+        r.gy = gv * D.syv * 1.0001f;
+        sb[s] = r;
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     float lo = INFINITY, hi = -INFINITY, gu = 0.0f, gv = 0.0f;
     for (int i = wave; i < D.n_u; i += 4) {  // row i by wave, columns by lane
@@ -281,8 +309,8 @@ __global__ void k_rng(uint64_t state0, uint64_t first, int64_t n, uint64_t* out)
 uint64_t splitmix_state0(uint64_t seed, uint64_t stream_id) { return mix64(seed + stream_id * GAMMA); }
 
 hipError_t launch_bounds(const DesignDev* designs, int n_designs, const float* Pz, int p, int q, BoundsDev* bounds,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_bounds, dim3(n_designs), dim3(256), 0, s, designs, Pz, p, q, bounds);
+                         SpanBounds* span_bounds, hipStream_t s) {
+    hipLaunchKernelGGL(k_bounds, dim3(n_designs), dim3(256), 0, s, designs, Pz, p, q, bounds, span_bounds);
     return hipGetLastError();
 }
 

@@ -53,6 +53,7 @@ struct DesignDev {
     // integer rint(v fx_scale), fx_scale = 2^26 / w0, so that one addend stays below 2^31 and a workgroup's
     // sum for one pixel (at most 2^11 rays) below 2^37.
     float fx_scale, fx_unscale;
+    int32_t sb_off, sb_pad_;         // first record of the design's span bounds (workspace)
 };
 
 // Per-design bounds of sec. 2.2.2 (global convex-hull box and slope bounds), formed by launch_bounds before
@@ -60,6 +61,13 @@ struct DesignDev {
 struct BoundsDev {
     float zmin, zmax, gx, gy;        // gx, gy: bounds of |dh/dx|, |dh/dy| from derivative control points
     float zref;                      // reference height subtracted from P^z in LDS
+};
+
+// The same bounds for one knot-span product (su, sv) of a design, record su * nsv + sv: the surface over
+// that span lies in [zmin, zmax] and its slopes within gx, gy (convex hull of the span's control points and
+// of its derivative control points).
+struct SpanBounds {
+    float zmin, zmax, gx, gy;
 };
 
 // Block map of one design for one block shape.
@@ -85,6 +93,8 @@ struct AdamArgs {
 struct TraceArgs {
     const DesignDev* designs;
     const BoundsDev* bounds;         // of the current Pz, for point and grid sources
+    const SpanBounds* span_bounds;   // per span product, for point and grid sources
+    int32_t lds_sb;                  // floats of the LDS span-bounds table (0: use the global bounds only)
     const float* knots;
     const BlockMap* bmap;            // n_designs entries for the launch's block shape
     int32_t n_designs;
@@ -135,9 +145,9 @@ struct KernelSet {
 const KernelSet* kernel_set(int P, int Q, int NU);
 
 // Kernels that do not depend on the degrees (ffrt_common.hip).
-// Bounds of sec. 2.2.2 of every design from Pz (one workgroup per design).
+// Bounds of sec. 2.2.2 of every design from Pz, globally and per span product (one workgroup per design).
 hipError_t launch_bounds(const DesignDev* designs, int n_designs, const float* Pz, int p, int q, BoundsDev* bounds,
-                         hipStream_t s);
+                         SpanBounds* span_bounds, hipStream_t s);
 // Image slices: LB = loss_blocks_per_design(largest image) workgroups per design, LB <= 64.
 int loss_blocks_per_design(int64_t max_pixels);
 // img64 -> irr (float), img64 cleared.  With stats, the partial-statistics slots are summed into stats and

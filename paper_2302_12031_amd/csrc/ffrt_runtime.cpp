@@ -64,7 +64,8 @@ struct ffrt_plan {
     std::vector<DesignDev> dd;
     std::vector<int64_t> cp_off, img_off;
     int64_t total_cp = 0, total_img = 0, total_rays = 0;
-    int max_cp = 0, max_kt = 0, loss_lb = 1;
+    int max_cp = 0, max_kt = 0, loss_lb = 1, max_spans = 0;
+    int64_t total_spans = 0;
     bool has_point = false;  // some design needs the root search (bounds kernel)
     int64_t max_img = 0;
     std::vector<float> knots;
@@ -74,7 +75,7 @@ struct ffrt_plan {
     // workspace
     char* ws = nullptr;
     size_t ws_bytes = 0;
-    size_t off_designs = 0, off_bounds = 0, off_valid = 0, off_knots = 0, off_bmap = 0, off_slots = 0, need = 0;
+    size_t off_designs = 0, off_bounds = 0, off_sb = 0, off_valid = 0, off_knots = 0, off_bmap = 0, off_slots = 0, need = 0;
     size_t off_lpart = 0, off_img64 = 0, off_gacc = 0, off_dldi = 0;
     int num_cu = 256;
     int fwd_cfg = 0, adj_cfg = 0;
@@ -83,6 +84,7 @@ struct ffrt_plan {
 
     DesignDev* d_designs() const { return reinterpret_cast<DesignDev*>(ws + off_designs); }
     BoundsDev* d_bounds() const { return reinterpret_cast<BoundsDev*>(ws + off_bounds); }
+    SpanBounds* d_sb() const { return reinterpret_cast<SpanBounds*>(ws + off_sb); }
     int32_t* d_valid() const { return reinterpret_cast<int32_t*>(ws + off_valid); }
     float* d_knots() const { return reinterpret_cast<float*>(ws + off_knots); }
     BlockMap* d_bmap(int shape, int kg) const {
@@ -235,6 +237,7 @@ TraceArgs make_args(ffrt_plan* pl, int shape, int kg) {
     std::memset(&A, 0, sizeof A);
     A.designs = pl->d_designs();
     A.bounds = pl->d_bounds();
+    A.span_bounds = pl->d_sb();
     A.knots = pl->d_knots();
     A.bmap = pl->d_bmap(shape, kg);
     A.n_designs = pl->nd;
@@ -242,6 +245,9 @@ TraceArgs make_args(ffrt_plan* pl, int shape, int kg) {
     A.kind_group = kg;
     A.lds_cp = (pl->max_cp + 3) / 4 * 4;
     A.lds_kt = (pl->max_kt + 3) / 4 * 4;
+    // point sources stage the span bounds too, when the kernels' LDS then stays within 64 KiB
+    const int sb = 4 * pl->max_spans;
+    if (kg == 1 && 4 * (A.lds_cp + A.lds_kt + sb + std::max(TILE_CAP, A.lds_cp)) <= 65536) A.lds_sb = sb;
     return A;
 }
 
@@ -293,7 +299,8 @@ AdamArgs no_adam() {
 
 // Bounds of sec. 2.2.2 for the current Pz (only plans with point or grid sources use them).
 ffrt_status run_bounds(ffrt_plan* pl, const float* Pz, hipStream_t s) {
-    if (pl->has_point) HIP_TRY(launch_bounds(pl->d_designs(), pl->nd, Pz, pl->P, pl->Q, pl->d_bounds(), s));
+    if (pl->has_point)
+        HIP_TRY(launch_bounds(pl->d_designs(), pl->nd, Pz, pl->P, pl->Q, pl->d_bounds(), pl->d_sb(), s));
     return FFRT_OK;
 }
 
@@ -389,6 +396,9 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
         int kt_v = (int)pl->knots.size();
         build_knot_table(pr.lens.q, pr.lens.n_v - pr.lens.q, pl->knots);
         DesignDev d = make_design(pr, cp, img, kt_u, kt_v);
+        d.sb_off = (int32_t)pl->total_spans;
+        pl->total_spans += (int64_t)d.nsu * d.nsv;
+        pl->max_spans = std::max(pl->max_spans, d.nsu * d.nsv);
         pl->dd.push_back(d);
         pl->cp_off.push_back(cp);
         pl->img_off.push_back(img);
@@ -426,6 +436,8 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
     off = align256(off + sizeof(DesignDev) * n_designs);
     pl->off_bounds = off;
     off = align256(off + sizeof(BoundsDev) * n_designs);
+    pl->off_sb = off;
+    off = align256(off + sizeof(SpanBounds) * (size_t)pl->total_spans);
     pl->off_valid = off;
     off = align256(off + sizeof(int32_t) * n_designs);
     pl->off_knots = off;
@@ -695,7 +707,7 @@ ffrt_status ffrt_trace_rays(ffrt_plan* plan, int32_t design, const float* Pz, co
         return fail(FFRT_E_ARG, "bad argument");
     hipStream_t s = (hipStream_t)stream;
     if (ffrt_status b = run_bounds(plan, Pz, s)) return b;
-    TraceArgs A = make_args(plan, 0, 0);
+    TraceArgs A = make_args(plan, 0, plan->dd[design].kind != 0 ? 1 : 0);  // the forward's LDS layout
     A.Pz = Pz;
     HIP_TRY(plan->ks->trace_rays(A, design, ray_ids, n, out8, s));
     return FFRT_OK;

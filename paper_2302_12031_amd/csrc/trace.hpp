@@ -297,7 +297,7 @@ struct RootOut {
 
 template <int P, int Q>
 __device__ RootOut intersect(const DesignDev& D, const BoundsDev& B, const float* sP, const float* sKu,
-                             const float* sKv, const RayIn& r) {
+                             const float* sKv, const float* sS, const RayIn& r) {
     RootOut R;
     R.status = ST_HIT;
     R.t = 0.0f;
@@ -326,13 +326,46 @@ __device__ RootOut intersect(const DesignDev& D, const BoundsDev& B, const float
             return R;
         }
     }
-    bool mono = B.gx * fabsf(r.dx) + B.gy * fabsf(r.dy) < r.dz;
+    float gx = B.gx, gy = B.gy;
+    if (sS) {
+        // Local bounds: over [t_lo, t_end] the ray stays above the few span products its (x, y) segment
+        // crosses, so every root lies where the ray height is inside their height range, and the slope
+        // bounds of those spans alone decide monotonicity.  Signs at the narrowed ends stay known: the ray
+        // is below the surface where its height is at most their minimum and above it at their maximum.
+        const float x0 = r.ox + t_lo * r.dx, y0 = r.oy + t_lo * r.dy;
+        const float x1 = r.ox + t_end * r.dx, y1 = r.oy + t_end * r.dy;
+        const int u0 = min(max((int)floorf(x0 * D.sxu + D.ubar0), 0), D.nsu - 1);
+        const int u1 = min(max((int)floorf(x1 * D.sxu + D.ubar0), 0), D.nsu - 1);
+        const int v0 = min(max((int)floorf(y0 * D.syv + D.vbar0), 0), D.nsv - 1);
+        const int v1 = min(max((int)floorf(y1 * D.syv + D.vbar0), 0), D.nsv - 1);
+        const int ua = min(u0, u1), ub = max(u0, u1), va = min(v0, v1), vb = max(v0, v1);
+        if ((ub - ua + 1) * (vb - va + 1) <= 9) {
+            float zl = INFINITY, zh = -INFINITY, gxl = 0.0f, gyl = 0.0f;
+            for (int su = ua; su <= ub; ++su)
+                for (int sv = va; sv <= vb; ++sv) {
+                    const float* rec = sS + 4 * (su * D.nsv + sv);
+                    zl = fminf(zl, rec[0]);
+                    zh = fmaxf(zh, rec[1]);
+                    gxl = fmaxf(gxl, rec[2]);
+                    gyl = fmaxf(gyl, rec[3]);
+                }
+            const float a2 = fmaxf(a, (zl - r.oz) * inv_dz - pad), b2 = fminf(b, (zh - r.oz) * inv_dz + pad);
+            if (a2 <= b2) {
+                a = a2;
+                b = b2;
+            }
+            gx = gxl;
+            gy = gyl;
+        }
+    }
+    const float t_scan_end = b;
+    bool mono = gx * fabsf(r.dx) + gy * fabsf(r.dy) < r.dz;
     if (!mono) {
         R.nonmono = 1;
         constexpr int SCAN = 32;
         float prev = a;
         for (int s = 1; s <= SCAN; ++s) {
-            float ts = a + (t_end - a) * ((float)s * (1.0f / SCAN));
+            float ts = a + (t_scan_end - a) * ((float)s * (1.0f / SCAN));
             if (f_and_slope<P, Q>(D, sP, sKu, sKv, r, ozr, ts, fp) <= 0.0f) {
                 a = prev;
                 b = ts;
@@ -477,8 +510,8 @@ struct FwdRay {
 
 template <int P, int Q, int KIND>
 __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const BoundsDev& B, const float* sP,
-                                                const float* sKu, const float* sKv, int e, int ku, int kv,
-                                                int64_t id) {
+                                                const float* sKu, const float* sKv, const float* sS, int e, int ku,
+                                                int kv, int64_t id) {
     FwdRay o;
     o.iters = o.failed = o.nonmono = o.refined = 0;
     o.X = o.Y = o.w = o.t = o.u = o.v = 0.0f;
@@ -487,7 +520,7 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
     if (r.status != ST_HIT) return o;
     float t;
     if constexpr (KIND != 0) {
-        RootOut R = intersect<P, Q>(D, B, sP, sKu, sKv, r);
+        RootOut R = intersect<P, Q>(D, B, sP, sKu, sKv, sS, r);
         o.iters = R.iters;
         o.failed = R.failed;
         o.nonmono = R.nonmono;
@@ -523,7 +556,8 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
 // ------------------------------------------------------------------------------------------------
 template <int P, int Q, int NU, int KIND>
 __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDev& B, const float* sP,
-                                              const float* sKu, const float* sKv, const float* __restrict__ G,
+                                              const float* sKu, const float* sKv, const float* sS,
+                                              const float* __restrict__ G,
                                               int e, int ku, int kv, int64_t id, int& cku, int& ckv,
                                               float* g) {
     RayIn r = ray_entry<KIND>(D, e, ku, kv, id);
@@ -531,7 +565,7 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
     float t = 0.0f;
     constexpr bool point = KIND != 0;
     if (point) {
-        RootOut R = intersect<P, Q>(D, B, sP, sKu, sKv, r);
+        RootOut R = intersect<P, Q>(D, B, sP, sKu, sKv, sS, r);
         if (R.status != ST_HIT) return false;
         t = R.t;
     }
@@ -662,6 +696,11 @@ __device__ BoundsDev stage_design(const TraceArgs& A, const DesignDev& D, int d,
     BoundsDev B;
     if (bracket) {
         B = load_uniform(A.bounds, d);
+        if (A.lds_sb) {  // span bounds follow the knot tables
+            const float* src = reinterpret_cast<const float*>(A.span_bounds + D.sb_off);
+            float* sS = sK + A.lds_kt;
+            for (int i = threadIdx.x; i < 4 * D.nsu * D.nsv; i += WG) sS[i] = src[i];
+        }
     } else {
         B.zmin = B.zmax = B.gx = B.gy = 0.0f;
         const float zc = load_uniform(P, (D.n_u / 2) * D.n_v + D.n_v / 2);
@@ -710,7 +749,9 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
     extern __shared__ float smem[];
     float* sP = smem;
     float* sK = sP + A.lds_cp;
-    uint32_t* tile = reinterpret_cast<uint32_t*>(sK + A.lds_kt);
+    float* sS = sK + A.lds_kt;  // span bounds (point sources, when they fit)
+    uint32_t* tile = reinterpret_cast<uint32_t*>(sS + A.lds_sb);
+    const float* sSb = KIND != 0 && A.lds_sb ? sS : nullptr;
     __shared__ int s_box[4][4];
     __shared__ float s_red[4][10];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -749,7 +790,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
             Y[r] = 0.0f;
             if (ku < D.grid_u && kv < D.grid_v) {
                 int64_t id = ebase + (int64_t)ku * D.grid_v + kv;
-                FwdRay o = trace_forward<P, Q, KIND>(D, B, sP, sKu, sKv, e, ku, kv, id);
+                FwdRay o = trace_forward<P, Q, KIND>(D, B, sP, sKu, sKv, sSb, e, ku, kv, id);
                 c_tr++;
                 c_fail += o.failed;
                 c_ref += o.refined;
@@ -948,7 +989,9 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
     extern __shared__ float smem[];
     float* sP = smem;
     float* sK = sP + A.lds_cp;
-    float* sG = sK + A.lds_kt;
+    float* sS = sK + A.lds_kt;  // span bounds (point sources, when they fit)
+    float* sG = sS + A.lds_sb;
+    const float* sSb = KIND != 0 && A.lds_sb ? sS : nullptr;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int MU = shape_mu(shape), MV = shape_mv(shape), RPT = MU * MV;
     const int BU = 16 * MU, BV = 16 * MV;
@@ -988,7 +1031,7 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
             float g[NT];
             int cku = -1, ckv = -1;
             int64_t id = ebase + (int64_t)ku * D.grid_v + kv;
-            if (!trace_adjoint<P, Q, NU, KIND>(D, B, sP, sKu, sKv, G, e, ku, kv, id, cku, ckv, g)) continue;
+            if (!trace_adjoint<P, Q, NU, KIND>(D, B, sP, sKu, sKv, sSb, G, e, ku, kv, id, cku, ckv, g)) continue;
             if (aku >= 0 && (cku != aku || ckv != akv)) {
                 cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc);
 #pragma unroll
@@ -1046,6 +1089,7 @@ __global__ __launch_bounds__(WG) void k_trace_rays(TraceArgs A, int design, cons
     extern __shared__ float smem[];
     float* sP = smem;
     float* sK = sP + A.lds_cp;
+    float* sS = sK + A.lds_kt;
     const DesignDev D = load_uniform(A.designs, design);
     const BoundsDev B = stage_design(A, D, design, sP, sK, P, Q, D.kind != 0);
     int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
@@ -1056,8 +1100,9 @@ __global__ __launch_bounds__(WG) void k_trace_rays(TraceArgs A, int design, cons
     int64_t rr = id - (int64_t)e * per;
     int ku = (int)(rr / D.grid_v), kv = (int)(rr - (rr / D.grid_v) * D.grid_v);
     const float* sKv = sK + D.nsu * kt_stride(P);
-    FwdRay o = D.kind == 0 ? trace_forward<P, Q, 0>(D, B, sP, sK, sKv, e, ku, kv, id)
-                           : trace_forward<P, Q, 1>(D, B, sP, sK, sKv, e, ku, kv, id);
+    const float* sSb = A.lds_sb && D.kind != 0 ? sS : nullptr;
+    FwdRay o = D.kind == 0 ? trace_forward<P, Q, 0>(D, B, sP, sK, sKv, nullptr, e, ku, kv, id)
+                           : trace_forward<P, Q, 1>(D, B, sP, sK, sKv, sSb, e, ku, kv, id);
     float* dst = out8 + 8 * i;
     dst[0] = (float)o.status;
     dst[1] = o.X;
@@ -1073,7 +1118,7 @@ __global__ __launch_bounds__(WG) void k_trace_rays(TraceArgs A, int design, cons
 // Launchers
 // ------------------------------------------------------------------------------------------------
 inline size_t trace_lds_bytes(const TraceArgs& A, int extra_floats) {
-    return sizeof(float) * (size_t)(A.lds_cp + A.lds_kt + extra_floats);
+    return sizeof(float) * (size_t)(A.lds_cp + A.lds_kt + A.lds_sb + extra_floats);
 }
 
 template <int P, int Q, int NU>
