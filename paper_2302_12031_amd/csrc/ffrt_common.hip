@@ -22,16 +22,17 @@ __host__ __device__ inline uint64_t mix64(uint64_t z) {
     return z ^ (z >> 31);
 }
 
-// Sum the NSLOT partial-statistics slots of design d into stats[d] and clear them (a 256-thread workgroup:
-// wave w sums fields w, w + 4, w + 8 across the 64 slots, one slot per lane), and count the lens checks of
-// sec. 2.1.2 (P^z >= z_in + delta_min, finite) over the design's control points.
+// Sum the NSLOT partial-statistics slots of design d into stats[d] and clear them (waves 0..3 of the
+// workgroup: wave w sums fields w, w + 4, w + 8 across the 64 slots, one slot per lane), and count the lens
+// checks of sec. 2.1.2 (P^z >= z_in + delta_min, finite) over the design's control points.  For workgroups
+// of 256 to 1024 threads; contains a barrier.
 __device__ void reduce_slots(int d, const DesignDev& D, const float* Pz, ffrt_stats* slots, ffrt_stats* stats) {
     constexpr int NF = sizeof(ffrt_stats) / 4;
     static_assert(NSLOT == 64 && NF == 12, "one slot per lane, three fields per wave");
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     uint32_t* slot = reinterpret_cast<uint32_t*>(slots + (size_t)d * NSLOT + lane);
     uint32_t* out = reinterpret_cast<uint32_t*>(stats + d);
-    for (int f = wave; f < NF - 2; f += 4) {  // the last two fields are the lens checks
+    for (int f = wave; wave < 4 && f < NF - 2; f += 4) {  // the last two fields are the lens checks
         const uint32_t x = slot[f];
         slot[f] = 0u;
         if (f == 0) {  // flux_on_screen (float)
@@ -42,7 +43,7 @@ __device__ void reduce_slots(int d, const DesignDev& D, const float* Pz, ffrt_st
             if (lane == 0) out[f] = sum;
         }
     }
-    __shared__ uint32_t s_chk[4][2];
+    __shared__ uint32_t s_chk[16][2];
     uint32_t nbad = 0, nnan = 0;
     const float* P = Pz + D.cp_off;
     for (int i = threadIdx.x; i < D.n_u * D.n_v; i += blockDim.x) {
@@ -58,8 +59,13 @@ __device__ void reduce_slots(int d, const DesignDev& D, const float* Pz, ffrt_st
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        stats[d].n_constraint_viol = s_chk[0][0] + s_chk[1][0] + s_chk[2][0] + s_chk[3][0];
-        stats[d].n_nan = s_chk[0][1] + s_chk[1][1] + s_chk[2][1] + s_chk[3][1];
+        uint32_t b = 0, n = 0;
+        for (int w = 0; w < nw; ++w) {
+            b += s_chk[w][0];
+            n += s_chk[w][1];
+        }
+        stats[d].n_constraint_viol = b;
+        stats[d].n_nan = n;
     }
 }
 

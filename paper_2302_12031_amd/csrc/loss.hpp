@@ -1,4 +1,4 @@
-// Loss of sec. 2.5 from per-slice sums, evaluated by one wave in every workgroup of the dL/dI kernel.
+// Loss of sec. 2.5 from per-slice sums, added up by one wave in every workgroup of the dL/dI kernel.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -16,21 +16,8 @@ struct LossOut {
     int valid;      // 0 without flux (the design's Adam update is skipped)
 };
 
-// I_hat = I / s, T_hat = T / s_T, D = I_hat - T_hat, L = ||D||_F / sqrt(n_x n_y),
-// dL/dI = (D - sum(D I_hat)) / (s sqrt(n_x n_y) ||D||) (0 where ||D|| = 0), with
-// ||D||^2 = A / s^2 - 2 B / (s s_T) + C / s_T^2 and sum(D I_hat) = A / s^2 - B / (s s_T) from the slice sums
-// (A = sum I^2, B = sum I T, C = sum T^2), which in double precision lose nothing that matters to the float
-// results.  The LB <= 64 slices are added by a butterfly over the wave, so every lane of every wave that
-// calls this gets the same bits (no workgroup has to wait for another).  Call with a full wave.
-__device__ inline LossOut loss_from_partials(const double* partial, int d, int LB, const DesignDev& D) {
-    const int lane = threadIdx.x & 63;
-    double q[LOSS_Q];
-#pragma unroll
-    for (int k = 0; k < LOSS_Q; ++k) q[k] = lane < LB ? partial[((size_t)d * LB + lane) * LOSS_Q + k] : 0.0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-        for (int k = 0; k < LOSS_Q; ++k) q[k] += __shfl_xor(q[k], o);
+// Loss and dL/dI scalars from the whole-image sums q = (sum I, sum T, sum I^2, sum I T, sum T^2).
+__device__ inline LossOut loss_from_sums(const double* q, const DesignDev& D) {
     LossOut r;
     r.L = {0.0f, 0.0f, 0.0f, 0.0f};
     const double s = q[0], sT = q[1];
@@ -49,6 +36,24 @@ __device__ inline LossOut loss_from_partials(const double* partial, int d, int L
     r.loss = (float)(nrm / rn);
     r.valid = 1;
     return r;
+}
+
+// I_hat = I / s, T_hat = T / s_T, D = I_hat - T_hat, L = ||D||_F / sqrt(n_x n_y),
+// dL/dI = (D - sum(D I_hat)) / (s sqrt(n_x n_y) ||D||) (0 where ||D|| = 0), with
+// ||D||^2 = A / s^2 - 2 B / (s s_T) + C / s_T^2 and sum(D I_hat) = A / s^2 - B / (s s_T) from the slice sums
+// (A = sum I^2, B = sum I T, C = sum T^2), which in double precision lose nothing that matters to the float
+// results.  The LB <= 64 slices are added by a butterfly over the wave, so every lane of every wave that
+// calls this gets the same bits (no workgroup has to wait for another).  Call with a full wave.
+__device__ inline LossOut loss_from_partials(const double* partial, int d, int LB, const DesignDev& D) {
+    const int lane = threadIdx.x & 63;
+    double q[LOSS_Q];
+#pragma unroll
+    for (int k = 0; k < LOSS_Q; ++k) q[k] = lane < LB ? partial[((size_t)d * LB + lane) * LOSS_Q + k] : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int k = 0; k < LOSS_Q; ++k) q[k] += __shfl_xor(q[k], o);
+    return loss_from_sums(q, D);
 }
 
 }  // namespace ffrt
