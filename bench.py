@@ -85,6 +85,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--shapes", default=None,
                     help="forward,adjoint kernel-shape indices to use instead of autotuning (e.g. 0,1)")
+    ap.add_argument("--compare-separate", action="store_true",
+                    help="multi-design workloads: also time every design in a plan and graph of its own")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 256 MiB buffer three times (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -165,10 +167,12 @@ def main():
     iters = 0.0
     n_point = sum(p.num_rays() for p in wl.problems if p.source.kind != 0)
     if n_point:
-        # Newton iterations are not counted on the device: use the mean the per-ray inspection reports
-        ids = np.linspace(0, wl.problems[0].num_rays() - 1, 4096).astype(np.int64)
-        pz0 = st["Pz"][plan.cp_offsets[0]:plan.cp_offsets[1]].contiguous()
-        sub = ffrt.Plan([wl.problems[0]])
+        # Newton iterations are not counted on the device: use the mean the per-ray inspection reports for
+        # the first point-source design
+        d0 = next(i for i, p in enumerate(wl.problems) if p.source.kind != 0)
+        ids = np.linspace(0, wl.problems[d0].num_rays() - 1, 4096).astype(np.int64)
+        pz0 = st["Pz"][plan.cp_offsets[d0]:plan.cp_offsets[d0 + 1]].contiguous()
+        sub = ffrt.Plan([wl.problems[d0]])
         tr = sub.trace_rays(0, pz0, ids).cpu().numpy()
         iters = float(tr[tr[:, 0] == 0, 7].mean()) if (tr[:, 0] == 0).any() else 0.0
 
@@ -263,6 +267,33 @@ def main():
             fd["adjoint_vs_oracle_fp64"] = float(np.abs(g_adj - g64).max() / np.abs(g64).max())
             fd["fd_vs_oracle_fp64_16cp"] = float(np.abs(g_fd[sel] - g64[sel]).max() / np.abs(g64).max())
         out["fd"] = fd
+
+    # ---- the same designs one plan (and one captured graph) each, launched one after another
+    if args.compare_separate and len(wl.problems) > 1:
+        sep_ms = 0.0
+        k_sep = 5
+        for d, p in enumerate(wl.problems):
+            pd = ffrt.Plan([p])
+            if not args.no_autotune:
+                P0 = pd.pack_cp([wl.Pz[d]])
+                irr0 = pd.forward(P0)
+                _, g0 = pd.loss(irr0, pd.pack_img([wl.targets[d]]))
+                pd.autotune(P0, irr0, g0, torch.empty_like(P0), reps=3)
+            sd = pd.new_state(pd.pack_cp([wl.Pz[d]]))
+            Td = pd.pack_img([wl.targets[d]])
+            with torch.cuda.stream(stream):
+                pd.graph_capture(sd, Td, steps=k_sep)
+                pd.graph_launch(stream)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            pd.graph_launch(stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            sep_ms += e0.elapsed_time(e1) / k_sep
+        out["separate_plans"] = {"designs": len(wl.problems), "ms_per_step_sum": sep_ms,
+                                 "batched_ms_per_step": ms_step, "speedup_of_batching": sep_ms / ms_step,
+                                 "rays_per_s_separate": rays / (sep_ms * 1e-3),
+                                 "note": "each design autotuned in its own plan; graphs of 5 steps, run back to back"}
 
     if not args.no_cpu and len(wl.problems) == 1:
         out["cpu_baseline"] = cpu_baseline(wl)
