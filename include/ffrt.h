@@ -181,6 +181,32 @@ ffrt_status ffrt_graph_capture(ffrt_plan* plan, int32_t steps, float* Pz, const 
                                ffrt_stats* stats, const ffrt_adam_hparams* hp, void* stream);
 ffrt_status ffrt_graph_launch(ffrt_plan* plan, void* stream);
 
+/* ---- range reparametrisation of the control heights (sec. 2.4.1, eq. of the output correction) ------ */
+/* The paper optimises, per control point, a variable theta mapped through tanh onto an allowed range,
+ * optionally offset by a function f of the control point's (x, y):  P^z = lo + (tanh(theta) + 1) span / 2,
+ * with lo = z_min (+ f(P^x, P^y)) and span = z_max - z_min >= 0 (both may vary per control point).  theta,
+ * lo, span, Pz, dL_dP, dL_dtheta: device float32, packed like Pz.  NULL buffers give FFRT_E_ARG. */
+ffrt_status ffrt_reparam_apply(ffrt_plan* plan, const float* theta, const float* lo, const float* span, float* Pz,
+                               void* stream);
+/* dL_dtheta = dL_dP (1 - tanh^2(theta)) span / 2. */
+ffrt_status ffrt_reparam_grad(ffrt_plan* plan, const float* theta, const float* span, const float* dL_dP,
+                              float* dL_dtheta, void* stream);
+/* One optimisation step on theta: as ffrt_step, with Adam (m, v, t) acting on theta through the chain rule
+ * above; Pz must hold P(theta) on entry (ffrt_reparam_apply) and holds P of the updated theta on return.
+ * dL_dP receives the gradient with respect to P^z. */
+ffrt_status ffrt_step_reparam(ffrt_plan* plan, float* theta, const float* lo, const float* span, float* Pz,
+                              const float* target, float* irr, float* loss, float* dL_dI, float* dL_dP, float* m,
+                              float* v, int32_t* t, ffrt_stats* stats, const ffrt_adam_hparams* hp, void* stream);
+/* ffrt_graph_capture for ffrt_step_reparam (replayed with ffrt_graph_launch). */
+ffrt_status ffrt_graph_capture_reparam(ffrt_plan* plan, int32_t steps, float* theta, const float* lo,
+                                       const float* span, float* Pz, const float* target, float* irr, float* loss,
+                                       float* dL_dI, float* dL_dP, float* m, float* v, int32_t* t, ffrt_stats* stats,
+                                       const ffrt_adam_hparams* hp, void* stream);
+/* Host-side (x, y) of every control point, packed like Pz (host float64 arrays): the Greville positions
+ * P^x_ij = (2 u*_i - 1) r_x, P^y_ij = (2 v*_j - 1) r_y of sec. 2.1.1, at which an offset function f is
+ * evaluated. */
+ffrt_status ffrt_plan_control_xy(const ffrt_plan* plan, double* x, double* y);
+
 /* ---- kernel shapes (autotuner) ------------------------------------------------------------------- */
 
 /* Number of candidate shapes for the forward (which = 0) or adjoint (which = 1) kernel, and selection. */

@@ -269,3 +269,32 @@ def adam(P, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 
 def rng(seed, stream, index):
     return lib().orc_rng(seed, stream, index)
+
+
+# ---------------------------------------------------------------------------------------------------
+# Range reparametrisation of the control heights (sec. 2.4.1, eq. of the output correction): each control
+# height is z_min (+ an offset f(P^x, P^y)) + (y + 1)(z_max - z_min) / 2 with y = tanh(theta).  Here lo holds
+# z_min (+ f) and span = z_max - z_min, per control point.
+# ---------------------------------------------------------------------------------------------------
+def reparam(theta, lo, span):
+    theta, lo, span = (np.asarray(a, dtype=np.float64) for a in (theta, lo, span))
+    return lo + 0.5 * (np.tanh(theta) + 1.0) * span
+
+
+def reparam_grad(theta, span, dLdP):
+    """dL/dtheta from dL/dP: d tanh(theta)/d theta = 1 / cosh^2(theta)."""
+    theta, span, dLdP = (np.asarray(a, dtype=np.float64) for a in (theta, span, dLdP))
+    return dLdP * 0.5 * span / np.cosh(theta) ** 2
+
+
+def control_xy(prob):
+    """(x, y) of every control point, [n_u][n_v] each: the Greville abscissae u*_i = (u_{i+1} + ... +
+    u_{i+p}) / p of the clamped knots (sec. 2.1.1, eq. of the nodal representation) mapped by
+    X = (2u - 1) r_x, Y = (2v - 1) r_y."""
+    L = prob.lens
+    Uu, Uv = knots(L.p, L.n_u), knots(L.q, L.n_v)
+    gu = np.array([Uu[i + 1:i + L.p + 1].mean() for i in range(L.n_u)])
+    gv = np.array([Uv[j + 1:j + L.q + 1].mean() for j in range(L.n_v)])
+    x = np.repeat(((2.0 * gu - 1.0) * L.r_x)[:, None], L.n_v, axis=1)
+    y = np.repeat(((2.0 * gv - 1.0) * L.r_y)[None, :], L.n_u, axis=0)
+    return x, y

@@ -260,11 +260,36 @@ __global__ __launch_bounds__(256) void k_finish(const DesignDev* designs, float*
         return g;
     };
     const int ncp = D.n_u * D.n_v;
-    if (adam.Pz && (!valid || valid[d])) {
+    const bool step = adam.Pz && (!valid || valid[d]);
+    if (step && adam.theta) {
+        // range reparametrisation (sec. 2.4.1): Adam on theta, then P from the new theta
+        float* th = adam.theta + D.cp_off;
+        const float* lo = adam.lo + D.cp_off;
+        const float* sp = adam.span + D.cp_off;
+        auto take_theta = [take, th, sp](int i) {
+            const float y = tanhf(th[i]);
+            return take(i) * (0.5f * (1.0f - y * y) * sp[i]);
+        };
+        adam_update(adam.theta, adam.m, adam.v, adam.t + d, D.cp_off, ncp, adam.hp, take_theta);
+        float* P = adam.Pz + D.cp_off;
+        for (int i = threadIdx.x; i < ncp; i += blockDim.x) P[i] = lo[i] + 0.5f * (tanhf(th[i]) + 1.0f) * sp[i];
+    } else if (step) {
         adam_update(adam.Pz, adam.m, adam.v, adam.t + d, D.cp_off, ncp, adam.hp, take);
     } else {
         for (int i = threadIdx.x; i < ncp; i += blockDim.x) take(i);
     }
+}
+
+// Range reparametrisation of sec. 2.4.1 (eq. of the output correction, with or without the offset
+// function folded into lo): P = lo + (tanh(theta) + 1) span / 2, and its chain rule.
+__global__ void k_reparam(int mode, int64_t n, const float* __restrict__ theta, const float* __restrict__ lo,
+                          const float* __restrict__ span, float* P, const float* __restrict__ dLdP,
+                          float* dLdtheta) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const float y = tanhf(theta[k]);
+    if (mode == 0) P[k] = lo[k] + 0.5f * (y + 1.0f) * span[k];
+    else dLdtheta[k] = dLdP[k] * (0.5f * (1.0f - y * y) * span[k]);
 }
 
 // The loss value of sec. 2.5 with double-precision reductions (finite-difference checks only).
@@ -343,6 +368,14 @@ hipError_t launch_loss(const DesignDev* designs, int n_designs, int LB, unsigned
 hipError_t launch_finish(const DesignDev* designs, int n_designs, float* gacc, float* dLdP, const int32_t* valid,
                          const AdamArgs& adam, hipStream_t s) {
     hipLaunchKernelGGL(k_finish, dim3(n_designs), dim3(256), 0, s, designs, gacc, dLdP, valid, adam);
+    return hipGetLastError();
+}
+
+hipError_t launch_reparam(int mode, int64_t n, const float* theta, const float* lo, const float* span, float* P,
+                          const float* dLdP, float* dLdtheta, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reparam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, mode, n, theta, lo, span, P,
+                       dLdP, dLdtheta);
     return hipGetLastError();
 }
 

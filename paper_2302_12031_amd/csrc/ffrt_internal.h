@@ -81,13 +81,18 @@ struct LossScalars {
     float is, isT, dot, coef;
 };
 
-// Adam applied by the finishing kernel after the adjoint (null Pz: plain gradient output).
+// Adam applied by the finishing kernel after the adjoint (null Pz: plain gradient output).  With theta set
+// the optimised variables are theta (sec. 2.4.1): P = lo + (tanh(theta) + 1) span / 2, Adam steps theta with
+// dL/dtheta = dL/dP (1 - tanh^2 theta) span / 2, and Pz is rewritten from the new theta.
 struct AdamArgs {
     float* Pz;
     float* m;
     float* v;
     int32_t* t;
     ffrt_adam_hparams hp;
+    float* theta;
+    const float* lo;
+    const float* span;
 };
 
 struct TraceArgs {
@@ -163,6 +168,10 @@ hipError_t launch_loss(const DesignDev* designs, int n_designs, int LB, unsigned
 // found flux (valid).
 hipError_t launch_finish(const DesignDev* designs, int n_designs, float* gacc, float* dLdP, const int32_t* valid,
                          const AdamArgs& adam, hipStream_t s);
+// Range reparametrisation of sec. 2.4.1 over n packed control points: mode 0 writes P from theta, mode 1
+// writes dL/dtheta from dL/dP.
+hipError_t launch_reparam(int mode, int64_t n, const float* theta, const float* lo, const float* span, float* P,
+                          const float* dLdP, float* dLdtheta, hipStream_t s);
 hipError_t launch_loss_f64(const DesignDev* designs, int n_designs, const float* irr, const float* target,
                            double* loss, hipStream_t s);
 hipError_t launch_adam(const DesignDev* designs, int n_designs, float* Pz, const float* g, float* m,

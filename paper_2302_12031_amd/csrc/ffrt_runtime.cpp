@@ -322,9 +322,11 @@ ffrt_status run_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, float
 // One optimisation step in five kernels (six with point or grid sources: their bounds of sec. 2.2.2 first):
 // forward, loss slice sums (resolving the irradiance, statistics), dL/dI (plus loss and validity), adjoint,
 // finish (dL/dP and Adam).  dL/dI goes to the plan's workspace when the caller passes no buffer for it.
+// With theta set (lo, span too) the optimised variables are theta, and Pz must hold P(theta) on entry (it
+// does again on exit).
 ffrt_status run_step(ffrt_plan* pl, float* Pz, const float* target, float* irr, float* loss, float* dLdI,
                      float* dLdP, float* m, float* v, int32_t* t, ffrt_stats* stats, const ffrt_adam_hparams& hp,
-                     hipStream_t s) {
+                     hipStream_t s, float* theta = nullptr, const float* lo = nullptr, const float* span = nullptr) {
     if (!dLdI) dLdI = pl->d_dldi();
     if (ffrt_status b = run_bounds(pl, Pz, s)) return b;
     ffrt_status st = launch_forward(pl, Pz, stats != nullptr, s);
@@ -339,7 +341,32 @@ ffrt_status run_step(ffrt_plan* pl, float* Pz, const float* target, float* irr, 
     adam.v = v;
     adam.t = t;
     adam.hp = hp;
+    adam.theta = theta;
+    adam.lo = lo;
+    adam.span = span;
     HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), dLdP, pl->d_valid(), adam, s));
+    return FFRT_OK;
+}
+
+ffrt_status capture(ffrt_plan* plan, int32_t steps, float* Pz, const float* target, float* irr, float* loss,
+                    float* dL_dI, float* dL_dP, float* m, float* v, int32_t* t, ffrt_stats* stats,
+                    const ffrt_adam_hparams* hp, void* stream, float* theta, const float* lo, const float* span) {
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->gexec) { (void)hipGraphExecDestroy(plan->gexec); plan->gexec = nullptr; }
+    if (plan->graph) { (void)hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    ffrt_status st = FFRT_OK;
+    for (int i = 0; i < steps && st == FFRT_OK; ++i)
+        st = run_step(plan, Pz, target, irr, loss, dL_dI, dL_dP, m, v, t, stats, *hp, s, theta, lo, span);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(e, "hipGraphInstantiate"); }
+    plan->graph = g;
+    plan->gexec = ge;
     return FFRT_OK;
 }
 
@@ -574,22 +601,69 @@ ffrt_status ffrt_graph_capture(ffrt_plan* plan, int32_t steps, float* Pz, const 
     if (steps < 1) return fail(FFRT_E_ARG, "steps must be >= 1");
     if (!Pz || !target || !irr || !loss || !dL_dP || !m || !v || !t || !hp)
         return fail(FFRT_E_ARG, "null buffer");
-    hipStream_t s = (hipStream_t)stream;
-    if (plan->gexec) { (void)hipGraphExecDestroy(plan->gexec); plan->gexec = nullptr; }
-    if (plan->graph) { (void)hipGraphDestroy(plan->graph); plan->graph = nullptr; }
-    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-    ffrt_status st = FFRT_OK;
-    for (int i = 0; i < steps && st == FFRT_OK; ++i)
-        st = run_step(plan, Pz, target, irr, loss, dL_dI, dL_dP, m, v, t, stats, *hp, s);
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(s, &g);
-    if (st) { if (g) (void)hipGraphDestroy(g); return st; }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    hipGraphExec_t ge = nullptr;
-    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-    if (e != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(e, "hipGraphInstantiate"); }
-    plan->graph = g;
-    plan->gexec = ge;
+    return capture(plan, steps, Pz, target, irr, loss, dL_dI, dL_dP, m, v, t, stats, hp, stream, nullptr, nullptr,
+                   nullptr);
+}
+
+
+ffrt_status ffrt_reparam_apply(ffrt_plan* plan, const float* theta, const float* lo, const float* span, float* Pz,
+                               void* stream) {
+    if (!plan) return fail(FFRT_E_ARG, "null plan");
+    if (!theta || !lo || !span || !Pz) return fail(FFRT_E_ARG, "null buffer");
+    HIP_TRY(launch_reparam(0, plan->total_cp, theta, lo, span, Pz, nullptr, nullptr, (hipStream_t)stream));
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_reparam_grad(ffrt_plan* plan, const float* theta, const float* span, const float* dL_dP,
+                              float* dL_dtheta, void* stream) {
+    if (!plan) return fail(FFRT_E_ARG, "null plan");
+    if (!theta || !span || !dL_dP || !dL_dtheta) return fail(FFRT_E_ARG, "null buffer");
+    HIP_TRY(launch_reparam(1, plan->total_cp, theta, nullptr, span, nullptr, dL_dP, dL_dtheta, (hipStream_t)stream));
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_step_reparam(ffrt_plan* plan, float* theta, const float* lo, const float* span, float* Pz,
+                              const float* target, float* irr, float* loss, float* dL_dI, float* dL_dP, float* m,
+                              float* v, int32_t* t, ffrt_stats* stats, const ffrt_adam_hparams* hp, void* stream) {
+    if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
+    if (!theta || !lo || !span || !Pz || !target || !irr || !loss || !dL_dP || !m || !v || !t || !hp)
+        return fail(FFRT_E_ARG, "null buffer");
+    return run_step(plan, Pz, target, irr, loss, dL_dI, dL_dP, m, v, t, stats, *hp, (hipStream_t)stream, theta, lo,
+                    span);
+}
+
+ffrt_status ffrt_graph_capture_reparam(ffrt_plan* plan, int32_t steps, float* theta, const float* lo,
+                                       const float* span, float* Pz, const float* target, float* irr, float* loss,
+                                       float* dL_dI, float* dL_dP, float* m, float* v, int32_t* t, ffrt_stats* stats,
+                                       const ffrt_adam_hparams* hp, void* stream) {
+    if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
+    if (!stream) return fail(FFRT_E_ARG, "graph capture needs a non-default stream");
+    if (steps < 1) return fail(FFRT_E_ARG, "steps must be >= 1");
+    if (!theta || !lo || !span || !Pz || !target || !irr || !loss || !dL_dP || !m || !v || !t || !hp)
+        return fail(FFRT_E_ARG, "null buffer");
+    return capture(plan, steps, Pz, target, irr, loss, dL_dI, dL_dP, m, v, t, stats, hp, stream, theta, lo, span);
+}
+
+ffrt_status ffrt_plan_control_xy(const ffrt_plan* plan, double* x, double* y) {
+    if (!plan || !x || !y) return fail(FFRT_E_ARG, "null argument");
+    for (int d = 0; d < plan->nd; ++d) {
+        const ffrt_lens& L = plan->probs[d].lens;
+        // Greville abscissae u*_i = (u_{i+1} + ... + u_{i+p}) / p of the clamped equispaced knots (sec. 2.1.1)
+        auto greville = [](int p, int n, int i) {
+            double acc = 0.0;
+            for (int k = i + 1; k <= i + p; ++k) {
+                const double u = k <= p ? 0.0 : (k >= n ? 1.0 : double(k - p) / double(n - p));
+                acc += u;
+            }
+            return acc / p;
+        };
+        const int64_t off = plan->cp_off[d];
+        for (int i = 0; i < L.n_u; ++i)
+            for (int j = 0; j < L.n_v; ++j) {
+                x[off + (int64_t)i * L.n_v + j] = (2.0 * greville(L.p, L.n_u, i) - 1.0) * L.r_x;
+                y[off + (int64_t)i * L.n_v + j] = (2.0 * greville(L.q, L.n_v, j) - 1.0) * L.r_y;
+            }
+    }
     return FFRT_OK;
 }
 

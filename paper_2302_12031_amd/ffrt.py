@@ -67,6 +67,8 @@ HEADER_FUNCTIONS = [
     "ffrt_plan_time_kernels", "ffrt_num_configs",
     "ffrt_config_name", "ffrt_plan_set_config", "ffrt_plan_get_config", "ffrt_plan_autotune",
     "ffrt_trace_rays", "ffrt_rng", "ffrt_status_string", "ffrt_last_error",
+    "ffrt_reparam_apply", "ffrt_reparam_grad", "ffrt_step_reparam", "ffrt_graph_capture_reparam",
+    "ffrt_plan_control_xy",
 ]
 
 _lib = None
@@ -105,6 +107,11 @@ def lib():
             "ffrt_plan_autotune": [vp, vp, vp, vp, vp, i32, vp],
             "ffrt_trace_rays": [vp, i32, vp, vp, i64, vp, vp],
             "ffrt_rng": [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, i64, vp, vp],
+            "ffrt_reparam_apply": [vp, vp, vp, vp, vp, vp],
+            "ffrt_reparam_grad": [vp, vp, vp, vp, vp, vp],
+            "ffrt_step_reparam": [vp] + [vp] * 13 + [P(CAdam), vp],
+            "ffrt_graph_capture_reparam": [vp, i32] + [vp] * 13 + [P(CAdam), vp],
+            "ffrt_plan_control_xy": [vp, vp, vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -302,6 +309,51 @@ class Plan:
                                         _ptr(st["loss"]), _ptr(st.get("dLdI")), _ptr(st["dLdP"]), _ptr(st["m"]),
                                         _ptr(st["v"]), _ptr(st["t"]), _ptr(st["stats"]), ctypes.byref(hp.c()),
                                         _stream(stream)), "ffrt_graph_capture")
+
+    # ---- range reparametrisation (sec. 2.4.1): P = lo + (tanh(theta) + 1) span / 2 ---------------------
+    def control_xy(self):
+        """Greville (x, y) of every control point, packed like Pz (float64 numpy arrays)."""
+        x = np.zeros(self.total_cp)
+        y = np.zeros(self.total_cp)
+        _check(lib().ffrt_plan_control_xy(self.h, x.ctypes.data_as(ctypes.c_void_p),
+                                          y.ctypes.data_as(ctypes.c_void_p)), "ffrt_plan_control_xy")
+        return x, y
+
+    def reparam_apply(self, theta, lo, span, Pz=None, stream=None):
+        for a, n in ((theta, "theta"), (lo, "lo"), (span, "span")):
+            self._f32(a, self.total_cp, n)
+        if Pz is None:
+            Pz = torch.empty(self.total_cp, dtype=torch.float32, device=self.device)
+        _check(lib().ffrt_reparam_apply(self.h, _ptr(theta), _ptr(lo), _ptr(span), _ptr(Pz), _stream(stream)),
+               "ffrt_reparam_apply")
+        return Pz
+
+    def reparam_grad(self, theta, span, dLdP, out=None, stream=None):
+        for a, n in ((theta, "theta"), (span, "span"), (dLdP, "dLdP")):
+            self._f32(a, self.total_cp, n)
+        if out is None:
+            out = torch.empty(self.total_cp, dtype=torch.float32, device=self.device)
+        _check(lib().ffrt_reparam_grad(self.h, _ptr(theta), _ptr(span), _ptr(dLdP), _ptr(out), _stream(stream)),
+               "ffrt_reparam_grad")
+        return out
+
+    def new_reparam_state(self, theta, lo, span, with_dLdI=False):
+        """Optimisation state on theta; Pz is kept equal to P(theta) by the steps."""
+        st = self.new_state(self.reparam_apply(theta, lo, span), with_dLdI)
+        st.update(theta=theta, lo=lo, span=span)
+        return st
+
+    def step_reparam(self, st, target, hp=AdamHP(), stream=None):
+        _check(lib().ffrt_step_reparam(self.h, _ptr(st["theta"]), _ptr(st["lo"]), _ptr(st["span"]), _ptr(st["Pz"]),
+                                       _ptr(target), _ptr(st["irr"]), _ptr(st["loss"]), _ptr(st.get("dLdI")),
+                                       _ptr(st["dLdP"]), _ptr(st["m"]), _ptr(st["v"]), _ptr(st["t"]),
+                                       _ptr(st["stats"]), ctypes.byref(hp.c()), _stream(stream)), "ffrt_step_reparam")
+
+    def graph_capture_reparam(self, st, target, steps=1, hp=AdamHP(), stream=None):
+        _check(lib().ffrt_graph_capture_reparam(
+            self.h, steps, _ptr(st["theta"]), _ptr(st["lo"]), _ptr(st["span"]), _ptr(st["Pz"]), _ptr(target),
+            _ptr(st["irr"]), _ptr(st["loss"]), _ptr(st.get("dLdI")), _ptr(st["dLdP"]), _ptr(st["m"]), _ptr(st["v"]),
+            _ptr(st["t"]), _ptr(st["stats"]), ctypes.byref(hp.c()), _stream(stream)), "ffrt_graph_capture_reparam")
 
     def time_kernels(self, Pz, irr, dLdI, dLdP, reps=20, stream=None):
         """Mean (forward, adjoint) trace-kernel durations in ms (HIP events on the stream)."""

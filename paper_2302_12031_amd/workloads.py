@@ -232,6 +232,32 @@ def c5(n_designs=64, ray_scale=1.0) -> Workload:
     return Workload(f"batch{n_designs}-uneven", probs, Pz, T)
 
 
+def circular_tophat(prob: Problem, radius: float) -> np.ndarray:
+    """Uniform disc of the given radius (mm) centred on the screen, sampled at pixel centres, sum 1."""
+    nx, ny = prob.image_shape()
+    d = prob.detector
+    cx, cy = _pixel_centres(nx, d.R_x)[:, None], _pixel_centres(ny, d.R_y)[None, :]
+    img = ((cx ** 2 + cy ** 2) <= radius ** 2).astype(np.float64)
+    return img / img.sum()
+
+
+def tophat(rays_side=512, cps_side=16, det_side=64) -> Workload:
+    """Design case of sec. 3.2 without a network: a collimated bundle shaped into a circular top hat.  The
+    lens starts flat (theta = 0 in the range reparametrisation of sec. 2.4.1, heights in [1.8, 2.2] mm); the
+    screen (R = 8 mm at 30 mm) first shows the 10 x 10 mm square of the aperture, the target is a disc of
+    radius 4 mm.  Ray count, control net and screen are synthetic (the paper's are in its supplement)."""
+    p = collimated_problem(rays_side, cps_side, det_side, jitter=0, seed=5, R=8.0, z=30.0)
+    lo, span = tophat_range(p)
+    return Workload(f"tophat-{rays_side}x{rays_side}-cp{cps_side}x{cps_side}-det{det_side}", [p],
+                    [lo + 0.5 * span], [circular_tophat(p, 4.0)])
+
+
+def tophat_range(prob: Problem, z_min: float = 1.8, z_max: float = 2.2):
+    """(lo, span) of the range reparametrisation, [n_u][n_v] each, no offset function."""
+    shape = prob.cp_shape()
+    return np.full(shape, z_min), np.full(shape, z_max - z_min)
+
+
 WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
 
 

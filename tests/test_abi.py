@@ -4,6 +4,7 @@ import os
 import re
 from dataclasses import replace
 
+import numpy as np
 import pytest
 
 from paper_2302_12031_amd import ffrt
@@ -98,3 +99,21 @@ def test_workload_sizes_match_the_stated_configurations():
     assert all(p.lens.n_u in (8, 16, 24, 32) for p in c5.problems)
     for wl in (W.c1(), W.c2(), W.c3(64)):
         assert abs(wl.targets[0].sum() - 1.0) < 1e-12 and (wl.targets[0] >= 0).all()
+
+
+def test_control_xy_matches_oracle_greville_positions():
+    """ffrt_plan_control_xy (host side, no GPU) against the oracle's Greville positions."""
+    import oracle as O
+    probs = [W.collimated_problem(32, 9, 16), W.point_problem(16, 12, 32)]
+    h = ffrt.create_plan_handle(probs)
+    K = sum(p.lens.n_u * p.lens.n_v for p in probs)
+    x, y = np.zeros(K), np.zeros(K)
+    assert ffrt.lib().ffrt_plan_control_xy(h, x.ctypes.data_as(ctypes.c_void_p), y.ctypes.data_as(ctypes.c_void_p)) == 0
+    off = 0
+    for p in probs:
+        ox, oy = O.control_xy(p)
+        n = ox.size
+        np.testing.assert_allclose(x[off:off + n], ox.ravel(), rtol=0, atol=1e-13)
+        np.testing.assert_allclose(y[off:off + n], oy.ravel(), rtol=0, atol=1e-13)
+        off += n
+    ffrt.lib().ffrt_plan_destroy(h)

@@ -475,3 +475,52 @@ def test_threads_do_not_change_results():
     ga = O.grad(p, Pz, T, threads=1)[1]
     gb = O.grad(p, Pz, T, threads=3)[1]
     np.testing.assert_allclose(ga, gb, rtol=1e-11, atol=1e-18)
+
+
+# ---------------------------------------------------------------------------------------------------
+# Range reparametrisation (sec. 2.4.1) and control-point positions (sec. 2.1.1)
+# ---------------------------------------------------------------------------------------------------
+def test_reparam_limits_and_derivative():
+    """P = lo + (tanh(theta) + 1) span / 2: the middle of the range at theta = 0, its ends as theta -> -+inf;
+    the chain-rule factor against central differences."""
+    lo, span = np.array([1.8, -0.3, 2.0]), np.array([0.4, 1.0, 0.0])
+    np.testing.assert_allclose(O.reparam(np.zeros(3), lo, span), lo + span / 2, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(O.reparam(np.full(3, 40.0), lo, span), lo + span, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(O.reparam(np.full(3, -40.0), lo, span), lo, rtol=0, atol=1e-15)
+    th = np.array([-1.3, 0.2, 0.9])
+    g = np.array([0.7, -2.0, 5.0])
+    h = 1e-6
+    fd = g * (O.reparam(th + h, lo, span) - O.reparam(th - h, lo, span)) / (2 * h)
+    np.testing.assert_allclose(O.reparam_grad(th, span, g), fd, rtol=1e-8, atol=1e-12)
+
+
+def test_reparam_gradient_through_the_loss_matches_fd():
+    """dL/dtheta = dL/dP * dP/dtheta through the traced loss, against central differences in theta."""
+    from paper_2302_12031_amd import workloads as W
+    p = W.collimated_problem(48, 6, 16, jitter=0, seed=3, R=8.0, z=30.0)
+    lo, span = W.tophat_range(p)
+    th = W.rng(3, 9).uniform(-0.5, 0.5, p.cp_shape())
+    T = W.circular_tophat(p, 4.0)
+    P = O.reparam(th, lo, span)
+    L0, gP, _, _ = O.grad(p, P, T)
+    gth = O.reparam_grad(th, span, gP)
+    h = 1e-6
+    for k in [(1, 1), (2, 3), (4, 2)]:
+        E = np.zeros_like(th)
+        E[k] = h
+        Lp = O.loss(O.forward(p, O.reparam(th + E, lo, span))[0], T)[0]
+        Lm = O.loss(O.forward(p, O.reparam(th - E, lo, span))[0], T)[0]
+        assert abs((Lp - Lm) / (2 * h) - gth[k]) <= 1e-5 * np.abs(gth).max(), k
+
+
+def test_control_xy_are_greville_positions():
+    """The control points' x make X(u) = (2u - 1) r_x exactly: sum_i x_i N_i(u) = (2u - 1) r_x."""
+    from paper_2302_12031_amd import workloads as W
+    p = W.collimated_problem(32, 9, 16)
+    x, y = O.control_xy(p)
+    L = p.lens
+    for u in np.linspace(0.0, 1.0, 13):
+        Nu = O.basis_all(L.p, L.n_u, u)
+        assert abs(Nu @ x[:, 0] - (2 * u - 1) * L.r_x) < 1e-13
+        Nv = O.basis_all(L.q, L.n_v, u)
+        assert abs(Nv @ y[0, :] - (2 * u - 1) * L.r_y) < 1e-13
