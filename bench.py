@@ -11,6 +11,12 @@ plano-freeform lens with a 16 x 16 bicubic control net onto a 128 x 128 detector
   fd          forward-only central finite-difference gradient over all control points on the same GPU:
               2K perturbed designs traced in one batched launch, and its agreement with the adjoint
   cpu_baseline  the FP64 oracle (forward + loss + forward-mode gradient) on the host cores
+
+With --generator dense|sparse the optimised variables are the parameters of the control-point generator of
+sec. 2.4 (three control-net-sized tanh layers and the output correction onto [Pz - 0.2, Pz + 0.2] mm,
+initialised U(-1e-4, 1e-4) as in the paper); each step then also runs the generator's forward pass, its
+back-propagation and Adam on its parameters.  The "generator" object gives those kernels' mean durations and
+their HBM roofline (algorithmic bytes below); the top-level roofline is that of the longest kernel group.
 """
 import argparse
 import hashlib
@@ -31,6 +37,11 @@ FLOPS = {
     # point sources: fixed part + per Newton iteration (surface value and slope, step)
     "point": {"forward": 420, "adjoint": 1060, "newton_iter": 224},
 }
+# Algorithmic HBM bytes of the generator per design with K control points and n parameters (fp32): the
+# forward reads the two weight matrices (dense 2 K^2, sparse 2 C K floats; vectors of K are negligible); the
+# dense back-propagation reads them again; the gradient + Adam kernel reads and writes parameters and both
+# moments (6 n floats; the sparse architecture fuses it with its back-propagation).
+PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 78.6         # 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, no packed FP32
 PEAK_FP32_PACKED_TFLOPS = 157.3
 
@@ -79,7 +90,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "tophat", "tophat64"])
+    ap.add_argument("--generator", default="none", choices=["none", "dense", "sparse"])
     ap.add_argument("--no-fd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -111,10 +123,24 @@ def main():
     from paper_2302_12031_amd import workloads as W
 
     torch.cuda.set_device(0)
-    wl = W.WORKLOADS[args.workload]()
+    if args.workload == "tophat":
+        wl = W.tophat()
+    elif args.workload == "tophat64":
+        wl = W.tophat(rays_side=1024, cps_side=64, det_side=128)
+    else:
+        wl = W.WORKLOADS[args.workload]()
     plan = ffrt.Plan(wl.problems)
-    st = plan.new_state(plan.pack_cp(wl.Pz))
     T = plan.pack_img(wl.targets)
+    arch = {"none": None, "dense": ffrt.MLP_DENSE, "sparse": ffrt.MLP_SPARSE}[args.generator]
+    if arch is None:
+        st = plan.new_state(plan.pack_cp(wl.Pz))
+    else:
+        lo = plan.pack_cp([z - 0.2 for z in wl.Pz])
+        span = torch.full_like(lo, 0.4)
+        n_par = plan.mlp_offsets(arch)[-1]
+        g = torch.Generator().manual_seed(W.STREAM_FD)
+        par = ((torch.rand(n_par, generator=g) * 2 - 1) * 1e-4).to(plan.device)
+        st = plan.new_mlp_state(par, lo, span, arch=arch)
     rays = wl.num_rays
     kinds = {("collimated" if p.source.kind == 0 else "point") for p in wl.problems}
 
@@ -130,8 +156,9 @@ def main():
     cfg = (plan.config_names(0)[plan.get_config(0)], plan.config_names(1)[plan.get_config(1)])
 
     stream = torch.cuda.Stream()
+    capture = ffrt.Plan.graph_capture if arch is None else ffrt.Plan.graph_capture_mlp
     with torch.cuda.stream(stream):
-        plan.graph_capture(st, T, steps=1)          # warm-up graph
+        capture(plan, st, T, steps=1)               # warm-up graph
     torch.cuda.synchronize()
     for _ in range(args.warmup):
         plan.graph_launch(stream)
@@ -140,7 +167,7 @@ def main():
     timed.set_config(0, plan.get_config(0))
     timed.set_config(1, plan.get_config(1))
     with torch.cuda.stream(stream):
-        timed.graph_capture(st, T, steps=args.steps)
+        capture(timed, st, T, steps=args.steps)
     torch.cuda.synchronize()
 
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -193,6 +220,32 @@ def main():
             "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS,
             "forward_ms": fwd_ms, "adjoint_ms": adj_ms, "newton_iters_mean": iters}
 
+    generator = None
+    if arch is not None:
+        with torch.cuda.stream(stream):
+            g_fwd, g_bwd, g_upd = timed.time_mlp(st, st["dLdP"], reps=args.steps, stream=stream)
+        Ks = [p.lens.n_u * p.lens.n_v for p in wl.problems]
+        Cs = [(2 * p.lens.p + 1) * (2 * p.lens.q + 1) for p in wl.problems]
+        W_floats = sum(2 * K * K if arch == ffrt.MLP_DENSE else 2 * C * K for K, C in zip(Ks, Cs))
+        n_par = timed.mlp_offsets(arch)[-1]
+        groups = {"forward": (g_fwd, 4 * W_floats),
+                  "backprop": (g_bwd, 4 * W_floats + (24 * n_par if arch == ffrt.MLP_SPARSE else 0)),
+                  "update": (g_upd, 24 * n_par if arch == ffrt.MLP_DENSE else 0)}
+        kern = {"forward": "k_mlp_layer1 + 2 x k_mlp_gemv" if arch == ffrt.MLP_DENSE else "k_smlp_forward",
+                "backprop": "k_mlp_seed + 2 x k_mlp_gemv_t" if arch == ffrt.MLP_DENSE else "k_smlp_backward",
+                "update": "k_mlp_grad_adam" if arch == ffrt.MLP_DENSE else "(fused)"}
+        gname = max(groups, key=lambda k: groups[k][0])
+        gms, gbytes = groups[gname]
+        gach = gbytes / (gms * 1e-3) / 1e9
+        groof = {"bound": "hbm", "achieved": gach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gach / PEAK_HBM_GBS,
+                 "traffic": None, "kernel": kern[gname], "kernel_ms": gms, "bytes_per_launch": gbytes}
+        generator = {"arch": args.generator, "parameters": n_par, "control_points": Ks,
+                     "ms": {k: v[0] for k, v in groups.items()},
+                     "bytes_per_launch": {k: v[1] for k, v in groups.items()}, "roofline": groof}
+        if gms > dom_ms:
+            roof = dict(groof, trace_kernels={"forward_ms": fwd_ms, "adjoint_ms": adj_ms,
+                                              "alu_frac_of_dominant": achieved / PEAK_FP32_TFLOPS})
+
     out = {"metric": METRIC, "value": rays * args.steps / (ms_total * 1e-3), "unit": "rays/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -204,9 +257,12 @@ def main():
            "loss_after": [float(x) for x in loss_now[:4]],
            "rays_hit_fraction": float(stats["n_hit"].sum()) / max(1, int(stats["n_traced"].sum())),
            "roofline": roof}
+    if generator is not None:
+        out["config"]["generator"] = args.generator
+        out["generator"] = generator
 
     # ---- finite-difference baseline on the same GPU (single-design workloads)
-    if not args.no_fd and len(wl.problems) == 1:
+    if not args.no_fd and len(wl.problems) == 1 and arch is None:
         # at the initial design (the optimised one has rays parked on the screen edge by the target's dark
         # border, whose discrete flips within +-h make any finite difference ill-defined)
         p = wl.problems[0]

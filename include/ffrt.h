@@ -207,6 +207,48 @@ ffrt_status ffrt_graph_capture_reparam(ffrt_plan* plan, int32_t steps, float* th
  * evaluated. */
 ffrt_status ffrt_plan_control_xy(const ffrt_plan* plan, double* x, double* y);
 
+/* ---- control-point generators (sec. 2.4) ----------------------------------------------------------- */
+/* Multi-layer perceptrons with the trivial input 1 and three tanh layers, each of the size K = n_u n_v of a
+ * design's control net (k = i n_v + j, as in Pz), whose output y passes through the output correction above:
+ *   h1 = tanh(w1 + b1),  h2 = tanh(W2 h1 + b2),  y = tanh(W3 h2 + b3),  P^z = lo + (y + 1) span / 2.
+ * arch selects how W2 and W3 connect:
+ *   FFRT_MLP_DENSE: fully connected; design d's parameters, packed: w1 (K), b1 (K), W2 (K x K, row-major: row i
+ *     holds the input weights of neuron i), b2 (K), W3 (K x K), b3 (K): 2 K^2 + 4 K floats.  K <= 16384.
+ *   FFRT_MLP_SPARSE: locally connected with the footprint of a (2p+1) x (2q+1) convolution (the control points
+ *     whose basis functions share a knot span), a weight per connection and a bias per neuron.  Neuron (i, j)
+ *     takes the layer input at (i + a - p, j + b - q), a in [0, 2p], b in [0, 2q]; packed: w1 (K), b1 (K),
+ *     W2 (C x K: W2[c][k], c = a (2q + 1) + b), b2 (K), W3 (C x K), b3 (K), C = (2p+1)(2q+1): 2 C K + 4 K floats.
+ *     A connection that would leave the net does not exist: its stored weight gets zero gradient.  K <= 3072.
+ * params: device float32; design d's parameters start at offsets[d] (ffrt_mlp_layout); offsets[n_designs] is
+ * the total.  acts: device float32 of 3 x (total control points), design d's h1, h2, y (K each) at 3 x its
+ * control-point offset; written by ffrt_mlp_forward, read by the backward pass.  lo, span, Pz, dL_dP: packed
+ * like Pz.  NULL buffers, an unknown arch or a control net above the limit give FFRT_E_ARG. */
+#define FFRT_MLP_DENSE 0
+#define FFRT_MLP_SPARSE 1
+/* Host int64 offsets[n_designs + 1] of each design's parameters in params. */
+ffrt_status ffrt_mlp_layout(const ffrt_plan* plan, int32_t arch, int64_t* offsets);
+/* Forward pass: writes acts and Pz. */
+ffrt_status ffrt_mlp_forward(ffrt_plan* plan, int32_t arch, const float* params, const float* lo, const float* span,
+                             float* acts, float* Pz, void* stream);
+/* Back-propagation of dL_dP (e.g. from ffrt_adjoint) through the output correction and the three layers:
+ * grad (device float32, laid out like params) receives dL/d(params).  acts must come from ffrt_mlp_forward
+ * on the same params.  Uses the plan's workspace. */
+ffrt_status ffrt_mlp_backward(ffrt_plan* plan, int32_t arch, const float* params, const float* acts,
+                              const float* span, const float* dL_dP, float* grad, void* stream);
+/* One optimisation step of the generator: as ffrt_step, with Adam acting on params (m, v laid out like
+ * params; t: one counter per design).  On entry acts and Pz must hold ffrt_mlp_forward of params; on return
+ * they hold it for the updated params.  dL_dP receives the gradient with respect to P^z.  A design whose
+ * loss found no flux keeps its params and counter. */
+ffrt_status ffrt_step_mlp(ffrt_plan* plan, int32_t arch, float* params, float* m, float* v, int32_t* t,
+                          const float* lo, const float* span, float* acts, float* Pz, const float* target, float* irr,
+                          float* loss, float* dL_dI, float* dL_dP, ffrt_stats* stats, const ffrt_adam_hparams* hp,
+                          void* stream);
+/* ffrt_graph_capture for ffrt_step_mlp (replayed with ffrt_graph_launch). */
+ffrt_status ffrt_graph_capture_mlp(ffrt_plan* plan, int32_t arch, int32_t steps, float* params, float* m, float* v,
+                                   int32_t* t, const float* lo, const float* span, float* acts, float* Pz,
+                                   const float* target, float* irr, float* loss, float* dL_dI, float* dL_dP,
+                                   ffrt_stats* stats, const ffrt_adam_hparams* hp, void* stream);
+
 /* ---- kernel shapes (autotuner) ------------------------------------------------------------------- */
 
 /* Number of candidate shapes for the forward (which = 0) or adjoint (which = 1) kernel, and selection. */
@@ -226,6 +268,16 @@ ffrt_status ffrt_plan_time_kernels(ffrt_plan* plan, const float* Pz, float* irr,
  * stream) and keep the fastest for each kernel.  irr and dL_dP are overwritten. */
 ffrt_status ffrt_plan_autotune(ffrt_plan* plan, const float* Pz, float* irr, const float* dL_dI,
                                float* dL_dP, int32_t reps, void* stream);
+
+/* Mean duration (ms) of the generator's forward pass, its back-propagation to the layer vectors, and its
+ * gradient + Adam update (the sparse architecture does both of the latter in one kernel, timed as the
+ * back-propagation; upd_ms is then 0), each launched `reps` times back to back between HIP events on `stream`
+ * after one untimed pass.  params, m and v are updated reps + 1 times (pass copies); acts and Pz are
+ * overwritten; t is read only.  Synchronises the stream. */
+ffrt_status ffrt_plan_time_mlp(ffrt_plan* plan, int32_t arch, float* params, float* m, float* v, const int32_t* t,
+                               const float* lo, const float* span, float* acts, float* Pz, const float* dL_dP,
+                               const ffrt_adam_hparams* hp, int32_t reps, float* fwd_ms, float* bwd_ms,
+                               float* upd_ms, void* stream);
 
 /* ---- inspection ------------------------------------------------------------------------------------ */
 

@@ -298,3 +298,82 @@ def control_xy(prob):
     x = np.repeat(((2.0 * gu - 1.0) * L.r_x)[:, None], L.n_v, axis=1)
     y = np.repeat(((2.0 * gv - 1.0) * L.r_y)[None, :], L.n_u, axis=0)
     return x, y
+
+
+# ---------------------------------------------------------------------------------------------------
+# Dense control-point generator (sec. 2.4, the fully connected architecture): a multi-layer perceptron with
+# the trivial input 1 and three fully connected tanh layers of the control-net size K = n_u n_v, whose output
+# passes through the output correction above.  The parameters of one design are (w1, b1, W2, b2, W3, b3) with
+# w1, b1, b2, b3 of length K and W2, W3 of shape K x K acting as z = W h + b (row i: inputs of neuron i).
+# Control points are indexed row-major over the net, k = i n_v + j, as the control heights are.
+# ---------------------------------------------------------------------------------------------------
+def mlp_forward(params, lo, span):
+    """Activations (h1, h2, y) and control heights P (length K) of one design's generator."""
+    w1, b1, W2, b2, W3, b3 = (np.asarray(a, dtype=np.float64) for a in params)
+    h1 = np.tanh(w1 * 1.0 + b1)          # the single input is the constant 1
+    h2 = np.tanh(W2 @ h1 + b2)
+    y = np.tanh(W3 @ h2 + b3)
+    P = np.asarray(lo, np.float64) + 0.5 * (y + 1.0) * np.asarray(span, np.float64)
+    return (h1, h2, y), P
+
+
+def mlp_backward(params, acts, span, dLdP):
+    """dL/d(w1, b1, W2, b2, W3, b3) from dL/dP by back-propagation through the output correction and the
+    three layers (chain rule with d tanh(z)/dz = 1 - tanh(z)^2)."""
+    w1, b1, W2, b2, W3, b3 = (np.asarray(a, dtype=np.float64) for a in params)
+    h1, h2, y = acts
+    dy = np.asarray(dLdP, np.float64) * 0.5 * np.asarray(span, np.float64)
+    dz3 = dy * (1.0 - y * y)
+    dW3, db3 = np.outer(dz3, h2), dz3
+    dh2 = W3.T @ dz3
+    dz2 = dh2 * (1.0 - h2 * h2)
+    dW2, db2 = np.outer(dz2, h1), dz2
+    dh1 = W2.T @ dz2
+    dz1 = dh1 * (1.0 - h1 * h1)
+    return dz1 * 1.0, dz1, dW2, db2, dW3, db3
+
+
+# The sparse architecture of sec. 2.4: the two K x K layers connect control point (i, j) only to the control
+# points (i + a - p, j + b - q), a in [0, 2p], b in [0, 2q], those whose basis functions share a knot span with
+# its own (the connectivity of a (2p+1) x (2q+1) convolution), with a weight per connection W[c][k],
+# c = a (2q + 1) + b, k = i n_v + j, and a bias per neuron.  Connections that leave the net do not exist.
+def sparse_matrix(Wc, n_u, n_v, p, q):
+    """The K x K matrix M with M[k, s] = W[c][k] for input s = connection c of neuron k, zero elsewhere."""
+    Wc = np.asarray(Wc, np.float64)
+    K = n_u * n_v
+    M = np.zeros((K, K))
+    for i in range(n_u):
+        for j in range(n_v):
+            for a in range(2 * p + 1):
+                for b in range(2 * q + 1):
+                    ii, jj = i + a - p, j + b - q
+                    if 0 <= ii < n_u and 0 <= jj < n_v:
+                        M[i * n_v + j, ii * n_v + jj] = Wc[a * (2 * q + 1) + b, i * n_v + j]
+    return M
+
+
+def sparse_mlp_forward(params, lo, span, n_u, n_v, p, q):
+    """The sparse generator is the dense one with W2, W3 replaced by their K x K matrices."""
+    w1, b1, W2, b2, W3, b3 = params
+    return mlp_forward([w1, b1, sparse_matrix(W2, n_u, n_v, p, q), b2, sparse_matrix(W3, n_u, n_v, p, q), b3],
+                       lo, span)
+
+
+def sparse_mlp_backward(params, acts, span, dLdP, n_u, n_v, p, q):
+    """Gradients of the sparse generator: the dense back-propagation through the K x K matrices, then the
+    gradient of each stored connection weight read off its matrix entry (zero for connections that leave the
+    net)."""
+    w1, b1, W2, b2, W3, b3 = params
+    dw1, db1, dM2, db2, dM3, db3 = mlp_backward(
+        [w1, b1, sparse_matrix(W2, n_u, n_v, p, q), b2, sparse_matrix(W3, n_u, n_v, p, q), b3], acts, span, dLdP)
+    C, K = (2 * p + 1) * (2 * q + 1), n_u * n_v
+    dW2, dW3 = np.zeros((C, K)), np.zeros((C, K))
+    for i in range(n_u):
+        for j in range(n_v):
+            for a in range(2 * p + 1):
+                for b in range(2 * q + 1):
+                    ii, jj = i + a - p, j + b - q
+                    if 0 <= ii < n_u and 0 <= jj < n_v:
+                        c, k, s = a * (2 * q + 1) + b, i * n_v + j, ii * n_v + jj
+                        dW2[c, k], dW3[c, k] = dM2[k, s], dM3[k, s]
+    return dw1, db1, dW2, db2, dW3, db3

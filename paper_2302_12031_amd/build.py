@@ -18,6 +18,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = [
     "ffrt_runtime.cpp",
     "ffrt_common.hip",
+    "ffrt_mlp.hip",
     "ffrt_inst_p3q3nu3.hip",
     "ffrt_inst_p3q3nu5.hip",
     "ffrt_inst_p3q3nu11.hip",

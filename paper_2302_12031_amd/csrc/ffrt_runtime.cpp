@@ -62,7 +62,7 @@ struct ffrt_plan {
     int nd = 0, P = 3, Q = 3, NU = 3;
     const KernelSet* ks = nullptr;
     std::vector<DesignDev> dd;
-    std::vector<int64_t> cp_off, img_off;
+    std::vector<int64_t> cp_off, img_off, mlp_off[2];
     int64_t total_cp = 0, total_img = 0, total_rays = 0;
     int max_cp = 0, max_kt = 0, loss_lb = 1, max_spans = 0;
     int64_t total_spans = 0;
@@ -76,7 +76,7 @@ struct ffrt_plan {
     char* ws = nullptr;
     size_t ws_bytes = 0;
     size_t off_designs = 0, off_bounds = 0, off_sb = 0, off_valid = 0, off_knots = 0, off_bmap = 0, off_slots = 0, need = 0;
-    size_t off_lpart = 0, off_img64 = 0, off_gacc = 0, off_dldi = 0;
+    size_t off_lpart = 0, off_img64 = 0, off_gacc = 0, off_dldi = 0, off_mlpoff = 0, off_mlpvec = 0;
     int num_cu = 256;
     int fwd_cfg = 0, adj_cfg = 0;
     hipGraph_t graph = nullptr;
@@ -95,6 +95,8 @@ struct ffrt_plan {
     unsigned long long* d_img64() const { return reinterpret_cast<unsigned long long*>(ws + off_img64); }
     float* d_gacc() const { return reinterpret_cast<float*>(ws + off_gacc); }
     float* d_dldi() const { return reinterpret_cast<float*>(ws + off_dldi); }
+    int64_t* d_mlpoff(int arch) const { return reinterpret_cast<int64_t*>(ws + off_mlpoff) + (size_t)arch * (nd + 1); }
+    float* d_mlpvec(int k) const { return reinterpret_cast<float*>(ws + off_mlpvec) + (size_t)k * total_cp; }
 };
 
 namespace {
@@ -326,7 +328,8 @@ ffrt_status run_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, float
 // does again on exit).
 ffrt_status run_step(ffrt_plan* pl, float* Pz, const float* target, float* irr, float* loss, float* dLdI,
                      float* dLdP, float* m, float* v, int32_t* t, ffrt_stats* stats, const ffrt_adam_hparams& hp,
-                     hipStream_t s, float* theta = nullptr, const float* lo = nullptr, const float* span = nullptr) {
+                     hipStream_t s, float* theta = nullptr, const float* lo = nullptr, const float* span = nullptr,
+                     bool adam_on_P = true) {
     if (!dLdI) dLdI = pl->d_dldi();
     if (ffrt_status b = run_bounds(pl, Pz, s)) return b;
     ffrt_status st = launch_forward(pl, Pz, stats != nullptr, s);
@@ -336,7 +339,8 @@ ffrt_status run_step(ffrt_plan* pl, float* Pz, const float* target, float* irr, 
     st = launch_adjoint(pl, Pz, dLdI, s);
     if (st) return st;
     AdamArgs adam;
-    adam.Pz = Pz;
+    std::memset(&adam, 0, sizeof adam);
+    adam.Pz = adam_on_P ? Pz : nullptr;
     adam.m = m;
     adam.v = v;
     adam.t = t;
@@ -345,6 +349,22 @@ ffrt_status run_step(ffrt_plan* pl, float* Pz, const float* target, float* irr, 
     adam.lo = lo;
     adam.span = span;
     HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), dLdP, pl->d_valid(), adam, s));
+    return FFRT_OK;
+}
+
+// One step of the dense control-point generator (sec. 2.4): the trace step without Adam on P, then the
+// generator's back-propagation with Adam on its parameters, and its forward pass for the next step's P.
+ffrt_status run_step_mlp(ffrt_plan* pl, int arch, float* par, float* m, float* v, int32_t* t, const float* lo,
+                         const float* span, float* acts, float* Pz, const float* target, float* irr, float* loss,
+                         float* dLdI, float* dLdP, ffrt_stats* stats, const ffrt_adam_hparams& hp, hipStream_t s) {
+    ffrt_status st = run_step(pl, Pz, target, irr, loss, dLdI, dLdP, nullptr, nullptr, nullptr, stats, hp, s, nullptr,
+                              nullptr, nullptr, false);
+    if (st) return st;
+    HIP_TRY(launch_mlp_backward(arch, MLP_ALL, pl->d_designs(), pl->nd, pl->max_cp, pl->d_mlpoff(arch), par, acts, span,
+                                dLdP, pl->d_mlpvec(0), pl->d_mlpvec(1), pl->d_mlpvec(2), nullptr, m, v, t,
+                                pl->d_valid(), &hp, s));
+    HIP_TRY(launch_mlp_forward(arch, pl->d_designs(), pl->nd, pl->max_cp, pl->d_mlpoff(arch), par, acts, lo, span,
+                               Pz, t, pl->d_valid(), s));
     return FFRT_OK;
 }
 
@@ -440,6 +460,15 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
     pl->cp_off.push_back(cp);
     pl->img_off.push_back(img);
     pl->total_cp = cp;
+    int64_t mo[2] = {0, 0};
+    for (const DesignDev& d : pl->dd) {
+        const int64_t K = (int64_t)d.n_u * d.n_v;
+        const int64_t C = (int64_t)(2 * (d.n_u - d.nsu) + 1) * (2 * (d.n_v - d.nsv) + 1);
+        for (int a = 0; a < 2; ++a) pl->mlp_off[a].push_back(mo[a]);
+        mo[FFRT_MLP_DENSE] += 2 * K * K + 4 * K;
+        mo[FFRT_MLP_SPARSE] += 2 * C * K + 4 * K;
+    }
+    for (int a = 0; a < 2; ++a) pl->mlp_off[a].push_back(mo[a]);
     pl->total_img = img;
     for (int sh = 0; sh < N_SHAPES; ++sh) {
         ShapeDims sd = shape_dims(sh);
@@ -482,6 +511,10 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
     off = align256(off + sizeof(float) * (size_t)pl->total_cp);
     pl->off_dldi = off;  // dL/dI of a step whose caller does not want it
     off = align256(off + sizeof(float) * (size_t)pl->total_img);
+    pl->off_mlpoff = off;  // parameter offsets of the control-point generators (dense, sparse)
+    off = align256(off + 2 * sizeof(int64_t) * (size_t)(n_designs + 1));
+    pl->off_mlpvec = off;  // its back-propagation vectors dz3, dh2, dh1
+    off = align256(off + sizeof(float) * 3 * (size_t)pl->total_cp);
     pl->need = off;
     *out = pl;
     return FFRT_OK;
@@ -519,6 +552,9 @@ ffrt_status ffrt_plan_set_workspace(ffrt_plan* plan, void* dev_ptr, size_t bytes
     HIP_TRY(hipMemset(plan->d_slots(), 0, sizeof(ffrt_stats) * NSLOT * plan->nd));
     HIP_TRY(hipMemset(plan->d_img64(), 0, sizeof(unsigned long long) * plan->total_img));
     HIP_TRY(hipMemset(plan->d_gacc(), 0, sizeof(float) * plan->total_cp));
+    for (int a = 0; a < 2; ++a)
+        HIP_TRY(hipMemcpy(plan->d_mlpoff(a), plan->mlp_off[a].data(), sizeof(int64_t) * plan->mlp_off[a].size(),
+                          hipMemcpyHostToDevice));
     if (!plan->knots.empty())
         HIP_TRY(hipMemcpy(plan->d_knots(), plan->knots.data(), sizeof(float) * plan->knots.size(),
                           hipMemcpyHostToDevice));
@@ -642,6 +678,84 @@ ffrt_status ffrt_graph_capture_reparam(ffrt_plan* plan, int32_t steps, float* th
     if (!theta || !lo || !span || !Pz || !target || !irr || !loss || !dL_dP || !m || !v || !t || !hp)
         return fail(FFRT_E_ARG, "null buffer");
     return capture(plan, steps, Pz, target, irr, loss, dL_dI, dL_dP, m, v, t, stats, hp, stream, theta, lo, span);
+}
+
+// The dense GEMV stages one layer's input vector (K floats) in LDS, the sparse kernels five such vectors.
+static constexpr int MLP_MAX_K[2] = {16384, 3072};
+static ffrt_status mlp_check(ffrt_plan* plan, int32_t arch) {
+    if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
+    if (arch != FFRT_MLP_DENSE && arch != FFRT_MLP_SPARSE) return fail(FFRT_E_ARG, "unknown generator architecture");
+    if (plan->max_cp > MLP_MAX_K[arch])
+        return fail(FFRT_E_ARG, arch == FFRT_MLP_DENSE ? "dense generator: a control net exceeds 16384 points"
+                                                       : "sparse generator: a control net exceeds 3072 points");
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_mlp_layout(const ffrt_plan* plan, int32_t arch, int64_t* offsets) {
+    if (!plan || !offsets) return fail(FFRT_E_ARG, "null argument");
+    if (arch != FFRT_MLP_DENSE && arch != FFRT_MLP_SPARSE) return fail(FFRT_E_ARG, "unknown generator architecture");
+    std::copy(plan->mlp_off[arch].begin(), plan->mlp_off[arch].end(), offsets);
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_mlp_forward(ffrt_plan* plan, int32_t arch, const float* params, const float* lo, const float* span,
+                             float* acts, float* Pz, void* stream) {
+    if (ffrt_status st = mlp_check(plan, arch)) return st;
+    if (!params || !lo || !span || !acts || !Pz) return fail(FFRT_E_ARG, "null buffer");
+    HIP_TRY(launch_mlp_forward(arch, plan->d_designs(), plan->nd, plan->max_cp, plan->d_mlpoff(arch), params, acts, lo,
+                               span, Pz,
+                               nullptr, nullptr, (hipStream_t)stream));
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_mlp_backward(ffrt_plan* plan, int32_t arch, const float* params, const float* acts, const float* span,
+                              const float* dL_dP, float* grad, void* stream) {
+    if (ffrt_status st = mlp_check(plan, arch)) return st;
+    if (!params || !acts || !span || !dL_dP || !grad) return fail(FFRT_E_ARG, "null buffer");
+    HIP_TRY(launch_mlp_backward(arch, MLP_ALL, plan->d_designs(), plan->nd, plan->max_cp, plan->d_mlpoff(arch),
+                                const_cast<float*>(params),
+                                acts, span, dL_dP, plan->d_mlpvec(0), plan->d_mlpvec(1), plan->d_mlpvec(2), grad,
+                                nullptr, nullptr, nullptr, nullptr, nullptr, (hipStream_t)stream));
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_step_mlp(ffrt_plan* plan, int32_t arch, float* params, float* m, float* v, int32_t* t, const float* lo,
+                          const float* span, float* acts, float* Pz, const float* target, float* irr, float* loss,
+                          float* dL_dI, float* dL_dP, ffrt_stats* stats, const ffrt_adam_hparams* hp, void* stream) {
+    if (ffrt_status st = mlp_check(plan, arch)) return st;
+    if (!params || !m || !v || !t || !lo || !span || !acts || !Pz || !target || !irr || !loss || !dL_dP || !hp)
+        return fail(FFRT_E_ARG, "null buffer");
+    return run_step_mlp(plan, arch, params, m, v, t, lo, span, acts, Pz, target, irr, loss, dL_dI, dL_dP, stats,
+                        *hp, (hipStream_t)stream);
+}
+
+ffrt_status ffrt_graph_capture_mlp(ffrt_plan* plan, int32_t arch, int32_t steps, float* params, float* m, float* v,
+                                   int32_t* t, const float* lo, const float* span, float* acts, float* Pz,
+                                   const float* target, float* irr, float* loss, float* dL_dI, float* dL_dP,
+                                   ffrt_stats* stats, const ffrt_adam_hparams* hp, void* stream) {
+    if (ffrt_status st = mlp_check(plan, arch)) return st;
+    if (!stream) return fail(FFRT_E_ARG, "graph capture needs a non-default stream");
+    if (steps < 1) return fail(FFRT_E_ARG, "steps must be >= 1");
+    if (!params || !m || !v || !t || !lo || !span || !acts || !Pz || !target || !irr || !loss || !dL_dP || !hp)
+        return fail(FFRT_E_ARG, "null buffer");
+    hipStream_t s = (hipStream_t)stream;
+    if (plan->gexec) { (void)hipGraphExecDestroy(plan->gexec); plan->gexec = nullptr; }
+    if (plan->graph) { (void)hipGraphDestroy(plan->graph); plan->graph = nullptr; }
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    ffrt_status st = FFRT_OK;
+    for (int i = 0; i < steps && st == FFRT_OK; ++i)
+        st = run_step_mlp(plan, arch, params, m, v, t, lo, span, acts, Pz, target, irr, loss, dL_dI, dL_dP, stats,
+                          *hp, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st) { if (g) (void)hipGraphDestroy(g); return st; }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) { (void)hipGraphDestroy(g); return hip_fail(e, "hipGraphInstantiate"); }
+    plan->graph = g;
+    plan->gexec = ge;
+    return FFRT_OK;
 }
 
 ffrt_status ffrt_plan_control_xy(const ffrt_plan* plan, double* x, double* y) {
@@ -771,6 +885,49 @@ ffrt_status ffrt_plan_time_kernels(ffrt_plan* plan, const float* Pz, float* irr,
     if (e != hipSuccess) return hip_fail(e, "kernel timing");
     *fwd_ms = f / reps;
     *adj_ms = a / reps;
+    return FFRT_OK;
+}
+
+ffrt_status ffrt_plan_time_mlp(ffrt_plan* plan, int32_t arch, float* params, float* m, float* v, const int32_t* t,
+                               const float* lo, const float* span, float* acts, float* Pz, const float* dL_dP,
+                               const ffrt_adam_hparams* hp, int32_t reps, float* fwd_ms, float* bwd_ms,
+                               float* upd_ms, void* stream) {
+    if (ffrt_status st = mlp_check(plan, arch)) return st;
+    if (!params || !m || !v || !t || !lo || !span || !acts || !Pz || !dL_dP || !hp || reps < 1 || !fwd_ms ||
+        !bwd_ms || !upd_ms)
+        return fail(FFRT_E_ARG, "bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t* po = plan->d_mlpoff(arch);
+    auto fwd = [&]() {
+        return launch_mlp_forward(arch, plan->d_designs(), plan->nd, plan->max_cp, po, params, acts, lo, span, Pz,
+                                  nullptr, nullptr, s);
+    };
+    auto bwd = [&](int part) {
+        return launch_mlp_backward(arch, part, plan->d_designs(), plan->nd, plan->max_cp, po, params, acts, span,
+                                   dL_dP, plan->d_mlpvec(0), plan->d_mlpvec(1), plan->d_mlpvec(2), nullptr, m, v, t,
+                                   nullptr, hp, s);
+    };
+    hipEvent_t ev[6];
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    hipError_t e = fwd();  // one untimed pass of each part
+    if (e == hipSuccess) e = bwd(MLP_ALL);
+    const int parts[2] = {MLP_BACKPROP, MLP_UPDATE};
+    if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = fwd();
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    for (int k = 0; k < 2; ++k) {
+        if (e == hipSuccess) e = hipEventRecord(ev[2 + 2 * k], s);
+        for (int r = 0; r < reps && e == hipSuccess; ++r) e = bwd(parts[k]);
+        if (e == hipSuccess) e = hipEventRecord(ev[3 + 2 * k], s);
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(ev[5]);
+    float ms[3] = {0.0f, 0.0f, 0.0f};
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipEventElapsedTime(&ms[k], ev[2 * k], ev[2 * k + 1]);
+    for (auto x : ev) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return hip_fail(e, "generator timing");
+    *fwd_ms = ms[0] / reps;
+    *bwd_ms = ms[1] / reps;
+    *upd_ms = ms[2] / reps;
     return FFRT_OK;
 }
 

@@ -59,6 +59,8 @@ STATS_FIELDS = ["flux_on_screen", "n_traced", "n_hit", "n_miss_entry", "n_side_w
 STATS_DTYPE = np.dtype([(STATS_FIELDS[0], np.float32)] + [(f, np.uint32) for f in STATS_FIELDS[1:]])
 STATS_BYTES = STATS_DTYPE.itemsize
 
+MLP_DENSE, MLP_SPARSE = 0, 1
+
 HEADER_FUNCTIONS = [
     "ffrt_plan_create", "ffrt_plan_destroy", "ffrt_plan_workspace_size", "ffrt_plan_set_workspace",
     "ffrt_plan_layout", "ffrt_plan_num_designs", "ffrt_plan_num_rays", "ffrt_forward", "ffrt_loss",
@@ -68,7 +70,8 @@ HEADER_FUNCTIONS = [
     "ffrt_config_name", "ffrt_plan_set_config", "ffrt_plan_get_config", "ffrt_plan_autotune",
     "ffrt_trace_rays", "ffrt_rng", "ffrt_status_string", "ffrt_last_error",
     "ffrt_reparam_apply", "ffrt_reparam_grad", "ffrt_step_reparam", "ffrt_graph_capture_reparam",
-    "ffrt_plan_control_xy",
+    "ffrt_plan_control_xy", "ffrt_mlp_layout", "ffrt_mlp_forward", "ffrt_mlp_backward", "ffrt_step_mlp",
+    "ffrt_graph_capture_mlp", "ffrt_plan_time_mlp",
 ]
 
 _lib = None
@@ -112,6 +115,12 @@ def lib():
             "ffrt_step_reparam": [vp] + [vp] * 13 + [P(CAdam), vp],
             "ffrt_graph_capture_reparam": [vp, i32] + [vp] * 13 + [P(CAdam), vp],
             "ffrt_plan_control_xy": [vp, vp, vp],
+            "ffrt_mlp_layout": [vp, i32, P(i64)],
+            "ffrt_mlp_forward": [vp, i32, vp, vp, vp, vp, vp, vp],
+            "ffrt_mlp_backward": [vp, i32, vp, vp, vp, vp, vp, vp],
+            "ffrt_step_mlp": [vp, i32] + [vp] * 14 + [P(CAdam), vp],
+            "ffrt_graph_capture_mlp": [vp, i32, i32] + [vp] * 14 + [P(CAdam), vp],
+            "ffrt_plan_time_mlp": [vp, i32] + [vp] * 9 + [P(CAdam), i32] + [P(ctypes.c_float)] * 3 + [vp],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -354,6 +363,104 @@ class Plan:
             self.h, steps, _ptr(st["theta"]), _ptr(st["lo"]), _ptr(st["span"]), _ptr(st["Pz"]), _ptr(target),
             _ptr(st["irr"]), _ptr(st["loss"]), _ptr(st.get("dLdI")), _ptr(st["dLdP"]), _ptr(st["m"]), _ptr(st["v"]),
             _ptr(st["t"]), _ptr(st["stats"]), ctypes.byref(hp.c()), _stream(stream)), "ffrt_graph_capture_reparam")
+
+    # ---- control-point generators (sec. 2.4): three K-wide tanh layers, then the output correction ------
+    # arch: MLP_DENSE (fully connected K x K layers) or MLP_SPARSE (weights W[c][k] over the (2p+1) x (2q+1)
+    # neighbourhood of each control point)
+    def mlp_offsets(self, arch=0):
+        """Offsets of each design's generator parameters in the packed parameter vector (n_designs + 1)."""
+        off = (ctypes.c_int64 * (self.n_designs + 1))()
+        _check(lib().ffrt_mlp_layout(self.h, arch, off), "ffrt_mlp_layout")
+        return list(off)
+
+    def _mlp_shapes(self, d, arch):
+        p = self.problems[d].lens
+        K = p.n_u * p.n_v
+        Wshape = (K, K) if arch == MLP_DENSE else ((2 * p.p + 1) * (2 * p.q + 1), K)
+        return [(K,), (K,), Wshape, (K,), Wshape, (K,)]
+
+    def pack_mlp(self, per_design, arch=0):
+        """Pack per-design (w1, b1, W2, b2, W3, b3) tuples into one float32 device vector."""
+        parts = []
+        for d, prm in enumerate(per_design):
+            for a, shp in zip(prm, self._mlp_shapes(d, arch)):
+                a = np.asarray(a, np.float32)
+                if a.shape != shp:
+                    raise FfrtError(f"design {d}: generator parameter of shape {a.shape}, expected {shp}")
+                parts.append(torch.as_tensor(a).reshape(-1))
+        return torch.cat(parts).to(self.device)
+
+    def unpack_mlp(self, flat, arch=0):
+        """Inverse of pack_mlp: per-design (w1, b1, W2, b2, W3, b3) views of a packed vector."""
+        off, out = self.mlp_offsets(arch), []
+        for d in range(self.n_designs):
+            o, views = off[d], []
+            for shp in self._mlp_shapes(d, arch):
+                n = int(np.prod(shp))
+                views.append(flat[o:o + n].reshape(shp))
+                o += n
+            out.append(tuple(views))
+        return out
+
+    def mlp_forward(self, params, lo, span, acts=None, Pz=None, arch=0, stream=None):
+        self._f32(params, self.mlp_offsets(arch)[-1], "params")
+        for a, n in ((lo, "lo"), (span, "span")):
+            self._f32(a, self.total_cp, n)
+        if acts is None:
+            acts = torch.empty(3 * self.total_cp, dtype=torch.float32, device=self.device)
+        if Pz is None:
+            Pz = torch.empty(self.total_cp, dtype=torch.float32, device=self.device)
+        self._f32(acts, 3 * self.total_cp, "acts")
+        _check(lib().ffrt_mlp_forward(self.h, arch, _ptr(params), _ptr(lo), _ptr(span), _ptr(acts), _ptr(Pz),
+                                      _stream(stream)), "ffrt_mlp_forward")
+        return acts, Pz
+
+    def mlp_backward(self, params, acts, span, dLdP, grad=None, arch=0, stream=None):
+        n = self.mlp_offsets(arch)[-1]
+        self._f32(params, n, "params")
+        self._f32(acts, 3 * self.total_cp, "acts")
+        for a, nm in ((span, "span"), (dLdP, "dLdP")):
+            self._f32(a, self.total_cp, nm)
+        if grad is None:
+            grad = torch.empty(n, dtype=torch.float32, device=self.device)
+        self._f32(grad, n, "grad")
+        _check(lib().ffrt_mlp_backward(self.h, arch, _ptr(params), _ptr(acts), _ptr(span), _ptr(dLdP), _ptr(grad),
+                                       _stream(stream)), "ffrt_mlp_backward")
+        return grad
+
+    def new_mlp_state(self, params, lo, span, arch=0, with_dLdI=False):
+        """Optimisation state on the generator parameters; acts and Pz are kept equal to the forward pass of
+        params by the steps."""
+        acts, Pz = self.mlp_forward(params, lo, span, arch=arch)
+        st = self.new_state(Pz, with_dLdI)
+        st.update(params=params, lo=lo, span=span, acts=acts, m=torch.zeros_like(params),
+                  v=torch.zeros_like(params), arch=arch)
+        return st
+
+    def step_mlp(self, st, target, hp=AdamHP(), stream=None):
+        _check(lib().ffrt_step_mlp(self.h, st["arch"], _ptr(st["params"]), _ptr(st["m"]), _ptr(st["v"]), _ptr(st["t"]),
+                                   _ptr(st["lo"]), _ptr(st["span"]), _ptr(st["acts"]), _ptr(st["Pz"]), _ptr(target),
+                                   _ptr(st["irr"]), _ptr(st["loss"]), _ptr(st.get("dLdI")), _ptr(st["dLdP"]),
+                                   _ptr(st["stats"]), ctypes.byref(hp.c()), _stream(stream)), "ffrt_step_mlp")
+
+    def graph_capture_mlp(self, st, target, steps=1, hp=AdamHP(), stream=None):
+        _check(lib().ffrt_graph_capture_mlp(
+            self.h, st["arch"], steps, _ptr(st["params"]), _ptr(st["m"]), _ptr(st["v"]), _ptr(st["t"]), _ptr(st["lo"]),
+            _ptr(st["span"]), _ptr(st["acts"]), _ptr(st["Pz"]), _ptr(target), _ptr(st["irr"]), _ptr(st["loss"]),
+            _ptr(st.get("dLdI")), _ptr(st["dLdP"]), _ptr(st["stats"]), ctypes.byref(hp.c()), _stream(stream)),
+            "ffrt_graph_capture_mlp")
+
+    def time_mlp(self, st, dLdP, reps=20, hp=AdamHP(), stream=None):
+        """Mean (forward, back-propagation, gradient + Adam) generator durations in ms (HIP events on the
+        stream), on copies of the state's parameters and moments."""
+        par, m, v = st["params"].clone(), st["m"].clone(), st["v"].clone()
+        acts, Pz = torch.empty_like(st["acts"]), torch.empty_like(st["Pz"])
+        f, b, u = ctypes.c_float(), ctypes.c_float(), ctypes.c_float()
+        _check(lib().ffrt_plan_time_mlp(self.h, st["arch"], _ptr(par), _ptr(m), _ptr(v), _ptr(st["t"]),
+                                        _ptr(st["lo"]), _ptr(st["span"]), _ptr(acts), _ptr(Pz), _ptr(dLdP),
+                                        ctypes.byref(hp.c()), reps, ctypes.byref(f), ctypes.byref(b),
+                                        ctypes.byref(u), _stream(stream)), "ffrt_plan_time_mlp")
+        return f.value, b.value, u.value
 
     def time_kernels(self, Pz, irr, dLdI, dLdP, reps=20, stream=None):
         """Mean (forward, adjoint) trace-kernel durations in ms (HIP events on the stream)."""

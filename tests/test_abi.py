@@ -117,3 +117,20 @@ def test_control_xy_matches_oracle_greville_positions():
         np.testing.assert_allclose(y[off:off + n], oy.ravel(), rtol=0, atol=1e-13)
         off += n
     ffrt.lib().ffrt_plan_destroy(h)
+
+
+def test_mlp_layout_packs_each_design_generator():
+    """ffrt_mlp_layout (host side): design d's dense generator holds 2 K^2 + 4 K parameters, K = n_u n_v, its
+    sparse one 2 C K + 4 K with C = (2p+1)(2q+1); an unknown architecture is rejected."""
+    probs = [W.collimated_problem(32, 9, 16), W.point_problem(16, 12, 32), W.collimated_problem(32, 7, 16)]
+    probs = [replace(p, lens=replace(p.lens, p=5, q=3)) for p in probs]      # one plan shares its degrees
+    h = ffrt.create_plan_handle(probs)
+    off = (ctypes.c_int64 * (len(probs) + 1))()
+    Ks = [p.lens.n_u * p.lens.n_v for p in probs]
+    Cs = [(2 * p.lens.p + 1) * (2 * p.lens.q + 1) for p in probs]
+    assert ffrt.lib().ffrt_mlp_layout(h, ffrt.MLP_DENSE, off) == 0
+    assert list(off) == [0] + np.cumsum([2 * K * K + 4 * K for K in Ks]).tolist()
+    assert ffrt.lib().ffrt_mlp_layout(h, ffrt.MLP_SPARSE, off) == 0
+    assert list(off) == [0] + np.cumsum([2 * C * K + 4 * K for K, C in zip(Ks, Cs)]).tolist()
+    assert ffrt.lib().ffrt_mlp_layout(h, 2, off) != 0
+    ffrt.lib().ffrt_plan_destroy(h)

@@ -524,3 +524,157 @@ def test_control_xy_are_greville_positions():
         assert abs(Nu @ x[:, 0] - (2 * u - 1) * L.r_x) < 1e-13
         Nv = O.basis_all(L.q, L.n_v, u)
         assert abs(Nv @ y[0, :] - (2 * u - 1) * L.r_y) < 1e-13
+
+
+# ------------------------------------------------------------------------------------------------
+# Dense control-point generator (sec. 2.4): three fully connected tanh layers of control-net size
+# ------------------------------------------------------------------------------------------------
+def _mlp_params(K, seed, scale=0.6):
+    g = np.random.default_rng(seed)
+    return [g.normal(0, scale, K), g.normal(0, scale, K), g.normal(0, scale / np.sqrt(K), (K, K)),
+            g.normal(0, scale, K), g.normal(0, scale / np.sqrt(K), (K, K)), g.normal(0, scale, K)]
+
+
+def test_mlp_forward_matches_torch_linear_layers():
+    """The forward pass equals torch.nn.Linear layers (weight [out, in], input 1) in float64, followed by
+    the output correction."""
+    import torch
+    K = 7
+    prm = _mlp_params(K, 1)
+    lo, span = np.linspace(1.8, 2.1, K), np.linspace(0.2, 0.5, K)
+    net = torch.nn.Sequential(torch.nn.Linear(1, K), torch.nn.Tanh(), torch.nn.Linear(K, K), torch.nn.Tanh(),
+                              torch.nn.Linear(K, K), torch.nn.Tanh()).double()
+    with torch.no_grad():
+        net[0].weight.copy_(torch.tensor(prm[0])[:, None])
+        net[0].bias.copy_(torch.tensor(prm[1]))
+        net[2].weight.copy_(torch.tensor(prm[2]))
+        net[2].bias.copy_(torch.tensor(prm[3]))
+        net[4].weight.copy_(torch.tensor(prm[4]))
+        net[4].bias.copy_(torch.tensor(prm[5]))
+        y = net(torch.ones(1, 1, dtype=torch.float64))[0].numpy()
+    (h1, h2, yo), P = O.mlp_forward(prm, lo, span)
+    np.testing.assert_allclose(yo, y, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(P, lo + 0.5 * (y + 1.0) * span, rtol=0, atol=1e-15)
+
+
+def test_mlp_backward_matches_central_fd():
+    """Every parameter's gradient of J = c . P against central differences (fp64, h = 1e-6)."""
+    K = 5
+    prm = _mlp_params(K, 2)
+    lo, span = np.full(K, 1.9), np.linspace(0.1, 0.6, K)
+    c = np.random.default_rng(3).normal(size=K)
+    acts, _ = O.mlp_forward(prm, lo, span)
+    grads = O.mlp_backward(prm, acts, span, c)
+    h = 1e-6
+    for a, (p, g) in enumerate(zip(prm, grads)):
+        assert g.shape == p.shape
+        fd = np.zeros_like(p)
+        for idx in np.ndindex(p.shape):
+            q = [x.copy() for x in prm]
+            q[a][idx] += h
+            Jp = c @ O.mlp_forward(q, lo, span)[1]
+            q[a][idx] -= 2 * h
+            Jm = c @ O.mlp_forward(q, lo, span)[1]
+            fd[idx] = (Jp - Jm) / (2 * h)
+        np.testing.assert_allclose(g, fd, rtol=0, atol=1e-8 * max(1.0, np.abs(fd).max()), err_msg=str(a))
+
+
+def test_mlp_hidden_unit_symmetries():
+    """Relabelling the neurons of a hidden layer (with the weights that touch them) or flipping the sign of
+    one (tanh is odd) leaves the output unchanged; negating every bias and w1 negates y."""
+    K = 6
+    prm = _mlp_params(K, 4)
+    lo, span = np.zeros(K), np.ones(K)
+    y0 = O.mlp_forward(prm, lo, span)[0][2]
+    pi = np.random.default_rng(5).permutation(K)
+    w1, b1, W2, b2, W3, b3 = prm
+    y1 = O.mlp_forward([w1[pi], b1[pi], W2[:, pi], b2, W3, b3], lo, span)[0][2]
+    y2 = O.mlp_forward([w1, b1, W2[pi, :], b2[pi], W3[:, pi], b3], lo, span)[0][2]
+    s = np.ones(K)
+    s[2] = -1.0
+    y3 = O.mlp_forward([w1 * s, b1 * s, W2 * s[None, :], b2, W3, b3], lo, span)[0][2]
+    y4 = O.mlp_forward([w1, b1, W2 * s[:, None], b2 * s, W3 * s[None, :], b3], lo, span)[0][2]
+    for y in (y1, y2, y3, y4):
+        np.testing.assert_allclose(y, y0, rtol=0, atol=1e-15)
+    y5 = O.mlp_forward([-w1, -b1, W2, -b2, W3, -b3], lo, span)[0][2]
+    np.testing.assert_allclose(y5, -y0, rtol=0, atol=1e-15)
+
+
+def test_mlp_at_zero_is_the_no_network_case():
+    """With every weight and the first two layers' biases zero, P = reparam(b3) and only b3 receives a
+    gradient, equal to the no-network chain rule at theta = b3: the generator started at zero follows the
+    no-network optimisation exactly."""
+    K = 9
+    b3 = np.random.default_rng(6).normal(0, 0.4, K)
+    prm = [np.zeros(K), np.zeros(K), np.zeros((K, K)), np.zeros(K), np.zeros((K, K)), b3]
+    lo, span = np.linspace(1.8, 2.0, K), np.linspace(0.3, 0.4, K)
+    g = np.random.default_rng(7).normal(size=K)
+    acts, P = O.mlp_forward(prm, lo, span)
+    np.testing.assert_allclose(P, O.reparam(b3, lo, span), rtol=0, atol=1e-15)
+    grads = O.mlp_backward(prm, acts, span, g)
+    for a in range(5):
+        assert not np.any(grads[a]), a
+    np.testing.assert_allclose(grads[5], O.reparam_grad(b3, span, g), rtol=1e-14, atol=0)
+
+
+def _sparse_params(n_u, n_v, p, q, seed, scale=0.5):
+    g = np.random.default_rng(seed)
+    K, C = n_u * n_v, (2 * p + 1) * (2 * q + 1)
+    return [g.normal(0, scale, K), g.normal(0, scale, K), g.normal(0, scale / np.sqrt(C), (C, K)),
+            g.normal(0, scale, K), g.normal(0, scale / np.sqrt(C), (C, K)), g.normal(0, scale, K)]
+
+
+@pytest.mark.parametrize("n_u,n_v,p,q", [(5, 4, 1, 2), (6, 6, 3, 3)])
+def test_sparse_layer_with_a_shared_kernel_is_a_convolution(n_u, n_v, p, q):
+    """With one kernel shared by every neuron the sparse layer is torch's zero-padded (2p+1) x (2q+1)
+    convolution (cross-correlation) of the layer input laid out on the control net."""
+    import torch
+    g = np.random.default_rng(8)
+    ker = g.normal(size=(2 * p + 1, 2 * q + 1))
+    x = g.normal(size=(n_u, n_v))
+    Wc = np.repeat(ker.reshape(-1, 1), n_u * n_v, axis=1)
+    z = O.sparse_matrix(Wc, n_u, n_v, p, q) @ x.ravel()
+    ref = torch.nn.functional.conv2d(torch.tensor(x)[None, None], torch.tensor(ker)[None, None],
+                                     padding=(p, q))[0, 0].numpy()
+    np.testing.assert_allclose(z, ref.ravel(), rtol=0, atol=1e-13)
+
+
+def test_sparse_mlp_backward_matches_central_fd():
+    """Every stored parameter's gradient of J = c . P against central differences, zero for connections that
+    leave the net."""
+    n_u, n_v, p, q = 4, 5, 1, 2
+    prm = _sparse_params(n_u, n_v, p, q, 9)
+    K = n_u * n_v
+    lo, span = np.full(K, 1.9), np.linspace(0.1, 0.6, K)
+    c = np.random.default_rng(10).normal(size=K)
+    acts, _ = O.sparse_mlp_forward(prm, lo, span, n_u, n_v, p, q)
+    grads = O.sparse_mlp_backward(prm, acts, span, c, n_u, n_v, p, q)
+    h = 1e-6
+    for a, (pa, g) in enumerate(zip(prm, grads)):
+        assert g.shape == pa.shape
+        fd = np.zeros_like(pa)
+        for idx in np.ndindex(pa.shape):
+            qq = [x.copy() for x in prm]
+            qq[a][idx] += h
+            Jp = c @ O.sparse_mlp_forward(qq, lo, span, n_u, n_v, p, q)[1]
+            qq[a][idx] -= 2 * h
+            Jm = c @ O.sparse_mlp_forward(qq, lo, span, n_u, n_v, p, q)[1]
+            fd[idx] = (Jp - Jm) / (2 * h)
+        np.testing.assert_allclose(g, fd, rtol=0, atol=1e-8 * max(1.0, np.abs(fd).max()), err_msg=str(a))
+    # the corner neuron (0, 0) has no input at a = 0 (row -1): those weights are inert
+    assert grads[2][0:2 * q + 1, 0].tolist() == [0.0] * (2 * q + 1)
+
+
+def test_sparse_mlp_at_zero_is_the_no_network_case():
+    n_u, n_v, p, q = 5, 5, 3, 3
+    K, C = 25, 49
+    b3 = np.random.default_rng(11).normal(0, 0.4, K)
+    prm = [np.zeros(K), np.zeros(K), np.zeros((C, K)), np.zeros(K), np.zeros((C, K)), b3]
+    lo, span = np.full(K, 1.8), np.full(K, 0.4)
+    g = np.random.default_rng(12).normal(size=K)
+    acts, P = O.sparse_mlp_forward(prm, lo, span, n_u, n_v, p, q)
+    np.testing.assert_allclose(P, O.reparam(b3, lo, span), rtol=0, atol=1e-15)
+    grads = O.sparse_mlp_backward(prm, acts, span, g, n_u, n_v, p, q)
+    for a in range(5):
+        assert not np.any(grads[a]), a
+    np.testing.assert_allclose(grads[5], O.reparam_grad(b3, span, g), rtol=1e-14, atol=0)
