@@ -37,6 +37,11 @@ FLOPS = {
     # point sources: fixed part + per Newton iteration (surface value and slope, step)
     "point": {"forward": 420, "adjoint": 1060, "newton_iter": 224},
 }
+# Triangle mesh (sec. 2.2.2) instead of the root: per visited cell, four span-basis evaluations at the
+# cell's nodes (~264), four corner heights (~96) and two plane tests (~30); the adjoint adds the hit cell's
+# barycentric basis weights (~64) and re-walks the cells.  A collimated ray visits exactly one cell.
+MESH_CELL_FLOPS = 390
+MESH_ADJ_EXTRA = 64
 # Algorithmic HBM bytes of the generator per design with K control points and n parameters (fp32): the
 # forward reads the two weight matrices (dense 2 K^2, sparse 2 C K floats; vectors of K are negligible); the
 # dense back-propagation reads them again; the gradient + Adam kernel reads and writes parameters and both
@@ -50,7 +55,7 @@ def _sha(path):
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
-def _traffic(kernel, workload):
+def _traffic(kernel, workload, source="trace.hpp"):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it matches the current source."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_hbm_counters.md")
     if not os.path.exists(path):
@@ -60,8 +65,8 @@ def _traffic(kernel, workload):
         if ":" in line and line.strip().startswith("- "):
             k, v = line.strip()[2:].split(":", 1)
             fields[k.strip()] = v.strip()
-    src = os.path.join(ROOT, "paper_2302_12031_amd", "csrc", "trace.hpp")
-    if fields.get("trace.hpp sha256/16") != _sha(src):
+    src = os.path.join(ROOT, "paper_2302_12031_amd", "csrc", source)
+    if fields.get(f"{source} sha256/16") != _sha(src):
         return None
     try:
         return float(fields["HBM bytes per launch"])
@@ -92,6 +97,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "tophat", "tophat64"])
     ap.add_argument("--generator", default="none", choices=["none", "dense", "sparse"])
+    ap.add_argument("--mesh", type=int, default=0,
+                    help="trace the triangle mesh of sec. 2.2.2 with this many rectangles per knot span and axis")
     ap.add_argument("--no-fd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -129,6 +136,8 @@ def main():
         wl = W.tophat(rays_side=1024, cps_side=64, det_side=128)
     else:
         wl = W.WORKLOADS[args.workload]()
+    if args.mesh:
+        wl = W.with_mesh(wl, args.mesh)
     plan = ffrt.Plan(wl.problems)
     T = plan.pack_img(wl.targets)
     arch = {"none": None, "dense": ffrt.MLP_DENSE, "sparse": ffrt.MLP_SPARSE}[args.generator]
@@ -207,7 +216,12 @@ def main():
         tot = 0.0
         for p in wl.problems:
             k = "collimated" if p.source.kind == 0 else "point"
-            f = FLOPS[k][kernel] + FLOPS[k]["newton_iter"] * iters
+            if p.options.mesh_u:
+                cells = 1.0 if k == "collimated" else iters
+                f = FLOPS[k][kernel] + MESH_CELL_FLOPS * (cells + (kernel == "adjoint"))
+                f += MESH_ADJ_EXTRA if kernel == "adjoint" else 0
+            else:
+                f = FLOPS[k][kernel] + FLOPS[k]["newton_iter"] * iters
             tot += f * p.num_rays()
         return tot
 
@@ -218,7 +232,8 @@ def main():
             "frac": achieved / PEAK_FP32_TFLOPS, "traffic": _traffic(dom, args.workload),
             "kernel": f"k_{dom}", "kernel_ms": dom_ms, "flops_per_launch": flops(dom),
             "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS,
-            "forward_ms": fwd_ms, "adjoint_ms": adj_ms, "newton_iters_mean": iters}
+            "forward_ms": fwd_ms, "adjoint_ms": adj_ms, "newton_iters_mean": iters,
+            "search_steps": "mesh cells visited" if args.mesh else "Newton iterations"}
 
     generator = None
     if arch is not None:
@@ -238,7 +253,8 @@ def main():
         gms, gbytes = groups[gname]
         gach = gbytes / (gms * 1e-3) / 1e9
         groof = {"bound": "hbm", "achieved": gach, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gach / PEAK_HBM_GBS,
-                 "traffic": None, "kernel": kern[gname], "kernel_ms": gms, "bytes_per_launch": gbytes}
+                 "traffic": _traffic(kern[gname], f"{args.workload}-{args.generator}", "ffrt_mlp.hip"),
+                 "kernel": kern[gname], "kernel_ms": gms, "bytes_per_launch": gbytes}
         generator = {"arch": args.generator, "parameters": n_par, "control_points": Ks,
                      "ms": {k: v[0] for k, v in groups.items()},
                      "bytes_per_launch": {k: v[1] for k, v in groups.items()}, "roofline": groof}
@@ -251,6 +267,7 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
            "config": {"workload": wl.name, "designs": len(wl.problems), "rays_per_step": rays,
+                      "intersection": f"triangle mesh {args.mesh}x{args.mesh} per span" if args.mesh else "exact root",
                       "sources": sorted(kinds), "graph": f"{args.steps} captured steps",
                       "kernel_shapes": {"forward": cfg[0], "adjoint": cfg[1]}},
            "adam_steps_per_s": 1e3 / ms_step, "wall_s_timed": t_wall,

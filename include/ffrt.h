@@ -85,9 +85,15 @@ typedef struct {
 } ffrt_detector;
 
 /* fresnel: 1 applies Schlick's approximation at both faces (cosine taken on the air side), 0 does not.
- * newton_max_iter: iteration cap of the freeform intersection (point sources), 1..32. */
+ * newton_max_iter: iteration cap of the freeform intersection (point sources), 1..32.
+ * mesh_u, mesh_v: 0 (both) intersects the B-spline itself; 1..64 (both) intersects the paper's triangle
+ * mesh instead (sec. 2.2.2): every knot span product divided into mesh_u x mesh_v equal rectangles, each
+ * split into a lower-left and an upper-right triangle with corners on the surface.  The hit lies on the
+ * mesh; the refraction uses the B-spline's normal at the hit, and the gradient follows the triangle's
+ * corner heights. */
 typedef struct {
     int32_t fresnel, newton_max_iter;
+    int32_t mesh_u, mesh_v;
 } ffrt_options;
 
 typedef struct {

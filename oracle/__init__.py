@@ -40,7 +40,8 @@ class OrcProblem(ctypes.Structure):
         ("R_x", ctypes.c_double), ("R_y", ctypes.c_double), ("z_screen", ctypes.c_double),
         ("alpha", ctypes.c_double),
         ("nu_x", ctypes.c_int32), ("nu_y", ctypes.c_int32), ("ghost", ctypes.c_int32),
-        ("fresnel", ctypes.c_int32), ("pad_", ctypes.c_int32),
+        ("fresnel", ctypes.c_int32), ("mesh_u", ctypes.c_int32), ("mesh_v", ctypes.c_int32),
+        ("pad_", ctypes.c_int32),
     ]
 
 
@@ -116,6 +117,7 @@ def to_struct(prob):
     s.n_x, s.n_y, s.R_x, s.R_y = D.n_x, D.n_y, D.R_x, D.R_y
     s.z_screen, s.alpha, s.nu_x, s.nu_y, s.ghost = D.z_screen, D.alpha, D.nu_x, D.nu_y, D.ghost
     s.fresnel = O.fresnel
+    s.mesh_u, s.mesh_v = getattr(O, "mesh_u", 0), getattr(O, "mesh_v", 0)
     return s
 
 

@@ -160,6 +160,8 @@ bool valid_problem(const orc_problem* pr) {
     if (pr->nu_x < 1 || pr->nu_y < 1 || pr->nu_x % 2 == 0 || pr->nu_y % 2 == 0) return false;
     if (!(pr->R_x > 0) || !(pr->R_y > 0) || !(pr->alpha > 0)) return false;
     if (pr->kind < 0 || pr->kind > 2) return false;
+    if (pr->mesh_u < 0 || pr->mesh_v < 0 || pr->mesh_u > 64 || pr->mesh_v > 64 || (pr->mesh_u == 0) != (pr->mesh_v == 0))
+        return false;
     if (pr->kind != 0) {
         if (!(pr->pos_z < pr->z_in)) return false;
         if (!(pr->half_angle >= 0.0 && pr->half_angle < M_PI / 2)) return false;
@@ -441,6 +443,189 @@ Root find_root(const Geo& g, const double* Pz, const Entry& E, bool ignore_apert
     return R;
 }
 
+// ---------------------------------------------------------------------------------------------------
+// Triangle-mesh intersection (sec. 2.2.2, the paper's own intersector).  Each knot span product is divided
+// into mesh_u x mesh_v rectangles of equal size in (u, v); each rectangle into a lower-left triangle (its
+// left and lower edges closed, the diagonal open) and an upper-right one (the diagonal closed, its right and
+// upper edges open, except on the border of [0,1]^2), whose corners lie on the surface: together they
+// partition the domain.  The hit is the ray's first point (smallest t >= 0) on that piecewise-linear
+// surface.  Work in (u, v, z): o_u = (o_x / r_x + 1) / 2, d_u = d_x / (2 r_x), likewise v.
+//   Phase 1: the ray must cross the box [0,1]^2 x [min P^z, max P^z]; then rectangles of knot span
+//            products are split into at most four and tested against their own boxes (the heights of the
+//            control points acting on them, by the strong convex hull property) down to single products.
+//   Phase 2/3: every triangle of a surviving span product is intersected as a plane T(u,v) = A u + B v + C
+//            through its three corners, and the hit kept if it lies in the triangle's (u, v) domain.  (The
+//            paper first selects candidate triangles by where the ray's (u, v) line crosses the grid lines;
+//            testing all of them here gives the same first hit.)
+// ---------------------------------------------------------------------------------------------------
+struct MeshHit {
+    bool hit;
+    double t;
+    int su, sv;      // knot span indices (U[su] <= u < U[su + 1])
+    int k, l;        // rectangle within the span product
+    int upper;       // 0 lower-left, 1 upper-right triangle
+};
+
+// Height Z(u, v) at a mesh node of span product (su, sv), evaluated with that product's basis functions
+// (which the paper notes depend on the node only, not on P).
+template <class S>
+S node_height(const Geo& g, const S* Pl, int su, int sv, double u, double v) {
+    double Nu[MAXDEG + 1], dNu[MAXDEG + 1], Nv[MAXDEG + 1], dNv[MAXDEG + 1];
+    basis<double>(g.p, g.U.data(), su, u, Nu, dNu, nullptr);
+    basis<double>(g.q, g.V.data(), sv, v, Nv, dNv, nullptr);
+    S h = 0.0;
+    for (int a = 0; a <= g.p; ++a)
+        for (int b = 0; b <= g.q; ++b) h = h + Pl[a * (g.q + 1) + b] * (Nu[a] * Nv[b]);
+    return h;
+}
+
+// Corner coordinates of rectangle (k, l) of span product (su, sv).
+void mesh_cell(const Geo& g, int su, int sv, int k, int l, double* u0, double* du, double* v0, double* dv) {
+    *du = (g.U[su + 1] - g.U[su]) / g.pr.mesh_u;
+    *dv = (g.V[sv + 1] - g.V[sv]) / g.pr.mesh_v;
+    *u0 = g.U[su] + k * *du;
+    *v0 = g.V[sv] + l * *dv;
+}
+
+// Plane of a triangle: T(u, v) = z_c + A (u - u_c) + B (v - v_c) through corner c, from the corner heights
+// z00 = Z(u_k, v_l), z10 = Z(u_k+1, v_l), z01 = Z(u_k, v_l+1), z11 = Z(u_k+1, v_l+1).
+template <class S>
+void tri_plane(int upper, const S* z, double du, double dv, S* A, S* B) {
+    if (!upper) { *A = (z[1] - z[0]) / du; *B = (z[2] - z[0]) / dv; }   // corners 00, 10, 01
+    else { *A = (z[3] - z[2]) / du; *B = (z[3] - z[1]) / dv; }          // corners 11, 01, 10
+}
+
+// Whether (a, b) = ((u - u_k)/du, (v - v_l)/dv) lies in the triangle; last_u / last_v close the open edges
+// on the border u = 1 / v = 1 of the domain.
+bool in_triangle(int upper, double a, double b, bool last_u, bool last_v) {
+    if (!upper) return a >= 0.0 && b >= 0.0 && a + b < 1.0;
+    return a + b >= 1.0 && (a < 1.0 || (last_u && a <= 1.0)) && (b < 1.0 || (last_v && b <= 1.0));
+}
+
+// The ray's hit on triangle (k, l, upper) of span product (su, sv), if any, with t in [t0, t1].
+bool mesh_triangle_hit(const Geo& g, const double* Pz, const double* o, const double* d, int su, int sv, int k,
+                       int l, int upper, double t0, double t1, double* t_out) {
+    double u0, du, v0, dv;
+    mesh_cell(g, su, sv, k, l, &u0, &du, &v0, &dv);
+    double Pl[MAXT];
+    local_cps(g, Pz, su, sv, Pl);
+    double z[4] = {node_height(g, Pl, su, sv, u0, v0), node_height(g, Pl, su, sv, u0 + du, v0),
+                   node_height(g, Pl, su, sv, u0, v0 + dv), node_height(g, Pl, su, sv, u0 + du, v0 + dv)};
+    double A, B;
+    tri_plane(upper, z, du, dv, &A, &B);
+    double uc = upper ? u0 + du : u0, vc = upper ? v0 + dv : v0, zc = upper ? z[3] : z[0];
+    double ou = 0.5 * (o[0] / g.pr.r_x + 1.0), ov = 0.5 * (o[1] / g.pr.r_y + 1.0);
+    double du_t = d[0] / (2.0 * g.pr.r_x), dv_t = d[1] / (2.0 * g.pr.r_y);
+    // o_z + d_z t = zc + A (o_u + d_u t - uc) + B (o_v + d_v t - vc)
+    double den = d[2] - A * du_t - B * dv_t;
+    if (den == 0.0) return false;  // ray parallel to the triangle
+    double t = (zc + A * (ou - uc) + B * (ov - vc) - o[2]) / den;
+    if (!(t >= t0 && t <= t1)) return false;
+    double a = (ou + du_t * t - u0) / du, b = (ov + dv_t * t - v0) / dv;
+    bool last_u = su == g.nu - 1 && k == g.pr.mesh_u - 1, last_v = sv == g.nv - 1 && l == g.pr.mesh_v - 1;
+    if (!in_triangle(upper, a, b, last_u, last_v)) return false;
+    *t_out = t;
+    return true;
+}
+
+// Ray parameters where the (u, v, z) ray crosses the box [ua, ub] x [va, vb] x [za, zb] (slab method).
+bool ray_box(const double* ouvz, const double* duvz, const double* lo, const double* hi, double* t0, double* t1) {
+    double a = *t0, b = *t1;
+    for (int ax = 0; ax < 3; ++ax) {
+        if (duvz[ax] == 0.0) {
+            if (ouvz[ax] < lo[ax] || ouvz[ax] > hi[ax]) return false;
+            continue;
+        }
+        double ta = (lo[ax] - ouvz[ax]) / duvz[ax], tb = (hi[ax] - ouvz[ax]) / duvz[ax];
+        if (ta > tb) std::swap(ta, tb);
+        a = std::max(a, ta);
+        b = std::min(b, tb);
+    }
+    *t0 = a; *t1 = b;
+    return a <= b;
+}
+
+// Phase 1 recursion over the rectangle of span products [a0, a1) x [b0, b1) (span indices counted from 0).
+void mesh_boxes(const Geo& g, const double* Pz, const double* o, const double* d, const double* ouvz,
+                const double* duvz, int a0, int a1, int b0, int b1, double t0, double t1, MeshHit* best) {
+    double zl = 1e300, zh = -1e300;
+    for (int i = a0; i <= a1 - 1 + g.p; ++i)       // control points acting on these products
+        for (int j = b0; j <= b1 - 1 + g.q; ++j) {
+            zl = std::min(zl, Pz[i * g.nv + j]);
+            zh = std::max(zh, Pz[i * g.nv + j]);
+        }
+    double pad = 1e-12 * (1.0 + std::fabs(zh));
+    double lo[3] = {g.U[g.p + a0], g.V[g.q + b0], zl - pad}, hi[3] = {g.U[g.p + a1], g.V[g.q + b1], zh + pad};
+    double ta = t0, tb = best->hit ? std::min(t1, best->t) : t1;
+    if (!ray_box(ouvz, duvz, lo, hi, &ta, &tb)) return;
+    if (a1 - a0 == 1 && b1 - b0 == 1) {
+        int su = g.p + a0, sv = g.q + b0;
+        for (int k = 0; k < g.pr.mesh_u; ++k)
+            for (int l = 0; l < g.pr.mesh_v; ++l)
+                for (int up = 0; up < 2; ++up) {
+                    double t;
+                    if (mesh_triangle_hit(g, Pz, o, d, su, sv, k, l, up, t0, t1, &t) && (!best->hit || t < best->t))
+                        *best = MeshHit{true, t, su, sv, k, l, up};
+                }
+        return;
+    }
+    int am = a1 - a0 > 1 ? (a0 + a1) / 2 : a1, bm = b1 - b0 > 1 ? (b0 + b1) / 2 : b1;
+    const int ra[3] = {a0, am, a1}, rb[3] = {b0, bm, b1};
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y)
+            if (ra[x] < ra[x + 1] && rb[y] < rb[y + 1])
+                mesh_boxes(g, Pz, o, d, ouvz, duvz, ra[x], ra[x + 1], rb[y], rb[y + 1], t0, t1, best);
+}
+
+MeshHit find_mesh_hit(const Geo& g, const double* Pz, const Entry& E) {
+    MeshHit best{false, 0.0, 0, 0, 0, 0, 0};
+    const double* o = E.o; const double* d = E.d;
+    double ouvz[3] = {0.5 * (o[0] / g.pr.r_x + 1.0), 0.5 * (o[1] / g.pr.r_y + 1.0), o[2]};
+    double duvz[3] = {d[0] / (2.0 * g.pr.r_x), d[1] / (2.0 * g.pr.r_y), d[2]};
+    mesh_boxes(g, Pz, o, d, ouvz, duvz, 0, g.nu - g.p, 0, g.nv - g.q, 0.0, 1e300, &best);
+    return best;
+}
+
+// The triangle containing the sample (u, v) of a collimated ray, and the hit's height on it.
+MeshHit mesh_cell_of(const Geo& g, double u, double v) {
+    MeshHit h{true, 0.0, find_span(g.p, g.nu, u), find_span(g.q, g.nv, v), 0, 0, 0};
+    double du = (g.U[h.su + 1] - g.U[h.su]) / g.pr.mesh_u, dv = (g.V[h.sv + 1] - g.V[h.sv]) / g.pr.mesh_v;
+    h.k = std::min(g.pr.mesh_u - 1, std::max(0, int(std::floor((u - g.U[h.su]) / du))));
+    h.l = std::min(g.pr.mesh_v - 1, std::max(0, int(std::floor((v - g.V[h.sv]) / dv))));
+    double a = (u - g.U[h.su]) / du - h.k, b = (v - g.V[h.sv]) / dv - h.l;
+    h.upper = a + b >= 1.0 ? 1 : 0;
+    return h;
+}
+
+// Ray parameter of the hit on triangle h: o_z + d_z t = T(o_u + d_u t, o_v + d_v t) (values or duals).
+template <class S>
+S mesh_t(const Geo& g, const S* Pl, const MeshHit& h, const double* o, const double* d) {
+    double u0, du, v0, dv;
+    mesh_cell(g, h.su, h.sv, h.k, h.l, &u0, &du, &v0, &dv);
+    S z[4] = {node_height(g, Pl, h.su, h.sv, u0, v0), node_height(g, Pl, h.su, h.sv, u0 + du, v0),
+              node_height(g, Pl, h.su, h.sv, u0, v0 + dv), node_height(g, Pl, h.su, h.sv, u0 + du, v0 + dv)};
+    S A, B;
+    tri_plane(h.upper, z, du, dv, &A, &B);
+    double uc = h.upper ? u0 + du : u0, vc = h.upper ? v0 + dv : v0;
+    S zc = h.upper ? z[3] : z[0];
+    double ou = 0.5 * (o[0] / g.pr.r_x + 1.0), ov = 0.5 * (o[1] / g.pr.r_y + 1.0);
+    double du_t = d[0] / (2.0 * g.pr.r_x), dv_t = d[1] / (2.0 * g.pr.r_y);
+    return (zc + A * (ou - uc) + B * (ov - vc) - o[2]) / (d[2] - A * du_t - B * dv_t);
+}
+
+// Height of the mesh at (u, v) on triangle h (values or duals over the product's control points).
+template <class S>
+S mesh_height(const Geo& g, const S* Pl, const MeshHit& h, const S& u, const S& v) {
+    double u0, du, v0, dv;
+    mesh_cell(g, h.su, h.sv, h.k, h.l, &u0, &du, &v0, &dv);
+    S z[4] = {node_height(g, Pl, h.su, h.sv, u0, v0), node_height(g, Pl, h.su, h.sv, u0 + du, v0),
+              node_height(g, Pl, h.su, h.sv, u0, v0 + dv), node_height(g, Pl, h.su, h.sv, u0 + du, v0 + dv)};
+    S A, B;
+    tri_plane(h.upper, z, du, dv, &A, &B);
+    if (!h.upper) return z[0] + A * (u - u0) + B * (v - v0);
+    return z[3] + A * (u - (u0 + du)) + B * (v - (v0 + dv));
+}
+
 // Result of the P-dependent part of a ray (templated: double for values, Dual for derivatives).
 template <class S>
 struct Exit {
@@ -536,6 +721,7 @@ struct RayOut {
     bool marginal;
     double k;
     Entry E;
+    MeshHit mh;          // mesh mode: the triangle hit
 };
 
 // Rounding-distance thresholds for "marginal" rays whose discrete state may differ in single precision
@@ -550,6 +736,8 @@ constexpr double EPS_SCREEN = 3e-5;    // landing to the screen edge, relative t
 RayOut trace_value(const Geo& g, const double* Pz, int64_t id, bool force = false) {
     RayOut R;
     R.marginal = false; R.X = R.Y = R.w = 0.0; R.u = R.v = R.t = 0.0; R.su = R.sv = 0; R.k = 1.0;
+    R.mh = MeshHit{false, 0.0, 0, 0, 0, 0, 0};
+    const bool mesh = g.pr.mesh_u > 0;
     R.E = ray_entry(g, id);
     Entry& E = R.E;
     if (std::fabs(E.margin) < EPS_APERTURE) R.marginal = true;
@@ -572,6 +760,14 @@ RayOut trace_value(const Geo& g, const double* Pz, int64_t id, bool force = fals
         R.t = 0.0;
         q[0] = E.o[0]; q[1] = E.o[1];
         R.u = E.u; R.v = E.v;
+        if (mesh) R.mh = mesh_cell_of(g, R.u, R.v);
+    } else if (mesh) {
+        // the first hit on the triangle mesh; a ray that meets no triangle leaves through the side wall
+        R.mh = find_mesh_hit(g, Pz, E);
+        if (!R.mh.hit) { R.status = ORC_SIDE_WALL; return R; }
+        R.t = R.mh.t;
+        q[0] = E.o[0] + R.t * E.d[0]; q[1] = E.o[1] + R.t * E.d[1];
+        R.u = 0.5 * (q[0] / g.pr.r_x + 1.0); R.v = 0.5 * (q[1] / g.pr.r_y + 1.0);
     } else {
         Root rt = find_root(g, Pz, E, force);
         if (rt.margin < EPS_SIDE) R.marginal = true;
@@ -580,11 +776,14 @@ RayOut trace_value(const Geo& g, const double* Pz, int64_t id, bool force = fals
         q[0] = E.o[0] + rt.t * E.d[0]; q[1] = E.o[1] + rt.t * E.d[1];
         R.u = 0.5 * (q[0] / g.pr.r_x + 1.0); R.v = 0.5 * (q[1] / g.pr.r_y + 1.0);
     }
-    R.su = find_span(g.p, g.nu, R.u); R.sv = find_span(g.q, g.nv, R.v);
+    // mesh mode: the normal is the B-spline's at the hit's (u, v), on the triangle's span product
+    R.su = mesh ? R.mh.su : find_span(g.p, g.nu, R.u);
+    R.sv = mesh ? R.mh.sv : find_span(g.q, g.nv, R.v);
     double Pl[MAXT];
     local_cps(g, Pz, R.su, R.sv, Pl);
     Surf<double> s = eval_surface<double>(g, Pl, R.su, R.sv, R.u, R.v, false);
-    q[2] = E.collimated ? s.h : E.o[2] + R.t * E.d[2];
+    if (E.collimated) q[2] = mesh ? mesh_height<double>(g, Pl, R.mh, R.u, R.v) : s.h;
+    else q[2] = E.o[2] + R.t * E.d[2];
     Exit<double> X = exit_and_screen<double>(g, q, E.d, s.hx, s.hy, E.w, false);
     R.k = X.k;
     if (std::fabs(X.k) < EPS_TIR) {
@@ -620,10 +819,17 @@ Exit<Dual> trace_dual(const Geo& g, const double* Pz, const RayOut& R, Dual* Xo,
         }
     Dual q[3];
     Surf<Dual> s;
+    const bool mesh = g.pr.mesh_u > 0;
     if (E.collimated) {
         Dual u(R.u), v(R.v);
         s = eval_surface<Dual>(g, Pl, R.su, R.sv, u, v, false);
-        q[0] = Dual(E.o[0]); q[1] = Dual(E.o[1]); q[2] = s.h;
+        q[0] = Dual(E.o[0]); q[1] = Dual(E.o[1]); q[2] = mesh ? mesh_height<Dual>(g, Pl, R.mh, u, v) : s.h;
+    } else if (mesh) {
+        // the plane of the hit triangle moves with its corner heights: t in dual arithmetic
+        Dual t = mesh_t<Dual>(g, Pl, R.mh, E.o, E.d);
+        for (int i = 0; i < 3; ++i) q[i] = E.o[i] + t * E.d[i];
+        Dual u = 0.5 * (q[0] / g.pr.r_x + 1.0), v = 0.5 * (q[1] / g.pr.r_y + 1.0);
+        s = eval_surface<Dual>(g, Pl, R.su, R.sv, u, v, false);
     } else {
         // Differentiate the root: two Newton steps in dual arithmetic from the converged root.
         Dual t(R.t);

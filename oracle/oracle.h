@@ -11,7 +11,8 @@
  *   sec. 2.1      B-spline surface (Cox-de Boor recursion, clamped uniform knots, tensor product)
  *   sec. 2.1.1    linear X, Y via Greville abscissae, so only P^z is free
  *   sec. 2.2.1    collimated and point sources (uniform in solid angle), grid of point sources (sec. 3.3)
- *   sec. 2.2.2    smallest positive root of f(t) = Z(o_uv + d_uv t) - d_z t - o_z, solved exactly here
+ *   sec. 2.2.2    smallest positive root of f(t) = Z(o_uv + d_uv t) - d_z t - o_z, solved exactly, or
+ *                 (mesh_u > 0) the first hit on the paper's triangle mesh of the surface
  *   sec. 2.2      refraction at both faces, TIR rays dropped, Schlick weights (sec. 2.3)
  *   sec. 2.3      Gaussian reconstruction filter, normalised, optional ghost pixels
  *   sec. 2.5      normalised images and the RMS Frobenius loss; Adam
@@ -46,6 +47,8 @@ typedef struct {
     int32_t nu_x, nu_y, ghost;
     /* options */
     int32_t fresnel;                 /* 1: Schlick weights at both faces, 0: none */
+    int32_t mesh_u, mesh_v;          /* 0: exact intersection; >= 1: the triangle mesh of sec. 2.2.2 with
+                                        mesh_u x mesh_v rectangles per knot span product */
     int32_t pad_;
 } orc_problem;
 

@@ -11,6 +11,7 @@ constexpr int WG = 256;               // threads per workgroup: 4 wave64s
 constexpr int TILE_CAP = 6144;        // 32-bit fixed-point pixels in the LDS irradiance tile of the forward kernel
 constexpr int MAX_DEG = 5;
 constexpr int N_SHAPES = 5;           // block shapes: rays per thread 1, 2, 4, 8, 16
+constexpr int N_KG = 4;               // kernel groups: bit 0 point source, bit 1 triangle mesh
 constexpr int RPT_OF_SHAPE[N_SHAPES] = {1, 2, 4, 8, 16};
 constexpr int NSLOT = 64;             // per-design partial-statistics slots (spreads the counter atomics)
 
@@ -53,8 +54,14 @@ struct DesignDev {
     // integer rint(v fx_scale), fx_scale = 2^26 / w0, so that one addend stays below 2^31 and a workgroup's
     // sum for one pixel (at most 2^11 rays) below 2^37.
     float fx_scale, fx_unscale;
-    int32_t sb_off, sb_pad_;         // first record of the design's span bounds (workspace)
+    int32_t sb_off;                  // first record of the design's span bounds (workspace)
+    int32_t mesh_u, mesh_v;          // triangle mesh of sec. 2.2.2: rectangles per knot span (0: exact root)
+    int32_t pad_;
+    float inv_mesh_u, inv_mesh_v;
 };
+
+// Kernel group of a design: the trace kernels are instantiated per source kind and intersection mode.
+inline int kind_group(const DesignDev& d) { return (d.mesh_u ? 2 : 0) + (d.kind != 0 ? 1 : 0); }
 
 // Per-design bounds of sec. 2.2.2 (global convex-hull box and slope bounds), formed by launch_bounds before
 // the trace kernels of designs whose rays need the root search (point and grid sources).

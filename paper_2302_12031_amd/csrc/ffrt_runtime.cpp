@@ -70,8 +70,8 @@ struct ffrt_plan {
     int64_t max_img = 0;
     std::vector<float> knots;
     // block maps per shape and source-kind group (designs of the other group get no blocks)
-    std::vector<BlockMap> bmaps[N_SHAPES][2];
-    int64_t nblocks[N_SHAPES][2] = {};
+    std::vector<BlockMap> bmaps[N_SHAPES][N_KG];
+    int64_t nblocks[N_SHAPES][N_KG] = {};
     // workspace
     char* ws = nullptr;
     size_t ws_bytes = 0;
@@ -88,7 +88,7 @@ struct ffrt_plan {
     int32_t* d_valid() const { return reinterpret_cast<int32_t*>(ws + off_valid); }
     float* d_knots() const { return reinterpret_cast<float*>(ws + off_knots); }
     BlockMap* d_bmap(int shape, int kg) const {
-        return reinterpret_cast<BlockMap*>(ws + off_bmap) + ((size_t)shape * 2 + kg) * nd;
+        return reinterpret_cast<BlockMap*>(ws + off_bmap) + ((size_t)shape * N_KG + kg) * nd;
     }
     ffrt_stats* d_slots() const { return reinterpret_cast<ffrt_stats*>(ws + off_slots); }
     double* d_lpart() const { return reinterpret_cast<double*>(ws + off_lpart); }
@@ -136,6 +136,9 @@ ffrt_status validate(const ffrt_problem& pr, int idx) {
     if (!(D.z_screen > L.z_in)) return bad("screen must lie above the entry face");
     if (pr.opt.fresnel != 0 && pr.opt.fresnel != 1) return bad("fresnel must be 0 or 1");
     if (pr.opt.newton_max_iter < 1 || pr.opt.newton_max_iter > 32) return bad("newton_max_iter in [1, 32]");
+    if (pr.opt.mesh_u < 0 || pr.opt.mesh_u > 64 || pr.opt.mesh_v < 0 || pr.opt.mesh_v > 64 ||
+        (pr.opt.mesh_u == 0) != (pr.opt.mesh_v == 0))
+        return bad("mesh_u, mesh_v: both 0 (exact root) or both in [1, 64]");
     int64_t n = (int64_t)S.grid_u * S.grid_v * (S.kind == 2 ? (int64_t)S.emit_nx * S.emit_ny : 1);
     // the forward's fixed-point pixel sums (at most 2^26 per ray) must stay below 2^63
     if (n > ((int64_t)1 << 36)) return bad("too many rays in one design (at most 2^36)");
@@ -218,6 +221,10 @@ DesignDev make_design(const ffrt_problem& pr, int64_t cp_off, int64_t img_off, i
     d.edge_y = (float)std::exp(-D.alpha * 0.25 * D.nu_y * D.nu_y);
     d.fresnel = pr.opt.fresnel;
     d.newton_max = pr.opt.newton_max_iter;
+    d.mesh_u = pr.opt.mesh_u;
+    d.mesh_v = pr.opt.mesh_v;
+    d.inv_mesh_u = d.mesh_u ? 1.0f / (float)d.mesh_u : 0.0f;
+    d.inv_mesh_v = d.mesh_v ? 1.0f / (float)d.mesh_v : 0.0f;
     double r0 = (L.n_lens - 1.0) / (L.n_lens + 1.0);
     d.R0 = (float)(r0 * r0);
     int64_t n = (int64_t)S.grid_u * S.grid_v * d.emit_nx * d.emit_ny;
@@ -266,7 +273,7 @@ int grid_for(ffrt_plan* pl, int shape, int kg, int persistent) {
 // when `stats` is set.  The image must be resolved (launch_resolve or the loss) before the next forward.
 ffrt_status launch_forward(ffrt_plan* pl, const float* Pz, bool stats, hipStream_t s) {
     const FwdCfg& c = FWD_CFGS[pl->fwd_cfg];
-    for (int kg = 0; kg < 2; ++kg) {
+    for (int kg = 0; kg < N_KG; ++kg) {
         if (pl->nblocks[c.shape][kg] == 0) continue;
         TraceArgs A = make_args(pl, c.shape, kg);
         A.Pz = Pz;
@@ -281,7 +288,7 @@ ffrt_status launch_forward(ffrt_plan* pl, const float* Pz, bool stats, hipStream
 // The adjoint trace kernel, into the plan's gradient accumulator (launch_finish turns it into dL/dP).
 ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hipStream_t s) {
     const AdjCfg& c = ADJ_CFGS[pl->adj_cfg];
-    for (int kg = 0; kg < 2; ++kg) {
+    for (int kg = 0; kg < N_KG; ++kg) {
         if (pl->nblocks[c.shape][kg] == 0) continue;
         TraceArgs A = make_args(pl, c.shape, kg);
         A.Pz = Pz;
@@ -472,7 +479,7 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
     pl->total_img = img;
     for (int sh = 0; sh < N_SHAPES; ++sh) {
         ShapeDims sd = shape_dims(sh);
-        for (int kg = 0; kg < 2; ++kg) {
+        for (int kg = 0; kg < N_KG; ++kg) {
             int64_t first = 0;
             for (int i = 0; i < n_designs; ++i) {
                 const DesignDev& d = pl->dd[i];
@@ -482,7 +489,7 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
                 bm.nbv = nbv;
                 bm.per_emitter = nbu * nbv;
                 pl->bmaps[sh][kg].push_back(bm);
-                if ((d.kind == 0) == (kg == 0)) first += (int64_t)bm.per_emitter * d.emit_nx * d.emit_ny;
+                if (kind_group(d) == kg) first += (int64_t)bm.per_emitter * d.emit_nx * d.emit_ny;
             }
             pl->nblocks[sh][kg] = first;
         }
@@ -499,7 +506,7 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
     pl->off_knots = off;
     off = align256(off + sizeof(float) * pl->knots.size());
     pl->off_bmap = off;
-    off = align256(off + sizeof(BlockMap) * N_SHAPES * 2 * n_designs);
+    off = align256(off + sizeof(BlockMap) * N_SHAPES * N_KG * n_designs);
     pl->off_slots = off;
     off = align256(off + sizeof(ffrt_stats) * NSLOT * n_designs);
     pl->loss_lb = loss_blocks_per_design(pl->max_img);
@@ -559,7 +566,7 @@ ffrt_status ffrt_plan_set_workspace(ffrt_plan* plan, void* dev_ptr, size_t bytes
         HIP_TRY(hipMemcpy(plan->d_knots(), plan->knots.data(), sizeof(float) * plan->knots.size(),
                           hipMemcpyHostToDevice));
     for (int sh = 0; sh < N_SHAPES; ++sh)
-        for (int kg = 0; kg < 2; ++kg)
+        for (int kg = 0; kg < N_KG; ++kg)
             HIP_TRY(hipMemcpy(plan->d_bmap(sh, kg), plan->bmaps[sh][kg].data(), sizeof(BlockMap) * plan->nd,
                               hipMemcpyHostToDevice));
     return FFRT_OK;
@@ -938,7 +945,7 @@ ffrt_status ffrt_trace_rays(ffrt_plan* plan, int32_t design, const float* Pz, co
         return fail(FFRT_E_ARG, "bad argument");
     hipStream_t s = (hipStream_t)stream;
     if (ffrt_status b = run_bounds(plan, Pz, s)) return b;
-    TraceArgs A = make_args(plan, 0, plan->dd[design].kind != 0 ? 1 : 0);  // the forward's LDS layout
+    TraceArgs A = make_args(plan, 0, kind_group(plan->dd[design]));  // the forward's LDS layout
     A.Pz = Pz;
     HIP_TRY(plan->ks->trace_rays(A, design, ray_ids, n, out8, s));
     return FFRT_OK;

@@ -144,15 +144,13 @@ struct SurfEval {
     T h, hx, hy, hxx, hxy, hyy;
 };
 
+// On the given span product (ku, kv); eval_surface below picks the one containing (x, y).
 template <int P, int Q, bool D2, class T>
-__device__ __forceinline__ void eval_surface(const DesignDev& D, const float* __restrict__ sP,
-                                             const float* __restrict__ sKu, const float* __restrict__ sKv, T x,
-                                             T y, SurfEval<P, Q, T>& S) {
+__device__ __forceinline__ void eval_surface_on(const DesignDev& D, const float* __restrict__ sP,
+                                                const float* __restrict__ sKu, const float* __restrict__ sKv, T x,
+                                                T y, int ku, int kv, SurfEval<P, Q, T>& S) {
     T ub = x * (T)D.sxu + (T)D.ubar0;
     T vb = y * (T)D.syv + (T)D.vbar0;
-    int ku = (int)floor(ub), kv = (int)floor(vb);
-    ku = min(max(ku, 0), D.nsu - 1);
-    kv = min(max(kv, 0), D.nsv - 1);
     S.ku = ku;
     S.kv = kv;
     // spans k with P-1 <= k <= nspan-P see only unclamped knots
@@ -196,6 +194,15 @@ __device__ __forceinline__ void eval_surface(const DesignDev& D, const float* __
     }
 }
 
+template <int P, int Q, bool D2, class T>
+__device__ __forceinline__ void eval_surface(const DesignDev& D, const float* __restrict__ sP,
+                                             const float* __restrict__ sKu, const float* __restrict__ sKv, T x,
+                                             T y, SurfEval<P, Q, T>& S) {
+    int ku = (int)floor(x * (T)D.sxu + (T)D.ubar0), kv = (int)floor(y * (T)D.syv + (T)D.vbar0);
+    eval_surface_on<P, Q, D2, T>(D, sP, sKu, sKv, x, y, min(max(ku, 0), D.nsu - 1), min(max(kv, 0), D.nsv - 1),
+                                 S);
+}
+
 // ------------------------------------------------------------------------------------------------
 // Sources (sec. 2.2.1) and the flat entry face (point sources).
 // ------------------------------------------------------------------------------------------------
@@ -206,14 +213,15 @@ struct RayIn {
     float w;            // weight after the entry face
 };
 
-// KIND 0: collimated source; KIND 1: point source or grid of point sources (D.kind 1 or 2).
+// KIND bit 0 clear: collimated source; set: point source or grid of point sources (D.kind 1 or 2).  Bit 1
+// selects the triangle-mesh intersection of sec. 2.2.2 instead of the exact root (see below).
 template <int KIND>
 __device__ __forceinline__ RayIn ray_entry(const DesignDev& D, int e, int ku, int kv, int64_t id) {
     RayIn r;
     r.status = ST_HIT;
     float x1 = 0.5f, x2 = 0.5f;
     if (D.jitter) two_uniforms(splitmix_at(D.rng_state0, (uint64_t)id), x1, x2);
-    if constexpr (KIND == 0) {
+    if constexpr ((KIND & 1) == 0) {
         // Collimated bundle: samples on the grid of [0,1]^2, mapped linearly to the aperture; the ray meets
         // the flat face at normal incidence (Schlick weight 1 - R0) and travels along +z.
         float u = ((float)ku + x1) * D.inv_gu;
@@ -407,6 +415,172 @@ __device__ RootOut intersect(const DesignDev& D, const BoundsDev& B, const float
 }
 
 // ------------------------------------------------------------------------------------------------
+// Triangle mesh of sec. 2.2.2, the paper's own intersector (an alternative to the exact root): each knot
+// span product is divided into mesh_u x mesh_v equal rectangles, each into a lower-left triangle (left and
+// lower edges closed) and an upper-right one (diagonal closed) whose corners lie on the surface.  In cell
+// units c_u = ubar mesh_u, c_v = vbar mesh_v (ubar in knot spans), cell (K, L) = (floor c_u, floor c_v)
+// belongs to span product (K / mesh_u, L / mesh_v); a = c_u - K, b = c_v - L place a point in its cell and
+// the lower-left triangle is a + b < 1.  Corner heights are B-spline values at the cell's nodes, from the
+// basis functions at the two node columns and rows of the cell (they depend on the node only, not on P).
+// ------------------------------------------------------------------------------------------------
+template <int P, int Q>
+struct MeshCell {
+    int su, sv;                                              // span product of the cell
+    float Nu0[P + 1], Nu1[P + 1], Nv0[Q + 1], Nv1[Q + 1];    // basis at the cell's node columns / rows
+    float z00, z10, z01, z11;                                // corner heights relative to zref
+};
+
+template <int P, int Q>
+__device__ __forceinline__ void mesh_cell(const DesignDev& D, const float* sP, const float* sKu, const float* sKv,
+                                          int K, int L, MeshCell<P, Q>& C) {
+    C.su = K / D.mesh_u;
+    C.sv = L / D.mesh_v;
+    const float tu0 = (float)(K - C.su * D.mesh_u) * D.inv_mesh_u, tu1 = tu0 + D.inv_mesh_u;
+    const float tv0 = (float)(L - C.sv * D.mesh_v) * D.inv_mesh_v, tv1 = tv0 + D.inv_mesh_v;
+    float dn[P + 1 > Q + 1 ? P + 1 : Q + 1];
+    if (C.su >= P - 1 && C.su <= D.nsu - P) {
+        span_basis<P, false, true, float>(nullptr, tu0, C.Nu0, dn, nullptr);
+        span_basis<P, false, true, float>(nullptr, tu1, C.Nu1, dn, nullptr);
+    } else {
+        span_basis<P, false, false, float>(sKu + C.su * kt_stride(P), tu0, C.Nu0, dn, nullptr);
+        span_basis<P, false, false, float>(sKu + C.su * kt_stride(P), tu1, C.Nu1, dn, nullptr);
+    }
+    if (C.sv >= Q - 1 && C.sv <= D.nsv - Q) {
+        span_basis<Q, false, true, float>(nullptr, tv0, C.Nv0, dn, nullptr);
+        span_basis<Q, false, true, float>(nullptr, tv1, C.Nv1, dn, nullptr);
+    } else {
+        span_basis<Q, false, false, float>(sKv + C.sv * kt_stride(Q), tv0, C.Nv0, dn, nullptr);
+        span_basis<Q, false, false, float>(sKv + C.sv * kt_stride(Q), tv1, C.Nv1, dn, nullptr);
+    }
+    const float* row = sP + C.su * D.n_v + C.sv;
+    float z00 = 0.0f, z10 = 0.0f, z01 = 0.0f, z11 = 0.0f;
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        float r0 = 0.0f, r1 = 0.0f;
+#pragma unroll
+        for (int b = 0; b <= Q; ++b) {
+            const float pz = row[a * D.n_v + b];
+            r0 += C.Nv0[b] * pz;
+            r1 += C.Nv1[b] * pz;
+        }
+        z00 += C.Nu0[a] * r0;
+        z10 += C.Nu1[a] * r0;
+        z01 += C.Nu0[a] * r1;
+        z11 += C.Nu1[a] * r1;
+    }
+    C.z00 = z00;
+    C.z10 = z10;
+    C.z01 = z01;
+    C.z11 = z11;
+}
+
+// Slopes of a triangle's plane per cell unit: T = z00 + A a + B b (lower-left, through corners 00, 10, 01)
+// or T = z11 + A (a - 1) + B (b - 1) (upper-right, through corners 11, 01, 10).
+template <int P, int Q>
+__device__ __forceinline__ void tri_slopes(const MeshCell<P, Q>& C, int upper, float& A, float& B) {
+    A = upper ? C.z11 - C.z01 : C.z10 - C.z00;
+    B = upper ? C.z11 - C.z10 : C.z01 - C.z00;
+}
+
+struct MeshRoot {
+    int status;
+    float t;
+    int K, L, upper, cells;
+};
+
+// First hit of a point-source ray on the mesh.  The ray is bracketed by the global height box as for the
+// exact root; its (u, v) track is then walked cell by cell in order of t (a 2-D DDA), and in each cell the
+// plane of either triangle is intersected; the first cell with a hit inside one of its triangles holds the
+// smallest t.  The triangle tests accept a rounding margin (a hit on a shared edge has the same t on both
+// sides), so no ray slips between triangles.  A ray whose track leaves the aperture or the bracket without
+// a hit leaves through the side wall.
+template <int P, int Q>
+__device__ MeshRoot intersect_mesh(const DesignDev& D, const BoundsDev& B, const float* sP, const float* sKu,
+                                   const float* sKv, const RayIn& r) {
+    MeshRoot R;
+    R.status = ST_SIDE_WALL;
+    R.t = 0.0f;
+    R.K = R.L = R.upper = R.cells = 0;
+    const float inv_dz = rcpf(r.dz);
+    const float pad = 4e-6f * (1.0f + fabsf(B.zmax - r.oz)) * inv_dz;
+    const float t_lo = fmaxf(0.0f, (B.zmin - r.oz) * inv_dz - pad);
+    const float t_hi = (B.zmax - r.oz) * inv_dz + pad;
+    float t_ap = INFINITY;
+    if (r.dx > 0.0f) t_ap = fminf(t_ap, (D.r_x - r.ox) * rcpf(r.dx));
+    if (r.dx < 0.0f) t_ap = fminf(t_ap, (-D.r_x - r.ox) * rcpf(r.dx));
+    if (r.dy > 0.0f) t_ap = fminf(t_ap, (D.r_y - r.oy) * rcpf(r.dy));
+    if (r.dy < 0.0f) t_ap = fminf(t_ap, (-D.r_y - r.oy) * rcpf(r.dy));
+    const float t_end = fminf(t_hi, t_ap);
+    if (t_end < t_lo) return R;
+    const int NK = D.nsu * D.mesh_u, NL = D.nsv * D.mesh_v;
+    const float cu0 = ((r.ox + t_lo * r.dx) * D.sxu + D.ubar0) * (float)D.mesh_u;
+    const float cv0 = ((r.oy + t_lo * r.dy) * D.syv + D.vbar0) * (float)D.mesh_v;
+    const float dcu = r.dx * D.sxu * (float)D.mesh_u, dcv = r.dy * D.syv * (float)D.mesh_v;  // cells per unit t
+    int K = min(max((int)floorf(cu0), 0), NK - 1), L = min(max((int)floorf(cv0), 0), NL - 1);
+    const int stK = dcu > 0.0f ? 1 : -1, stL = dcv > 0.0f ? 1 : -1;
+    float tK = dcu != 0.0f ? t_lo + ((float)(K + (dcu > 0.0f ? 1 : 0)) - cu0) * rcpf(dcu) : INFINITY;
+    float tL = dcv != 0.0f ? t_lo + ((float)(L + (dcv > 0.0f ? 1 : 0)) - cv0) * rcpf(dcv) : INFINITY;
+    const float dtK = dcu != 0.0f ? fabsf(rcpf(dcu)) : INFINITY, dtL = dcv != 0.0f ? fabsf(rcpf(dcv)) : INFINITY;
+    const float zr0 = (r.oz - B.zref) + t_lo * r.dz;  // ray height above zref at t_lo
+    constexpr float EPS = 2e-5f;                      // cell units
+    const float s_max = t_end - t_lo + pad;
+    for (int it = 0; it <= NK + NL; ++it) {
+        MeshCell<P, Q> C;
+        mesh_cell<P, Q>(D, sP, sKu, sKv, K, L, C);
+        R.cells++;
+        const float a0 = cu0 - (float)K, b0 = cv0 - (float)L;  // the ray's cell coordinates at t_lo
+        float best = INFINITY;
+        int up = 0;
+#pragma unroll
+        for (int tri = 0; tri < 2; ++tri) {
+            float A, Bs;
+            tri_slopes<P, Q>(C, tri, A, Bs);
+            // z at s = t - t_lo: zr0 + dz s = T(a0 + dcu s, b0 + dcv s)
+            const float den = r.dz - A * dcu - Bs * dcv;
+            const float num = tri ? C.z11 + A * (a0 - 1.0f) + Bs * (b0 - 1.0f) - zr0 : C.z00 + A * a0 + Bs * b0 - zr0;
+            if (den == 0.0f) continue;
+            const float sh = num * rcpf(den);
+            const float a = a0 + dcu * sh, b = b0 + dcv * sh;
+            const bool inside = tri ? (a + b >= 1.0f - EPS && a <= 1.0f + EPS && b <= 1.0f + EPS)
+                                    : (a >= -EPS && b >= -EPS && a + b <= 1.0f + EPS);
+            if (inside && sh >= -pad && sh <= s_max && sh < best) {
+                best = sh;
+                up = tri;
+            }
+        }
+        if (best < INFINITY) {
+            R.status = ST_HIT;
+            R.t = t_lo + best;
+            R.K = K;
+            R.L = L;
+            R.upper = up;
+            return R;
+        }
+        if (fminf(tK, tL) > t_end) break;
+        if (tK < tL) {
+            K += stK;
+            tK += dtK;
+            if (K < 0 || K >= NK) break;
+        } else {
+            L += stL;
+            tL += dtL;
+            if (L < 0 || L >= NL) break;
+        }
+    }
+    return R;
+}
+
+// Cell, triangle and in-cell coordinates of a point (x, y).
+__device__ __forceinline__ void mesh_locate(const DesignDev& D, float x, float y, int& K, int& L, float& a,
+                                            float& b) {
+    const float cu = (x * D.sxu + D.ubar0) * (float)D.mesh_u, cv = (y * D.syv + D.vbar0) * (float)D.mesh_v;
+    K = min(max((int)floorf(cu), 0), D.nsu * D.mesh_u - 1);
+    L = min(max((int)floorf(cv), 0), D.nsv * D.mesh_v - 1);
+    a = cu - (float)K;
+    b = cv - (float)L;
+}
+
+// ------------------------------------------------------------------------------------------------
 // Exit face (sec. 2.2): vector Snell glass -> air at n_hat = (-h_x, -h_y, 1)/|.|, TIR dropped, Schlick
 // weight with the air-side cosine sqrt(k), propagation to the screen plane (sec. 2.3).
 // ------------------------------------------------------------------------------------------------
@@ -515,11 +689,52 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
     FwdRay o;
     o.iters = o.failed = o.nonmono = o.refined = 0;
     o.X = o.Y = o.w = o.t = o.u = o.v = 0.0f;
+    constexpr bool POINT = (KIND & 1) != 0, MESH = (KIND & 2) != 0;
     RayIn r = ray_entry<KIND>(D, e, ku, kv, id);
     o.status = r.status;
     if (r.status != ST_HIT) return o;
     float t;
-    if constexpr (KIND != 0) {
+    if constexpr (MESH) {
+        // the hit on the triangle mesh; the normal is the B-spline's at the hit, on the triangle's span
+        int K, L, upper = 0;
+        float qz;
+        if constexpr (POINT) {
+            MeshRoot M = intersect_mesh<P, Q>(D, B, sP, sKu, sKv, r);
+            o.iters = M.cells;
+            if (M.status != ST_HIT) {
+                o.status = M.status;
+                return o;
+            }
+            t = M.t;
+            K = M.K;
+            L = M.L;
+            qz = r.oz + t * r.dz;
+        } else {
+            float a, b;
+            mesh_locate(D, r.ox, r.oy, K, L, a, b);
+            upper = a + b >= 1.0f;
+            MeshCell<P, Q> C;
+            mesh_cell<P, Q>(D, sP, sKu, sKv, K, L, C);
+            float A, Bs;
+            tri_slopes<P, Q>(C, upper, A, Bs);
+            qz = (upper ? C.z11 + A * (a - 1.0f) + Bs * (b - 1.0f) : C.z00 + A * a + Bs * b) + B.zref;
+            t = qz - r.oz;
+        }
+        const float qx = r.ox + t * r.dx, qy = r.oy + t * r.dy;
+        SurfEval<P, Q, float> S;
+        eval_surface_on<P, Q, false, float>(D, sP, sKu, sKv, qx, qy, K / D.mesh_u, L / D.mesh_v, S);
+        o.t = t;
+        o.u = qx * (0.5f / D.r_x) + 0.5f;
+        o.v = qy * (0.5f / D.r_y) + 0.5f;
+        ExitState E = exit_face(D, qx, qy, qz, r.dx, r.dy, r.dz, S.hx, S.hy, r.w);
+        o.status = E.status;
+        if (E.status == ST_TIR) return o;
+        o.X = E.X;
+        o.Y = E.Y;
+        o.w = E.w;
+        return o;
+    }
+    if constexpr (POINT) {
         RootOut R = intersect<P, Q>(D, B, sP, sKu, sKv, sS, r);
         o.iters = R.iters;
         o.failed = R.failed;
@@ -536,8 +751,8 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
     float qx = r.ox + t * r.dx, qy = r.oy + t * r.dy;
     SurfEval<P, Q, float> S;
     eval_surface<P, Q, false, float>(D, sP, sKu, sKv, qx, qy, S);
-    float qz = (KIND == 0) ? S.h + B.zref : r.oz + t * r.dz;
-    if constexpr (KIND == 0) t = qz - r.oz;
+    float qz = POINT ? r.oz + t * r.dz : S.h + B.zref;
+    if constexpr (!POINT) t = qz - r.oz;
     o.t = t;
     o.u = qx * (0.5f / D.r_x) + 0.5f;
     o.v = qy * (0.5f / D.r_y) + 0.5f;
@@ -563,21 +778,48 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
     RayIn r = ray_entry<KIND>(D, e, ku, kv, id);
     if (r.status != ST_HIT) return false;
     float t = 0.0f;
-    constexpr bool point = KIND != 0;
-    if (point) {
+    constexpr bool point = (KIND & 1) != 0, MESH = (KIND & 2) != 0;
+    // mesh: the hit triangle, its cell (corner heights and node basis) and the hit's in-cell coordinates
+    MeshCell<P, Q> C;
+    int mK = 0, mL = 0, mup = 0;
+    float ma = 0.0f, mb = 0.0f, mqz = 0.0f;
+    if constexpr (MESH) {
+        if constexpr (point) {
+            MeshRoot M = intersect_mesh<P, Q>(D, B, sP, sKu, sKv, r);
+            if (M.status != ST_HIT) return false;
+            t = M.t;
+            mK = M.K;
+            mL = M.L;
+            mup = M.upper;
+            ma = ((r.ox + t * r.dx) * D.sxu + D.ubar0) * (float)D.mesh_u - (float)mK;
+            mb = ((r.oy + t * r.dy) * D.syv + D.vbar0) * (float)D.mesh_v - (float)mL;
+        } else {
+            mesh_locate(D, r.ox, r.oy, mK, mL, ma, mb);
+            mup = ma + mb >= 1.0f;
+        }
+        mesh_cell<P, Q>(D, sP, sKu, sKv, mK, mL, C);
+        if constexpr (!point) {
+            float A, Bs;
+            tri_slopes<P, Q>(C, mup, A, Bs);
+            mqz = (mup ? C.z11 + A * (ma - 1.0f) + Bs * (mb - 1.0f) : C.z00 + A * ma + Bs * mb) + B.zref;
+        }
+    } else if constexpr (point) {
         RootOut R = intersect<P, Q>(D, B, sP, sKu, sKv, sS, r);
         if (R.status != ST_HIT) return false;
         t = R.t;
     }
     float qx = r.ox + t * r.dx, qy = r.oy + t * r.dy;
     SurfEval<P, Q, float> S;
-    if (point) {
+    if constexpr (MESH) {
+        // the normal is the B-spline's at the hit, on the triangle's span product
+        eval_surface_on<P, Q, point, float>(D, sP, sKu, sKv, qx, qy, C.su, C.sv, S);
+    } else if constexpr (point) {
         eval_surface<P, Q, true, float>(D, sP, sKu, sKv, qx, qy, S);
     } else {
         // the hit of a collimated ray does not move with P: no second derivatives needed
         eval_surface<P, Q, false, float>(D, sP, sKu, sKv, qx, qy, S);
     }
-    float qz = point ? r.oz + t * r.dz : S.h + B.zref;
+    float qz = point ? r.oz + t * r.dz : (MESH ? mqz : S.h + B.zref);
     ExitState E = exit_face(D, qx, qy, qz, r.dx, r.dy, r.dz, S.hx, S.hy, r.w);
     if (E.status != ST_HIT) return false;
 
@@ -640,12 +882,46 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
         float tb = qxb * r.dx + qyb * r.dy + qzb * r.dz + hxb * (S.hxx * r.dx + S.hxy * r.dy) +
                    hyb * (S.hxy * r.dx + S.hyy * r.dy);
         float fp = S.hx * r.dx + S.hy * r.dy - r.dz;
+        if constexpr (MESH) {
+            // on the mesh f(t) = T(q(t)) - q_z(t): f' = T_x d_x + T_y d_y - d_z, and T moves with the corner
+            // heights, dT/dz_c = the barycentric weight of corner c (applied below)
+            float A, Bs;
+            tri_slopes<P, Q>(C, mup, A, Bs);
+            fp = A * D.sxu * (float)D.mesh_u * r.dx + Bs * D.syv * (float)D.mesh_v * r.dy - r.dz;
+        }
         g0 = -tb * rcpf(fp);
     } else {
-        g0 = qzb;  // q_z = h(x, y)
+        g0 = qzb;  // q_z = h(x, y), or the triangle's height on the mesh
     }
     // h_x = sum dN_a/du M_b P_ab * sxu, h_y = sum N_a dM_b/dv P_ab * syv
     float gx = hxb * D.sxu, gy = hyb * D.syv;
+    if constexpr (MESH) {
+        // the hit (and the height of a collimated hit) follows the triangle: its corner heights carry the
+        // weights l_c of the hit, z_c = sum_ab N_a(u_c) M_b(v_c) P_ab, so dP_ab gets
+        // g0 sum_c l_c N_a(u_c) M_b(v_c) = g0 (X0_a Nv0_b + X1_a Nv1_b); the normal's terms are the exact ones
+        float X0[P + 1], X1[P + 1];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) {
+            if (mup) {  // corners 11 (a + b - 1), 01 (1 - a), 10 (1 - b)
+                X0[a] = (1.0f - mb) * C.Nu1[a];
+                X1[a] = (ma + mb - 1.0f) * C.Nu1[a] + (1.0f - ma) * C.Nu0[a];
+            } else {    // corners 00 (1 - a - b), 10 (a), 01 (b)
+                X0[a] = (1.0f - ma - mb) * C.Nu0[a] + ma * C.Nu1[a];
+                X1[a] = mb * C.Nu0[a];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a <= P; ++a) {
+            float du = gx * S.dNu[a];
+#pragma unroll
+            for (int b = 0; b <= Q; ++b)
+                g[a * (Q + 1) + b] = g0 * (X0[a] * C.Nv0[b] + X1[a] * C.Nv1[b]) + S.Nu[a] * gy * S.dNv[b] +
+                                     du * S.Nv[b];
+        }
+        cku = S.ku;
+        ckv = S.kv;
+        return true;
+    }
     float cv[Q + 1];
 #pragma unroll
     for (int b = 0; b <= Q; ++b) cv[b] = g0 * S.Nv[b] + gy * S.dNv[b];
@@ -751,7 +1027,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
     float* sK = sP + A.lds_cp;
     float* sS = sK + A.lds_kt;  // span bounds (point sources, when they fit)
     uint32_t* tile = reinterpret_cast<uint32_t*>(sS + A.lds_sb);
-    const float* sSb = KIND != 0 && A.lds_sb ? sS : nullptr;
+    const float* sSb = (KIND & 1) != 0 && A.lds_sb ? sS : nullptr;
     __shared__ int s_box[4][4];
     __shared__ float s_red[4][10];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -763,7 +1039,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
         const DesignDev D = load_uniform(A.designs, d);
         if (d != cur) {
             __syncthreads();
-            B = stage_design(A, D, d, sP, sK, P, Q, KIND != 0);
+            B = stage_design(A, D, d, sP, sK, P, Q, (KIND & 1) != 0);
             cur = d;
         }
         const float* sKu = sK;
@@ -991,7 +1267,7 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
     float* sK = sP + A.lds_cp;
     float* sS = sK + A.lds_kt;  // span bounds (point sources, when they fit)
     float* sG = sS + A.lds_sb;
-    const float* sSb = KIND != 0 && A.lds_sb ? sS : nullptr;
+    const float* sSb = (KIND & 1) != 0 && A.lds_sb ? sS : nullptr;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int MU = shape_mu(shape), MV = shape_mv(shape), RPT = MU * MV;
     const int BU = 16 * MU, BV = 16 * MV;
@@ -1008,7 +1284,7 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
             if (cur >= 0) adjoint_flush(A, cur, sG);
             __syncthreads();
             for (int i = threadIdx.x; i < D.n_u * D.n_v; i += WG) sG[i] = 0.0f;
-            B = stage_design(A, D, d, sP, sK, P, Q, KIND != 0);
+            B = stage_design(A, D, d, sP, sK, P, Q, (KIND & 1) != 0);
             cur = d;
         }
         const float* G = A.dLdI + D.img_off;
@@ -1101,8 +1377,11 @@ __global__ __launch_bounds__(WG) void k_trace_rays(TraceArgs A, int design, cons
     int ku = (int)(rr / D.grid_v), kv = (int)(rr - (rr / D.grid_v) * D.grid_v);
     const float* sKv = sK + D.nsu * kt_stride(P);
     const float* sSb = A.lds_sb && D.kind != 0 ? sS : nullptr;
-    FwdRay o = D.kind == 0 ? trace_forward<P, Q, 0>(D, B, sP, sK, sKv, nullptr, e, ku, kv, id)
-                           : trace_forward<P, Q, 1>(D, B, sP, sK, sKv, sSb, e, ku, kv, id);
+    FwdRay o;
+    if (D.mesh_u) o = D.kind == 0 ? trace_forward<P, Q, 2>(D, B, sP, sK, sKv, nullptr, e, ku, kv, id)
+                                  : trace_forward<P, Q, 3>(D, B, sP, sK, sKv, nullptr, e, ku, kv, id);
+    else o = D.kind == 0 ? trace_forward<P, Q, 0>(D, B, sP, sK, sKv, nullptr, e, ku, kv, id)
+                         : trace_forward<P, Q, 1>(D, B, sP, sK, sKv, sSb, e, ku, kv, id);
     float* dst = out8 + 8 * i;
     dst[0] = (float)o.status;
     dst[1] = o.X;
@@ -1126,8 +1405,13 @@ struct KernelsFor {
     template <int SHAPE>
     static hipError_t fwd_shape(const TraceArgs& A, int grid, hipStream_t s) {
         size_t lds = trace_lds_bytes(A, A.use_tile ? TILE_CAP : 0);
-        if (A.kind_group == 0) hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 0>), dim3(grid), dim3(WG), lds, s, A);
-        else hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 1>), dim3(grid), dim3(WG), lds, s, A);
+        switch (A.kind_group) {
+            case 0: hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 0>), dim3(grid), dim3(WG), lds, s, A); break;
+            case 1: hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 1>), dim3(grid), dim3(WG), lds, s, A); break;
+            case 2: hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 2>), dim3(grid), dim3(WG), lds, s, A); break;
+            case 3: hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 3>), dim3(grid), dim3(WG), lds, s, A); break;
+            default: return hipErrorInvalidValue;
+        }
         return hipGetLastError();
     }
     static hipError_t forward(const TraceArgs& A, int shape, int grid, hipStream_t s) {
@@ -1142,12 +1426,18 @@ struct KernelsFor {
     static hipError_t adjoint(const TraceArgs& A, int shape, int grid, hipStream_t s) {
         size_t lds = trace_lds_bytes(A, A.lds_cp);
         constexpr bool cap = P == 3 && Q == 3 && NU == 3;
-        if (A.kind_group == 0)
-            hipLaunchKernelGGL((k_adjoint<P, Q, NU, 0>), dim3(grid), dim3(WG), lds, s, A, shape);
-        else if constexpr (cap)
-            hipLaunchKernelGGL((k_adjoint_w3<P, Q, NU, 1>), dim3(grid), dim3(WG), lds, s, A, shape);
-        else
-            hipLaunchKernelGGL((k_adjoint<P, Q, NU, 1>), dim3(grid), dim3(WG), lds, s, A, shape);
+        switch (A.kind_group) {
+            case 0: hipLaunchKernelGGL((k_adjoint<P, Q, NU, 0>), dim3(grid), dim3(WG), lds, s, A, shape); break;
+            case 1:
+                if constexpr (cap)
+                    hipLaunchKernelGGL((k_adjoint_w3<P, Q, NU, 1>), dim3(grid), dim3(WG), lds, s, A, shape);
+                else
+                    hipLaunchKernelGGL((k_adjoint<P, Q, NU, 1>), dim3(grid), dim3(WG), lds, s, A, shape);
+                break;
+            case 2: hipLaunchKernelGGL((k_adjoint<P, Q, NU, 2>), dim3(grid), dim3(WG), lds, s, A, shape); break;
+            case 3: hipLaunchKernelGGL((k_adjoint<P, Q, NU, 3>), dim3(grid), dim3(WG), lds, s, A, shape); break;
+            default: return hipErrorInvalidValue;
+        }
         return hipGetLastError();
     }
     static hipError_t trace_rays(const TraceArgs& A, int design, const int64_t* ids, int64_t n, float* out8,

@@ -62,6 +62,8 @@ class Detector:
 class Options:
     fresnel: int = 1
     newton_max_iter: int = 8
+    mesh_u: int = 0           # 0: exact intersection; >= 1: triangle mesh of sec. 2.2.2, rectangles per span
+    mesh_v: int = 0
 
 
 @dataclass
@@ -264,3 +266,10 @@ WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
 def with_rays(prob: Problem, side: int) -> Problem:
     """Same geometry with a different number of rays (or strata) per axis."""
     return replace(prob, source=replace(prob.source, grid_u=side, grid_v=side))
+
+
+def with_mesh(wl: Workload, m: int) -> Workload:
+    """The same workload traced on the triangle mesh of sec. 2.2.2 (m x m rectangles per knot span product)
+    instead of the exact surface."""
+    probs = [replace(p, options=replace(p.options, mesh_u=m, mesh_v=m)) for p in wl.problems]
+    return Workload(f"{wl.name}-mesh{m}", probs, wl.Pz, wl.targets)

@@ -2,6 +2,7 @@
 import ctypes
 import os
 import re
+import subprocess
 from dataclasses import replace
 
 import numpy as np
@@ -29,11 +30,22 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
-def test_struct_layout_matches_header():
-    # sizes from the header's struct definitions (x86-64 / gfx950 share the layout)
-    assert ctypes.sizeof(ffrt.CProblem) == 200
-    assert ffrt.CProblem.det.offset == 136 and ffrt.CProblem.opt.offset == 192
-    assert ffrt.STATS_BYTES == 48 and ctypes.sizeof(ffrt.CAdam) == 16
+def test_struct_layout_matches_header(tmp_path):
+    """The ctypes mirrors have the sizes and offsets the C compiler gives the header's structs (x86-64 and
+    gfx950 share the layout)."""
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stddef.h>\n#include <stdio.h>\n#include "ffrt.h"\n'
+        "int main(void) { printf(\"%zu %zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(ffrt_problem),"
+        " offsetof(ffrt_problem, src), offsetof(ffrt_problem, det), offsetof(ffrt_problem, opt),"
+        " sizeof(ffrt_options), offsetof(ffrt_options, mesh_u), sizeof(ffrt_stats), sizeof(ffrt_adam_hparams));"
+        " return 0; }\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == [ctypes.sizeof(ffrt.CProblem), ffrt.CProblem.src.offset, ffrt.CProblem.det.offset,
+                   ffrt.CProblem.opt.offset, ctypes.sizeof(ffrt.COptions), ffrt.COptions.mesh_u.offset,
+                   ffrt.STATS_BYTES, ctypes.sizeof(ffrt.CAdam)]
 
 
 def test_status_strings():

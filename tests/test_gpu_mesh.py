@@ -1,0 +1,128 @@
+"""GPU: the triangle-mesh intersection of sec. 2.2.2 (the paper's own intersector, an option beside the
+exact root), through the C ABI, against the oracle's mesh mode: irradiance per pixel, gradient, per-ray hits
+at full size, plans that mix mesh and exact designs, and optimisation steps."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2302_12031_amd import ffrt
+from paper_2302_12031_amd import workloads as W
+from parity import MAX_MARGINAL, assert_gradient, assert_irradiance
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run(wl):
+    plan = ffrt.Plan(wl.problems)
+    Pz = plan.pack_cp(wl.Pz)
+    T = plan.pack_img(wl.targets)
+    st = plan.new_stats()
+    irr = plan.forward(Pz, stats=st)
+    loss, dLdI = plan.loss(irr, T)
+    g = plan.adjoint(Pz, dLdI)
+    torch.cuda.synchronize()
+    return plan, dict(irr=plan.unpack_img(irr.cpu().numpy()), loss=loss.cpu().numpy(),
+                      g=plan.unpack_cp(g.cpu().numpy()), stats=plan.decode_stats(st))
+
+
+# Per-pixel parity needs pixels that collect many rays (one FP32 landing carries up to ~1e-4 relative filter
+# weight error), so the irradiance is compared where the workload has them: collimated c1 and c2, and the
+# point source at its full 2048^2 strata.  The gradient sums many rays per control point and is compared at
+# every size (the point source with 512^2 strata, whose oracle gradient takes seconds).
+MESH_WORKLOADS = {
+    "c1-mesh4": (lambda: W.with_mesh(W.c1(), 4), True),
+    "c2-mesh2": (lambda: W.with_mesh(W.c2(), 2), True),
+    "c3-mesh4": (lambda: W.with_mesh(W.c3(), 4), True),
+    "c3s-mesh4": (lambda: W.with_mesh(W.c3(512), 4), False),
+    "c3s-mesh1": (lambda: W.with_mesh(W.c3(512), 1), False),
+}
+
+
+@pytest.mark.parametrize("name", list(MESH_WORKLOADS))
+def test_mesh_forward_and_gradient_parity(name):
+    make, per_pixel = MESH_WORKLOADS[name]
+    wl = make()
+    _say(f"[mesh] {name}: {wl.name}, {wl.num_rays} rays")
+    plan, out = _run(wl)
+    p, Pz, T = wl.problems[0], wl.Pz[0], wl.targets[0]
+    I64, st64, mask = O.forward(p, Pz, with_mask=True)
+    worst, rel, eg = float("nan"), float("nan"), float("nan")
+    if per_pixel:
+        worst, rel = assert_irradiance(out["irr"][0], I64, mask, what=name)
+    s = out["stats"][0]
+    assert s["n_traced"] == st64["n_rays"]
+    assert st64["n_marginal"] <= MAX_MARGINAL * st64["n_rays"] + 5
+    assert abs(int(s["n_hit"]) - st64["n_hit"]) <= st64["n_marginal"] + 2
+    # the flux counter is a float sum of per-wave partials (atomics): 1e-4 relative
+    assert abs(float(s["flux_on_screen"]) - st64["flux_on_screen"]) <= 1e-4 * st64["flux_on_screen"]
+    if wl.num_rays <= 2 ** 20:
+        L64, g64, _, _ = O.grad(p, Pz, T)
+        assert abs(out["loss"][0] - L64) <= 1e-4 * L64
+        eg = assert_gradient(out["g"][0], g64, what=name)
+    _say(f"[mesh] {name}: irr worst err/tol {worst:.3g}, bright rel {rel:.2e}, grad rel {eg:.2e}")
+
+
+def test_mesh_per_ray_parity_full_size():
+    """Full-size point-source workload (2048^2 strata) on the mesh, on a sample of rays the oracle traces one
+    by one: status, landing, weight and hit (u, v)."""
+    wl = W.with_mesh(W.c3(), 4)
+    p, Pz = wl.problems[0], wl.Pz[0]
+    plan = ffrt.Plan(wl.problems)
+    ids = np.unique(np.random.default_rng(2).integers(0, wl.num_rays, 4096))
+    gpu = plan.trace_rays(0, plan.pack_cp([Pz]), ids).cpu().numpy()
+    ref = O.trace_rays(p, Pz, ids)
+    clear = ref[:, 7] == 0
+    assert (gpu[clear, 0] == ref[clear, 0]).sum() >= clear.sum() - 2
+    hit = clear & (ref[:, 0] == O.HIT) & (gpu[:, 0] == O.HIT)
+    scale = p.detector.z_screen * (1.0 + np.abs(ref[hit, 1:3]).max(1, keepdims=True) / p.detector.z_screen)
+    dxy = np.abs(gpu[hit, 1:3] - ref[hit, 1:3]) / scale
+    assert dxy.max() <= 2e-5, dxy.max()
+    assert np.median(dxy) <= 5e-7, np.median(dxy)
+    np.testing.assert_allclose(gpu[hit, 4], ref[hit, 4], atol=1e-6)
+    np.testing.assert_allclose(gpu[hit, 5], ref[hit, 5], atol=1e-6)
+    _say(f"[mesh per-ray] {hit.sum()} hits, landing err max {dxy.max():.2e}, median {np.median(dxy):.2e}, "
+         f"cells visited mean {gpu[hit, 7].mean():.2f}")
+
+
+def test_plan_mixing_mesh_and_exact_designs():
+    """One plan holding exact and mesh designs of both source kinds (four kernel groups) gives each design
+    what a plan of its own gives."""
+    a, b = W.c1(), W.c3(256)
+    designs = [(a, 0), (W.with_mesh(a, 3), 0), (b, 0), (W.with_mesh(b, 2), 0)]
+    wl = W.Workload("mixed", [w.problems[i] for w, i in designs], [w.Pz[i] for w, i in designs],
+                    [w.targets[i] for w, i in designs])
+    plan, out = _run(wl)
+    for d, (w, i) in enumerate(designs):
+        _, o1 = _run(W.Workload("one", [w.problems[i]], [w.Pz[i]], [w.targets[i]]))
+        np.testing.assert_allclose(out["irr"][d], o1["irr"][0], rtol=1e-5, atol=1e-6 * o1["irr"][0].max())
+        np.testing.assert_allclose(out["g"][d], o1["g"][0], rtol=1e-4, atol=1e-5 * np.abs(o1["g"][0]).max())
+
+
+def test_mesh_steps_reduce_the_loss():
+    """Graph-captured Adam steps on the mesh (collimated, c1 geometry): the loss falls and the last loss
+    agrees with the oracle's for the final heights."""
+    wl = W.with_mesh(W.c1(), 4)
+    plan = ffrt.Plan(wl.problems)
+    st = plan.new_state(plan.pack_cp(wl.Pz))
+    T = plan.pack_img(wl.targets)
+    plan.step(st, T, hp=ffrt.AdamHP(lr=1e-3))
+    L0 = st["loss"].item()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.graph_capture(st, T, steps=50, hp=ffrt.AdamHP(lr=1e-3))
+        plan.graph_launch(s)
+    torch.cuda.synchronize()
+    L1 = plan.loss(plan.forward(st["Pz"]), T)[0].item()
+    _say(f"[mesh steps] loss {L0:.4e} -> {L1:.4e}")
+    assert L1 < 0.9 * L0
+    P = st["Pz"].cpu().numpy().reshape(wl.problems[0].cp_shape()).astype(np.float64)
+    L64 = O.loss(O.forward(wl.problems[0], P)[0], wl.targets[0])[0]
+    assert abs(L1 - L64) <= 1e-4 * L64

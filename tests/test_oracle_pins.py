@@ -678,3 +678,135 @@ def test_sparse_mlp_at_zero_is_the_no_network_case():
     for a in range(5):
         assert not np.any(grads[a]), a
     np.testing.assert_allclose(grads[5], O.reparam_grad(b3, span, g), rtol=1e-14, atol=0)
+
+
+# ------------------------------------------------------------------------------------------------
+# Triangle-mesh intersection (sec. 2.2.2): the paper's own intersector, as an option of the oracle
+# ------------------------------------------------------------------------------------------------
+def _mesh(p, m):
+    return replace(p, options=replace(p.options, mesh_u=m, mesh_v=m))
+
+
+def _glass_rays(p, ids):
+    """Origins on the entry face and directions inside the glass of point-source rays, rebuilt here from the
+    oracle's samples with the refraction pinned above (sec. 2.2.1)."""
+    S = O.samples(p, ids)
+    ca = 1.0 - (1.0 - np.cos(p.source.half_angle)) * S[:, 1]
+    sa = np.sqrt(1.0 - ca ** 2)
+    d0 = np.stack([np.cos(S[:, 0]) * sa, np.sin(S[:, 0]) * sa, ca], 1)
+    t0 = (p.lens.z_in - p.source.pos[2]) / d0[:, 2]
+    o = np.stack([S[:, 2] + t0 * d0[:, 0], S[:, 3] + t0 * d0[:, 1], np.full(len(ids), p.lens.z_in)], 1)
+    d = np.array([O.refract(x, [0.0, 0.0, 1.0], 1.0 / p.lens.n_lens) for x in d0])
+    return o, d
+
+
+def _mesh_triangles(p, Pz, m):
+    """Every triangle of the mesh as three (x, y, z) corners on the surface: m x m rectangles per knot span
+    product, each split along the diagonal from (u_k+1, v_l) to (u_k, v_l+1)."""
+    L = p.lens
+    U, V = O.knots(L.p, L.n_u), O.knots(L.q, L.n_v)
+    us = np.unique(np.concatenate([np.linspace(U[i], U[i + 1], m + 1) for i in range(L.p, L.n_u)]))
+    vs = np.unique(np.concatenate([np.linspace(V[j], V[j + 1], m + 1) for j in range(L.q, L.n_v)]))
+    node = {}
+    for a, u in enumerate(us):
+        for b, v in enumerate(vs):
+            x, y = (2 * u - 1) * L.r_x, (2 * v - 1) * L.r_y
+            node[a, b] = np.array([x, y, O.surface(p, Pz, x, y)[0]])
+    tris = []
+    for a in range(len(us) - 1):
+        for b in range(len(vs) - 1):
+            tris.append((node[a, b], node[a + 1, b], node[a, b + 1]))
+            tris.append((node[a + 1, b + 1], node[a, b + 1], node[a + 1, b]))
+    return tris
+
+
+def _moller_trumbore(o, d, tri):
+    """Ray-triangle intersection (Moller & Trumbore 1997): t, or None."""
+    v0, v1, v2 = tri
+    e1, e2 = v1 - v0, v2 - v0
+    pv = np.cross(d, e2)
+    det = e1 @ pv
+    if abs(det) < 1e-14:
+        return None
+    s = o - v0
+    a = (s @ pv) / det
+    qv = np.cross(s, e1)
+    b = (d @ qv) / det
+    if a < -1e-12 or b < -1e-12 or a + b > 1 + 1e-12:
+        return None
+    return (e2 @ qv) / det
+
+
+def test_mesh_hit_is_the_first_triangle_hit_by_brute_force():
+    """Point-source rays on a 3 x 3-span surface with 2 x 2 rectangles per span: the oracle's hit (box
+    recursion, then the triangles of surviving spans) equals the smallest t over all 72 triangles found by
+    Moller-Trumbore, and rays that meet none leave through the side wall."""
+    p = _mesh(W.point_problem(12, 6, 16, seed=21, half_angle_deg=40.0), 2)
+    Pz = W.random_heights(6, 6, 21, spread=0.4)
+    tris = _mesh_triangles(p, Pz, 2)
+    ids = np.arange(0, 144, 1)
+    o, d = _glass_rays(p, ids)
+    out = O.trace_rays(p, Pz, ids)
+    n_hit = 0
+    for r in range(len(ids)):
+        if out[r, 0] == O.MISS_ENTRY:
+            continue
+        ts = [t for t in (_moller_trumbore(o[r], d[r], tr) for tr in tris) if t is not None and t >= 0]
+        if not ts:
+            assert out[r, 0] == O.SIDE_WALL, r
+            continue
+        n_hit += 1
+        assert out[r, 0] != O.SIDE_WALL and out[r, 0] != O.MISS_ENTRY, r
+        assert abs(out[r, 6] - min(ts)) <= 1e-9 * (1 + min(ts)), (r, out[r, 6], min(ts))
+    assert n_hit > 100
+
+
+def test_mesh_is_exact_on_a_plane():
+    """Control heights a + b x_i + c y_j at the Greville positions make the surface a plane (sec. 2.1.1),
+    which every triangle mesh represents exactly: mesh and exact hits agree for every ray."""
+    p = W.point_problem(16, 8, 32, seed=22, half_angle_deg=35.0)
+    x, y = O.control_xy(p)
+    Pz = 2.0 + 0.03 * x - 0.02 * y
+    ids = np.arange(256)
+    ex = O.trace_rays(p, Pz, ids)
+    for m in (1, 3):
+        me = O.trace_rays(_mesh(p, m), Pz, ids)
+        np.testing.assert_array_equal(me[:, 0], ex[:, 0])
+        hit = ex[:, 0] == O.HIT
+        np.testing.assert_allclose(me[hit, 1:7], ex[hit, 1:7], rtol=0, atol=1e-10)
+
+
+def test_mesh_converges_quadratically_to_the_exact_hit():
+    """Linear interpolation on triangles of size h errs by O(h^2): doubling the rectangles per span cuts
+    the largest hit-height error about fourfold."""
+    p = W.point_problem(16, 8, 32, seed=23, half_angle_deg=30.0)
+    Pz = W.random_heights(8, 8, 23, spread=0.3)
+    ids = np.arange(0, 256, 1)
+    ex = O.trace_rays(p, Pz, ids)
+    errs = []
+    for m in (2, 4, 8, 16):
+        me = O.trace_rays(_mesh(p, m), Pz, ids)
+        ok = (ex[:, 0] == O.HIT) & (me[:, 0] == O.HIT)
+        errs.append(np.abs(me[ok, 6] - ex[ok, 6]).max())
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(2.5 < r < 6.0 for r in ratios), (errs, ratios)
+
+
+@pytest.mark.parametrize("kind", ["collimated", "point"])
+def test_mesh_gradient_matches_central_fd(kind):
+    """dL/dP of the mesh-mode trace (the hit moves with the corner heights of its triangle; the normal is
+    the B-spline's) against central differences of the mesh-mode loss."""
+    if kind == "collimated":
+        p = _mesh(W.collimated_problem(48, 6, 16, jitter=1, seed=24, R=8.0, z=30.0), 3)
+    else:
+        p = _mesh(W.point_problem(40, 6, 16, seed=24, R=12.0, z=25.0, half_angle_deg=25.0), 3)
+    Pz = W.random_heights(6, 6, 24, spread=0.15)
+    T = W.rng(24, 3).uniform(0.5, 1.0, p.image_shape())
+    L0, g, _, _ = O.grad(p, Pz, T)
+    h = 1e-6
+    for k in [(1, 2), (2, 3), (3, 3), (4, 1)]:
+        E = np.zeros_like(Pz)
+        E[k] = h
+        Lp = O.loss(O.forward(p, Pz + E)[0], T)[0]
+        Lm = O.loss(O.forward(p, Pz - E)[0], T)[0]
+        assert abs((Lp - Lm) / (2 * h) - g[k]) <= 2e-5 * np.abs(g).max(), (k, (Lp - Lm) / (2 * h), g[k])
