@@ -44,8 +44,8 @@ MESH_CELL_FLOPS = 390
 MESH_ADJ_EXTRA = 64
 # Algorithmic HBM bytes of the generator per design with K control points and n parameters (fp32): the
 # forward reads the two weight matrices (dense 2 K^2, sparse 2 C K floats; vectors of K are negligible); the
-# dense back-propagation reads them again; the gradient + Adam kernel reads and writes parameters and both
-# moments (6 n floats; the sparse architecture fuses it with its back-propagation).
+# back-propagation reads them again; the gradient + Adam pass reads and writes parameters and both moments
+# (6 n floats).
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 78.6         # 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz, no packed FP32
 PEAK_FP32_PACKED_TFLOPS = 157.3
@@ -243,12 +243,10 @@ def main():
         Cs = [(2 * p.lens.p + 1) * (2 * p.lens.q + 1) for p in wl.problems]
         W_floats = sum(2 * K * K if arch == ffrt.MLP_DENSE else 2 * C * K for K, C in zip(Ks, Cs))
         n_par = timed.mlp_offsets(arch)[-1]
-        groups = {"forward": (g_fwd, 4 * W_floats),
-                  "backprop": (g_bwd, 4 * W_floats + (24 * n_par if arch == ffrt.MLP_SPARSE else 0)),
-                  "update": (g_upd, 24 * n_par if arch == ffrt.MLP_DENSE else 0)}
+        groups = {"forward": (g_fwd, 4 * W_floats), "backprop": (g_bwd, 4 * W_floats), "update": (g_upd, 24 * n_par)}
         kern = {"forward": "k_mlp_layer1 + 2 x k_mlp_gemv" if arch == ffrt.MLP_DENSE else "k_smlp_forward",
-                "backprop": "k_mlp_seed + 2 x k_mlp_gemv_t" if arch == ffrt.MLP_DENSE else "k_smlp_backward",
-                "update": "k_mlp_grad_adam" if arch == ffrt.MLP_DENSE else "(fused)"}
+                "backprop": "k_mlp_seed + 2 x k_mlp_gemv_t" if arch == ffrt.MLP_DENSE else "k_smlp_backprop",
+                "update": "k_mlp_grad_adam" if arch == ffrt.MLP_DENSE else "k_smlp_update"}
         gname = max(groups, key=lambda k: groups[k][0])
         gms, gbytes = groups[gname]
         gach = gbytes / (gms * 1e-3) / 1e9

@@ -77,11 +77,13 @@ typedef struct {
 
 /* Detector (sec. 2.3): n_x x n_y pixels on [-R_x, R_x) x [-R_y, R_y) at z = z_screen.  Filter
  * f(x) = exp(-alpha ((x - c)/w)^2) - exp(-alpha (nu/2)^2) inside nu pixels (alpha per pixel width^2),
- * normalised over the grid.  ghost = 1 adds (nu-1)/2 ghost pixels on each side. */
+ * normalised over the grid.  ghost = 1 adds (nu-1)/2 ghost pixels on each side.  filter = 1 selects box
+ * reconstruction instead (the pixel's indicator: a ray's weight goes to its landing pixel; the image then
+ * has no derivative in the landing position, only through the Fresnel weights). */
 typedef struct {
     int32_t n_x, n_y;
     double R_x, R_y, z_screen, alpha;
-    int32_t nu_x, nu_y, ghost;
+    int32_t nu_x, nu_y, ghost, filter;
 } ffrt_detector;
 
 /* fresnel: 1 applies Schlick's approximation at both faces (cosine taken on the air side), 0 does not.
@@ -224,7 +226,7 @@ ffrt_status ffrt_plan_control_xy(const ffrt_plan* plan, double* x, double* y);
  *     whose basis functions share a knot span), a weight per connection and a bias per neuron.  Neuron (i, j)
  *     takes the layer input at (i + a - p, j + b - q), a in [0, 2p], b in [0, 2q]; packed: w1 (K), b1 (K),
  *     W2 (C x K: W2[c][k], c = a (2q + 1) + b), b2 (K), W3 (C x K), b3 (K), C = (2p+1)(2q+1): 2 C K + 4 K floats.
- *     A connection that would leave the net does not exist: its stored weight gets zero gradient.  K <= 3072.
+ *     A connection that would leave the net does not exist: its stored weight gets zero gradient.  K <= 6144.
  * params: device float32; design d's parameters start at offsets[d] (ffrt_mlp_layout); offsets[n_designs] is
  * the total.  acts: device float32 of 3 x (total control points), design d's h1, h2, y (K each) at 3 x its
  * control-point offset; written by ffrt_mlp_forward, read by the backward pass.  lo, span, Pz, dL_dP: packed
@@ -276,8 +278,7 @@ ffrt_status ffrt_plan_autotune(ffrt_plan* plan, const float* Pz, float* irr, con
                                float* dL_dP, int32_t reps, void* stream);
 
 /* Mean duration (ms) of the generator's forward pass, its back-propagation to the layer vectors, and its
- * gradient + Adam update (the sparse architecture does both of the latter in one kernel, timed as the
- * back-propagation; upd_ms is then 0), each launched `reps` times back to back between HIP events on `stream`
+ * gradient + Adam update, each launched `reps` times back to back between HIP events on `stream`
  * after one untimed pass.  params, m and v are updated reps + 1 times (pass copies); acts and Pz are
  * overwritten; t is read only.  Synchronises the stream. */
 ffrt_status ffrt_plan_time_mlp(ffrt_plan* plan, int32_t arch, float* params, float* m, float* v, const int32_t* t,

@@ -41,7 +41,7 @@ class OrcProblem(ctypes.Structure):
         ("alpha", ctypes.c_double),
         ("nu_x", ctypes.c_int32), ("nu_y", ctypes.c_int32), ("ghost", ctypes.c_int32),
         ("fresnel", ctypes.c_int32), ("mesh_u", ctypes.c_int32), ("mesh_v", ctypes.c_int32),
-        ("pad_", ctypes.c_int32),
+        ("filter", ctypes.c_int32),
     ]
 
 
@@ -118,6 +118,7 @@ def to_struct(prob):
     s.z_screen, s.alpha, s.nu_x, s.nu_y, s.ghost = D.z_screen, D.alpha, D.nu_x, D.nu_y, D.ghost
     s.fresnel = O.fresnel
     s.mesh_u, s.mesh_v = getattr(O, "mesh_u", 0), getattr(O, "mesh_v", 0)
+    s.filter = getattr(D, "filter", 0)
     return s
 
 

@@ -160,6 +160,7 @@ bool valid_problem(const orc_problem* pr) {
     if (pr->nu_x < 1 || pr->nu_y < 1 || pr->nu_x % 2 == 0 || pr->nu_y % 2 == 0) return false;
     if (!(pr->R_x > 0) || !(pr->R_y > 0) || !(pr->alpha > 0)) return false;
     if (pr->kind < 0 || pr->kind > 2) return false;
+    if (pr->filter != 0 && pr->filter != 1) return false;
     if (pr->mesh_u < 0 || pr->mesh_v < 0 || pr->mesh_u > 64 || pr->mesh_v > 64 || (pr->mesh_u == 0) != (pr->mesh_v == 0))
         return false;
     if (pr->kind != 0) {
@@ -672,11 +673,18 @@ Exit<S> exit_and_screen(const Geo& g, const S* q, const double* d, const S& hx, 
 // Reading: distances in pixel widths (alpha per pixel^2); pixel i is [i w - R*, (i+1) w - R*) (0-based);
 // the sum runs over the pixels of the grid.  Window = the nu pixels centred on the landing pixel, which
 // holds the whole support.  Fills idx[] with pixel indices and F[] with the normalised weights.
+// With box (the simplest reconstruction of sec. 2.3) the filter of pixel i is the indicator of the pixel:
+// the ray's weight goes to its landing pixel alone, and the pixel value does not move with X.
 template <class S>
-int filter_axis(int n, double R, double w, int nu, double alpha, const S& X, int* idx, S* F) {
+int filter_axis(int n, double R, double w, int nu, double alpha, const S& X, int* idx, S* F, bool box) {
     int i0 = int(std::floor((val(X) + R) / w));
     if (i0 < 0) i0 = 0;
     if (i0 > n - 1) i0 = n - 1;
+    if (box) {
+        idx[0] = i0;
+        F[0] = S(1.0);
+        return 1;
+    }
     int h = (nu - 1) / 2;
     double edge = std::exp(-alpha * (0.5 * nu) * (0.5 * nu));
     S sum = 0.0;
@@ -704,8 +712,8 @@ template <class S, class Fn>
 void splat(const Geo& g, const S& X, const S& Y, const S& w, Fn fn) {
     int ix[MAXNU], iy[MAXNU];
     S Fx[MAXNU], Fy[MAXNU];
-    int cx = filter_axis(g.nxe, g.Rxe, g.wx, g.pr.nu_x, g.pr.alpha, X, ix, Fx);
-    int cy = filter_axis(g.nye, g.Rye, g.wy, g.pr.nu_y, g.pr.alpha, Y, iy, Fy);
+    int cx = filter_axis(g.nxe, g.Rxe, g.wx, g.pr.nu_x, g.pr.alpha, X, ix, Fx, g.pr.filter == 1);
+    int cy = filter_axis(g.nye, g.Rye, g.wy, g.pr.nu_y, g.pr.alpha, Y, iy, Fy, g.pr.filter == 1);
     for (int a = 0; a < cx; ++a)
         for (int b = 0; b < cy; ++b) fn(int64_t(ix[a]) * g.nye + iy[b], w * Fx[a] * Fy[b]);
 }

@@ -49,7 +49,7 @@ typedef struct {
     int32_t fresnel;                 /* 1: Schlick weights at both faces, 0: none */
     int32_t mesh_u, mesh_v;          /* 0: exact intersection; >= 1: the triangle mesh of sec. 2.2.2 with
                                         mesh_u x mesh_v rectangles per knot span product */
-    int32_t pad_;
+    int32_t filter;                  /* 0: Gaussian reconstruction filter, 1: box (indicator of the pixel) */
 } orc_problem;
 
 typedef struct {

@@ -56,7 +56,7 @@ struct DesignDev {
     float fx_scale, fx_unscale;
     int32_t sb_off;                  // first record of the design's span bounds (workspace)
     int32_t mesh_u, mesh_v;          // triangle mesh of sec. 2.2.2: rectangles per knot span (0: exact root)
-    int32_t pad_;
+    int32_t box;                     // box reconstruction (sec. 2.3) instead of the Gaussian filter
     float inv_mesh_u, inv_mesh_v;
 };
 
@@ -179,21 +179,20 @@ hipError_t launch_finish(const DesignDev* designs, int n_designs, float* gacc, f
 // writes dL/dtheta from dL/dP.
 hipError_t launch_reparam(int mode, int64_t n, const float* theta, const float* lo, const float* span, float* P,
                           const float* dLdP, float* dLdtheta, hipStream_t s);
-// The control-point generators of sec. 2.4 (ffrt_mlp.hip); arch: FFRT_MLP_DENSE or FFRT_MLP_SPARSE.  poff:
-// device offsets of each design's parameters; acts: h1, h2, y per design at 3 cp_off.  Forward: activations
-// and Pz (with t set, the step counter of every valid design advances).  Backward: dz3, dh2, dh1 (packed like
-// Pz; dense only) are scratch; grad (may be null) receives the parameter gradient; with hp set, Adam updates
-// the parameters of valid designs.  The sparse kernels hold 2 (forward) and 5 (backward) Kmax floats in LDS.
-// part: MLP_ALL, or (for timing) MLP_BACKPROP (vectors only) / MLP_UPDATE (gradient and Adam only; a no-op for
-// the sparse architecture, whose single backward kernel does both).
+// The control-point generators of sec. 2.4 (ffrt_mlp.hip); arch: FFRT_MLP_DENSE or FFRT_MLP_SPARSE, P and Q
+// the plan's degrees (the sparse footprint).  poff: device offsets of each design's parameters; acts: h1, h2,
+// y per design at 3 cp_off.  Forward: activations and Pz (with t set, the step counter of every valid design
+// advances).  Backward: dz3, dh2, dh1 (packed like Pz) are scratch; grad (may be null) receives the parameter
+// gradient; with hp set, Adam updates the parameters of valid designs.  The sparse kernels hold 2 Kmax floats
+// in LDS.  part: MLP_ALL, or (for timing) MLP_BACKPROP (vectors only) / MLP_UPDATE (gradient and Adam only).
 enum { MLP_ALL = 0, MLP_BACKPROP = 1, MLP_UPDATE = 2 };
-hipError_t launch_mlp_forward(int arch, const DesignDev* designs, int nd, int Kmax, const int64_t* poff,
-                              const float* par, float* acts, const float* lo, const float* span, float* Pz, int32_t* t,
-                              const int32_t* valid, hipStream_t s);
-hipError_t launch_mlp_backward(int arch, int part, const DesignDev* designs, int nd, int Kmax, const int64_t* poff,
-                               float* par, const float* acts, const float* span, const float* dLdP, float* dz3,
-                               float* dh2, float* dh1, float* grad, float* m, float* v, const int32_t* t,
-                               const int32_t* valid, const ffrt_adam_hparams* hp, hipStream_t s);
+hipError_t launch_mlp_forward(int arch, int P, int Q, const DesignDev* designs, int nd, int Kmax,
+                              const int64_t* poff, const float* par, float* acts, const float* lo, const float* span,
+                              float* Pz, int32_t* t, const int32_t* valid, hipStream_t s);
+hipError_t launch_mlp_backward(int arch, int part, int P, int Q, const DesignDev* designs, int nd, int Kmax,
+                               const int64_t* poff, float* par, const float* acts, const float* span,
+                               const float* dLdP, float* dz3, float* dh2, float* dh1, float* grad, float* m, float* v,
+                               const int32_t* t, const int32_t* valid, const ffrt_adam_hparams* hp, hipStream_t s);
 hipError_t launch_loss_f64(const DesignDev* designs, int n_designs, const float* irr, const float* target,
                            double* loss, hipStream_t s);
 hipError_t launch_adam(const DesignDev* designs, int n_designs, float* Pz, const float* g, float* m,

@@ -75,7 +75,8 @@ struct ffrt_plan {
     // workspace
     char* ws = nullptr;
     size_t ws_bytes = 0;
-    size_t off_designs = 0, off_bounds = 0, off_sb = 0, off_valid = 0, off_knots = 0, off_bmap = 0, off_slots = 0, need = 0;
+    size_t off_designs = 0, off_bounds = 0, off_sb = 0, off_valid = 0, off_knots = 0, off_bmap = 0, off_slots = 0;
+    size_t need = 0;
     size_t off_lpart = 0, off_img64 = 0, off_gacc = 0, off_dldi = 0, off_mlpoff = 0, off_mlpvec = 0;
     int num_cu = 256;
     int fwd_cfg = 0, adj_cfg = 0;
@@ -133,6 +134,7 @@ ffrt_status validate(const ffrt_problem& pr, int idx) {
     if (!(D.alpha > 0)) return bad("alpha must be > 0");
     if (!odd3(D.nu_x) || !odd3(D.nu_y)) return bad("filter sizes must be odd and >= 3");
     if (D.ghost != 0 && D.ghost != 1) return bad("ghost must be 0 or 1");
+    if (D.filter != 0 && D.filter != 1) return bad("filter must be 0 (Gaussian) or 1 (box)");
     if (!(D.z_screen > L.z_in)) return bad("screen must lie above the entry face");
     if (pr.opt.fresnel != 0 && pr.opt.fresnel != 1) return bad("fresnel must be 0 or 1");
     if (pr.opt.newton_max_iter < 1 || pr.opt.newton_max_iter > 32) return bad("newton_max_iter in [1, 32]");
@@ -221,6 +223,7 @@ DesignDev make_design(const ffrt_problem& pr, int64_t cp_off, int64_t img_off, i
     d.edge_y = (float)std::exp(-D.alpha * 0.25 * D.nu_y * D.nu_y);
     d.fresnel = pr.opt.fresnel;
     d.newton_max = pr.opt.newton_max_iter;
+    d.box = pr.det.filter;
     d.mesh_u = pr.opt.mesh_u;
     d.mesh_v = pr.opt.mesh_v;
     d.inv_mesh_u = d.mesh_u ? 1.0f / (float)d.mesh_u : 0.0f;
@@ -367,11 +370,12 @@ ffrt_status run_step_mlp(ffrt_plan* pl, int arch, float* par, float* m, float* v
     ffrt_status st = run_step(pl, Pz, target, irr, loss, dLdI, dLdP, nullptr, nullptr, nullptr, stats, hp, s, nullptr,
                               nullptr, nullptr, false);
     if (st) return st;
-    HIP_TRY(launch_mlp_backward(arch, MLP_ALL, pl->d_designs(), pl->nd, pl->max_cp, pl->d_mlpoff(arch), par, acts, span,
+    const int64_t* po = pl->d_mlpoff(arch);
+    HIP_TRY(launch_mlp_backward(arch, MLP_ALL, pl->P, pl->Q, pl->d_designs(), pl->nd, pl->max_cp, po, par, acts, span,
                                 dLdP, pl->d_mlpvec(0), pl->d_mlpvec(1), pl->d_mlpvec(2), nullptr, m, v, t,
                                 pl->d_valid(), &hp, s));
-    HIP_TRY(launch_mlp_forward(arch, pl->d_designs(), pl->nd, pl->max_cp, pl->d_mlpoff(arch), par, acts, lo, span,
-                               Pz, t, pl->d_valid(), s));
+    HIP_TRY(launch_mlp_forward(arch, pl->P, pl->Q, pl->d_designs(), pl->nd, pl->max_cp, po, par, acts, lo, span, Pz, t,
+                               pl->d_valid(), s));
     return FFRT_OK;
 }
 
@@ -687,14 +691,14 @@ ffrt_status ffrt_graph_capture_reparam(ffrt_plan* plan, int32_t steps, float* th
     return capture(plan, steps, Pz, target, irr, loss, dL_dI, dL_dP, m, v, t, stats, hp, stream, theta, lo, span);
 }
 
-// The dense GEMV stages one layer's input vector (K floats) in LDS, the sparse kernels five such vectors.
-static constexpr int MLP_MAX_K[2] = {16384, 3072};
+// The dense GEMV stages one layer's input vector (K floats) in LDS, the sparse kernels two such vectors.
+static constexpr int MLP_MAX_K[2] = {16384, 6144};
 static ffrt_status mlp_check(ffrt_plan* plan, int32_t arch) {
     if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
     if (arch != FFRT_MLP_DENSE && arch != FFRT_MLP_SPARSE) return fail(FFRT_E_ARG, "unknown generator architecture");
     if (plan->max_cp > MLP_MAX_K[arch])
         return fail(FFRT_E_ARG, arch == FFRT_MLP_DENSE ? "dense generator: a control net exceeds 16384 points"
-                                                       : "sparse generator: a control net exceeds 3072 points");
+                                                       : "sparse generator: a control net exceeds 6144 points");
     return FFRT_OK;
 }
 
@@ -709,9 +713,9 @@ ffrt_status ffrt_mlp_forward(ffrt_plan* plan, int32_t arch, const float* params,
                              float* acts, float* Pz, void* stream) {
     if (ffrt_status st = mlp_check(plan, arch)) return st;
     if (!params || !lo || !span || !acts || !Pz) return fail(FFRT_E_ARG, "null buffer");
-    HIP_TRY(launch_mlp_forward(arch, plan->d_designs(), plan->nd, plan->max_cp, plan->d_mlpoff(arch), params, acts, lo,
-                               span, Pz,
-                               nullptr, nullptr, (hipStream_t)stream));
+    HIP_TRY(launch_mlp_forward(arch, plan->P, plan->Q, plan->d_designs(), plan->nd, plan->max_cp,
+                               plan->d_mlpoff(arch), params, acts, lo, span, Pz, nullptr, nullptr,
+                               (hipStream_t)stream));
     return FFRT_OK;
 }
 
@@ -719,10 +723,10 @@ ffrt_status ffrt_mlp_backward(ffrt_plan* plan, int32_t arch, const float* params
                               const float* dL_dP, float* grad, void* stream) {
     if (ffrt_status st = mlp_check(plan, arch)) return st;
     if (!params || !acts || !span || !dL_dP || !grad) return fail(FFRT_E_ARG, "null buffer");
-    HIP_TRY(launch_mlp_backward(arch, MLP_ALL, plan->d_designs(), plan->nd, plan->max_cp, plan->d_mlpoff(arch),
-                                const_cast<float*>(params),
-                                acts, span, dL_dP, plan->d_mlpvec(0), plan->d_mlpvec(1), plan->d_mlpvec(2), grad,
-                                nullptr, nullptr, nullptr, nullptr, nullptr, (hipStream_t)stream));
+    HIP_TRY(launch_mlp_backward(arch, MLP_ALL, plan->P, plan->Q, plan->d_designs(), plan->nd, plan->max_cp,
+                                plan->d_mlpoff(arch), const_cast<float*>(params), acts, span, dL_dP,
+                                plan->d_mlpvec(0), plan->d_mlpvec(1), plan->d_mlpvec(2), grad, nullptr, nullptr,
+                                nullptr, nullptr, nullptr, (hipStream_t)stream));
     return FFRT_OK;
 }
 
@@ -906,13 +910,13 @@ ffrt_status ffrt_plan_time_mlp(ffrt_plan* plan, int32_t arch, float* params, flo
     hipStream_t s = (hipStream_t)stream;
     const int64_t* po = plan->d_mlpoff(arch);
     auto fwd = [&]() {
-        return launch_mlp_forward(arch, plan->d_designs(), plan->nd, plan->max_cp, po, params, acts, lo, span, Pz,
-                                  nullptr, nullptr, s);
+        return launch_mlp_forward(arch, plan->P, plan->Q, plan->d_designs(), plan->nd, plan->max_cp, po, params, acts,
+                                  lo, span, Pz, nullptr, nullptr, s);
     };
     auto bwd = [&](int part) {
-        return launch_mlp_backward(arch, part, plan->d_designs(), plan->nd, plan->max_cp, po, params, acts, span,
-                                   dL_dP, plan->d_mlpvec(0), plan->d_mlpvec(1), plan->d_mlpvec(2), nullptr, m, v, t,
-                                   nullptr, hp, s);
+        return launch_mlp_backward(arch, part, plan->P, plan->Q, plan->d_designs(), plan->nd, plan->max_cp, po,
+                                   params, acts, span, dL_dP, plan->d_mlpvec(0), plan->d_mlpvec(1),
+                                   plan->d_mlpvec(2), nullptr, m, v, t, nullptr, hp, s);
     };
     hipEvent_t ev[6];
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));

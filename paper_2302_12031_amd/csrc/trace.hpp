@@ -638,14 +638,24 @@ __device__ __forceinline__ ExitState exit_face(const DesignDev& D, float qx, flo
 // Gaussian reconstruction filter along one axis (sec. 2.3, filter eq.):
 //   f_i = exp(-alpha ((X - c_i)/w)^2) - exp(-alpha (nu/2)^2) inside the support, c_i = (i + 1/2) w - R,
 // window = the NU pixels centred on the landing pixel i0, pixels outside the grid excluded, normalised.
-// F[m] is the weight of pixel i0 - (NU-1)/2 + m; dF[m] = dF/dX.
+// F[m] is the weight of pixel i0 - (NU-1)/2 + m; dF[m] = dF/dX.  With box (the simplest reconstruction of
+// sec. 2.3, the indicator of the pixel) the window holds the landing pixel alone, with weight 1 and no
+// derivative.
 // ------------------------------------------------------------------------------------------------
 template <int NU, bool DERIV>
 __device__ __forceinline__ int filter_axis(float X, float R, float w, float inv_w, int n, float alpha,
-                                           float edge, float* F, float* dF) {
+                                           float edge, float* F, float* dF, bool box) {
     constexpr int H = (NU - 1) / 2;
     int i0 = (int)floorf((X + R) * inv_w);
     i0 = min(max(i0, 0), n - 1);
+    if (box) {
+#pragma unroll
+        for (int m = 0; m < NU; ++m) {
+            F[m] = m == H ? 1.0f : 0.0f;
+            if constexpr (DERIV) dF[m] = 0.0f;
+        }
+        return i0;
+    }
     float c0 = ((float)i0 + 0.5f) * w - R;
     float delta = (X - c0) * inv_w;  // offset from the centre of pixel i0, in pixel widths
     float S = 0.0f, Sp = 0.0f;
@@ -825,8 +835,8 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
 
     // ---- splat, reverse: I_ij += w Fx_i Fy_j
     float Fx[NU], dFx[NU], Fy[NU], dFy[NU];
-    int i0 = filter_axis<NU, true>(E.X, D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, dFx);
-    int j0 = filter_axis<NU, true>(E.Y, D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, dFy);
+    int i0 = filter_axis<NU, true>(E.X, D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, dFx, D.box);
+    int j0 = filter_axis<NU, true>(E.Y, D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, dFy, D.box);
     constexpr int H = (NU - 1) / 2;
     float wbar = 0.0f, Xbar = 0.0f, Ybar = 0.0f;
 #pragma unroll
@@ -1163,8 +1173,12 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
             for (int r = 0; r < RPT; ++r) {
                 if (W[r] == 0.0f) continue;
                 float Fx[NU], Fy[NU];
-                const int di = filter_axis<NU, false>(X[r], D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr) - H - ai;
-                const int dj = filter_axis<NU, false>(Y[r], D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr) - H - aj;
+                const int di =
+                    filter_axis<NU, false>(X[r], D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr, D.box) -
+                    H - ai;
+                const int dj =
+                    filter_axis<NU, false>(Y[r], D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr, D.box) -
+                    H - aj;
                 if (di > WN - NU || dj > WN - NU) {
 #pragma unroll
                     for (int a = 0; a < NU; ++a) {
@@ -1199,8 +1213,10 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
             for (int r = 0; r < RPT; ++r) {
                 if (W[r] == 0.0f) continue;
                 float Fx[NU], Fy[NU];
-                int i0 = filter_axis<NU, false>(X[r], D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr);
-                int j0 = filter_axis<NU, false>(Y[r], D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr);
+                int i0 =
+                    filter_axis<NU, false>(X[r], D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr, D.box);
+                int j0 =
+                    filter_axis<NU, false>(Y[r], D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr, D.box);
 #pragma unroll
                 for (int a = 0; a < NU; ++a) {
                     int i = i0 + a - H;

@@ -38,7 +38,8 @@ class CSource(ctypes.Structure):
 class CDetector(ctypes.Structure):
     _fields_ = [("n_x", ctypes.c_int32), ("n_y", ctypes.c_int32), ("R_x", ctypes.c_double),
                 ("R_y", ctypes.c_double), ("z_screen", ctypes.c_double), ("alpha", ctypes.c_double),
-                ("nu_x", ctypes.c_int32), ("nu_y", ctypes.c_int32), ("ghost", ctypes.c_int32)]
+                ("nu_x", ctypes.c_int32), ("nu_y", ctypes.c_int32), ("ghost", ctypes.c_int32),
+                ("filter", ctypes.c_int32)]
 
 
 class COptions(ctypes.Structure):
@@ -148,7 +149,7 @@ def to_cproblem(p):
     c.lens = CLens(L.n_lens, L.r_x, L.r_y, L.z_in, L.delta_min, L.p, L.q, L.n_u, L.n_v)
     c.src = CSource(S.kind, S.grid_u, S.grid_v, S.jitter, (ctypes.c_double * 3)(*S.pos), S.half_angle,
                     S.emit_nx, S.emit_ny, S.emit_wx, S.emit_wy, S.seed)
-    c.det = CDetector(D.n_x, D.n_y, D.R_x, D.R_y, D.z_screen, D.alpha, D.nu_x, D.nu_y, D.ghost)
+    c.det = CDetector(D.n_x, D.n_y, D.R_x, D.R_y, D.z_screen, D.alpha, D.nu_x, D.nu_y, D.ghost, D.filter)
     c.opt = COptions(O.fresnel, O.newton_max_iter, O.mesh_u, O.mesh_v)
     return c
 

@@ -56,6 +56,7 @@ class Detector:
     nu_x: int = 3
     nu_y: int = 3
     ghost: int = 0
+    filter: int = 0           # 0: Gaussian reconstruction filter, 1: box (the landing pixel's indicator)
 
 
 @dataclass

@@ -158,3 +158,27 @@ def test_batched_plan_matches_separate_plans():
         assert_irradiance(out["irr"][d], I64, mask, what=f"design {d}")
         L64, g64, _, _ = O.grad(wl.problems[d], wl.Pz[d], wl.targets[d])
         assert_gradient(out["g"][d], g64, what=f"design {d}")
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_box_reconstruction_parity(name):
+    """Box reconstruction (sec. 2.3): each ray's weight in its landing pixel.  A ray whose FP32 landing lies
+    within rounding distance of a pixel edge may change pixel, so pixels may differ by up to two ray weights
+    (a handful do); the flux and the gradient (the Fresnel-weight part only) agree as for the Gaussian."""
+    from dataclasses import replace
+    base = WORKLOADS[name]()
+    probs = [replace(p, detector=replace(p.detector, filter=1)) for p in base.problems]
+    wl = W.Workload(base.name + "-box", probs, base.Pz, base.targets)
+    _say(f"[box] {name}: {wl.num_rays} rays")
+    plan, out = _run(wl)
+    p, Pz, T = wl.problems[0], wl.Pz[0], wl.targets[0]
+    I64, st64 = O.forward(p, Pz)
+    w_ray = 1.0 / wl.num_rays
+    d = np.abs(out["irr"][0] - I64)
+    assert d.max() <= 2.0 * w_ray, d.max() / w_ray
+    assert (d > 0.5 * w_ray).sum() <= 1e-3 * wl.num_rays + 10
+    assert abs(out["irr"][0].sum() - I64.sum()) <= 1e-5 * I64.sum()
+    if wl.num_rays <= 2 ** 21:
+        L64, g64, _, _ = O.grad(p, Pz, T)
+        assert_gradient(out["g"][0], g64, rel=1e-2, what=f"{name} box")
+    _say(f"[box] {name}: pixels off by more than half a ray weight: {int((d > 0.5 * w_ray).sum())}")

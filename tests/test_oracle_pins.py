@@ -810,3 +810,53 @@ def test_mesh_gradient_matches_central_fd(kind):
         Lp = O.loss(O.forward(p, Pz + E)[0], T)[0]
         Lm = O.loss(O.forward(p, Pz - E)[0], T)[0]
         assert abs((Lp - Lm) / (2 * h) - g[k]) <= 2e-5 * np.abs(g).max(), (k, (Lp - Lm) / (2 * h), g[k])
+
+
+# ------------------------------------------------------------------------------------------------
+# Box reconstruction (sec. 2.3, the simplest reconstruction): each ray's weight in its landing pixel
+# ------------------------------------------------------------------------------------------------
+def _box(p):
+    return replace(p, detector=replace(p.detector, filter=1))
+
+
+@pytest.mark.parametrize("kind", ["collimated", "point"])
+def test_box_image_is_the_weighted_histogram_of_landings(kind):
+    """The box image equals numpy's weighted 2-D histogram of the oracle's own ray landings over the pixel
+    grid (a library routine), and it conserves the flux on the screen."""
+    if kind == "collimated":
+        p = _box(W.collimated_problem(64, 8, 32, jitter=1, seed=31))
+    else:
+        p = _box(W.point_problem(48, 8, 32, seed=31))
+    Pz = W.random_heights(8, 8, 31)
+    I, st = O.forward(p, Pz)
+    R = O.trace_rays(p, Pz, np.arange(O.num_rays(p)))
+    hit = R[:, 0] == O.HIT
+    D = p.detector
+    H, _, _ = np.histogram2d(R[hit, 1], R[hit, 2], bins=[D.n_x, D.n_y], range=[[-D.R_x, D.R_x], [-D.R_y, D.R_y]],
+                             weights=R[hit, 3])
+    np.testing.assert_allclose(I, H, rtol=1e-12, atol=1e-15)
+    assert abs(I.sum() - st["flux_on_screen"]) <= 1e-12
+
+
+def test_box_gradient_is_the_fresnel_part_only():
+    """The box image does not move with the landing position: without Fresnel weights its pathwise gradient
+    vanishes; with them it is the weights' derivative, checked against central differences of the image
+    with every ray's pixel held fixed."""
+    p0 = _box(W.collimated_problem(48, 6, 16, jitter=1, seed=32, R=8.0, z=30.0))
+    Pz = W.random_heights(6, 6, 32, spread=0.15)
+    T = W.rng(32, 3).uniform(0.5, 1.0, p0.image_shape())
+    _, g, _, _ = O.grad(replace(p0, options=replace(p0.options, fresnel=0)), Pz, T)
+    assert np.abs(g).max() == 0.0
+    L, g, _, G = O.grad(p0, Pz, T)
+    ids = np.arange(O.num_rays(p0))
+    base = O.trace_rays(p0, Pz, ids)
+    k, h = (2, 3), 1e-6
+    E = np.zeros_like(Pz)
+    E[k] = h
+    Rp, Rm = O.trace_rays(p0, Pz + E, ids), O.trace_rays(p0, Pz - E, ids)
+    ok = (base[:, 0] == O.HIT) & (Rp[:, 0] == O.HIT) & (Rm[:, 0] == O.HIT)
+    D = p0.detector
+    pix = (np.floor((base[ok, 1] + D.R_x) / (2 * D.R_x / D.n_x)).astype(int) * D.n_y +
+           np.floor((base[ok, 2] + D.R_y) / (2 * D.R_y / D.n_y)).astype(int))
+    fd = np.sum(G.ravel()[pix] * (Rp[ok, 3] - Rm[ok, 3]) / (2 * h))
+    assert abs(fd - g[k]) <= 1e-6 * max(abs(fd), 1e-12) + 1e-12, (fd, g[k])
