@@ -41,7 +41,7 @@ class OrcProblem(ctypes.Structure):
         ("alpha", ctypes.c_double),
         ("nu_x", ctypes.c_int32), ("nu_y", ctypes.c_int32), ("ghost", ctypes.c_int32),
         ("fresnel", ctypes.c_int32), ("mesh_u", ctypes.c_int32), ("mesh_v", ctypes.c_int32),
-        ("filter", ctypes.c_int32),
+        ("filter", ctypes.c_int32), ("entry_freeform", ctypes.c_int32), ("pad2_", ctypes.c_int32),
     ]
 
 
@@ -119,6 +119,7 @@ def to_struct(prob):
     s.fresnel = O.fresnel
     s.mesh_u, s.mesh_v = getattr(O, "mesh_u", 0), getattr(O, "mesh_v", 0)
     s.filter = getattr(D, "filter", 0)
+    s.entry_freeform = getattr(L, "entry_freeform", 0)
     return s
 
 

@@ -37,7 +37,7 @@ struct NoInit {};
 
 struct Dual {
     double v;
-    double d[MAXT];
+    double d[2 * MAXT];  // both faces' local control points when the entry face is freeform too
     Dual() : v(0.0) { for (int k = 0; k < tl_nt; ++k) d[k] = 0.0; }
     Dual(double x) : v(x) { for (int k = 0; k < tl_nt; ++k) d[k] = 0.0; }
     Dual(double x, NoInit) : v(x) {}
@@ -144,6 +144,8 @@ struct Geo {
     std::vector<double> U, V;
     double zmin, zmax;      // global convex-hull bounds of P^z (sec. 2.2.2, whole-surface test)
     double Gx, Gy;          // bounds of |h_x|, |h_y| from the derivative control points
+    int K;                  // control points of one face
+    double zmin_in, zmax_in, Gx_in, Gy_in;  // the same for a freeform entry face (its net follows the exit's)
     int nxe, nye;           // effective detector resolution
     double Rxe, Rye, wx, wy;
     double R0;              // Schlick reflectance at normal incidence
@@ -161,6 +163,8 @@ bool valid_problem(const orc_problem* pr) {
     if (!(pr->R_x > 0) || !(pr->R_y > 0) || !(pr->alpha > 0)) return false;
     if (pr->kind < 0 || pr->kind > 2) return false;
     if (pr->filter != 0 && pr->filter != 1) return false;
+    if (pr->entry_freeform != 0 && pr->entry_freeform != 1) return false;
+    if (pr->entry_freeform && pr->mesh_u) return false;  // the mesh option covers the exit face only
     if (pr->mesh_u < 0 || pr->mesh_v < 0 || pr->mesh_u > 64 || pr->mesh_v > 64 || (pr->mesh_u == 0) != (pr->mesh_v == 0))
         return false;
     if (pr->kind != 0) {
@@ -171,29 +175,38 @@ bool valid_problem(const orc_problem* pr) {
     return true;
 }
 
+// Height range of one face's control net and bounds of |h_x|, |h_y| from its derivative control points:
+// Z_u = sum N_{i,p-1} N_{j,q} p (P_{i+1,j} - P_{i,j}) / (U[i+p+1] - U[i+1]) (likewise in v).
+void face_bounds(const Geo& g, const double* Pz, double* zmin, double* zmax, double* Gx, double* Gy) {
+    *zmin = *zmax = Pz[0];
+    *Gx = *Gy = 0.0;
+    for (int i = 0; i < g.nu * g.nv; ++i) { *zmin = std::min(*zmin, Pz[i]); *zmax = std::max(*zmax, Pz[i]); }
+    for (int i = 0; i + 1 < g.nu; ++i)
+        for (int j = 0; j < g.nv; ++j) {
+            double den = g.U[i + g.p + 1] - g.U[i + 1];
+            double Q = g.p * (Pz[(i + 1) * g.nv + j] - Pz[i * g.nv + j]) / den;
+            *Gx = std::max(*Gx, std::fabs(Q) / (2.0 * g.pr.r_x));
+        }
+    for (int i = 0; i < g.nu; ++i)
+        for (int j = 0; j + 1 < g.nv; ++j) {
+            double den = g.V[j + g.q + 1] - g.V[j + 1];
+            double Q = g.q * (Pz[i * g.nv + j + 1] - Pz[i * g.nv + j]) / den;
+            *Gy = std::max(*Gy, std::fabs(Q) / (2.0 * g.pr.r_y));
+        }
+}
+
 Geo make_geo(const orc_problem* pr, const double* Pz) {
     Geo g;
     g.pr = *pr;
     g.p = pr->p; g.q = pr->q; g.nu = pr->n_u; g.nv = pr->n_v;
     g.U = make_knots(g.p, g.nu);
     g.V = make_knots(g.q, g.nv);
-    g.zmin = Pz ? Pz[0] : 0.0; g.zmax = g.zmin;
-    g.Gx = 0.0; g.Gy = 0.0;
+    g.K = g.nu * g.nv;
+    g.zmin = g.zmax = g.Gx = g.Gy = 0.0;
+    g.zmin_in = g.zmax_in = g.Gx_in = g.Gy_in = 0.0;
     if (Pz) {
-        for (int i = 0; i < g.nu * g.nv; ++i) { g.zmin = std::min(g.zmin, Pz[i]); g.zmax = std::max(g.zmax, Pz[i]); }
-        // Derivative control points: Z_u = sum N_{i,p-1} N_{j,q} p (P_{i+1,j} - P_{i,j}) / (U[i+p+1] - U[i+1]).
-        for (int i = 0; i + 1 < g.nu; ++i)
-            for (int j = 0; j < g.nv; ++j) {
-                double den = g.U[i + g.p + 1] - g.U[i + 1];
-                double Q = g.p * (Pz[(i + 1) * g.nv + j] - Pz[i * g.nv + j]) / den;
-                g.Gx = std::max(g.Gx, std::fabs(Q) / (2.0 * pr->r_x));
-            }
-        for (int i = 0; i < g.nu; ++i)
-            for (int j = 0; j + 1 < g.nv; ++j) {
-                double den = g.V[j + g.q + 1] - g.V[j + 1];
-                double Q = g.q * (Pz[i * g.nv + j + 1] - Pz[i * g.nv + j]) / den;
-                g.Gy = std::max(g.Gy, std::fabs(Q) / (2.0 * pr->r_y));
-            }
+        face_bounds(g, Pz, &g.zmin, &g.zmax, &g.Gx, &g.Gy);
+        if (pr->entry_freeform) face_bounds(g, Pz + g.K, &g.zmin_in, &g.zmax_in, &g.Gx_in, &g.Gy_in);
     }
     double wx = 2.0 * pr->R_x / pr->n_x, wy = 2.0 * pr->R_y / pr->n_y;
     g.wx = wx; g.wy = wy;
@@ -330,19 +343,146 @@ S schlick(const S& c, double R0) {
 // eta = n_i / n_t, c = d . n_hat, k = 1 - eta^2 (1 - c^2); k < 0 is TIR; d_t = eta d + (sqrt(k) - eta c) n_hat.
 // ---------------------------------------------------------------------------------------------------
 
-struct Entry {          // P-independent part of a ray: origin/direction inside the glass and weight
+struct Entry {          // the ray up to the exit face: origin/direction inside the glass and weight
     int status;         // ORC_HIT (continues) or ORC_MISS_ENTRY
     double o[3], d[3], w;
-    bool collimated;
+    bool collimated;    // sampled on the exit face itself (flat entry face): no root search there
     double u, v;        // collimated: the sample on the surface
     double margin;      // distance of the entry point to the aperture edge (point sources)
+    // freeform entry face: the source ray (air) and where it met the entry face
+    bool freeform;
+    double s[3], d0[3]; // point of departure (source, or the collimated sample below the lens) and direction
+    double t_in;        // parameter of the entry hit along s + t d0
+    int su_in, sv_in;   // its knot span product
 };
 
-Entry ray_entry(const Geo& g, int64_t id) {
+// Entry face z = g(x, y) as a second B-spline (its control net follows the exit face's in Pz): the source ray
+// s + t d0 meets it at the smallest t whose point lies over the aperture.  The aperture prism is crossed for
+// t in [t_a, t_b]; the ray must enter it below the face and leave it above, else it passes the lens
+// (ORC_MISS_ENTRY).  Root: bracket by the face's height range, strict monotonicity from its slope bounds, or
+// a scan for the first sign change; bisection, then Newton polish (as for the exit face).
+double f_in_of_t(const Geo& g, const double* Pz_in, const double* s, const double* d0, double t);
+bool find_entry_root(const Geo& g, const double* Pz_in, const double* s, const double* d0, double* t_out,
+                     double* margin) {
+    double t_a = 0.0, t_b = std::numeric_limits<double>::infinity();
+    const double r[2] = {g.pr.r_x, g.pr.r_y};
+    for (int ax = 0; ax < 2; ++ax) {
+        if (d0[ax] == 0.0) {
+            if (std::fabs(s[ax]) > r[ax]) return false;
+            continue;
+        }
+        double ta = (-r[ax] - s[ax]) / d0[ax], tb = (r[ax] - s[ax]) / d0[ax];
+        if (ta > tb) std::swap(ta, tb);
+        t_a = std::max(t_a, ta);
+        t_b = std::min(t_b, tb);
+    }
+    double pad = 1e-9 * (1.0 + std::fabs(g.zmax_in - s[2])) / d0[2];
+    double a = std::max(t_a, (g.zmin_in - s[2]) / d0[2] - pad), b = std::min(t_b, (g.zmax_in - s[2]) / d0[2] + pad);
+    a = std::max(a, 0.0);
+    if (!(a <= b)) { *margin = 0.0; return false; }
+    double fa = f_in_of_t(g, Pz_in, s, d0, a), fb = f_in_of_t(g, Pz_in, s, d0, b);
+    *margin = std::min(std::fabs(fa), std::fabs(fb));
+    if (fa < 0.0 || fb > 0.0) return false;  // entered the prism above the face, or left it below
+    bool monotone = g.Gx_in * std::fabs(d0[0]) + g.Gy_in * std::fabs(d0[1]) < d0[2];
+    if (!monotone) {
+        double du = std::fabs(d0[0]) * (b - a) / (2.0 * g.pr.r_x) * (g.nu - g.p);
+        double dv = std::fabs(d0[1]) * (b - a) / (2.0 * g.pr.r_y) * (g.nv - g.q);
+        int64_t M = std::max<int64_t>(64, int64_t(std::ceil(64.0 * (du + dv))) + 1);
+        double prev = a;
+        for (int64_t k = 1; k <= M; ++k) {
+            double t = a + (b - a) * double(k) / double(M);
+            if (f_in_of_t(g, Pz_in, s, d0, t) <= 0.0) { b = t; a = prev; break; }
+            prev = t;
+        }
+    }
+    for (int it = 0; it < 200 && (b - a) > 1e-11 * (1.0 + b); ++it) {
+        double m = 0.5 * (a + b);
+        if (f_in_of_t(g, Pz_in, s, d0, m) > 0.0) a = m; else b = m;
+    }
+    double t = 0.5 * (a + b);
+    double slack = b - a;
+    for (int it = 0; it < 6; ++it) {
+        Surf<double> sf = surface_at(g, Pz_in, s[0] + t * d0[0], s[1] + t * d0[1], false);
+        double f = sf.h - s[2] - t * d0[2];
+        double fp = sf.hx * d0[0] + sf.hy * d0[1] - d0[2];
+        if (fp == 0.0) break;
+        double tn = t - f / fp;
+        if (!(tn >= a - slack && tn <= b + slack)) break;
+        bool done = std::fabs(tn - t) <= 1e-15 * (1.0 + std::fabs(t));
+        t = tn;
+        if (done) break;
+    }
+    *t_out = t;
+    return true;
+}
+
+double f_in_of_t(const Geo& g, const double* Pz_in, const double* s, const double* d0, double t) {
+    return surface_at(g, Pz_in, s[0] + t * d0[0], s[1] + t * d0[1], false).h - s[2] - t * d0[2];
+}
+
+// Refraction air -> glass at the freeform entry face (normal (-g_x, -g_y, 1)/|.|, pointing into the glass)
+// and the Schlick weight with the air-side cosine d0 . n.
+template <class S>
+void refract_in(const Geo& g, const S* d0, const S& gx, const S& gy, S* d1, S* wfac) {
+    S nn = sqrt(gx * gx + gy * gy + 1.0);
+    S n0 = -gx / nn, n1 = -gy / nn, n2 = 1.0 / nn;
+    double eta = 1.0 / g.pr.n_lens;
+    S c = d0[0] * n0 + d0[1] * n1 + d0[2] * n2;
+    S k = 1.0 - eta * eta * (1.0 - c * c);
+    S beta = sqrt(k) - eta * c;
+    d1[0] = eta * d0[0] + beta * n0;
+    d1[1] = eta * d0[1] + beta * n1;
+    d1[2] = eta * d0[2] + beta * n2;
+    *wfac = g.pr.fresnel ? 1.0 - schlick(c, g.R0) : S(1.0);
+}
+
+Entry ray_entry(const Geo& g, const double* Pz, int64_t id) {
     Entry E;
     E.status = ORC_HIT;
     E.margin = 1e300;
+    E.freeform = false;
+    E.t_in = 0.0;
+    E.su_in = E.sv_in = 0;
     const orc_problem& pr = g.pr;
+    if (pr.entry_freeform) {
+        // both faces freeform: the ray crosses the entry B-spline, then searches the exit face like any ray
+        E.freeform = true;
+        E.collimated = false;
+        const double* Pin = Pz + g.K;
+        if (pr.kind == 0) {
+            sample_collimated(g, id, &E.u, &E.v);
+            E.s[0] = (2.0 * E.u - 1.0) * pr.r_x;
+            E.s[1] = (2.0 * E.v - 1.0) * pr.r_y;
+            E.s[2] = g.zmin_in - 1.0;
+            E.d0[0] = 0.0; E.d0[1] = 0.0; E.d0[2] = 1.0;
+            Surf<double> sf = surface_at(g, Pin, E.s[0], E.s[1], false);
+            E.t_in = sf.h - E.s[2];
+        } else {
+            double theta, a, ex, ey;
+            sample_point(g, id, &theta, &a, &ex, &ey);
+            double cphi = 1.0 - (1.0 - std::cos(pr.half_angle)) * a;
+            double sphi = std::sqrt(std::max(0.0, 1.0 - cphi * cphi));
+            E.s[0] = ex; E.s[1] = ey; E.s[2] = pr.pos_z;
+            E.d0[0] = std::cos(theta) * sphi; E.d0[1] = std::sin(theta) * sphi; E.d0[2] = cphi;
+            double margin;
+            bool ok = find_entry_root(g, Pin, E.s, E.d0, &E.t_in, &margin);
+            E.margin = margin;
+            if (!ok) { E.status = ORC_MISS_ENTRY; return E; }
+        }
+        double p0[3];
+        for (int i = 0; i < 3; ++i) p0[i] = E.s[i] + E.t_in * E.d0[i];
+        if (pr.kind != 0)
+            E.margin = std::min(E.margin, std::min(pr.r_x - std::fabs(p0[0]), pr.r_y - std::fabs(p0[1])));
+        double u = 0.5 * (p0[0] / pr.r_x + 1.0), v = 0.5 * (p0[1] / pr.r_y + 1.0);
+        E.su_in = find_span(g.p, g.nu, u);
+        E.sv_in = find_span(g.q, g.nv, v);
+        Surf<double> sf = surface_at(g, Pin, p0[0], p0[1], false);
+        double wfac;
+        refract_in<double>(g, E.d0, sf.hx, sf.hy, E.d, &wfac);
+        for (int i = 0; i < 3; ++i) E.o[i] = p0[i];
+        E.w = g.w0 * wfac;
+        return E;
+    }
     if (pr.kind == 0) {
         // Collimated bundle: the path to the freeform is parallel to z, rays start on the surface with
         // d = (0,0,1).  They cross the flat face at normal incidence: Schlick weight 1 - R0.
@@ -637,7 +777,7 @@ struct Exit {
 
 // Exit refraction at the freeform, Schlick weight, propagation to the screen.
 template <class S>
-Exit<S> exit_and_screen(const Geo& g, const S* q, const double* d, const S& hx, const S& hy, double w_in,
+Exit<S> exit_and_screen(const Geo& g, const S* q, const S* d, const S& hx, const S& hy, const S& w_in,
                         bool ignore_tir) {
     Exit<S> X;
     X.status = ORC_HIT;
@@ -746,10 +886,10 @@ RayOut trace_value(const Geo& g, const double* Pz, int64_t id, bool force = fals
     R.marginal = false; R.X = R.Y = R.w = 0.0; R.u = R.v = R.t = 0.0; R.su = R.sv = 0; R.k = 1.0;
     R.mh = MeshHit{false, 0.0, 0, 0, 0, 0, 0};
     const bool mesh = g.pr.mesh_u > 0;
-    R.E = ray_entry(g, id);
+    R.E = ray_entry(g, Pz, id);
     Entry& E = R.E;
     if (std::fabs(E.margin) < EPS_APERTURE) R.marginal = true;
-    if (force && E.status == ORC_MISS_ENTRY) {  // continue as if the entry face were large enough
+    if (force && E.status == ORC_MISS_ENTRY && !E.freeform) {  // continue as if the entry face were large enough
         double theta, a, ex, ey;
         sample_point(g, id, &theta, &a, &ex, &ey);
         double cphi = 1.0 - (1.0 - std::cos(g.pr.half_angle)) * a;
@@ -817,7 +957,7 @@ RayOut trace_value(const Geo& g, const double* Pz, int64_t id, bool force = fals
 Exit<Dual> trace_dual(const Geo& g, const double* Pz, const RayOut& R, Dual* Xo, Dual* Yo) {
     const Entry& E = R.E;
     int nt = (g.p + 1) * (g.q + 1);
-    tl_nt = nt;
+    tl_nt = E.freeform ? 2 * nt : nt;
     Dual Pl[MAXT];
     for (int a = 0; a <= g.p; ++a)
         for (int b = 0; b <= g.q; ++b) {
@@ -825,6 +965,43 @@ Exit<Dual> trace_dual(const Geo& g, const double* Pz, const RayOut& R, Dual* Xo,
             Pl[l] = Dual(Pz[(R.su - g.p + a) * g.nv + (R.sv - g.q + b)]);
             Pl[l].d[l] = 1.0;
         }
+    // the ray inside the glass: fixed for a flat entry face; with a freeform entry it moves with the entry
+    // net (tangents nt .. 2 nt - 1): the entry hit differentiated by Newton steps in dual arithmetic from the
+    // converged root (a collimated ray meets the face at a fixed (x, y)), then the refraction and the weight
+    Dual o[3], d[3], w(E.w);
+    for (int i = 0; i < 3; ++i) { o[i] = Dual(E.o[i]); d[i] = Dual(E.d[i]); }
+    if (E.freeform) {
+        Dual Pin[MAXT];
+        for (int a = 0; a <= g.p; ++a)
+            for (int b = 0; b <= g.q; ++b) {
+                int l = a * (g.q + 1) + b;
+                Pin[l] = Dual(Pz[g.K + (E.su_in - g.p + a) * g.nv + (E.sv_in - g.q + b)]);
+                Pin[l].d[nt + l] = 1.0;
+            }
+        Surf<Dual> si;
+        if (g.pr.kind == 0) {
+            Dual u(E.u), v(E.v);
+            si = eval_surface<Dual>(g, Pin, E.su_in, E.sv_in, u, v, false);
+            o[0] = Dual(E.s[0]); o[1] = Dual(E.s[1]); o[2] = si.h;
+        } else {
+            Dual t(E.t_in);
+            for (int it = 0; it < 2; ++it) {
+                Dual x = E.s[0] + t * E.d0[0], y = E.s[1] + t * E.d0[1];
+                Dual u = 0.5 * (x / g.pr.r_x + 1.0), v = 0.5 * (y / g.pr.r_y + 1.0);
+                Surf<Dual> sn = eval_surface<Dual>(g, Pin, E.su_in, E.sv_in, u, v, false);
+                Dual f = sn.h - E.s[2] - t * E.d0[2];
+                Dual fp = sn.hx * E.d0[0] + sn.hy * E.d0[1] - E.d0[2];
+                t = t - f / fp;
+            }
+            for (int i = 0; i < 3; ++i) o[i] = E.s[i] + t * E.d0[i];
+            Dual u = 0.5 * (o[0] / g.pr.r_x + 1.0), v = 0.5 * (o[1] / g.pr.r_y + 1.0);
+            si = eval_surface<Dual>(g, Pin, E.su_in, E.sv_in, u, v, false);
+        }
+        Dual d0[3] = {Dual(E.d0[0]), Dual(E.d0[1]), Dual(E.d0[2])};
+        Dual wfac;
+        refract_in<Dual>(g, d0, si.hx, si.hy, d, &wfac);
+        w = g.w0 * wfac;
+    }
     Dual q[3];
     Surf<Dual> s;
     const bool mesh = g.pr.mesh_u > 0;
@@ -842,23 +1019,31 @@ Exit<Dual> trace_dual(const Geo& g, const double* Pz, const RayOut& R, Dual* Xo,
         // Differentiate the root: two Newton steps in dual arithmetic from the converged root.
         Dual t(R.t);
         for (int it = 0; it < 2; ++it) {
-            Dual x = E.o[0] + t * E.d[0], y = E.o[1] + t * E.d[1];
+            Dual x = o[0] + t * d[0], y = o[1] + t * d[1];
             Dual u = 0.5 * (x / g.pr.r_x + 1.0), v = 0.5 * (y / g.pr.r_y + 1.0);
             Surf<Dual> sn = eval_surface<Dual>(g, Pl, R.su, R.sv, u, v, false);
-            Dual f = sn.h - E.o[2] - t * E.d[2];
-            Dual fp = sn.hx * E.d[0] + sn.hy * E.d[1] - E.d[2];
+            Dual f = sn.h - o[2] - t * d[2];
+            Dual fp = sn.hx * d[0] + sn.hy * d[1] - d[2];
             t = t - f / fp;
         }
-        for (int i = 0; i < 3; ++i) q[i] = E.o[i] + t * E.d[i];
+        for (int i = 0; i < 3; ++i) q[i] = o[i] + t * d[i];
         Dual u = 0.5 * (q[0] / g.pr.r_x + 1.0), v = 0.5 * (q[1] / g.pr.r_y + 1.0);
         s = eval_surface<Dual>(g, Pl, R.su, R.sv, u, v, false);
     }
-    Exit<Dual> X = exit_and_screen<Dual>(g, q, E.d, s.hx, s.hy, E.w, false);
+    Exit<Dual> X = exit_and_screen<Dual>(g, q, d, s.hx, s.hy, w, false);
     *Xo = X.X; *Yo = X.Y;
     return X;
 }
 
+// Control point of tangent l: the exit face's local points first, then (freeform entry) the entry face's,
+// whose net follows the exit net in Pz.
 int64_t cp_index(const Geo& g, const RayOut& R, int l) {
+    const int nt = (g.p + 1) * (g.q + 1);
+    if (l >= nt) {
+        l -= nt;
+        int a = l / (g.q + 1), b = l % (g.q + 1);
+        return g.K + int64_t(R.E.su_in - g.p + a) * g.nv + (R.E.sv_in - g.q + b);
+    }
     int a = l / (g.q + 1), b = l % (g.q + 1);
     return int64_t(R.su - g.p + a) * g.nv + (R.sv - g.q + b);
 }
@@ -1086,7 +1271,7 @@ static int grad_impl(const orc_problem* pr, const double* Pz, const double* targ
     if (loss) *loss = L;
     if (irr_out) std::copy(irr.begin(), irr.end(), irr_out);
     if (dLdI_out) std::copy(G.begin(), G.end(), dLdI_out);
-    int64_t K = int64_t(g.nu) * g.nv;
+    int64_t K = int64_t(g.K) * (g.pr.entry_freeform ? 2 : 1);
     int T = nthreads(threads, g.nrays);
     std::vector<std::vector<double>> gr(T, std::vector<double>(K, 0.0));
     std::vector<std::vector<double>> gi(T, std::vector<double>(K, 0.0));
@@ -1099,8 +1284,7 @@ static int grad_impl(const orc_problem* pr, const double* Pz, const double* targ
         splat<Dual>(g, X, Y, E.w, [&](int64_t pix, const Dual& v) { acc = acc + v * G[pix]; });
         bool ill = dL_dP_ill && std::fabs(R.k) < k_min;
         double* dst = ill ? gi[t].data() : gr[t].data();
-        int nt = (g.p + 1) * (g.q + 1);
-        for (int l = 0; l < nt; ++l) dst[cp_index(g, R, l)] += acc.d[l];
+        for (int l = 0; l < tl_nt; ++l) dst[cp_index(g, R, l)] += acc.d[l];
         tl_nt = 0;
     });
     for (int64_t k = 0; k < K; ++k) {
@@ -1133,11 +1317,10 @@ int orc_jvp(const orc_problem* pr, const double* Pz, const double* vdir, double*
         if (R.status != ORC_HIT) return;
         Dual X, Y;
         Exit<Dual> E = trace_dual(g, Pz, R, &X, &Y);
-        int nt = (g.p + 1) * (g.q + 1);
         double* A = acc[t].data();
         splat<Dual>(g, X, Y, E.w, [&](int64_t pix, const Dual& v) {
             double s = 0.0;
-            for (int l = 0; l < nt; ++l) s += v.d[l] * vdir[cp_index(g, R, l)];
+            for (int l = 0; l < tl_nt; ++l) s += v.d[l] * vdir[cp_index(g, R, l)];
             A[pix] += s;
         });
         tl_nt = 0;

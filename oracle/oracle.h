@@ -50,6 +50,8 @@ typedef struct {
     int32_t mesh_u, mesh_v;          /* 0: exact intersection; >= 1: the triangle mesh of sec. 2.2.2 with
                                         mesh_u x mesh_v rectangles per knot span product */
     int32_t filter;                  /* 0: Gaussian reconstruction filter, 1: box (indicator of the pixel) */
+    int32_t entry_freeform;          /* 1: the entry face is a second B-spline (net after the exit's in Pz) */
+    int32_t pad2_;
 } orc_problem;
 
 typedef struct {

@@ -28,6 +28,7 @@ class Lens:
     q: int = 3
     n_u: int = 8
     n_v: int = 8
+    entry_freeform: int = 0   # 1: the entry face is a second B-spline; its net follows the exit net in Pz
 
 
 @dataclass
@@ -87,8 +88,10 @@ class Problem:
             return d.n_x + d.nu_x - 1, d.n_y + d.nu_y - 1
         return d.n_x, d.n_y
 
-    def cp_shape(self) -> Tuple[int, int]:
-        return self.lens.n_u, self.lens.n_v
+    def cp_shape(self) -> Tuple[int, ...]:
+        """Shape of the design's control heights: the exit net, or (exit, entry) with a freeform entry."""
+        L = self.lens
+        return (2, L.n_u, L.n_v) if L.entry_freeform else (L.n_u, L.n_v)
 
 
 @dataclass

@@ -860,3 +860,73 @@ def test_box_gradient_is_the_fresnel_part_only():
            np.floor((base[ok, 2] + D.R_y) / (2 * D.R_y / D.n_y)).astype(int))
     fd = np.sum(G.ravel()[pix] * (Rp[ok, 3] - Rm[ok, 3]) / (2 * h))
     assert abs(fd - g[k]) <= 1e-6 * max(abs(fd), 1e-12) + 1e-12, (fd, g[k])
+
+
+# ------------------------------------------------------------------------------------------------
+# Both faces freeform (sec. 3.3 and the conclusion propose optimising the entry face too): the entry net
+# follows the exit net in Pz
+# ------------------------------------------------------------------------------------------------
+def _two_faces(p):
+    return replace(p, lens=replace(p.lens, entry_freeform=1))
+
+
+@pytest.mark.parametrize("kind", ["collimated", "point"])
+def test_flat_entry_net_reduces_to_the_plano_freeform_lens(kind):
+    """An entry net with every height at z_in is the flat entry face: every ray is traced as by the
+    plano-freeform lens, to rounding."""
+    if kind == "collimated":
+        p = W.collimated_problem(32, 8, 32, jitter=1, seed=41)
+    else:
+        p = W.point_problem(24, 8, 32, seed=41, half_angle_deg=35.0)
+    Pz = W.random_heights(8, 8, 41)
+    P2 = np.stack([Pz, np.full_like(Pz, p.lens.z_in)])
+    ids = np.arange(O.num_rays(p))
+    a = O.trace_rays(p, Pz, ids)
+    b = O.trace_rays(_two_faces(p), P2, ids)
+    np.testing.assert_array_equal(a[:, 0], b[:, 0])
+    hit = a[:, 0] == O.HIT
+    np.testing.assert_allclose(b[hit, 1:6], a[hit, 1:6], rtol=0, atol=1e-9)
+
+
+def test_parallel_plate_keeps_every_direction():
+    """Two parallel tilted planes make a plate: a ray leaves it in its incoming direction (textbook), so the
+    segment from the exit point to the landing point is parallel to the source direction."""
+    p = _two_faces(W.point_problem(16, 6, 32, seed=42, half_angle_deg=30.0, R=60.0, z=80.0))
+    x, y = O.control_xy(p)
+    entry = 0.5 + 0.04 * x - 0.03 * y
+    P2 = np.stack([entry + 2.0, entry])
+    ids = np.arange(O.num_rays(p))
+    R = O.trace_rays(p, P2, ids)
+    S = O.samples(p, ids)
+    hit = R[:, 0] == O.HIT
+    assert hit.sum() > 100
+    ca = 1.0 - (1.0 - np.cos(p.source.half_angle)) * S[hit, 1]
+    sa = np.sqrt(1.0 - ca ** 2)
+    d0 = np.stack([np.cos(S[hit, 0]) * sa, np.sin(S[hit, 0]) * sa, ca], 1)
+    L = p.lens
+    qx, qy = (2 * R[hit, 4] - 1) * L.r_x, (2 * R[hit, 5] - 1) * L.r_y
+    qz = np.array([O.surface(p, P2[0], a, b)[0] for a, b in zip(qx, qy)])
+    seg = np.stack([R[hit, 1] - qx, R[hit, 2] - qy, p.detector.z_screen - qz], 1)
+    seg /= np.linalg.norm(seg, axis=1, keepdims=True)
+    np.testing.assert_allclose(seg, d0, rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("kind", ["collimated", "point"])
+def test_two_face_gradient_matches_central_fd(kind):
+    """dL/dP over both nets (exit then entry) against central differences of the loss."""
+    if kind == "collimated":
+        p = _two_faces(W.collimated_problem(48, 6, 16, jitter=1, seed=43, R=8.0, z=30.0))
+    else:
+        p = _two_faces(W.point_problem(40, 6, 16, seed=43, R=12.0, z=25.0, half_angle_deg=25.0))
+    g0 = W.rng(43, 5)
+    P2 = np.stack([W.random_heights(6, 6, 43, spread=0.15) + 1.0, 0.2 + g0.uniform(-0.1, 0.1, (6, 6))])
+    T = W.rng(43, 3).uniform(0.5, 1.0, p.image_shape())
+    L0, g, _, _ = O.grad(p, P2, T)
+    assert g.shape == P2.shape and np.abs(g[1]).max() > 0
+    h = 1e-6
+    for k in [(0, 1, 2), (0, 3, 3), (1, 2, 2), (1, 3, 4), (1, 4, 1)]:
+        E = np.zeros_like(P2)
+        E[k] = h
+        Lp = O.loss(O.forward(p, P2 + E)[0], T)[0]
+        Lm = O.loss(O.forward(p, P2 - E)[0], T)[0]
+        assert abs((Lp - Lm) / (2 * h) - g[k]) <= 2e-5 * np.abs(g).max(), (k, (Lp - Lm) / (2 * h), g[k])
