@@ -42,6 +42,10 @@ FLOPS = {
 # barycentric basis weights (~64) and re-walks the cells.  A collimated ray visits exactly one cell.
 MESH_CELL_FLOPS = 390
 MESH_ADJ_EXTRA = 64
+# Freeform entry face: the entry root search (bracket, ~2 Newton steps of a surface value and slope), the entry
+# normal and refraction; every ray then searches the exit face like a point-source ray.  The adjoint adds the
+# entry reverse (second derivatives at the entry hit, the entry refraction, the entry root).
+ENTRY_FLOPS = {"forward": 600, "adjoint": 900}
 # Algorithmic HBM bytes of the generator per design with K control points and n parameters (fp32): the
 # forward reads the two weight matrices (dense 2 K^2, sparse 2 C K floats; vectors of K are negligible); the
 # back-propagation reads them again; the gradient + Adam pass reads and writes parameters and both moments
@@ -97,6 +101,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "tophat", "tophat64"])
     ap.add_argument("--generator", default="none", choices=["none", "dense", "sparse"])
+    ap.add_argument("--entry-freeform", action="store_true",
+                    help="make the entry face a second freeform B-spline (both nets optimised)")
     ap.add_argument("--mesh", type=int, default=0,
                     help="trace the triangle mesh of sec. 2.2.2 with this many rectangles per knot span and axis")
     ap.add_argument("--no-fd", action="store_true")
@@ -138,6 +144,8 @@ def main():
         wl = W.WORKLOADS[args.workload]()
     if args.mesh:
         wl = W.with_mesh(wl, args.mesh)
+    if args.entry_freeform:
+        wl = W.with_entry_freeform(wl)
     plan = ffrt.Plan(wl.problems)
     T = plan.pack_img(wl.targets)
     arch = {"none": None, "dense": ffrt.MLP_DENSE, "sparse": ffrt.MLP_SPARSE}[args.generator]
@@ -201,11 +209,14 @@ def main():
 
     # ---- roofline of the dominant trace kernel
     iters = 0.0
-    n_point = sum(p.num_rays() for p in wl.problems if p.source.kind != 0)
+    def searched(p):  # rays of this design search the exit face for its root
+        return p.source.kind != 0 or p.lens.entry_freeform
+
+    n_point = sum(p.num_rays() for p in wl.problems if searched(p))
     if n_point:
         # Newton iterations are not counted on the device: use the mean the per-ray inspection reports for
         # the first point-source design
-        d0 = next(i for i, p in enumerate(wl.problems) if p.source.kind != 0)
+        d0 = next(i for i, p in enumerate(wl.problems) if searched(p))
         ids = np.linspace(0, wl.problems[d0].num_rays() - 1, 4096).astype(np.int64)
         pz0 = st["Pz"][plan.cp_offsets[d0]:plan.cp_offsets[d0 + 1]].contiguous()
         sub = ffrt.Plan([wl.problems[d0]])
@@ -215,8 +226,10 @@ def main():
     def flops(kernel):
         tot = 0.0
         for p in wl.problems:
-            k = "collimated" if p.source.kind == 0 else "point"
-            if p.options.mesh_u:
+            k = "collimated" if p.source.kind == 0 and not p.lens.entry_freeform else "point"
+            if p.lens.entry_freeform:
+                f = FLOPS["point"][kernel] + FLOPS["point"]["newton_iter"] * iters + ENTRY_FLOPS[kernel]
+            elif p.options.mesh_u:
                 cells = 1.0 if k == "collimated" else iters
                 f = FLOPS[k][kernel] + MESH_CELL_FLOPS * (cells + (kernel == "adjoint"))
                 f += MESH_ADJ_EXTRA if kernel == "adjoint" else 0
@@ -266,6 +279,7 @@ def main():
            "data": "synthetic",
            "config": {"workload": wl.name, "designs": len(wl.problems), "rays_per_step": rays,
                       "intersection": f"triangle mesh {args.mesh}x{args.mesh} per span" if args.mesh else "exact root",
+                      "entry_face": "freeform" if args.entry_freeform else "flat",
                       "sources": sorted(kinds), "graph": f"{args.steps} captured steps",
                       "kernel_shapes": {"forward": cfg[0], "adjoint": cfg[1]}},
            "adam_steps_per_s": 1e3 / ms_step, "wall_s_timed": t_wall,

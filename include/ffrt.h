@@ -51,10 +51,19 @@ typedef enum {
 
 /* Lens (sec. 2.1 - 2.1.2).  n_u = n_1 + 1 and n_v = n_2 + 1 control points, degrees p, q.  The aperture is
  * [-r_x, r_x] x [-r_y, r_y]; the flat entry face is z = z_in; delta_min is the minimal thickness used by
- * the constraint count (P^z >= z_in + delta_min). */
+ * the constraint count (P^z >= z_in + delta_min).
+ * entry_freeform = 1 makes the entry face a second B-spline height field on the same knots (the paper's
+ * proposal for extended sources, sec. 3.3 and the conclusion): the design's control heights are then
+ * 2 n_u n_v floats, the exit net followed by the entry net, and both are optimised.  Point-source rays meet
+ * the entry face at its smallest root over the aperture (else they miss the lens), collimated rays at their
+ * sampled (x, y); both faces refract with Schlick weights; the thickness check becomes
+ * P_exit - P_entry >= delta_min per control point.  At most 2048 control points per face; not combined
+ * with the triangle mesh; the sparse generator does not apply. */
 typedef struct {
     double n_lens, r_x, r_y, z_in, delta_min;
     int32_t p, q, n_u, n_v;
+    int32_t entry_freeform;  /* 0 or 1 */
+    int32_t reserved;        /* 0 */
 } ffrt_lens;
 
 /* Source (sec. 2.2.1, sec. 3.3).

@@ -46,10 +46,13 @@ __device__ void reduce_slots(int d, const DesignDev& D, const float* Pz, ffrt_st
     __shared__ uint32_t s_chk[16][2];
     uint32_t nbad = 0, nnan = 0;
     const float* P = Pz + D.cp_off;
-    for (int i = threadIdx.x; i < D.n_u * D.n_v; i += blockDim.x) {
+    const int K = D.n_u * D.n_v;
+    for (int i = threadIdx.x; i < D.ncp; i += blockDim.x) {
         const float z = P[i];
         nnan += isfinite(z) ? 0u : 1u;
-        nbad += (z >= D.zmin_allowed) ? 0u : 1u;
+        // sec. 2.1.2: above the flat entry face by delta_min; with a freeform entry face, at least delta_min
+        // between the two nets at every control point (then everywhere, by the convex hull property)
+        if (i < K) nbad += (D.entry_ff ? z - P[K + i] >= D.delta_min : z >= D.zmin_allowed) ? 0u : 1u;
     }
     nbad = wave_sum(nbad);
     nnan = wave_sum(nnan);
@@ -84,9 +87,48 @@ __device__ inline double block_sum_f64(double v, double* sh) {
 // Bounds of sec. 2.2.2 for design blockIdx.x: the global convex-hull box [min P^z, max P^z], zref at its
 // middle, and slope bounds from the derivative control points p (P_{i+1,j} - P_{i,j}) / (u_{i+p+1} - u_{i+1})
 // (the textbook derivative of a B-spline; knot units, so d(ubar)/dx = sxu converts them to mm).
+__device__ void face_bounds(const DesignDev& D, const float* P, int p, int q, float* s_b, float& zmin, float& zmax,
+                            float& gx, float& gy) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float lo = INFINITY, hi = -INFINITY, gu = 0.0f, gv = 0.0f;
+    for (int i = wave; i < D.n_u; i += 4) {  // row i by wave, columns by lane
+        const float fu = (float)p / (float)(min(i + 1, D.nsu) - max(i + 1 - p, 0));
+        for (int j = lane; j < D.n_v; j += 64) {
+            const int idx = i * D.n_v + j;
+            const float z = P[idx];
+            lo = fminf(lo, z);
+            hi = fmaxf(hi, z);
+            if (i + 1 < D.n_u) gu = fmaxf(gu, fabsf(fu * (P[idx + D.n_v] - z)));
+            if (j + 1 < D.n_v) {
+                const float fv = (float)q / (float)(min(j + 1, D.nsv) - max(j + 1 - q, 0));
+                gv = fmaxf(gv, fabsf(fv * (P[idx + 1] - z)));
+            }
+        }
+    }
+    auto fmin_ = [](float a, float b) { return fminf(a, b); };
+    auto fmax_ = [](float a, float b) { return fmaxf(a, b); };
+    lo = wave_reduce(lo, fmin_);
+    hi = wave_reduce(hi, fmax_);
+    gu = wave_reduce(gu, fmax_);
+    gv = wave_reduce(gv, fmax_);
+    __syncthreads();
+    if (lane == 0) {
+        s_b[wave * 4 + 0] = lo;
+        s_b[wave * 4 + 1] = hi;
+        s_b[wave * 4 + 2] = gu;
+        s_b[wave * 4 + 3] = gv;
+    }
+    __syncthreads();
+    zmin = fminf(fminf(s_b[0], s_b[4]), fminf(s_b[8], s_b[12]));
+    zmax = fmaxf(fmaxf(s_b[1], s_b[5]), fmaxf(s_b[9], s_b[13]));
+    // a small relative margin keeps the slope bounds conservative under rounding
+    gx = fmaxf(fmaxf(s_b[2], s_b[6]), fmaxf(s_b[10], s_b[14])) * D.sxu * 1.0001f;
+    gy = fmaxf(fmaxf(s_b[3], s_b[7]), fmaxf(s_b[11], s_b[15])) * D.syv * 1.0001f;
+}
+
 __global__ __launch_bounds__(256) void k_bounds(const DesignDev* designs, const float* __restrict__ Pz, int p, int q,
                                                 BoundsDev* bounds, SpanBounds* span_bounds) {
-    __shared__ float s_b[4][4];
+    __shared__ float s_b[16];
     const int d = blockIdx.x;
     const DesignDev& D = designs[d];
     const float* P = Pz + D.cp_off;
@@ -118,45 +160,15 @@ __global__ __launch_bounds__(256) void k_bounds(const DesignDev* designs, const 
         r.gy = gv * D.syv * 1.0001f;
         sb[s] = r;
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    float lo = INFINITY, hi = -INFINITY, gu = 0.0f, gv = 0.0f;
-    for (int i = wave; i < D.n_u; i += 4) {  // row i by wave, columns by lane
-        const float fu = (float)p / (float)(min(i + 1, D.nsu) - max(i + 1 - p, 0));
-        for (int j = lane; j < D.n_v; j += 64) {
-            const int idx = i * D.n_v + j;
-            const float z = P[idx];
-            lo = fminf(lo, z);
-            hi = fmaxf(hi, z);
-            if (i + 1 < D.n_u) gu = fmaxf(gu, fabsf(fu * (P[idx + D.n_v] - z)));
-            if (j + 1 < D.n_v) {
-                const float fv = (float)q / (float)(min(j + 1, D.nsv) - max(j + 1 - q, 0));
-                gv = fmaxf(gv, fabsf(fv * (P[idx + 1] - z)));
-            }
-        }
+    BoundsDev B;
+    face_bounds(D, P, p, q, s_b, B.zmin, B.zmax, B.gx, B.gy);
+    B.zref = 0.5f * (B.zmin + B.zmax);
+    B.zmin_in = B.zmax_in = B.gx_in = B.gy_in = B.zref_in = 0.0f;
+    if (D.entry_ff) {  // the entry net follows the exit net
+        face_bounds(D, P + D.n_u * D.n_v, p, q, s_b, B.zmin_in, B.zmax_in, B.gx_in, B.gy_in);
+        B.zref_in = 0.5f * (B.zmin_in + B.zmax_in);
     }
-    auto fmin_ = [](float a, float b) { return fminf(a, b); };
-    auto fmax_ = [](float a, float b) { return fmaxf(a, b); };
-    lo = wave_reduce(lo, fmin_);
-    hi = wave_reduce(hi, fmax_);
-    gu = wave_reduce(gu, fmax_);
-    gv = wave_reduce(gv, fmax_);
-    if (lane == 0) {
-        s_b[wave][0] = lo;
-        s_b[wave][1] = hi;
-        s_b[wave][2] = gu;
-        s_b[wave][3] = gv;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        BoundsDev B;
-        B.zmin = fminf(fminf(s_b[0][0], s_b[1][0]), fminf(s_b[2][0], s_b[3][0]));
-        B.zmax = fmaxf(fmaxf(s_b[0][1], s_b[1][1]), fmaxf(s_b[2][1], s_b[3][1]));
-        B.zref = 0.5f * (B.zmin + B.zmax);
-        // a small relative margin keeps the slope bounds conservative under rounding
-        B.gx = fmaxf(fmaxf(s_b[0][2], s_b[1][2]), fmaxf(s_b[2][2], s_b[3][2])) * D.sxu * 1.0001f;
-        B.gy = fmaxf(fmaxf(s_b[0][3], s_b[1][3]), fmaxf(s_b[2][3], s_b[3][3])) * D.syv * 1.0001f;
-        bounds[d] = B;
-    }
+    if (threadIdx.x == 0) bounds[d] = B;
 }
 
 // Slice [lo, hi) of the image of design D handled by workgroup b of LB.
@@ -259,7 +271,7 @@ __global__ __launch_bounds__(256) void k_finish(const DesignDev* designs, float*
         out[i] = g;
         return g;
     };
-    const int ncp = D.n_u * D.n_v;
+    const int ncp = D.ncp;
     const bool step = adam.Pz && (!valid || valid[d]);
     if (step && adam.theta) {
         // range reparametrisation (sec. 2.4.1): Adam on theta, then P from the new theta
@@ -327,7 +339,7 @@ __global__ __launch_bounds__(256) void k_adam(const DesignDev* designs, float* P
     if (valid && !valid[d]) return;
     const DesignDev& D = designs[d];
     const float* gd = g + D.cp_off;
-    adam_update(Pz, m, v, t + d, D.cp_off, D.n_u * D.n_v, hp, [gd](int i) { return gd[i]; });
+    adam_update(Pz, m, v, t + d, D.cp_off, D.ncp, hp, [gd](int i) { return gd[i]; });
 }
 
 __global__ void k_rng(uint64_t state0, uint64_t first, int64_t n, uint64_t* out) {

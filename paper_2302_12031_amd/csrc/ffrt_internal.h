@@ -11,7 +11,7 @@ constexpr int WG = 256;               // threads per workgroup: 4 wave64s
 constexpr int TILE_CAP = 6144;        // 32-bit fixed-point pixels in the LDS irradiance tile of the forward kernel
 constexpr int MAX_DEG = 5;
 constexpr int N_SHAPES = 5;           // block shapes: rays per thread 1, 2, 4, 8, 16
-constexpr int N_KG = 4;               // kernel groups: bit 0 point source, bit 1 triangle mesh
+constexpr int N_KG = 8;               // kernel groups: bit 0 point source, bit 1 mesh, bit 2 freeform entry
 constexpr int RPT_OF_SHAPE[N_SHAPES] = {1, 2, 4, 8, 16};
 constexpr int NSLOT = 64;             // per-design partial-statistics slots (spreads the counter atomics)
 
@@ -58,16 +58,24 @@ struct DesignDev {
     int32_t mesh_u, mesh_v;          // triangle mesh of sec. 2.2.2: rectangles per knot span (0: exact root)
     int32_t box;                     // box reconstruction (sec. 2.3) instead of the Gaussian filter
     float inv_mesh_u, inv_mesh_v;
+    // freeform entry face: its control net follows the exit net (ncp = 2 n_u n_v heights per design); the
+    // lens must stay at least delta_min thick between control points of equal index
+    int32_t entry_ff, ncp;
+    float delta_min;
 };
 
 // Kernel group of a design: the trace kernels are instantiated per source kind and intersection mode.
-inline int kind_group(const DesignDev& d) { return (d.mesh_u ? 2 : 0) + (d.kind != 0 ? 1 : 0); }
+inline int kind_group(const DesignDev& d) {
+    return (d.entry_ff ? 4 : 0) + (d.mesh_u ? 2 : 0) + (d.kind != 0 ? 1 : 0);
+}
 
 // Per-design bounds of sec. 2.2.2 (global convex-hull box and slope bounds), formed by launch_bounds before
 // the trace kernels of designs whose rays need the root search (point and grid sources).
 struct BoundsDev {
     float zmin, zmax, gx, gy;        // gx, gy: bounds of |dh/dx|, |dh/dy| from derivative control points
     float zref;                      // reference height subtracted from P^z in LDS
+    // the same for a freeform entry face (zero otherwise)
+    float zmin_in, zmax_in, gx_in, gy_in, zref_in;
 };
 
 // The same bounds for one knot-span product (su, sv) of a design, record su * nsv + sv: the surface over

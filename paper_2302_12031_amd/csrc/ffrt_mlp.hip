@@ -2,7 +2,8 @@
 // layers of the size K = n_u n_v of the control net, followed by the output correction of sec. 2.4.1 (eq. of
 // the output correction; the offset function folded into lo):
 //   h1 = tanh(w1 + b1),  h2 = tanh(W2 h1 + b2),  y = tanh(W3 h2 + b3),  P = lo + (y + 1) span / 2.
-// Activations of a design, packed at 3 cp_off: h1, h2, y (K each).
+// Activations of a design, packed at 3 cp_off: h1, h2, y (K each).  K counts all of a design's heights (both
+// nets of a lens with a freeform entry face) for the dense architecture.
 //
 // Dense architecture: W2, W3 fully connected.  Parameters of a design, packed: w1 (K), b1 (K), W2 (K x K, row
 // i = inputs of neuron i), b2 (K), W3 (K x K), b3 (K).  The two K x K layers are matrix-vector products,
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(256) void k_mlp_layer1(const DesignDev* designs, co
                                                     const int32_t* valid) {
     const int d = blockIdx.y;
     const DesignDev& D = designs[d];
-    const int K = D.n_u * D.n_v;
+    const int K = D.ncp;
     const float* w1 = par + poff[d];
     const float* b1 = w1 + K;
     float* h1 = acts + 3 * D.cp_off;
@@ -105,7 +106,7 @@ __global__ __launch_bounds__(256) void k_mlp_gemv(const DesignDev* designs, cons
     extern __shared__ float sx[];
     const int d = blockIdx.y;
     const DesignDev& D = designs[d];
-    const int K = D.n_u * D.n_v;
+    const int K = D.ncp;
     if ((int)blockIdx.x * 4 >= K) return;
     const float* base = par + poff[d];
     const float* W = base + 2 * K + (layer == 3 ? (int64_t)K * K + K : 0);
@@ -157,7 +158,7 @@ __global__ __launch_bounds__(256) void k_mlp_gemv_t(const DesignDev* designs, co
     __shared__ float sdz[GT_ROWS];
     const int d = blockIdx.z;
     const DesignDev& D = designs[d];
-    const int K = D.n_u * D.n_v;
+    const int K = D.ncp;
     const int r0 = blockIdx.y * GT_ROWS;
     if (r0 >= K) return;
     const float* W = par + poff[d] + 2 * K + (layer == 3 ? (int64_t)K * K + K : 0);
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(256) void k_mlp_grad_adam(const DesignDev* designs,
                                                        ffrt_adam_hparams hp) {
     const int d = blockIdx.y;
     const DesignDev& D = designs[d];
-    const int K = D.n_u * D.n_v;
+    const int K = D.ncp;
     const int nrb = (K + MR - 1) / MR;
     if ((int)blockIdx.x > nrb) return;
     const bool upd = adam && (!valid || valid[d]);
@@ -246,7 +247,7 @@ __global__ void k_mlp_seed(const DesignDev* designs, const float* dLdP, const fl
                            float* dz3, float* dh2, float* dh1) {
     const int d = blockIdx.y;
     const DesignDev& D = designs[d];
-    const int K = D.n_u * D.n_v;
+    const int K = D.ncp;
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= K) return;
     const int64_t c = D.cp_off + k;

@@ -117,6 +117,10 @@ ffrt_status validate(const ffrt_problem& pr, int idx) {
     if (L.n_u <= L.p || L.n_v <= L.q) return bad("need more control points than the degree");
     if ((int64_t)L.n_u * L.n_v > 4096 || L.n_u - L.p > 64 || L.n_v - L.q > 64)
         return bad("control net larger than 64 x 64");
+    if (L.entry_freeform != 0 && L.entry_freeform != 1) return bad("entry_freeform must be 0 or 1");
+    if (L.entry_freeform && (int64_t)L.n_u * L.n_v > 2048)
+        return bad("a lens with two freeform faces allows at most 2048 control points per face");
+    if (L.entry_freeform && pr.opt.mesh_u) return bad("the triangle mesh applies to a flat entry face only");
     if (!(L.n_lens > 1.0) || !std::isfinite(L.n_lens)) return bad("n_lens must be > 1");
     if (!(L.r_x > 0) || !(L.r_y > 0)) return bad("aperture half widths must be > 0");
     if (!(L.delta_min >= 0)) return bad("delta_min must be >= 0");
@@ -184,6 +188,9 @@ DesignDev make_design(const ffrt_problem& pr, int64_t cp_off, int64_t img_off, i
     d.ubar0 = 0.5f * (float)d.nsu;
     d.vbar0 = 0.5f * (float)d.nsv;
     d.zmin_allowed = (float)(L.z_in + L.delta_min);
+    d.entry_ff = L.entry_freeform;
+    d.ncp = L.n_u * L.n_v * (L.entry_freeform ? 2 : 1);
+    d.delta_min = (float)L.delta_min;
     d.kind = S.kind;
     d.grid_u = S.grid_u;
     d.grid_v = S.grid_v;
@@ -259,7 +266,8 @@ TraceArgs make_args(ffrt_plan* pl, int shape, int kg) {
     A.lds_kt = (pl->max_kt + 3) / 4 * 4;
     // point sources stage the span bounds too, when the kernels' LDS then stays within 64 KiB
     const int sb = 4 * pl->max_spans;
-    if (kg == 1 && 4 * (A.lds_cp + A.lds_kt + sb + std::max(TILE_CAP, A.lds_cp)) <= 65536) A.lds_sb = sb;
+    const bool search = kg == 1 || kg >= 4;  // exact exit root search (point sources, freeform entry faces)
+    if (search && 4 * (A.lds_cp + A.lds_kt + sb + std::max(TILE_CAP, A.lds_cp)) <= 65536) A.lds_sb = sb;
     return A;
 }
 
@@ -460,12 +468,12 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
         pl->dd.push_back(d);
         pl->cp_off.push_back(cp);
         pl->img_off.push_back(img);
-        cp += (int64_t)d.n_u * d.n_v;
+        cp += (int64_t)d.ncp;
         img += (int64_t)d.nx * d.ny;
         pl->total_rays += d.n_rays;
-        pl->max_cp = std::max(pl->max_cp, d.n_u * d.n_v);
+        pl->max_cp = std::max(pl->max_cp, d.ncp);
         pl->max_img = std::max<int64_t>(pl->max_img, (int64_t)d.nx * d.ny);
-        if (d.kind != 0) pl->has_point = true;
+        if (d.kind != 0 || d.entry_ff) pl->has_point = true;
         pl->max_kt = std::max(pl->max_kt, d.nsu * kt_stride(pl->P) + d.nsv * kt_stride(pl->Q));
     }
     pl->cp_off.push_back(cp);
@@ -473,11 +481,13 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
     pl->total_cp = cp;
     int64_t mo[2] = {0, 0};
     for (const DesignDev& d : pl->dd) {
-        const int64_t K = (int64_t)d.n_u * d.n_v;
+        // the dense generator outputs all of a design's heights (both nets of a freeform entry); the sparse one
+        // is defined on one control net
+        const int64_t K = d.ncp, K1 = (int64_t)d.n_u * d.n_v;
         const int64_t C = (int64_t)(2 * (d.n_u - d.nsu) + 1) * (2 * (d.n_v - d.nsv) + 1);
         for (int a = 0; a < 2; ++a) pl->mlp_off[a].push_back(mo[a]);
         mo[FFRT_MLP_DENSE] += 2 * K * K + 4 * K;
-        mo[FFRT_MLP_SPARSE] += 2 * C * K + 4 * K;
+        mo[FFRT_MLP_SPARSE] += 2 * C * K1 + 4 * K1;
     }
     for (int a = 0; a < 2; ++a) pl->mlp_off[a].push_back(mo[a]);
     pl->total_img = img;
@@ -696,6 +706,9 @@ static constexpr int MLP_MAX_K[2] = {16384, 6144};
 static ffrt_status mlp_check(ffrt_plan* plan, int32_t arch) {
     if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
     if (arch != FFRT_MLP_DENSE && arch != FFRT_MLP_SPARSE) return fail(FFRT_E_ARG, "unknown generator architecture");
+    if (arch == FFRT_MLP_SPARSE)
+        for (const DesignDev& d : plan->dd)
+            if (d.entry_ff) return fail(FFRT_E_ARG, "sparse generator: defined for one control net per design");
     if (plan->max_cp > MLP_MAX_K[arch])
         return fail(FFRT_E_ARG, arch == FFRT_MLP_DENSE ? "dense generator: a control net exceeds 16384 points"
                                                        : "sparse generator: a control net exceeds 6144 points");
@@ -782,12 +795,15 @@ ffrt_status ffrt_plan_control_xy(const ffrt_plan* plan, double* x, double* y) {
             }
             return acc / p;
         };
-        const int64_t off = plan->cp_off[d];
-        for (int i = 0; i < L.n_u; ++i)
-            for (int j = 0; j < L.n_v; ++j) {
-                x[off + (int64_t)i * L.n_v + j] = (2.0 * greville(L.p, L.n_u, i) - 1.0) * L.r_x;
-                y[off + (int64_t)i * L.n_v + j] = (2.0 * greville(L.q, L.n_v, j) - 1.0) * L.r_y;
-            }
+        const int64_t K = (int64_t)L.n_u * L.n_v;
+        for (int face = 0; face <= L.entry_freeform; ++face) {  // a freeform entry net repeats the positions
+            const int64_t off = plan->cp_off[d] + face * K;
+            for (int i = 0; i < L.n_u; ++i)
+                for (int j = 0; j < L.n_v; ++j) {
+                    x[off + (int64_t)i * L.n_v + j] = (2.0 * greville(L.p, L.n_u, i) - 1.0) * L.r_x;
+                    y[off + (int64_t)i * L.n_v + j] = (2.0 * greville(L.q, L.n_v, j) - 1.0) * L.r_y;
+                }
+        }
     }
     return FFRT_OK;
 }

@@ -415,6 +415,159 @@ __device__ RootOut intersect(const DesignDev& D, const BoundsDev& B, const float
 }
 
 // ------------------------------------------------------------------------------------------------
+// Freeform entry face (both faces freeform): the entry face is a second B-spline whose net follows the exit
+// net; its LDS copy holds heights relative to zref_in.  A point-source ray meets it at the smallest root over
+// the aperture prism (it must enter the prism below the face and leave it above, else it passes the lens:
+// ST_MISS_ENTRY), found like the exit root: bracket from the face's height range, monotonicity from its slope
+// bounds or a scan, safeguarded Newton.  A collimated ray meets it at its sampled (x, y).  The ray refracts
+// into the glass with the vector Snell law at n_hat = (-g_x, -g_y, 1)/|.| and takes the Schlick weight with
+// the air-side cosine d0 . n_hat.
+// ------------------------------------------------------------------------------------------------
+struct EntryHit {
+    float sx, sy, sz, d0x, d0y, d0z;  // source ray in air
+    float t;                          // its parameter at the entry hit
+};
+
+template <int P, int Q, bool POINT>
+__device__ __forceinline__ RayIn ray_entry_ff(const DesignDev& D, const BoundsDev& B, const float* sPin,
+                                              const float* sKu, const float* sKv, int e, int ku, int kv, int64_t id,
+                                              EntryHit& H) {
+    RayIn r;
+    r.status = ST_HIT;
+    float x1 = 0.5f, x2 = 0.5f;
+    if (D.jitter) two_uniforms(splitmix_at(D.rng_state0, (uint64_t)id), x1, x2);
+    if constexpr (!POINT) {
+        const float u = ((float)ku + x1) * D.inv_gu, v = ((float)kv + x2) * D.inv_gv;
+        H.sx = (2.0f * u - 1.0f) * D.r_x;
+        H.sy = (2.0f * v - 1.0f) * D.r_y;
+        H.sz = B.zmin_in - 1.0f;
+        H.d0x = 0.0f;
+        H.d0y = 0.0f;
+        H.d0z = 1.0f;
+    } else {
+        float sth, cth;
+        sincospif(2.0f * ((float)ku + x1) * D.inv_gu, &sth, &cth);
+        const float ao = ((float)kv + x2) * D.inv_gv * D.omc;
+        const float cphi = 1.0f - ao, sphi = sqrtf(ao * (2.0f - ao));
+        float px = D.pos_x, py = D.pos_y;
+        if (D.kind == 2) {
+            int ix = e / D.emit_ny, iy = e - ix * D.emit_ny;
+            px += D.ex0 + (float)ix * D.edx;
+            py += D.ey0 + (float)iy * D.edy;
+        }
+        H.sx = px;
+        H.sy = py;
+        H.sz = D.pos_z;
+        H.d0x = cth * sphi;
+        H.d0y = sth * sphi;
+        H.d0z = cphi;
+    }
+    RayIn s0;  // the source ray, in the form the surface evaluation takes
+    s0.ox = H.sx;
+    s0.oy = H.sy;
+    s0.oz = H.sz;
+    s0.dx = H.d0x;
+    s0.dy = H.d0y;
+    s0.dz = H.d0z;
+    const float ozr = H.sz - B.zref_in;
+    float t;
+    if constexpr (!POINT) {
+        SurfEval<P, Q, float> S;
+        eval_surface<P, Q, false, float>(D, sPin, sKu, sKv, H.sx, H.sy, S);
+        t = S.h - ozr;
+    } else {
+        float t_a = 0.0f, t_b = INFINITY;
+        if (H.d0x != 0.0f) {
+            const float ta = (-D.r_x - H.sx) * rcpf(H.d0x), tb = (D.r_x - H.sx) * rcpf(H.d0x);
+            t_a = fmaxf(t_a, fminf(ta, tb));
+            t_b = fminf(t_b, fmaxf(ta, tb));
+        } else if (fabsf(H.sx) > D.r_x) {
+            t_b = -1.0f;
+        }
+        if (H.d0y != 0.0f) {
+            const float ta = (-D.r_y - H.sy) * rcpf(H.d0y), tb = (D.r_y - H.sy) * rcpf(H.d0y);
+            t_a = fmaxf(t_a, fminf(ta, tb));
+            t_b = fminf(t_b, fmaxf(ta, tb));
+        } else if (fabsf(H.sy) > D.r_y) {
+            t_b = -1.0f;
+        }
+        const float inv_dz = rcpf(H.d0z);
+        const float pad = 4e-6f * (1.0f + fabsf(B.zmax_in - H.sz)) * inv_dz;
+        float a = fmaxf(t_a, (B.zmin_in - H.sz) * inv_dz - pad), b = fminf(t_b, (B.zmax_in - H.sz) * inv_dz + pad);
+        if (!(a <= b)) {
+            r.status = ST_MISS_ENTRY;
+            return r;
+        }
+        float fp;
+        // enter the prism below the face and leave it above, else the ray passes the lens
+        if (f_and_slope<P, Q>(D, sPin, sKu, sKv, s0, ozr, a, fp) < 0.0f ||
+            f_and_slope<P, Q>(D, sPin, sKu, sKv, s0, ozr, b, fp) > 0.0f) {
+            r.status = ST_MISS_ENTRY;
+            return r;
+        }
+        if (!(B.gx_in * fabsf(H.d0x) + B.gy_in * fabsf(H.d0y) < H.d0z)) {
+            constexpr int SCAN = 32;
+            float prev = a;
+            const float end = b;
+            for (int k = 1; k <= SCAN; ++k) {
+                const float ts = a + (end - a) * ((float)k * (1.0f / SCAN));
+                if (f_and_slope<P, Q>(D, sPin, sKu, sKv, s0, ozr, ts, fp) <= 0.0f) {
+                    a = prev;
+                    b = ts;
+                    break;
+                }
+                prev = ts;
+            }
+        }
+        t = 0.5f * (a + b);
+        bool done = false;
+        for (int it = 0; it < D.newton_max && !done; ++it) {
+            const float f = f_and_slope<P, Q>(D, sPin, sKu, sKv, s0, ozr, t, fp);
+            if (f > 0.0f) a = t; else b = t;
+            float tn = t - f * rcpf(fp);
+            if (!(tn >= a && tn <= b) || !(fp < 0.0f)) tn = 0.5f * (a + b);
+            done = fabsf(tn - t) <= 2e-6f * (1.0f + fabsf(t));
+            t = tn;
+        }
+        if (fabsf(fp) < GRAZING_FP) {
+            // grazing hit: double-precision residual at the root and one Newton correction, as at the exit
+            SurfEval<P, Q, double> S;
+            const double td = (double)t;
+            eval_surface<P, Q, false, double>(D, sPin, sKu, sKv, (double)H.sx + td * (double)H.d0x,
+                                              (double)H.sy + td * (double)H.d0y, S);
+            const double fd = S.h - ((double)H.sz - (double)B.zref_in) - td * (double)H.d0z;
+            const double fpd = S.hx * (double)H.d0x + S.hy * (double)H.d0y - (double)H.d0z;
+            if (fpd < 0.0) {
+                const double tn = td - fd / fpd;
+                if (tn >= (double)a - 1e-6 && tn <= (double)b + 1e-6) t = (float)tn;
+            }
+        }
+    }
+    H.t = t;
+    r.ox = H.sx + t * H.d0x;
+    r.oy = H.sy + t * H.d0y;
+    r.oz = H.sz + t * H.d0z;
+    SurfEval<P, Q, float> S;
+    eval_surface<P, Q, false, float>(D, sPin, sKu, sKv, r.ox, r.oy, S);
+    const float inv = rsqrtf(S.hx * S.hx + S.hy * S.hy + 1.0f);
+    const float nx = -S.hx * inv, ny = -S.hy * inv, nz = inv;
+    const float eta = rcpf(D.n_lens);
+    const float c = H.d0x * nx + H.d0y * ny + H.d0z * nz;
+    const float k = 1.0f - eta * eta * (1.0f - c * c);
+    const float beta = sqrtf(k) - eta * c;
+    r.dx = eta * H.d0x + beta * nx;
+    r.dy = eta * H.d0y + beta * ny;
+    r.dz = eta * H.d0z + beta * nz;
+    float w = D.w0;
+    if (D.fresnel) {
+        const float m = 1.0f - c, m2 = m * m;
+        w *= 1.0f - (D.R0 + (1.0f - D.R0) * m2 * m2 * m);
+    }
+    r.w = w;
+    return r;
+}
+
+// ------------------------------------------------------------------------------------------------
 // Triangle mesh of sec. 2.2.2, the paper's own intersector (an alternative to the exact root): each knot
 // span product is divided into mesh_u x mesh_v equal rectangles, each into a lower-left triangle (left and
 // lower edges closed) and an upper-right one (diagonal closed) whose corners lie on the surface.  In cell
@@ -699,8 +852,17 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
     FwdRay o;
     o.iters = o.failed = o.nonmono = o.refined = 0;
     o.X = o.Y = o.w = o.t = o.u = o.v = 0.0f;
-    constexpr bool POINT = (KIND & 1) != 0, MESH = (KIND & 2) != 0;
-    RayIn r = ray_entry<KIND>(D, e, ku, kv, id);
+    constexpr bool POINT = (KIND & 1) != 0, MESH = (KIND & 2) != 0, ENTRY = (KIND & 4) != 0;
+    // with a freeform entry face every ray reaches the exit face from an arbitrary point and direction: the
+    // exit hit needs the root search for collimated rays too
+    constexpr bool SEARCH = POINT || ENTRY;
+    RayIn r;
+    if constexpr (ENTRY) {
+        EntryHit H;
+        r = ray_entry_ff<P, Q, POINT>(D, B, sP + D.n_u * D.n_v, sKu, sKv, e, ku, kv, id, H);
+    } else {
+        r = ray_entry<KIND>(D, e, ku, kv, id);
+    }
     o.status = r.status;
     if (r.status != ST_HIT) return o;
     float t;
@@ -744,7 +906,7 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
         o.w = E.w;
         return o;
     }
-    if constexpr (POINT) {
+    if constexpr (SEARCH) {
         RootOut R = intersect<P, Q>(D, B, sP, sKu, sKv, sS, r);
         o.iters = R.iters;
         o.failed = R.failed;
@@ -761,8 +923,8 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
     float qx = r.ox + t * r.dx, qy = r.oy + t * r.dy;
     SurfEval<P, Q, float> S;
     eval_surface<P, Q, false, float>(D, sP, sKu, sKv, qx, qy, S);
-    float qz = POINT ? r.oz + t * r.dz : S.h + B.zref;
-    if constexpr (!POINT) t = qz - r.oz;
+    float qz = SEARCH ? r.oz + t * r.dz : S.h + B.zref;
+    if constexpr (!SEARCH) t = qz - r.oz;
     o.t = t;
     o.u = qx * (0.5f / D.r_x) + 0.5f;
     o.v = qy * (0.5f / D.r_y) + 0.5f;
@@ -777,18 +939,26 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
 
 // ------------------------------------------------------------------------------------------------
 // One ray, adjoint: re-trace, gather dL/dI over the filter window, reverse sweep.  Returns false when the
-// ray does not reach the screen.  g[] receives dL/dP for control point (ku + a, kv + b) at a * (Q+1) + b.
+// ray does not reach the screen.  g[] receives dL/dP for control point (ku + a, kv + b) at a * (Q+1) + b;
+// with a freeform entry face gin[] receives dL/dP of the entry net's points (cku_in + a, ckv_in + b).
 // ------------------------------------------------------------------------------------------------
 template <int P, int Q, int NU, int KIND>
 __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDev& B, const float* sP,
                                               const float* sKu, const float* sKv, const float* sS,
                                               const float* __restrict__ G,
                                               int e, int ku, int kv, int64_t id, int& cku, int& ckv,
-                                              float* g) {
-    RayIn r = ray_entry<KIND>(D, e, ku, kv, id);
+                                              float* g, int& cku_in, int& ckv_in, float* gin) {
+    constexpr bool point = (KIND & 1) != 0, MESH = (KIND & 2) != 0, ENTRY = (KIND & 4) != 0;
+    constexpr bool SEARCH = point || ENTRY;
+    EntryHit EH;
+    RayIn r;
+    if constexpr (ENTRY) {
+        r = ray_entry_ff<P, Q, point>(D, B, sP + D.n_u * D.n_v, sKu, sKv, e, ku, kv, id, EH);
+    } else {
+        r = ray_entry<KIND>(D, e, ku, kv, id);
+    }
     if (r.status != ST_HIT) return false;
     float t = 0.0f;
-    constexpr bool point = (KIND & 1) != 0, MESH = (KIND & 2) != 0;
     // mesh: the hit triangle, its cell (corner heights and node basis) and the hit's in-cell coordinates
     MeshCell<P, Q> C;
     int mK = 0, mL = 0, mup = 0;
@@ -813,7 +983,7 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
             tri_slopes<P, Q>(C, mup, A, Bs);
             mqz = (mup ? C.z11 + A * (ma - 1.0f) + Bs * (mb - 1.0f) : C.z00 + A * ma + Bs * mb) + B.zref;
         }
-    } else if constexpr (point) {
+    } else if constexpr (SEARCH) {
         RootOut R = intersect<P, Q>(D, B, sP, sKu, sKv, sS, r);
         if (R.status != ST_HIT) return false;
         t = R.t;
@@ -823,13 +993,13 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
     if constexpr (MESH) {
         // the normal is the B-spline's at the hit, on the triangle's span product
         eval_surface_on<P, Q, point, float>(D, sP, sKu, sKv, qx, qy, C.su, C.sv, S);
-    } else if constexpr (point) {
+    } else if constexpr (SEARCH) {
         eval_surface<P, Q, true, float>(D, sP, sKu, sKv, qx, qy, S);
     } else {
         // the hit of a collimated ray does not move with P: no second derivatives needed
         eval_surface<P, Q, false, float>(D, sP, sKu, sKv, qx, qy, S);
     }
-    float qz = point ? r.oz + t * r.dz : (MESH ? mqz : S.h + B.zref);
+    float qz = SEARCH ? r.oz + t * r.dz : (MESH ? mqz : S.h + B.zref);
     ExitState E = exit_face(D, qx, qy, qz, r.dx, r.dy, r.dz, S.hx, S.hy, r.w);
     if (E.status != ST_HIT) return false;
 
@@ -887,7 +1057,7 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
     float hxb = -mxb, hyb = -myb;
     // ---- hit point: coefficient of N_a M_b in dL/dP
     float g0;
-    if (point) {
+    if (SEARCH) {
         // q = o + t d; t moves with P through f(t, P) = 0: dt/dP_ab = -N_a M_b / f'(t)
         float tb = qxb * r.dx + qyb * r.dy + qzb * r.dz + hxb * (S.hxx * r.dx + S.hxy * r.dy) +
                    hyb * (S.hxy * r.dx + S.hyy * r.dy);
@@ -943,6 +1113,58 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
     }
     cku = S.ku;
     ckv = S.kv;
+    if constexpr (ENTRY) {
+        // ---- back through the exit root into the ray inside the glass, q = o + t d with f(t; o, d) = 0:
+        // dt/do = -(h_x, h_y, -1) / f', dt/dd = t dt/do; q_bar includes the exit normal's dependence on q
+        const float qbx = qxb + hxb * S.hxx + hyb * S.hxy, qby = qyb + hxb * S.hxy + hyb * S.hyy;
+        const float obx = qbx + g0 * S.hx, oby = qby + g0 * S.hy, obz = qzb - g0;
+        // d: directly through the exit refraction (e = n d + beta n_hat, c = d . n_hat) and through q
+        const float dbx = n * exb + cb * E.nxh + t * obx;
+        const float dby = n * eyb + cb * E.nyh + t * oby;
+        const float dbz = n * ezb + cb * E.nzh + t * obz;
+        // ---- entry refraction, air -> glass: d = eta d0 + beta_i m_hat, beta_i = sqrt(k_i) - eta c_i,
+        // c_i = d0 . m_hat, k_i = 1 - eta^2 (1 - c_i^2); weight w1 = w0 (1 - Schlick(c_i)); final w = w1 T_exit
+        const float* sPin = sP + D.n_u * D.n_v;
+        SurfEval<P, Q, float> Si;
+        eval_surface<P, Q, point, float>(D, sPin, sKu, sKv, r.ox, r.oy, Si);
+        const float inv_i = rsqrtf(Si.hx * Si.hx + Si.hy * Si.hy + 1.0f);
+        const float mx = -Si.hx * inv_i, my = -Si.hy * inv_i, mz = inv_i;
+        const float eta = rcpf(D.n_lens);
+        const float ci = EH.d0x * mx + EH.d0y * my + EH.d0z * mz;
+        const float ski = sqrtf(fmaxf(1.0f - eta * eta * (1.0f - ci * ci), 1e-30f));
+        const float betai = ski - eta * ci;
+        float cib = (dbx * mx + dby * my + dbz * mz) * (eta * eta * ci / ski - eta);
+        if (D.fresnel) {
+            const float mm = 1.0f - ci, mm2 = mm * mm;
+            cib += wbar * E.T * D.w0 * 5.0f * (1.0f - D.R0) * mm2 * mm2;
+        }
+        const float nbx = betai * dbx + cib * EH.d0x, nby = betai * dby + cib * EH.d0y,
+                    nbz = betai * dbz + cib * EH.d0z;
+        const float nd = nbx * mx + nby * my + nbz * mz;
+        const float gxb_i = -(nbx - nd * mx) * inv_i, gyb_i = -(nby - nd * my) * inv_i;
+        // ---- entry hit: collimated rays meet the face at fixed (x, y), so only its height moves; point-source
+        // rays move along s + t_i d0 with g(s + t_i d0) = s_z + t_i d0_z (the entry normal's dependence on the
+        // hit included, as at the exit face)
+        float c0;
+        if constexpr (point) {
+            const float pbx = obx + gxb_i * Si.hxx + gyb_i * Si.hxy, pby = oby + gxb_i * Si.hxy + gyb_i * Si.hyy;
+            const float tbi = pbx * EH.d0x + pby * EH.d0y + obz * EH.d0z;
+            const float fpi = Si.hx * EH.d0x + Si.hy * EH.d0y - EH.d0z;
+            c0 = -tbi * rcpf(fpi);
+        } else {
+            c0 = obz;
+        }
+        const float gxi = gxb_i * D.sxu, gyi = gyb_i * D.syv;
+#pragma unroll
+        for (int a = 0; a <= P; ++a) {
+            const float du = gxi * Si.dNu[a];
+#pragma unroll
+            for (int b = 0; b <= Q; ++b)
+                gin[a * (Q + 1) + b] = Si.Nu[a] * (c0 * Si.Nv[b] + gyi * Si.dNv[b]) + du * Si.Nv[b];
+        }
+        cku_in = Si.ku;
+        ckv_in = Si.kv;
+    }
     return true;
 }
 
@@ -975,7 +1197,7 @@ __device__ __forceinline__ int find_design(const BlockMap* bm, int n, int64_t b)
 __device__ BoundsDev stage_design(const TraceArgs& A, const DesignDev& D, int d, float* sP, float* sK, int p, int q,
                                   bool bracket) {
     const float* P = A.Pz + D.cp_off;
-    const int ncp = D.n_u * D.n_v;
+    const int ncp = D.n_u * D.n_v;  // exit net; a freeform entry net follows it, relative to zref_in
     const int nku = D.nsu * kt_stride(p), nkv = D.nsv * kt_stride(q);
     const float* ku = A.knots + D.kt_u;
     const float* kv = A.knots + D.kt_v;
@@ -993,6 +1215,8 @@ __device__ BoundsDev stage_design(const TraceArgs& A, const DesignDev& D, int d,
         B.zref = isfinite(zc) ? zc : D.zmin_allowed;
     }
     for (int i = threadIdx.x; i < ncp; i += WG) sP[i] = P[i] - B.zref;
+    if (D.entry_ff)
+        for (int i = threadIdx.x; i < ncp; i += WG) sP[ncp + i] = P[ncp + i] - B.zref_in;
     for (int i = threadIdx.x; i < nku; i += WG) sK[i] = ku[i];
     for (int i = threadIdx.x; i < nkv; i += WG) sK[nku + i] = kv[i];
     __syncthreads();
@@ -1035,9 +1259,9 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
     extern __shared__ float smem[];
     float* sP = smem;
     float* sK = sP + A.lds_cp;
-    float* sS = sK + A.lds_kt;  // span bounds (point sources, when they fit)
+    float* sS = sK + A.lds_kt;  // span bounds (exit root searches, when they fit)
     uint32_t* tile = reinterpret_cast<uint32_t*>(sS + A.lds_sb);
-    const float* sSb = (KIND & 1) != 0 && A.lds_sb ? sS : nullptr;
+    const float* sSb = (KIND & 5) != 0 && A.lds_sb ? sS : nullptr;
     __shared__ int s_box[4][4];
     __shared__ float s_red[4][10];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -1049,7 +1273,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
         const DesignDev D = load_uniform(A.designs, d);
         if (d != cur) {
             __syncthreads();
-            B = stage_design(A, D, d, sP, sK, P, Q, (KIND & 1) != 0);
+            B = stage_design(A, D, d, sP, sK, P, Q, (KIND & 5) != 0);
             cur = d;
         }
         const float* sKu = sK;
@@ -1267,7 +1491,7 @@ __device__ void adjoint_flush(const TraceArgs& A, int d, const float* sG) {
     __syncthreads();
     const DesignDev D = load_uniform(A.designs, d);
     float* acc = A.gacc + D.cp_off;
-    for (int i = threadIdx.x; i < D.n_u * D.n_v; i += WG) {
+    for (int i = threadIdx.x; i < D.ncp; i += WG) {
         const float v = sG[i];
         if (v != 0.0f) atomicAdd(&acc[i], v);
     }
@@ -1281,9 +1505,9 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
     extern __shared__ float smem[];
     float* sP = smem;
     float* sK = sP + A.lds_cp;
-    float* sS = sK + A.lds_kt;  // span bounds (point sources, when they fit)
+    float* sS = sK + A.lds_kt;  // span bounds (exit root searches, when they fit)
     float* sG = sS + A.lds_sb;
-    const float* sSb = (KIND & 1) != 0 && A.lds_sb ? sS : nullptr;
+    const float* sSb = (KIND & 5) != 0 && A.lds_sb ? sS : nullptr;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int MU = shape_mu(shape), MV = shape_mv(shape), RPT = MU * MV;
     const int BU = 16 * MU, BV = 16 * MV;
@@ -1299,8 +1523,8 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
         if (d != cur) {
             if (cur >= 0) adjoint_flush(A, cur, sG);
             __syncthreads();
-            for (int i = threadIdx.x; i < D.n_u * D.n_v; i += WG) sG[i] = 0.0f;
-            B = stage_design(A, D, d, sP, sK, P, Q, (KIND & 1) != 0);
+            for (int i = threadIdx.x; i < D.ncp; i += WG) sG[i] = 0.0f;
+            B = stage_design(A, D, d, sP, sK, P, Q, (KIND & 5) != 0);
             cur = d;
         }
         const float* G = A.dLdI + D.img_off;
@@ -1312,18 +1536,25 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
         int64_t ebase = (int64_t)e * D.grid_u * D.grid_v;
         const int ku0 = bu * BU + (wave >> 1) * 8 * MU + (lane >> 3) * MU;
         const int kv0 = bv * BV + (wave & 1) * 8 * MV + (lane & 7) * MV;
-        // per-thread accumulator of the span product its rays hit; flushed when the span changes
-        float acc[NV];
+        // per-thread accumulator of the span product its rays hit; flushed when the span changes (a second one
+        // for the entry net of a lens with a freeform entry face, whose LDS gradient follows the exit net's)
+        constexpr bool ENTRY = (KIND & 4) != 0;
+        float acc[NV], acc_in[ENTRY ? NV : 1];
 #pragma unroll
         for (int i = 0; i < NV; ++i) acc[i] = 0.0f;
-        int aku = -1, akv = -1;
+#pragma unroll
+        for (int i = 0; i < (ENTRY ? NV : 1); ++i) acc_in[i] = 0.0f;
+        int aku = -1, akv = -1, aku_in = -1, akv_in = -1;
+        float* sG_in = sG + D.n_u * D.n_v;
         for (int r = 0; r < RPT; ++r) {
             const int ku = ku0 + (r >> mv_shift), kv = kv0 + (r & (MV - 1));
             if (ku >= D.grid_u || kv >= D.grid_v) continue;
-            float g[NT];
-            int cku = -1, ckv = -1;
+            float g[NT], gin[ENTRY ? NT : 1];
+            int cku = -1, ckv = -1, cku_in = -1, ckv_in = -1;
             int64_t id = ebase + (int64_t)ku * D.grid_v + kv;
-            if (!trace_adjoint<P, Q, NU, KIND>(D, B, sP, sKu, sKv, sSb, G, e, ku, kv, id, cku, ckv, g)) continue;
+            if (!trace_adjoint<P, Q, NU, KIND>(D, B, sP, sKu, sKv, sSb, G, e, ku, kv, id, cku, ckv, g, cku_in, ckv_in,
+                                               gin))
+                continue;
             if (aku >= 0 && (cku != aku || ckv != akv)) {
                 cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc);
 #pragma unroll
@@ -1333,6 +1564,20 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
             akv = ckv;
 #pragma unroll
             for (int i = 0; i < NT; ++i) acc[i] += g[i];
+            if constexpr (ENTRY) {
+                if (aku_in >= 0 && (cku_in != aku_in || ckv_in != akv_in)) {
+                    cp_flush_lane<P, Q, NV>(sG_in, D.n_v, aku_in, akv_in, acc_in);
+#pragma unroll
+                    for (int i = 0; i < NV; ++i) acc_in[i] = 0.0f;
+                }
+                aku_in = cku_in;
+                akv_in = ckv_in;
+#pragma unroll
+                for (int i = 0; i < NT; ++i) acc_in[i] += gin[i];
+            }
+        }
+        if constexpr (ENTRY) {
+            if (aku_in >= 0) cp_flush_lane<P, Q, NV>(sG_in, D.n_v, aku_in, akv_in, acc_in);
         }
         // end of the block: one round per distinct span product held in the wave, in which the lanes of the
         // leader's span product sum their accumulators with a butterfly (one LDS atomic per control point)
@@ -1383,7 +1628,7 @@ __global__ __launch_bounds__(WG) void k_trace_rays(TraceArgs A, int design, cons
     float* sK = sP + A.lds_cp;
     float* sS = sK + A.lds_kt;
     const DesignDev D = load_uniform(A.designs, design);
-    const BoundsDev B = stage_design(A, D, design, sP, sK, P, Q, D.kind != 0);
+    const BoundsDev B = stage_design(A, D, design, sP, sK, P, Q, D.kind != 0 || D.entry_ff);
     int64_t i = (int64_t)blockIdx.x * WG + threadIdx.x;
     if (i >= n) return;
     int64_t id = ids[i];
@@ -1392,10 +1637,12 @@ __global__ __launch_bounds__(WG) void k_trace_rays(TraceArgs A, int design, cons
     int64_t rr = id - (int64_t)e * per;
     int ku = (int)(rr / D.grid_v), kv = (int)(rr - (rr / D.grid_v) * D.grid_v);
     const float* sKv = sK + D.nsu * kt_stride(P);
-    const float* sSb = A.lds_sb && D.kind != 0 ? sS : nullptr;
+    const float* sSb = A.lds_sb && (D.kind != 0 || D.entry_ff) ? sS : nullptr;
     FwdRay o;
-    if (D.mesh_u) o = D.kind == 0 ? trace_forward<P, Q, 2>(D, B, sP, sK, sKv, nullptr, e, ku, kv, id)
-                                  : trace_forward<P, Q, 3>(D, B, sP, sK, sKv, nullptr, e, ku, kv, id);
+    if (D.entry_ff) o = D.kind == 0 ? trace_forward<P, Q, 4>(D, B, sP, sK, sKv, sSb, e, ku, kv, id)
+                                    : trace_forward<P, Q, 5>(D, B, sP, sK, sKv, sSb, e, ku, kv, id);
+    else if (D.mesh_u) o = D.kind == 0 ? trace_forward<P, Q, 2>(D, B, sP, sK, sKv, nullptr, e, ku, kv, id)
+                                       : trace_forward<P, Q, 3>(D, B, sP, sK, sKv, nullptr, e, ku, kv, id);
     else o = D.kind == 0 ? trace_forward<P, Q, 0>(D, B, sP, sK, sKv, nullptr, e, ku, kv, id)
                          : trace_forward<P, Q, 1>(D, B, sP, sK, sKv, sSb, e, ku, kv, id);
     float* dst = out8 + 8 * i;
@@ -1426,6 +1673,8 @@ struct KernelsFor {
             case 1: hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 1>), dim3(grid), dim3(WG), lds, s, A); break;
             case 2: hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 2>), dim3(grid), dim3(WG), lds, s, A); break;
             case 3: hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 3>), dim3(grid), dim3(WG), lds, s, A); break;
+            case 4: hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 4>), dim3(grid), dim3(WG), lds, s, A); break;
+            case 5: hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 5>), dim3(grid), dim3(WG), lds, s, A); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -1452,6 +1701,8 @@ struct KernelsFor {
                 break;
             case 2: hipLaunchKernelGGL((k_adjoint<P, Q, NU, 2>), dim3(grid), dim3(WG), lds, s, A, shape); break;
             case 3: hipLaunchKernelGGL((k_adjoint<P, Q, NU, 3>), dim3(grid), dim3(WG), lds, s, A, shape); break;
+            case 4: hipLaunchKernelGGL((k_adjoint<P, Q, NU, 4>), dim3(grid), dim3(WG), lds, s, A, shape); break;
+            case 5: hipLaunchKernelGGL((k_adjoint<P, Q, NU, 5>), dim3(grid), dim3(WG), lds, s, A, shape); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();

@@ -25,7 +25,8 @@ class FfrtError(RuntimeError):
 class CLens(ctypes.Structure):
     _fields_ = [("n_lens", ctypes.c_double), ("r_x", ctypes.c_double), ("r_y", ctypes.c_double),
                 ("z_in", ctypes.c_double), ("delta_min", ctypes.c_double),
-                ("p", ctypes.c_int32), ("q", ctypes.c_int32), ("n_u", ctypes.c_int32), ("n_v", ctypes.c_int32)]
+                ("p", ctypes.c_int32), ("q", ctypes.c_int32), ("n_u", ctypes.c_int32), ("n_v", ctypes.c_int32),
+                ("entry_freeform", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CSource(ctypes.Structure):
@@ -146,7 +147,7 @@ def to_cproblem(p):
     """Problem (workloads.Problem layout) -> CProblem."""
     c = CProblem()
     L, S, D, O = p.lens, p.source, p.detector, p.options
-    c.lens = CLens(L.n_lens, L.r_x, L.r_y, L.z_in, L.delta_min, L.p, L.q, L.n_u, L.n_v)
+    c.lens = CLens(L.n_lens, L.r_x, L.r_y, L.z_in, L.delta_min, L.p, L.q, L.n_u, L.n_v, L.entry_freeform, 0)
     c.src = CSource(S.kind, S.grid_u, S.grid_v, S.jitter, (ctypes.c_double * 3)(*S.pos), S.half_angle,
                     S.emit_nx, S.emit_ny, S.emit_wx, S.emit_wy, S.seed)
     c.det = CDetector(D.n_x, D.n_y, D.R_x, D.R_y, D.z_screen, D.alpha, D.nu_x, D.nu_y, D.ghost, D.filter)
@@ -241,7 +242,7 @@ class Plan:
         out = []
         for d, p in enumerate(self.problems):
             a, b = self.cp_offsets[d], self.cp_offsets[d + 1]
-            out.append(flat[a:b].reshape(p.lens.n_u, p.lens.n_v))
+            out.append(flat[a:b].reshape(p.cp_shape()))
         return out
 
     def unpack_img(self, flat):

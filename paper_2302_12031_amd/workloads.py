@@ -277,3 +277,15 @@ def with_mesh(wl: Workload, m: int) -> Workload:
     instead of the exact surface."""
     probs = [replace(p, options=replace(p.options, mesh_u=m, mesh_v=m)) for p in wl.problems]
     return Workload(f"{wl.name}-mesh{m}", probs, wl.Pz, wl.targets)
+
+
+def with_entry_freeform(wl: Workload, seed: int = 11, base: float = 0.5, spread: float = 0.05) -> Workload:
+    """The same workload with a freeform entry face: entry heights z_in + base +- spread (seeded), the exit
+    net unchanged (the paper's proposal of optimising both faces).  The default spread gives entry slopes of
+    at most ~0.3 on the 32 x 32 net, a gently curved face."""
+    probs, Pz = [], []
+    for d, (p, P) in enumerate(zip(wl.problems, wl.Pz)):
+        probs.append(replace(p, lens=replace(p.lens, entry_freeform=1)))
+        entry = p.lens.z_in + base + rng(seed + d, STREAM_PZ).uniform(-spread, spread, size=P.shape)
+        Pz.append(np.stack([P, entry]))
+    return Workload(f"{wl.name}-twofaces", probs, Pz, wl.targets)

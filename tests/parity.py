@@ -11,8 +11,8 @@ MAX_MARGINAL = 2e-5
 GRAD_REL = 1e-3
 
 
-def irradiance_errors(I_gpu, I_64, mask=None):
-    tol = IRR_REL * np.maximum(I_64, IRR_FLOOR * I_64.max())
+def irradiance_errors(I_gpu, I_64, mask=None, rel=IRR_REL):
+    tol = rel * np.maximum(I_64, IRR_FLOOR * I_64.max())
     err = np.abs(I_gpu - I_64)
     ok = err <= tol
     if mask is not None:
@@ -24,8 +24,8 @@ def irradiance_errors(I_gpu, I_64, mask=None):
     return ok, float((err / np.maximum(tol, 1e-300)).max()), float(rel_big)
 
 
-def assert_irradiance(I_gpu, I_64, mask=None, max_masked_frac=0.05, what=""):
-    ok, worst, rel_big = irradiance_errors(I_gpu, I_64, mask)
+def assert_irradiance(I_gpu, I_64, mask=None, max_masked_frac=0.05, what="", rel=IRR_REL):
+    ok, worst, rel_big = irradiance_errors(I_gpu, I_64, mask, rel)
     n_mask = int(mask.sum()) if mask is not None else 0
     assert n_mask <= max_masked_frac * I_64.size + 9, f"{what}: {n_mask} masked pixels"
     bad = np.argwhere(~ok)

@@ -1,0 +1,141 @@
+"""GPU: lenses with both faces freeform (the entry face a second B-spline whose net follows the exit net),
+through the C ABI, against the oracle: irradiance per pixel, the gradient over both nets, per-ray hits at full
+size, the reduction to the plano-freeform lens, and optimisation steps."""
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2302_12031_amd import ffrt
+from paper_2302_12031_amd import workloads as W
+from parity import MAX_MARGINAL, assert_gradient, assert_irradiance
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run(wl):
+    plan = ffrt.Plan(wl.problems)
+    Pz = plan.pack_cp(wl.Pz)
+    T = plan.pack_img(wl.targets)
+    st = plan.new_stats()
+    irr = plan.forward(Pz, stats=st)
+    loss, dLdI = plan.loss(irr, T)
+    g = plan.adjoint(Pz, dLdI)
+    torch.cuda.synchronize()
+    return plan, dict(irr=plan.unpack_img(irr.cpu().numpy()), loss=loss.cpu().numpy(),
+                      g=plan.unpack_cp(g.cpu().numpy()), stats=plan.decode_stats(st))
+
+
+# Rays that leave the exit face close to the critical angle refract along a direction that varies as
+# dk / (2 sqrt(k)): FP32 rounding of their inputs alone moves their landing by up to ~1e-3 mm on the point-source
+# geometry with two freeform faces (a 1M-ray per-ray comparison with the oracle: no status mismatch, every
+# landing within 1e-3 mm), against ~1e-5 mm elsewhere.  Through the normalised Gaussian filter (slope at most
+# ~0.9 per pixel width, about twice that after normalisation) a pixel fed by such rays may then differ by up to
+# 2 x 0.9 x 1e-3 / 0.625 ~ 3e-3 of its value: the per-pixel tolerance on that geometry.  The per-ray test below
+# keeps the landing bound itself.
+REL_NEAR_CRITICAL = 3e-3
+
+# (workload, per-pixel irradiance at this size and its relative tolerance, gradient compared)
+CASES = {
+    "c1": (lambda: W.with_entry_freeform(W.c1()), 1e-4, True),
+    "c2": (lambda: W.with_entry_freeform(W.c2()), 1e-4, True),
+    "c3": (lambda: W.with_entry_freeform(W.c3()), REL_NEAR_CRITICAL, False),
+    "c3s": (lambda: W.with_entry_freeform(W.c3(512)), None, True),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_two_face_forward_and_gradient_parity(name):
+    make, irr_rel, grad = CASES[name]
+    wl = make()
+    _say(f"[two faces] {name}: {wl.name}, {wl.num_rays} rays")
+    plan, out = _run(wl)
+    p, Pz, T = wl.problems[0], wl.Pz[0], wl.targets[0]
+    I64, st64, mask = O.forward(p, Pz, with_mask=True)
+    worst, rel, eg = float("nan"), float("nan"), float("nan")
+    if irr_rel is not None:
+        worst, rel = assert_irradiance(out["irr"][0], I64, mask, what=name, rel=irr_rel)
+    s = out["stats"][0]
+    assert s["n_traced"] == st64["n_rays"]
+    assert st64["n_marginal"] <= MAX_MARGINAL * st64["n_rays"] + 5
+    assert abs(int(s["n_hit"]) - st64["n_hit"]) <= st64["n_marginal"] + 2
+    assert abs(float(s["flux_on_screen"]) - st64["flux_on_screen"]) <= 1e-4 * st64["flux_on_screen"]
+    assert int(s["n_constraint_viol"]) == 0
+    if grad:
+        L64, g64, _, _ = O.grad(p, Pz, T)
+        assert abs(out["loss"][0] - L64) <= 1e-4 * L64
+        eg = assert_gradient(out["g"][0], g64, what=name)
+        # both nets carry gradient, each within the tolerance of its own scale
+        for f in range(2):
+            assert np.abs(g64[f]).max() > 0
+            assert np.abs(out["g"][0][f] - g64[f]).max() <= 2e-3 * np.abs(g64[f]).max(), f
+    _say(f"[two faces] {name}: irr worst err/tol {worst:.3g}, bright rel {rel:.2e}, grad rel {eg:.2e}, "
+         f"hits {int(s['n_hit'])}")
+
+
+def test_flat_entry_net_matches_the_plano_freeform_lens():
+    """An entry net at z_in reproduces the plano-freeform lens: the irradiance and the exit-net gradient of
+    the plan without a freeform entry face, to the per-pixel parity tolerance.  The two paths round
+    differently (a plane hit against a root search on a flat net), so the pixels of rays whose discrete
+    state is within rounding of flipping are masked as in the parity tests."""
+    for base, rel in ((W.c1(), 1e-4), (W.c3(1024), REL_NEAR_CRITICAL)):
+        two = W.with_entry_freeform(base, base=0.0, spread=0.0)
+        _, a = _run(base)
+        _, b = _run(two)
+        _, _, mask = O.forward(base.problems[0], base.Pz[0], with_mask=True)
+        assert_irradiance(b["irr"][0], a["irr"][0], mask, what=base.name, rel=rel)
+        assert_gradient(b["g"][0][0], a["g"][0], what=base.name)
+
+
+def test_two_face_per_ray_parity_full_size():
+    wl = W.with_entry_freeform(W.c3())
+    p, Pz = wl.problems[0], wl.Pz[0]
+    plan = ffrt.Plan(wl.problems)
+    ids = np.unique(np.random.default_rng(3).integers(0, wl.num_rays, 4096))
+    gpu = plan.trace_rays(0, plan.pack_cp([Pz]), ids).cpu().numpy()
+    ref = O.trace_rays(p, Pz, ids)
+    clear = ref[:, 7] == 0
+    assert (gpu[clear, 0] == ref[clear, 0]).sum() >= clear.sum() - 2
+    hit = clear & (ref[:, 0] == O.HIT) & (gpu[:, 0] == O.HIT)
+    scale = p.detector.z_screen * (1.0 + np.abs(ref[hit, 1:3]).max(1, keepdims=True) / p.detector.z_screen)
+    dxy = np.abs(gpu[hit, 1:3] - ref[hit, 1:3]) / scale
+    assert dxy.max() <= 2e-5, dxy.max()
+    assert np.median(dxy) <= 5e-7, np.median(dxy)
+    np.testing.assert_allclose(gpu[hit, 3], ref[hit, 3], rtol=2e-5)
+    _say(f"[two faces per-ray] {hit.sum()} hits, landing err max {dxy.max():.2e}, median {np.median(dxy):.2e}")
+
+
+def test_two_face_steps_reduce_the_loss_and_count_thin_spots():
+    """Graph-captured Adam steps move both nets and lower the loss; a net pushed through the other is
+    reported by the thickness counter."""
+    wl = W.with_entry_freeform(W.c1())
+    plan = ffrt.Plan(wl.problems)
+    st = plan.new_state(plan.pack_cp(wl.Pz))
+    T = plan.pack_img(wl.targets)
+    P0 = st["Pz"].clone()
+    plan.step(st, T, hp=ffrt.AdamHP(lr=1e-3))
+    L0 = st["loss"].item()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        plan.graph_capture(st, T, steps=50, hp=ffrt.AdamHP(lr=1e-3))
+        plan.graph_launch(s)
+    torch.cuda.synchronize()
+    L1 = plan.loss(plan.forward(st["Pz"]), T)[0].item()
+    _say(f"[two faces steps] loss {L0:.4e} -> {L1:.4e}")
+    assert L1 < 0.9 * L0
+    K = wl.problems[0].lens.n_u * wl.problems[0].lens.n_v
+    moved = (st["Pz"] - P0).abs()
+    assert moved[:K].max() > 0 and moved[K:].max() > 0
+    bad = P0.clone()
+    bad[K + 5] = bad[5] + 0.5                     # entry point above the exit point
+    stt = plan.new_stats()
+    plan.forward(bad, stats=stt)
+    assert int(plan.decode_stats(stt)[0]["n_constraint_viol"]) == 1
