@@ -167,10 +167,11 @@ def test_graph_replay_of_mlp_steps_matches_eager(arch):
             plan_e.step_mlp(st_e, T, hp=hp)
         _ = torch.ones(1000, device="cuda").sum().item()      # unrelated eager work between replays
         torch.cuda.synchronize()
-        # the adjoint adds partial sums atomically, so replays agree to rounding, not bit for bit: a few tens
-        # of float ulps of heights near 2
-        torch.testing.assert_close(st_g["params"], st_e["params"], rtol=0, atol=5e-6)
-        torch.testing.assert_close(st_g["Pz"], st_e["Pz"], rtol=0, atol=5e-6)
+        # the adjoint adds partial sums atomically: a gradient component whose ray contributions nearly
+        # cancel carries up to ~1e-4 relative rounding between runs, which Adam turns into ~lr 1e-4 parameter
+        # differences per step.  A replay that skipped a step or read stale parameters would differ by ~lr.
+        torch.testing.assert_close(st_g["params"], st_e["params"], rtol=0, atol=3e-5)
+        torch.testing.assert_close(st_g["Pz"], st_e["Pz"], rtol=0, atol=3e-5)
         assert int(st_g["t"][0]) == 3 * (k + 1)
 
 
@@ -192,8 +193,9 @@ def test_zero_initialised_generator_follows_the_no_network_optimisation(arch):
     w1, b1, W2, b2, W3, b3 = plan.unpack_mlp(st_m["params"], arch)[0]
     for a in (w1, b1, W2, b2, W3):
         assert not torch.any(a)
-    torch.testing.assert_close(b3, st_r["theta"], rtol=0, atol=5e-6)
-    torch.testing.assert_close(st_m["Pz"], st_r["Pz"], rtol=0, atol=5e-6)
+    # separate runs of the adjoint differ by the rounding of its atomic sums (see the replay test)
+    torch.testing.assert_close(b3, st_r["theta"], rtol=0, atol=3e-5)
+    torch.testing.assert_close(st_m["Pz"], st_r["Pz"], rtol=0, atol=3e-5)
 
 
 @pytest.mark.parametrize("arch", ARCHS)
