@@ -125,7 +125,7 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": src.numel() * 4}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: the tracer runs on a single MI355X in this build "
+        print("bench.py measures one GPU: the tracer runs on a single MI355X "
               "(multi-GPU sharding is a design note, not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
