@@ -1347,7 +1347,10 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
             }
             __syncthreads();
         }
-        // ---- footprint of the block (landing pixels widened by the filter half-width)
+        // ---- footprint of the block: the landing pixels widened by the filter half-width, and by one more
+        // row and column for the per-thread windows below.  The tile is not clipped to the image, so every
+        // window of a thread with a hit lies inside it and needs no per-pixel test; pixels outside the
+        // image only ever receive zero weights, and the flush skips them.
         unsigned long long* img = A.img64 + D.img_off;
         bool use_tile = false;
         int ilo = 0, jlo = 0, tw = 0, area = 0, ncopy = 1;
@@ -1367,12 +1370,11 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
             b1 = max(max(s_box[0][3], s_box[1][3]), max(s_box[2][3], s_box[3][3]));
             __syncthreads();
             if (a1 < 0) continue;  // no ray of the block reached the screen
-            ilo = max(a0 - H, 0);
-            int ihi = min(a1 + H, D.nx - 1);
-            jlo = max(b0 - H, 0);
-            int jhi = min(b1 + H, D.ny - 1);
-            tw = jhi - jlo + 1;
-            area = (ihi - ilo + 1) * tw;
+            constexpr int PAD = ACCUM ? 1 : 0;
+            ilo = a0 - H;
+            jlo = b0 - H;
+            tw = b1 + H + PAD - jlo + 1;
+            area = (a1 + H + PAD - ilo + 1) * tw;
             use_tile = area <= TILE_CAP;
             if (use_tile) {
                 // Neighbouring lanes usually add to the same pixels, and LDS atomics on one address serialise:
@@ -1388,11 +1390,13 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
         if constexpr (ACCUM) {
             // The window is anchored at the thread's lowest landing pixel (imin, jmin); rays whose filter
             // window starts at most one pixel further along each axis are summed in registers, the others
-            // are added directly.
+            // are added directly.  With the tile the sums are kept in tile units.
             const int ai = imin - H, aj = jmin - H;
+            const float wsc = use_tile ? D.fx_scale * (1.0f / (float)(1 << TSH)) : 1.0f;
             float acc[WN * WN];
 #pragma unroll
             for (int k = 0; k < WN * WN; ++k) acc[k] = 0.0f;
+            bool last_row = false, last_col = false;  // whether row / column WN - 1 of the window is used
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
                 if (W[r] == 0.0f) continue;
@@ -1416,22 +1420,48 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
                     }
                     continue;
                 }
+                last_row |= di != 0;
+                last_col |= dj != 0;
                 // add the NU x NU window at offset (di, dj) in {0, 1}^2 without indexing registers dynamically
+                const float wr = W[r] * wsc;
                 float fx[WN], fy[WN];
 #pragma unroll
                 for (int k = 0; k < WN; ++k) {
                     float a0 = k < NU ? Fx[k] : 0.0f, a1 = k > 0 ? Fx[k - 1] : 0.0f;
                     float b0 = k < NU ? Fy[k] : 0.0f, b1 = k > 0 ? Fy[k - 1] : 0.0f;
-                    fx[k] = W[r] * (di == 0 ? a0 : a1);
+                    fx[k] = wr * (di == 0 ? a0 : a1);
                     fy[k] = dj == 0 ? b0 : b1;
                 }
 #pragma unroll
                 for (int k = 0; k < WN * WN; ++k) acc[k] += fx[k / WN] * fy[k % WN];
             }
+            if (use_tile) {
+                if (imax >= 0) {  // the window lies inside the tile: one row address per window row
+                    uint32_t* t0 = mytile + (ai - ilo) * tw + (aj - jlo);
+                    auto add = [](uint32_t* p, float v) {
+                        __hip_atomic_fetch_add(p, (uint32_t)__float2int_rn(v), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                    };
 #pragma unroll
-            for (int k = 0; k < WN * WN; ++k)
-                if (acc[k] != 0.0f)
-                    splat_add<TSH>(use_tile, mytile, tw, ilo, jlo, D.fx_scale, img, D.ny, ai + k / WN, aj + k % WN, acc[k]);
+                    for (int a = 0; a < WN - 1; ++a) {
+                        uint32_t* row = t0 + a * tw;
+#pragma unroll
+                        for (int bb = 0; bb < WN - 1; ++bb) add(row + bb, acc[a * WN + bb]);
+                        if (last_col) add(row + WN - 1, acc[a * WN + WN - 1]);
+                    }
+                    if (last_row) {
+                        uint32_t* row = t0 + (WN - 1) * tw;
+#pragma unroll
+                        for (int bb = 0; bb < WN; ++bb) add(row + bb, acc[(WN - 1) * WN + bb]);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < WN * WN; ++k)
+                    if (acc[k] != 0.0f)
+                        splat_add<TSH>(false, mytile, tw, ilo, jlo, D.fx_scale, img, D.ny, ai + k / WN,
+                                       aj + k % WN, acc[k]);
+            }
         } else {
 #pragma unroll
             for (int r = 0; r < RPT; ++r) {
@@ -1461,9 +1491,10 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
                 for (int c = 1; c < ncopy; ++c) q += tile[c * area + i];
                 q <<= TSH;
                 const int ti = i / tw;
-                if (q != 0ull)
-                    __hip_atomic_fetch_add(&img[(int64_t)(ilo + ti) * D.ny + jlo + (i - ti * tw)], q,
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int gi = ilo + ti, gj = jlo + (i - ti * tw);
+                if (q != 0ull && gi >= 0 && gi < D.nx && gj >= 0 && gj < D.ny)
+                    __hip_atomic_fetch_add(&img[(int64_t)gi * D.ny + gj], q, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
             }
             __syncthreads();
         }
