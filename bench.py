@@ -31,21 +31,23 @@ sys.path.insert(0, ROOT)
 METRIC = "forward+adjoint rays/s and Adam steps/s vs finite-diff gradient, same GPU @1e-3"
 
 # Algorithmic FP32 operations per ray (add, mul, compare-free arithmetic; fma = 2; exp, sqrt, rsqrt, rcp,
-# sincos = 1 each), counted stage by stage from the kernels' formulation for p = q = 3, nu = 3.
+# sincos = 1 each), counted stage by stage from the kernels' formulation for p = q = 3, nu = 3, with the
+# closed-form uniform cubic of interior spans: 27 operations per axis for N and N', 4 more for N''
+# (the generic recurrence takes ~42 and ~20).
 FLOPS = {
-    "collimated": {"forward": 350, "adjoint": 555, "newton_iter": 0},
+    "collimated": {"forward": 320, "adjoint": 525, "newton_iter": 0},
     # point sources: fixed part + per Newton iteration (surface value and slope, step)
-    "point": {"forward": 420, "adjoint": 1060, "newton_iter": 224},
+    "point": {"forward": 390, "adjoint": 998, "newton_iter": 194},
 }
 # Triangle mesh (sec. 2.2.2) instead of the root: per visited cell, four span-basis evaluations at the
-# cell's nodes (~264), four corner heights (~96) and two plane tests (~30); the adjoint adds the hit cell's
+# cell's nodes (~204), four corner heights (~96) and two plane tests (~30); the adjoint adds the hit cell's
 # barycentric basis weights (~64) and re-walks the cells.  A collimated ray visits exactly one cell.
-MESH_CELL_FLOPS = 390
+MESH_CELL_FLOPS = 330
 MESH_ADJ_EXTRA = 64
 # Freeform entry face: the entry root search (bracket, ~2 Newton steps of a surface value and slope), the entry
 # normal and refraction; every ray then searches the exit face like a point-source ray.  The adjoint adds the
 # entry reverse (second derivatives at the entry hit, the entry refraction, the entry root).
-ENTRY_FLOPS = {"forward": 600, "adjoint": 900}
+ENTRY_FLOPS = {"forward": 510, "adjoint": 778}
 # Algorithmic HBM bytes of the generator per design with K control points and n parameters (fp32): the
 # forward reads the two weight matrices (dense 2 K^2, sparse 2 C K floats; vectors of K are negligible); the
 # back-propagation reads them again; the gradient + Adam pass reads and writes parameters and both moments
