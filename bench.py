@@ -36,9 +36,13 @@ METRIC = "forward+adjoint rays/s and Adam steps/s vs finite-diff gradient, same 
 # (the generic recurrence takes ~42 and ~20).
 FLOPS = {
     "collimated": {"forward": 320, "adjoint": 525, "newton_iter": 0},
-    # point sources: fixed part + per Newton iteration (surface value and slope, step)
-    "point": {"forward": 390, "adjoint": 998, "newton_iter": 194},
+    # point sources: fixed part (with the exit-root bracket) + per Newton iteration (surface value and slope,
+    # step).  Inside a step the adjoint of exact-root, flat-entry designs reads the roots the forward stored:
+    # it does neither the bracket nor the iterations.
+    "point": {"forward": 390, "adjoint": 998, "newton_iter": 194, "bracket": 35},
 }
+# Plans keep the exit roots for the adjoint when they take at most this many bytes (4 per ray).
+ROOTS_CAP_BYTES = 1 << 30
 # Triangle mesh (sec. 2.2.2) instead of the root: per visited cell, four span-basis evaluations at the
 # cell's nodes (~204), four corner heights (~96) and two plane tests (~30); the adjoint adds the hit cell's
 # barycentric basis weights (~64) and re-walks the cells.  A collimated ray visits exactly one cell.
@@ -225,6 +229,10 @@ def main():
         tr = sub.trace_rays(0, pz0, ids).cpu().numpy()
         iters = float(tr[tr[:, 0] == 0, 7].mean()) if (tr[:, 0] == 0).any() else 0.0
 
+    root_rays = sum(p.num_rays() for p in wl.problems
+                    if p.source.kind != 0 and not p.lens.entry_freeform and not p.options.mesh_u)
+    roots_reused = 0 < 4 * root_rays <= ROOTS_CAP_BYTES
+
     def flops(kernel):
         tot = 0.0
         for p in wl.problems:
@@ -235,6 +243,8 @@ def main():
                 cells = 1.0 if k == "collimated" else iters
                 f = FLOPS[k][kernel] + MESH_CELL_FLOPS * (cells + (kernel == "adjoint"))
                 f += MESH_ADJ_EXTRA if kernel == "adjoint" else 0
+            elif k == "point" and kernel == "adjoint" and roots_reused:
+                f = FLOPS[k][kernel] - FLOPS[k]["bracket"]
             else:
                 f = FLOPS[k][kernel] + FLOPS[k]["newton_iter"] * iters
             tot += f * p.num_rays()
@@ -250,6 +260,7 @@ def main():
             "kernel": f"k_{dom}", "kernel_ms": dom_ms, "flops_per_launch": flops(dom),
             "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS,
             "forward_ms": fwd_ms, "adjoint_ms": adj_ms, "newton_iters_mean": iters,
+            "adjoint_reuses_exit_roots": roots_reused,
             "search_steps": "mesh cells visited" if args.mesh else "Newton iterations"}
 
     generator = None

@@ -142,7 +142,9 @@ ffrt_status ffrt_plan_destroy(ffrt_plan* plan);
 
 /* Device workspace bytes the plan needs: design descriptors, knot tables, bounds, loss flags and partial
  * sums, a dL/dI buffer for steps, and the accumulators of the trace kernels (a 64-bit fixed-point
- * irradiance image and a gradient buffer, each kept at zero between calls). */
+ * irradiance image and a gradient buffer, each kept at zero between calls).  When the rays of the point and
+ * emitter-grid designs with the exact root and a flat entry face number at most 2^28 (1 GiB at 4 bytes per
+ * ray), the workspace also holds their exit roots for the adjoint of a step (see ffrt_step). */
 ffrt_status ffrt_plan_workspace_size(const ffrt_plan* plan, size_t* bytes);
 
 /* Hand over caller-allocated device workspace (>= the size above, 256-byte aligned) on the current
@@ -174,7 +176,7 @@ ffrt_status ffrt_loss(ffrt_plan* plan, const float* irr, const float* target, fl
 ffrt_status ffrt_loss_f64(ffrt_plan* plan, const float* irr, const float* target, double* loss, void* stream);
 
 /* Pathwise gradient dL/dP^z (packed like Pz) of sum_ij dL_dI_ij I_ij: re-traces every ray (nothing per ray
- * is stored) and back-propagates through splat, screen, refraction and the root (implicit function
+ * is taken from an earlier call) and back-propagates through splat, screen, refraction and the root (implicit function
  * theorem).  dL_dP is overwritten. */
 ffrt_status ffrt_adjoint(ffrt_plan* plan, const float* Pz, const float* dL_dI, float* dL_dP, void* stream);
 
@@ -185,7 +187,9 @@ ffrt_status ffrt_adam(ffrt_plan* plan, float* Pz, const float* dL_dP, float* m, 
 
 /* One optimisation step: forward, loss, adjoint, Adam (all device-side, no host synchronisation).  irr,
  * loss, dL_dI, dL_dP and stats (if not NULL) receive the step's values before the update; Pz, m, v, t are
- * updated.  dL_dI may be NULL, in which case dL/dI is kept in the plan's workspace. */
+ * updated.  dL_dI may be NULL, in which case dL/dI is kept in the plan's workspace.  The forward keeps the
+ * exit root of every point-source ray (exact root, flat entry face; when the workspace holds them) and the
+ * adjoint of the same step starts from it instead of repeating the search of sec. 2.2.1. */
 ffrt_status ffrt_step(ffrt_plan* plan, float* Pz, const float* target, float* irr, float* loss,
                       float* dL_dI, float* dL_dP, float* m, float* v, int32_t* t, ffrt_stats* stats,
                       const ffrt_adam_hparams* hp, void* stream);
@@ -276,13 +280,13 @@ ffrt_status ffrt_plan_get_config(const ffrt_plan* plan, int32_t which, int32_t* 
 
 /* Mean duration (ms) of the forward and the adjoint trace kernel alone, each launched `reps` times back to
  * back between two HIP events recorded on `stream` with the plan's current shapes (the zeroing and bounds
- * kernels of the full calls run once before).  Synchronises the stream.  irr and dL_dP are overwritten
+ * kernels of the full calls run once before), as a step launches them (the adjoint reusing the exit roots).  Synchronises the stream.  irr and dL_dP are overwritten
  * (they accumulate over the repetitions). */
 ffrt_status ffrt_plan_time_kernels(ffrt_plan* plan, const float* Pz, float* irr, const float* dL_dI,
                                    float* dL_dP, int32_t reps, float* fwd_ms, float* adj_ms, void* stream);
 
 /* Time every candidate shape on the caller's buffers (reps launches each, HIP events, synchronises the
- * stream) and keep the fastest for each kernel.  irr and dL_dP are overwritten. */
+ * stream; the adjoint as a step launches it) and keep the fastest for each kernel.  irr and dL_dP are overwritten. */
 ffrt_status ffrt_plan_autotune(ffrt_plan* plan, const float* Pz, float* irr, const float* dL_dI,
                                float* dL_dP, int32_t reps, void* stream);
 

@@ -14,6 +14,7 @@ constexpr int N_SHAPES = 5;           // block shapes: rays per thread 1, 2, 4, 
 constexpr int N_KG = 8;               // kernel groups: bit 0 point source, bit 1 mesh, bit 2 freeform entry
 constexpr int RPT_OF_SHAPE[N_SHAPES] = {1, 2, 4, 8, 16};
 constexpr int NSLOT = 64;             // per-design partial-statistics slots (spreads the counter atomics)
+constexpr size_t ROOTS_CAP = size_t(1) << 30;  // bytes of the per-ray exit-root buffer of a plan, at most
 
 // Ray status codes (same meaning as the public ffrt_trace_rays status).
 enum : int { ST_HIT = 0, ST_MISS_ENTRY = 1, ST_SIDE_WALL = 2, ST_TIR = 3, ST_OFF_SCREEN = 4 };
@@ -49,6 +50,7 @@ struct DesignDev {
     float R0, w0;                    // Schlick R0, initial ray weight 1/N
     // layout
     int64_t cp_off, img_off, n_rays;
+    int64_t root_off;                // first slot of the design's rays in the exit-root buffer (-1: none)
     int32_t kt_u, kt_v;              // float offsets of the knot tables (workspace)
     // Fixed-point scale of the forward's LDS tile: a pixel contribution v (at most RPT w0) is added as the
     // integer rint(v fx_scale), fx_scale = 2^26 / w0, so that one addend stays below 2^31 and a workgroup's
@@ -129,6 +131,10 @@ struct TraceArgs {
     int32_t use_tile;                // forward: LDS footprint tile
     int32_t butterfly;               // adjoint: wave-level reduce-scatter of control-point gradients
     int32_t kind_group;              // 0: collimated designs, 1: point-source designs (bmap covers only these)
+    // Exit roots of the point-source rays of kernel group 1 (exact root, flat entry), one float per ray at
+    // root_off + ray index (-1: no hit).  The forward stores them and the adjoint of the same step reads
+    // them instead of searching again; null: every kernel searches.
+    float* roots;
 };
 
 struct FwdCfg { int shape; int tile; int persistent; const char* name; };

@@ -67,6 +67,8 @@ struct ffrt_plan {
     int max_cp = 0, max_kt = 0, loss_lb = 1, max_spans = 0;
     int64_t total_spans = 0;
     bool has_point = false;  // some design needs the root search (bounds kernel)
+    int64_t root_rays = 0;   // rays of kernel group 1 (point source, exact root, flat entry)
+    bool roots_on = false;   // their exit-root buffer fits the cap and is in the workspace
     int64_t max_img = 0;
     std::vector<float> knots;
     // block maps per shape and source-kind group (designs of the other group get no blocks)
@@ -77,7 +79,7 @@ struct ffrt_plan {
     size_t ws_bytes = 0;
     size_t off_designs = 0, off_bounds = 0, off_sb = 0, off_valid = 0, off_knots = 0, off_bmap = 0, off_slots = 0;
     size_t need = 0;
-    size_t off_lpart = 0, off_img64 = 0, off_gacc = 0, off_dldi = 0, off_mlpoff = 0, off_mlpvec = 0;
+    size_t off_lpart = 0, off_img64 = 0, off_gacc = 0, off_dldi = 0, off_mlpoff = 0, off_mlpvec = 0, off_roots = 0;
     int num_cu = 256;
     int fwd_cfg = 0, adj_cfg = 0;
     hipGraph_t graph = nullptr;
@@ -98,6 +100,7 @@ struct ffrt_plan {
     float* d_dldi() const { return reinterpret_cast<float*>(ws + off_dldi); }
     int64_t* d_mlpoff(int arch) const { return reinterpret_cast<int64_t*>(ws + off_mlpoff) + (size_t)arch * (nd + 1); }
     float* d_mlpvec(int k) const { return reinterpret_cast<float*>(ws + off_mlpvec) + (size_t)k * total_cp; }
+    float* d_roots() const { return roots_on ? reinterpret_cast<float*>(ws + off_roots) : nullptr; }
 };
 
 namespace {
@@ -282,7 +285,8 @@ int grid_for(ffrt_plan* pl, int shape, int kg, int persistent) {
 
 // The forward trace kernel, into the plan's fixed-point image; partial statistics go to the plan's slots
 // when `stats` is set.  The image must be resolved (launch_resolve or the loss) before the next forward.
-ffrt_status launch_forward(ffrt_plan* pl, const float* Pz, bool stats, hipStream_t s) {
+// With `roots` the exit roots of kernel group 1 go to the plan's root buffer (when it has one).
+ffrt_status launch_forward(ffrt_plan* pl, const float* Pz, bool stats, hipStream_t s, bool roots = false) {
     const FwdCfg& c = FWD_CFGS[pl->fwd_cfg];
     for (int kg = 0; kg < N_KG; ++kg) {
         if (pl->nblocks[c.shape][kg] == 0) continue;
@@ -291,13 +295,16 @@ ffrt_status launch_forward(ffrt_plan* pl, const float* Pz, bool stats, hipStream
         A.img64 = pl->d_img64();
         A.slots = stats ? pl->d_slots() : nullptr;
         A.use_tile = c.tile;
+        A.roots = roots && kg == 1 ? pl->d_roots() : nullptr;
         HIP_TRY(pl->ks->forward(A, c.shape, grid_for(pl, c.shape, kg, c.persistent), s));
     }
     return FFRT_OK;
 }
 
-// The adjoint trace kernel, into the plan's gradient accumulator (launch_finish turns it into dL/dP).
-ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hipStream_t s) {
+// The adjoint trace kernel, into the plan's gradient accumulator (launch_finish turns it into dL/dP).  With
+// `roots` the rays of kernel group 1 take their exit roots from the root buffer, which a forward with the
+// same Pz must have filled.
+ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hipStream_t s, bool roots = false) {
     const AdjCfg& c = ADJ_CFGS[pl->adj_cfg];
     for (int kg = 0; kg < N_KG; ++kg) {
         if (pl->nblocks[c.shape][kg] == 0) continue;
@@ -306,6 +313,7 @@ ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hi
         A.dLdI = dLdI;
         A.gacc = pl->d_gacc();
         A.butterfly = c.butterfly;
+        A.roots = roots && kg == 1 ? pl->d_roots() : nullptr;
         HIP_TRY(pl->ks->adjoint(A, c.shape, grid_for(pl, c.shape, kg, c.persistent), s));
     }
     return FFRT_OK;
@@ -324,17 +332,19 @@ ffrt_status run_bounds(ffrt_plan* pl, const float* Pz, hipStream_t s) {
     return FFRT_OK;
 }
 
-ffrt_status run_forward(ffrt_plan* pl, const float* Pz, float* irr, ffrt_stats* stats, hipStream_t s) {
+ffrt_status run_forward(ffrt_plan* pl, const float* Pz, float* irr, ffrt_stats* stats, hipStream_t s,
+                        bool roots = false) {
     if (ffrt_status b = run_bounds(pl, Pz, s)) return b;
-    ffrt_status st = launch_forward(pl, Pz, stats != nullptr, s);
+    ffrt_status st = launch_forward(pl, Pz, stats != nullptr, s, roots);
     if (st) return st;
     HIP_TRY(launch_resolve(pl->d_designs(), pl->nd, pl->loss_lb, pl->d_img64(), irr, Pz, pl->d_slots(), stats, s));
     return FFRT_OK;
 }
 
-ffrt_status run_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, float* dLdP, hipStream_t s) {
+ffrt_status run_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, float* dLdP, hipStream_t s,
+                        bool roots = false) {
     if (ffrt_status b = run_bounds(pl, Pz, s)) return b;
-    if (ffrt_status a = launch_adjoint(pl, Pz, dLdI, s)) return a;
+    if (ffrt_status a = launch_adjoint(pl, Pz, dLdI, s, roots)) return a;
     HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), dLdP, nullptr, no_adam(), s));
     return FFRT_OK;
 }
@@ -350,11 +360,12 @@ ffrt_status run_step(ffrt_plan* pl, float* Pz, const float* target, float* irr, 
                      bool adam_on_P = true) {
     if (!dLdI) dLdI = pl->d_dldi();
     if (ffrt_status b = run_bounds(pl, Pz, s)) return b;
-    ffrt_status st = launch_forward(pl, Pz, stats != nullptr, s);
+    // the adjoint below sees the same Pz: it reuses the forward's exit roots
+    ffrt_status st = launch_forward(pl, Pz, stats != nullptr, s, true);
     if (st) return st;
     HIP_TRY(launch_loss(pl->d_designs(), pl->nd, pl->loss_lb, pl->d_img64(), irr, target, Pz, pl->d_slots(), stats,
                         pl->d_lpart(), loss, dLdI, pl->d_valid(), s));
-    st = launch_adjoint(pl, Pz, dLdI, s);
+    st = launch_adjoint(pl, Pz, dLdI, s, true);
     if (st) return st;
     AdamArgs adam;
     std::memset(&adam, 0, sizeof adam);
@@ -462,6 +473,11 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
         int kt_v = (int)pl->knots.size();
         build_knot_table(pr.lens.q, pr.lens.n_v - pr.lens.q, pl->knots);
         DesignDev d = make_design(pr, cp, img, kt_u, kt_v);
+        d.root_off = -1;
+        if (kind_group(d) == 1) {
+            d.root_off = pl->root_rays;
+            pl->root_rays += d.n_rays;
+        }
         d.sb_off = (int32_t)pl->total_spans;
         pl->total_spans += (int64_t)d.nsu * d.nsv;
         pl->max_spans = std::max(pl->max_spans, d.nsu * d.nsv);
@@ -536,6 +552,11 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
     off = align256(off + 2 * sizeof(int64_t) * (size_t)(n_designs + 1));
     pl->off_mlpvec = off;  // its back-propagation vectors dz3, dh2, dh1
     off = align256(off + sizeof(float) * 3 * (size_t)pl->total_cp);
+    // exit roots of the exact-root point-source rays, reused by the adjoint of a step (at most ROOTS_CAP bytes;
+    // larger plans search again in the adjoint)
+    pl->off_roots = off;
+    pl->roots_on = pl->root_rays > 0 && (size_t)pl->root_rays * sizeof(float) <= ROOTS_CAP;
+    if (pl->roots_on) off = align256(off + sizeof(float) * (size_t)pl->root_rays);
     pl->need = off;
     *out = pl;
     return FFRT_OK;
@@ -860,11 +881,13 @@ ffrt_status ffrt_plan_autotune(ffrt_plan* plan, const float* Pz, float* irr, con
         for (int c = 0; c < n && st == FFRT_OK; ++c) {
             if (which == 0) plan->fwd_cfg = c; else plan->adj_cfg = c;
             // one untimed launch, then reps timed
-            st = which == 0 ? run_forward(plan, Pz, irr, nullptr, s) : run_adjoint(plan, Pz, dL_dI, dL_dP, s);
+            st = which == 0 ? run_forward(plan, Pz, irr, nullptr, s, true)
+                            : run_adjoint(plan, Pz, dL_dI, dL_dP, s, true);
             if (st) break;
             if (hipEventRecord(e0, s) != hipSuccess) { st = hip_fail(hipGetLastError(), "hipEventRecord"); break; }
             for (int r = 0; r < reps && st == FFRT_OK; ++r)
-                st = which == 0 ? run_forward(plan, Pz, irr, nullptr, s) : run_adjoint(plan, Pz, dL_dI, dL_dP, s);
+                st = which == 0 ? run_forward(plan, Pz, irr, nullptr, s, true)
+                                : run_adjoint(plan, Pz, dL_dI, dL_dP, s, true);
             if (st) break;
             hipError_t e = hipEventRecord(e1, s);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -887,15 +910,16 @@ ffrt_status ffrt_plan_time_kernels(ffrt_plan* plan, const float* Pz, float* irr,
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t ev[4];
     for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
-    ffrt_status st = run_forward(plan, Pz, irr, nullptr, s);
-    if (!st) st = run_adjoint(plan, Pz, dL_dI, dL_dP, s);
+    // the kernels as a step launches them: the adjoint reuses the forward's exit roots
+    ffrt_status st = run_forward(plan, Pz, irr, nullptr, s, true);
+    if (!st) st = run_adjoint(plan, Pz, dL_dI, dL_dP, s, true);
     hipError_t e = hipSuccess;
     if (!st) e = hipEventRecord(ev[0], s);
-    for (int r = 0; r < reps && !st && e == hipSuccess; ++r) st = launch_forward(plan, Pz, false, s);
+    for (int r = 0; r < reps && !st && e == hipSuccess; ++r) st = launch_forward(plan, Pz, false, s, true);
     if (!st && e == hipSuccess) e = hipEventRecord(ev[1], s);
     if (!st && e == hipSuccess) e = hipEventRecord(ev[2], s);
     for (int r = 0; r < reps && !st && e == hipSuccess; ++r)
-        st = launch_adjoint(plan, Pz, dL_dI, s);
+        st = launch_adjoint(plan, Pz, dL_dI, s, true);
     if (!st && e == hipSuccess) e = hipEventRecord(ev[3], s);
     if (!st && e == hipSuccess) e = hipEventSynchronize(ev[3]);
     // the timed launches accumulated into the fixed-point image and the gradient accumulator without

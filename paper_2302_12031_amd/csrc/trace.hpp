@@ -868,7 +868,8 @@ struct FwdRay {
 template <int P, int Q, int KIND>
 __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const BoundsDev& B, const float* sP,
                                                 const float* sKu, const float* sKv, const float* sS, int e, int ku,
-                                                int kv, int64_t id) {
+                                                int kv, int64_t id,
+                                                float* tsave = nullptr) {
     FwdRay o;
     o.iters = o.failed = o.nonmono = o.refined = 0;
     o.X = o.Y = o.w = o.t = o.u = o.v = 0.0f;
@@ -884,6 +885,10 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
         r = ray_entry<KIND>(D, e, ku, kv, id);
     }
     o.status = r.status;
+    // exit root for the adjoint of the same step (point sources, exact root, flat entry): -1 when none
+    constexpr bool STORE = POINT && !MESH && !ENTRY;
+    if constexpr (STORE)
+        if (tsave && r.status != ST_HIT) *tsave = -1.0f;
     if (r.status != ST_HIT) return o;
     float t;
     if constexpr (MESH) {
@@ -928,6 +933,8 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
     }
     if constexpr (SEARCH) {
         RootOut R = intersect<P, Q>(D, B, sP, sKu, sKv, sS, r);
+        if constexpr (STORE)
+            if (tsave) *tsave = R.status == ST_HIT ? R.t : -1.0f;
         o.iters = R.iters;
         o.failed = R.failed;
         o.nonmono = R.nonmono;
@@ -967,7 +974,8 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
                                               const float* sKu, const float* sKv, const float* sS,
                                               const float* __restrict__ G,
                                               int e, int ku, int kv, int64_t id, int& cku, int& ckv,
-                                              float* g, int& cku_in, int& ckv_in, float* gin) {
+                                              float* g, int& cku_in, int& ckv_in, float* gin,
+                                              const float* tload = nullptr) {
     constexpr bool point = (KIND & 1) != 0, MESH = (KIND & 2) != 0, ENTRY = (KIND & 4) != 0;
     constexpr bool SEARCH = point || ENTRY;
     EntryHit EH;
@@ -1004,9 +1012,20 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
             mqz = (mup ? C.z11 + A * (ma - 1.0f) + Bs * (mb - 1.0f) : C.z00 + A * ma + Bs * mb) + B.zref;
         }
     } else if constexpr (SEARCH) {
-        RootOut R = intersect<P, Q>(D, B, sP, sKu, sKv, sS, r);
-        if (R.status != ST_HIT) return false;
-        t = R.t;
+        bool found = false;
+        if constexpr (!ENTRY) {
+            // the exit root the forward of this step stored (-1: no hit), instead of searching again
+            if (tload) {
+                t = *tload;
+                if (!(t >= 0.0f)) return false;
+                found = true;
+            }
+        }
+        if (!found) {
+            RootOut R = intersect<P, Q>(D, B, sP, sKu, sKv, sS, r);
+            if (R.status != ST_HIT) return false;
+            t = R.t;
+        }
     }
     float qx = r.ox + t * r.dx, qy = r.oy + t * r.dy;
     SurfEval<P, Q, float> S;
@@ -1320,7 +1339,10 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
             Y[r] = 0.0f;
             if (ku < D.grid_u && kv < D.grid_v) {
                 int64_t id = ebase + (int64_t)ku * D.grid_v + kv;
-                FwdRay o = trace_forward<P, Q, KIND>(D, B, sP, sKu, sKv, sSb, e, ku, kv, id);
+                float* ts = nullptr;
+                if constexpr (KIND == 1)
+                    if (A.roots) ts = A.roots + D.root_off + id;
+                FwdRay o = trace_forward<P, Q, KIND>(D, B, sP, sKu, sKv, sSb, e, ku, kv, id, ts);
                 c_tr++;
                 c_fail += o.failed;
                 c_ref += o.refined;
@@ -1603,8 +1625,11 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
             float g[NT], gin[ENTRY ? NT : 1];
             int cku = -1, ckv = -1, cku_in = -1, ckv_in = -1;
             int64_t id = ebase + (int64_t)ku * D.grid_v + kv;
+            const float* tl = nullptr;
+            if constexpr (KIND == 1)
+                if (A.roots) tl = A.roots + D.root_off + id;
             if (!trace_adjoint<P, Q, NU, KIND>(D, B, sP, sKu, sKv, sSb, G, e, ku, kv, id, cku, ckv, g, cku_in, ckv_in,
-                                               gin))
+                                               gin, tl))
                 continue;
             if (aku >= 0 && (cku != aku || ckv != akv)) {
                 cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc);
