@@ -46,7 +46,9 @@ def test_step_with_reused_roots_matches_separate_calls(name):
     p = wl.problems[0]
     _, g64, _, _ = O.grad(p, wl.Pz[0], wl.targets[0])
     gs = st["dLdP"].cpu().numpy().reshape(g64.shape)
-    assert np.abs(gs - g64).max() <= 1e-3 * np.abs(g64).max()
+    e = np.abs(gs - g64).max() / np.abs(g64).max()
+    _say(f"[roots] {name}: step gradient vs FP64 oracle {e:.3g} of max |g|")
+    assert e <= 1e-3
 
 
 def test_graph_replay_with_reused_roots_matches_eager_steps():
