@@ -146,3 +146,37 @@ def test_mlp_layout_packs_each_design_generator():
     assert list(off) == [0] + np.cumsum([2 * C * K + 4 * K for K, C in zip(Ks, Cs)]).tolist()
     assert ffrt.lib().ffrt_mlp_layout(h, 2, off) != 0
     ffrt.lib().ffrt_plan_destroy(h)
+
+
+def _workspace(problems):
+    h = ffrt.create_plan_handle(problems)
+    sz = ctypes.c_size_t()
+    assert ffrt.lib().ffrt_plan_workspace_size(h, ctypes.byref(sz)) == 0
+    assert ffrt.lib().ffrt_plan_destroy(h) == 0
+    return sz.value
+
+
+def test_workspace_holds_exit_roots_of_exact_root_point_rays_up_to_the_cap():
+    """4 bytes per ray of point / emitter-grid designs with the exact root and a flat entry face, kept for the
+    adjoint of a step while they total at most 1 GiB; collimated, mesh and two-face designs add nothing."""
+    align = lambda b: (b + 255) // 256 * 256
+    on_mesh = lambda p: replace(p, options=replace(p.options, mesh_u=2, mesh_v=2))
+    collimated = lambda p: replace(p, source=replace(p.source, kind=0))  # same grid of samples, no search
+    pt = W.point_problem(300, 12, 64, seed=6)
+    grid = W.point_problem(64, 9, 48, seed=8, emitters=3, emit_w=1.0)
+    col = W.collimated_problem(200, 8, 48, jitter=1, seed=5)
+    # the same designs on the triangle mesh keep no roots: the difference is exactly the aligned root block
+    for probs in ([pt], [pt, grid], [grid, col, pt]):
+        n = sum(p.num_rays() for p in probs if p.source.kind != 0)
+        meshed = [on_mesh(p) if p.source.kind != 0 else p for p in probs]
+        assert _workspace(probs) - _workspace(meshed) == align(4 * n)
+    # a point source behind a freeform entry face keeps none either (it searches both faces)
+    two = replace(pt, lens=replace(pt.lens, entry_freeform=1))
+    assert _workspace([two]) == _workspace([collimated(two)])
+    assert _workspace([pt]) - _workspace([collimated(pt)]) == align(4 * pt.num_rays())
+    # the cap: 2^28 rays take 1 GiB of roots, 2^28 + 2^14 rays none
+    big = W.point_problem(16384, 12, 64, seed=6)
+    bigger = replace(big, source=replace(big.source, grid_u=16385))
+    assert big.num_rays() == 1 << 28
+    assert _workspace([big]) - _workspace([on_mesh(big)]) == 1 << 30
+    assert _workspace([bigger]) == _workspace([on_mesh(bigger)])
