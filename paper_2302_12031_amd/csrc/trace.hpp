@@ -9,7 +9,8 @@
 //   - forward: rays are traced into registers, the workgroup reduces the pixel footprint of the block and,
 //     when it fits, splats into a privatised LDS tile that is merged into HBM with one global atomic per
 //     touched pixel;
-//   - adjoint: every ray is re-traced, dL/dI is gathered over its filter window, the reverse sweep gives
+//   - adjoint: every ray is re-traced (inside a step, point-source rays start from the exit root the forward
+//     stored), dL/dI is gathered over its filter window, the reverse sweep gives
 //     dL/dP for the (P+1)(Q+1) control points of the hit span, reduced across the wave when all its lanes
 //     share the span, and accumulated in a privatised LDS copy of the control net.
 #pragma once
@@ -966,7 +967,8 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
 
 // ------------------------------------------------------------------------------------------------
 // One ray, adjoint: re-trace, gather dL/dI over the filter window, reverse sweep.  Returns false when the
-// ray does not reach the screen.  g[] receives dL/dP for control point (ku + a, kv + b) at a * (Q+1) + b;
+// ray does not reach the screen.  With tload (point sources, exact root, flat entry) the exit root comes from
+// the forward of the same step instead of the search.  g[] receives dL/dP for control point (ku + a, kv + b) at a * (Q+1) + b;
 // with a freeform entry face gin[] receives dL/dP of the entry net's points (cku_in + a, ckv_in + b).
 // ------------------------------------------------------------------------------------------------
 template <int P, int Q, int NU, int KIND>
