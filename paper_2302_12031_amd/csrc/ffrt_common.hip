@@ -244,14 +244,30 @@ __global__ __launch_bounds__(256) void k_loss_grad(const DesignDev* designs, int
                                                    float* loss, int32_t* valid, float* dLdI) {
     const int d = blockIdx.x / LB, b = blockIdx.x - d * LB;
     const DesignDev& D = designs[d];
+    int64_t lo, hi;
+    image_slice(D, LB, b, lo, hi);
+    // the slice's first pixels (all of them up to 1024 per slice) are loaded before the slice sums are
+    // added up, so that both sets of loads overlap
+    constexpr int PF = 4;
+    const int64_t base = D.img_off + lo + threadIdx.x, end = D.img_off + hi;
+    float I[PF], T[PF];
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+        const int64_t i = base + (int64_t)k * blockDim.x;
+        I[k] = i < end ? irr[i] : 0.0f;
+        T[k] = i < end ? target[i] : 0.0f;
+    }
     const LossOut R = loss_from_partials(partial, d, LB, D);
     if (b == 0 && threadIdx.x == 0) {
         loss[d] = R.loss;
         valid[d] = R.valid;
     }
-    int64_t lo, hi;
-    image_slice(D, LB, b, lo, hi);
-    for (int64_t i = D.img_off + lo + threadIdx.x; i < D.img_off + hi; i += blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+        const int64_t i = base + (int64_t)k * blockDim.x;
+        if (i < end) dLdI[i] = ((I[k] * R.L.is - T[k] * R.L.isT) - R.L.dot) * R.L.coef;
+    }
+    for (int64_t i = base + (int64_t)PF * blockDim.x; i < end; i += blockDim.x) {
         const float Dv = irr[i] * R.L.is - target[i] * R.L.isT;
         dLdI[i] = (Dv - R.L.dot) * R.L.coef;
     }

@@ -15,18 +15,33 @@ namespace ffrt {
 template <class GradAt>
 __device__ inline void adam_update(float* Pz, float* m, float* v, int32_t* t, int64_t off, int n,
                                    const ffrt_adam_hparams& hp, GradAt g) {
+    // The thread's first point is loaded before the step counter, so that its loads overlap the counter's
+    // and the bias corrections instead of waiting for them.
+    const int i0 = threadIdx.x;
+    const bool first = i0 < n;
+    float g0 = 0.0f, m0 = 0.0f, v0 = 0.0f, p0 = 0.0f;
+    if (first) {
+        g0 = g(i0);
+        m0 = m[off + i0];
+        v0 = v[off + i0];
+        p0 = Pz[off + i0];
+    }
     const int tn = t[0] + 1;
     const float bc1 = 1.0f - powf(hp.beta1, (float)tn);
     const float bc2 = 1.0f - powf(hp.beta2, (float)tn);
     const float step = hp.lr / bc1, rb2 = 1.0f / sqrtf(bc2);
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int64_t k = off + i;
-        const float gi = g(i);
-        const float mi = hp.beta1 * m[k] + (1.0f - hp.beta1) * gi;
-        const float vi = hp.beta2 * v[k] + (1.0f - hp.beta2) * gi * gi;
+    auto update = [&](int64_t k, float gi, float mk, float vk, float pk) {
+        const float mi = hp.beta1 * mk + (1.0f - hp.beta1) * gi;
+        const float vi = hp.beta2 * vk + (1.0f - hp.beta2) * gi * gi;
         m[k] = mi;
         v[k] = vi;
-        Pz[k] -= step * mi / (sqrtf(vi) * rb2 + hp.eps);
+        Pz[k] = pk - step * mi / (sqrtf(vi) * rb2 + hp.eps);
+    };
+    if (first) update(off + i0, g0, m0, v0, p0);
+    for (int i = i0 + (int)blockDim.x; i < n; i += blockDim.x) {
+        const int64_t k = off + i;
+        const float gi = g(i);
+        update(k, gi, m[k], v[k], Pz[k]);
     }
     __syncthreads();
     if (threadIdx.x == 0) t[0] = tn;
