@@ -196,11 +196,19 @@ __global__ __launch_bounds__(256) void k_resolve(const DesignDev* designs, int L
 
 // Slice sums of the loss of sec. 2.5 (sum I, sum T, sum I^2, sum I T, sum T^2 in double precision) of
 // slice b of design d, resolving the fixed-point irradiance first when img64 is given.  No workgroup waits
-// for another: the consumers (k_loss_grad, the adjoint) each add up the LB slices themselves.
-__global__ __launch_bounds__(256) void k_loss_sums(const DesignDev* designs, int LB, unsigned long long* img64,
-                                                   float* irr, const float* __restrict__ target, const float* Pz,
+// for another: the consumers (k_loss_grad, the adjoint) each add up the LB slices themselves.  With stats,
+// n_designs more workgroups after the slices reduce each design's statistics, beside the slices rather than
+// after one of them.
+__global__ __launch_bounds__(256) void k_loss_sums(const DesignDev* designs, int n_designs, int LB,
+                                                   unsigned long long* img64, float* irr,
+                                                   const float* __restrict__ target, const float* Pz,
                                                    ffrt_stats* slots, ffrt_stats* stats, double* partial) {
     __shared__ double sh[4][LOSS_Q];
+    if ((int)blockIdx.x >= n_designs * LB) {
+        const int d = blockIdx.x - n_designs * LB;
+        reduce_slots(d, designs[d], Pz, slots, stats);
+        return;
+    }
     const int d = blockIdx.x / LB, b = blockIdx.x - d * LB;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const DesignDev& D = designs[d];
@@ -235,7 +243,6 @@ __global__ __launch_bounds__(256) void k_loss_sums(const DesignDev* designs, int
         const int k = threadIdx.x;
         partial[((size_t)d * LB + b) * LOSS_Q + k] = ((sh[0][k] + sh[1][k]) + sh[2][k]) + sh[3][k];
     }
-    if (stats && b == 0) reduce_slots(d, D, Pz, slots, stats);
 }
 
 // dL/dI of slice b of design d; workgroup 0 also stores the loss value and the validity flag.
@@ -386,8 +393,8 @@ hipError_t launch_resolve(const DesignDev* designs, int n_designs, int LB, unsig
 hipError_t launch_loss(const DesignDev* designs, int n_designs, int LB, unsigned long long* img64, float* irr,
                        const float* target, const float* Pz, ffrt_stats* slots, ffrt_stats* stats, double* partial,
                        float* loss, float* dLdI, int32_t* valid, hipStream_t s) {
-    hipLaunchKernelGGL(k_loss_sums, dim3(n_designs * LB), dim3(256), 0, s, designs, LB, img64, irr, target, Pz, slots,
-                       stats, partial);
+    hipLaunchKernelGGL(k_loss_sums, dim3(n_designs * LB + (stats ? n_designs : 0)), dim3(256), 0, s, designs,
+                       n_designs, LB, img64, irr, target, Pz, slots, stats, partial);
     hipLaunchKernelGGL(k_loss_grad, dim3(n_designs * LB), dim3(256), 0, s, designs, LB, irr, target, partial, loss,
                            valid, dLdI);
     return hipGetLastError();
