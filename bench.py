@@ -107,6 +107,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "tophat", "tophat64"])
     ap.add_argument("--generator", default="none", choices=["none", "dense", "sparse"])
+    ap.add_argument("--rays-side", type=int, default=0,
+                    help="rays (collimated) or strata (point sources) per axis, per emitter, instead of the "
+                         "workload's own count (c2, c3, c4): the same geometry at another size")
     ap.add_argument("--entry-freeform", action="store_true",
                     help="make the entry face a second freeform B-spline (both nets optimised)")
     ap.add_argument("--mesh", type=int, default=0,
@@ -146,6 +149,10 @@ def main():
         wl = W.tophat()
     elif args.workload == "tophat64":
         wl = W.tophat(rays_side=1024, cps_side=64, det_side=128)
+    elif args.rays_side:
+        if args.workload not in ("c2", "c3", "c4"):
+            sys.exit("--rays-side applies to c2, c3 and c4")
+        wl = W.WORKLOADS[args.workload](args.rays_side)
     else:
         wl = W.WORKLOADS[args.workload]()
     if args.mesh:
@@ -255,8 +262,9 @@ def main():
     achieved = flops(dom) / (dom_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            # HBM counters were taken on the exact-root, flat-entry kernels of the named workloads
-            "traffic": None if (args.mesh or args.entry_freeform) else _traffic(f"k_{dom}", args.workload),
+            # HBM counters were taken on the exact-root, flat-entry kernels of the named workloads at their own sizes
+            "traffic": None if (args.mesh or args.entry_freeform or args.rays_side)
+            else _traffic(f"k_{dom}", args.workload),
             "kernel": f"k_{dom}", "kernel_ms": dom_ms, "flops_per_launch": flops(dom),
             "frac_of_packed_peak": achieved / PEAK_FP32_PACKED_TFLOPS,
             "forward_ms": fwd_ms, "adjoint_ms": adj_ms, "newton_iters_mean": iters,
