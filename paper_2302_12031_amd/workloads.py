@@ -116,8 +116,15 @@ def rng(seed: int, stream: int) -> np.random.Generator:
     return np.random.default_rng([int(seed), int(stream)])
 
 
+def single(a) -> np.ndarray:
+    """The values rounded to single precision (returned as float64): the device path takes its inputs in
+    single precision, so every generated input is representable there and both the device and the
+    double-precision checks see exactly the same lens and target."""
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
 def random_heights(n_u: int, n_v: int, seed: int, base: float = 2.0, spread: float = 0.2) -> np.ndarray:
-    return base + rng(seed, STREAM_PZ).uniform(-spread, spread, size=(n_u, n_v))
+    return single(base + rng(seed, STREAM_PZ).uniform(-spread, spread, size=(n_u, n_v)))
 
 
 def _pixel_centres(n: int, R: float) -> np.ndarray:
@@ -156,7 +163,7 @@ def target_mixture(prob: Problem, seed: int, n_min=3, n_max=3, rectangle=False) 
         ys = np.sort(g.uniform(-0.6 * d.R_y, 0.6 * d.R_y, 2))
         img = img / img.max() + 0.5 * ((cx >= xs[0]) & (cx <= xs[1]) & (cy >= ys[0]) & (cy <= ys[1]))
         img = _blur(img, 1.0)
-    return img / img.sum()
+    return single(img / img.sum())
 
 
 # --------------------------------------------------------------------------------------------------
@@ -244,7 +251,7 @@ def circular_tophat(prob: Problem, radius: float) -> np.ndarray:
     d = prob.detector
     cx, cy = _pixel_centres(nx, d.R_x)[:, None], _pixel_centres(ny, d.R_y)[None, :]
     img = ((cx ** 2 + cy ** 2) <= radius ** 2).astype(np.float64)
-    return img / img.sum()
+    return single(img / img.sum())
 
 
 def tophat(rays_side=512, cps_side=16, det_side=64) -> Workload:
@@ -286,6 +293,6 @@ def with_entry_freeform(wl: Workload, seed: int = 11, base: float = 0.5, spread:
     probs, Pz = [], []
     for d, (p, P) in enumerate(zip(wl.problems, wl.Pz)):
         probs.append(replace(p, lens=replace(p.lens, entry_freeform=1)))
-        entry = p.lens.z_in + base + rng(seed + d, STREAM_PZ).uniform(-spread, spread, size=P.shape)
+        entry = single(p.lens.z_in + base + rng(seed + d, STREAM_PZ).uniform(-spread, spread, size=P.shape))
         Pz.append(np.stack([P, entry]))
     return Workload(f"{wl.name}-twofaces", probs, Pz, wl.targets)
