@@ -382,18 +382,24 @@ bool find_entry_root(const Geo& g, const double* Pz_in, const double* s, const d
     if (!(a <= b)) { *margin = 0.0; return false; }
     double fa = f_in_of_t(g, Pz_in, s, d0, a), fb = f_in_of_t(g, Pz_in, s, d0, b);
     *margin = std::min(std::fabs(fa), std::fabs(fb));
-    if (fa < 0.0 || fb > 0.0) return false;  // entered the prism above the face, or left it below
+    if (fa < 0.0) return false;  // entered the prism above the face (through the side wall)
     bool monotone = g.Gx_in * std::fabs(d0[0]) + g.Gy_in * std::fabs(d0[1]) < d0[2];
-    if (!monotone) {
+    if (monotone) {
+        if (fb > 0.0) return false;  // left the prism below the face: passed the lens
+    } else {
+        // the first sign change (a ray that crossed the face and met it again before leaving the prism has
+        // its smallest root in between); none at any sample: the ray passed the lens
         double du = std::fabs(d0[0]) * (b - a) / (2.0 * g.pr.r_x) * (g.nu - g.p);
         double dv = std::fabs(d0[1]) * (b - a) / (2.0 * g.pr.r_y) * (g.nv - g.q);
         int64_t M = std::max<int64_t>(64, int64_t(std::ceil(64.0 * (du + dv))) + 1);
         double prev = a;
+        bool found = false;
         for (int64_t k = 1; k <= M; ++k) {
             double t = a + (b - a) * double(k) / double(M);
-            if (f_in_of_t(g, Pz_in, s, d0, t) <= 0.0) { b = t; a = prev; break; }
+            if (f_in_of_t(g, Pz_in, s, d0, t) <= 0.0) { b = t; a = prev; found = true; break; }
             prev = t;
         }
+        if (!found) return false;
     }
     for (int it = 0; it < 200 && (b - a) > 1e-11 * (1.0 + b); ++it) {
         double m = 0.5 * (a + b);
@@ -547,19 +553,26 @@ Root find_root(const Geo& g, const double* Pz, const Entry& E, bool ignore_apert
     if (t_end < t_lo) { R.status = ORC_SIDE_WALL; R.margin = (t_lo - t_end) * d[2]; return R; }
     double f_end = f_of_t(g, Pz, E, t_end);
     if (t_ap <= t_hi) R.margin = std::fabs(f_end);
-    if (f_end > 0.0) { R.status = ORC_SIDE_WALL; return R; }
     double a = t_lo, b = t_end;
     bool monotone = g.Gx * std::fabs(d[0]) + g.Gy * std::fabs(d[1]) < d[2];
-    if (!monotone) {
+    if (monotone) {
+        // f strictly decreasing: still below the surface where the ray leaves the aperture means no root
+        if (f_end > 0.0) { R.status = ORC_SIDE_WALL; return R; }
+    } else {
+        // the first sign change; a ray that crossed the surface and met it again before leaving the aperture
+        // (f back above zero at t_end) has its smallest root in between, and only a ray that stays below the
+        // surface at every sample leaves through the side wall
         double du = std::fabs(d[0]) * (t_end - t_lo) / (2.0 * g.pr.r_x) * (g.nu - g.p);
         double dv = std::fabs(d[1]) * (t_end - t_lo) / (2.0 * g.pr.r_y) * (g.nv - g.q);
         int64_t M = std::max<int64_t>(64, int64_t(std::ceil(64.0 * (du + dv))) + 1);
         double prev = t_lo;
+        bool found = false;
         for (int64_t k = 1; k <= M; ++k) {
             double t = t_lo + (t_end - t_lo) * double(k) / double(M);
-            if (f_of_t(g, Pz, E, t) <= 0.0) { a = prev; b = t; break; }
+            if (f_of_t(g, Pz, E, t) <= 0.0) { a = prev; b = t; found = true; break; }
             prev = t;
         }
+        if (!found) { R.status = ORC_SIDE_WALL; return R; }
     }
     // Bisection: f(a) > 0 >= f(b).
     for (int it = 0; it < 200 && (b - a) > 1e-11 * (1.0 + b); ++it) {

@@ -331,6 +331,99 @@ def test_rng_uniformity_and_streams():
     assert O.rng(7, 2, 5) != O.rng(7, 3, 5) and O.rng(7, 2, 5) != O.rng(8, 2, 5)
 
 
+def test_splitmix64_matches_the_published_outputs():
+    """The counter-based generator against the reference implementation's outputs for seed 0."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "splitmix64_seed0.txt")
+    ref = [int(l, 16) for l in open(path) if l.strip() and not l.startswith("#")]
+    assert [O.rng(0, 0, i) for i in range(len(ref))] == ref
+
+
+@pytest.mark.parametrize("jitter", [0, 1])
+def test_collimated_samples_one_per_cell(jitter):
+    """Collimated samples (sec. 2.2.1): cell (k_u, k_v) of the N_u x N_v grid holds exactly one sample, at the
+    cell centre ((k + 1/2) / N) without jitter, anywhere inside it with jitter, with 24-bit sub-cell offsets
+    (so that single precision represents the sample exactly)."""
+    pr = replace(W.c1().problems[0], source=replace(W.c1().problems[0].source, grid_u=24, grid_v=16, jitter=jitter,
+                                                                                 seed=3))
+    ids = np.arange(24 * 16)
+    S = O.samples(pr, ids)
+    ku, kv = ids // 16, ids % 16
+    fu, fv = S[:, 0] * 24 - ku, S[:, 1] * 16 - kv
+    if jitter:
+        assert (fu >= 0).all() and (fu < 1).all() and (fv >= 0).all() and (fv < 1).all()
+        for f in (fu, fv):
+            np.testing.assert_array_equal(f * 2 ** 24, np.round(f * 2 ** 24))
+            assert abs(f.mean() - 0.5) < 0.05 and len(set(f.tolist())) == len(f)
+    else:
+        np.testing.assert_array_equal(fu, 0.5)
+        np.testing.assert_array_equal(fv, 0.5)
+    assert (S[:, 0] * 24).astype(int).tolist() == ku.tolist() and (S[:, 1] * 16).astype(int).tolist() == kv.tolist()
+
+
+def _valley(c0=2.0, kappa=0.5, n_u=8, n_v=4, p=3, r=5.0):
+    """Control heights that make the bicubic B-spline exactly h(x, y) = c0 + kappa x^2: with X linear
+    (X = (2u - 1) r), h is a quadratic g(u) = A + B u + C u^2 of u, reproduced by the control points given by its
+    polar form at the Greville knots: c_i = A + B s1_i / p + C s2_i / binom(p, 2), s1, s2 the first and second
+    elementary symmetric functions of the knots u_{i+1} .. u_{i+p} (Marsden's identity)."""
+    A, B, C = c0 + kappa * r * r, -4.0 * kappa * r * r, 4.0 * kappa * r * r
+    U = O.knots(p, n_u)
+    cps = []
+    for i in range(n_u):
+        k = U[i + 1:i + p + 1]
+        s1 = k.sum()
+        s2 = sum(k[a] * k[b] for a in range(p) for b in range(a + 1, p))
+        cps.append(A + B * s1 / p + C * s2 / (p * (p - 1) / 2))
+    return np.repeat(np.array(cps)[:, None], n_v, axis=1)
+
+
+def test_smallest_root_of_rays_that_cross_the_surface_twice():
+    """The root problem of sec. 2.2.1 asks for the smallest positive root.  On the valley h = 2 + x^2 / 2 (an
+    exact B-spline, checked first) rays from a wide cone cross the exit face, leave the glass and meet the
+    rising wall again: f(t) = h(o + t d) - o_z - t d_z is a quadratic in t with two positive roots inside the
+    aperture, known in closed form.  The oracle must return the smaller one (its scan for the first sign
+    change), for every ray whose two roots are not within rounding of each other."""
+    pr = W.Problem(lens=W.Lens(n_u=8, n_v=4),
+                   source=W.Source(kind=W.POINT, grid_u=64, grid_v=64, jitter=1, pos=(-4.0, 0.0, -1.0),
+                                   half_angle=np.deg2rad(70.0), seed=4),
+                   detector=W.Detector(n_x=32, n_y=32, R_x=200.0, R_y=200.0, z_screen=40.0))
+    Pz = _valley()
+    xs = np.linspace(-5, 5, 23)
+    for x in xs:
+        for y in (-4.0, 0.3, 4.9):
+            np.testing.assert_allclose(O.surface(pr, Pz, x, y)[0], 2.0 + 0.5 * x * x, rtol=0, atol=1e-12)
+    ids = np.arange(pr.num_rays())
+    o, d = _glass_rays(pr, ids)
+    out = O.trace_rays(pr, Pz, ids)
+    # f(t) = a t^2 + b t + c
+    a = 0.5 * d[:, 0] ** 2
+    b = d[:, 0] * o[:, 0] - d[:, 2]
+    c = 2.0 + 0.5 * o[:, 0] ** 2 - o[:, 2]
+    disc = b * b - 4 * a * c
+    ok = (disc > 0) & (a > 0)
+    sq = np.sqrt(np.where(ok, disc, 0.0))
+    t1 = np.where(ok, (-b - sq) / (2 * a), np.nan)
+    t2 = np.where(ok, (-b + sq) / (2 * a), np.nan)
+    # where the ray leaves the aperture prism
+    with np.errstate(divide="ignore", invalid="ignore"):
+        tx = np.where(d[:, 0] > 0, (5 - o[:, 0]) / d[:, 0], np.where(d[:, 0] < 0, (-5 - o[:, 0]) / d[:, 0], np.inf))
+        ty = np.where(d[:, 1] > 0, (5 - o[:, 1]) / d[:, 1], np.where(d[:, 1] < 0, (-5 - o[:, 1]) / d[:, 1], np.inf))
+    t_ap = np.minimum(tx, ty)
+    entered = out[:, 0] != O.MISS_ENTRY
+    # both roots inside the aperture and further apart than the oracle's scan step (1/64 of a projected
+    # knot span, at most ~0.07 here): the scan must stop at the first
+    two = entered & ok & (t1 > 0) & (t2 < t_ap - 1e-6) & (t2 - t1 > 0.2)
+    assert two.sum() >= 200, two.sum()
+    assert (out[two, 0] != O.SIDE_WALL).all()
+    np.testing.assert_allclose(out[two, 6], t1[two], rtol=0, atol=1e-9)
+    # rays with a single crossing inside the aperture find it too
+    one = entered & ok & (t1 > 0) & (t1 < t_ap - 1e-6) & (t2 > t_ap + 1e-6)
+    assert one.sum() >= 200, one.sum()
+    np.testing.assert_allclose(out[one, 6], t1[one], rtol=0, atol=1e-9)
+    # and rays that stay below the surface until they leave the aperture go through the side wall
+    none = entered & (~ok | (t1 > t_ap + 1e-6)) & (t_ap > 0)
+    assert none.sum() >= 100 and (out[none, 0] == O.SIDE_WALL).all()
+
+
 def test_grid_source_emitters_include_endpoints():
     pr = W.c4(8, 3).problems[0]
     per = 64
