@@ -248,7 +248,7 @@ __global__ __launch_bounds__(256) void k_loss_sums(const DesignDev* designs, int
 // dL/dI of slice b of design d; workgroup 0 also stores the loss value and the validity flag.
 __global__ __launch_bounds__(256) void k_loss_grad(const DesignDev* designs, int LB, const float* __restrict__ irr,
                                                    const float* __restrict__ target, const double* partial,
-                                                   float* loss, int32_t* valid, float* dLdI) {
+                                                   float* loss, int32_t* valid, float* dLdI, uint32_t* gmax) {
     const int d = blockIdx.x / LB, b = blockIdx.x - d * LB;
     const DesignDev& D = designs[d];
     int64_t lo, hi;
@@ -269,28 +269,60 @@ __global__ __launch_bounds__(256) void k_loss_grad(const DesignDev* designs, int
         loss[d] = R.loss;
         valid[d] = R.valid;
     }
+    float gm = 0.0f;  // max |dL/dI| over the thread's pixels
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
         const int64_t i = base + (int64_t)k * blockDim.x;
-        if (i < end) dLdI[i] = ((I[k] * R.L.is - T[k] * R.L.isT) - R.L.dot) * R.L.coef;
+        if (i < end) {
+            const float g = ((I[k] * R.L.is - T[k] * R.L.isT) - R.L.dot) * R.L.coef;
+            dLdI[i] = g;
+            gm = fmaxf(gm, fabsf(g));
+        }
     }
     for (int64_t i = base + (int64_t)PF * blockDim.x; i < end; i += blockDim.x) {
         const float Dv = irr[i] * R.L.is - target[i] * R.L.isT;
-        dLdI[i] = (Dv - R.L.dot) * R.L.coef;
+        const float g = (Dv - R.L.dot) * R.L.coef;
+        dLdI[i] = g;
+        gm = fmaxf(gm, fabsf(g));
+    }
+    if (gmax) {
+        // the cotangent bound of the adjoint's fixed-point unit: the largest |dL/dI| of the design, as float
+        // bits (ordered like the values, being non-negative); kept at zero between steps by the finishing kernel
+        gm = wave_reduce(gm, [](float a, float b) { return fmaxf(a, b); });
+        if ((threadIdx.x & 63) == 0 && gm > 0.0f) atomicMax(gmax + d, __builtin_bit_cast(uint32_t, gm));
     }
 }
 
-// One workgroup per design after the adjoint: dL/dP from the accumulator (which is cleared for the next
-// adjoint) and, when asked, Adam for the designs whose loss found flux.
-__global__ __launch_bounds__(256) void k_finish(const DesignDev* designs, float* gacc, float* dLdP,
-                                                const int32_t* valid, AdamArgs adam) {
+// The adjoint's cotangent bound of design blockIdx.x from the dL/dI it is given: max |dL/dI| (float bits).
+__global__ __launch_bounds__(256) void k_gscale(const DesignDev* designs, const float* __restrict__ dLdI,
+                                                uint32_t* gmax) {
+    __shared__ float sh[4];
+    const DesignDev& D = designs[blockIdx.x];
+    const int64_t n = (int64_t)D.nx * D.ny;
+    const float* G = dLdI + D.img_off;
+    float m = 0.0f;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, fabsf(G[i]));
+    m = wave_reduce(m, [](float a, float b) { return fmaxf(a, b); });
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) sh[wave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) gmax[blockIdx.x] = __builtin_bit_cast(uint32_t, fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3])));
+}
+
+// One workgroup per design after the adjoint: dL/dP from the fixed-point accumulator (which is cleared for
+// the next adjoint, as is the cotangent bound) and, when asked, Adam for the designs whose loss found flux.
+__global__ __launch_bounds__(256) void k_finish(const DesignDev* designs, unsigned long long* gacc, uint32_t* gmax,
+                                                float* dLdP, const int32_t* valid, AdamArgs adam) {
     const int d = blockIdx.x;
     const DesignDev& D = designs[d];
-    float* acc = gacc + D.cp_off;
+    unsigned long long* acc = gacc + D.cp_off;
     float* out = dLdP + D.cp_off;
-    auto take = [acc, out](int i) {
-        const float g = acc[i];
-        acc[i] = 0.0f;
+    const double unit = ldexp(1.0, fixed_point_exponent(gmax[d], D.w0));
+    __syncthreads();
+    if (threadIdx.x == 0) gmax[d] = 0u;
+    auto take = [acc, out, unit](int i) {
+        const float g = (float)((double)(long long)acc[i] * unit);
+        acc[i] = 0ull;
         out[i] = g;
         return g;
     };
@@ -392,17 +424,22 @@ hipError_t launch_resolve(const DesignDev* designs, int n_designs, int LB, unsig
 
 hipError_t launch_loss(const DesignDev* designs, int n_designs, int LB, unsigned long long* img64, float* irr,
                        const float* target, const float* Pz, ffrt_stats* slots, ffrt_stats* stats, double* partial,
-                       float* loss, float* dLdI, int32_t* valid, hipStream_t s) {
+                       float* loss, float* dLdI, int32_t* valid, uint32_t* gmax, hipStream_t s) {
     hipLaunchKernelGGL(k_loss_sums, dim3(n_designs * LB + (stats ? n_designs : 0)), dim3(256), 0, s, designs,
                        n_designs, LB, img64, irr, target, Pz, slots, stats, partial);
     hipLaunchKernelGGL(k_loss_grad, dim3(n_designs * LB), dim3(256), 0, s, designs, LB, irr, target, partial, loss,
-                           valid, dLdI);
+                       valid, dLdI, gmax);
     return hipGetLastError();
 }
 
-hipError_t launch_finish(const DesignDev* designs, int n_designs, float* gacc, float* dLdP, const int32_t* valid,
-                         const AdamArgs& adam, hipStream_t s) {
-    hipLaunchKernelGGL(k_finish, dim3(n_designs), dim3(256), 0, s, designs, gacc, dLdP, valid, adam);
+hipError_t launch_gscale(const DesignDev* designs, int n_designs, const float* dLdI, uint32_t* gmax, hipStream_t s) {
+    hipLaunchKernelGGL(k_gscale, dim3(n_designs), dim3(256), 0, s, designs, dLdI, gmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const DesignDev* designs, int n_designs, unsigned long long* gacc, uint32_t* gmax,
+                         float* dLdP, const int32_t* valid, const AdamArgs& adam, hipStream_t s) {
+    hipLaunchKernelGGL(k_finish, dim3(n_designs), dim3(256), 0, s, designs, gacc, gmax, dLdP, valid, adam);
     return hipGetLastError();
 }
 

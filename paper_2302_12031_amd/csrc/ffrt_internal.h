@@ -127,7 +127,10 @@ struct TraceArgs {
     unsigned long long* img64;       // forward: fixed-point irradiance accumulator (zero on entry)
     ffrt_stats* slots;               // forward: NSLOT partial-statistics slots per design (may be null)
     const float* dLdI;               // adjoint input
-    float* gacc;                     // adjoint: gradient accumulator (zero on entry; launch_finish clears it)
+    // adjoint: gradient accumulator in 64-bit fixed point (zero on entry; launch_finish converts and clears
+    // it), and per design the cotangent bound max |dL/dI| (float bits) that sets its unit
+    unsigned long long* gacc;
+    const uint32_t* gmax;
     int32_t use_tile;                // forward: LDS footprint tile
     int32_t butterfly;               // adjoint: wave-level reduce-scatter of control-point gradients
     int32_t kind_group;              // 0: collimated designs, 1: point-source designs (bmap covers only these)
@@ -181,14 +184,17 @@ int loss_blocks_per_design(int64_t max_pixels);
 hipError_t launch_resolve(const DesignDev* designs, int n_designs, int LB, unsigned long long* img64, float* irr,
                           const float* Pz, ffrt_stats* slots, ffrt_stats* stats, hipStream_t s);
 // Slice sums of the loss into partial (n_designs * LB * 5 doubles), resolving the irradiance from img64
-// first when img64 is not null (as launch_resolve, statistics included); then dL/dI, loss and valid.
+// first when img64 is not null (as launch_resolve, statistics included); then dL/dI, loss and valid.  With
+// gmax set (zero on entry), the largest |dL/dI| of every design goes there too, for the adjoint's unit.
 hipError_t launch_loss(const DesignDev* designs, int n_designs, int LB, unsigned long long* img64, float* irr,
                        const float* target, const float* Pz, ffrt_stats* slots, ffrt_stats* stats, double* partial,
-                       float* loss, float* dLdI, int32_t* valid, hipStream_t s);
-// After the adjoint: dL/dP = gacc, gacc cleared; with adam.Pz set, Adam updates the designs whose loss
-// found flux (valid).
-hipError_t launch_finish(const DesignDev* designs, int n_designs, float* gacc, float* dLdP, const int32_t* valid,
-                         const AdamArgs& adam, hipStream_t s);
+                       float* loss, float* dLdI, int32_t* valid, uint32_t* gmax, hipStream_t s);
+// The largest |dL/dI| of every design of a given dL/dI into gmax (one workgroup per design).
+hipError_t launch_gscale(const DesignDev* designs, int n_designs, const float* dLdI, uint32_t* gmax, hipStream_t s);
+// After the adjoint: dL/dP from the fixed-point gacc, gacc and gmax cleared; with adam.Pz set, Adam updates the
+// designs whose loss found flux (valid).
+hipError_t launch_finish(const DesignDev* designs, int n_designs, unsigned long long* gacc, uint32_t* gmax,
+                         float* dLdP, const int32_t* valid, const AdamArgs& adam, hipStream_t s);
 // Range reparametrisation of sec. 2.4.1 over n packed control points: mode 0 writes P from theta, mode 1
 // writes dL/dtheta from dL/dP.
 hipError_t launch_reparam(int mode, int64_t n, const float* theta, const float* lo, const float* span, float* P,

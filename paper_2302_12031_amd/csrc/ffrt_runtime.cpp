@@ -79,7 +79,8 @@ struct ffrt_plan {
     size_t ws_bytes = 0;
     size_t off_designs = 0, off_bounds = 0, off_sb = 0, off_valid = 0, off_knots = 0, off_bmap = 0, off_slots = 0;
     size_t need = 0;
-    size_t off_lpart = 0, off_img64 = 0, off_gacc = 0, off_dldi = 0, off_mlpoff = 0, off_mlpvec = 0, off_roots = 0;
+    size_t off_lpart = 0, off_img64 = 0, off_gacc = 0, off_gmax = 0, off_dldi = 0, off_mlpoff = 0, off_mlpvec = 0,
+           off_roots = 0;
     int num_cu = 256;
     int fwd_cfg = 0, adj_cfg = 0;
     hipGraph_t graph = nullptr;
@@ -96,7 +97,8 @@ struct ffrt_plan {
     ffrt_stats* d_slots() const { return reinterpret_cast<ffrt_stats*>(ws + off_slots); }
     double* d_lpart() const { return reinterpret_cast<double*>(ws + off_lpart); }
     unsigned long long* d_img64() const { return reinterpret_cast<unsigned long long*>(ws + off_img64); }
-    float* d_gacc() const { return reinterpret_cast<float*>(ws + off_gacc); }
+    unsigned long long* d_gacc() const { return reinterpret_cast<unsigned long long*>(ws + off_gacc); }
+    uint32_t* d_gmax() const { return reinterpret_cast<uint32_t*>(ws + off_gmax); }
     float* d_dldi() const { return reinterpret_cast<float*>(ws + off_dldi); }
     int64_t* d_mlpoff(int arch) const { return reinterpret_cast<int64_t*>(ws + off_mlpoff) + (size_t)arch * (nd + 1); }
     float* d_mlpvec(int k) const { return reinterpret_cast<float*>(ws + off_mlpvec) + (size_t)k * total_cp; }
@@ -270,7 +272,8 @@ TraceArgs make_args(ffrt_plan* pl, int shape, int kg) {
     // point sources stage the span bounds too, when the kernels' LDS then stays within 64 KiB
     const int sb = 4 * pl->max_spans;
     const bool search = kg == 1 || kg >= 4;  // exact exit root search (point sources, freeform entry faces)
-    if (search && 4 * (A.lds_cp + A.lds_kt + sb + std::max(TILE_CAP, A.lds_cp)) <= 65536) A.lds_sb = sb;
+    // (the forward's tile, or the adjoint's gradient net in 64-bit fixed point)
+    if (search && 4 * (A.lds_cp + A.lds_kt + sb + std::max(TILE_CAP, 2 * A.lds_cp)) <= 65536) A.lds_sb = sb;
     return A;
 }
 
@@ -312,6 +315,7 @@ ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hi
         A.Pz = Pz;
         A.dLdI = dLdI;
         A.gacc = pl->d_gacc();
+        A.gmax = pl->d_gmax();
         A.butterfly = c.butterfly;
         A.roots = roots && kg == 1 ? pl->d_roots() : nullptr;
         HIP_TRY(pl->ks->adjoint(A, c.shape, grid_for(pl, c.shape, kg, c.persistent), s));
@@ -344,8 +348,10 @@ ffrt_status run_forward(ffrt_plan* pl, const float* Pz, float* irr, ffrt_stats* 
 ffrt_status run_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, float* dLdP, hipStream_t s,
                         bool roots = false) {
     if (ffrt_status b = run_bounds(pl, Pz, s)) return b;
+    // the cotangent bound that sets the unit of the fixed-point gradient sums, from the dL/dI given
+    HIP_TRY(launch_gscale(pl->d_designs(), pl->nd, dLdI, pl->d_gmax(), s));
     if (ffrt_status a = launch_adjoint(pl, Pz, dLdI, s, roots)) return a;
-    HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), dLdP, nullptr, no_adam(), s));
+    HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), pl->d_gmax(), dLdP, nullptr, no_adam(), s));
     return FFRT_OK;
 }
 
@@ -364,7 +370,7 @@ ffrt_status run_step(ffrt_plan* pl, float* Pz, const float* target, float* irr, 
     ffrt_status st = launch_forward(pl, Pz, stats != nullptr, s, true);
     if (st) return st;
     HIP_TRY(launch_loss(pl->d_designs(), pl->nd, pl->loss_lb, pl->d_img64(), irr, target, Pz, pl->d_slots(), stats,
-                        pl->d_lpart(), loss, dLdI, pl->d_valid(), s));
+                        pl->d_lpart(), loss, dLdI, pl->d_valid(), pl->d_gmax(), s));
     st = launch_adjoint(pl, Pz, dLdI, s, true);
     if (st) return st;
     AdamArgs adam;
@@ -377,7 +383,7 @@ ffrt_status run_step(ffrt_plan* pl, float* Pz, const float* target, float* irr, 
     adam.theta = theta;
     adam.lo = lo;
     adam.span = span;
-    HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), dLdP, pl->d_valid(), adam, s));
+    HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), pl->d_gmax(), dLdP, pl->d_valid(), adam, s));
     return FFRT_OK;
 }
 
@@ -544,8 +550,10 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
     off = align256(off + sizeof(double) * 5 * pl->loss_lb * n_designs);
     pl->off_img64 = off;
     off = align256(off + sizeof(unsigned long long) * (size_t)pl->total_img);
-    pl->off_gacc = off;
-    off = align256(off + sizeof(float) * (size_t)pl->total_cp);
+    pl->off_gacc = off;  // 64-bit fixed point
+    off = align256(off + sizeof(unsigned long long) * (size_t)pl->total_cp);
+    pl->off_gmax = off;
+    off = align256(off + sizeof(uint32_t) * n_designs);
     pl->off_dldi = off;  // dL/dI of a step whose caller does not want it
     off = align256(off + sizeof(float) * (size_t)pl->total_img);
     pl->off_mlpoff = off;  // parameter offsets of the control-point generators (dense, sparse)
@@ -593,7 +601,8 @@ ffrt_status ffrt_plan_set_workspace(ffrt_plan* plan, void* dev_ptr, size_t bytes
     // accumulators and counters that the kernels expect to be zero on entry (and leave zero on exit)
     HIP_TRY(hipMemset(plan->d_slots(), 0, sizeof(ffrt_stats) * NSLOT * plan->nd));
     HIP_TRY(hipMemset(plan->d_img64(), 0, sizeof(unsigned long long) * plan->total_img));
-    HIP_TRY(hipMemset(plan->d_gacc(), 0, sizeof(float) * plan->total_cp));
+    HIP_TRY(hipMemset(plan->d_gacc(), 0, sizeof(unsigned long long) * plan->total_cp));
+    HIP_TRY(hipMemset(plan->d_gmax(), 0, sizeof(uint32_t) * plan->nd));
     for (int a = 0; a < 2; ++a)
         HIP_TRY(hipMemcpy(plan->d_mlpoff(a), plan->mlp_off[a].data(), sizeof(int64_t) * plan->mlp_off[a].size(),
                           hipMemcpyHostToDevice));
@@ -637,7 +646,8 @@ ffrt_status ffrt_loss(ffrt_plan* plan, const float* irr, const float* target, fl
     if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");
     if (!irr || !target || !loss || !dL_dI) return fail(FFRT_E_ARG, "null buffer");
     HIP_TRY(launch_loss(plan->d_designs(), plan->nd, plan->loss_lb, nullptr, const_cast<float*>(irr), target, nullptr,
-                        plan->d_slots(), nullptr, plan->d_lpart(), loss, dL_dI, plan->d_valid(), (hipStream_t)stream));
+                        plan->d_slots(), nullptr, plan->d_lpart(), loss, dL_dI, plan->d_valid(), nullptr,
+                        (hipStream_t)stream));
     return FFRT_OK;
 }
 
@@ -925,7 +935,8 @@ ffrt_status ffrt_plan_time_kernels(ffrt_plan* plan, const float* Pz, float* irr,
     // the timed launches accumulated into the fixed-point image and the gradient accumulator without
     // consuming them: clear both in any case
     hipError_t ez = hipMemsetAsync(plan->d_img64(), 0, sizeof(unsigned long long) * plan->total_img, s);
-    if (ez == hipSuccess) ez = hipMemsetAsync(plan->d_gacc(), 0, sizeof(float) * plan->total_cp, s);
+    if (ez == hipSuccess) ez = hipMemsetAsync(plan->d_gacc(), 0, sizeof(unsigned long long) * plan->total_cp, s);
+    if (ez == hipSuccess) ez = hipMemsetAsync(plan->d_gmax(), 0, sizeof(uint32_t) * plan->nd, s);
     if (!st && e == hipSuccess) e = ez;
     if (!st && e == hipSuccess) e = hipStreamSynchronize(s);
     float f = 0.0f, a = 0.0f;

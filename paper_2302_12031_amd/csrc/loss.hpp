@@ -16,6 +16,18 @@ struct LossOut {
     int valid;      // 0 without flux (the design's Adam update is skipped)
 };
 
+// Exponent e of the adjoint's fixed-point unit 2^e for a design with cotangent bound gmax = max |dL/dI| (its
+// float bits, as the kernels keep it) and ray weight w0: 32 bits below the leading bit of S = gmax w0, the
+// size of a single ray's weighted cotangent (0 when S is zero or not finite, where every contribution is
+// zero).
+__device__ inline int fixed_point_exponent(uint32_t gmax_bits, float w0) {
+    const double S = (double)__builtin_bit_cast(float, gmax_bits) * (double)w0;
+    if (!(S > 0.0) || !(S < 1e300)) return 0;
+    int e = 0;
+    (void)frexp(S, &e);  // S = m 2^e, m in [0.5, 1): floor(log2 S) = e - 1
+    return e - 1 - 32;
+}
+
 // Loss and dL/dI scalars from the whole-image sums q = (sum I, sum T, sum I^2, sum I T, sum T^2).
 __device__ inline LossOut loss_from_sums(const double* q, const DesignDev& D) {
     LossOut r;

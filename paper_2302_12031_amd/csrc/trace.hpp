@@ -18,6 +18,7 @@
 #include <stdint.h>
 
 #include "ffrt_internal.h"
+#include "loss.hpp"
 #include "wave.hpp"
 
 namespace ffrt {
@@ -300,7 +301,9 @@ __device__ __forceinline__ RayIn ray_entry(const DesignDev& D, int e, int ku, in
 // Freeform intersection (sec. 2.2.1 root problem; sec. 2.2.2 bounding box).
 // f(t) = h(o_xy + t d_xy) - o_z - t d_z.  Bracket from the global convex-hull box [min P^z, max P^z]
 // intersected with the aperture; f > 0 below it and f < 0 above.  When the slope bound proves f strictly
-// decreasing the root is unique; otherwise the bracket is scanned for its first sign change.  Safeguarded
+// decreasing the root is unique; otherwise the bracket is scanned for its first sign change (64 samples per
+// projected knot span), which is the smallest root even where the ray meets the surface again before it
+// leaves the aperture.  Safeguarded
 // Newton (bisection when a step leaves the bracket), at most newton_max iterations.  Grazing hits
 // (|f'| small) get their residual re-evaluated in double precision and one double Newton correction.
 // ------------------------------------------------------------------------------------------------
@@ -348,13 +351,9 @@ __device__ RootOut intersect(const DesignDev& D, const BoundsDev& B, const float
     }
     const float ozr = r.oz - B.zref;
     float a = t_lo, b = t_end, fp;
-    if (t_ap <= t_hi) {
-        // the aperture ends the search: the ray must be above the surface where it leaves the aperture
-        if (f_and_slope<P, Q>(D, sP, sKu, sKv, r, ozr, t_end, fp) > 0.0f) {
-            R.status = ST_SIDE_WALL;
-            return R;
-        }
-    }
+    // the aperture ends the search: a ray still below the surface where it leaves the aperture has no root,
+    // unless (f not monotone) it crossed the surface and met it again before the aperture edge
+    const bool end_below = t_ap <= t_hi && f_and_slope<P, Q>(D, sP, sKu, sKv, r, ozr, t_end, fp) > 0.0f;
     float gx = B.gx, gy = B.gy;
     if (sS) {
         // Local bounds: over [t_lo, t_end] the ray stays above the few span products its (x, y) segment
@@ -387,20 +386,34 @@ __device__ RootOut intersect(const DesignDev& D, const BoundsDev& B, const float
             gy = gyl;
         }
     }
-    const float t_scan_end = b;
-    bool mono = gx * fabsf(r.dx) + gy * fabsf(r.dy) < r.dz;
-    if (!mono) {
+    const bool mono = gx * fabsf(r.dx) + gy * fabsf(r.dy) < r.dz;
+    if (mono) {
+        if (end_below) {
+            R.status = ST_SIDE_WALL;
+            return R;
+        }
+    } else {
+        // the first sign change, sampled at 64 points per knot span the segment [a, b] projects onto (at least
+        // 64, at most 4096); no sign change at any sample: the ray leaves through the side wall
         R.nonmono = 1;
-        constexpr int SCAN = 32;
-        float prev = a;
-        for (int s = 1; s <= SCAN; ++s) {
-            float ts = a + (t_scan_end - a) * ((float)s * (1.0f / SCAN));
+        const float du = fabsf(r.dx) * (b - a) * D.sxu, dv = fabsf(r.dy) * (b - a) * D.syv;
+        const int M = min(max(64, (int)ceilf(64.0f * (du + dv)) + 1), 4096);
+        const float a0 = a, len = b - a, inv_m = 1.0f / (float)M;
+        float prev = a0;
+        bool found = false;
+        for (int s = 1; s <= M; ++s) {
+            const float ts = s == M ? a0 + len : a0 + len * ((float)s * inv_m);
             if (f_and_slope<P, Q>(D, sP, sKu, sKv, r, ozr, ts, fp) <= 0.0f) {
                 a = prev;
                 b = ts;
+                found = true;
                 break;
             }
             prev = ts;
+        }
+        if (!found) {
+            R.status = ST_SIDE_WALL;
+            return R;
         }
     }
     float t = 0.5f * (a + b);
@@ -520,24 +533,38 @@ __device__ __forceinline__ RayIn ray_entry_ff(const DesignDev& D, const BoundsDe
             return r;
         }
         float fp;
-        // enter the prism below the face and leave it above, else the ray passes the lens
-        if (f_and_slope<P, Q>(D, sPin, sKu, sKv, s0, ozr, a, fp) < 0.0f ||
-            f_and_slope<P, Q>(D, sPin, sKu, sKv, s0, ozr, b, fp) > 0.0f) {
+        // enter the prism below the face (else through the side wall) and cross it before leaving the prism
+        // (else the ray passes the lens): with a monotone f the sign where it leaves decides, otherwise the
+        // first sign change of the scan, as at the exit face
+        if (f_and_slope<P, Q>(D, sPin, sKu, sKv, s0, ozr, a, fp) < 0.0f) {
             r.status = ST_MISS_ENTRY;
             return r;
         }
-        if (!(B.gx_in * fabsf(H.d0x) + B.gy_in * fabsf(H.d0y) < H.d0z)) {
-            constexpr int SCAN = 32;
-            float prev = a;
-            const float end = b;
-            for (int k = 1; k <= SCAN; ++k) {
-                const float ts = a + (end - a) * ((float)k * (1.0f / SCAN));
+        const bool exit_below = f_and_slope<P, Q>(D, sPin, sKu, sKv, s0, ozr, b, fp) > 0.0f;
+        if (B.gx_in * fabsf(H.d0x) + B.gy_in * fabsf(H.d0y) < H.d0z) {
+            if (exit_below) {
+                r.status = ST_MISS_ENTRY;
+                return r;
+            }
+        } else {
+            const float du = fabsf(H.d0x) * (b - a) * D.sxu, dv = fabsf(H.d0y) * (b - a) * D.syv;
+            const int M = min(max(64, (int)ceilf(64.0f * (du + dv)) + 1), 4096);
+            const float a0 = a, len = b - a, inv_m = 1.0f / (float)M;
+            float prev = a0;
+            bool found = false;
+            for (int k = 1; k <= M; ++k) {
+                const float ts = k == M ? a0 + len : a0 + len * ((float)k * inv_m);
                 if (f_and_slope<P, Q>(D, sPin, sKu, sKv, s0, ozr, ts, fp) <= 0.0f) {
                     a = prev;
                     b = ts;
+                    found = true;
                     break;
                 }
                 prev = ts;
+            }
+            if (!found) {
+                r.status = ST_MISS_ENTRY;
+                return r;
             }
         }
         t = 0.5f * (a + b);
@@ -1394,11 +1421,13 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
         // ---- footprint of the block: the landing pixels widened by the filter half-width, and by one more
         // row and column for the per-thread windows below.  The tile is not clipped to the image, so every
         // window of a thread with a hit lies inside it and needs no per-pixel test; pixels outside the
-        // image only ever receive zero weights, and the flush skips them.
+        // image only ever receive zero weights, and the flush skips them.  A footprint larger than the tile
+        // is splatted in slabs of whole rows, one pass each (every pass clears the tile, adds the block's
+        // contributions to the slab's rows and flushes them), so that the device image still receives one
+        // atomic per touched pixel and pass instead of one per ray and pixel.
         unsigned long long* img = A.img64 + D.img_off;
         bool use_tile = false;
-        int ilo = 0, jlo = 0, tw = 0, area = 0, ncopy = 1;
-        uint32_t* mytile = tile;
+        int ilo = 0, jlo = 0, tw = 0, rows = 0, slab = 0, ncopy = 1;
         if (A.use_tile) {
             int a0 = wave_min(imin), a1 = wave_max(imax), b0 = wave_min(jmin), b1 = wave_max(jmax);
             if (lane == 0) {
@@ -1418,129 +1447,149 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
             ilo = a0 - H;
             jlo = b0 - H;
             tw = b1 + H + PAD - jlo + 1;
-            area = (a1 + H + PAD - ilo + 1) * tw;
-            use_tile = area <= TILE_CAP;
+            rows = a1 + H + PAD - ilo + 1;
+            // slabs for the searched rays (point sources, freeform entry faces), whose blocks may fan out over
+            // the screen; a collimated block's footprint stays compact, and its kernels keep a single pass (a
+            // footprint beyond the tile then goes to the device image directly)
+            constexpr bool SLABS = (KIND & 5) != 0;
+            use_tile = SLABS ? tw <= TILE_CAP : rows * tw <= TILE_CAP;
             if (use_tile) {
+                slab = min(rows, TILE_CAP / tw);
                 // Neighbouring lanes usually add to the same pixels, and LDS atomics on one address serialise:
-                // when it fits, each of the four lanes of a 2 x 2 patch of the wave's 8 x 8 lane grid adds to
-                // its own copy of the tile, and the flush sums the copies.
-                ncopy = 4 * area <= TILE_CAP ? 4 : 1;
+                // when the footprint fits four times, each of the four lanes of a 2 x 2 patch of the wave's
+                // 8 x 8 lane grid adds to its own copy of the tile, and the flush sums the copies.
+                ncopy = slab == rows && 4 * rows * tw <= TILE_CAP ? 4 : 1;
+            }
+        }
+        const int npass = (KIND & 5) != 0 && use_tile ? (rows + slab - 1) / slab : 1;
+        for (int pass = 0; pass < npass; ++pass) {
+            // the slab: image rows [r0, r0 + nrow) of the footprint, in the tile at (i - r0) tw + (j - jlo)
+            const int r0 = ilo + pass * slab;
+            const int nrow = use_tile ? min(slab, rows - pass * slab) : 0;
+            const int area = nrow * tw;
+            uint32_t* mytile = tile;
+            if (use_tile) {
                 for (int i = threadIdx.x; i < ncopy * area; i += WG) tile[i] = 0u;
                 __syncthreads();
                 mytile = tile + (ncopy == 4 ? ((lane & 1) | ((lane >> 2) & 2)) * area : 0);
             }
-        }
-        // ---- splat
-        if constexpr (ACCUM) {
-            // The window is anchored at the thread's lowest landing pixel (imin, jmin); rays whose filter
-            // window starts at most one pixel further along each axis are summed in registers, the others
-            // are added directly.  With the tile the sums are kept in tile units.
-            const int ai = imin - H, aj = jmin - H;
-            const float wsc = use_tile ? D.fx_scale * (1.0f / (float)(1 << TSH)) : 1.0f;
-            float acc[WN * WN];
+            auto in_slab = [&](int i) { return !use_tile || (i >= r0 && i < r0 + nrow); };
+            // ---- splat.  Every pass evaluates the filter weights of the thread's rays again (cheap beside the
+            // trace) and keeps the contributions to the slab's rows; registers then carry only the landings
+            // from one pass to the next.  The empty asm makes each landing look pass-dependent, so that the
+            // compiler does not hoist the weights of every ray out of the pass loop.
+            if constexpr (ACCUM) {
+                // Per-thread accumulation window anchored at the thread's lowest landing pixel (imin, jmin): rays
+                // whose filter window starts at most one pixel further along each axis are summed in registers,
+                // the others are added directly.  With the tile the sums are kept in tile units.
+                const int ai = imin - H, aj = jmin - H;
+                const float wsc = use_tile ? D.fx_scale * (1.0f / (float)(1 << TSH)) : 1.0f;
+                float acc[WN * WN];
 #pragma unroll
-            for (int k = 0; k < WN * WN; ++k) acc[k] = 0.0f;
-            bool last_row = false, last_col = false;  // whether row / column WN - 1 of the window is used
+                for (int k = 0; k < WN * WN; ++k) acc[k] = 0.0f;
+                bool last_row = false, last_col = false;  // whether row / column WN - 1 of the window is used
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                if (W[r] == 0.0f) continue;
-                float Fx[NU], Fy[NU];
-                const int di =
-                    filter_axis<NU, false>(X[r], D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr, D.box) -
-                    H - ai;
-                const int dj =
-                    filter_axis<NU, false>(Y[r], D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr, D.box) -
-                    H - aj;
-                if (di > WN - NU || dj > WN - NU) {
+                for (int r = 0; r < RPT; ++r) {
+                    if (W[r] == 0.0f) continue;
+                    float xr = X[r], yr = Y[r];
+                    if (npass > 1) asm volatile("" : "+v"(xr), "+v"(yr));
+                    float Fx[NU], Fy[NU];
+                    const int di =
+                        filter_axis<NU, false>(xr, D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr, D.box) -
+                        H - ai;
+                    const int dj =
+                        filter_axis<NU, false>(yr, D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr, D.box) -
+                        H - aj;
+                    if (di > WN - NU || dj > WN - NU) {
 #pragma unroll
-                    for (int a = 0; a < NU; ++a) {
+                        for (int a = 0; a < NU; ++a) {
+                            if (!in_slab(ai + di + a)) continue;
 #pragma unroll
-                        for (int bb = 0; bb < NU; ++bb) {
-                            const float v = W[r] * Fx[a] * Fy[bb];
-                            if (v != 0.0f)
-                                splat_add<TSH>(use_tile, mytile, tw, ilo, jlo, D.fx_scale, img, D.ny, ai + di + a,
-                                          aj + dj + bb, v);
+                            for (int bb = 0; bb < NU; ++bb) {
+                                const float v = W[r] * Fx[a] * Fy[bb];
+                                if (v != 0.0f)
+                                    splat_add<TSH>(use_tile, mytile, tw, r0, jlo, D.fx_scale, img, D.ny, ai + di + a,
+                                                   aj + dj + bb, v);
+                            }
+                        }
+                        continue;
+                    }
+                    last_row |= di != 0;
+                    last_col |= dj != 0;
+                    // add the NU x NU window at offset (di, dj) in {0, 1}^2 without indexing registers dynamically
+                    const float wr = W[r] * wsc;
+                    float fx[WN], fy[WN];
+#pragma unroll
+                    for (int k = 0; k < WN; ++k) {
+                        float a0 = k < NU ? Fx[k] : 0.0f, a1 = k > 0 ? Fx[k - 1] : 0.0f;
+                        float b0 = k < NU ? Fy[k] : 0.0f, b1 = k > 0 ? Fy[k - 1] : 0.0f;
+                        fx[k] = wr * (di == 0 ? a0 : a1);
+                        fy[k] = dj == 0 ? b0 : b1;
+                    }
+#pragma unroll
+                    for (int k = 0; k < WN * WN; ++k) acc[k] += fx[k / WN] * fy[k % WN];
+                }
+                if (use_tile) {
+                    if (imax >= 0) {  // the window lies inside the footprint: one row address per window row
+                        auto add = [](uint32_t* p, float v) {
+                            __hip_atomic_fetch_add(p, (uint32_t)__float2int_rn(v), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                        };
+#pragma unroll
+                        for (int a = 0; a < WN; ++a) {
+                            if ((a == WN - 1 && !last_row) || !in_slab(ai + a)) continue;
+                            uint32_t* row = mytile + (ai + a - r0) * tw + (aj - jlo);
+#pragma unroll
+                            for (int bb = 0; bb < WN - 1; ++bb) add(row + bb, acc[a * WN + bb]);
+                            if (last_col) add(row + WN - 1, acc[a * WN + WN - 1]);
                         }
                     }
-                    continue;
-                }
-                last_row |= di != 0;
-                last_col |= dj != 0;
-                // add the NU x NU window at offset (di, dj) in {0, 1}^2 without indexing registers dynamically
-                const float wr = W[r] * wsc;
-                float fx[WN], fy[WN];
+                } else {
 #pragma unroll
-                for (int k = 0; k < WN; ++k) {
-                    float a0 = k < NU ? Fx[k] : 0.0f, a1 = k > 0 ? Fx[k - 1] : 0.0f;
-                    float b0 = k < NU ? Fy[k] : 0.0f, b1 = k > 0 ? Fy[k - 1] : 0.0f;
-                    fx[k] = wr * (di == 0 ? a0 : a1);
-                    fy[k] = dj == 0 ? b0 : b1;
-                }
-#pragma unroll
-                for (int k = 0; k < WN * WN; ++k) acc[k] += fx[k / WN] * fy[k % WN];
-            }
-            if (use_tile) {
-                if (imax >= 0) {  // the window lies inside the tile: one row address per window row
-                    uint32_t* t0 = mytile + (ai - ilo) * tw + (aj - jlo);
-                    auto add = [](uint32_t* p, float v) {
-                        __hip_atomic_fetch_add(p, (uint32_t)__float2int_rn(v), __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-                    };
-#pragma unroll
-                    for (int a = 0; a < WN - 1; ++a) {
-                        uint32_t* row = t0 + a * tw;
-#pragma unroll
-                        for (int bb = 0; bb < WN - 1; ++bb) add(row + bb, acc[a * WN + bb]);
-                        if (last_col) add(row + WN - 1, acc[a * WN + WN - 1]);
-                    }
-                    if (last_row) {
-                        uint32_t* row = t0 + (WN - 1) * tw;
-#pragma unroll
-                        for (int bb = 0; bb < WN; ++bb) add(row + bb, acc[(WN - 1) * WN + bb]);
-                    }
+                    for (int k = 0; k < WN * WN; ++k)
+                        if (acc[k] != 0.0f)
+                            splat_add<TSH>(false, mytile, tw, r0, jlo, D.fx_scale, img, D.ny, ai + k / WN,
+                                           aj + k % WN, acc[k]);
                 }
             } else {
 #pragma unroll
-                for (int k = 0; k < WN * WN; ++k)
-                    if (acc[k] != 0.0f)
-                        splat_add<TSH>(false, mytile, tw, ilo, jlo, D.fx_scale, img, D.ny, ai + k / WN,
-                                       aj + k % WN, acc[k]);
-            }
-        } else {
+                for (int r = 0; r < RPT; ++r) {
+                    if (W[r] == 0.0f) continue;
+                    float xr = X[r], yr = Y[r];
+                    if (npass > 1) asm volatile("" : "+v"(xr), "+v"(yr));
+                    float Fx[NU], Fy[NU];
+                    const int i0 =
+                        filter_axis<NU, false>(xr, D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr, D.box);
+                    const int j0 =
+                        filter_axis<NU, false>(yr, D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr, D.box);
 #pragma unroll
-            for (int r = 0; r < RPT; ++r) {
-                if (W[r] == 0.0f) continue;
-                float Fx[NU], Fy[NU];
-                int i0 =
-                    filter_axis<NU, false>(X[r], D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr, D.box);
-                int j0 =
-                    filter_axis<NU, false>(Y[r], D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr, D.box);
+                    for (int a = 0; a < NU; ++a) {
+                        const int i = i0 + a - H;
+                        if (i < 0 || i >= D.nx || !in_slab(i)) continue;
 #pragma unroll
-                for (int a = 0; a < NU; ++a) {
-                    int i = i0 + a - H;
-                    if (i < 0 || i >= D.nx) continue;
-#pragma unroll
-                    for (int bb = 0; bb < NU; ++bb) {
-                        int j = j0 + bb - H;
-                        if (j < 0 || j >= D.ny) continue;
-                        splat_add<TSH>(use_tile, mytile, tw, ilo, jlo, D.fx_scale, img, D.ny, i, j, W[r] * Fx[a] * Fy[bb]);
+                        for (int bb = 0; bb < NU; ++bb) {
+                            const int j = j0 + bb - H;
+                            if (j < 0 || j >= D.ny) continue;
+                            splat_add<TSH>(use_tile, mytile, tw, r0, jlo, D.fx_scale, img, D.ny, i, j,
+                                           W[r] * Fx[a] * Fy[bb]);
+                        }
                     }
                 }
             }
-        }
-        if (use_tile) {
-            __syncthreads();
-            for (int i = threadIdx.x; i < area; i += WG) {
-                unsigned long long q = tile[i];
-                for (int c = 1; c < ncopy; ++c) q += tile[c * area + i];
-                q <<= TSH;
-                const int ti = i / tw;
-                const int gi = ilo + ti, gj = jlo + (i - ti * tw);
-                if (q != 0ull && gi >= 0 && gi < D.nx && gj >= 0 && gj < D.ny)
-                    __hip_atomic_fetch_add(&img[(int64_t)gi * D.ny + gj], q, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+            if (use_tile) {
+                __syncthreads();
+                for (int i = threadIdx.x; i < area; i += WG) {
+                    unsigned long long q = tile[i];
+                    for (int c = 1; c < ncopy; ++c) q += tile[c * area + i];
+                    q <<= TSH;
+                    const int ti = i / tw;
+                    const int gi = r0 + ti, gj = jlo + (i - ti * tw);
+                    if (q != 0ull && gi >= 0 && gi < D.nx && gj >= 0 && gj < D.ny)
+                        __hip_atomic_fetch_add(&img[(int64_t)gi * D.ny + gj], q, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
 }
@@ -1548,27 +1597,39 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
 // ------------------------------------------------------------------------------------------------
 // Adjoint kernel
 // ------------------------------------------------------------------------------------------------
+// The adjoint sums its gradient contributions as signed 64-bit integers (fixed point): integer additions do
+// not depend on their order, so dL/dP is reproducible bit for bit whatever order the lanes, waves and
+// workgroups add in.  The unit is set per design from the size of a single ray's weighted cotangent,
+// S = max |dL/dI| w0, as 2^(floor(log2 S) - 32) (fixed_point_exponent): a contribution of size S keeps 32
+// bits below its leading bit, and a sum of up to 2^31 S fits (the gradient itself stays far below: on the
+// stated workloads max |dL/dP| < 2^22 S).  Two's-complement sums wrap around, so only the final value has to
+// fit.
+__device__ __forceinline__ unsigned long long to_fixed(float v, float inv_unit) {
+    return (unsigned long long)__float2ll_rn(v * inv_unit);
+}
+
 // Add a thread's control-point accumulator (span product (ku, kv)) to the LDS copy of the control net.
 template <int P, int Q, int NV>
-__device__ __forceinline__ void cp_flush_lane(float* sG, int n_v, int ku, int kv, const float* acc) {
+__device__ __forceinline__ void cp_flush_lane(unsigned long long* sG, int n_v, int ku, int kv, const float* acc,
+                                              float inv_unit) {
 #pragma unroll
     for (int a = 0; a <= P; ++a)
 #pragma unroll
         for (int b = 0; b <= Q; ++b) {
             float v = acc[a * (Q + 1) + b];
-            if (v != 0.0f) atomicAdd(&sG[(ku + a) * n_v + kv + b], v);
+            if (v != 0.0f) atomicAdd(&sG[(ku + a) * n_v + kv + b], to_fixed(v, inv_unit));
         }
 }
 
 // End of a workgroup's run of blocks of design d: add its LDS control-net gradient to the device
 // accumulator (cleared again by the finishing kernel that reads it).
-__device__ void adjoint_flush(const TraceArgs& A, int d, const float* sG) {
+__device__ void adjoint_flush(const TraceArgs& A, int d, const unsigned long long* sG) {
     __syncthreads();
     const DesignDev D = load_uniform(A.designs, d);
-    float* acc = A.gacc + D.cp_off;
+    unsigned long long* acc = A.gacc + D.cp_off;
     for (int i = threadIdx.x; i < D.ncp; i += WG) {
-        const float v = sG[i];
-        if (v != 0.0f) atomicAdd(&acc[i], v);
+        const unsigned long long v = sG[i];
+        if (v != 0ull) atomicAdd(&acc[i], v);
     }
 }
 
@@ -1581,7 +1642,7 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
     float* sP = smem;
     float* sK = sP + A.lds_cp;
     float* sS = sK + A.lds_kt;  // span bounds (exit root searches, when they fit)
-    float* sG = sS + A.lds_sb;
+    unsigned long long* sG = reinterpret_cast<unsigned long long*>(sS + A.lds_sb);  // 64-bit fixed point
     const float* sSb = (KIND & 5) != 0 && A.lds_sb ? sS : nullptr;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int MU = shape_mu(shape), MV = shape_mv(shape), RPT = MU * MV;
@@ -1598,7 +1659,7 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
         if (d != cur) {
             if (cur >= 0) adjoint_flush(A, cur, sG);
             __syncthreads();
-            for (int i = threadIdx.x; i < D.ncp; i += WG) sG[i] = 0.0f;
+            for (int i = threadIdx.x; i < D.ncp; i += WG) sG[i] = 0ull;
             B = stage_design(A, D, d, sP, sK, P, Q, (KIND & 5) != 0);
             cur = d;
         }
@@ -1620,7 +1681,8 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
 #pragma unroll
         for (int i = 0; i < (ENTRY ? NV : 1); ++i) acc_in[i] = 0.0f;
         int aku = -1, akv = -1, aku_in = -1, akv_in = -1;
-        float* sG_in = sG + D.n_u * D.n_v;
+        unsigned long long* sG_in = sG + D.n_u * D.n_v;
+        const float inv_unit = ldexpf(1.0f, -fixed_point_exponent(load_uniform(A.gmax, d), D.w0));
         for (int r = 0; r < RPT; ++r) {
             const int ku = ku0 + (r >> mv_shift), kv = kv0 + (r & (MV - 1));
             if (ku >= D.grid_u || kv >= D.grid_v) continue;
@@ -1634,7 +1696,7 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
                                                gin, tl))
                 continue;
             if (aku >= 0 && (cku != aku || ckv != akv)) {
-                cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc);
+                cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc, inv_unit);
 #pragma unroll
                 for (int i = 0; i < NV; ++i) acc[i] = 0.0f;
             }
@@ -1644,7 +1706,7 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
             for (int i = 0; i < NT; ++i) acc[i] += g[i];
             if constexpr (ENTRY) {
                 if (aku_in >= 0 && (cku_in != aku_in || ckv_in != akv_in)) {
-                    cp_flush_lane<P, Q, NV>(sG_in, D.n_v, aku_in, akv_in, acc_in);
+                    cp_flush_lane<P, Q, NV>(sG_in, D.n_v, aku_in, akv_in, acc_in, inv_unit);
 #pragma unroll
                     for (int i = 0; i < NV; ++i) acc_in[i] = 0.0f;
                 }
@@ -1655,7 +1717,7 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
             }
         }
         if constexpr (ENTRY) {
-            if (aku_in >= 0) cp_flush_lane<P, Q, NV>(sG_in, D.n_v, aku_in, akv_in, acc_in);
+            if (aku_in >= 0) cp_flush_lane<P, Q, NV>(sG_in, D.n_v, aku_in, akv_in, acc_in, inv_unit);
         }
         // end of the block: one round per distinct span product held in the wave, in which the lanes of the
         // leader's span product sum their accumulators with a butterfly (one LDS atomic per control point)
@@ -1672,12 +1734,12 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
                 const int idx = lane >> (6 - LOG_NV);
                 if ((lane & ((1 << (6 - LOG_NV)) - 1)) == 0 && idx < NT && sum != 0.0f) {
                     const int a = idx / (Q + 1), bb = idx - (idx / (Q + 1)) * (Q + 1);
-                    atomicAdd(&sG[((lkey >> 16) + a) * D.n_v + (lkey & 0xFFFF) + bb], sum);
+                    atomicAdd(&sG[((lkey >> 16) + a) * D.n_v + (lkey & 0xFFFF) + bb], to_fixed(sum, inv_unit));
                 }
                 pend = pend && !take;
             }
         } else if (pend) {
-            cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc);
+            cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc, inv_unit);
         }
     }
     if (cur >= 0) adjoint_flush(A, cur, sG);
@@ -1767,7 +1829,7 @@ struct KernelsFor {
         }
     }
     static hipError_t adjoint(const TraceArgs& A, int shape, int grid, hipStream_t s) {
-        size_t lds = trace_lds_bytes(A, A.lds_cp);
+        size_t lds = trace_lds_bytes(A, 2 * A.lds_cp);  // the gradient net in 64-bit fixed point
         constexpr bool cap = P == 3 && Q == 3 && NU == 3;
         switch (A.kind_group) {
             case 0: hipLaunchKernelGGL((k_adjoint<P, Q, NU, 0>), dim3(grid), dim3(WG), lds, s, A, shape); break;

@@ -104,10 +104,12 @@ def _tophat_setup(init, arch):
 
 
 def _linear_hp(plan, st, T, lr):
-    """Adam hyper-parameters with eps at the largest first gradient component.  The adjoint adds float partial
-    sums atomically, so two runs of one step differ by rounding (~1e-7 relative) in the gradient; with a tiny
-    eps Adam maps a component near eps to an update anywhere in [0, lr], and comparisons of separate runs would
-    see that noise, not the computation.  With this eps every update is close to linear in its gradient."""
+    """Adam hyper-parameters with eps at the largest first gradient component, for comparisons of steps whose
+    parameter gradients differ by rounding (~1e-7 relative): two chain rules (the generator's against the
+    reparametrised one), or two runs of the dense generator's back-propagation, whose transposed products add
+    float partial sums atomically.  With a tiny eps Adam maps a component near eps to an update anywhere in
+    [0, lr], so such comparisons would see that noise, not the computation.  With this eps every update is
+    close to linear in its gradient."""
     gP = plan.adjoint(st["Pz"], plan.loss(plan.forward(st["Pz"]), T)[1])
     g = plan.mlp_backward(st["params"], st["acts"], st["span"], gP, arch=st["arch"])
     torch.cuda.synchronize()
@@ -140,8 +142,8 @@ def test_step_mlp_equals_its_components(arch):
     # the generator's forward pass has no atomics: the step's closing forward is bit-exact
     acts1, P1 = plan.mlp_forward(st["params"], lo_d, sp_d, arch=arch)
     torch.cuda.synchronize()
-    torch.testing.assert_close(st["loss"], loss, rtol=1e-6, atol=0)
-    torch.testing.assert_close(st["dLdP"], gP, rtol=1e-4, atol=1e-5 * gP.abs().max().item())
+    assert torch.equal(st["loss"], loss)
+    assert torch.equal(st["dLdP"], gP)          # fixed-point gradient sums: reproducible bit for bit
     np.testing.assert_allclose(st["params"].cpu().numpy(), x1, rtol=0, atol=2e-6)
     assert torch.equal(st["Pz"], P1) and torch.equal(st["acts"], acts1)
     assert int(st["t"][0]) == 1
@@ -167,9 +169,10 @@ def test_graph_replay_of_mlp_steps_matches_eager(arch):
             plan_e.step_mlp(st_e, T, hp=hp)
         _ = torch.ones(1000, device="cuda").sum().item()      # unrelated eager work between replays
         torch.cuda.synchronize()
-        # the adjoint adds partial sums atomically: a gradient component whose ray contributions nearly
-        # cancel carries up to ~1e-4 relative rounding between runs, which Adam turns into ~lr 1e-4 parameter
-        # differences per step.  A replay that skipped a step or read stale parameters would differ by ~lr.
+        # dL/dP is reproducible bit for bit, but the dense generator's transposed products add their
+        # partial sums with float atomics: a component whose terms nearly cancel carries up to ~1e-4 relative
+        # rounding between runs, which Adam turns into ~lr 1e-4 parameter differences per step.  A replay
+        # that skipped a step or read stale parameters would differ by ~lr.
         torch.testing.assert_close(st_g["params"], st_e["params"], rtol=0, atol=3e-5)
         torch.testing.assert_close(st_g["Pz"], st_e["Pz"], rtol=0, atol=3e-5)
         assert int(st_g["t"][0]) == 3 * (k + 1)
@@ -193,7 +196,7 @@ def test_zero_initialised_generator_follows_the_no_network_optimisation(arch):
     w1, b1, W2, b2, W3, b3 = plan.unpack_mlp(st_m["params"], arch)[0]
     for a in (w1, b1, W2, b2, W3):
         assert not torch.any(a)
-    # separate runs of the adjoint differ by the rounding of its atomic sums (see the replay test)
+    # the two chain rules round differently (see _linear_hp)
     torch.testing.assert_close(b3, st_r["theta"], rtol=0, atol=3e-5)
     torch.testing.assert_close(st_m["Pz"], st_r["Pz"], rtol=0, atol=3e-5)
 

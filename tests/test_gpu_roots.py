@@ -73,8 +73,8 @@ def test_graph_replay_with_reused_roots_matches_eager_steps():
             plan_e.step(st_e, T)
         _ = torch.ones(1000, device="cuda").sum().item()  # unrelated eager work between replays
         torch.cuda.synchronize()
-        torch.testing.assert_close(st_g["Pz"], st_e["Pz"], rtol=0, atol=2e-6)
-        torch.testing.assert_close(st_g["loss"], st_e["loss"], rtol=1e-4, atol=0)
+        assert torch.equal(st_g["Pz"], st_e["Pz"])
+        assert torch.equal(st_g["loss"], st_e["loss"])
     _say(f"[roots] graph loss after 6 steps {st_g['loss'].item():.6e}")
 
 
@@ -104,3 +104,43 @@ def test_batched_plan_root_slots_match_separate_plans():
         np.testing.assert_allclose(g_all[off[d]:off[d + 1]], g1, rtol=1e-4, atol=1e-5 * np.abs(g1).max())
         np.testing.assert_allclose(loss_all[d], s1["loss"].cpu().numpy()[0], rtol=1e-5)
     _say(f"[roots] batched plan of {len(probs)} designs matches separate plans")
+
+
+def test_rays_that_cross_the_exit_face_twice_take_the_smallest_root():
+    """Sec. 2.2.1: the hit is the smallest positive root.  On the valley h = 2 + x^2 / 2 (an exact cubic
+    B-spline) rays from a wide off-axis cone cross the exit face and meet its rising wall again before the
+    aperture edge; the slope bounds cannot prove these rays monotone, so the kernels scan for the first sign
+    change.  Per ray (all 65536), the device takes the oracle's status and root.  Rays whose two roots lie
+    within 0.2 of each other (towards a tangential double root, where either side's sampling may pass between
+    them: parity unpinned) and the oracle's marginal rays are left out of the comparison."""
+    import surfaces as S
+    pr = S.valley_problem(strata=256)
+    Pz = S.valley_heights()
+    plan = ffrt.Plan([pr])
+    P = plan.pack_cp([Pz])
+    stt = plan.new_stats()
+    plan.forward(P, stats=stt)
+    stats = plan.decode_stats(stt)[0]
+    ids = np.arange(pr.num_rays())
+    _say(f"[roots] valley: {len(ids)} rays, non-monotone searches {int(stats['n_nonmonotone'])}")
+    gpu = plan.trace_rays(0, P, ids).cpu().numpy()
+    ref = O.trace_rays(pr, Pz, ids)
+    o, d = S.glass_rays(pr, ids)
+    t1, t2 = S.valley_roots(o, d)
+    t_ap = S.aperture_exit(o, d)
+    ok = np.isfinite(t1)
+    entered = ref[:, 0] != O.MISS_ENTRY
+    two = entered & ok & (t1 > 0) & (t2 < t_ap - 1e-6) & (t2 - t1 > 0.2)
+    near = ok & (t2 - t1 <= 0.2) & (t1 < t_ap + 1e-6)
+    clear = (ref[:, 7] == 0) & ~near
+    assert int(stats["n_nonmonotone"]) > 0
+    assert two.sum() >= 1000, two.sum()
+    assert (gpu[clear, 0] == ref[clear, 0]).all(), int((gpu[clear, 0] != ref[clear, 0]).sum())
+    sel = two & clear
+    np.testing.assert_allclose(gpu[sel, 6], ref[sel, 6], rtol=0, atol=5e-5)
+    np.testing.assert_allclose(ref[sel, 6], t1[sel], rtol=0, atol=1e-9)
+    hit = clear & (ref[:, 0] == O.HIT)
+    np.testing.assert_allclose(gpu[hit, 1:3], ref[hit, 1:3], rtol=0, atol=2e-5 * (40.0 + np.abs(ref[hit, 1:3]).max()))
+    _say(f"[roots] valley: {int(two.sum())} rays with two roots inside the aperture, "
+         f"{int(sel.sum())} compared; status mismatches left out as near-tangent: "
+         f"{int((gpu[near, 0] != ref[near, 0]).sum())} of {int(near.sum())}")

@@ -13,6 +13,7 @@ import pytest
 from scipy.interpolate import BSpline
 
 import oracle as O
+import surfaces as S
 from paper_2302_12031_amd import workloads as W
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -360,33 +361,14 @@ def test_collimated_samples_one_per_cell(jitter):
     assert (S[:, 0] * 24).astype(int).tolist() == ku.tolist() and (S[:, 1] * 16).astype(int).tolist() == kv.tolist()
 
 
-def _valley(c0=2.0, kappa=0.5, n_u=8, n_v=4, p=3, r=5.0):
-    """Control heights that make the bicubic B-spline exactly h(x, y) = c0 + kappa x^2: with X linear
-    (X = (2u - 1) r), h is a quadratic g(u) = A + B u + C u^2 of u, reproduced by the control points given by its
-    polar form at the Greville knots: c_i = A + B s1_i / p + C s2_i / binom(p, 2), s1, s2 the first and second
-    elementary symmetric functions of the knots u_{i+1} .. u_{i+p} (Marsden's identity)."""
-    A, B, C = c0 + kappa * r * r, -4.0 * kappa * r * r, 4.0 * kappa * r * r
-    U = O.knots(p, n_u)
-    cps = []
-    for i in range(n_u):
-        k = U[i + 1:i + p + 1]
-        s1 = k.sum()
-        s2 = sum(k[a] * k[b] for a in range(p) for b in range(a + 1, p))
-        cps.append(A + B * s1 / p + C * s2 / (p * (p - 1) / 2))
-    return np.repeat(np.array(cps)[:, None], n_v, axis=1)
-
-
 def test_smallest_root_of_rays_that_cross_the_surface_twice():
     """The root problem of sec. 2.2.1 asks for the smallest positive root.  On the valley h = 2 + x^2 / 2 (an
     exact B-spline, checked first) rays from a wide cone cross the exit face, leave the glass and meet the
     rising wall again: f(t) = h(o + t d) - o_z - t d_z is a quadratic in t with two positive roots inside the
     aperture, known in closed form.  The oracle must return the smaller one (its scan for the first sign
     change), for every ray whose two roots are not within rounding of each other."""
-    pr = W.Problem(lens=W.Lens(n_u=8, n_v=4),
-                   source=W.Source(kind=W.POINT, grid_u=64, grid_v=64, jitter=1, pos=(-4.0, 0.0, -1.0),
-                                   half_angle=np.deg2rad(70.0), seed=4),
-                   detector=W.Detector(n_x=32, n_y=32, R_x=200.0, R_y=200.0, z_screen=40.0))
-    Pz = _valley()
+    pr = S.valley_problem()
+    Pz = S.valley_heights()
     xs = np.linspace(-5, 5, 23)
     for x in xs:
         for y in (-4.0, 0.3, 4.9):
@@ -394,20 +376,9 @@ def test_smallest_root_of_rays_that_cross_the_surface_twice():
     ids = np.arange(pr.num_rays())
     o, d = _glass_rays(pr, ids)
     out = O.trace_rays(pr, Pz, ids)
-    # f(t) = a t^2 + b t + c
-    a = 0.5 * d[:, 0] ** 2
-    b = d[:, 0] * o[:, 0] - d[:, 2]
-    c = 2.0 + 0.5 * o[:, 0] ** 2 - o[:, 2]
-    disc = b * b - 4 * a * c
-    ok = (disc > 0) & (a > 0)
-    sq = np.sqrt(np.where(ok, disc, 0.0))
-    t1 = np.where(ok, (-b - sq) / (2 * a), np.nan)
-    t2 = np.where(ok, (-b + sq) / (2 * a), np.nan)
-    # where the ray leaves the aperture prism
-    with np.errstate(divide="ignore", invalid="ignore"):
-        tx = np.where(d[:, 0] > 0, (5 - o[:, 0]) / d[:, 0], np.where(d[:, 0] < 0, (-5 - o[:, 0]) / d[:, 0], np.inf))
-        ty = np.where(d[:, 1] > 0, (5 - o[:, 1]) / d[:, 1], np.where(d[:, 1] < 0, (-5 - o[:, 1]) / d[:, 1], np.inf))
-    t_ap = np.minimum(tx, ty)
+    t1, t2 = S.valley_roots(o, d)
+    ok = np.isfinite(t1)
+    t_ap = S.aperture_exit(o, d)
     entered = out[:, 0] != O.MISS_ENTRY
     # both roots inside the aperture and further apart than the oracle's scan step (1/64 of a projected
     # knot span, at most ~0.07 here): the scan must stop at the first
@@ -781,16 +752,7 @@ def _mesh(p, m):
 
 
 def _glass_rays(p, ids):
-    """Origins on the entry face and directions inside the glass of point-source rays, rebuilt here from the
-    oracle's samples with the refraction pinned above (sec. 2.2.1)."""
-    S = O.samples(p, ids)
-    ca = 1.0 - (1.0 - np.cos(p.source.half_angle)) * S[:, 1]
-    sa = np.sqrt(1.0 - ca ** 2)
-    d0 = np.stack([np.cos(S[:, 0]) * sa, np.sin(S[:, 0]) * sa, ca], 1)
-    t0 = (p.lens.z_in - p.source.pos[2]) / d0[:, 2]
-    o = np.stack([S[:, 2] + t0 * d0[:, 0], S[:, 3] + t0 * d0[:, 1], np.full(len(ids), p.lens.z_in)], 1)
-    d = np.array([O.refract(x, [0.0, 0.0, 1.0], 1.0 / p.lens.n_lens) for x in d0])
-    return o, d
+    return S.glass_rays(p, ids)
 
 
 def _mesh_triangles(p, Pz, m):
