@@ -165,6 +165,18 @@ ffrt_status ffrt_plan_num_rays(const ffrt_plan* plan, int64_t* n);
  * does not depend on the order in which rays are added. */
 ffrt_status ffrt_forward(ffrt_plan* plan, const float* Pz, float* irr, ffrt_stats* stats, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): ffrt_forward without a caller workspace.  The plan need not have one
+ * set (ffrt_plan_create makes no HIP call).  Its descriptor tables, the bounds, the statistics slots and the
+ * fixed-point image live instead in a device array the library holds per GPU from module load until the
+ * process ends: 32 MiB, so the call returns FFRT_E_OOM, with the size it needs in ffrt_last_error(), for a
+ * plan whose images, control nets and tables do not fit (about 32 designs of 256 x 256 pixels).  Each call
+ * copies the plan's host tables into the array with hipMemcpyAsync on `stream` and clears the slots and the
+ * image with a kernel; it calls no allocating routine.  Every call on one GPU shares that array, whatever
+ * the plan or stream: calls that overlap in time on one GPU race, so issue them on one stream or order them.
+ * Results are those of ffrt_forward, bit for bit. */
+ffrt_status ffrt_forward_static(ffrt_plan* plan, const float* Pz, float* irr, ffrt_stats* stats, void* stream);
+
 /* Loss of sec. 2.5 per design and dL/dI.  loss: n_designs floats (NaN for a design without flux, whose
  * dL/dI is then zero and whose next Adam update is skipped); dL_dI: packed like irr. */
 ffrt_status ffrt_loss(ffrt_plan* plan, const float* irr, const float* target, float* loss, float* dL_dI,

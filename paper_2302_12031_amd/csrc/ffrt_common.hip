@@ -4,6 +4,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "ffrt_internal.h"
 #include "loss.hpp"
@@ -402,7 +403,51 @@ __global__ void k_rng(uint64_t state0, uint64_t first, int64_t n, uint64_t* out)
     if (i < n) out[i] = mix64(state0 + (first + (uint64_t)i + 1) * GAMMA);
 }
 
+// Fill n 32-bit words with v (a kernel, not a memset node, so that graph captures of its callers replay it
+// like any other kernel).
+__global__ void k_fill_u32(uint32_t* p, int64_t n, uint32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Device memory owned by the library for the entry points that take no caller workspace: one copy per GPU,
+// resident from module load until the process ends.  Host code never uses this name as an address (on the
+// host it is only a stand-in for the symbol): static_scratch() resolves each device's own address once.
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
 }  // namespace
+
+hipError_t static_scratch(void** ptr, int* num_cu) {
+    constexpr int MAX_DEV = 64;
+    static std::mutex mu;
+    static void* addr[MAX_DEV] = {};
+    static int ncu[MAX_DEV] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= MAX_DEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        int n = 0;
+        e = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+        ncu[dev] = n > 0 ? n : 256;
+    }
+    *ptr = addr[dev];
+    *num_cu = ncu[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t g = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)g), dim3(256), 0, s, static_cast<uint32_t*>(p), n, v);
+    return hipGetLastError();
+}
 
 uint64_t splitmix_state0(uint64_t seed, uint64_t stream_id) { return mix64(seed + stream_id * GAMMA); }
 

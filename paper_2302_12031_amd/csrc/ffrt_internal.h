@@ -15,6 +15,7 @@ constexpr int N_KG = 8;               // kernel groups: bit 0 point source, bit 
 constexpr int RPT_OF_SHAPE[N_SHAPES] = {1, 2, 4, 8, 16};
 constexpr int NSLOT = 64;             // per-design partial-statistics slots (spreads the counter atomics)
 constexpr size_t ROOTS_CAP = size_t(1) << 30;  // bytes of the per-ray exit-root buffer of a plan, at most
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(32) << 20;  // library-owned device array per GPU (ffrt_forward_static)
 
 // Ray status codes (same meaning as the public ffrt_trace_rays status).
 enum : int { ST_HIT = 0, ST_MISS_ENTRY = 1, ST_SIDE_WALL = 2, ST_TIR = 3, ST_OFF_SCREEN = 4 };
@@ -219,6 +220,12 @@ hipError_t launch_adam(const DesignDev* designs, int n_designs, float* Pz, const
                        float* v, int32_t* t, const int32_t* valid, ffrt_adam_hparams hp, hipStream_t s);
 hipError_t launch_rng(uint64_t seed, uint64_t stream_id, uint64_t first, int64_t n, uint64_t* out,
                       hipStream_t s);
+
+// Address of this device's copy of the library's static scratch array (STATIC_SCRATCH_BYTES, 256-byte
+// aligned), resolved with hipGetSymbolAddress on the first call per device, and the device's CU count.
+hipError_t static_scratch(void** ptr, int* num_cu);
+// n 32-bit words at p set to v by a kernel on stream s.
+hipError_t launch_fill_u32(void* p, int64_t n, uint32_t v, hipStream_t s);
 
 // Host-side SplitMix64 state (same published definition as the device generator).
 uint64_t splitmix_state0(uint64_t seed, uint64_t stream_id);

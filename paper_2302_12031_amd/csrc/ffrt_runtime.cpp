@@ -641,6 +641,50 @@ ffrt_status ffrt_forward(ffrt_plan* plan, const float* Pz, float* irr, ffrt_stat
     return run_forward(plan, Pz, irr, stats, (hipStream_t)stream);
 }
 
+ffrt_status ffrt_forward_static(ffrt_plan* plan, const float* Pz, float* irr, ffrt_stats* stats, void* stream) {
+    if (!plan) return fail(FFRT_E_ARG, "null plan");
+    if (!Pz || !irr) return fail(FFRT_E_ARG, "null buffer");
+    // the forward reads the plan's tables and uses the accumulators up to the fixed-point image; the layout is
+    // the workspace's, so everything it touches ends where the gradient accumulator would begin
+    const size_t need = plan->off_gacc;
+    if (need > STATIC_SCRATCH_BYTES) {
+        char b[160];
+        snprintf(b, sizeof b, "ffrt_forward_static: the plan needs %zu bytes of scratch, at most %zu are available",
+                 need, STATIC_SCRATCH_BYTES);
+        return fail(FFRT_E_OOM, b);
+    }
+    void* base = nullptr;
+    int ncu = 0;
+    HIP_TRY(static_scratch(&base, &ncu));
+    hipStream_t s = (hipStream_t)stream;
+    char* saved_ws = plan->ws;
+    const size_t saved_bytes = plan->ws_bytes;
+    const int saved_cu = plan->num_cu;
+    plan->ws = static_cast<char*>(base);
+    plan->ws_bytes = STATIC_SCRATCH_BYTES;
+    plan->num_cu = ncu;
+    // the array keeps whatever the last call on this device left there: write this plan's tables and clear
+    // the statistics slots and the fixed-point image, which the forward expects at zero
+    ffrt_status st = FFRT_OK;
+    hipError_t e = hipMemcpyAsync(plan->d_designs(), plan->dd.data(), sizeof(DesignDev) * plan->nd,
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !plan->knots.empty())
+        e = hipMemcpyAsync(plan->d_knots(), plan->knots.data(), sizeof(float) * plan->knots.size(),
+                           hipMemcpyHostToDevice, s);
+    for (int sh = 0; sh < N_SHAPES && e == hipSuccess; ++sh)
+        for (int kg = 0; kg < N_KG && e == hipSuccess; ++kg)
+            e = hipMemcpyAsync(plan->d_bmap(sh, kg), plan->bmaps[sh][kg].data(), sizeof(BlockMap) * plan->nd,
+                               hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_fill_u32(plan->d_slots(), (int64_t)(sizeof(ffrt_stats) / 4) * NSLOT * plan->nd, 0u, s);
+    if (e == hipSuccess) e = launch_fill_u32(plan->d_img64(), 2 * plan->total_img, 0u, s);
+    if (e != hipSuccess) st = hip_fail(e, "ffrt_forward_static set-up");
+    if (!st) st = run_forward(plan, Pz, irr, stats, s);
+    plan->ws = saved_ws;
+    plan->ws_bytes = saved_bytes;
+    plan->num_cu = saved_cu;
+    return st;
+}
+
 ffrt_status ffrt_loss(ffrt_plan* plan, const float* irr, const float* target, float* loss, float* dL_dI,
                       void* stream) {
     if (!ready(plan)) return fail(FFRT_E_STATE, "no workspace set");

@@ -74,7 +74,7 @@ HEADER_FUNCTIONS = [
     "ffrt_trace_rays", "ffrt_rng", "ffrt_status_string", "ffrt_last_error",
     "ffrt_reparam_apply", "ffrt_reparam_grad", "ffrt_step_reparam", "ffrt_graph_capture_reparam",
     "ffrt_plan_control_xy", "ffrt_mlp_layout", "ffrt_mlp_forward", "ffrt_mlp_backward", "ffrt_step_mlp",
-    "ffrt_graph_capture_mlp", "ffrt_plan_time_mlp",
+    "ffrt_graph_capture_mlp", "ffrt_plan_time_mlp", "ffrt_forward_static",
 ]
 
 _lib = None
@@ -98,6 +98,7 @@ def lib():
             "ffrt_plan_num_designs": [vp, P(i32)],
             "ffrt_plan_num_rays": [vp, P(i64)],
             "ffrt_forward": [vp, vp, vp, vp, vp],
+            "ffrt_forward_static": [vp, vp, vp, vp, vp],
             "ffrt_loss": [vp, vp, vp, vp, vp, vp],
             "ffrt_loss_f64": [vp, vp, vp, vp, vp],
             "ffrt_adjoint": [vp, vp, vp, vp, vp],
@@ -266,6 +267,17 @@ class Plan:
             irr = torch.empty(self.total_img, dtype=torch.float32, device=self.device)
         self._f32(irr, self.total_img, "irr")
         _check(lib().ffrt_forward(self.h, _ptr(Pz), _ptr(irr), _ptr(stats), _stream(stream)), "ffrt_forward")
+        return irr
+
+    def forward_static(self, Pz, irr=None, stats=None, stream=None):
+        """ffrt_forward_static: the forward in the library's static device array instead of the plan's
+        workspace (for callers that cannot allocate; calls on one GPU must not overlap)."""
+        self._f32(Pz, self.total_cp, "Pz")
+        if irr is None:
+            irr = torch.empty(self.total_img, dtype=torch.float32, device=self.device)
+        self._f32(irr, self.total_img, "irr")
+        _check(lib().ffrt_forward_static(self.h, _ptr(Pz), _ptr(irr), _ptr(stats), _stream(stream)),
+               "ffrt_forward_static")
         return irr
 
     def loss(self, irr, target, loss=None, dLdI=None, stream=None):
