@@ -67,6 +67,24 @@ struct DesignDev {
     float delta_min;
 };
 
+// The same design's parameters in double precision, for the adjoint's double-precision re-trace of rays whose
+// pathwise derivative single precision cannot resolve (see k_adjoint_fp64).
+struct DesignDev64 {
+    double r_x, r_y, z_in, n_lens, R0, w0;
+    double sxu, syv, ubar0, vbar0;           // knot units per mm and at x = 0
+    double pos_x, pos_y, pos_z, omc;         // point source (emitter-grid centre); omc = 1 - cos(phi_max)
+    double ex0, edx, ey0, edy;               // emitter grid
+    double Rx, Ry, wx, wy, z_screen, alpha, edge_x, edge_y;
+};
+
+// A ray queued by the adjoint for the double-precision re-trace: its design, its exit root in single
+// precision (point sources; the start of the double-precision Newton polish) and its id.
+struct QEntry {
+    int32_t design;
+    float t;
+    int64_t id;
+};
+
 // Kernel group of a design: the trace kernels are instantiated per source kind and intersection mode.
 inline int kind_group(const DesignDev& d) {
     return (d.entry_ff ? 4 : 0) + (d.mesh_u ? 2 : 0) + (d.kind != 0 ? 1 : 0);
@@ -139,7 +157,17 @@ struct TraceArgs {
     // root_off + ray index (-1: no hit).  The forward stores them and the adjoint of the same step reads
     // them instead of searching again; null: every kernel searches.
     float* roots;
+    // Adjoint, kernel groups 0 and 1: rays whose derivative single precision cannot resolve (landing within
+    // rounding of a pixel edge, near total internal reflection) are left out and queued for the
+    // double-precision re-trace: logical block b of the launch writes up to queue_cap(shape) entries at
+    // queue + (qbase + b) queue_cap and their number at qcount[qbase + b].  Null: no queue.
+    QEntry* queue;
+    int32_t* qcount;
+    int64_t qbase;
 };
+
+// Queue capacity per logical block of the adjoint: 1/64 of its rays (the re-traced rays are ~0.4 %).
+__host__ __device__ constexpr int queue_cap(int shape) { return (WG << shape) / 64; }  // RPT = 2^shape
 
 struct FwdCfg { int shape; int tile; int persistent; const char* name; };
 struct AdjCfg { int shape; int butterfly; int persistent; const char* name; };
@@ -163,10 +191,12 @@ constexpr AdjCfg ADJ_CFGS[] = {
 constexpr int N_FWD_CFGS = sizeof(FWD_CFGS) / sizeof(FWD_CFGS[0]);
 constexpr int N_ADJ_CFGS = sizeof(ADJ_CFGS) / sizeof(ADJ_CFGS[0]);
 
-// Launchers of the templated trace kernels, one set per compiled (P, Q, NU).
+// Launchers of the templated trace kernels, one set per compiled (P, Q, NU).  adjoint_fp64 re-traces the queued
+// rays of nblocks logical blocks (queue and qcount as in TraceArgs, qbase 0) in double precision.
 struct KernelSet {
     hipError_t (*forward)(const TraceArgs&, int shape, int grid, hipStream_t);
     hipError_t (*adjoint)(const TraceArgs&, int shape, int grid, hipStream_t);
+    hipError_t (*adjoint_fp64)(const TraceArgs&, const DesignDev64* d64, int shape, int64_t nblocks, hipStream_t);
     hipError_t (*trace_rays)(const TraceArgs&, int design, const int64_t* ids, int64_t n, float* out8,
                              hipStream_t);
 };

@@ -62,6 +62,7 @@ struct ffrt_plan {
     int nd = 0, P = 3, Q = 3, NU = 3;
     const KernelSet* ks = nullptr;
     std::vector<DesignDev> dd;
+    std::vector<DesignDev64> dd64;
     std::vector<int64_t> cp_off, img_off, mlp_off[2];
     int64_t total_cp = 0, total_img = 0, total_rays = 0;
     int max_cp = 0, max_kt = 0, loss_lb = 1, max_spans = 0;
@@ -80,7 +81,7 @@ struct ffrt_plan {
     size_t off_designs = 0, off_bounds = 0, off_sb = 0, off_valid = 0, off_knots = 0, off_bmap = 0, off_slots = 0;
     size_t need = 0;
     size_t off_lpart = 0, off_img64 = 0, off_gacc = 0, off_gmax = 0, off_dldi = 0, off_mlpoff = 0, off_mlpvec = 0,
-           off_roots = 0;
+           off_roots = 0, off_d64 = 0, off_queue = 0, off_qcount = 0;
     int num_cu = 256;
     int fwd_cfg = 0, adj_cfg = 0;
     hipGraph_t graph = nullptr;
@@ -103,6 +104,9 @@ struct ffrt_plan {
     int64_t* d_mlpoff(int arch) const { return reinterpret_cast<int64_t*>(ws + off_mlpoff) + (size_t)arch * (nd + 1); }
     float* d_mlpvec(int k) const { return reinterpret_cast<float*>(ws + off_mlpvec) + (size_t)k * total_cp; }
     float* d_roots() const { return roots_on ? reinterpret_cast<float*>(ws + off_roots) : nullptr; }
+    DesignDev64* d_d64() const { return reinterpret_cast<DesignDev64*>(ws + off_d64); }
+    QEntry* d_queue() const { return reinterpret_cast<QEntry*>(ws + off_queue); }
+    int32_t* d_qcount() const { return reinterpret_cast<int32_t*>(ws + off_qcount); }
 };
 
 namespace {
@@ -254,6 +258,49 @@ DesignDev make_design(const ffrt_problem& pr, int64_t cp_off, int64_t img_off, i
     return d;
 }
 
+// The design's parameters in double precision, for the adjoint's double-precision re-trace (the same
+// quantities as make_design without the single-precision rounding).
+DesignDev64 make_design64(const ffrt_problem& pr) {
+    DesignDev64 d;
+    std::memset(&d, 0, sizeof d);
+    const ffrt_lens& L = pr.lens;
+    const ffrt_source& S = pr.src;
+    const ffrt_detector& D = pr.det;
+    d.r_x = L.r_x;
+    d.r_y = L.r_y;
+    d.z_in = L.z_in;
+    d.n_lens = L.n_lens;
+    const double r0 = (L.n_lens - 1.0) / (L.n_lens + 1.0);
+    d.R0 = r0 * r0;
+    const int64_t n = (int64_t)S.grid_u * S.grid_v * (S.kind == 2 ? (int64_t)S.emit_nx * S.emit_ny : 1);
+    d.w0 = 1.0 / (double)n;
+    d.sxu = (double)(L.n_u - L.p) / (2.0 * L.r_x);
+    d.syv = (double)(L.n_v - L.q) / (2.0 * L.r_y);
+    d.ubar0 = 0.5 * (double)(L.n_u - L.p);
+    d.vbar0 = 0.5 * (double)(L.n_v - L.q);
+    d.pos_x = S.pos[0];
+    d.pos_y = S.pos[1];
+    d.pos_z = S.pos[2];
+    d.omc = 1.0 - std::cos(S.half_angle);
+    if (S.kind == 2 && S.emit_nx > 1) {
+        d.ex0 = -0.5 * S.emit_wx;
+        d.edx = S.emit_wx / (S.emit_nx - 1);
+    }
+    if (S.kind == 2 && S.emit_ny > 1) {
+        d.ey0 = -0.5 * S.emit_wy;
+        d.edy = S.emit_wy / (S.emit_ny - 1);
+    }
+    d.wx = 2.0 * D.R_x / D.n_x;
+    d.wy = 2.0 * D.R_y / D.n_y;
+    d.Rx = D.ghost ? D.R_x + 0.5 * (D.nu_x - 1) * d.wx : D.R_x;
+    d.Ry = D.ghost ? D.R_y + 0.5 * (D.nu_y - 1) * d.wy : D.R_y;
+    d.z_screen = D.z_screen;
+    d.alpha = D.alpha;
+    d.edge_x = std::exp(-D.alpha * 0.25 * D.nu_x * D.nu_x);
+    d.edge_y = std::exp(-D.alpha * 0.25 * D.nu_y * D.nu_y);
+    return d;
+}
+
 bool ready(ffrt_plan* p) { return p && p->ws; }
 
 TraceArgs make_args(ffrt_plan* pl, int shape, int kg) {
@@ -309,6 +356,9 @@ ffrt_status launch_forward(ffrt_plan* pl, const float* Pz, bool stats, hipStream
 // same Pz must have filled.
 ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hipStream_t s, bool roots = false) {
     const AdjCfg& c = ADJ_CFGS[pl->adj_cfg];
+    // the rays of kernel groups 0 and 1 whose derivative single precision cannot resolve are queued per
+    // logical block (group 1's blocks after group 0's) and re-traced in double precision afterwards
+    const int64_t qblocks = pl->nblocks[c.shape][0] + pl->nblocks[c.shape][1];
     for (int kg = 0; kg < N_KG; ++kg) {
         if (pl->nblocks[c.shape][kg] == 0) continue;
         TraceArgs A = make_args(pl, c.shape, kg);
@@ -318,7 +368,22 @@ ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hi
         A.gmax = pl->d_gmax();
         A.butterfly = c.butterfly;
         A.roots = roots && kg == 1 ? pl->d_roots() : nullptr;
+        if (kg <= 1) {
+            A.queue = pl->d_queue();
+            A.qcount = pl->d_qcount();
+            A.qbase = kg == 1 ? pl->nblocks[c.shape][0] : 0;
+        }
         HIP_TRY(pl->ks->adjoint(A, c.shape, grid_for(pl, c.shape, kg, c.persistent), s));
+    }
+    if (qblocks > 0) {
+        TraceArgs A = make_args(pl, c.shape, 0);
+        A.Pz = Pz;
+        A.dLdI = dLdI;
+        A.gacc = pl->d_gacc();
+        A.gmax = pl->d_gmax();
+        A.queue = pl->d_queue();
+        A.qcount = pl->d_qcount();
+        HIP_TRY(pl->ks->adjoint_fp64(A, pl->d_d64(), c.shape, qblocks, s));
     }
     return FFRT_OK;
 }
@@ -479,6 +544,7 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
         int kt_v = (int)pl->knots.size();
         build_knot_table(pr.lens.q, pr.lens.n_v - pr.lens.q, pl->knots);
         DesignDev d = make_design(pr, cp, img, kt_u, kt_v);
+        pl->dd64.push_back(make_design64(pr));
         d.root_off = -1;
         if (kind_group(d) == 1) {
             d.root_off = pl->root_rays;
@@ -554,6 +620,22 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
     off = align256(off + sizeof(unsigned long long) * (size_t)pl->total_cp);
     pl->off_gmax = off;
     off = align256(off + sizeof(uint32_t) * n_designs);
+    // the adjoint's double-precision re-trace: design parameters, and a queue segment of queue_cap / 4 rays
+    // per wave of every logical block (sized over all kernel groups, of which 0 and 1 use it, for the adjoint
+    // shape that needs most)
+    pl->off_d64 = off;
+    off = align256(off + sizeof(DesignDev64) * n_designs);
+    int64_t qent = 0, qblk = 0;
+    for (int sh = 0; sh < N_SHAPES; ++sh) {
+        int64_t nb = 0;
+        for (int kg = 0; kg < N_KG; ++kg) nb += pl->nblocks[sh][kg];
+        qent = std::max<int64_t>(qent, nb * queue_cap(sh));
+        qblk = std::max<int64_t>(qblk, nb);
+    }
+    pl->off_queue = off;
+    off = align256(off + sizeof(QEntry) * (size_t)qent);
+    pl->off_qcount = off;
+    off = align256(off + sizeof(int32_t) * 4 * (size_t)qblk);
     pl->off_dldi = off;  // dL/dI of a step whose caller does not want it
     off = align256(off + sizeof(float) * (size_t)pl->total_img);
     pl->off_mlpoff = off;  // parameter offsets of the control-point generators (dense, sparse)
@@ -596,6 +678,7 @@ ffrt_status ffrt_plan_set_workspace(ffrt_plan* plan, void* dev_ptr, size_t bytes
     HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     plan->num_cu = ncu > 0 ? ncu : 256;
     HIP_TRY(hipMemcpy(plan->d_designs(), plan->dd.data(), sizeof(DesignDev) * plan->nd, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(plan->d_d64(), plan->dd64.data(), sizeof(DesignDev64) * plan->nd, hipMemcpyHostToDevice));
     std::vector<int32_t> ones(plan->nd, 1);
     HIP_TRY(hipMemcpy(plan->d_valid(), ones.data(), sizeof(int32_t) * plan->nd, hipMemcpyHostToDevice));
     // accumulators and counters that the kernels expect to be zero on entry (and leave zero on exit)

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "ffrt_internal.h"
 #include "loss.hpp"
 #include "wave.hpp"
@@ -788,16 +790,18 @@ __device__ __forceinline__ void mesh_locate(const DesignDev& D, float x, float y
 struct ExitState {
     int status;
     float nxh, nyh, nzh, inv_m;   // unit normal and 1/|m|
+    float k;                      // Snell discriminant 1 - n^2 sin^2 (negative: TIR)
     float c, sk, beta;            // d.n_hat, sqrt(k), sqrt(k) - n c
     float ex, ey, ez;             // direction in air
     float tau, T;                 // screen distance parameter, Schlick transmittance
-    float X, Y, w;
+    float X, Y, w;                // landing (NaN when the ray does not reach the screen plane)
 };
 
 __device__ __forceinline__ ExitState exit_face(const DesignDev& D, float qx, float qy, float qz, float dx,
                                                float dy, float dz, float hx, float hy, float w1) {
     ExitState E;
     E.status = ST_HIT;
+    E.X = E.Y = __builtin_nanf("");
     float inv = rsqrtf(hx * hx + hy * hy + 1.0f);
     E.inv_m = inv;
     E.nxh = -hx * inv;
@@ -809,6 +813,7 @@ __device__ __forceinline__ ExitState exit_face(const DesignDev& D, float qx, flo
     float s2 = cx * cx + cy * cy + cz * cz;
     float n = D.n_lens;
     float k = 1.0f - n * n * s2;
+    E.k = k;
     if (!(k >= 0.0f)) {
         E.status = ST_TIR;
         return E;
@@ -993,18 +998,41 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
 }
 
 // ------------------------------------------------------------------------------------------------
+// Rays whose pathwise derivative single precision cannot resolve.  The derivative of a ray's contribution
+// jumps where its landing crosses a pixel edge (for odd nu the filter's support edges are pixel edges, where
+// the filter is only continuous) or the screen edge, and it grows as 1 / sqrt(k) towards total internal
+// reflection.  A landing carries ~1e-5 pixel of single-precision error (at most ~1e-3 on the stated
+// workloads, 4e-4 for 1 ray in 10^4), so single precision may take the other side of such a kink.  The adjoint (flat entry face,
+// exact root) leaves these rays out and queues them; k_adjoint_fp64 re-traces them in double precision from
+// their samples and adds their contributions to the same fixed-point sums.
+// ------------------------------------------------------------------------------------------------
+constexpr float FLAG_EDGE_PX = 5e-4f;   // landing within this many pixel widths of a pixel edge
+constexpr float FLAG_K_HIT = 1e-4f;     // a kept ray with k below this: derivative error above ~1e-3 of it
+constexpr float FLAG_K_TIR = 1e-5f;     // a ray dropped for TIR with k above -this may be kept in double
+
+__device__ __forceinline__ bool near_pixel_edge(float X, float R, float inv_w, int n) {
+    const float px = (X + R) * inv_w;
+    const float r = rintf(px);
+    return r >= 0.0f && r <= (float)n && fabsf(px - r) < FLAG_EDGE_PX;
+}
+
+// ------------------------------------------------------------------------------------------------
 // One ray, adjoint: re-trace, gather dL/dI over the filter window, reverse sweep.  Returns false when the
 // ray does not reach the screen.  With tload (point sources, exact root, flat entry) the exit root comes from
 // the forward of the same step instead of the search.  g[] receives dL/dP for control point (ku + a, kv + b) at a * (Q+1) + b;
 // with a freeform entry face gin[] receives dL/dP of the entry net's points (cku_in + a, ckv_in + b).
 // ------------------------------------------------------------------------------------------------
-template <int P, int Q, int NU, int KIND>
+struct NoQueue {
+    __device__ bool operator()(float) const { return false; }
+};
+
+template <int P, int Q, int NU, int KIND, class Enqueue = NoQueue>
 __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDev& B, const float* sP,
                                               const float* sKu, const float* sKv, const float* sS,
                                               const float* __restrict__ G,
                                               int e, int ku, int kv, int64_t id, int& cku, int& ckv,
                                               float* g, int& cku_in, int& ckv_in, float* gin,
-                                              const float* tload = nullptr) {
+                                              const float* tload = nullptr, Enqueue enqueue = Enqueue()) {
     constexpr bool point = (KIND & 1) != 0, MESH = (KIND & 2) != 0, ENTRY = (KIND & 4) != 0;
     constexpr bool SEARCH = point || ENTRY;
     EntryHit EH;
@@ -1069,6 +1097,14 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
     }
     float qz = SEARCH ? r.oz + t * r.dz : (MESH ? mqz : S.h + B.zref);
     ExitState E = exit_face(D, qx, qy, qz, r.dx, r.dy, r.dz, S.hx, S.hy, r.w);
+    if constexpr ((KIND & 6) == 0) {
+        // a derivative single precision cannot resolve (see FLAG_EDGE_PX): enqueue() may take the ray for the
+        // double-precision re-trace (with its root), which then makes the contribution instead of this sweep
+        const bool flag = E.status == ST_TIR ? E.k > -FLAG_K_TIR
+                                             : E.k < FLAG_K_HIT || near_pixel_edge(E.X, D.Rx, D.inv_wx, D.nx) ||
+                                                   near_pixel_edge(E.Y, D.Ry, D.inv_wy, D.ny);
+        if (flag && !D.box && enqueue(t)) return false;
+    }
     if (E.status != ST_HIT) return false;
 
     // ---- splat, reverse: I_ij += w Fx_i Fy_j
@@ -1234,6 +1270,358 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
         ckv_in = Si.kv;
     }
     return true;
+}
+
+// B-spline basis of span k (0-based) of nspan on the clamped uniform knots, in double precision, with the
+// local knots and reciprocals of the Cox-de Boor recursion formed in double (the knot table in LDS holds
+// single-precision reciprocals).  t = ubar - k in [0, 1].
+template <int P, bool D2>
+__device__ inline void basis_f64(int k, int nspan, double t, double* N, double* dN, double* d2N) {
+    if (k >= P - 1 && k <= nspan - P) {  // unclamped knots: the uniform B-spline
+        span_basis<P, D2, true, double>(nullptr, t, N, dN, d2N);
+        return;
+    }
+    int kap[2 * P];
+#pragma unroll
+    for (int i = 0; i < 2 * P; ++i) kap[i] = min(max(i + 1 - P, -k), nspan - k);
+    auto KAP = [&](int o) { return (double)kap[o + P - 1]; };
+    auto REC = [&](int deg, int j) {  // 1 / (kap(j) - kap(j - deg)), a knot difference of 0 .. P units
+        const int d = kap[j + P - 1] - kap[j - deg + P - 1];
+        return d == 1 ? 1.0 : d == 2 ? 0.5 : d == 3 ? 1.0 / 3.0 : d == 4 ? 0.25 : d == 5 ? 0.2 : 0.0;
+    };
+    double tb[P + 1][P + 1];
+    tb[0][0] = 1.0;
+#pragma unroll
+    for (int deg = 1; deg <= P; ++deg) {
+#pragma unroll
+        for (int m = 0; m <= deg; ++m) {
+            double acc = 0.0;
+            if (m >= 1) acc += (t - KAP(m - deg)) * REC(deg, m) * tb[deg - 1][m - 1];
+            if (m <= deg - 1) acc += (KAP(m + 1) - t) * REC(deg, m + 1) * tb[deg - 1][m];
+            tb[deg][m] = acc;
+        }
+    }
+#pragma unroll
+    for (int m = 0; m <= P; ++m) {
+        N[m] = tb[P][m];
+        const double a = m >= 1 ? REC(P, m) * tb[P - 1][m - 1] : 0.0;
+        const double b = m <= P - 1 ? REC(P, m + 1) * tb[P - 1][m] : 0.0;
+        dN[m] = (double)P * (a - b);
+    }
+    if constexpr (D2) {
+        if constexpr (P >= 2) {
+            double d1[P];
+#pragma unroll
+            for (int m = 0; m <= P - 1; ++m) {
+                const double a = m >= 1 ? REC(P - 1, m) * tb[P - 2][m - 1] : 0.0;
+                const double b = m <= P - 2 ? REC(P - 1, m + 1) * tb[P - 2][m] : 0.0;
+                d1[m] = (double)(P - 1) * (a - b);
+            }
+#pragma unroll
+            for (int m = 0; m <= P; ++m) {
+                const double a = m >= 1 ? REC(P, m) * d1[m - 1] : 0.0;
+                const double b = m <= P - 1 ? REC(P, m + 1) * d1[m] : 0.0;
+                d2N[m] = (double)P * (a - b);
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m <= P; ++m) d2N[m] = 0.0;
+        }
+    }
+}
+
+// Surface and derivatives in double precision from the device control heights (absolute), on the span
+// product containing (x, y).
+template <int P, int Q, bool D2>
+__device__ inline void surface_f64(const DesignDev& D, const DesignDev64& E, const float* __restrict__ Pz, double x,
+                                   double y, SurfEval<P, Q, double>& S) {
+    const double ub = x * E.sxu + E.ubar0, vb = y * E.syv + E.vbar0;
+    const int ku = min(max((int)floor(ub), 0), D.nsu - 1), kv = min(max((int)floor(vb), 0), D.nsv - 1);
+    S.ku = ku;
+    S.kv = kv;
+    basis_f64<P, D2>(ku, D.nsu, ub - (double)ku, S.Nu, S.dNu, S.d2Nu);
+    basis_f64<Q, D2>(kv, D.nsv, vb - (double)kv, S.Nv, S.dNv, S.d2Nv);
+    const float* row = Pz + D.cp_off + (int64_t)ku * D.n_v + kv;
+    double h = 0.0, hu = 0.0, hv = 0.0, huu = 0.0, huv = 0.0, hvv = 0.0;
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+#pragma unroll
+        for (int b = 0; b <= Q; ++b) {
+            const double pz = (double)row[a * D.n_v + b];
+            r0 += S.Nv[b] * pz;
+            r1 += S.dNv[b] * pz;
+            if constexpr (D2) r2 += S.d2Nv[b] * pz;
+        }
+        h += S.Nu[a] * r0;
+        hu += S.dNu[a] * r0;
+        hv += S.Nu[a] * r1;
+        if constexpr (D2) {
+            huu += S.d2Nu[a] * r0;
+            huv += S.dNu[a] * r1;
+            hvv += S.Nu[a] * r2;
+        }
+    }
+    S.h = h;
+    S.hx = hu * E.sxu;
+    S.hy = hv * E.syv;
+    if constexpr (D2) {
+        S.hxx = huu * E.sxu * E.sxu;
+        S.hxy = huv * E.sxu * E.syv;
+        S.hyy = hvv * E.syv * E.syv;
+    }
+}
+
+// The normalised filter of one axis and its derivative in double precision (as filter_axis).
+template <int NU>
+__device__ inline int filter_axis_f64(double X, double R, double w, int n, double alpha, double edge, double* F,
+                                      double* dF) {
+    constexpr int H = (NU - 1) / 2;
+    int i0 = (int)floor((X + R) / w);
+    i0 = min(max(i0, 0), n - 1);
+    const double delta = (X - (((double)i0 + 0.5) * w - R)) / w;
+    double S = 0.0, Sp = 0.0, fp[NU];
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+        const int i = i0 + m - H;
+        const double dm = delta - (double)(m - H);
+        const bool in = i >= 0 && i < n && fabs(dm) < 0.5 * NU;
+        const double e = exp(-alpha * dm * dm);
+        F[m] = in ? e - edge : 0.0;
+        fp[m] = in ? -2.0 * alpha * dm * e / w : 0.0;
+        S += F[m];
+        Sp += fp[m];
+    }
+#pragma unroll
+    for (int m = 0; m < NU; ++m) {
+        F[m] /= S;
+        dF[m] = (fp[m] - F[m] * Sp) / S;
+    }
+    return i0;
+}
+
+// One queued ray in double precision: the whole trace from its sample (flat entry face, exact root polished
+// from the single-precision one by Newton steps on the double-precision surface) and the reverse sweep of
+// trace_adjoint.  Returns false when, in double precision, the ray does not reach the screen; else g[] holds
+// dL/dP of the control points (ku + a, kv + b) at a (Q+1) + b.
+template <int P, int Q, int NU>
+__device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, const float* __restrict__ Pz,
+                                  const float* __restrict__ G, int64_t id, float t32, int& cku, int& ckv, double* g) {
+    const int64_t per = (int64_t)D.grid_u * D.grid_v;
+    const int e = (int)(id / per);
+    const int64_t rr = id - (int64_t)e * per;
+    const int ku = (int)(rr / D.grid_v), kv = (int)(rr - (rr / D.grid_v) * D.grid_v);
+    float x1f = 0.5f, x2f = 0.5f;
+    if (D.jitter) two_uniforms(splitmix_at(D.rng_state0, (uint64_t)id), x1f, x2f);  // exact 24-bit values
+    const double x1 = x1f, x2 = x2f;
+    const bool point = D.kind != 0;
+    double ox, oy, oz, dx, dy, dz, w1;
+    if (!point) {
+        ox = (2.0 * (((double)ku + x1) / (double)D.grid_u) - 1.0) * E.r_x;
+        oy = (2.0 * (((double)kv + x2) / (double)D.grid_v) - 1.0) * E.r_y;
+        oz = E.z_in;
+        dx = dy = 0.0;
+        dz = 1.0;
+        w1 = D.fresnel ? E.w0 * (1.0 - E.R0) : E.w0;
+    } else {
+        double sth, cth;
+        sincospi(2.0 * ((double)ku + x1) / (double)D.grid_u, &sth, &cth);
+        const double ao = ((double)kv + x2) / (double)D.grid_v * E.omc;
+        const double cphi = 1.0 - ao, sphi = sqrt(ao * (2.0 - ao));
+        double px = E.pos_x, py = E.pos_y;
+        if (D.kind == 2) {
+            const int ix = e / D.emit_ny, iy = e - ix * D.emit_ny;
+            px += E.ex0 + (double)ix * E.edx;
+            py += E.ey0 + (double)iy * E.edy;
+        }
+        const double t0 = (E.z_in - E.pos_z) / cphi;
+        ox = px + t0 * cth * sphi;
+        oy = py + t0 * sth * sphi;
+        oz = E.z_in;
+        if (fabs(ox) > E.r_x || fabs(oy) > E.r_y) return false;
+        const double eta = 1.0 / E.n_lens;
+        dx = eta * cth * sphi;
+        dy = eta * sth * sphi;
+        dz = sqrt(1.0 - eta * eta * sphi * sphi);
+        w1 = E.w0;
+        if (D.fresnel) {
+            const double m = 1.0 - cphi, m2 = m * m;
+            w1 *= 1.0 - (E.R0 + (1.0 - E.R0) * m2 * m2 * m);
+        }
+    }
+    SurfEval<P, Q, double> S;
+    double t = 0.0, qx = ox, qy = oy, qz;
+    if (point) {
+        t = (double)t32;
+        for (int it = 0; it < 2; ++it) {  // from ~1e-6 relative: ~1e-12 after one step, rounding after two
+            surface_f64<P, Q, false>(D, E, Pz, ox + t * dx, oy + t * dy, S);
+            const double f = S.h - oz - t * dz, fp = S.hx * dx + S.hy * dy - dz;
+            if (!(fp < 0.0)) break;
+            t -= f / fp;
+        }
+        qx = ox + t * dx;
+        qy = oy + t * dy;
+        qz = oz + t * dz;
+        surface_f64<P, Q, true>(D, E, Pz, qx, qy, S);
+    } else {
+        surface_f64<P, Q, false>(D, E, Pz, qx, qy, S);
+        qz = S.h;
+    }
+    // ---- exit face: vector Snell, TIR dropped, Schlick with the air-side cosine, screen
+    const double n = E.n_lens;
+    const double inv_m = 1.0 / sqrt(S.hx * S.hx + S.hy * S.hy + 1.0);
+    const double nxh = -S.hx * inv_m, nyh = -S.hy * inv_m, nzh = inv_m;
+    const double c = dx * nxh + dy * nyh + dz * nzh;
+    const double cx = dy * nzh - dz * nyh, cy = dz * nxh - dx * nzh, cz = dx * nyh - dy * nxh;
+    const double k = 1.0 - n * n * (cx * cx + cy * cy + cz * cz);
+    if (!(k >= 0.0)) return false;
+    const double sk = sqrt(k), beta = sk - n * c;
+    const double ex = n * dx + beta * nxh, ey = n * dy + beta * nyh, ez = n * dz + beta * nzh;
+    double T = 1.0;
+    if (D.fresnel) {
+        const double m = 1.0 - sk, m2 = m * m;
+        T = 1.0 - (E.R0 + (1.0 - E.R0) * m2 * m2 * m);
+    }
+    const double w = w1 * T;
+    if (!(ez > 0.0)) return false;
+    const double tau = (E.z_screen - qz) / ez;
+    const double X = qx + tau * ex, Y = qy + tau * ey;
+    if (!(X >= -E.Rx && X < E.Rx && Y >= -E.Ry && Y < E.Ry)) return false;
+    // ---- splat, reverse
+    double Fx[NU], dFx[NU], Fy[NU], dFy[NU];
+    const int i0 = filter_axis_f64<NU>(X, E.Rx, E.wx, D.nx, E.alpha, E.edge_x, Fx, dFx);
+    const int j0 = filter_axis_f64<NU>(Y, E.Ry, E.wy, D.ny, E.alpha, E.edge_y, Fy, dFy);
+    constexpr int H = (NU - 1) / 2;
+    const float* Gd = G + D.img_off;
+    double wbar = 0.0, Xbar = 0.0, Ybar = 0.0;
+#pragma unroll
+    for (int a = 0; a < NU; ++a) {
+        const int i = min(max(i0 + a - H, 0), D.nx - 1);
+        double gb = 0.0, gbp = 0.0;
+#pragma unroll
+        for (int b = 0; b < NU; ++b) {
+            const int j = min(max(j0 + b - H, 0), D.ny - 1);
+            const double Gij = (double)Gd[(int64_t)i * D.ny + j];
+            gb += Gij * Fy[b];
+            gbp += Gij * dFy[b];
+        }
+        wbar += Fx[a] * gb;
+        Xbar += dFx[a] * gb;
+        Ybar += Fx[a] * gbp;
+    }
+    Xbar *= w;
+    Ybar *= w;
+    const double taub = Xbar * ex + Ybar * ey;
+    const double exb = Xbar * tau, eyb = Ybar * tau, ezb = -taub * tau / ez;
+    const double qxb = Xbar, qyb = Ybar, qzb = -taub / ez;
+    double skb = 0.0;
+    if (D.fresnel) {
+        const double m = 1.0 - sk, m2 = m * m;
+        skb = wbar * w1 * 5.0 * (1.0 - E.R0) * m2 * m2;
+    }
+    const double betab = exb * nxh + eyb * nyh + ezb * nzh;
+    double nxb = beta * exb, nyb = beta * eyb, nzb = beta * ezb;
+    skb += betab;
+    double cb = -n * betab;
+    const double kb = skb * 0.5 / fmax(sk, 1e-300);
+    cb += 2.0 * n * n * c * kb;
+    nxb += cb * dx;
+    nyb += cb * dy;
+    nzb += cb * dz;
+    const double ndot = nxb * nxh + nyb * nyh + nzb * nzh;
+    const double hxb = -(nxb - ndot * nxh) * inv_m, hyb = -(nyb - ndot * nyh) * inv_m;
+    double g0;
+    if (point) {
+        const double tb = qxb * dx + qyb * dy + qzb * dz + hxb * (S.hxx * dx + S.hxy * dy) +
+                          hyb * (S.hxy * dx + S.hyy * dy);
+        g0 = -tb / (S.hx * dx + S.hy * dy - dz);
+    } else {
+        g0 = qzb;
+    }
+    const double gx = hxb * E.sxu, gy = hyb * E.syv;
+#pragma unroll
+    for (int a = 0; a <= P; ++a)
+#pragma unroll
+        for (int b = 0; b <= Q; ++b)
+            g[a * (Q + 1) + b] = S.Nu[a] * (g0 * S.Nv[b] + gy * S.dNv[b]) + gx * S.dNu[a] * S.Nv[b];
+    cku = S.ku;
+    ckv = S.kv;
+    return true;
+}
+
+// The double-precision re-trace of the queued rays.  A workgroup takes 64 consecutive queue segments (one per
+// wave of a logical block, ~2 rays each), forms the prefix sums of their counts in LDS and gives its threads the
+// rays densely, one per thread.  Their contributions are summed in an LDS copy of the control net of the
+// round's design (the design of its first ray; rays of another design, at a design boundary, add to the
+// device accumulator directly), which is then added to the device accumulator once: one atomic per touched
+// control point and round instead of one per ray.  Both sums are in the design's fixed-point unit, so the result
+// does not depend on which kernel adds them or in which order.
+template <int P, int Q, int NU>
+__global__ __launch_bounds__(WG) void k_adjoint_fp64(TraceArgs A, const DesignDev64* d64, int shape, int64_t nseg) {
+    constexpr int SPW = 64;  // segments per workgroup and round
+    __shared__ int s_off[SPW + 1];
+    __shared__ int s_design;
+    extern __shared__ unsigned long long sG[];  // A.lds_cp entries
+    const int per_wave = queue_cap(shape) / 4;
+    for (int64_t s0 = (int64_t)blockIdx.x * SPW; s0 < nseg; s0 += (int64_t)gridDim.x * SPW) {
+        if (threadIdx.x < SPW) {  // inclusive scan of the counts over wave 0
+            int c = s0 + threadIdx.x < nseg ? A.qcount[s0 + threadIdx.x] : 0;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int u = __shfl_up(c, o);
+                if ((int)threadIdx.x >= o) c += u;
+            }
+            s_off[threadIdx.x + 1] = c;
+            if (threadIdx.x == 0) s_off[0] = 0;
+        }
+        __syncthreads();
+        const int total = s_off[SPW];
+        if (total == 0) {
+            __syncthreads();  // s_off is rewritten by the next round
+            continue;
+        }
+        if (threadIdx.x == 0) {
+            int k = 0;  // the segment of the round's first ray
+            while (s_off[k + 1] == 0) ++k;
+            s_design = A.queue[(s0 + k) * per_wave].design;
+        }
+        __syncthreads();
+        const int dmain = s_design;
+        const DesignDev Dm = load_uniform(A.designs, dmain);
+        for (int i = threadIdx.x; i < Dm.ncp; i += WG) sG[i] = 0ull;
+        __syncthreads();
+        for (int i = threadIdx.x; i < total; i += WG) {
+            int lo = 0, hi = SPW - 1;  // the segment of ray i: the last k with s_off[k] <= i
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= i) lo = mid; else hi = mid - 1;
+            }
+            const QEntry q = A.queue[(s0 + lo) * per_wave + (i - s_off[lo])];
+            const DesignDev D = A.designs[q.design];
+            const DesignDev64 E = d64[q.design];
+            double g[(P + 1) * (Q + 1)];
+            int cku = 0, ckv = 0;
+            if (!trace_adjoint_f64<P, Q, NU>(D, E, A.Pz, A.dLdI, q.id, q.t, cku, ckv, g)) continue;
+            const double inv_unit = ldexp(1.0, -fixed_point_exponent(A.gmax[q.design], D.w0));
+            unsigned long long* acc = q.design == dmain ? sG : A.gacc + D.cp_off;
+#pragma unroll
+            for (int a = 0; a <= P; ++a)
+#pragma unroll
+                for (int b = 0; b <= Q; ++b) {
+                    const double v = g[a * (Q + 1) + b];
+                    if (v != 0.0)
+                        atomicAdd(&acc[(int64_t)(cku + a) * D.n_v + ckv + b],
+                                  (unsigned long long)__double2ll_rn(v * inv_unit));
+                }
+        }
+        __syncthreads();
+        unsigned long long* gacc = A.gacc + Dm.cp_off;
+        for (int i = threadIdx.x; i < Dm.ncp; i += WG) {
+            const unsigned long long v = sG[i];
+            if (v != 0ull) atomicAdd(&gacc[i], v);
+        }
+        __syncthreads();  // s_off and sG are rewritten by the next round
+    }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1648,6 +2036,10 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
     const int MU = shape_mu(shape), MV = shape_mv(shape), RPT = MU * MV;
     const int BU = 16 * MU, BV = 16 * MV;
     const int mv_shift = MV == 1 ? 0 : (MV == 2 ? 1 : 2);
+    // per-wave count of the block's rays queued for the double-precision re-trace (KIND 0 and 1)
+    __shared__ int s_qn[WG / 64];
+    const int qcap_w = queue_cap(shape) / 4;
+    if (lane == 0) s_qn[wave] = 0;
     int cur = -1;
     BoundsDev B;
     for (int64_t pb = blockIdx.x; pb < A.n_blocks; pb += gridDim.x) {
@@ -1692,8 +2084,19 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
             const float* tl = nullptr;
             if constexpr (KIND == 1)
                 if (A.roots) tl = A.roots + D.root_off + id;
+            // queued for the double-precision re-trace while the wave's segment of the queue has room
+            auto enqueue = [&](float tq) {
+                if (!A.queue) return false;
+                const int slot = atomicAdd(&s_qn[wave], 1);
+                if (slot >= qcap_w) return false;
+                // the ray id again from the block's base and the ray's place (cheaper than keeping it live)
+                const int kq = ku0 + (r >> mv_shift), lq = kv0 + (r & (MV - 1));
+                A.queue[((A.qbase + b) * 4 + wave) * qcap_w + slot] =
+                    QEntry{d, tq, ebase + (int64_t)kq * D.grid_v + lq};
+                return true;
+            };
             if (!trace_adjoint<P, Q, NU, KIND>(D, B, sP, sKu, sKv, sSb, G, e, ku, kv, id, cku, ckv, g, cku_in, ckv_in,
-                                               gin, tl))
+                                               gin, tl, enqueue))
                 continue;
             if (aku >= 0 && (cku != aku || ckv != akv)) {
                 cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc, inv_unit);
@@ -1740,6 +2143,13 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
             }
         } else if (pend) {
             cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc, inv_unit);
+        }
+        if constexpr ((KIND & 6) == 0) {
+            // the wave's queued rays of this block (its lanes' LDS atomics completed in order before this read)
+            if (A.queue && lane == 0) {
+                A.qcount[(A.qbase + b) * 4 + wave] = min(s_qn[wave], qcap_w);
+                s_qn[wave] = 0;
+            }
         }
     }
     if (cur >= 0) adjoint_flush(A, cur, sG);
@@ -1847,6 +2257,15 @@ struct KernelsFor {
         }
         return hipGetLastError();
     }
+    static hipError_t adjoint_fp64(const TraceArgs& A, const DesignDev64* d64, int shape, int64_t nblocks,
+                                   hipStream_t s) {
+        const int64_t nseg = 4 * nblocks;  // one segment per (logical block, wave)
+        const int grid = (int)std::min<int64_t>((nseg + 63) / 64, 4096);
+        if (grid <= 0) return hipSuccess;
+        const size_t lds = sizeof(unsigned long long) * (size_t)A.lds_cp;  // the round design's control net
+        hipLaunchKernelGGL((k_adjoint_fp64<P, Q, NU>), dim3(grid), dim3(WG), lds, s, A, d64, shape, nseg);
+        return hipGetLastError();
+    }
     static hipError_t trace_rays(const TraceArgs& A, int design, const int64_t* ids, int64_t n, float* out8,
                                  hipStream_t s) {
         if (n <= 0) return hipSuccess;
@@ -1856,7 +2275,7 @@ struct KernelsFor {
         return hipGetLastError();
     }
     static const KernelSet* get() {
-        static const KernelSet ks = {&forward, &adjoint, &trace_rays};
+        static const KernelSet ks = {&forward, &adjoint, &adjoint_fp64, &trace_rays};
         return &ks;
     }
 };
