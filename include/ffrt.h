@@ -96,6 +96,8 @@ typedef struct {
 } ffrt_detector;
 
 /* fresnel: 1 applies Schlick's approximation at both faces (cosine taken on the air side), 0 does not.
+ * loss: 0 the paper's loss of sec. 2.5, L = ||I/sum I - T/sum T||_F / sqrt(n_x n_y) (RMS Frobenius norm of the
+ * difference of the normalised images); 1 its sum of squares, L = ||I/sum I - T/sum T||_F^2.
  * newton_max_iter: iteration cap of the freeform intersection (point sources), 1..32.
  * mesh_u, mesh_v: 0 (both) intersects the B-spline itself; 1..64 (both) intersects the paper's triangle
  * mesh instead (sec. 2.2.2): every knot span product divided into mesh_u x mesh_v equal rectangles, each
@@ -105,6 +107,8 @@ typedef struct {
 typedef struct {
     int32_t fresnel, newton_max_iter;
     int32_t mesh_u, mesh_v;
+    int32_t loss;            /* 0 RMS (the paper's), 1 sum of squares */
+    int32_t reserved;        /* 0 */
 } ffrt_options;
 
 typedef struct {

@@ -20,8 +20,11 @@ HIT, MISS_ENTRY, SIDE_WALL, TIR, OFF_SCREEN = 0, 1, 2, 3, 4
 
 def build():
     """Compile the oracle with the host C++ compiler (no GPU code)."""
-    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-o", _LIB, _SRC]
+    # built beside the library and renamed over it, so a process that has the old one loaded keeps it intact
+    tmp = _LIB + f".tmp{os.getpid()}"
+    cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread", "-o", tmp, _SRC]
     subprocess.run(cmd, check=True, cwd=_HERE)
+    os.replace(tmp, _LIB)
 
 
 class OrcProblem(ctypes.Structure):
@@ -41,7 +44,7 @@ class OrcProblem(ctypes.Structure):
         ("alpha", ctypes.c_double),
         ("nu_x", ctypes.c_int32), ("nu_y", ctypes.c_int32), ("ghost", ctypes.c_int32),
         ("fresnel", ctypes.c_int32), ("mesh_u", ctypes.c_int32), ("mesh_v", ctypes.c_int32),
-        ("filter", ctypes.c_int32), ("entry_freeform", ctypes.c_int32), ("pad2_", ctypes.c_int32),
+        ("filter", ctypes.c_int32), ("entry_freeform", ctypes.c_int32), ("loss", ctypes.c_int32),
     ]
 
 
@@ -80,6 +83,9 @@ def lib():
             "orc_trace_rays": (ctypes.c_int, [pp, dp, i64p, ctypes.c_int64, dp]),
             "orc_forward": (ctypes.c_int, [pp, dp, dp, P(OrcStats), dp, ctypes.c_int32]),
             "orc_loss": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, dp, dp, dp, dp]),
+            "orc_landing_gain": (ctypes.c_int, [pp, dp, i64p, ctypes.c_int64, dp]),
+            "orc_marginal_rays": (ctypes.c_int, [pp, dp, ctypes.c_int64, i64p, dp, i64p, ctypes.c_int32]),
+            "orc_loss_kind": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, dp, dp, dp, dp]),
             "orc_grad": (ctypes.c_int, [pp, dp, dp, dp, dp, dp, dp, ctypes.c_int32]),
             "orc_grad_split": (ctypes.c_int, [pp, dp, dp, ctypes.c_double, dp, dp, dp, ctypes.c_int32]),
             "orc_jvp": (ctypes.c_int, [pp, dp, dp, dp, ctypes.c_int32]),
@@ -120,6 +126,7 @@ def to_struct(prob):
     s.mesh_u, s.mesh_v = getattr(O, "mesh_u", 0), getattr(O, "mesh_v", 0)
     s.filter = getattr(D, "filter", 0)
     s.entry_freeform = getattr(L, "entry_freeform", 0)
+    s.loss = getattr(O, "loss", 0)
     return s
 
 
@@ -197,6 +204,32 @@ def trace_rays(prob, Pz, ids):
     return out
 
 
+def landing_gain(prob, Pz, ids):
+    """Per-ray landing displacement (mm) per radian of rotation of the ray inside the glass (0: no landing)."""
+    s = to_struct(prob)
+    P = _f64(Pz).ravel()
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    out = np.zeros(len(ids))
+    assert lib().orc_landing_gain(ctypes.byref(s), _dp(P), ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                  len(ids), _dp(out)) == 0
+    return out
+
+
+def marginal_rays(prob, Pz, threads=0):
+    """Ids of the rays whose discrete state is within rounding distance of flipping, and where each lands or
+    would land on the other side of its decision ((n, 2), NaN where nowhere on the screen plane)."""
+    s = to_struct(prob)
+    P = _f64(Pz).ravel()
+    n = ctypes.c_int64()
+    i64 = ctypes.POINTER(ctypes.c_int64)
+    assert lib().orc_marginal_rays(ctypes.byref(s), _dp(P), 0, None, None, ctypes.byref(n), threads) == 0
+    ids = np.zeros(n.value, np.int64)
+    xy = np.zeros((n.value, 2))
+    assert lib().orc_marginal_rays(ctypes.byref(s), _dp(P), n.value, ids.ctypes.data_as(i64), _dp(xy),
+                                   ctypes.byref(n), threads) == 0
+    return ids, xy
+
+
 def forward(prob, Pz, threads=0, with_mask=False):
     """Irradiance image (n_x, n_y), stats dict, and (optionally) the marginal-ray pixel mask."""
     s = to_struct(prob)
@@ -214,12 +247,13 @@ def forward(prob, Pz, threads=0, with_mask=False):
     return img, st.as_dict()
 
 
-def loss(irr, target):
+def loss(irr, target, kind=0):
+    """Loss of sec. 2.5 (kind 0, RMS) or its sum of squares (kind 1), and dL/dI."""
     irr, target = _f64(irr), _f64(target)
     nx, ny = irr.shape
     L = ctypes.c_double()
     g = np.zeros_like(irr)
-    rc = lib().orc_loss(nx, ny, _dp(irr), _dp(target), ctypes.byref(L), _dp(g))
+    rc = lib().orc_loss_kind(kind, nx, ny, _dp(irr), _dp(target), ctypes.byref(L), _dp(g))
     if rc:
         raise RuntimeError(f"orc_loss failed: {rc}")
     return L.value, g

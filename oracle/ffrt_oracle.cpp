@@ -164,6 +164,7 @@ bool valid_problem(const orc_problem* pr) {
     if (pr->kind < 0 || pr->kind > 2) return false;
     if (pr->filter != 0 && pr->filter != 1) return false;
     if (pr->entry_freeform != 0 && pr->entry_freeform != 1) return false;
+    if (pr->loss != 0 && pr->loss != 1) return false;
     if (pr->entry_freeform && pr->mesh_u) return false;  // the mesh option covers the exit face only
     if (pr->mesh_u < 0 || pr->mesh_v < 0 || pr->mesh_u > 64 || pr->mesh_v > 64 || (pr->mesh_u == 0) != (pr->mesh_v == 0))
         return false;
@@ -381,7 +382,11 @@ bool find_entry_root(const Geo& g, const double* Pz_in, const double* s, const d
     a = std::max(a, 0.0);
     if (!(a <= b)) { *margin = 0.0; return false; }
     double fa = f_in_of_t(g, Pz_in, s, d0, a), fb = f_in_of_t(g, Pz_in, s, d0, b);
-    *margin = std::min(std::fabs(fa), std::fabs(fb));
+    // The signs of f at the bracket ends are decisions (side wall, passed the lens) only where an end is the
+    // aperture prism's wall; an end set by the face's height range has its sign by construction.
+    *margin = std::numeric_limits<double>::infinity();
+    if (a == t_a) *margin = std::fabs(fa);
+    if (b == t_b) *margin = std::min(*margin, std::fabs(fb));
     if (fa < 0.0) return false;  // entered the prism above the face (through the side wall)
     bool monotone = g.Gx_in * std::fabs(d0[0]) + g.Gy_in * std::fabs(d0[1]) < d0[2];
     if (monotone) {
@@ -470,7 +475,7 @@ Entry ray_entry(const Geo& g, const double* Pz, int64_t id) {
             double sphi = std::sqrt(std::max(0.0, 1.0 - cphi * cphi));
             E.s[0] = ex; E.s[1] = ey; E.s[2] = pr.pos_z;
             E.d0[0] = std::cos(theta) * sphi; E.d0[1] = std::sin(theta) * sphi; E.d0[2] = cphi;
-            double margin;
+            double margin = 0.0;
             bool ok = find_entry_root(g, Pin, E.s, E.d0, &E.t_in, &margin);
             E.margin = margin;
             if (!ok) { E.status = ORC_MISS_ENTRY; return E; }
@@ -786,6 +791,7 @@ struct Exit {
     int status;
     S X, Y, w;
     double k;        // Snell discriminant at the exit face (TIR margin)
+    double gain;     // landing displacement per radian of rotation of the ray inside the glass (mm)
 };
 
 // Exit refraction at the freeform, Schlick weight, propagation to the screen.
@@ -794,6 +800,7 @@ Exit<S> exit_and_screen(const Geo& g, const S* q, const S* d, const S& hx, const
                         bool ignore_tir) {
     Exit<S> X;
     X.status = ORC_HIT;
+    X.gain = 0.0;
     // Outward unit normal of z = h(x,y): (-h_x, -h_y, 1) / |.|
     S m0 = -hx, m1 = -hy;
     S nn = sqrt(m0 * m0 + m1 * m1 + 1.0);
@@ -815,6 +822,11 @@ Exit<S> exit_and_screen(const Geo& g, const S* q, const S* d, const S& hx, const
     S tau = (g.pr.z_screen - q[2]) / e2;
     X.X = q[0] + tau * e0;
     X.Y = q[1] + tau * e1;
+    // Conditioning of the landing: a rotation d(theta) of the ray inside the glass turns the exit ray by
+    // eta c / sqrt(k) d(theta) (Snell's law differentiated), which moves the landing by L / e_z^2 per radian.
+    X.gain = val(k) > 0.0 ? (g.pr.z_screen - val(q[2])) * eta * std::fabs(val(c)) /
+                                (val(e2) * val(e2) * std::sqrt(val(k)))
+                          : std::numeric_limits<double>::infinity();
     if (!(val(X.X) >= -g.Rxe && val(X.X) < g.Rxe && val(X.Y) >= -g.Rye && val(X.Y) < g.Rye))
         X.status = ORC_OFF_SCREEN;
     return X;
@@ -881,6 +893,7 @@ struct RayOut {
     int su, sv;          // hit span product
     bool marginal;
     double k;
+    double gain;         // landing conditioning (mm per radian), exact-root and mesh hits
     Entry E;
     MeshHit mh;          // mesh mode: the triangle hit
 };
@@ -896,7 +909,7 @@ constexpr double EPS_SCREEN = 3e-5;    // landing to the screen edge, relative t
 // a marginal ray would land if single precision took the other side of such a decision.
 RayOut trace_value(const Geo& g, const double* Pz, int64_t id, bool force = false) {
     RayOut R;
-    R.marginal = false; R.X = R.Y = R.w = 0.0; R.u = R.v = R.t = 0.0; R.su = R.sv = 0; R.k = 1.0;
+    R.marginal = false; R.X = R.Y = R.w = 0.0; R.u = R.v = R.t = 0.0; R.su = R.sv = 0; R.k = 1.0; R.gain = 0.0;
     R.mh = MeshHit{false, 0.0, 0, 0, 0, 0, 0};
     const bool mesh = g.pr.mesh_u > 0;
     R.E = ray_entry(g, Pz, id);
@@ -947,6 +960,7 @@ RayOut trace_value(const Geo& g, const double* Pz, int64_t id, bool force = fals
     else q[2] = E.o[2] + R.t * E.d[2];
     Exit<double> X = exit_and_screen<double>(g, q, E.d, s.hx, s.hy, E.w, false);
     R.k = X.k;
+    R.gain = X.gain;
     if (std::fabs(X.k) < EPS_TIR) {
         R.marginal = true;
         if (X.status == ORC_TIR) {  // landing the ray would have had: for the mask only
@@ -1182,6 +1196,52 @@ int orc_trace_rays(const orc_problem* pr, const double* Pz, const int64_t* ids, 
     return ORC_OK;
 }
 
+int orc_landing_gain(const orc_problem* pr, const double* Pz, const int64_t* ids, int64_t n, double* out) {
+    if (!valid_problem(pr)) return ORC_E_ARG;
+    Geo g = make_geo(pr, Pz);
+    for (int64_t r = 0; r < n; ++r) {
+        RayOut R = trace_value(g, Pz, ids[r]);
+        out[r] = R.status == ORC_HIT ? R.gain : 0.0;
+    }
+    return ORC_OK;
+}
+
+// Where a marginal ray lands, or would land if single precision took the other side of its decision (entry
+// aperture, side wall, total internal reflection); false if it would not reach the screen plane.
+static bool marginal_landing(const Geo& g, const double* Pz, int64_t id, const RayOut& R, double* X, double* Y) {
+    RayOut F = (R.status == ORC_MISS_ENTRY || R.status == ORC_SIDE_WALL) ? trace_value(g, Pz, id, true) : R;
+    bool landed = F.status == ORC_HIT || F.status == ORC_OFF_SCREEN || (F.status == ORC_TIR && std::fabs(F.k) < EPS_TIR);
+    if (!landed) return false;
+    *X = std::min(std::max(F.X, -g.Rxe), std::nextafter(g.Rxe, 0.0));
+    *Y = std::min(std::max(F.Y, -g.Rye), std::nextafter(g.Rye, 0.0));
+    return std::isfinite(*X) && std::isfinite(*Y);
+}
+
+int orc_marginal_rays(const orc_problem* pr, const double* Pz, int64_t cap, int64_t* ids, double* xy,
+                      int64_t* count, int32_t threads) {
+    if (!valid_problem(pr) || !Pz || !count || (cap > 0 && (!ids || !xy))) return ORC_E_ARG;
+    Geo g = make_geo(pr, Pz);
+    int T = nthreads(threads, g.nrays);
+    std::vector<std::vector<int64_t>> found(T);
+    parallel_rays(g.nrays, T, [&](int t, int64_t id) {
+        RayOut R = trace_value(g, Pz, id);
+        if (R.marginal) found[t].push_back(id);
+    });
+    std::vector<int64_t> all;
+    for (auto& f : found) all.insert(all.end(), f.begin(), f.end());
+    std::sort(all.begin(), all.end());
+    *count = int64_t(all.size());
+    for (int64_t i = 0; i < std::min<int64_t>(cap, *count); ++i) {
+        ids[i] = all[i];
+        RayOut R = trace_value(g, Pz, all[i]);
+        double X, Y;
+        bool landed = marginal_landing(g, Pz, all[i], R, &X, &Y);
+        xy[2 * i] = landed ? X : std::numeric_limits<double>::quiet_NaN();
+        xy[2 * i + 1] = landed ? Y : std::numeric_limits<double>::quiet_NaN();
+    }
+    return ORC_OK;
+}
+
 int orc_forward(const orc_problem* pr, const double* Pz, double* irr, orc_stats* st, double* mask,
                 int32_t threads) {
     if (!valid_problem(pr) || !Pz || !irr) return ORC_E_ARG;
@@ -1198,16 +1258,8 @@ int orc_forward(const orc_problem* pr, const double* Pz, double* irr, orc_stats*
         s.n_rays++;
         if (R.marginal) {
             s.n_marginal++;
-            if (mask) {
-                RayOut F = (R.status == ORC_MISS_ENTRY || R.status == ORC_SIDE_WALL) ? trace_value(g, Pz, id, true) : R;
-                bool landed = F.status == ORC_HIT || F.status == ORC_OFF_SCREEN ||
-                              (F.status == ORC_TIR && std::fabs(F.k) < EPS_TIR);
-                if (landed) {
-                    double X = std::min(std::max(F.X, -g.Rxe), std::nextafter(g.Rxe, 0.0));
-                    double Y = std::min(std::max(F.Y, -g.Rye), std::nextafter(g.Rye, 0.0));
-                    if (std::isfinite(X) && std::isfinite(Y)) mark_window(g, X, Y, msk[t].data());
-                }
-            }
+            double X, Y;
+            if (mask && marginal_landing(g, Pz, id, R, &X, &Y)) mark_window(g, X, Y, msk[t].data());
         }
         switch (R.status) {
             case ORC_HIT: s.n_hit++; break;
@@ -1245,8 +1297,15 @@ int orc_forward(const orc_problem* pr, const double* Pz, double* irr, orc_stats*
 
 // Loss (sec. 2.5): I_hat = I / sum I, I_ref_hat likewise, L = ||I_hat - I_ref_hat||_F / sqrt(n_x n_y).
 // dL/dI_kl = (D_kl - sum_ij D_ij I_hat_ij) / (s sqrt(n_x n_y) ||D||), with D = I_hat - I_ref_hat, s = sum I;
-// reading: dL/dI = 0 where ||D|| = 0.
+// reading: dL/dI = 0 where ||D|| = 0.  Kind 1, the sum of squares L = ||D||_F^2, has
+// dL/dI_kl = 2 (D_kl - sum_ij D_ij I_hat_ij) / s (dD_ij/dI_kl = delta / s - I_ij / s^2).
 int orc_loss(int32_t nx, int32_t ny, const double* irr, const double* target, double* loss, double* dL_dI) {
+    return orc_loss_kind(0, nx, ny, irr, target, loss, dL_dI);
+}
+
+int orc_loss_kind(int32_t kind, int32_t nx, int32_t ny, const double* irr, const double* target, double* loss,
+                  double* dL_dI) {
+    if (kind != 0 && kind != 1) return ORC_E_ARG;
     int64_t n = int64_t(nx) * ny;
     double s = 0.0, sT = 0.0;
     for (int64_t i = 0; i < n; ++i) { s += irr[i]; sT += target[i]; }
@@ -1259,11 +1318,12 @@ int orc_loss(int32_t nx, int32_t ny, const double* irr, const double* target, do
         dot += D * irr[i] / s;
     }
     double nrm = std::sqrt(d2), rn = std::sqrt(double(n));
-    *loss = nrm / rn;
+    *loss = kind == 1 ? d2 : nrm / rn;
     if (dL_dI) {
         for (int64_t i = 0; i < n; ++i) {
             double D = irr[i] / s - target[i] / sT;
-            dL_dI[i] = nrm > 0.0 ? (D - dot) / (s * rn * nrm) : 0.0;
+            if (kind == 1) dL_dI[i] = 2.0 * (D - dot) / s;
+            else dL_dI[i] = nrm > 0.0 ? (D - dot) / (s * rn * nrm) : 0.0;
         }
     }
     return ORC_OK;
@@ -1279,7 +1339,7 @@ static int grad_impl(const orc_problem* pr, const double* Pz, const double* targ
     int rc = orc_forward(pr, Pz, irr.data(), nullptr, nullptr, threads);
     if (rc) return rc;
     double L = 0.0;
-    rc = orc_loss(g.nxe, g.nye, irr.data(), target, &L, G.data());
+    rc = orc_loss_kind(pr->loss, g.nxe, g.nye, irr.data(), target, &L, G.data());
     if (rc) return rc;
     if (loss) *loss = L;
     if (irr_out) std::copy(irr.begin(), irr.end(), irr_out);

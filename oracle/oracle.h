@@ -51,7 +51,7 @@ typedef struct {
                                         mesh_u x mesh_v rectangles per knot span product */
     int32_t filter;                  /* 0: Gaussian reconstruction filter, 1: box (indicator of the pixel) */
     int32_t entry_freeform;          /* 1: the entry face is a second B-spline (net after the exit's in Pz) */
-    int32_t pad2_;
+    int32_t loss;                    /* 0: the RMS loss of sec. 2.5; 1: its sum of squares */
 } orc_problem;
 
 typedef struct {
@@ -96,6 +96,16 @@ int orc_splat_one(const orc_problem* pr, double X, double Y, double* img);
 /* Trace the given rays.  out8 per ray: {status, X, Y, w, u_hit, v_hit, t_hit, marginal}. */
 int orc_trace_rays(const orc_problem* pr, const double* Pz, const int64_t* ids, int64_t n, double* out8);
 
+/* Conditioning of each ray's landing: the displacement (mm) of the landing point per radian of rotation of
+ * the ray inside the glass (0 for rays that do not land). */
+int orc_landing_gain(const orc_problem* pr, const double* Pz, const int64_t* ids, int64_t n, double* out);
+
+/* The rays whose discrete state (status) is within rounding distance of flipping ("marginal"), in id order:
+ * their number in *count, the first min(cap, count) ids, and where each lands or would land on the other side
+ * of its decision (xy, NaN if nowhere on the screen plane). */
+int orc_marginal_rays(const orc_problem* pr, const double* Pz, int64_t cap, int64_t* ids, double* xy,
+                      int64_t* count, int32_t threads);
+
 /* Irradiance image (row-major [n_x][n_y], i along x).  mask (optional): pixels touched by rays whose
  * discrete state is within rounding distance of flipping are set to 1.  threads <= 0 means all cores. */
 int orc_forward(const orc_problem* pr, const double* Pz, double* irr, orc_stats* st, double* mask,
@@ -103,6 +113,9 @@ int orc_forward(const orc_problem* pr, const double* Pz, double* irr, orc_stats*
 
 /* Loss of sec. 2.5 and dL/dI.  Returns ORC_E_NOFLUX if sum(I) = 0. */
 int orc_loss(int32_t nx, int32_t ny, const double* irr, const double* target, double* loss, double* dL_dI);
+/* The same for loss kind 0 (the RMS loss of sec. 2.5) or 1 (its sum of squares, ||I_hat - T_hat||_F^2). */
+int orc_loss_kind(int32_t kind, int32_t nx, int32_t ny, const double* irr, const double* target, double* loss,
+                  double* dL_dI);
 
 /* Forward, loss, and the pathwise gradient dL/dP^z (row-major [n_u][n_v]).  irr and dL_dI optional. */
 int orc_grad(const orc_problem* pr, const double* Pz, const double* target, double* loss, double* dL_dP,

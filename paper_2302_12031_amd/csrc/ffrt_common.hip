@@ -360,7 +360,8 @@ __global__ void k_reparam(int mode, int64_t n, const float* __restrict__ theta, 
     else dLdtheta[k] = dLdP[k] * (0.5f * (1.0f - y * y) * span[k]);
 }
 
-// The loss value of sec. 2.5 with double-precision reductions (finite-difference checks only).
+// The loss value of sec. 2.5 (or its sum of squares) with double-precision reductions (finite-difference
+// checks only).
 __global__ __launch_bounds__(1024) void k_loss_f64(const DesignDev* designs, const float* __restrict__ irr,
                                                    const float* __restrict__ target, double* loss) {
     __shared__ double sh[16];
@@ -384,7 +385,7 @@ __global__ __launch_bounds__(1024) void k_loss_f64(const DesignDev* designs, con
         d2 += Dv * Dv;
     }
     d2 = block_sum_f64(d2, sh);
-    if (threadIdx.x == 0) loss[blockIdx.x] = sqrt(d2 / (double)n);
+    if (threadIdx.x == 0) loss[blockIdx.x] = D.loss_kind == 1 ? d2 : sqrt(d2 / (double)n);
 }
 
 // Adam per design; the step counter lives on the device so the update can be replayed from a graph.

@@ -65,6 +65,8 @@ struct DesignDev {
     // lens must stay at least delta_min thick between control points of equal index
     int32_t entry_ff, ncp;
     float delta_min;
+    int32_t loss_kind;               // 0 RMS (sec. 2.5), 1 sum of squares
+    float sxu_lo, syv_lo;            // (n_u - p) / (2 r_x) - sxu exactly, to a float: sxu + sxu_lo is the scale
 };
 
 // The same design's parameters in double precision, for the adjoint's double-precision re-trace of rays whose

@@ -151,6 +151,8 @@ ffrt_status validate(const ffrt_problem& pr, int idx) {
     if (!(D.z_screen > L.z_in)) return bad("screen must lie above the entry face");
     if (pr.opt.fresnel != 0 && pr.opt.fresnel != 1) return bad("fresnel must be 0 or 1");
     if (pr.opt.newton_max_iter < 1 || pr.opt.newton_max_iter > 32) return bad("newton_max_iter in [1, 32]");
+    if (pr.opt.loss != 0 && pr.opt.loss != 1) return bad("loss must be 0 (RMS) or 1 (sum of squares)");
+    if (pr.opt.reserved != 0) return bad("options.reserved must be 0");
     if (pr.opt.mesh_u < 0 || pr.opt.mesh_u > 64 || pr.opt.mesh_v < 0 || pr.opt.mesh_v > 64 ||
         (pr.opt.mesh_u == 0) != (pr.opt.mesh_v == 0))
         return bad("mesh_u, mesh_v: both 0 (exact root) or both in [1, 64]");
@@ -194,6 +196,8 @@ DesignDev make_design(const ffrt_problem& pr, int64_t cp_off, int64_t img_off, i
     d.nsv = L.n_v - L.q;
     d.sxu = (float)(d.nsu / (2.0 * L.r_x));
     d.syv = (float)(d.nsv / (2.0 * L.r_y));
+    d.sxu_lo = (float)(d.nsu / (2.0 * L.r_x) - (double)d.sxu);
+    d.syv_lo = (float)(d.nsv / (2.0 * L.r_y) - (double)d.syv);
     d.ubar0 = 0.5f * (float)d.nsu;
     d.vbar0 = 0.5f * (float)d.nsv;
     d.zmin_allowed = (float)(L.z_in + L.delta_min);
@@ -241,6 +245,7 @@ DesignDev make_design(const ffrt_problem& pr, int64_t cp_off, int64_t img_off, i
     d.newton_max = pr.opt.newton_max_iter;
     d.box = pr.det.filter;
     d.mesh_u = pr.opt.mesh_u;
+    d.loss_kind = pr.opt.loss;
     d.mesh_v = pr.opt.mesh_v;
     d.inv_mesh_u = d.mesh_u ? 1.0f / (float)d.mesh_u : 0.0f;
     d.inv_mesh_v = d.mesh_v ? 1.0f / (float)d.mesh_v : 0.0f;

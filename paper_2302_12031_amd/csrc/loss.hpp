@@ -44,14 +44,21 @@ __device__ inline LossOut loss_from_sums(const double* q, const DesignDev& D) {
     r.L.is = (float)(1.0 / s);
     r.L.isT = (float)(1.0 / sT);
     r.L.dot = (float)(a2 - ab);
-    r.L.coef = nrm > 0.0 ? (float)(1.0 / (s * rn * nrm)) : 0.0f;
-    r.loss = (float)(nrm / rn);
+    if (D.loss_kind == 1) {
+        // sum of squares L = ||D||^2: dL/dI = 2 (D - sum(D I_hat)) / s
+        r.L.coef = (float)(2.0 / s);
+        r.loss = (float)d2;
+    } else {
+        r.L.coef = nrm > 0.0 ? (float)(1.0 / (s * rn * nrm)) : 0.0f;
+        r.loss = (float)(nrm / rn);
+    }
     r.valid = 1;
     return r;
 }
 
 // I_hat = I / s, T_hat = T / s_T, D = I_hat - T_hat, L = ||D||_F / sqrt(n_x n_y),
-// dL/dI = (D - sum(D I_hat)) / (s sqrt(n_x n_y) ||D||) (0 where ||D|| = 0), with
+// dL/dI = (D - sum(D I_hat)) / (s sqrt(n_x n_y) ||D||) (0 where ||D|| = 0) (or, for the sum of squares
+// L = ||D||^2, dL/dI = 2 (D - sum(D I_hat)) / s), with
 // ||D||^2 = A / s^2 - 2 B / (s s_T) + C / s_T^2 and sum(D I_hat) = A / s^2 - B / (s s_T) from the slice sums
 // (A = sum I^2, B = sum I T, C = sum T^2), which in double precision lose nothing that matters to the float
 // results.  The LB <= 64 slices are added by a butterfly over the wave, so every lane of every wave that

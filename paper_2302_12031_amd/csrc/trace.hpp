@@ -168,24 +168,34 @@ struct SurfEval {
     T h, hx, hy, hxx, hxy, hyy;
 };
 
-// On the given span product (ku, kv); eval_surface below picks the one containing (x, y).
+// The offset x sxu + ubar0 - k of a point from the start of knot span k, in knot units.  The scale is held as
+// two floats (sxu + sxu_lo equals the exact (n_u - p) / (2 r_x) to ~1e-15) and the offset is formed by two
+// fused multiply-adds whose one visible rounding is that of the result (below 1): rounding x sxu + ubar0
+// first would cost up to half an ulp of nspan, ~1e-6 of a span for 30 spans, which moves the normal by
+// h_xx times as much and the landing by ~1e-3 pixel on curved, strongly refracting surfaces.
+__device__ __forceinline__ float span_offset(float x, float s, float s_lo, float c0) {
+    return fmaf(x, s_lo, fmaf(x, s, c0));
+}
+__device__ __forceinline__ double span_offset(double x, float s, float s_lo, float c0) {
+    return fma(x, (double)s + (double)s_lo, (double)c0);
+}
+
+// On the given span product (ku, kv) at the local offsets (tu, tv) (knot units from the spans' starts).
 template <int P, int Q, bool D2, class T>
-__device__ __forceinline__ void eval_surface_on(const DesignDev& D, const float* __restrict__ sP,
-                                                const float* __restrict__ sKu, const float* __restrict__ sKv, T x,
-                                                T y, int ku, int kv, SurfEval<P, Q, T>& S) {
-    T ub = x * (T)D.sxu + (T)D.ubar0;
-    T vb = y * (T)D.syv + (T)D.vbar0;
+__device__ __forceinline__ void eval_surface_local(const DesignDev& D, const float* __restrict__ sP,
+                                                   const float* __restrict__ sKu, const float* __restrict__ sKv,
+                                                   int ku, int kv, T tu, T tv, SurfEval<P, Q, T>& S) {
     S.ku = ku;
     S.kv = kv;
     // spans k with P-1 <= k <= nspan-P see only unclamped knots
     if (ku >= P - 1 && ku <= D.nsu - P)
-        span_basis<P, D2, true, T>(nullptr, ub - (T)ku, S.Nu, S.dNu, S.d2Nu);
+        span_basis<P, D2, true, T>(nullptr, tu, S.Nu, S.dNu, S.d2Nu);
     else
-        span_basis<P, D2, false, T>(sKu + ku * kt_stride(P), ub - (T)ku, S.Nu, S.dNu, S.d2Nu);
+        span_basis<P, D2, false, T>(sKu + ku * kt_stride(P), tu, S.Nu, S.dNu, S.d2Nu);
     if (kv >= Q - 1 && kv <= D.nsv - Q)
-        span_basis<Q, D2, true, T>(nullptr, vb - (T)kv, S.Nv, S.dNv, S.d2Nv);
+        span_basis<Q, D2, true, T>(nullptr, tv, S.Nv, S.dNv, S.d2Nv);
     else
-        span_basis<Q, D2, false, T>(sKv + kv * kt_stride(Q), vb - (T)kv, S.Nv, S.dNv, S.d2Nv);
+        span_basis<Q, D2, false, T>(sKv + kv * kt_stride(Q), tv, S.Nv, S.dNv, S.d2Nv);
     const float* row = sP + ku * D.n_v + kv;  // control point (ku + a, kv + b) of span product (ku, kv)
     T h = 0, hu = 0, hv = 0, huu = 0, huv = 0, hvv = 0;
 #pragma unroll
@@ -218,12 +228,31 @@ __device__ __forceinline__ void eval_surface_on(const DesignDev& D, const float*
     }
 }
 
-template <int P, int Q, bool D2, class T>
+// On the given span product (ku, kv) at the point (x, y); eval_surface below picks the one containing it.
+// FAST rounds x sxu + ubar0 before taking the span's start off (two operations fewer per axis): good enough
+// inside a root search, whose result the offset's rounding moves by ~1e-7 of a span at most, but not for the
+// normal that refracts the ray.
+template <int P, int Q, bool D2, class T, bool FAST = false>
+__device__ __forceinline__ void eval_surface_on(const DesignDev& D, const float* __restrict__ sP,
+                                                const float* __restrict__ sKu, const float* __restrict__ sKv, T x,
+                                                T y, int ku, int kv, SurfEval<P, Q, T>& S) {
+    T tu, tv;
+    if constexpr (FAST) {
+        tu = (x * (T)D.sxu + (T)D.ubar0) - (T)ku;
+        tv = (y * (T)D.syv + (T)D.vbar0) - (T)kv;
+    } else {
+        tu = span_offset(x, D.sxu, D.sxu_lo, D.ubar0 - (float)ku);
+        tv = span_offset(y, D.syv, D.syv_lo, D.vbar0 - (float)kv);
+    }
+    eval_surface_local<P, Q, D2, T>(D, sP, sKu, sKv, ku, kv, tu, tv, S);
+}
+
+template <int P, int Q, bool D2, class T, bool FAST = false>
 __device__ __forceinline__ void eval_surface(const DesignDev& D, const float* __restrict__ sP,
                                              const float* __restrict__ sKu, const float* __restrict__ sKv, T x,
                                              T y, SurfEval<P, Q, T>& S) {
     int ku = (int)floor(x * (T)D.sxu + (T)D.ubar0), kv = (int)floor(y * (T)D.syv + (T)D.vbar0);
-    eval_surface_on<P, Q, D2, T>(D, sP, sKu, sKv, x, y, min(max(ku, 0), D.nsu - 1), min(max(kv, 0), D.nsv - 1),
+    eval_surface_on<P, Q, D2, T, FAST>(D, sP, sKu, sKv, x, y, min(max(ku, 0), D.nsu - 1), min(max(kv, 0), D.nsv - 1),
                                  S);
 }
 
@@ -235,7 +264,38 @@ struct RayIn {
     float ox, oy, oz;   // point on the entry plane (collimated: below the sample, on z = z_in)
     float dx, dy, dz;   // unit direction in the glass
     float w;            // weight after the entry face
+    int su, sv;         // collimated: the knot spans of the sample and its offsets in them (knot units)
+    float tu, tv;
 };
+
+// Azimuth of stratum k of S with jitter xi: theta = 2 pi (k + xi) / S, split into whole quarter turns n and a
+// remainder r = (4k - nS) / (2S) + 2 xi / S (|r| <= 1/4 + 2/S) so that the argument of sincospi is rounded once
+// at the magnitude of r (exactly, for S a power of two, but for that last rounding) instead of at that of
+// theta / pi < 2; the quarter turns are then exact swaps and sign changes.
+__device__ __forceinline__ void sample_azimuth(int k, float xi, int S, float inv_S, float& s, float& c) {
+    const int n = (int)rintf(4.0f * (float)k * inv_S);
+    const float r = fmaf(2.0f * xi, inv_S, (float)(4 * k - n * S) * (0.5f * inv_S));
+    float sr, cr;
+    sincospif(r, &sr, &cr);
+    const bool odd = (n & 1) != 0;
+    const float a = odd ? cr : sr, b = odd ? sr : cr;
+    s = (n & 2) ? -a : a;
+    c = ((n + 1) & 2) ? -b : b;
+}
+
+// Knot span and offset in it (knot units) of the sample (k + xi) / G of a collimated grid, from the integers:
+// (k + xi) nspan / G = m + (rem + xi nspan) / G with k nspan = m G + rem, so the offset is rounded once, at
+// its own magnitude, instead of through the aperture coordinate.
+__device__ __forceinline__ void sample_span(int k, float xi, int G, float inv_G, int nspan, int& m, float& t) {
+    const int q = k * nspan;
+    m = (int)((float)q * inv_G);
+    int rem = q - m * G;
+    if (rem < 0) { --m; rem += G; }
+    if (rem >= G) { ++m; rem -= G; }
+    t = fmaf(xi, (float)nspan, (float)rem) * inv_G;
+    if (t >= 1.0f && m < nspan - 1) { ++m; t -= 1.0f; }
+    m = min(max(m, 0), nspan - 1);   // k in [0, G) keeps m there; a stray k stays inside the net
+}
 
 // KIND bit 0 clear: collimated source; set: point source or grid of point sources (D.kind 1 or 2).  Bit 1
 // selects the triangle-mesh intersection of sec. 2.2.2 instead of the exact root (see below).
@@ -252,6 +312,8 @@ __device__ __forceinline__ RayIn ray_entry(const DesignDev& D, int e, int ku, in
         float v = ((float)kv + x2) * D.inv_gv;
         r.ox = (2.0f * u - 1.0f) * D.r_x;
         r.oy = (2.0f * v - 1.0f) * D.r_y;
+        sample_span(ku, x1, D.grid_u, D.inv_gu, D.nsu, r.su, r.tu);
+        sample_span(kv, x2, D.grid_v, D.inv_gv, D.nsv, r.sv, r.tv);
         r.oz = D.z_in;
         r.dx = 0.0f;
         r.dy = 0.0f;
@@ -263,7 +325,7 @@ __device__ __forceinline__ RayIn ray_entry(const DesignDev& D, int e, int ku, in
     // angle), a = (k_a + xi) / S_a.  sin(phi) = sqrt(a' (2 - a')) with a' = (1 - cos phi_max) a avoids the
     // cancellation of 1 - cos^2.
     float sth, cth;
-    sincospif(2.0f * ((float)ku + x1) * D.inv_gu, &sth, &cth);
+    sample_azimuth(ku, x1, D.grid_u, D.inv_gu, sth, cth);
     float a = ((float)kv + x2) * D.inv_gv;
     float ao = a * D.omc;
     float cphi = 1.0f - ao;
@@ -317,7 +379,7 @@ __device__ __forceinline__ float f_and_slope(const DesignDev& D, const float* sP
                                              const float* sKv, const RayIn& r, float oz_rel, float t,
                                              float& fp) {
     SurfEval<P, Q, float> S;
-    eval_surface<P, Q, false, float>(D, sP, sKu, sKv, r.ox + t * r.dx, r.oy + t * r.dy, S);
+    eval_surface<P, Q, false, float, true>(D, sP, sKu, sKv, r.ox + t * r.dx, r.oy + t * r.dy, S);
     fp = S.hx * r.dx + S.hy * r.dy - r.dz;
     return S.h - oz_rel - t * r.dz;
 }
@@ -482,7 +544,7 @@ __device__ __forceinline__ RayIn ray_entry_ff(const DesignDev& D, const BoundsDe
         H.d0z = 1.0f;
     } else {
         float sth, cth;
-        sincospif(2.0f * ((float)ku + x1) * D.inv_gu, &sth, &cth);
+        sample_azimuth(ku, x1, D.grid_u, D.inv_gu, sth, cth);
         const float ao = ((float)kv + x2) * D.inv_gv * D.omc;
         const float cphi = 1.0f - ao, sphi = sqrtf(ao * (2.0f - ao));
         float px = D.pos_x, py = D.pos_y;
@@ -982,7 +1044,10 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
     }
     float qx = r.ox + t * r.dx, qy = r.oy + t * r.dy;
     SurfEval<P, Q, float> S;
-    eval_surface<P, Q, false, float>(D, sP, sKu, sKv, qx, qy, S);
+    if constexpr (SEARCH)
+        eval_surface<P, Q, false, float>(D, sP, sKu, sKv, qx, qy, S);
+    else
+        eval_surface_local<P, Q, false, float>(D, sP, sKu, sKv, r.su, r.sv, r.tu, r.tv, S);
     float qz = SEARCH ? r.oz + t * r.dz : S.h + B.zref;
     if constexpr (!SEARCH) t = qz - r.oz;
     o.t = t;
@@ -1093,7 +1158,7 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
         eval_surface<P, Q, true, float>(D, sP, sKu, sKv, qx, qy, S);
     } else {
         // the hit of a collimated ray does not move with P: no second derivatives needed
-        eval_surface<P, Q, false, float>(D, sP, sKu, sKv, qx, qy, S);
+        eval_surface_local<P, Q, false, float>(D, sP, sKu, sKv, r.su, r.sv, r.tu, r.tv, S);
     }
     float qz = SEARCH ? r.oz + t * r.dz : (MESH ? mqz : S.h + B.zref);
     ExitState E = exit_face(D, qx, qy, qz, r.dx, r.dy, r.dz, S.hx, S.hy, r.w);

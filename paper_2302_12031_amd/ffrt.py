@@ -45,7 +45,7 @@ class CDetector(ctypes.Structure):
 
 class COptions(ctypes.Structure):
     _fields_ = [("fresnel", ctypes.c_int32), ("newton_max_iter", ctypes.c_int32), ("mesh_u", ctypes.c_int32),
-                ("mesh_v", ctypes.c_int32)]
+                ("mesh_v", ctypes.c_int32), ("loss", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CProblem(ctypes.Structure):
@@ -152,7 +152,7 @@ def to_cproblem(p):
     c.src = CSource(S.kind, S.grid_u, S.grid_v, S.jitter, (ctypes.c_double * 3)(*S.pos), S.half_angle,
                     S.emit_nx, S.emit_ny, S.emit_wx, S.emit_wy, S.seed)
     c.det = CDetector(D.n_x, D.n_y, D.R_x, D.R_y, D.z_screen, D.alpha, D.nu_x, D.nu_y, D.ghost, D.filter)
-    c.opt = COptions(O.fresnel, O.newton_max_iter, O.mesh_u, O.mesh_v)
+    c.opt = COptions(O.fresnel, O.newton_max_iter, O.mesh_u, O.mesh_v, getattr(O, "loss", 0), 0)
     return c
 
 

@@ -66,6 +66,7 @@ class Options:
     newton_max_iter: int = 8
     mesh_u: int = 0           # 0: exact intersection; >= 1: triangle mesh of sec. 2.2.2, rectangles per span
     mesh_v: int = 0
+    loss: int = 0             # 0: the paper's RMS loss of the normalised images (sec. 2.5); 1: sum of squares
 
 
 @dataclass

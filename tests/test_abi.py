@@ -69,6 +69,7 @@ def test_plan_validation_rejects_bad_problems():
     _bad(replace(p, source=replace(p.source, kind=1, half_angle=1.6)), "half angle")
     _bad(replace(p, options=replace(p.options, newton_max_iter=0)), "newton")
     _bad(replace(p, detector=replace(p.detector, z_screen=-1.0)), "screen")
+    _bad(replace(p, options=replace(p.options, loss=2)), "loss")
     with pytest.raises(ffrt.FfrtError, match="unsupported"):
         ffrt.create_plan_handle([replace(p, lens=replace(p.lens, p=4, q=4))])
     q = replace(p, lens=replace(p.lens, p=5, q=3, n_u=10))

@@ -10,7 +10,7 @@ import torch
 import oracle as O
 from paper_2302_12031_amd import ffrt
 from paper_2302_12031_amd import workloads as W
-from parity import MAX_MARGINAL, assert_gradient, assert_irradiance, gradient_errors
+from parity import MAX_MARGINAL, assert_gradient, assert_irradiance, flip_mask, gradient_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +53,8 @@ def test_mesh_forward_and_gradient_parity(name):
     _say(f"[mesh] {name}: {wl.name}, {wl.num_rays} rays")
     plan, out = _run(wl)
     p, Pz, T = wl.problems[0], wl.Pz[0], wl.targets[0]
-    I64, st64, mask = O.forward(p, Pz, with_mask=True)
+    I64, st64 = O.forward(p, Pz)
+    mask, _, _ = flip_mask(plan, 0, plan.pack_cp(wl.Pz), p, Pz, I64.shape, name)
     worst, rel, eg = float("nan"), float("nan"), float("nan")
     if per_pixel:
         worst, rel = assert_irradiance(out["irr"][0], I64, mask, what=name)

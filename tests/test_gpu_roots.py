@@ -140,7 +140,13 @@ def test_rays_that_cross_the_exit_face_twice_take_the_smallest_root():
     np.testing.assert_allclose(gpu[sel, 6], ref[sel, 6], rtol=0, atol=5e-5)
     np.testing.assert_allclose(ref[sel, 6], t1[sel], rtol=0, atol=1e-9)
     hit = clear & (ref[:, 0] == O.HIT)
-    np.testing.assert_allclose(gpu[hit, 1:3], ref[hit, 1:3], rtol=0, atol=2e-5 * (40.0 + np.abs(ref[hit, 1:3]).max()))
+    # landings within 2e-5 of the screen scale, plus 2e-6 rad (~30 single-precision ulps of a direction) times
+    # the ray's own conditioning: the landing's displacement per radian of rotation inside the glass, which the
+    # grazing rays of the valley's walls raise to metres per radian
+    gain = O.landing_gain(pr, Pz, ids[hit])
+    err = np.abs(gpu[hit, 1:3] - ref[hit, 1:3]).max(1)
+    tol = 2e-5 * (40.0 + np.abs(ref[hit, 1:3]).max()) + 2e-6 * gain
+    assert (err <= tol).all(), (int((err > tol).sum()), float((err / tol).max()), float(gain[np.argmax(err / tol)]))
     _say(f"[roots] valley: {int(two.sum())} rays with two roots inside the aperture, "
          f"{int(sel.sum())} compared; status mismatches left out as near-tangent: "
          f"{int((gpu[near, 0] != ref[near, 0]).sum())} of {int(near.sum())}")

@@ -426,6 +426,32 @@ def test_loss_invariances_and_gradient_fd():
     assert abs((G * I).sum()) < 1e-14           # scale invariance: dL/dI is orthogonal to I
 
 
+def test_sum_of_squares_loss_hand_computed_2x2():
+    """Loss kind 1, ||I_hat - T_hat||_F^2.  I = e_00, T = 1: I_hat = e_00, T_hat = 1/4, D = (3/4, -1/4, -1/4,
+    -1/4), so L = 12/16 = 3/4; sum(D I_hat) = 3/4, s = 1, so dL/dI = 2 (D - 3/4) = (0, -2, -2, -2)."""
+    I = np.array([[1.0, 0.0], [0.0, 0.0]])
+    L, G = O.loss(I, np.ones((2, 2)), kind=1)
+    assert L == 0.75
+    np.testing.assert_array_equal(G, [[0.0, -2.0], [-2.0, -2.0]])
+    # the RMS loss of the same pair: sqrt(3/4) / 2
+    assert abs(O.loss(I, np.ones((2, 2)))[0] - np.sqrt(0.75) / 2) < 1e-16
+
+
+def test_sum_of_squares_loss_invariances_and_gradient_fd():
+    g = np.random.default_rng(3)
+    I, T = g.uniform(0, 1, (7, 4)), g.uniform(0, 1, (7, 4))
+    L, G = O.loss(I, T, kind=1)
+    assert abs(O.loss(0.3 * I, 5.0 * T, kind=1)[0] - L) < 1e-15
+    h = 1e-6
+    for idx in [(0, 0), (4, 1), (6, 3)]:
+        E = np.zeros_like(I); E[idx] = h
+        fd = (O.loss(I + E, T, kind=1)[0] - O.loss(I - E, T, kind=1)[0]) / (2 * h)
+        assert abs(fd - G[idx]) < 1e-8 * max(1, abs(G).max())
+    assert abs((G * I).sum()) < 1e-14
+    with pytest.raises(Exception):
+        O.loss(I, T, kind=2)
+
+
 # ------------------------------------------------------------------------------------------------
 # Gradient (pathwise derivative) against brute-force finite differences on tiny inputs
 # ------------------------------------------------------------------------------------------------
@@ -466,6 +492,28 @@ def test_gradient_matches_central_fd(kind):
         Lp = O.loss(O.forward(pr, Pz + E)[0], T)[0]
         Lm = O.loss(O.forward(pr, Pz - E)[0], T)[0]
         fd = (Lp - Lm) / (2 * h)
+        assert abs(fd - g.flat[k]) <= 1e-6 * np.abs(g).max() + 1e-7 * abs(fd), (k, fd, g.flat[k])
+        checked += 1
+    assert checked >= Pz.size // 2
+
+
+def test_sum_of_squares_gradient_matches_central_fd():
+    """The pathwise gradient of the sum-of-squares loss (option loss = 1) against central differences of that
+    loss, on the tiny point-source problem."""
+    pr, Pz, T = _tiny("point")
+    pr = replace(pr, options=replace(pr.options, loss=1))
+    L, g, irr, G = O.grad(pr, Pz, T)
+    assert abs(L - O.loss(irr, T, kind=1)[0]) < 1e-15
+    ids = np.arange(pr.num_rays())
+    base = O.trace_rays(pr, Pz, ids)[:, 0]
+    h = 1e-6
+    checked = 0
+    for k in range(Pz.size):
+        E = np.zeros(Pz.size); E[k] = h
+        E = E.reshape(Pz.shape)
+        if (O.trace_rays(pr, Pz + E, ids)[:, 0] != base).any() or (O.trace_rays(pr, Pz - E, ids)[:, 0] != base).any():
+            continue
+        fd = (O.loss(O.forward(pr, Pz + E)[0], T, kind=1)[0] - O.loss(O.forward(pr, Pz - E)[0], T, kind=1)[0]) / (2 * h)
         assert abs(fd - g.flat[k]) <= 1e-6 * np.abs(g).max() + 1e-7 * abs(fd), (k, fd, g.flat[k])
         checked += 1
     assert checked >= Pz.size // 2
