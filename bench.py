@@ -211,25 +211,34 @@ def mean_search_steps(ffrt, wl, plan, Pz):
     return float(tr[tr[:, 0] == 0, 7].mean()) if (tr[:, 0] == 0).any() else 0.0
 
 
-def algorithmic_flops(wl, kernel, iters):
-    """FP32 operations of one launch of the forward or adjoint trace kernel over the whole workload."""
+def algorithmic_flops(wl, kernel, iters, steps=None):
+    """FP32 operations of one launch of the forward or adjoint trace kernel over the whole workload: a fixed
+    part per ray plus a part per search step (Newton iteration, or triangle-mesh cell).  `steps` (per design)
+    are the forward's own search-step totals (its statistics); otherwise every searching ray takes `iters`,
+    the mean of a per-ray inspection (which starts each search afresh, as the adjoint does)."""
     root_rays = sum(p.num_rays() for p in wl.problems
                     if p.source.kind != 0 and not p.lens.entry_freeform and not p.options.mesh_u)
     roots_reused = 0 < 4 * root_rays <= ROOTS_CAP_BYTES
     tot = 0.0
-    for p in wl.problems:
+    for d, p in enumerate(wl.problems):
         k = "collimated" if p.source.kind == 0 and not p.lens.entry_freeform else "point"
+        n = p.num_rays()
         if p.lens.entry_freeform:
-            f = FLOPS["point"][kernel] + FLOPS["point"]["newton_iter"] * iters + ENTRY_FLOPS[kernel]
+            f0, fs = FLOPS["point"][kernel] + ENTRY_FLOPS[kernel], FLOPS["point"]["newton_iter"]
         elif p.options.mesh_u:
-            cells = 1.0 if k == "collimated" else iters
-            f = FLOPS[k][kernel] + MESH_CELL_FLOPS * (cells + (kernel == "adjoint"))
-            f += MESH_ADJ_EXTRA if kernel == "adjoint" else 0
+            f0 = FLOPS[k][kernel] + (MESH_CELL_FLOPS + MESH_ADJ_EXTRA if kernel == "adjoint" else 0)
+            fs = MESH_CELL_FLOPS
         elif k == "point" and kernel == "adjoint" and roots_reused:
-            f = FLOPS[k][kernel] - FLOPS[k]["bracket"]
+            f0, fs = FLOPS[k][kernel] - FLOPS[k]["bracket"], 0.0
         else:
-            f = FLOPS[k][kernel] + FLOPS[k]["newton_iter"] * iters
-        tot += f * p.num_rays()
+            f0, fs = FLOPS[k][kernel], FLOPS[k]["newton_iter"]
+        if k == "collimated" and p.options.mesh_u:
+            s = float(n)                                # one cell per collimated ray
+        elif steps is not None and kernel == "forward":
+            s = float(steps[d])
+        else:
+            s = iters * n
+        tot += f0 * n + fs * s
     return tot, roots_reused
 
 
@@ -400,11 +409,16 @@ def main():
         fwd_ms, adj_ms = timed.time_kernels(st["Pz"], scratch_irr, dLdI, scratch_g, reps=args.steps,
                                             stream=stream)
 
-    # ---- roofline of the dominant trace kernel
+    # ---- roofline of the dominant trace kernel; the forward's search steps from its own statistics (it starts
+    # each Newton search at the previous ray's root), the adjoint's from a per-ray inspection
     iters = mean_search_steps(ffrt, wl, plan, st["Pz"])
+    stt = timed.new_stats()
+    timed.forward(st["Pz"], stats=stt)
+    fstats = timed.decode_stats(stt)
+    fwd_steps = [int(x) for x in fstats["n_search_steps"]]
     dom = "adjoint" if adj_ms >= fwd_ms else "forward"
     dom_ms = adj_ms if dom == "adjoint" else fwd_ms
-    dom_flops, roots_reused = algorithmic_flops(wl, dom, iters)
+    dom_flops, roots_reused = algorithmic_flops(wl, dom, iters, fwd_steps)
     achieved = dom_flops / (dom_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
@@ -415,10 +429,11 @@ def main():
             "peak_nonpacked": PEAK_FP32_NONPACKED_TFLOPS,
             "frac_of_nonpacked": achieved / PEAK_FP32_NONPACKED_TFLOPS,
             "forward_ms": fwd_ms, "adjoint_ms": adj_ms, "newton_iters_mean": iters,
+            "forward_search_steps_per_ray": sum(fwd_steps) / max(1, int(fstats["n_traced"].sum())),
             "adjoint_reuses_exit_roots": roots_reused,
             "search_steps": "mesh cells visited" if args.mesh else "Newton iterations"}
     other = "forward" if dom == "adjoint" else "adjoint"
-    other_flops, _ = algorithmic_flops(wl, other, iters)
+    other_flops, _ = algorithmic_flops(wl, other, iters, fwd_steps)
     other_ms = fwd_ms if other == "forward" else adj_ms
     roof[f"{other}_frac"] = other_flops / (other_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS
 

@@ -127,6 +127,7 @@ typedef struct {
     uint32_t n_newton_fail;       /* roots not converged within newton_max_iter */
     uint32_t n_fp64_refined;      /* grazing hits whose residual was re-checked in double precision */
     uint32_t n_nonmonotone;       /* rays whose root needed the bracket scan */
+    uint32_t n_search_steps;      /* Newton iterations (exact root) or mesh cells visited, summed over rays */
     uint32_t n_constraint_viol;   /* control points below z_in + delta_min (sec. 2.1.2) */
     uint32_t n_nan;               /* non-finite control points */
 } ffrt_stats;

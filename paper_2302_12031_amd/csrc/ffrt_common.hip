@@ -29,7 +29,7 @@ __host__ __device__ inline uint64_t mix64(uint64_t z) {
 // of 256 to 1024 threads; contains a barrier.
 __device__ void reduce_slots(int d, const DesignDev& D, const float* Pz, ffrt_stats* slots, ffrt_stats* stats) {
     constexpr int NF = sizeof(ffrt_stats) / 4;
-    static_assert(NSLOT == 64 && NF == 12, "one slot per lane, three fields per wave");
+    static_assert(NSLOT == 64 && NF == 13, "one slot per lane, at most three fields per wave");
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     uint32_t* slot = reinterpret_cast<uint32_t*>(slots + (size_t)d * NSLOT + lane);
     uint32_t* out = reinterpret_cast<uint32_t*>(stats + d);

@@ -58,7 +58,7 @@ class CAdam(ctypes.Structure):
 
 
 STATS_FIELDS = ["flux_on_screen", "n_traced", "n_hit", "n_miss_entry", "n_side_wall", "n_tir", "n_off_screen",
-                "n_newton_fail", "n_fp64_refined", "n_nonmonotone", "n_constraint_viol", "n_nan"]
+                "n_newton_fail", "n_fp64_refined", "n_nonmonotone", "n_search_steps", "n_constraint_viol", "n_nan"]
 STATS_DTYPE = np.dtype([(STATS_FIELDS[0], np.float32)] + [(f, np.uint32) for f in STATS_FIELDS[1:]])
 STATS_BYTES = STATS_DTYPE.itemsize
 
