@@ -420,7 +420,10 @@ __device__ RootOut intersect(const DesignDev& D, const BoundsDev& B, const float
     // unless (f not monotone) it crossed the surface and met it again before the aperture edge
     const bool end_below = t_ap <= t_hi && f_and_slope<P, Q>(D, sP, sKu, sKv, r, ozr, t_end, fp) > 0.0f;
     float gx = B.gx, gy = B.gy;
-    if (sS) {
+    // A ray that the design's global slope bounds already prove monotone and that has a start for Newton
+    // needs neither the narrowed bracket nor the local bounds.
+    const bool mono_global = gx * fabsf(r.dx) + gy * fabsf(r.dy) < r.dz;
+    if (sS && !(mono_global && t_guess >= 0.0f)) {
         // Local bounds: over [t_lo, t_end] the ray stays above the few span products its (x, y) segment
         // crosses, so every root lies where the ray height is inside their height range, and the slope
         // bounds of those spans alone decide monotonicity.  Signs at the narrowed ends stay known: the ray
@@ -931,18 +934,22 @@ __device__ __forceinline__ int filter_axis(float X, float R, float w, float inv_
     float delta = (X - c0) * inv_w;  // offset from the centre of pixel i0, in pixel widths
     float S = 0.0f, Sp = 0.0f;
     float fp[NU];
+    const float alpha_l2 = alpha * 1.44269504f;  // exp(-alpha d^2) = 2^(-alpha log2(e) d^2)
 #pragma unroll
     for (int m = 0; m < NU; ++m) {
         int i = i0 + m - H;
         float dm = delta - (float)(m - H);
-        bool in = (i >= 0) && (i < n) && (fabsf(dm) < 0.5f * (float)NU);
-        float e = __expf(-alpha * dm * dm);
-        F[m] = in ? e - edge : 0.0f;
-        S += F[m];
+        float e = DERIV ? __expf(-alpha * dm * dm) : __builtin_amdgcn_exp2f(-alpha_l2 * dm * dm);
         if constexpr (DERIV) {
+            bool in = (i >= 0) && (i < n) && (fabsf(dm) < 0.5f * (float)NU);
+            F[m] = in ? e - edge : 0.0f;
             fp[m] = in ? -2.0f * alpha * dm * e * inv_w : 0.0f;
             Sp += fp[m];
+        } else {
+            // the window is centred on the landing pixel, so |dm| <= nu / 2 and the support test is e >= edge
+            F[m] = (i >= 0) && (i < n) ? fmaxf(e - edge, 0.0f) : 0.0f;
         }
+        S += F[m];
     }
     float invS = rcpf(S);
 #pragma unroll
@@ -1778,8 +1785,12 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
     constexpr int TSH = 4 + (RPT >= 2) + (RPT >= 4) + (RPT >= 8) + (RPT >= 16);
     // per-thread accumulation window of WN x WN pixels: the filter windows of a thread's neighbouring rays
     // usually fall inside one such window, so most rays cost no atomic at all
-    constexpr bool ACCUM = NU <= 5;
-    constexpr int WN = NU + 1;
+    // Per-thread accumulation pays where a thread's neighbouring samples land within a pixel of each other
+    // (collimated bundles); the searched rays of point sources fan out, and a wave whose lanes leave their
+    // windows takes the direct path anyway: they add each ray's window to the tile directly.
+    constexpr bool ACCUM = NU <= 5 && (KIND & 5) == 0;
+    constexpr int SLACK = 1;  // a thread's rays whose filter windows start up to SLACK pixels apart share one window
+    constexpr int WN = NU + SLACK;
     extern __shared__ float smem[];
     float* sP = smem;
     float* sK = sP + A.lds_cp;
@@ -1933,14 +1944,16 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
             // compiler does not hoist the weights of every ray out of the pass loop.
             if constexpr (ACCUM) {
                 // Per-thread accumulation window anchored at the thread's lowest landing pixel (imin, jmin): rays
-                // whose filter window starts at most one pixel further along each axis are summed in registers,
-                // the others are added directly.  With the tile the sums are kept in tile units.
+                // whose filter window starts at most SLACK pixels further along each axis are summed in registers,
+                // the others are added directly.  With the tile the sums are kept in tile units.  A wave takes
+                // the direct path when any of its lanes needs it, so the slack covers the landing spread of a
+                // thread's neighbouring samples on fanned-out footprints.
                 const int ai = imin - H, aj = jmin - H;
                 const float wsc = use_tile ? D.fx_scale * (1.0f / (float)(1 << TSH)) : 1.0f;
                 float acc[WN * WN];
 #pragma unroll
                 for (int k = 0; k < WN * WN; ++k) acc[k] = 0.0f;
-                bool last_row = false, last_col = false;  // whether row / column WN - 1 of the window is used
+                int used_r = 0, used_c = 0;  // the largest window offsets of the thread's rays
 #pragma unroll
                 for (int r = 0; r < RPT; ++r) {
                     if (W[r] == 0.0f) continue;
@@ -1953,7 +1966,7 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
                     const int dj =
                         filter_axis<NU, false>(yr, D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr, D.box) -
                         H - aj;
-                    if (di > WN - NU || dj > WN - NU) {
+                    if (di > SLACK || dj > SLACK) {
 #pragma unroll
                         for (int a = 0; a < NU; ++a) {
                             if (!in_slab(ai + di + a)) continue;
@@ -1967,17 +1980,23 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
                         }
                         continue;
                     }
-                    last_row |= di != 0;
-                    last_col |= dj != 0;
-                    // add the NU x NU window at offset (di, dj) in {0, 1}^2 without indexing registers dynamically
+                    used_r = max(used_r, di);
+                    used_c = max(used_c, dj);
+                    // add the NU x NU window at offset (di, dj) in [0, SLACK]^2 without indexing registers
+                    // dynamically
                     const float wr = W[r] * wsc;
                     float fx[WN], fy[WN];
 #pragma unroll
                     for (int k = 0; k < WN; ++k) {
-                        float a0 = k < NU ? Fx[k] : 0.0f, a1 = k > 0 ? Fx[k - 1] : 0.0f;
-                        float b0 = k < NU ? Fy[k] : 0.0f, b1 = k > 0 ? Fy[k - 1] : 0.0f;
-                        fx[k] = wr * (di == 0 ? a0 : a1);
-                        fy[k] = dj == 0 ? b0 : b1;
+                        float xa = 0.0f, ya = 0.0f;
+#pragma unroll
+                        for (int o = 0; o <= SLACK; ++o) {
+                            if (k - o < 0 || k - o >= NU) continue;
+                            xa = di == o ? Fx[k - o] : xa;
+                            ya = dj == o ? Fy[k - o] : ya;
+                        }
+                        fx[k] = wr * xa;
+                        fy[k] = ya;
                     }
 #pragma unroll
                     for (int k = 0; k < WN * WN; ++k) acc[k] += fx[k / WN] * fy[k % WN];
@@ -1990,11 +2009,11 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
                         };
 #pragma unroll
                         for (int a = 0; a < WN; ++a) {
-                            if ((a == WN - 1 && !last_row) || !in_slab(ai + a)) continue;
+                            if (a >= used_r + NU || !in_slab(ai + a)) continue;
                             uint32_t* row = mytile + (ai + a - r0) * tw + (aj - jlo);
 #pragma unroll
-                            for (int bb = 0; bb < WN - 1; ++bb) add(row + bb, acc[a * WN + bb]);
-                            if (last_col) add(row + WN - 1, acc[a * WN + WN - 1]);
+                            for (int bb = 0; bb < WN; ++bb)
+                                if (bb < used_c + NU) add(row + bb, acc[a * WN + bb]);
                         }
                     }
                 } else {
