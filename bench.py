@@ -39,13 +39,15 @@ METRIC = "forward+adjoint rays/s and Adam steps/s vs finite-diff gradient, same 
 # Algorithmic FP32 operations per ray (add, mul, compare-free arithmetic; fma = 2; exp, sqrt, rsqrt, rcp,
 # sincos = 1 each), counted stage by stage from the kernels' formulation for p = q = 3, nu = 3, with the
 # closed-form uniform cubic of interior spans: 27 operations per axis for N and N', 4 more for N''
-# (the generic recurrence takes ~42 and ~20).
+# (the generic recurrence takes ~42 and ~20).  tests/test_flop_table.py holds the totals against the FP32
+# instructions the hardware counted per ray (rocprofv3 SQ_INSTS_VALU_{FMA,MUL,ADD,TRANS}_F32, summaries in
+# profiles/); the point-source adjoint's total is that count (its stage-by-stage sum overstated it).
 FLOPS = {
     "collimated": {"forward": 320, "adjoint": 525, "newton_iter": 0},
     # point sources: fixed part (with the exit-root bracket) + per Newton iteration (surface value and slope,
     # step).  Inside a step the adjoint of exact-root, flat-entry designs reads the roots the forward stored:
     # it does neither the bracket nor the iterations.
-    "point": {"forward": 390, "adjoint": 998, "newton_iter": 194, "bracket": 35},
+    "point": {"forward": 390, "adjoint": 777, "newton_iter": 194, "bracket": 35},
 }
 # Plans keep the exit roots for the adjoint when they take at most this many bytes (4 per ray).
 ROOTS_CAP_BYTES = 1 << 30
@@ -242,6 +244,26 @@ def algorithmic_flops(wl, kernel, iters, steps=None):
     return tot, roots_reused
 
 
+def lds_atomic_roofline(ffrt, wl, fstats, fwd_cfg, fwd_ms, stream):
+    """The forward's LDS-tile atomics against the chip's measured LDS-atomic throughput (ffrt_lds_atomic_rate:
+    distinct banks, and the splat's own access pattern).  Point-source and freeform-entry rays add their
+    nu_x x nu_y window per hit; collimated threads add one (nu_x + 1) x (nu_y + 1) window per RPT rays."""
+    if "lds-tile" not in fwd_cfg:
+        return None
+    rpt = int(fwd_cfg.split("rpt")[1].split()[0])
+    n = 0.0
+    for d, p in enumerate(wl.problems):
+        hits = float(fstats["n_hit"][d])
+        nu = p.detector.nu_x * p.detector.nu_y
+        direct = p.source.kind != 0 or p.lens.entry_freeform or nu > 25
+        n += hits * (nu if direct else (p.detector.nu_x + 1) * (p.detector.nu_y + 1) / rpt)
+    peak = ffrt.lds_atomic_rate(0, stream=stream)
+    splat = ffrt.lds_atomic_rate(1, stream=stream)
+    achieved = n / (fwd_ms * 1e-3)
+    return {"per_launch": n, "achieved_per_s": achieved, "peak_per_s": peak, "splat_pattern_per_s": splat,
+            "frac_of_peak": achieved / peak, "frac_of_splat_pattern": achieved / splat}
+
+
 def finite_differences(ffrt, W, wl, plan, T, ms_step, with_oracle):
     """Forward-only central differences over every control point of a single-design workload at its initial
     design, on the same GPU, against the adjoint."""
@@ -436,6 +458,7 @@ def main():
     other_flops, _ = algorithmic_flops(wl, other, iters, fwd_steps)
     other_ms = fwd_ms if other == "forward" else adj_ms
     roof[f"{other}_frac"] = other_flops / (other_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS
+    roof["lds_atomics"] = lds_atomic_roofline(ffrt, wl, fstats, R["cfg"][0], fwd_ms, stream)
 
     generator = None
     if arch is not None:

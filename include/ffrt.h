@@ -324,6 +324,14 @@ ffrt_status ffrt_plan_time_mlp(ffrt_plan* plan, int32_t arch, float* params, flo
 ffrt_status ffrt_trace_rays(ffrt_plan* plan, int32_t design, const float* Pz, const int64_t* ray_ids,
                             int64_t n, float* out8, void* stream);
 
+/* Throughput of LDS atomic adds (ds_add_u32, workgroup scope) on the current device, in atomics per second
+ * over the whole chip: 8 workgroups of 256 threads per compute unit each add 256 rounds of 9 values to a
+ * tile of their own, launched reps times after one untimed launch (HIP events on `stream`, synchronised).
+ * pattern 0: distinct addresses in distinct banks (the unit's peak); pattern 1: the forward's splat (an
+ * 8 x 8 lane grid of rays two pixels apart, each adding its 3 x 3 filter window).  Allocates and frees a
+ * small device buffer (hipMalloc), so it is not for graph capture.  A measurement aid for the roofline of the splat, not part of the method. */
+ffrt_status ffrt_lds_atomic_rate(int32_t pattern, int32_t reps, double* atomics_per_s, void* stream);
+
 /* The ray-sampling random numbers: out[i] = SplitMix64 output for (seed, stream, first + i) (device). */
 ffrt_status ffrt_rng(uint64_t seed, uint64_t stream_id, uint64_t first, int64_t n, uint64_t* out,
                      void* stream);

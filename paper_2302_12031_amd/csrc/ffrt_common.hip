@@ -315,37 +315,7 @@ __global__ __launch_bounds__(256) void k_gscale(const DesignDev* designs, const 
 __global__ __launch_bounds__(256) void k_finish(const DesignDev* designs, unsigned long long* gacc, uint32_t* gmax,
                                                 float* dLdP, const int32_t* valid, AdamArgs adam) {
     const int d = blockIdx.x;
-    const DesignDev& D = designs[d];
-    unsigned long long* acc = gacc + D.cp_off;
-    float* out = dLdP + D.cp_off;
-    const double unit = ldexp(1.0, fixed_point_exponent(gmax[d], D.w0));
-    __syncthreads();
-    if (threadIdx.x == 0) gmax[d] = 0u;
-    auto take = [acc, out, unit](int i) {
-        const float g = (float)((double)(long long)acc[i] * unit);
-        acc[i] = 0ull;
-        out[i] = g;
-        return g;
-    };
-    const int ncp = D.ncp;
-    const bool step = adam.Pz && (!valid || valid[d]);
-    if (step && adam.theta) {
-        // range reparametrisation (sec. 2.4.1): Adam on theta, then P from the new theta
-        float* th = adam.theta + D.cp_off;
-        const float* lo = adam.lo + D.cp_off;
-        const float* sp = adam.span + D.cp_off;
-        auto take_theta = [take, th, sp](int i) {
-            const float y = tanhf(th[i]);
-            return take(i) * (0.5f * (1.0f - y * y) * sp[i]);
-        };
-        adam_update(adam.theta, adam.m, adam.v, adam.t + d, D.cp_off, ncp, adam.hp, take_theta);
-        float* P = adam.Pz + D.cp_off;
-        for (int i = threadIdx.x; i < ncp; i += blockDim.x) P[i] = lo[i] + 0.5f * (tanhf(th[i]) + 1.0f) * sp[i];
-    } else if (step) {
-        adam_update(adam.Pz, adam.m, adam.v, adam.t + d, D.cp_off, ncp, adam.hp, take);
-    } else {
-        for (int i = threadIdx.x; i < ncp; i += blockDim.x) take(i);
-    }
+    finish_design(designs[d], d, gacc, gmax, dLdP, valid, adam);
 }
 
 // Range reparametrisation of sec. 2.4.1 (eq. of the output correction, with or without the offset
@@ -402,6 +372,43 @@ __global__ __launch_bounds__(256) void k_adam(const DesignDev* designs, float* P
 __global__ void k_rng(uint64_t state0, uint64_t first, int64_t n, uint64_t* out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = mix64(state0 + (first + (uint64_t)i + 1) * GAMMA);
+}
+
+// LDS-atomic throughput: every thread adds `iters` rounds of 9 values to a per-workgroup tile of TILE_CAP words
+// with ds_add_u32.  Pattern 0: lane l of wave w adds to word 64 w + l + 256 k for tap k (distinct banks, no
+// shared addresses: the unit's peak).  Pattern 1: the forward's splat: the lanes of a wave are an 8 x 8 grid
+// of rays landing two pixels apart (a hash of lane and round moves each by a pixel) in a tile 40 pixels wide,
+// and each adds the 3 x 3 filter window around its landing pixel, one tap per instruction.  The tile's sum
+// goes to out[blockIdx.x] so that nothing is left out.
+__global__ __launch_bounds__(256) void k_lds_atomics(int pattern, int iters, uint32_t* out) {
+    __shared__ uint32_t tile[TILE_CAP];
+    for (int i = threadIdx.x; i < TILE_CAP; i += 256) tile[i] = 0u;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int TW = 40;
+    for (int it = 0; it < iters; ++it) {
+        const uint32_t h = (uint32_t)(lane * 0x9E3779B1u) ^ (uint32_t)(it * 0x85EBCA77u);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            int a;
+            if (pattern == 0) {
+                a = wave * 64 + lane + 256 * k;
+            } else {
+                const int px = 2 * (lane & 7) + ((h >> 3) & 1) + (wave & 1) * 16 + k % 3;
+                const int py = 2 * (lane >> 3) + ((h >> 7) & 1) + (wave >> 1) * 16 + k / 3;
+                a = py * TW + px;
+            }
+            __hip_atomic_fetch_add(&tile[a], 1u + (h & 1u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    __syncthreads();
+    uint32_t s = 0;
+    for (int i = threadIdx.x; i < TILE_CAP; i += 256) s += tile[i];
+    s = wave_sum(s);
+    __shared__ uint32_t part[4];
+    if (lane == 0) part[wave] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
 }
 
 // Fill n 32-bit words with v (a kernel, not a memset node, so that graph captures of its callers replay it
@@ -506,6 +513,11 @@ hipError_t launch_loss_f64(const DesignDev* designs, int n_designs, const float*
 hipError_t launch_adam(const DesignDev* designs, int n_designs, float* Pz, const float* g, float* m,
                        float* v, int32_t* t, const int32_t* valid, ffrt_adam_hparams hp, hipStream_t s) {
     hipLaunchKernelGGL(k_adam, dim3(n_designs), dim3(256), 0, s, designs, Pz, g, m, v, t, valid, hp);
+    return hipGetLastError();
+}
+
+hipError_t launch_lds_atomics(int pattern, int iters, int grid, uint32_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_lds_atomics, dim3(grid), dim3(256), 0, s, pattern, iters, out);
     return hipGetLastError();
 }
 

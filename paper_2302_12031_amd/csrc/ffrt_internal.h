@@ -133,6 +133,16 @@ struct AdamArgs {
     const float* span;
 };
 
+// The end of a step's adjoint: dL/dP from the fixed-point accumulator, and Adam when adam.Pz is set (see
+// finish_design).  With `done` set the last workgroup of the adjoint's double-precision re-trace does it for
+// every design (done: a zeroed device counter that the kernel leaves zero).
+struct FinishArgs {
+    float* dLdP;
+    const int32_t* valid;
+    AdamArgs adam;
+    uint32_t* done;
+};
+
 struct TraceArgs {
     const DesignDev* designs;
     const BoundsDev* bounds;         // of the current Pz, for point and grid sources
@@ -166,6 +176,7 @@ struct TraceArgs {
     QEntry* queue;
     int32_t* qcount;
     int64_t qbase;
+    FinishArgs fin;                  // adjoint_fp64: the step's finish in its last workgroup (fin.done null: none)
 };
 
 // Queue capacity per logical block of the adjoint: 1/64 of its rays (the re-traced rays are ~0.4 %).
@@ -250,6 +261,7 @@ hipError_t launch_loss_f64(const DesignDev* designs, int n_designs, const float*
                            double* loss, hipStream_t s);
 hipError_t launch_adam(const DesignDev* designs, int n_designs, float* Pz, const float* g, float* m,
                        float* v, int32_t* t, const int32_t* valid, ffrt_adam_hparams hp, hipStream_t s);
+hipError_t launch_lds_atomics(int pattern, int iters, int grid, uint32_t* out, hipStream_t s);
 hipError_t launch_rng(uint64_t seed, uint64_t stream_id, uint64_t first, int64_t n, uint64_t* out,
                       hipStream_t s);
 

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "ffrt_internal.h"
+#include "loss.hpp"
 
 namespace ffrt {
 
@@ -45,6 +46,46 @@ __device__ inline void adam_update(float* Pz, float* m, float* v, int32_t* t, in
     }
     __syncthreads();
     if (threadIdx.x == 0) t[0] = tn;
+}
+
+// dL/dP of design d from its 64-bit fixed-point accumulator (unit from the cotangent bound gmax[d]), which is
+// cleared with gmax[d]; then Adam on P, or on theta of the range reparametrisation (sec. 2.4.1) followed by
+// P = lo + (tanh(theta) + 1) span / 2, when adam.Pz is set and the design's step is valid.  One workgroup
+// per design; every thread must call it (it contains barriers).  The accumulator is read with device-scope
+// atomic loads, so that the last workgroup of the kernel that produced it may call this too.
+__device__ inline void finish_design(const DesignDev& D, int d, unsigned long long* gacc, uint32_t* gmax,
+                                     float* dLdP, const int32_t* valid, const AdamArgs& adam) {
+    unsigned long long* acc = gacc + D.cp_off;
+    float* out = dLdP + D.cp_off;
+    const double unit = ldexp(1.0, fixed_point_exponent(gmax[d], D.w0));
+    __syncthreads();
+    if (threadIdx.x == 0) gmax[d] = 0u;
+    auto take = [acc, out, unit](int i) {
+        const unsigned long long q = __hip_atomic_load(&acc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const float g = (float)((double)(long long)q * unit);
+        acc[i] = 0ull;
+        out[i] = g;
+        return g;
+    };
+    const int ncp = D.ncp;
+    const bool step = adam.Pz && (!valid || valid[d]);
+    if (step && adam.theta) {
+        float* th = adam.theta + D.cp_off;
+        const float* lo = adam.lo + D.cp_off;
+        const float* sp = adam.span + D.cp_off;
+        auto take_theta = [take, th, sp](int i) {
+            const float y = tanhf(th[i]);
+            return take(i) * (0.5f * (1.0f - y * y) * sp[i]);
+        };
+        adam_update(adam.theta, adam.m, adam.v, adam.t + d, D.cp_off, ncp, adam.hp, take_theta);
+        float* P = adam.Pz + D.cp_off;
+        for (int i = threadIdx.x; i < ncp; i += blockDim.x) P[i] = lo[i] + 0.5f * (tanhf(th[i]) + 1.0f) * sp[i];
+    } else if (step) {
+        adam_update(adam.Pz, adam.m, adam.v, adam.t + d, D.cp_off, ncp, adam.hp, take);
+    } else {
+        for (int i = threadIdx.x; i < ncp; i += blockDim.x) take(i);
+    }
+    __syncthreads();
 }
 
 }  // namespace ffrt

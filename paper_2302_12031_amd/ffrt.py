@@ -74,7 +74,7 @@ HEADER_FUNCTIONS = [
     "ffrt_trace_rays", "ffrt_rng", "ffrt_status_string", "ffrt_last_error",
     "ffrt_reparam_apply", "ffrt_reparam_grad", "ffrt_step_reparam", "ffrt_graph_capture_reparam",
     "ffrt_plan_control_xy", "ffrt_mlp_layout", "ffrt_mlp_forward", "ffrt_mlp_backward", "ffrt_step_mlp",
-    "ffrt_graph_capture_mlp", "ffrt_plan_time_mlp", "ffrt_forward_static",
+    "ffrt_graph_capture_mlp", "ffrt_plan_time_mlp", "ffrt_forward_static", "ffrt_lds_atomic_rate",
 ]
 
 _lib = None
@@ -114,6 +114,7 @@ def lib():
             "ffrt_plan_autotune": [vp, vp, vp, vp, vp, i32, vp],
             "ffrt_trace_rays": [vp, i32, vp, vp, i64, vp, vp],
             "ffrt_rng": [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, i64, vp, vp],
+            "ffrt_lds_atomic_rate": [i32, i32, P(ctypes.c_double), vp],
             "ffrt_reparam_apply": [vp, vp, vp, vp, vp, vp],
             "ffrt_reparam_grad": [vp, vp, vp, vp, vp, vp],
             "ffrt_step_reparam": [vp] + [vp] * 13 + [P(CAdam), vp],
@@ -526,6 +527,13 @@ def rng(seed, stream_id, first, n, device="cuda"):
     out = torch.empty(n, dtype=torch.int64, device=device)
     _check(lib().ffrt_rng(seed, stream_id, first, n, _ptr(out), _stream()), "ffrt_rng")
     return out.cpu().numpy().view(np.uint64)
+
+
+def lds_atomic_rate(pattern, reps=20, stream=None):
+    """LDS atomic adds per second over the chip (pattern 0: distinct banks, 1: the forward's splat)."""
+    r = ctypes.c_double()
+    _check(lib().ffrt_lds_atomic_rate(pattern, reps, ctypes.byref(r), _stream(stream)), "ffrt_lds_atomic_rate")
+    return r.value
 
 
 class TraceLoss(torch.autograd.Function):

@@ -275,3 +275,15 @@ def test_gradient_is_reproducible_bit_for_bit(name):
     torch.cuda.synchronize()
     assert torch.equal(g1, g2)
     assert g1.abs().max().item() > 0
+
+
+def test_lds_atomic_rate_microbenchmark():
+    """ffrt_lds_atomic_rate: a positive chip-wide rate for both access patterns; the splat's pattern (shared
+    banks and addresses) cannot beat distinct banks by more than timing noise."""
+    peak = ffrt.lds_atomic_rate(0, reps=5)
+    splat = ffrt.lds_atomic_rate(1, reps=5)
+    _say(f"[lds] atomics/s: distinct banks {peak:.3e}, splat pattern {splat:.3e}")
+    assert peak > 1e11 and splat > 1e10
+    assert splat <= 1.1 * peak
+    with pytest.raises(ffrt.FfrtError):
+        ffrt.lds_atomic_rate(2)
