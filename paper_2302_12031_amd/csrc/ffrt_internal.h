@@ -133,16 +133,6 @@ struct AdamArgs {
     const float* span;
 };
 
-// The end of a step's adjoint: dL/dP from the fixed-point accumulator, and Adam when adam.Pz is set (see
-// finish_design).  With `done` set the last workgroup of the adjoint's double-precision re-trace does it for
-// every design (done: a zeroed device counter that the kernel leaves zero).
-struct FinishArgs {
-    float* dLdP;
-    const int32_t* valid;
-    AdamArgs adam;
-    uint32_t* done;
-};
-
 struct TraceArgs {
     const DesignDev* designs;
     const BoundsDev* bounds;         // of the current Pz, for point and grid sources
@@ -176,7 +166,6 @@ struct TraceArgs {
     QEntry* queue;
     int32_t* qcount;
     int64_t qbase;
-    FinishArgs fin;                  // adjoint_fp64: the step's finish in its last workgroup (fin.done null: none)
 };
 
 // Queue capacity per logical block of the adjoint: 1/64 of its rays (the re-traced rays are ~0.4 %).

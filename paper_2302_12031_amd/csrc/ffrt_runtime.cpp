@@ -81,7 +81,7 @@ struct ffrt_plan {
     size_t off_designs = 0, off_bounds = 0, off_sb = 0, off_valid = 0, off_knots = 0, off_bmap = 0, off_slots = 0;
     size_t need = 0;
     size_t off_lpart = 0, off_img64 = 0, off_gacc = 0, off_gmax = 0, off_dldi = 0, off_mlpoff = 0, off_mlpvec = 0,
-           off_roots = 0, off_d64 = 0, off_queue = 0, off_qcount = 0, off_done = 0;
+           off_roots = 0, off_d64 = 0, off_queue = 0, off_qcount = 0;
     int num_cu = 256;
     int fwd_cfg = 0, adj_cfg = 0;
     hipGraph_t graph = nullptr;
@@ -100,7 +100,6 @@ struct ffrt_plan {
     unsigned long long* d_img64() const { return reinterpret_cast<unsigned long long*>(ws + off_img64); }
     unsigned long long* d_gacc() const { return reinterpret_cast<unsigned long long*>(ws + off_gacc); }
     uint32_t* d_gmax() const { return reinterpret_cast<uint32_t*>(ws + off_gmax); }
-    uint32_t* d_done() const { return reinterpret_cast<uint32_t*>(ws + off_done); }
     float* d_dldi() const { return reinterpret_cast<float*>(ws + off_dldi); }
     int64_t* d_mlpoff(int arch) const { return reinterpret_cast<int64_t*>(ws + off_mlpoff) + (size_t)arch * (nd + 1); }
     float* d_mlpvec(int k) const { return reinterpret_cast<float*>(ws + off_mlpvec) + (size_t)k * total_cp; }
@@ -359,11 +358,8 @@ ffrt_status launch_forward(ffrt_plan* pl, const float* Pz, bool stats, hipStream
 
 // The adjoint trace kernel, into the plan's gradient accumulator (launch_finish turns it into dL/dP).  With
 // `roots` the rays of kernel group 1 take their exit roots from the root buffer, which a forward with the
-// same Pz must have filled.  With `fin` the last workgroup of the double-precision re-trace, when there is
-// one, also finishes the step (dL/dP, Adam) and *folded is set; otherwise the caller launches k_finish.
-ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hipStream_t s, bool roots = false,
-                           const FinishArgs* fin = nullptr, bool* folded = nullptr) {
-    if (folded) *folded = false;
+// same Pz must have filled.
+ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hipStream_t s, bool roots = false) {
     const AdjCfg& c = ADJ_CFGS[pl->adj_cfg];
     // the rays of kernel groups 0 and 1 whose derivative single precision cannot resolve are queued per
     // logical block (group 1's blocks after group 0's) and re-traced in double precision afterwards
@@ -392,12 +388,7 @@ ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hi
         A.gmax = pl->d_gmax();
         A.queue = pl->d_queue();
         A.qcount = pl->d_qcount();
-        if (fin) {
-            A.fin = *fin;
-            A.fin.done = pl->d_done();
-        }
         HIP_TRY(pl->ks->adjoint_fp64(A, pl->d_d64(), c.shape, qblocks, s));
-        if (fin && folded) *folded = true;
     }
     return FFRT_OK;
 }
@@ -429,11 +420,8 @@ ffrt_status run_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, float
     if (ffrt_status b = run_bounds(pl, Pz, s)) return b;
     // the cotangent bound that sets the unit of the fixed-point gradient sums, from the dL/dI given
     HIP_TRY(launch_gscale(pl->d_designs(), pl->nd, dLdI, pl->d_gmax(), s));
-    const FinishArgs fin{dLdP, nullptr, no_adam(), nullptr};
-    bool folded = false;
-    if (ffrt_status a = launch_adjoint(pl, Pz, dLdI, s, roots, &fin, &folded)) return a;
-    if (!folded)
-        HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), pl->d_gmax(), dLdP, nullptr, no_adam(), s));
+    if (ffrt_status a = launch_adjoint(pl, Pz, dLdI, s, roots)) return a;
+    HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), pl->d_gmax(), dLdP, nullptr, no_adam(), s));
     return FFRT_OK;
 }
 
@@ -463,12 +451,9 @@ ffrt_status run_step(ffrt_plan* pl, float* Pz, const float* target, float* irr, 
     adam.theta = theta;
     adam.lo = lo;
     adam.span = span;
-    const FinishArgs fin{dLdP, pl->d_valid(), adam, nullptr};
-    bool folded = false;
-    st = launch_adjoint(pl, Pz, dLdI, s, true, &fin, &folded);
+    st = launch_adjoint(pl, Pz, dLdI, s, true);
     if (st) return st;
-    if (!folded)
-        HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), pl->d_gmax(), dLdP, pl->d_valid(), adam, s));
+    HIP_TRY(launch_finish(pl->d_designs(), pl->nd, pl->d_gacc(), pl->d_gmax(), dLdP, pl->d_valid(), adam, s));
     return FFRT_OK;
 }
 
@@ -640,8 +625,6 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
     off = align256(off + sizeof(unsigned long long) * (size_t)pl->total_cp);
     pl->off_gmax = off;
     off = align256(off + sizeof(uint32_t) * n_designs);
-    pl->off_done = off;  // workgroups of the adjoint's last kernel that have finished (zero between launches)
-    off = align256(off + sizeof(uint32_t));
     // the adjoint's double-precision re-trace: design parameters, and a queue segment of queue_cap / 4 rays
     // per wave of every logical block (sized over all kernel groups, of which 0 and 1 use it, for the adjoint
     // shape that needs most)
@@ -708,7 +691,6 @@ ffrt_status ffrt_plan_set_workspace(ffrt_plan* plan, void* dev_ptr, size_t bytes
     HIP_TRY(hipMemset(plan->d_img64(), 0, sizeof(unsigned long long) * plan->total_img));
     HIP_TRY(hipMemset(plan->d_gacc(), 0, sizeof(unsigned long long) * plan->total_cp));
     HIP_TRY(hipMemset(plan->d_gmax(), 0, sizeof(uint32_t) * plan->nd));
-    HIP_TRY(hipMemset(plan->d_done(), 0, sizeof(uint32_t)));
     for (int a = 0; a < 2; ++a)
         HIP_TRY(hipMemcpy(plan->d_mlpoff(a), plan->mlp_off[a].data(), sizeof(int64_t) * plan->mlp_off[a].size(),
                           hipMemcpyHostToDevice));

@@ -1,5 +1,5 @@
 // Adam update of one design's control points (Kingma & Ba, bias-corrected), shared by the standalone Adam
-// kernel and the adjoint's last-workgroup epilogue.
+// kernel and the step's finish.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -51,8 +51,7 @@ __device__ inline void adam_update(float* Pz, float* m, float* v, int32_t* t, in
 // dL/dP of design d from its 64-bit fixed-point accumulator (unit from the cotangent bound gmax[d]), which is
 // cleared with gmax[d]; then Adam on P, or on theta of the range reparametrisation (sec. 2.4.1) followed by
 // P = lo + (tanh(theta) + 1) span / 2, when adam.Pz is set and the design's step is valid.  One workgroup
-// per design; every thread must call it (it contains barriers).  The accumulator is read with device-scope
-// atomic loads, so that the last workgroup of the kernel that produced it may call this too.
+// per design; every thread must call it (it contains barriers).
 __device__ inline void finish_design(const DesignDev& D, int d, unsigned long long* gacc, uint32_t* gmax,
                                      float* dLdP, const int32_t* valid, const AdamArgs& adam) {
     unsigned long long* acc = gacc + D.cp_off;
@@ -61,8 +60,7 @@ __device__ inline void finish_design(const DesignDev& D, int d, unsigned long lo
     __syncthreads();
     if (threadIdx.x == 0) gmax[d] = 0u;
     auto take = [acc, out, unit](int i) {
-        const unsigned long long q = __hip_atomic_load(&acc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const float g = (float)((double)(long long)q * unit);
+        const float g = (float)((double)(long long)acc[i] * unit);
         acc[i] = 0ull;
         out[i] = g;
         return g;

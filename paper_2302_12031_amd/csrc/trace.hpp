@@ -21,7 +21,6 @@
 
 #include "ffrt_internal.h"
 #include "loss.hpp"
-#include "optim.hpp"
 #include "wave.hpp"
 
 namespace ffrt {
@@ -1697,22 +1696,6 @@ __global__ __launch_bounds__(WG) void k_adjoint_fp64(TraceArgs A, const DesignDe
             if (v != 0ull) atomicAdd(&gacc[i], v);
         }
         __syncthreads();  // s_off and sG are rewritten by the next round
-    }
-    if (A.fin.done) {
-        // the last workgroup to get here finishes the step for every design: all other workgroups' additions
-        // to the accumulator (and the main adjoint's, a kernel earlier) are visible after the fences
-        __shared__ bool s_last;
-        __threadfence();
-        __syncthreads();
-        if (threadIdx.x == 0) s_last = atomicAdd(A.fin.done, 1u) == gridDim.x - 1;
-        __syncthreads();
-        if (s_last) {
-            __threadfence();
-            for (int d = 0; d < A.n_designs; ++d)
-                finish_design(load_uniform(A.designs, d), d, A.gacc, const_cast<uint32_t*>(A.gmax), A.fin.dLdP,
-                              A.fin.valid, A.fin.adam);
-            if (threadIdx.x == 0) *A.fin.done = 0u;
-        }
     }
 }
 
