@@ -2034,15 +2034,32 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
                         filter_axis<NU, false>(xr, D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr, D.box);
                     const int j0 =
                         filter_axis<NU, false>(yr, D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr, D.box);
+                    if (use_tile) {
+                        // the tile holds every row and column of the window (pixels off the image get zero
+                        // weights, which the flush skips): nine adds without a test, rows outside the slab aside
+                        const float wr = W[r] * (D.fx_scale * (1.0f / (float)(1 << TSH)));
+#pragma unroll
+                        for (int a = 0; a < NU; ++a) {
+                            const int i = i0 + a - H;
+                            if (npass > 1 && !in_slab(i)) continue;
+                            uint32_t* row = mytile + (i - r0) * tw + (j0 - H - jlo);
+                            const float wa = wr * Fx[a];
+#pragma unroll
+                            for (int bb = 0; bb < NU; ++bb)
+                                __hip_atomic_fetch_add(row + bb, (uint32_t)__float2int_rn(wa * Fy[bb]), __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                        continue;
+                    }
 #pragma unroll
                     for (int a = 0; a < NU; ++a) {
                         const int i = i0 + a - H;
-                        if (i < 0 || i >= D.nx || !in_slab(i)) continue;
+                        if (i < 0 || i >= D.nx) continue;
 #pragma unroll
                         for (int bb = 0; bb < NU; ++bb) {
                             const int j = j0 + bb - H;
                             if (j < 0 || j >= D.ny) continue;
-                            splat_add<TSH>(use_tile, mytile, tw, r0, jlo, D.fx_scale, img, D.ny, i, j,
+                            splat_add<TSH>(false, mytile, tw, r0, jlo, D.fx_scale, img, D.ny, i, j,
                                            W[r] * Fx[a] * Fy[bb]);
                         }
                     }
