@@ -40,8 +40,14 @@ __device__ __forceinline__ uint64_t splitmix_mix(uint64_t z) {
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
 }
+constexpr uint64_t SPLITMIX_GAMMA = 0x9E3779B97F4A7C15ull;
 __device__ __forceinline__ uint64_t splitmix_at(uint64_t state0, uint64_t index) {
-    return splitmix_mix(state0 + (index + 1) * 0x9E3779B97F4A7C15ull);
+    return splitmix_mix(state0 + (index + 1) * SPLITMIX_GAMMA);
+}
+// The counter of ray `id`, splitmix_at(state0, id) = splitmix_mix(rng_counter(state0, id)): ray id + k has the
+// counter + k gamma, so a thread's further rays take a 64-bit addition instead of a multiplication.
+__device__ __forceinline__ uint64_t rng_counter(uint64_t state0, int64_t id) {
+    return state0 + ((uint64_t)id + 1) * SPLITMIX_GAMMA;
 }
 // Two 24-bit uniforms in [0, 1), exact in float.
 __device__ __forceinline__ void two_uniforms(uint64_t h, float& a, float& b) {
@@ -300,11 +306,11 @@ __device__ __forceinline__ void sample_span(int k, float xi, int G, float inv_G,
 // KIND bit 0 clear: collimated source; set: point source or grid of point sources (D.kind 1 or 2).  Bit 1
 // selects the triangle-mesh intersection of sec. 2.2.2 instead of the exact root (see below).
 template <int KIND>
-__device__ __forceinline__ RayIn ray_entry(const DesignDev& D, int e, int ku, int kv, int64_t id) {
+__device__ __forceinline__ RayIn ray_entry(const DesignDev& D, int e, int ku, int kv, uint64_t ctr) {
     RayIn r;
     r.status = ST_HIT;
     float x1 = 0.5f, x2 = 0.5f;
-    if (D.jitter) two_uniforms(splitmix_at(D.rng_state0, (uint64_t)id), x1, x2);
+    if (D.jitter) two_uniforms(splitmix_mix(ctr), x1, x2);
     if constexpr ((KIND & 1) == 0) {
         // Collimated bundle: samples on the grid of [0,1]^2, mapped linearly to the aperture; the ray meets
         // the flat face at normal incidence (Schlick weight 1 - R0) and travels along +z.
@@ -534,12 +540,12 @@ struct EntryHit {
 
 template <int P, int Q, bool POINT>
 __device__ __forceinline__ RayIn ray_entry_ff(const DesignDev& D, const BoundsDev& B, const float* sPin,
-                                              const float* sKu, const float* sKv, int e, int ku, int kv, int64_t id,
-                                              EntryHit& H) {
+                                              const float* sKu, const float* sKv, int e, int ku, int kv,
+                                              uint64_t ctr, EntryHit& H) {
     RayIn r;
     r.status = ST_HIT;
     float x1 = 0.5f, x2 = 0.5f;
-    if (D.jitter) two_uniforms(splitmix_at(D.rng_state0, (uint64_t)id), x1, x2);
+    if (D.jitter) two_uniforms(splitmix_mix(ctr), x1, x2);
     if constexpr (!POINT) {
         const float u = ((float)ku + x1) * D.inv_gu, v = ((float)kv + x2) * D.inv_gv;
         H.sx = (2.0f * u - 1.0f) * D.r_x;
@@ -973,7 +979,7 @@ struct FwdRay {
 template <int P, int Q, int KIND>
 __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const BoundsDev& B, const float* sP,
                                                 const float* sKu, const float* sKv, const float* sS, int e, int ku,
-                                                int kv, int64_t id,
+                                                int kv, uint64_t ctr,
                                                 float* tsave = nullptr, float t_guess = -1.0f) {
     FwdRay o;
     o.iters = o.failed = o.nonmono = o.refined = 0;
@@ -985,9 +991,9 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
     RayIn r;
     if constexpr (ENTRY) {
         EntryHit H;
-        r = ray_entry_ff<P, Q, POINT>(D, B, sP + D.n_u * D.n_v, sKu, sKv, e, ku, kv, id, H);
+        r = ray_entry_ff<P, Q, POINT>(D, B, sP + D.n_u * D.n_v, sKu, sKv, e, ku, kv, ctr, H);
     } else {
-        r = ray_entry<KIND>(D, e, ku, kv, id);
+        r = ray_entry<KIND>(D, e, ku, kv, ctr);
     }
     o.status = r.status;
     // exit root for the adjoint of the same step (point sources, exact root, flat entry): -1 when none
@@ -1105,7 +1111,7 @@ template <int P, int Q, int NU, int KIND, class Enqueue = NoQueue>
 __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDev& B, const float* sP,
                                               const float* sKu, const float* sKv, const float* sS,
                                               const float* __restrict__ G,
-                                              int e, int ku, int kv, int64_t id, int& cku, int& ckv,
+                                              int e, int ku, int kv, uint64_t ctr, int& cku, int& ckv,
                                               float* g, int& cku_in, int& ckv_in, float* gin,
                                               const float* tload = nullptr, Enqueue enqueue = Enqueue()) {
     constexpr bool point = (KIND & 1) != 0, MESH = (KIND & 2) != 0, ENTRY = (KIND & 4) != 0;
@@ -1113,9 +1119,9 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
     EntryHit EH;
     RayIn r;
     if constexpr (ENTRY) {
-        r = ray_entry_ff<P, Q, point>(D, B, sP + D.n_u * D.n_v, sKu, sKv, e, ku, kv, id, EH);
+        r = ray_entry_ff<P, Q, point>(D, B, sP + D.n_u * D.n_v, sKu, sKv, e, ku, kv, ctr, EH);
     } else {
-        r = ray_entry<KIND>(D, e, ku, kv, id);
+        r = ray_entry<KIND>(D, e, ku, kv, ctr);
     }
     if (r.status != ST_HIT) return false;
     float t = 0.0f;
@@ -1828,6 +1834,10 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
         float flux = 0.0f;
         int imin = 1 << 30, imax = -1, jmin = 1 << 30, jmax = -1;
         float t_prev = -1.0f;  // the exit root of the thread's previous ray (its samples are adjacent)
+        // ray (ku0 + r / MV, kv0 + r % MV) is id0 + off: its id and RNG counter from the first ray's by additions
+        // of workgroup-uniform offsets
+        const int64_t id0 = ebase + (int64_t)ku0 * D.grid_v + kv0;
+        const uint64_t ctr0 = rng_counter(D.rng_state0, id0);
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             const int ku = ku0 + r / MV, kv = kv0 + r % MV;
@@ -1835,11 +1845,12 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
             X[r] = 0.0f;
             Y[r] = 0.0f;
             if (ku < D.grid_u && kv < D.grid_v) {
-                int64_t id = ebase + (int64_t)ku * D.grid_v + kv;
+                const int64_t off = (int64_t)(r / MV) * D.grid_v + r % MV;
                 float* ts = nullptr;
                 if constexpr (KIND == 1)
-                    if (A.roots) ts = A.roots + D.root_off + id;
-                FwdRay o = trace_forward<P, Q, KIND>(D, B, sP, sKu, sKv, sSb, e, ku, kv, id, ts, t_prev);
+                    if (A.roots) ts = A.roots + D.root_off + id0 + off;
+                FwdRay o = trace_forward<P, Q, KIND>(D, B, sP, sKu, sKv, sSb, e, ku, kv,
+                                                     ctr0 + (uint64_t)off * SPLITMIX_GAMMA, ts, t_prev);
                 if (o.t > 0.0f) t_prev = o.t;
                 c_tr++;
                 c_fail += o.failed;
@@ -1908,10 +1919,11 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
                 s_box[wave][3] = b1;
             }
             __syncthreads();
-            a0 = min(min(s_box[0][0], s_box[1][0]), min(s_box[2][0], s_box[3][0]));
-            a1 = max(max(s_box[0][1], s_box[1][1]), max(s_box[2][1], s_box[3][1]));
-            b0 = min(min(s_box[0][2], s_box[1][2]), min(s_box[2][2], s_box[3][2]));
-            b1 = max(max(s_box[0][3], s_box[1][3]), max(s_box[2][3], s_box[3][3]));
+            // workgroup-uniform: kept in scalar registers, with everything derived from them below
+            a0 = __builtin_amdgcn_readfirstlane(min(min(s_box[0][0], s_box[1][0]), min(s_box[2][0], s_box[3][0])));
+            a1 = __builtin_amdgcn_readfirstlane(max(max(s_box[0][1], s_box[1][1]), max(s_box[2][1], s_box[3][1])));
+            b0 = __builtin_amdgcn_readfirstlane(min(min(s_box[0][2], s_box[1][2]), min(s_box[2][2], s_box[3][2])));
+            b1 = __builtin_amdgcn_readfirstlane(max(max(s_box[0][3], s_box[1][3]), max(s_box[2][3], s_box[3][3])));
             __syncthreads();
             if (a1 < 0) continue;  // no ray of the block reached the screen
             constexpr int PAD = ACCUM ? 1 : 0;
@@ -2036,18 +2048,20 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
                         filter_axis<NU, false>(yr, D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr, D.box);
                     if (use_tile) {
                         // the tile holds every row and column of the window (pixels off the image get zero
-                        // weights, which the flush skips): nine adds without a test, rows outside the slab aside
+                        // weights, which the flush skips): nine adds without a test, rows outside the slab aside.
+                        // Tile offsets fit 24-bit products; the weights are >= 0, so adding one half and
+                        // truncating rounds them to the nearest unit.
                         const float wr = W[r] * (D.fx_scale * (1.0f / (float)(1 << TSH)));
+                        const int base = __mul24(i0 - H - r0, tw) + (j0 - H - jlo);
 #pragma unroll
                         for (int a = 0; a < NU; ++a) {
-                            const int i = i0 + a - H;
-                            if (npass > 1 && !in_slab(i)) continue;
-                            uint32_t* row = mytile + (i - r0) * tw + (j0 - H - jlo);
+                            if (npass > 1 && !in_slab(i0 + a - H)) continue;
+                            uint32_t* row = mytile + base + a * tw;
                             const float wa = wr * Fx[a];
 #pragma unroll
                             for (int bb = 0; bb < NU; ++bb)
-                                __hip_atomic_fetch_add(row + bb, (uint32_t)__float2int_rn(wa * Fy[bb]), __ATOMIC_RELAXED,
-                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                                __hip_atomic_fetch_add(row + bb, __float2uint_rz(fmaf(wa, Fy[bb], 0.5f)),
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                         }
                         continue;
                     }
@@ -2067,13 +2081,22 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
             }
             if (use_tile) {
                 __syncthreads();
+                // element i = ti tw + tj of the slab: row and column follow from the previous element's
+                // (WG = qs tw + rs), one division per pass instead of one per element
+                const int qs = WG / tw, rs = WG - qs * tw;
+                int ti = (int)threadIdx.x / tw, tj = (int)threadIdx.x - ti * tw;
                 for (int i = threadIdx.x; i < area; i += WG) {
-                    unsigned long long q = (unsigned long long)tile[i] << TSH;
-                    const int ti = i / tw;
-                    const int gi = r0 + ti, gj = jlo + (i - ti * tw);
-                    if (q != 0ull && gi >= 0 && gi < D.nx && gj >= 0 && gj < D.ny)
-                        __hip_atomic_fetch_add(&img[(int64_t)gi * D.ny + gj], q, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+                    const uint32_t v = tile[i];
+                    const int gi = r0 + ti, gj = jlo + tj;
+                    if (v != 0u && gi >= 0 && gi < D.nx && gj >= 0 && gj < D.ny)
+                        __hip_atomic_fetch_add(&img[(int64_t)gi * D.ny + gj], (unsigned long long)v << TSH,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ti += qs;
+                    tj += rs;
+                    if (tj >= tw) {
+                        tj -= tw;
+                        ++ti;
+                    }
                 }
                 __syncthreads();
             }
@@ -2174,15 +2197,23 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
         int aku = -1, akv = -1, aku_in = -1, akv_in = -1;
         unsigned long long* sG_in = sG + D.n_u * D.n_v;
         const float inv_unit = ldexpf(1.0f, -fixed_point_exponent(load_uniform(A.gmax, d), D.w0));
+        // ray r is id0 + off (a workgroup-uniform offset): its RNG counter follows by an addition.  The
+        // point-source instance with stored roots computes both per ray instead (its registers are full).
+        const uint64_t ctr0 = rng_counter(D.rng_state0, ebase + (int64_t)ku0 * D.grid_v + kv0);
         for (int r = 0; r < RPT; ++r) {
             const int ku = ku0 + (r >> mv_shift), kv = kv0 + (r & (MV - 1));
             if (ku >= D.grid_u || kv >= D.grid_v) continue;
             float g[NT], gin[ENTRY ? NT : 1];
             int cku = -1, ckv = -1, cku_in = -1, ckv_in = -1;
-            int64_t id = ebase + (int64_t)ku * D.grid_v + kv;
+            uint64_t ctr;
             const float* tl = nullptr;
-            if constexpr (KIND == 1)
+            if constexpr (KIND == 1) {
+                const int64_t id = ebase + (int64_t)ku * D.grid_v + kv;
+                ctr = rng_counter(D.rng_state0, id);
                 if (A.roots) tl = A.roots + D.root_off + id;
+            } else {
+                ctr = ctr0 + (uint64_t)((int64_t)(r >> mv_shift) * D.grid_v + (r & (MV - 1))) * SPLITMIX_GAMMA;
+            }
             // queued for the double-precision re-trace while the wave's segment of the queue has room
             auto enqueue = [&](float tq) {
                 if (!A.queue) return false;
@@ -2194,7 +2225,7 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
                     QEntry{d, tq, ebase + (int64_t)kq * D.grid_v + lq};
                 return true;
             };
-            if (!trace_adjoint<P, Q, NU, KIND>(D, B, sP, sKu, sKv, sSb, G, e, ku, kv, id, cku, ckv, g, cku_in, ckv_in,
+            if (!trace_adjoint<P, Q, NU, KIND>(D, B, sP, sKu, sKv, sSb, G, e, ku, kv, ctr, cku, ckv, g, cku_in, ckv_in,
                                                gin, tl, enqueue))
                 continue;
             if (aku >= 0 && (cku != aku || ckv != akv)) {
@@ -2287,13 +2318,14 @@ __global__ __launch_bounds__(WG) void k_trace_rays(TraceArgs A, int design, cons
     int ku = (int)(rr / D.grid_v), kv = (int)(rr - (rr / D.grid_v) * D.grid_v);
     const float* sKv = sK + D.nsu * kt_stride(P);
     const float* sSb = A.lds_sb && (D.kind != 0 || D.entry_ff) ? sS : nullptr;
+    const uint64_t c = rng_counter(D.rng_state0, id);
     FwdRay o;
-    if (D.entry_ff) o = D.kind == 0 ? trace_forward<P, Q, 4>(D, B, sP, sK, sKv, sSb, e, ku, kv, id)
-                                    : trace_forward<P, Q, 5>(D, B, sP, sK, sKv, sSb, e, ku, kv, id);
-    else if (D.mesh_u) o = D.kind == 0 ? trace_forward<P, Q, 2>(D, B, sP, sK, sKv, nullptr, e, ku, kv, id)
-                                       : trace_forward<P, Q, 3>(D, B, sP, sK, sKv, nullptr, e, ku, kv, id);
-    else o = D.kind == 0 ? trace_forward<P, Q, 0>(D, B, sP, sK, sKv, nullptr, e, ku, kv, id)
-                         : trace_forward<P, Q, 1>(D, B, sP, sK, sKv, sSb, e, ku, kv, id);
+    if (D.entry_ff) o = D.kind == 0 ? trace_forward<P, Q, 4>(D, B, sP, sK, sKv, sSb, e, ku, kv, c)
+                                    : trace_forward<P, Q, 5>(D, B, sP, sK, sKv, sSb, e, ku, kv, c);
+    else if (D.mesh_u) o = D.kind == 0 ? trace_forward<P, Q, 2>(D, B, sP, sK, sKv, nullptr, e, ku, kv, c)
+                                       : trace_forward<P, Q, 3>(D, B, sP, sK, sKv, nullptr, e, ku, kv, c);
+    else o = D.kind == 0 ? trace_forward<P, Q, 0>(D, B, sP, sK, sKv, nullptr, e, ku, kv, c)
+                         : trace_forward<P, Q, 1>(D, B, sP, sK, sKv, sSb, e, ku, kv, c);
     float* dst = out8 + 8 * i;
     dst[0] = (float)o.status;
     dst[1] = o.X;
