@@ -130,14 +130,25 @@ __device__ void face_bounds(const DesignDev& D, const float* P, int p, int q, fl
 __global__ __launch_bounds__(256) void k_bounds(const DesignDev* designs, const float* __restrict__ Pz, int p, int q,
                                                 BoundsDev* bounds, SpanBounds* span_bounds) {
     __shared__ float s_b[16];
+    __shared__ float s_net[MAX_CP];  // one face's control net: every bound below reads it from LDS
     const int d = blockIdx.x;
-    const DesignDev& D = designs[d];
-    const float* P = Pz + D.cp_off;
+    const DesignDev D = designs[d];  // one load: stores below may alias designs[]
+    const int ncp = D.n_u * D.n_v;
+    for (int i = threadIdx.x; i < ncp; i += blockDim.x) s_net[i] = Pz[D.cp_off + i];
+    __syncthreads();
+    const float* P = s_net;
     // per span product (su, sv): control points su..su+p x sv..sv+q; derivative control points along u are
     // i = su..su+p-1 (times the factor of their knot interval), along v likewise
+    // (the span products are split over the gridDim.y workgroups of the design; workgroup 0 also forms the
+    // global bounds below)
     SpanBounds* sb = span_bounds + D.sb_off;
-    for (int s = threadIdx.x; s < D.nsu * D.nsv; s += blockDim.x) {
+    for (int s = blockIdx.y * blockDim.x + threadIdx.x; s < D.nsu * D.nsv; s += gridDim.y * blockDim.x) {
         const int su = s / D.nsv, sv = s - (s / D.nsv) * D.nsv;
+        float fv[MAX_DEG];  // the factors of the span's derivative control points along v
+        for (int b = 0; b < q; ++b) {
+            const int j = sv + b;
+            fv[b] = (float)q / (float)(min(j + 1, D.nsv) - max(j + 1 - q, 0));
+        }
         float lo = INFINITY, hi = -INFINITY, gu = 0.0f, gv = 0.0f;
         for (int a = 0; a <= p; ++a) {
             const int i = su + a;
@@ -148,10 +159,7 @@ __global__ __launch_bounds__(256) void k_bounds(const DesignDev* designs, const 
                 lo = fminf(lo, z);
                 hi = fmaxf(hi, z);
                 if (a < p) gu = fmaxf(gu, fabsf(fu * (P[(i + 1) * D.n_v + j] - z)));
-                if (b < q) {
-                    const float fv = (float)q / (float)(min(j + 1, D.nsv) - max(j + 1 - q, 0));
-                    gv = fmaxf(gv, fabsf(fv * (P[i * D.n_v + j + 1] - z)));
-                }
+                if (b < q) gv = fmaxf(gv, fabsf(fv[b] * (P[i * D.n_v + j + 1] - z)));
             }
         }
         SpanBounds r;
@@ -161,12 +169,16 @@ __global__ __launch_bounds__(256) void k_bounds(const DesignDev* designs, const 
         r.gy = gv * D.syv * 1.0001f;
         sb[s] = r;
     }
+    if (blockIdx.y != 0) return;
     BoundsDev B;
     face_bounds(D, P, p, q, s_b, B.zmin, B.zmax, B.gx, B.gy);
     B.zref = 0.5f * (B.zmin + B.zmax);
     B.zmin_in = B.zmax_in = B.gx_in = B.gy_in = B.zref_in = 0.0f;
     if (D.entry_ff) {  // the entry net follows the exit net
-        face_bounds(D, P + D.n_u * D.n_v, p, q, s_b, B.zmin_in, B.zmax_in, B.gx_in, B.gy_in);
+        __syncthreads();
+        for (int i = threadIdx.x; i < ncp; i += blockDim.x) s_net[i] = Pz[D.cp_off + ncp + i];
+        __syncthreads();
+        face_bounds(D, P, p, q, s_b, B.zmin_in, B.zmax_in, B.gx_in, B.gy_in);
         B.zref_in = 0.5f * (B.zmin_in + B.zmax_in);
     }
     if (threadIdx.x == 0) bounds[d] = B;
@@ -185,7 +197,7 @@ __device__ inline void image_slice(const DesignDev& D, int LB, int b, int64_t& l
 __global__ __launch_bounds__(256) void k_resolve(const DesignDev* designs, int LB, unsigned long long* img64,
                                                  float* irr, const float* Pz, ffrt_stats* slots, ffrt_stats* stats) {
     const int d = blockIdx.x / LB, b = blockIdx.x - d * LB;
-    const DesignDev& D = designs[d];
+    const DesignDev D = designs[d];  // one load: stores below may alias designs[]
     int64_t lo, hi;
     image_slice(D, LB, b, lo, hi);
     for (int64_t i = D.img_off + lo + threadIdx.x; i < D.img_off + hi; i += blockDim.x) {
@@ -212,7 +224,7 @@ __global__ __launch_bounds__(256) void k_loss_sums(const DesignDev* designs, int
     }
     const int d = blockIdx.x / LB, b = blockIdx.x - d * LB;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const DesignDev& D = designs[d];
+    const DesignDev D = designs[d];  // one load: stores below may alias designs[]
     int64_t lo, hi;
     image_slice(D, LB, b, lo, hi);
     double q[LOSS_Q] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -251,7 +263,7 @@ __global__ __launch_bounds__(256) void k_loss_grad(const DesignDev* designs, int
                                                    const float* __restrict__ target, const double* partial,
                                                    float* loss, int32_t* valid, float* dLdI, uint32_t* gmax) {
     const int d = blockIdx.x / LB, b = blockIdx.x - d * LB;
-    const DesignDev& D = designs[d];
+    const DesignDev D = designs[d];  // one load: stores below may alias designs[]
     int64_t lo, hi;
     image_slice(D, LB, b, lo, hi);
     // the slice's first pixels (all of them up to 1024 per slice) are loaded before the slice sums are
@@ -298,7 +310,7 @@ __global__ __launch_bounds__(256) void k_loss_grad(const DesignDev* designs, int
 __global__ __launch_bounds__(256) void k_gscale(const DesignDev* designs, const float* __restrict__ dLdI,
                                                 uint32_t* gmax) {
     __shared__ float sh[4];
-    const DesignDev& D = designs[blockIdx.x];
+    const DesignDev D = designs[blockIdx.x];
     const int64_t n = (int64_t)D.nx * D.ny;
     const float* G = dLdI + D.img_off;
     float m = 0.0f;
@@ -315,7 +327,8 @@ __global__ __launch_bounds__(256) void k_gscale(const DesignDev* designs, const 
 __global__ __launch_bounds__(256) void k_finish(const DesignDev* designs, unsigned long long* gacc, uint32_t* gmax,
                                                 float* dLdP, const int32_t* valid, AdamArgs adam) {
     const int d = blockIdx.x;
-    finish_design(designs[d], d, gacc, gmax, dLdP, valid, adam);
+    const DesignDev D = designs[d];
+    finish_design(D, d, gacc, gmax, dLdP, valid, adam);
 }
 
 // Range reparametrisation of sec. 2.4.1 (eq. of the output correction, with or without the offset
@@ -335,7 +348,7 @@ __global__ void k_reparam(int mode, int64_t n, const float* __restrict__ theta, 
 __global__ __launch_bounds__(1024) void k_loss_f64(const DesignDev* designs, const float* __restrict__ irr,
                                                    const float* __restrict__ target, double* loss) {
     __shared__ double sh[16];
-    const DesignDev& D = designs[blockIdx.x];
+    const DesignDev D = designs[blockIdx.x];
     const int64_t n = (int64_t)D.nx * D.ny;
     const float* I = irr + D.img_off;
     const float* T = target + D.img_off;
@@ -364,7 +377,7 @@ __global__ __launch_bounds__(256) void k_adam(const DesignDev* designs, float* P
                                               ffrt_adam_hparams hp) {
     const int d = blockIdx.x;
     if (valid && !valid[d]) return;
-    const DesignDev& D = designs[d];
+    const DesignDev D = designs[d];  // one load: stores below may alias designs[]
     const float* gd = g + D.cp_off;
     adam_update(Pz, m, v, t + d, D.cp_off, D.ncp, hp, [gd](int i) { return gd[i]; });
 }
@@ -461,7 +474,7 @@ uint64_t splitmix_state0(uint64_t seed, uint64_t stream_id) { return mix64(seed 
 
 hipError_t launch_bounds(const DesignDev* designs, int n_designs, const float* Pz, int p, int q, BoundsDev* bounds,
                          SpanBounds* span_bounds, hipStream_t s) {
-    hipLaunchKernelGGL(k_bounds, dim3(n_designs), dim3(256), 0, s, designs, Pz, p, q, bounds, span_bounds);
+    hipLaunchKernelGGL(k_bounds, dim3(n_designs, 4), dim3(256), 0, s, designs, Pz, p, q, bounds, span_bounds);
     return hipGetLastError();
 }
 

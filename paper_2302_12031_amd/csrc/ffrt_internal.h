@@ -10,6 +10,7 @@ namespace ffrt {
 constexpr int WG = 256;               // threads per workgroup: 4 wave64s
 constexpr int TILE_CAP = 6144;        // 32-bit fixed-point pixels in the LDS irradiance tile of the forward kernel
 constexpr int MAX_DEG = 5;
+constexpr int MAX_CP = 4096;          // control points of one face (the net is at most 64 x 64)
 constexpr int N_SHAPES = 5;           // block shapes: rays per thread 1, 2, 4, 8, 16
 constexpr int N_KG = 8;               // kernel groups: bit 0 point source, bit 1 mesh, bit 2 freeform entry
 constexpr int RPT_OF_SHAPE[N_SHAPES] = {1, 2, 4, 8, 16};
