@@ -160,12 +160,14 @@ struct TraceArgs {
     // root_off + ray index (-1: no hit).  The forward stores them and the adjoint of the same step reads
     // them instead of searching again; null: every kernel searches.
     float* roots;
-    // Adjoint, kernel groups 0 and 1: rays whose derivative single precision cannot resolve (landing within
-    // rounding of a pixel edge, near total internal reflection) are left out and queued for the
+    // Adjoint, kernel groups 0, 1 and 5: rays whose derivative single precision cannot resolve (landing
+    // within rounding of a pixel edge, near total internal reflection) are left out and queued for the
     // double-precision re-trace: logical block b of the launch writes up to queue_cap(shape) entries at
-    // queue + (qbase + b) queue_cap and their number at qcount[qbase + b].  Null: no queue.
+    // queue + (qbase + b) queue_cap and their number at qcount[qbase + b]; group 5 (two freeform faces) also
+    // writes each ray's entry root at the same place of queue_tin.  Null: no queue.
     QEntry* queue;
     int32_t* qcount;
+    float* queue_tin;
     int64_t qbase;
 };
 
@@ -195,11 +197,13 @@ constexpr int N_FWD_CFGS = sizeof(FWD_CFGS) / sizeof(FWD_CFGS[0]);
 constexpr int N_ADJ_CFGS = sizeof(ADJ_CFGS) / sizeof(ADJ_CFGS[0]);
 
 // Launchers of the templated trace kernels, one set per compiled (P, Q, NU).  adjoint_fp64 re-traces the queued
-// rays of nblocks logical blocks (queue and qcount as in TraceArgs, qbase 0) in double precision.
+// rays of logical blocks [first, first + nblocks) (queue and qcount as in TraceArgs, qbase 0) in double
+// precision; two: the blocks of point sources through two freeform faces (an instance of its own).
 struct KernelSet {
     hipError_t (*forward)(const TraceArgs&, int shape, int grid, hipStream_t);
     hipError_t (*adjoint)(const TraceArgs&, int shape, int grid, hipStream_t);
-    hipError_t (*adjoint_fp64)(const TraceArgs&, const DesignDev64* d64, int shape, int64_t nblocks, hipStream_t);
+    hipError_t (*adjoint_fp64)(const TraceArgs&, const DesignDev64* d64, int shape, int64_t first, int64_t nblocks,
+                               bool two, hipStream_t);
     hipError_t (*trace_rays)(const TraceArgs&, int design, const int64_t* ids, int64_t n, float* out8,
                              hipStream_t);
 };

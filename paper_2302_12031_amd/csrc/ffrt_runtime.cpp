@@ -81,7 +81,7 @@ struct ffrt_plan {
     size_t off_designs = 0, off_bounds = 0, off_sb = 0, off_valid = 0, off_knots = 0, off_bmap = 0, off_slots = 0;
     size_t need = 0;
     size_t off_lpart = 0, off_img64 = 0, off_gacc = 0, off_gmax = 0, off_dldi = 0, off_mlpoff = 0, off_mlpvec = 0,
-           off_roots = 0, off_d64 = 0, off_queue = 0, off_qcount = 0;
+           off_roots = 0, off_d64 = 0, off_queue = 0, off_qcount = 0, off_qtin = 0;
     int num_cu = 256;
     int fwd_cfg = 0, adj_cfg = 0;
     hipGraph_t graph = nullptr;
@@ -107,6 +107,7 @@ struct ffrt_plan {
     DesignDev64* d_d64() const { return reinterpret_cast<DesignDev64*>(ws + off_d64); }
     QEntry* d_queue() const { return reinterpret_cast<QEntry*>(ws + off_queue); }
     int32_t* d_qcount() const { return reinterpret_cast<int32_t*>(ws + off_qcount); }
+    float* d_qtin() const { return reinterpret_cast<float*>(ws + off_qtin); }
 };
 
 namespace {
@@ -361,9 +362,11 @@ ffrt_status launch_forward(ffrt_plan* pl, const float* Pz, bool stats, hipStream
 // same Pz must have filled.
 ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hipStream_t s, bool roots = false) {
     const AdjCfg& c = ADJ_CFGS[pl->adj_cfg];
-    // the rays of kernel groups 0 and 1 whose derivative single precision cannot resolve are queued per
-    // logical block (group 1's blocks after group 0's) and re-traced in double precision afterwards
-    const int64_t qblocks = pl->nblocks[c.shape][0] + pl->nblocks[c.shape][1];
+    // the rays of kernel groups 0, 1 and 5 (flat entry face; point sources through two freeform faces) whose
+    // derivative single precision cannot resolve are queued per logical block (group 1's blocks after group
+    // 0's, group 5's after those) and re-traced in double precision afterwards
+    const int64_t qb0 = pl->nblocks[c.shape][0], qb1 = pl->nblocks[c.shape][1], qb5 = pl->nblocks[c.shape][5];
+    const int64_t qblocks = qb0 + qb1 + qb5;
     for (int kg = 0; kg < N_KG; ++kg) {
         if (pl->nblocks[c.shape][kg] == 0) continue;
         TraceArgs A = make_args(pl, c.shape, kg);
@@ -373,10 +376,11 @@ ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hi
         A.gmax = pl->d_gmax();
         A.butterfly = c.butterfly;
         A.roots = roots && kg == 1 ? pl->d_roots() : nullptr;
-        if (kg <= 1) {
+        if (kg == 0 || kg == 1 || kg == 5) {
             A.queue = pl->d_queue();
             A.qcount = pl->d_qcount();
-            A.qbase = kg == 1 ? pl->nblocks[c.shape][0] : 0;
+            A.queue_tin = pl->d_qtin();
+            A.qbase = kg == 0 ? 0 : (kg == 1 ? qb0 : qb0 + qb1);
         }
         HIP_TRY(pl->ks->adjoint(A, c.shape, grid_for(pl, c.shape, kg, c.persistent), s));
     }
@@ -388,7 +392,9 @@ ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hi
         A.gmax = pl->d_gmax();
         A.queue = pl->d_queue();
         A.qcount = pl->d_qcount();
-        HIP_TRY(pl->ks->adjoint_fp64(A, pl->d_d64(), c.shape, qblocks, s));
+        A.queue_tin = pl->d_qtin();
+        if (qb0 + qb1 > 0) HIP_TRY(pl->ks->adjoint_fp64(A, pl->d_d64(), c.shape, 0, qb0 + qb1, false, s));
+        if (qb5 > 0) HIP_TRY(pl->ks->adjoint_fp64(A, pl->d_d64(), c.shape, qb0 + qb1, qb5, true, s));
     }
     return FFRT_OK;
 }
@@ -639,6 +645,8 @@ ffrt_status ffrt_plan_create(const ffrt_problem* probs, int32_t n_designs, ffrt_
     }
     pl->off_queue = off;
     off = align256(off + sizeof(QEntry) * (size_t)qent);
+    pl->off_qtin = off;
+    off = align256(off + sizeof(float) * (size_t)qent);
     pl->off_qcount = off;
     off = align256(off + sizeof(int32_t) * 4 * (size_t)qblk);
     pl->off_dldi = off;  // dL/dI of a step whose caller does not want it

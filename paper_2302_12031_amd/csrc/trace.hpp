@@ -1104,7 +1104,7 @@ __device__ __forceinline__ bool near_pixel_edge(float X, float R, float inv_w, i
 // with a freeform entry face gin[] receives dL/dP of the entry net's points (cku_in + a, ckv_in + b).
 // ------------------------------------------------------------------------------------------------
 struct NoQueue {
-    __device__ bool operator()(float) const { return false; }
+    __device__ bool operator()(float, float) const { return false; }
 };
 
 template <int P, int Q, int NU, int KIND, class Enqueue = NoQueue>
@@ -1178,13 +1178,13 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
     }
     float qz = SEARCH ? r.oz + t * r.dz : (MESH ? mqz : S.h + B.zref);
     ExitState E = exit_face(D, qx, qy, qz, r.dx, r.dy, r.dz, S.hx, S.hy, r.w);
-    if constexpr ((KIND & 6) == 0) {
+    if constexpr ((KIND & 6) == 0 || KIND == 5) {
         // a derivative single precision cannot resolve (see FLAG_EDGE_PX): enqueue() may take the ray for the
-        // double-precision re-trace (with its root), which then makes the contribution instead of this sweep
+        // double-precision re-trace (with its roots), which then makes the contribution instead of this sweep
         const bool flag = E.status == ST_TIR ? E.k > -FLAG_K_TIR
                                              : E.k < FLAG_K_HIT || near_pixel_edge(E.X, D.Rx, D.inv_wx, D.nx) ||
                                                    near_pixel_edge(E.Y, D.Ry, D.inv_wy, D.ny);
-        if (flag && !D.box && enqueue(t)) return false;
+        if (flag && !D.box && enqueue(t, ENTRY ? EH.t : 0.0f)) return false;
     }
     if (E.status != ST_HIT) return false;
 
@@ -1481,13 +1481,17 @@ __device__ inline int filter_axis_f64(double X, double R, double w, int n, doubl
     return i0;
 }
 
-// One queued ray in double precision: the whole trace from its sample (flat entry face, exact root polished
-// from the single-precision one by Newton steps on the double-precision surface) and the reverse sweep of
+// One queued ray in double precision: the whole trace from its sample (exact roots polished from the
+// single-precision ones by Newton steps on the double-precision surfaces) and the reverse sweep of
 // trace_adjoint.  Returns false when, in double precision, the ray does not reach the screen; else g[] holds
-// dL/dP of the control points (ku + a, kv + b) at a (Q+1) + b.
-template <int P, int Q, int NU>
+// dL/dP of the exit net's control points (ku + a, kv + b) at a (Q+1) + b.  TWO: a point-source ray through a
+// lens whose entry face is freeform too (its entry root ti32 queued beside the exit root); gin[] then holds
+// dL/dP of the entry net's points (cku_in + a, ckv_in + b).
+template <int P, int Q, int NU, bool TWO = false>
 __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, const float* __restrict__ Pz,
-                                  const float* __restrict__ G, int64_t id, float t32, int& cku, int& ckv, double* g) {
+                                  const float* __restrict__ G, int64_t id, float t32, int& cku, int& ckv, double* g,
+                                  float ti32 = 0.0f, int* cku_in = nullptr, int* ckv_in = nullptr,
+                                  double* gin = nullptr) {
     const int64_t per = (int64_t)D.grid_u * D.grid_v;
     const int e = (int)(id / per);
     const int64_t rr = id - (int64_t)e * per;
@@ -1495,8 +1499,13 @@ __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, cons
     float x1f = 0.5f, x2f = 0.5f;
     if (D.jitter) two_uniforms(splitmix_at(D.rng_state0, (uint64_t)id), x1f, x2f);  // exact 24-bit values
     const double x1 = x1f, x2 = x2f;
-    const bool point = D.kind != 0;
+    const bool point = TWO || D.kind != 0;
     double ox, oy, oz, dx, dy, dz, w1;
+    // (TWO) the source ray d0, the entry face at the entry hit (Si, unit normal m) and its refraction
+    SurfEval<P, Q, double> Si;
+    double d0x = 0.0, d0y = 0.0, d0z = 0.0, mx = 0.0, my = 0.0, mz = 0.0, inv_i = 0.0, ci = 0.0, ski = 1.0,
+           betai = 0.0;
+    const float* Pin = Pz + D.n_u * D.n_v;  // the entry net follows the exit net
     if (!point) {
         ox = (2.0 * (((double)ku + x1) / (double)D.grid_u) - 1.0) * E.r_x;
         oy = (2.0 * (((double)kv + x2) / (double)D.grid_v) - 1.0) * E.r_y;
@@ -1515,19 +1524,55 @@ __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, cons
             px += E.ex0 + (double)ix * E.edx;
             py += E.ey0 + (double)iy * E.edy;
         }
-        const double t0 = (E.z_in - E.pos_z) / cphi;
-        ox = px + t0 * cth * sphi;
-        oy = py + t0 * sth * sphi;
-        oz = E.z_in;
-        if (fabs(ox) > E.r_x || fabs(oy) > E.r_y) return false;
         const double eta = 1.0 / E.n_lens;
-        dx = eta * cth * sphi;
-        dy = eta * sth * sphi;
-        dz = sqrt(1.0 - eta * eta * sphi * sphi);
-        w1 = E.w0;
-        if (D.fresnel) {
-            const double m = 1.0 - cphi, m2 = m * m;
-            w1 *= 1.0 - (E.R0 + (1.0 - E.R0) * m2 * m2 * m);
+        if constexpr (TWO) {
+            // entry root: g(s + t d0) = s_z + t d0_z on the entry face, polished from the single-precision one
+            d0x = cth * sphi;
+            d0y = sth * sphi;
+            d0z = cphi;
+            const double sz = E.pos_z;
+            double ti = (double)ti32;
+            for (int it = 0; it < 2; ++it) {
+                surface_f64<P, Q, false>(D, E, Pin, px + ti * d0x, py + ti * d0y, Si);
+                const double f = Si.h - sz - ti * d0z, fp = Si.hx * d0x + Si.hy * d0y - d0z;
+                if (!(fp < 0.0)) break;
+                ti -= f / fp;
+            }
+            ox = px + ti * d0x;
+            oy = py + ti * d0y;
+            oz = sz + ti * d0z;
+            if (fabs(ox) > E.r_x || fabs(oy) > E.r_y) return false;
+            // refraction air -> glass at m = (-g_x, -g_y, 1) / |.|, Schlick with the air-side cosine
+            surface_f64<P, Q, true>(D, E, Pin, ox, oy, Si);
+            inv_i = 1.0 / sqrt(Si.hx * Si.hx + Si.hy * Si.hy + 1.0);
+            mx = -Si.hx * inv_i;
+            my = -Si.hy * inv_i;
+            mz = inv_i;
+            ci = d0x * mx + d0y * my + d0z * mz;
+            ski = sqrt(fmax(1.0 - eta * eta * (1.0 - ci * ci), 1e-300));
+            betai = ski - eta * ci;
+            dx = eta * d0x + betai * mx;
+            dy = eta * d0y + betai * my;
+            dz = eta * d0z + betai * mz;
+            w1 = E.w0;
+            if (D.fresnel) {
+                const double m = 1.0 - ci, m2 = m * m;
+                w1 *= 1.0 - (E.R0 + (1.0 - E.R0) * m2 * m2 * m);
+            }
+        } else {
+            const double t0 = (E.z_in - E.pos_z) / cphi;
+            ox = px + t0 * cth * sphi;
+            oy = py + t0 * sth * sphi;
+            oz = E.z_in;
+            if (fabs(ox) > E.r_x || fabs(oy) > E.r_y) return false;
+            dx = eta * cth * sphi;
+            dy = eta * sth * sphi;
+            dz = sqrt(1.0 - eta * eta * sphi * sphi);
+            w1 = E.w0;
+            if (D.fresnel) {
+                const double m = 1.0 - cphi, m2 = m * m;
+                w1 *= 1.0 - (E.R0 + (1.0 - E.R0) * m2 * m2 * m);
+            }
         }
     }
     SurfEval<P, Q, double> S;
@@ -1627,6 +1672,38 @@ __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, cons
             g[a * (Q + 1) + b] = S.Nu[a] * (g0 * S.Nv[b] + gy * S.dNv[b]) + gx * S.dNu[a] * S.Nv[b];
     cku = S.ku;
     ckv = S.kv;
+    if constexpr (TWO) {
+        // ---- back through the exit root into the ray inside the glass, q = o + t d with f(t; o, d) = 0 (as in
+        // trace_adjoint): the exit normal's dependence on q, then o and d
+        const double qbx = qxb + hxb * S.hxx + hyb * S.hxy, qby = qyb + hxb * S.hxy + hyb * S.hyy;
+        const double obx = qbx + g0 * S.hx, oby = qby + g0 * S.hy, obz = qzb - g0;
+        const double dbx = n * exb + cb * nxh + t * obx;
+        const double dby = n * eyb + cb * nyh + t * oby;
+        const double dbz = n * ezb + cb * nzh + t * obz;
+        // ---- entry refraction d = eta d0 + beta_i m, beta_i = sqrt(k_i) - eta c_i, c_i = d0 . m; w1 = w0 (1 -
+        // Schlick(c_i)) and w = w1 T
+        const double eta = 1.0 / n;
+        double cib = (dbx * mx + dby * my + dbz * mz) * (eta * eta * ci / ski - eta);
+        if (D.fresnel) {
+            const double mm = 1.0 - ci, mm2 = mm * mm;
+            cib += wbar * T * E.w0 * 5.0 * (1.0 - E.R0) * mm2 * mm2;
+        }
+        const double nbx = betai * dbx + cib * d0x, nby = betai * dby + cib * d0y, nbz = betai * dbz + cib * d0z;
+        const double nd = nbx * mx + nby * my + nbz * mz;
+        const double gxb_i = -(nbx - nd * mx) * inv_i, gyb_i = -(nby - nd * my) * inv_i;
+        // ---- the entry hit moves along s + t_i d0 with g(s + t_i d0) = s_z + t_i d0_z
+        const double pbx = obx + gxb_i * Si.hxx + gyb_i * Si.hxy, pby = oby + gxb_i * Si.hxy + gyb_i * Si.hyy;
+        const double tbi = pbx * d0x + pby * d0y + obz * d0z;
+        const double c0 = -tbi / (Si.hx * d0x + Si.hy * d0y - d0z);
+        const double gxi = gxb_i * E.sxu, gyi = gyb_i * E.syv;
+#pragma unroll
+        for (int a = 0; a <= P; ++a)
+#pragma unroll
+            for (int b = 0; b <= Q; ++b)
+                gin[a * (Q + 1) + b] = Si.Nu[a] * (c0 * Si.Nv[b] + gyi * Si.dNv[b]) + gxi * Si.dNu[a] * Si.Nv[b];
+        *cku_in = Si.ku;
+        *ckv_in = Si.kv;
+    }
     return true;
 }
 
@@ -1637,13 +1714,18 @@ __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, cons
 // device accumulator directly), which is then added to the device accumulator once: one atomic per touched
 // control point and round instead of one per ray.  Both sums are in the design's fixed-point unit, so the result
 // does not depend on which kernel adds them or in which order.
-template <int P, int Q, int NU>
-__global__ __launch_bounds__(WG) void k_adjoint_fp64(TraceArgs A, const DesignDev64* d64, int shape, int64_t nseg) {
+// TWO: the instance for the segments of point sources through two freeform faces (seg0 on).
+template <int P, int Q, int NU, bool TWO>
+__global__ __launch_bounds__(WG) void k_adjoint_fp64(TraceArgs A, const DesignDev64* d64, int shape, int64_t seg0,
+                                                     int64_t nseg) {
     constexpr int SPW = 64;  // segments per workgroup and round
     __shared__ int s_off[SPW + 1];
     __shared__ int s_design;
     extern __shared__ unsigned long long sG[];  // A.lds_cp entries
     const int per_wave = queue_cap(shape) / 4;
+    A.queue += seg0 * per_wave;
+    A.queue_tin += seg0 * per_wave;
+    A.qcount += seg0;
     for (int64_t s0 = (int64_t)blockIdx.x * SPW; s0 < nseg; s0 += (int64_t)gridDim.x * SPW) {
         if (threadIdx.x < SPW) {  // inclusive scan of the counts over wave 0
             int c = s0 + threadIdx.x < nseg ? A.qcount[s0 + threadIdx.x] : 0;
@@ -1677,14 +1759,18 @@ __global__ __launch_bounds__(WG) void k_adjoint_fp64(TraceArgs A, const DesignDe
                 const int mid = (lo + hi + 1) >> 1;
                 if (s_off[mid] <= i) lo = mid; else hi = mid - 1;
             }
-            const QEntry q = A.queue[(s0 + lo) * per_wave + (i - s_off[lo])];
-            const DesignDev D = A.designs[q.design];
-            const DesignDev64 E = d64[q.design];
-            double g[(P + 1) * (Q + 1)];
-            int cku = 0, ckv = 0;
-            if (!trace_adjoint_f64<P, Q, NU>(D, E, A.Pz, A.dLdI, q.id, q.t, cku, ckv, g)) continue;
-            const double inv_unit = ldexp(1.0, -fixed_point_exponent(A.gmax[q.design], D.w0));
-            unsigned long long* acc = q.design == dmain ? sG : A.gacc + D.cp_off;
+            const int64_t qi = (s0 + lo) * per_wave + (i - s_off[lo]);
+            const QEntry q = A.queue[qi];
+            const int qd = q.design;
+            const DesignDev D = A.designs[qd];
+            const DesignDev64 E = d64[qd];
+            double g[(P + 1) * (Q + 1)], gin[(P + 1) * (Q + 1)];
+            int cku = 0, ckv = 0, cku_in = -1, ckv_in = -1;
+            if (!trace_adjoint_f64<P, Q, NU, TWO>(D, E, A.Pz, A.dLdI, q.id, q.t, cku, ckv, g,
+                                                  TWO ? A.queue_tin[qi] : 0.0f, &cku_in, &ckv_in, gin))
+                continue;
+            const double inv_unit = ldexp(1.0, -fixed_point_exponent(A.gmax[qd], D.w0));
+            unsigned long long* acc = qd == dmain ? sG : A.gacc + D.cp_off;
 #pragma unroll
             for (int a = 0; a <= P; ++a)
 #pragma unroll
@@ -1694,6 +1780,18 @@ __global__ __launch_bounds__(WG) void k_adjoint_fp64(TraceArgs A, const DesignDe
                         atomicAdd(&acc[(int64_t)(cku + a) * D.n_v + ckv + b],
                                   (unsigned long long)__double2ll_rn(v * inv_unit));
                 }
+            if (cku_in >= 0) {  // the entry net follows the exit net in the accumulator too
+                unsigned long long* acc_in = acc + D.n_u * D.n_v;
+#pragma unroll
+                for (int a = 0; a <= P; ++a)
+#pragma unroll
+                    for (int b = 0; b <= Q; ++b) {
+                        const double v = gin[a * (Q + 1) + b];
+                        if (v != 0.0)
+                            atomicAdd(&acc_in[(int64_t)(cku_in + a) * D.n_v + ckv_in + b],
+                                      (unsigned long long)__double2ll_rn(v * inv_unit));
+                    }
+            }
         }
         __syncthreads();
         unsigned long long* gacc = A.gacc + Dm.cp_off;
@@ -2215,14 +2313,15 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
                 ctr = ctr0 + (uint64_t)((int64_t)(r >> mv_shift) * D.grid_v + (r & (MV - 1))) * SPLITMIX_GAMMA;
             }
             // queued for the double-precision re-trace while the wave's segment of the queue has room
-            auto enqueue = [&](float tq) {
+            auto enqueue = [&](float tq, float tq_in) {
                 if (!A.queue) return false;
                 const int slot = atomicAdd(&s_qn[wave], 1);
                 if (slot >= qcap_w) return false;
                 // the ray id again from the block's base and the ray's place (cheaper than keeping it live)
                 const int kq = ku0 + (r >> mv_shift), lq = kv0 + (r & (MV - 1));
-                A.queue[((A.qbase + b) * 4 + wave) * qcap_w + slot] =
-                    QEntry{d, tq, ebase + (int64_t)kq * D.grid_v + lq};
+                const int64_t qi = ((A.qbase + b) * 4 + wave) * qcap_w + slot;
+                A.queue[qi] = QEntry{d, tq, ebase + (int64_t)kq * D.grid_v + lq};
+                if constexpr (KIND == 5) A.queue_tin[qi] = tq_in;
                 return true;
             };
             if (!trace_adjoint<P, Q, NU, KIND>(D, B, sP, sKu, sKv, sSb, G, e, ku, kv, ctr, cku, ckv, g, cku_in, ckv_in,
@@ -2274,7 +2373,7 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
         } else if (pend) {
             cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc, inv_unit);
         }
-        if constexpr ((KIND & 6) == 0) {
+        if constexpr ((KIND & 6) == 0 || KIND == 5) {
             // the wave's queued rays of this block (its lanes' LDS atomics completed in order before this read)
             if (A.queue && lane == 0) {
                 A.qcount[(A.qbase + b) * 4 + wave] = min(s_qn[wave], qcap_w);
@@ -2388,13 +2487,18 @@ struct KernelsFor {
         }
         return hipGetLastError();
     }
-    static hipError_t adjoint_fp64(const TraceArgs& A, const DesignDev64* d64, int shape, int64_t nblocks,
-                                   hipStream_t s) {
-        const int64_t nseg = 4 * nblocks;  // one segment per (logical block, wave)
+    static hipError_t adjoint_fp64(const TraceArgs& A, const DesignDev64* d64, int shape, int64_t first,
+                                   int64_t nblocks, bool two, hipStream_t s) {
+        const int64_t nseg = 4 * nblocks, seg0 = 4 * first;  // one segment per (logical block, wave)
         const int grid = (int)std::min<int64_t>((nseg + 63) / 64, 4096);
         if (grid <= 0) return hipSuccess;
-        const size_t lds = sizeof(unsigned long long) * (size_t)A.lds_cp;  // the round design's control net
-        hipLaunchKernelGGL((k_adjoint_fp64<P, Q, NU>), dim3(grid), dim3(WG), lds, s, A, d64, shape, nseg);
+        const size_t lds = sizeof(unsigned long long) * (size_t)A.lds_cp;  // the round design's control net(s)
+        if (two)
+            hipLaunchKernelGGL((k_adjoint_fp64<P, Q, NU, true>), dim3(grid), dim3(WG), lds, s, A, d64, shape, seg0,
+                               nseg);
+        else
+            hipLaunchKernelGGL((k_adjoint_fp64<P, Q, NU, false>), dim3(grid), dim3(WG), lds, s, A, d64, shape, seg0,
+                               nseg);
         return hipGetLastError();
     }
     static hipError_t trace_rays(const TraceArgs& A, int design, const int64_t* ids, int64_t n, float* out8,
