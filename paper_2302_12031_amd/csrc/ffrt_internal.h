@@ -198,12 +198,14 @@ constexpr int N_ADJ_CFGS = sizeof(ADJ_CFGS) / sizeof(ADJ_CFGS[0]);
 
 // Launchers of the templated trace kernels, one set per compiled (P, Q, NU).  adjoint_fp64 re-traces the queued
 // rays of logical blocks [first, first + nblocks) (queue and qcount as in TraceArgs, qbase 0) in double
-// precision; two: the blocks of point sources through two freeform faces (an instance of its own).
+// precision; mode: which kind of rays those blocks queued, each with an instance of its own: F64_FLAT (flat entry
+// face, exact root), F64_TWO (point sources through two freeform faces), F64_MESH (point sources on the mesh).
+constexpr int F64_FLAT = 0, F64_TWO = 1, F64_MESH = 2;
 struct KernelSet {
     hipError_t (*forward)(const TraceArgs&, int shape, int grid, hipStream_t);
     hipError_t (*adjoint)(const TraceArgs&, int shape, int grid, hipStream_t);
     hipError_t (*adjoint_fp64)(const TraceArgs&, const DesignDev64* d64, int shape, int64_t first, int64_t nblocks,
-                               bool two, hipStream_t);
+                               int mode, hipStream_t);
     hipError_t (*trace_rays)(const TraceArgs&, int design, const int64_t* ids, int64_t n, float* out8,
                              hipStream_t);
 };

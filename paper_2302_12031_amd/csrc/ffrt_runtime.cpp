@@ -362,11 +362,12 @@ ffrt_status launch_forward(ffrt_plan* pl, const float* Pz, bool stats, hipStream
 // same Pz must have filled.
 ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hipStream_t s, bool roots = false) {
     const AdjCfg& c = ADJ_CFGS[pl->adj_cfg];
-    // the rays of kernel groups 0, 1 and 5 (flat entry face; point sources through two freeform faces) whose
-    // derivative single precision cannot resolve are queued per logical block (group 1's blocks after group
-    // 0's, group 5's after those) and re-traced in double precision afterwards
-    const int64_t qb0 = pl->nblocks[c.shape][0], qb1 = pl->nblocks[c.shape][1], qb5 = pl->nblocks[c.shape][5];
-    const int64_t qblocks = qb0 + qb1 + qb5;
+    // the rays of kernel groups 0, 1, 5, 3 and 2 (flat entry face; point sources through two freeform faces; the
+    // mesh) whose derivative single precision cannot resolve are queued per logical block (in that order of the
+    // groups) and re-traced in double precision afterwards
+    const int64_t qb0 = pl->nblocks[c.shape][0], qb1 = pl->nblocks[c.shape][1], qb5 = pl->nblocks[c.shape][5],
+                  qb3 = pl->nblocks[c.shape][3], qb2 = pl->nblocks[c.shape][2];
+    const int64_t qblocks = qb0 + qb1 + qb5 + qb3 + qb2;
     for (int kg = 0; kg < N_KG; ++kg) {
         if (pl->nblocks[c.shape][kg] == 0) continue;
         TraceArgs A = make_args(pl, c.shape, kg);
@@ -376,11 +377,11 @@ ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hi
         A.gmax = pl->d_gmax();
         A.butterfly = c.butterfly;
         A.roots = roots && kg == 1 ? pl->d_roots() : nullptr;
-        if (kg == 0 || kg == 1 || kg == 5) {
+        if (kg != 4) {
             A.queue = pl->d_queue();
             A.qcount = pl->d_qcount();
             A.queue_tin = pl->d_qtin();
-            A.qbase = kg == 0 ? 0 : (kg == 1 ? qb0 : qb0 + qb1);
+            A.qbase = kg == 0 ? 0 : kg == 1 ? qb0 : kg == 5 ? qb0 + qb1 : kg == 3 ? qb0 + qb1 + qb5 : qb0 + qb1 + qb5 + qb3;
         }
         HIP_TRY(pl->ks->adjoint(A, c.shape, grid_for(pl, c.shape, kg, c.persistent), s));
     }
@@ -393,8 +394,10 @@ ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hi
         A.queue = pl->d_queue();
         A.qcount = pl->d_qcount();
         A.queue_tin = pl->d_qtin();
-        if (qb0 + qb1 > 0) HIP_TRY(pl->ks->adjoint_fp64(A, pl->d_d64(), c.shape, 0, qb0 + qb1, false, s));
-        if (qb5 > 0) HIP_TRY(pl->ks->adjoint_fp64(A, pl->d_d64(), c.shape, qb0 + qb1, qb5, true, s));
+        if (qb0 + qb1 > 0) HIP_TRY(pl->ks->adjoint_fp64(A, pl->d_d64(), c.shape, 0, qb0 + qb1, F64_FLAT, s));
+        if (qb5 > 0) HIP_TRY(pl->ks->adjoint_fp64(A, pl->d_d64(), c.shape, qb0 + qb1, qb5, F64_TWO, s));
+        if (qb3 + qb2 > 0)
+            HIP_TRY(pl->ks->adjoint_fp64(A, pl->d_d64(), c.shape, qb0 + qb1 + qb5, qb3 + qb2, F64_MESH, s));
     }
     return FFRT_OK;
 }

@@ -1090,6 +1090,7 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
 constexpr float FLAG_EDGE_PX = 5e-4f;   // landing within this many pixel widths of a pixel edge
 constexpr float FLAG_K_HIT = 1e-4f;     // a kept ray with k below this: derivative error above ~1e-3 of it
 constexpr float FLAG_K_TIR = 1e-5f;     // a ray dropped for TIR with k above -this may be kept in double
+constexpr float FLAG_TRI = 1e-4f;       // mesh: a hit within this many cell units of its triangle's edge
 
 __device__ __forceinline__ bool near_pixel_edge(float X, float R, float inv_w, int n) {
     const float px = (X + R) * inv_w;
@@ -1178,12 +1179,16 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
     }
     float qz = SEARCH ? r.oz + t * r.dz : (MESH ? mqz : S.h + B.zref);
     ExitState E = exit_face(D, qx, qy, qz, r.dx, r.dy, r.dz, S.hx, S.hy, r.w);
-    if constexpr ((KIND & 6) == 0 || KIND == 5) {
+    if constexpr (KIND != 4) {  // every kind but collimated rays through two freeform faces
         // a derivative single precision cannot resolve (see FLAG_EDGE_PX): enqueue() may take the ray for the
-        // double-precision re-trace (with its roots), which then makes the contribution instead of this sweep
-        const bool flag = E.status == ST_TIR ? E.k > -FLAG_K_TIR
-                                             : E.k < FLAG_K_HIT || near_pixel_edge(E.X, D.Rx, D.inv_wx, D.nx) ||
-                                                   near_pixel_edge(E.Y, D.Ry, D.inv_wy, D.ny);
+        // double-precision re-trace (with its roots), which then makes the contribution instead of this sweep.
+        // On the mesh the derivative also jumps where the hit crosses a triangle's edge (the slopes change).
+        bool flag = E.status == ST_TIR ? E.k > -FLAG_K_TIR
+                                       : E.k < FLAG_K_HIT || near_pixel_edge(E.X, D.Rx, D.inv_wx, D.nx) ||
+                                             near_pixel_edge(E.Y, D.Ry, D.inv_wy, D.ny);
+        if constexpr (MESH)
+            flag = flag || fminf(fminf(ma, mb), fminf(1.0f - ma, 1.0f - mb)) < FLAG_TRI ||
+                   fabsf(ma + mb - 1.0f) < FLAG_TRI;
         if (flag && !D.box && enqueue(t, ENTRY ? EH.t : 0.0f)) return false;
     }
     if (E.status != ST_HIT) return false;
@@ -1481,13 +1486,153 @@ __device__ inline int filter_axis_f64(double X, double R, double w, int n, doubl
     return i0;
 }
 
+// Surface and derivatives in double precision on a given span product (su, sv) at (x, y) (the mesh's normal is
+// the B-spline's on the hit triangle's span product).
+template <int P, int Q, bool D2>
+__device__ inline void surface_f64_on(const DesignDev& D, const DesignDev64& E, const float* __restrict__ Pz, double x,
+                                      double y, int su, int sv, SurfEval<P, Q, double>& S) {
+    S.ku = su;
+    S.kv = sv;
+    basis_f64<P, D2>(su, D.nsu, x * E.sxu + E.ubar0 - (double)su, S.Nu, S.dNu, S.d2Nu);
+    basis_f64<Q, D2>(sv, D.nsv, y * E.syv + E.vbar0 - (double)sv, S.Nv, S.dNv, S.d2Nv);
+    const float* row = Pz + D.cp_off + (int64_t)su * D.n_v + sv;
+    double h = 0.0, hu = 0.0, hv = 0.0, huu = 0.0, huv = 0.0, hvv = 0.0;
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+#pragma unroll
+        for (int b = 0; b <= Q; ++b) {
+            const double pz = (double)row[a * D.n_v + b];
+            r0 += S.Nv[b] * pz;
+            r1 += S.dNv[b] * pz;
+            if constexpr (D2) r2 += S.d2Nv[b] * pz;
+        }
+        h += S.Nu[a] * r0;
+        hu += S.dNu[a] * r0;
+        hv += S.Nu[a] * r1;
+        if constexpr (D2) {
+            huu += S.d2Nu[a] * r0;
+            huv += S.dNu[a] * r1;
+            hvv += S.Nu[a] * r2;
+        }
+    }
+    S.h = h;
+    S.hx = hu * E.sxu;
+    S.hy = hv * E.syv;
+    if constexpr (D2) {
+        S.hxx = huu * E.sxu * E.sxu;
+        S.hxy = huv * E.sxu * E.syv;
+        S.hyy = hvv * E.syv * E.syv;
+    }
+}
+
+// The hit of a ray on the triangle mesh in double precision, found near the single-precision hit t32 (a
+// collimated ray, d = (0, 0, 1), meets the mesh above its sample): the cell holding that hit first, then, while neither of a cell's triangles holds its plane's hit, the
+// neighbouring cell where the lower triangle's plane is met.  Triangles as in intersect_mesh, with the
+// partition's closed and open edges (the lower triangle's diagonal open, the upper one's right and upper edges
+// open but on the border of the net).  Out: t, the triangle (span product su, sv; upper), the hit's in-cell
+// coordinates (a, b), the triangle's slopes per cell unit (A, B) and the basis at the cell's node columns
+// and rows.
+template <int P, int Q>
+struct MeshHit64 {
+    double t, a, b, A, B;
+    int su, sv, upper;
+    double Nu0[P + 1], Nu1[P + 1], Nv0[Q + 1], Nv1[Q + 1];
+};
+
+template <int P, int Q>
+__device__ bool mesh_hit_f64(const DesignDev& D, const DesignDev64& E, const float* __restrict__ Pz, double ox,
+                             double oy, double oz, double dx, double dy, double dz, float t32, MeshHit64<P, Q>& M) {
+    const int MU = D.mesh_u, MV = D.mesh_v, NK = D.nsu * MU, NL = D.nsv * MV;
+    const double cu = (ox * E.sxu + E.ubar0) * MU, dcu = dx * E.sxu * MU;  // cell coordinates at t: cu + dcu t
+    const double cv = (oy * E.syv + E.vbar0) * MV, dcv = dy * E.syv * MV;
+    const double t0 = (double)t32;
+    int K = min(max((int)floor(cu + dcu * t0), 0), NK - 1), L = min(max((int)floor(cv + dcv * t0), 0), NL - 1);
+    double dn[(P > Q ? P : Q) + 1];
+    for (int it = 0; it < 8; ++it) {
+        const int su = K / MU, sv = L / MV;
+        basis_f64<P, false>(su, D.nsu, (double)(K - su * MU) / MU, M.Nu0, dn, nullptr);
+        basis_f64<P, false>(su, D.nsu, (double)(K - su * MU + 1) / MU, M.Nu1, dn, nullptr);
+        basis_f64<Q, false>(sv, D.nsv, (double)(L - sv * MV) / MV, M.Nv0, dn, nullptr);
+        basis_f64<Q, false>(sv, D.nsv, (double)(L - sv * MV + 1) / MV, M.Nv1, dn, nullptr);
+        const float* row = Pz + D.cp_off + (int64_t)su * D.n_v + sv;
+        double z00 = 0.0, z10 = 0.0, z01 = 0.0, z11 = 0.0;
+#pragma unroll
+        for (int a = 0; a <= P; ++a) {
+            double r0 = 0.0, r1 = 0.0;
+#pragma unroll
+            for (int b = 0; b <= Q; ++b) {
+                const double pz = (double)row[a * D.n_v + b];
+                r0 += M.Nv0[b] * pz;
+                r1 += M.Nv1[b] * pz;
+            }
+            z00 += M.Nu0[a] * r0;
+            z10 += M.Nu1[a] * r0;
+            z01 += M.Nu0[a] * r1;
+            z11 += M.Nu1[a] * r1;
+        }
+        const bool last_u = K == NK - 1, last_v = L == NL - 1;
+        const double a0 = cu - (double)K, b0 = cv - (double)L;
+        int mK = 0, mL = 0;
+        double t_up = -1.0, a_up = 0.0, b_up = 0.0;
+        for (int tri = 0; tri < 2; ++tri) {
+            const double A = tri ? z11 - z01 : z10 - z00, B = tri ? z11 - z10 : z01 - z00;
+            const double den = dz - A * dcu - B * dcv;
+            if (den == 0.0) continue;
+            const double num = tri ? z11 + A * (a0 - 1.0) + B * (b0 - 1.0) - oz : z00 + A * a0 + B * b0 - oz;
+            const double t = num / den, a = a0 + dcu * t, b = b0 + dcv * t;
+            const bool in = tri ? (a + b >= 1.0 && (a < 1.0 || (last_u && a <= 1.0)) && (b < 1.0 || (last_v && b <= 1.0)))
+                                : (a >= 0.0 && b >= 0.0 && a + b < 1.0);
+            if (in && t >= 0.0) {
+                M.t = t;
+                M.a = a;
+                M.b = b;
+                M.A = A;
+                M.B = B;
+                M.su = su;
+                M.sv = sv;
+                M.upper = tri;
+                return true;
+            }
+            if (tri == 0) {
+                mK = a < 0.0 ? -1 : (a >= 1.0 ? 1 : 0);
+                mL = b < 0.0 ? -1 : (b >= 1.0 ? 1 : 0);
+            } else {
+                t_up = t;
+                a_up = a;
+                b_up = b;
+            }
+        }
+        if (mK == 0 && mL == 0) {
+            // both planes met inside the cell, each on the other triangle's side: the ray crosses the fold at
+            // the diagonal, which belongs to the upper triangle
+            if (!(t_up >= 0.0)) return false;
+            M.t = t_up;
+            M.a = a_up;
+            M.b = b_up;
+            M.A = z11 - z01;
+            M.B = z11 - z10;
+            M.su = su;
+            M.sv = sv;
+            M.upper = 1;
+            return true;
+        }
+        K += mK;
+        L += mL;
+        if (K < 0 || K >= NK || L < 0 || L >= NL) return false;
+    }
+    return false;
+}
+
 // One queued ray in double precision: the whole trace from its sample (exact roots polished from the
 // single-precision ones by Newton steps on the double-precision surfaces) and the reverse sweep of
 // trace_adjoint.  Returns false when, in double precision, the ray does not reach the screen; else g[] holds
-// dL/dP of the exit net's control points (ku + a, kv + b) at a (Q+1) + b.  TWO: a point-source ray through a
-// lens whose entry face is freeform too (its entry root ti32 queued beside the exit root); gin[] then holds
-// dL/dP of the entry net's points (cku_in + a, ckv_in + b).
-template <int P, int Q, int NU, bool TWO = false>
+// dL/dP of the exit net's control points (ku + a, kv + b) at a (Q+1) + b.  MODE 0: flat entry face, exact
+// root.  MODE 1 (F64_TWO): a point-source ray through a lens whose entry face is freeform too (its entry root
+// ti32 queued beside the exit root); gin[] then holds dL/dP of the entry net's points (cku_in + a,
+// ckv_in + b).  MODE 2 (F64_MESH): a ray on the triangle mesh of sec. 2.2.2, whose hit triangle is found again
+// in double precision near the single-precision hit.
+template <int P, int Q, int NU, int MODE = F64_FLAT>
 __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, const float* __restrict__ Pz,
                                   const float* __restrict__ G, int64_t id, float t32, int& cku, int& ckv, double* g,
                                   float ti32 = 0.0f, int* cku_in = nullptr, int* ckv_in = nullptr,
@@ -1499,6 +1644,7 @@ __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, cons
     float x1f = 0.5f, x2f = 0.5f;
     if (D.jitter) two_uniforms(splitmix_at(D.rng_state0, (uint64_t)id), x1f, x2f);  // exact 24-bit values
     const double x1 = x1f, x2 = x2f;
+    constexpr bool TWO = MODE == F64_TWO, MESH = MODE == F64_MESH;
     const bool point = TWO || D.kind != 0;
     double ox, oy, oz, dx, dy, dz, w1;
     // (TWO) the source ray d0, the entry face at the entry hit (Si, unit normal m) and its refraction
@@ -1577,7 +1723,15 @@ __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, cons
     }
     SurfEval<P, Q, double> S;
     double t = 0.0, qx = ox, qy = oy, qz;
-    if (point) {
+    MeshHit64<P, Q> M;  // (MESH) the hit triangle
+    if (MESH) {
+        if (!mesh_hit_f64<P, Q>(D, E, Pz, ox, oy, oz, dx, dy, dz, t32, M)) return false;
+        t = M.t;
+        qx = ox + t * dx;
+        qy = oy + t * dy;
+        qz = oz + t * dz;
+        surface_f64_on<P, Q, true>(D, E, Pz, qx, qy, M.su, M.sv, S);
+    } else if (point) {
         t = (double)t32;
         for (int it = 0; it < 2; ++it) {  // from ~1e-6 relative: ~1e-12 after one step, rounding after two
             surface_f64<P, Q, false>(D, E, Pz, ox + t * dx, oy + t * dy, S);
@@ -1660,16 +1814,41 @@ __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, cons
     if (point) {
         const double tb = qxb * dx + qyb * dy + qzb * dz + hxb * (S.hxx * dx + S.hxy * dy) +
                           hyb * (S.hxy * dx + S.hyy * dy);
-        g0 = -tb / (S.hx * dx + S.hy * dy - dz);
+        // on the mesh f(t) = T(q(t)) - q_z(t), whose slope is the triangle's
+        const double fp = MESH ? M.A * E.sxu * D.mesh_u * dx + M.B * E.syv * D.mesh_v * dy - dz
+                               : S.hx * dx + S.hy * dy - dz;
+        g0 = -tb / fp;
     } else {
         g0 = qzb;
     }
     const double gx = hxb * E.sxu, gy = hyb * E.syv;
+    if constexpr (MESH) {
+        // the hit follows the triangle, whose corner heights carry the hit's barycentric weights l_c:
+        // dP_ab gets g0 (X0_a Nv0_b + X1_a Nv1_b) (as in trace_adjoint); the normal's terms are the B-spline's
+        double X0[P + 1], X1[P + 1];
 #pragma unroll
-    for (int a = 0; a <= P; ++a)
+        for (int a = 0; a <= P; ++a) {
+            if (M.upper) {
+                X0[a] = (1.0 - M.b) * M.Nu1[a];
+                X1[a] = (M.a + M.b - 1.0) * M.Nu1[a] + (1.0 - M.a) * M.Nu0[a];
+            } else {
+                X0[a] = (1.0 - M.a - M.b) * M.Nu0[a] + M.a * M.Nu1[a];
+                X1[a] = M.b * M.Nu0[a];
+            }
+        }
 #pragma unroll
-        for (int b = 0; b <= Q; ++b)
-            g[a * (Q + 1) + b] = S.Nu[a] * (g0 * S.Nv[b] + gy * S.dNv[b]) + gx * S.dNu[a] * S.Nv[b];
+        for (int a = 0; a <= P; ++a)
+#pragma unroll
+            for (int b = 0; b <= Q; ++b)
+                g[a * (Q + 1) + b] = g0 * (X0[a] * M.Nv0[b] + X1[a] * M.Nv1[b]) + S.Nu[a] * gy * S.dNv[b] +
+                                     gx * S.dNu[a] * S.Nv[b];
+    } else {
+#pragma unroll
+        for (int a = 0; a <= P; ++a)
+#pragma unroll
+            for (int b = 0; b <= Q; ++b)
+                g[a * (Q + 1) + b] = S.Nu[a] * (g0 * S.Nv[b] + gy * S.dNv[b]) + gx * S.dNu[a] * S.Nv[b];
+    }
     cku = S.ku;
     ckv = S.kv;
     if constexpr (TWO) {
@@ -1714,8 +1893,8 @@ __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, cons
 // device accumulator directly), which is then added to the device accumulator once: one atomic per touched
 // control point and round instead of one per ray.  Both sums are in the design's fixed-point unit, so the result
 // does not depend on which kernel adds them or in which order.
-// TWO: the instance for the segments of point sources through two freeform faces (seg0 on).
-template <int P, int Q, int NU, bool TWO>
+// MODE (F64_FLAT, F64_TWO, F64_MESH): the instance for the segments of one kind of queued rays (seg0 on).
+template <int P, int Q, int NU, int MODE>
 __global__ __launch_bounds__(WG) void k_adjoint_fp64(TraceArgs A, const DesignDev64* d64, int shape, int64_t seg0,
                                                      int64_t nseg) {
     constexpr int SPW = 64;  // segments per workgroup and round
@@ -1766,8 +1945,8 @@ __global__ __launch_bounds__(WG) void k_adjoint_fp64(TraceArgs A, const DesignDe
             const DesignDev64 E = d64[qd];
             double g[(P + 1) * (Q + 1)], gin[(P + 1) * (Q + 1)];
             int cku = 0, ckv = 0, cku_in = -1, ckv_in = -1;
-            if (!trace_adjoint_f64<P, Q, NU, TWO>(D, E, A.Pz, A.dLdI, q.id, q.t, cku, ckv, g,
-                                                  TWO ? A.queue_tin[qi] : 0.0f, &cku_in, &ckv_in, gin))
+            if (!trace_adjoint_f64<P, Q, NU, MODE>(D, E, A.Pz, A.dLdI, q.id, q.t, cku, ckv, g,
+                                                   MODE == F64_TWO ? A.queue_tin[qi] : 0.0f, &cku_in, &ckv_in, gin))
                 continue;
             const double inv_unit = ldexp(1.0, -fixed_point_exponent(A.gmax[qd], D.w0));
             unsigned long long* acc = qd == dmain ? sG : A.gacc + D.cp_off;
@@ -2373,7 +2552,7 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
         } else if (pend) {
             cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc, inv_unit);
         }
-        if constexpr ((KIND & 6) == 0 || KIND == 5) {
+        if constexpr (KIND != 4) {
             // the wave's queued rays of this block (its lanes' LDS atomics completed in order before this read)
             if (A.queue && lane == 0) {
                 A.qcount[(A.qbase + b) * 4 + wave] = min(s_qn[wave], qcap_w);
@@ -2488,17 +2667,26 @@ struct KernelsFor {
         return hipGetLastError();
     }
     static hipError_t adjoint_fp64(const TraceArgs& A, const DesignDev64* d64, int shape, int64_t first,
-                                   int64_t nblocks, bool two, hipStream_t s) {
+                                   int64_t nblocks, int mode, hipStream_t s) {
         const int64_t nseg = 4 * nblocks, seg0 = 4 * first;  // one segment per (logical block, wave)
         const int grid = (int)std::min<int64_t>((nseg + 63) / 64, 4096);
         if (grid <= 0) return hipSuccess;
         const size_t lds = sizeof(unsigned long long) * (size_t)A.lds_cp;  // the round design's control net(s)
-        if (two)
-            hipLaunchKernelGGL((k_adjoint_fp64<P, Q, NU, true>), dim3(grid), dim3(WG), lds, s, A, d64, shape, seg0,
-                               nseg);
-        else
-            hipLaunchKernelGGL((k_adjoint_fp64<P, Q, NU, false>), dim3(grid), dim3(WG), lds, s, A, d64, shape, seg0,
-                               nseg);
+        switch (mode) {
+            case F64_FLAT:
+                hipLaunchKernelGGL((k_adjoint_fp64<P, Q, NU, F64_FLAT>), dim3(grid), dim3(WG), lds, s, A, d64, shape,
+                                   seg0, nseg);
+                break;
+            case F64_TWO:
+                hipLaunchKernelGGL((k_adjoint_fp64<P, Q, NU, F64_TWO>), dim3(grid), dim3(WG), lds, s, A, d64, shape,
+                                   seg0, nseg);
+                break;
+            case F64_MESH:
+                hipLaunchKernelGGL((k_adjoint_fp64<P, Q, NU, F64_MESH>), dim3(grid), dim3(WG), lds, s, A, d64, shape,
+                                   seg0, nseg);
+                break;
+            default: return hipErrorInvalidValue;
+        }
         return hipGetLastError();
     }
     static hipError_t trace_rays(const TraceArgs& A, int design, const int64_t* ids, int64_t n, float* out8,

@@ -67,9 +67,11 @@ def test_mesh_forward_and_gradient_parity(name):
     if wl.num_rays <= 2 ** 20:
         L64, g64, _, _ = O.grad(p, Pz, T)
         assert abs(out["loss"][0] - L64) <= 1e-4 * L64
-        eg = assert_gradient(out["g"][0], g64, what=name, per_component=False)
+        # global and per-component bars; point-source rays at a kink of their derivative (a landing at a pixel
+        # edge, a hit at a triangle's edge) are re-traced in double precision
+        eg = assert_gradient(out["g"][0], g64, what=name)
         _, per, nbig = gradient_errors(out["g"][0], g64)
-        _say(f"[mesh] {name}: per-component error (reported) {per:.3g} over {nbig} components")
+        _say(f"[mesh] {name}: per-component error {per:.3g} over {nbig} components")
     _say(f"[mesh] {name}: irr worst err/tol {worst:.3g}, bright rel {rel:.2e}, grad rel {eg:.2e}")
 
 
