@@ -138,3 +138,43 @@ def test_two_face_steps_reduce_the_loss_and_count_thin_spots():
     stt = plan.new_stats()
     plan.forward(bad, stats=stt)
     assert int(plan.decode_stats(stt)[0]["n_constraint_viol"]) == 1
+
+
+def test_plan_with_every_retraced_group_matches_separate_plans():
+    """One plan holding a design of every kernel group: plano collimated and point, two-face collimated and
+    point, mesh collimated and point.  The groups whose kink rays go to the double-precision re-trace queue them
+    in segments of their own, one after another; each design's image, loss and gradient must equal its own
+    plan's, the image and gradient bit for bit (both are integer sums)."""
+    base = [
+        W.collimated_problem(160, 8, 48, jitter=1, seed=21, R=20.0, z=50.0),
+        W.point_problem(192, 12, 64, seed=22),
+    ]
+    probs, Pz, Ts = [], [], []
+    for k, p in enumerate(base):
+        P = W.random_heights(p.lens.n_u, p.lens.n_v, 40 + k)
+        T = W.target_mixture(p, 40 + k, 3, 3)
+        two = W.with_entry_freeform(W.Workload("x", [p], [P], [T]))
+        mesh = W.with_mesh(W.Workload("x", [p], [P], [T]), 2)
+        for wl in (W.Workload("x", [p], [P], [T]), two, mesh):
+            probs += wl.problems
+            Pz += wl.Pz
+            Ts += wl.targets
+    plan = ffrt.Plan(probs)
+    Pp, Tp = plan.pack_cp(Pz), plan.pack_img(Ts)
+    irr = plan.forward(Pp)
+    loss, dLdI = plan.loss(irr, Tp)
+    g = plan.adjoint(Pp, dLdI)
+    torch.cuda.synchronize()
+    irr_all, g_all = plan.unpack_img(irr.cpu().numpy()), plan.unpack_cp(g.cpu().numpy())
+    loss_all = loss.cpu().numpy()
+    for d, p in enumerate(probs):
+        one = ffrt.Plan([p])
+        P1, T1 = one.pack_cp([Pz[d]]), one.pack_img([Ts[d]])
+        i1 = one.forward(P1)
+        l1, dl1 = one.loss(i1, T1)
+        g1 = one.adjoint(P1, dl1)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(irr_all[d], one.unpack_img(i1.cpu().numpy())[0], err_msg=f"design {d}")
+        np.testing.assert_allclose(loss_all[d], l1.cpu().numpy()[0], rtol=1e-6)
+        np.testing.assert_array_equal(g_all[d], one.unpack_cp(g1.cpu().numpy())[0], err_msg=f"design {d}")
+    _say(f"[two faces] a plan of {len(probs)} designs over every kernel group matches separate plans bit for bit")
