@@ -1082,10 +1082,12 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
 // Rays whose pathwise derivative single precision cannot resolve.  The derivative of a ray's contribution
 // jumps where its landing crosses a pixel edge (for odd nu the filter's support edges are pixel edges, where
 // the filter is only continuous) or the screen edge, and it grows as 1 / sqrt(k) towards total internal
-// reflection.  A landing carries ~1e-5 pixel of single-precision error (at most ~1e-3 on the stated
-// workloads, 4e-4 for 1 ray in 10^4), so single precision may take the other side of such a kink.  The adjoint (flat entry face,
-// exact root) leaves these rays out and queues them; k_adjoint_fp64 re-traces them in double precision from
-// their samples and adds their contributions to the same fixed-point sums.
+// reflection; on the triangle mesh it also jumps where the hit crosses a triangle's edge.  A landing carries
+// ~1e-5 pixel of single-precision error (at most ~1e-3 on the stated workloads, 4e-4 for 1 ray in 10^4), so
+// single precision may take the other side of such a kink.  The adjoint (every kernel group but collimated rays
+// through two freeform faces, which meet the gradient bar without it) leaves these rays out and queues them;
+// k_adjoint_fp64 re-traces them in double precision from their samples and adds their contributions to the same
+// fixed-point sums.
 // ------------------------------------------------------------------------------------------------
 constexpr float FLAG_EDGE_PX = 5e-4f;   // landing within this many pixel widths of a pixel edge
 constexpr float FLAG_K_HIT = 1e-4f;     // a kept ray with k below this: derivative error above ~1e-3 of it
