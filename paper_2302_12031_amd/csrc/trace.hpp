@@ -2062,7 +2062,7 @@ __device__ __forceinline__ void splat_add(bool to_tile, uint32_t* tile, int tile
 }
 
 template <int P, int Q, int NU, int SHAPE, int KIND>
-__global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
+__device__ __forceinline__ void forward_body(TraceArgs A) {
     constexpr int MU = shape_mu(SHAPE), MV = shape_mv(SHAPE), RPT = MU * MV;
     constexpr int BU = 16 * MU, BV = 16 * MV;
     constexpr int H = (NU - 1) / 2;
@@ -2383,6 +2383,19 @@ __global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
     }
 }
 
+template <int P, int Q, int NU, int SHAPE, int KIND>
+__global__ __launch_bounds__(WG) void k_forward(TraceArgs A) {
+    forward_body<P, Q, NU, SHAPE, KIND>(A);
+}
+
+// The same with at least three waves per SIMD, for the point-source forward at 8 rays per thread: uncapped it
+// takes ~174 VGPRs (two waves); capped it fits 168 without a spill and runs faster than at 4 rays per thread
+// (its first, cold-started Newton search is one ray in 8 instead of one in 4).
+template <int P, int Q, int NU, int SHAPE, int KIND>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(3))) void k_forward_w3(TraceArgs A) {
+    forward_body<P, Q, NU, SHAPE, KIND>(A);
+}
+
 // ------------------------------------------------------------------------------------------------
 // Adjoint kernel
 // ------------------------------------------------------------------------------------------------
@@ -2631,7 +2644,12 @@ struct KernelsFor {
         size_t lds = trace_lds_bytes(A, A.use_tile ? TILE_CAP : 0);
         switch (A.kind_group) {
             case 0: hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 0>), dim3(grid), dim3(WG), lds, s, A); break;
-            case 1: hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 1>), dim3(grid), dim3(WG), lds, s, A); break;
+            case 1:
+                if constexpr (SHAPE == 3 && P == 3 && Q == 3 && NU == 3)
+                    hipLaunchKernelGGL((k_forward_w3<P, Q, NU, SHAPE, 1>), dim3(grid), dim3(WG), lds, s, A);
+                else
+                    hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 1>), dim3(grid), dim3(WG), lds, s, A);
+                break;
             case 2: hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 2>), dim3(grid), dim3(WG), lds, s, A); break;
             case 3: hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 3>), dim3(grid), dim3(WG), lds, s, A); break;
             case 4: hipLaunchKernelGGL((k_forward<P, Q, NU, SHAPE, 4>), dim3(grid), dim3(WG), lds, s, A); break;
