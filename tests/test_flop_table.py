@@ -38,7 +38,7 @@ def _per_ray(wl, kernel, iters, steps=None):
 
 def test_point_source_forward_and_adjoint_match_the_counters():
     wl = W.c4()
-    fwd, text = _counted("trace_kernels_c4_valu_counters.md", "ffrt::k_forward<3, 3, 3, 2, 1>")
+    fwd, text = _counted("trace_kernels_c4_valu_counters.md", "ffrt::k_forward_w3<3, 3, 3, 3, 1>")
     adj, _ = _counted("trace_kernels_c4_valu_counters.md", "ffrt::k_adjoint_w3<3, 3, 3, 1>")
     iters = float(re.search(r"\(([0-9.]+) Newton iterations per ray", text).group(1))
     t_fwd = _per_ray(wl, "forward", 0.0, [iters * wl.num_rays])
