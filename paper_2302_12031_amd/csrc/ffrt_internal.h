@@ -199,8 +199,9 @@ constexpr int N_ADJ_CFGS = sizeof(ADJ_CFGS) / sizeof(ADJ_CFGS[0]);
 // Launchers of the templated trace kernels, one set per compiled (P, Q, NU).  adjoint_fp64 re-traces the queued
 // rays of logical blocks [first, first + nblocks) (queue and qcount as in TraceArgs, qbase 0) in double
 // precision; mode: which kind of rays those blocks queued, each with an instance of its own: F64_FLAT (flat entry
-// face, exact root), F64_TWO (point sources through two freeform faces), F64_MESH (point sources on the mesh).
-constexpr int F64_FLAT = 0, F64_TWO = 1, F64_MESH = 2;
+// face, exact root), F64_TWO and F64_TWO_COLL (point sources and collimated rays through two freeform faces),
+// F64_MESH (the mesh).
+constexpr int F64_FLAT = 0, F64_TWO = 1, F64_MESH = 2, F64_TWO_COLL = 3;
 struct KernelSet {
     hipError_t (*forward)(const TraceArgs&, int shape, int grid, hipStream_t);
     hipError_t (*adjoint)(const TraceArgs&, int shape, int grid, hipStream_t);

@@ -362,12 +362,22 @@ ffrt_status launch_forward(ffrt_plan* pl, const float* Pz, bool stats, hipStream
 // same Pz must have filled.
 ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hipStream_t s, bool roots = false) {
     const AdjCfg& c = ADJ_CFGS[pl->adj_cfg];
-    // the rays of kernel groups 0, 1, 5, 3 and 2 (flat entry face; point sources through two freeform faces; the
-    // mesh) whose derivative single precision cannot resolve are queued per logical block (in that order of the
-    // groups) and re-traced in double precision afterwards
+    // the rays whose derivative single precision cannot resolve are queued per logical block, the groups' blocks
+    // in the order 0, 1 (flat entry face), 5, 4 (two freeform faces), 3, 2 (the mesh), and re-traced in double
+    // precision afterwards, one kernel instance per kind
     const int64_t qb0 = pl->nblocks[c.shape][0], qb1 = pl->nblocks[c.shape][1], qb5 = pl->nblocks[c.shape][5],
-                  qb3 = pl->nblocks[c.shape][3], qb2 = pl->nblocks[c.shape][2];
-    const int64_t qblocks = qb0 + qb1 + qb5 + qb3 + qb2;
+                  qb4 = pl->nblocks[c.shape][4], qb3 = pl->nblocks[c.shape][3], qb2 = pl->nblocks[c.shape][2];
+    const int64_t qblocks = qb0 + qb1 + qb5 + qb4 + qb3 + qb2;
+    auto qfirst = [&](int kg) -> int64_t {
+        switch (kg) {
+            case 0: return 0;
+            case 1: return qb0;
+            case 5: return qb0 + qb1;
+            case 4: return qb0 + qb1 + qb5;
+            case 3: return qb0 + qb1 + qb5 + qb4;
+            default: return qb0 + qb1 + qb5 + qb4 + qb3;  // group 2
+        }
+    };
     for (int kg = 0; kg < N_KG; ++kg) {
         if (pl->nblocks[c.shape][kg] == 0) continue;
         TraceArgs A = make_args(pl, c.shape, kg);
@@ -377,11 +387,11 @@ ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hi
         A.gmax = pl->d_gmax();
         A.butterfly = c.butterfly;
         A.roots = roots && kg == 1 ? pl->d_roots() : nullptr;
-        if (kg != 4) {
+        if (kg <= 5) {
             A.queue = pl->d_queue();
             A.qcount = pl->d_qcount();
             A.queue_tin = pl->d_qtin();
-            A.qbase = kg == 0 ? 0 : kg == 1 ? qb0 : kg == 5 ? qb0 + qb1 : kg == 3 ? qb0 + qb1 + qb5 : qb0 + qb1 + qb5 + qb3;
+            A.qbase = qfirst(kg);
         }
         HIP_TRY(pl->ks->adjoint(A, c.shape, grid_for(pl, c.shape, kg, c.persistent), s));
     }
@@ -395,9 +405,9 @@ ffrt_status launch_adjoint(ffrt_plan* pl, const float* Pz, const float* dLdI, hi
         A.qcount = pl->d_qcount();
         A.queue_tin = pl->d_qtin();
         if (qb0 + qb1 > 0) HIP_TRY(pl->ks->adjoint_fp64(A, pl->d_d64(), c.shape, 0, qb0 + qb1, F64_FLAT, s));
-        if (qb5 > 0) HIP_TRY(pl->ks->adjoint_fp64(A, pl->d_d64(), c.shape, qb0 + qb1, qb5, F64_TWO, s));
-        if (qb3 + qb2 > 0)
-            HIP_TRY(pl->ks->adjoint_fp64(A, pl->d_d64(), c.shape, qb0 + qb1 + qb5, qb3 + qb2, F64_MESH, s));
+        if (qb5 > 0) HIP_TRY(pl->ks->adjoint_fp64(A, pl->d_d64(), c.shape, qfirst(5), qb5, F64_TWO, s));
+        if (qb4 > 0) HIP_TRY(pl->ks->adjoint_fp64(A, pl->d_d64(), c.shape, qfirst(4), qb4, F64_TWO_COLL, s));
+        if (qb3 + qb2 > 0) HIP_TRY(pl->ks->adjoint_fp64(A, pl->d_d64(), c.shape, qfirst(3), qb3 + qb2, F64_MESH, s));
     }
     return FFRT_OK;
 }

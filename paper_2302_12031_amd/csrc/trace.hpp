@@ -1084,10 +1084,9 @@ __device__ __forceinline__ FwdRay trace_forward(const DesignDev& D, const Bounds
 // the filter is only continuous) or the screen edge, and it grows as 1 / sqrt(k) towards total internal
 // reflection; on the triangle mesh it also jumps where the hit crosses a triangle's edge.  A landing carries
 // ~1e-5 pixel of single-precision error (at most ~1e-3 on the stated workloads, 4e-4 for 1 ray in 10^4), so
-// single precision may take the other side of such a kink.  The adjoint (every kernel group but collimated rays
-// through two freeform faces, which meet the gradient bar without it) leaves these rays out and queues them;
-// k_adjoint_fp64 re-traces them in double precision from their samples and adds their contributions to the same
-// fixed-point sums.
+// single precision may take the other side of such a kink.  The adjoint (every kernel group) leaves these rays
+// out and queues them; k_adjoint_fp64 re-traces them in double precision from their samples and adds their
+// contributions to the same fixed-point sums.
 // ------------------------------------------------------------------------------------------------
 constexpr float FLAG_EDGE_PX = 5e-4f;   // landing within this many pixel widths of a pixel edge
 constexpr float FLAG_K_HIT = 1e-4f;     // a kept ray with k below this: derivative error above ~1e-3 of it
@@ -1181,7 +1180,7 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
     }
     float qz = SEARCH ? r.oz + t * r.dz : (MESH ? mqz : S.h + B.zref);
     ExitState E = exit_face(D, qx, qy, qz, r.dx, r.dy, r.dz, S.hx, S.hy, r.w);
-    if constexpr (KIND != 4) {  // every kind but collimated rays through two freeform faces
+    {
         // a derivative single precision cannot resolve (see FLAG_EDGE_PX): enqueue() may take the ray for the
         // double-precision re-trace (with its roots), which then makes the contribution instead of this sweep.
         // On the mesh the derivative also jumps where the hit crosses a triangle's edge (the slopes change).
@@ -1630,10 +1629,10 @@ __device__ bool mesh_hit_f64(const DesignDev& D, const DesignDev64& E, const flo
 // single-precision ones by Newton steps on the double-precision surfaces) and the reverse sweep of
 // trace_adjoint.  Returns false when, in double precision, the ray does not reach the screen; else g[] holds
 // dL/dP of the exit net's control points (ku + a, kv + b) at a (Q+1) + b.  MODE 0: flat entry face, exact
-// root.  MODE 1 (F64_TWO): a point-source ray through a lens whose entry face is freeform too (its entry root
-// ti32 queued beside the exit root); gin[] then holds dL/dP of the entry net's points (cku_in + a,
-// ckv_in + b).  MODE 2 (F64_MESH): a ray on the triangle mesh of sec. 2.2.2, whose hit triangle is found again
-// in double precision near the single-precision hit.
+// root.  MODE 1 (F64_TWO), 3 (F64_TWO_COLL): a point-source (collimated) ray through a lens whose entry face is
+// freeform too (a point-source ray's entry root ti32 queued beside the exit root; a collimated ray meets the
+// entry face above its sample); gin[] then holds dL/dP of the entry net's points (cku_in + a, ckv_in + b).  MODE 2 (F64_MESH): a ray on the triangle mesh of
+// sec. 2.2.2, whose hit triangle is found again in double precision near the single-precision hit.
 template <int P, int Q, int NU, int MODE = F64_FLAT>
 __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, const float* __restrict__ Pz,
                                   const float* __restrict__ G, int64_t id, float t32, int& cku, int& ckv, double* g,
@@ -1646,7 +1645,7 @@ __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, cons
     float x1f = 0.5f, x2f = 0.5f;
     if (D.jitter) two_uniforms(splitmix_at(D.rng_state0, (uint64_t)id), x1f, x2f);  // exact 24-bit values
     const double x1 = x1f, x2 = x2f;
-    constexpr bool TWO = MODE == F64_TWO, MESH = MODE == F64_MESH;
+    constexpr bool TWOC = MODE == F64_TWO_COLL, TWO = MODE == F64_TWO || TWOC, MESH = MODE == F64_MESH;
     const bool point = TWO || D.kind != 0;
     double ox, oy, oz, dx, dy, dz, w1;
     // (TWO) the source ray d0, the entry face at the entry hit (Si, unit normal m) and its refraction
@@ -1654,7 +1653,14 @@ __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, cons
     double d0x = 0.0, d0y = 0.0, d0z = 0.0, mx = 0.0, my = 0.0, mz = 0.0, inv_i = 0.0, ci = 0.0, ski = 1.0,
            betai = 0.0;
     const float* Pin = Pz + D.n_u * D.n_v;  // the entry net follows the exit net
-    if (!point) {
+    if constexpr (TWOC) {
+        // collimated through two freeform faces: the ray meets the entry face above its sample, along +z
+        ox = (2.0 * (((double)ku + x1) / (double)D.grid_u) - 1.0) * E.r_x;
+        oy = (2.0 * (((double)kv + x2) / (double)D.grid_v) - 1.0) * E.r_y;
+        d0z = 1.0;
+        surface_f64<P, Q, true>(D, E, Pin, ox, oy, Si);
+        oz = Si.h;
+    } else if (!point) {
         ox = (2.0 * (((double)ku + x1) / (double)D.grid_u) - 1.0) * E.r_x;
         oy = (2.0 * (((double)kv + x2) / (double)D.grid_v) - 1.0) * E.r_y;
         oz = E.z_in;
@@ -1690,23 +1696,7 @@ __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, cons
             oy = py + ti * d0y;
             oz = sz + ti * d0z;
             if (fabs(ox) > E.r_x || fabs(oy) > E.r_y) return false;
-            // refraction air -> glass at m = (-g_x, -g_y, 1) / |.|, Schlick with the air-side cosine
             surface_f64<P, Q, true>(D, E, Pin, ox, oy, Si);
-            inv_i = 1.0 / sqrt(Si.hx * Si.hx + Si.hy * Si.hy + 1.0);
-            mx = -Si.hx * inv_i;
-            my = -Si.hy * inv_i;
-            mz = inv_i;
-            ci = d0x * mx + d0y * my + d0z * mz;
-            ski = sqrt(fmax(1.0 - eta * eta * (1.0 - ci * ci), 1e-300));
-            betai = ski - eta * ci;
-            dx = eta * d0x + betai * mx;
-            dy = eta * d0y + betai * my;
-            dz = eta * d0z + betai * mz;
-            w1 = E.w0;
-            if (D.fresnel) {
-                const double m = 1.0 - ci, m2 = m * m;
-                w1 *= 1.0 - (E.R0 + (1.0 - E.R0) * m2 * m2 * m);
-            }
         } else {
             const double t0 = (E.z_in - E.pos_z) / cphi;
             ox = px + t0 * cth * sphi;
@@ -1721,6 +1711,25 @@ __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, cons
                 const double m = 1.0 - cphi, m2 = m * m;
                 w1 *= 1.0 - (E.R0 + (1.0 - E.R0) * m2 * m2 * m);
             }
+        }
+    }
+    if constexpr (TWO) {
+        // refraction air -> glass at the entry hit at m = (-g_x, -g_y, 1) / |.|, Schlick with the air-side cosine
+        const double eta = 1.0 / E.n_lens;
+        inv_i = 1.0 / sqrt(Si.hx * Si.hx + Si.hy * Si.hy + 1.0);
+        mx = -Si.hx * inv_i;
+        my = -Si.hy * inv_i;
+        mz = inv_i;
+        ci = d0x * mx + d0y * my + d0z * mz;
+        ski = sqrt(fmax(1.0 - eta * eta * (1.0 - ci * ci), 1e-300));
+        betai = ski - eta * ci;
+        dx = eta * d0x + betai * mx;
+        dy = eta * d0y + betai * my;
+        dz = eta * d0z + betai * mz;
+        w1 = E.w0;
+        if (D.fresnel) {
+            const double m = 1.0 - ci, m2 = m * m;
+            w1 *= 1.0 - (E.R0 + (1.0 - E.R0) * m2 * m2 * m);
         }
     }
     SurfEval<P, Q, double> S;
@@ -1872,10 +1881,11 @@ __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, cons
         const double nbx = betai * dbx + cib * d0x, nby = betai * dby + cib * d0y, nbz = betai * dbz + cib * d0z;
         const double nd = nbx * mx + nby * my + nbz * mz;
         const double gxb_i = -(nbx - nd * mx) * inv_i, gyb_i = -(nby - nd * my) * inv_i;
-        // ---- the entry hit moves along s + t_i d0 with g(s + t_i d0) = s_z + t_i d0_z
+        // ---- a point-source ray's entry hit moves along s + t_i d0 with g(s + t_i d0) = s_z + t_i d0_z; a
+        // collimated ray meets the face at fixed (x, y), so only its height moves
         const double pbx = obx + gxb_i * Si.hxx + gyb_i * Si.hxy, pby = oby + gxb_i * Si.hxy + gyb_i * Si.hyy;
         const double tbi = pbx * d0x + pby * d0y + obz * d0z;
-        const double c0 = -tbi / (Si.hx * d0x + Si.hy * d0y - d0z);
+        const double c0 = TWOC ? obz : -tbi / (Si.hx * d0x + Si.hy * d0y - d0z);
         const double gxi = gxb_i * E.sxu, gyi = gyb_i * E.syv;
 #pragma unroll
         for (int a = 0; a <= P; ++a)
@@ -1895,7 +1905,8 @@ __device__ bool trace_adjoint_f64(const DesignDev& D, const DesignDev64& E, cons
 // device accumulator directly), which is then added to the device accumulator once: one atomic per touched
 // control point and round instead of one per ray.  Both sums are in the design's fixed-point unit, so the result
 // does not depend on which kernel adds them or in which order.
-// MODE (F64_FLAT, F64_TWO, F64_MESH): the instance for the segments of one kind of queued rays (seg0 on).
+// MODE (F64_FLAT, F64_TWO, F64_TWO_COLL, F64_MESH): the instance for the segments of one kind of queued rays
+// (seg0 on).
 template <int P, int Q, int NU, int MODE>
 __global__ __launch_bounds__(WG) void k_adjoint_fp64(TraceArgs A, const DesignDev64* d64, int shape, int64_t seg0,
                                                      int64_t nseg) {
@@ -2567,7 +2578,7 @@ __device__ __forceinline__ void adjoint_body(const TraceArgs& A, int shape) {
         } else if (pend) {
             cp_flush_lane<P, Q, NV>(sG, D.n_v, aku, akv, acc, inv_unit);
         }
-        if constexpr (KIND != 4) {
+        {
             // the wave's queued rays of this block (its lanes' LDS atomics completed in order before this read)
             if (A.queue && lane == 0) {
                 A.qcount[(A.qbase + b) * 4 + wave] = min(s_qn[wave], qcap_w);
@@ -2704,6 +2715,10 @@ struct KernelsFor {
             case F64_MESH:
                 hipLaunchKernelGGL((k_adjoint_fp64<P, Q, NU, F64_MESH>), dim3(grid), dim3(WG), lds, s, A, d64, shape,
                                    seg0, nseg);
+                break;
+            case F64_TWO_COLL:
+                hipLaunchKernelGGL((k_adjoint_fp64<P, Q, NU, F64_TWO_COLL>), dim3(grid), dim3(WG), lds, s, A, d64,
+                                   shape, seg0, nseg);
                 break;
             default: return hipErrorInvalidValue;
         }

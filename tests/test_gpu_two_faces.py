@@ -64,8 +64,8 @@ def test_two_face_forward_and_gradient_parity(name):
     if grad:
         L64, g64, _, _ = O.grad(p, Pz, T)
         assert abs(out["loss"][0] - L64) <= 1e-4 * L64
-        # global and per-component bars; point-source rays at a kink of their derivative are re-traced in double
-        # precision through both faces, collimated ones stay in single precision and meet the bars as they are
+        # global and per-component bars; rays at a kink of their derivative are re-traced in double precision
+        # through both faces
         eg = assert_gradient(out["g"][0], g64, what=name)
         _, per, nbig = gradient_errors(out["g"][0], g64)
         _say(f"[two faces] {name}: per-component error {per:.3g} over {nbig} components")
@@ -89,8 +89,8 @@ def test_flat_entry_net_matches_the_plano_freeform_lens():
         for plan, wl, out, tag in ((plan_a, base, a, "plano"), (plan_b, two, b, "flat entry net")):
             mask, _, _ = flip_mask(plan, 0, plan.pack_cp(wl.Pz), wl.problems[0], wl.Pz[0], I64.shape, tag)
             assert_irradiance(out["irr"][0], I64, mask, what=f"{base.name} {tag}")
-        # both plans re-trace their point-source kink rays in double precision, but the flat entry net's root search
-        # and the plane hit round differently: the global bar
+        # both plans re-trace their kink rays in double precision, but the flat entry net's root search and the
+        # plane hit round differently: the global bar
         assert_gradient(b["g"][0][0], a["g"][0], what=base.name, per_component=False)
 
 
