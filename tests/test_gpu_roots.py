@@ -101,7 +101,8 @@ def test_batched_plan_root_slots_match_separate_plans():
         one.step(s1, one.pack_img([Ts[d]]))
         torch.cuda.synchronize()
         g1 = s1["dLdP"].cpu().numpy()
-        np.testing.assert_allclose(g_all[off[d]:off[d + 1]], g1, rtol=1e-4, atol=1e-5 * np.abs(g1).max())
+        # the gradient is an integer (fixed-point) sum: the same bits in either plan
+        np.testing.assert_array_equal(g_all[off[d]:off[d + 1]], g1, err_msg=f"design {d}")
         np.testing.assert_allclose(loss_all[d], s1["loss"].cpu().numpy()[0], rtol=1e-5)
     _say(f"[roots] batched plan of {len(probs)} designs matches separate plans")
 
