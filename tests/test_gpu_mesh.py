@@ -107,8 +107,9 @@ def test_plan_mixing_mesh_and_exact_designs():
     plan, out = _run(wl)
     for d, (w, i) in enumerate(designs):
         _, o1 = _run(W.Workload("one", [w.problems[i]], [w.Pz[i]], [w.targets[i]]))
-        np.testing.assert_allclose(out["irr"][d], o1["irr"][0], rtol=1e-5, atol=1e-6 * o1["irr"][0].max())
-        np.testing.assert_allclose(out["g"][d], o1["g"][0], rtol=1e-4, atol=1e-5 * np.abs(o1["g"][0]).max())
+        # image and gradient are integer (fixed-point) sums: the same bits in either plan
+        np.testing.assert_array_equal(out["irr"][d], o1["irr"][0], err_msg=f"design {d}")
+        np.testing.assert_array_equal(out["g"][d], o1["g"][0], err_msg=f"design {d}")
 
 
 def test_mesh_steps_reduce_the_loss():

@@ -140,8 +140,9 @@ def test_batched_plan_matches_separate_plans():
     for d in range(len(wl.problems)):
         single = W.Workload("one", [wl.problems[d]], [wl.Pz[d]], [wl.targets[d]])
         _, o1 = _run(single)
-        np.testing.assert_allclose(out["irr"][d], o1["irr"][0], rtol=1e-5, atol=1e-6 * o1["irr"][0].max())
-        np.testing.assert_allclose(out["g"][d], o1["g"][0], rtol=1e-4, atol=1e-5 * np.abs(o1["g"][0]).max())
+        # image and gradient are integer (fixed-point) sums: the same bits in either plan
+        np.testing.assert_array_equal(out["irr"][d], o1["irr"][0], err_msg=f"design {d}")
+        np.testing.assert_array_equal(out["g"][d], o1["g"][0], err_msg=f"design {d}")
         I64, _ = O.forward(wl.problems[d], wl.Pz[d])
         mask, _, _ = flip_mask(plan, d, plan.pack_cp(wl.Pz), wl.problems[d], wl.Pz[d], I64.shape, f"design {d}")
         assert_irradiance(out["irr"][d], I64, mask, what=f"design {d}", w_ray=1.0 / wl.problems[d].num_rays())
