@@ -126,7 +126,7 @@ ffrt_status validate(const ffrt_problem& pr, int idx) {
     if (L.p < 1 || L.q < 1 || L.p > MAX_DEG || L.q > MAX_DEG) return bad("degrees must be in [1, 5]");
     if (L.n_u <= L.p || L.n_v <= L.q) return bad("need more control points than the degree");
     if ((int64_t)L.n_u * L.n_v > MAX_CP || L.n_u - L.p > 64 || L.n_v - L.q > 64)
-        return bad("control net larger than 64 x 64");
+        return bad("control net above 4096 points or 64 knot spans along an axis");
     if (L.entry_freeform != 0 && L.entry_freeform != 1) return bad("entry_freeform must be 0 or 1");
     if (L.entry_freeform && (int64_t)L.n_u * L.n_v > 2048)
         return bad("a lens with two freeform faces allows at most 2048 control points per face");

@@ -92,9 +92,9 @@ def gradient_errors(g_gpu, g_64):
 
 
 # The per-component check needs exact decisions at the kinks of a ray's derivative (pixel and screen edges,
-# total internal reflection), which the double-precision re-trace gives the plano-freeform lens with the exact
-# root.  The triangle-mesh and two-face kernels keep single-precision decisions there: for them the global
-# bound is asserted and the per-component error reported.
+# total internal reflection, triangle edges), which the double-precision re-trace of the flagged rays gives every
+# kernel group.  per_component=False is for comparisons of two device paths that round differently (a plane hit
+# against a root search on a flat net), where only the global bound applies.
 def assert_gradient(g_gpu, g_64, rel=GRAD_REL, what="", per_component=True):
     e, per, n = gradient_errors(g_gpu, g_64)
     assert e <= rel, f"{what}: gradient error {e:.3g} of max |g| (tolerance {rel})"

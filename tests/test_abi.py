@@ -77,6 +77,22 @@ def test_plan_validation_rejects_bad_problems():
         ffrt.create_plan_handle([p, q])
 
 
+def test_plan_limits_on_the_control_net_and_empty_inputs():
+    """The largest nets are accepted (4096 points, 64 knot spans along an axis; 2048 per face with two freeform
+    faces) and one point past each limit is rejected, as are empty plans, grids and detectors."""
+    p = W.point_problem(64, 8, 64)
+    net = lambda n_u, n_v, ff=0: replace(p, lens=replace(p.lens, n_u=n_u, n_v=n_v, entry_freeform=ff))
+    for ok in (net(67, 61), net(64, 64), net(61, 67), net(64, 32, 1), net(32, 64, 1)):
+        assert ffrt.lib().ffrt_plan_destroy(ffrt.create_plan_handle([ok])) == 0
+    for bad in (net(65, 64), net(68, 60), net(60, 68)):
+        _bad(bad, "4096 points or 64 knot spans")
+    _bad(net(64, 33, 1), "2048 control points per face")
+    _bad(replace(p, source=replace(p.source, grid_u=0)), "sample grid")
+    _bad(replace(p, detector=replace(p.detector, n_x=0)), "detector resolution")
+    with pytest.raises(ffrt.FfrtError, match="at least one design"):
+        ffrt.create_plan_handle([])
+
+
 def test_plan_accepts_all_workloads_and_reports_layout():
     for wl in (W.c1(), W.c2(), W.c3(), W.c4(), W.c5()):
         h = ffrt.create_plan_handle(wl.problems)

@@ -1,0 +1,129 @@
+"""GPU: designs at the limits a plan accepts, through the C ABI, against the oracle.
+
+The largest control nets: a face holds at most 4096 control points and 64 knot spans per axis (its heights,
+knot tables and, when they fit, its span bounds sit in LDS); a lens with two freeform faces at most 2048 per
+face.  At these sizes the span bounds no longer fit beside the forward's tile, so point-source rays bracket
+their root with the design's global bounds alone and, the surface being steep on that scale, mostly take the
+sampled scan for the first sign change.  The smallest designs: a single ray, on a 3 x 3 detector.  Ray grids
+are odd so that the last block of each design is ragged.  The plans one control point past each limit are
+rejected on the host (test_abi)."""
+import sys
+from dataclasses import replace
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2302_12031_amd import ffrt
+from paper_2302_12031_amd import workloads as W
+from parity import MAX_MARGINAL, assert_gradient, assert_irradiance, flip_mask, gradient_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run(wl):
+    plan = ffrt.Plan(wl.problems)
+    Pz = plan.pack_cp(wl.Pz)
+    T = plan.pack_img(wl.targets)
+    st = plan.new_stats()
+    irr = plan.forward(Pz, stats=st)
+    loss, dLdI = plan.loss(irr, T)
+    g = plan.adjoint(Pz, dLdI)
+    torch.cuda.synchronize()
+    return plan, dict(irr=plan.unpack_img(irr.cpu().numpy()), loss=loss.cpu().numpy(),
+                      g=plan.unpack_cp(g.cpu().numpy()), stats=plan.decode_stats(st))
+
+
+def _net(p, n_u, n_v, seed, spread, mesh=0, entry_spread=None):
+    """Problem p on an n_u x n_v net (heights 2 +- spread, seeded), optionally on the triangle mesh or with a
+    freeform entry face (heights 0.5 +- entry_spread)."""
+    p = replace(p, lens=replace(p.lens, n_u=n_u, n_v=n_v))
+    if mesh:
+        p = replace(p, options=replace(p.options, mesh_u=mesh, mesh_v=mesh))
+    Pz = W.random_heights(n_u, n_v, seed, spread=spread)
+    wl = W.Workload(f"net{n_u}x{n_v}", [p], [Pz], [W.target_mixture(p, seed, 3, 3)])
+    if entry_spread is not None:
+        wl = W.with_entry_freeform(wl, seed=seed + 1, spread=entry_spread)
+    return wl
+
+
+# Heights +-0.1 on the ~0.16 mm control spacing of a 64-point axis keep the control polygon's slopes near
+# those of the 32 x 32 workloads (+-0.2 on ~0.34 mm); its curvature is about 2.5 times theirs, and so is the
+# landing error that single precision leaves per ray.  The per-pixel bar needs pixels that average many rays'
+# errors: the point-source cases land ~250 rays per pixel on a 64 x 64 detector.  On 128 x 128 (~64 rays per
+# pixel) the mesh case's bright pixels reach 1.3e-4: its 0.04 mm facets take their normals from differences of
+# single-precision vertex heights, which tilt a ray by ~1e-6 rad, ~1e-4 pixel at the screen.
+LARGEST = {
+    # 67 x 61 = 4087 control points, 64 knot spans along u: both per-axis limits and near the total
+    "point-67x61": lambda: _net(W.point_problem(1021, 8, 64, seed=5), 67, 61, 5, 0.1),
+    "collimated-64x64": lambda: _net(W.collimated_problem(1021, 8, 128, jitter=1, seed=6), 64, 64, 6, 0.1),
+    "twofaces-64x32": lambda: _net(W.point_problem(1021, 8, 128, seed=7), 64, 32, 7, 0.1, entry_spread=0.02),
+    "mesh4-64x64": lambda: _net(W.point_problem(1021, 8, 64, seed=8), 64, 64, 8, 0.1, mesh=4),
+}
+
+
+@pytest.mark.parametrize("name", list(LARGEST))
+def test_largest_control_nets_match_the_oracle(name):
+    """Irradiance per pixel, statistics, loss and gradient (global and per-component bars) at the largest
+    control nets, about a million rays each."""
+    wl = LARGEST[name]()
+    p, Pz, T = wl.problems[0], wl.Pz[0], wl.targets[0]
+    _say(f"[limits] {name}: {wl.num_rays} rays, {Pz.size} control heights")
+    plan, out = _run(wl)
+    I64, st64 = O.forward(p, Pz)
+    mask, n_flip, n_marg = flip_mask(plan, 0, plan.pack_cp(wl.Pz), p, Pz, I64.shape, name)
+    # the tolerance's floor is the weight of IRR_FLOOR_RAYS rays, as for the batch's sparse designs: on these
+    # nets the edge pixels of the detector collect a fraction of one ray's weight from filter tails
+    worst, rel = assert_irradiance(out["irr"][0], I64, mask, what=name, w_ray=1.0 / wl.num_rays)
+    s = out["stats"][0]
+    assert s["n_traced"] == st64["n_rays"]
+    assert st64["n_marginal"] <= MAX_MARGINAL * st64["n_rays"] + 5
+    assert abs(int(s["n_hit"]) - st64["n_hit"]) <= st64["n_marginal"] + 2
+    assert abs(float(s["flux_on_screen"]) - st64["flux_on_screen"]) <= 1e-4 * st64["flux_on_screen"]
+    L64, g64, _, _ = O.grad(p, Pz, T)
+    assert abs(out["loss"][0] - L64) <= 1e-4 * L64
+    eg = assert_gradient(out["g"][0], g64, what=name)
+    _, per, nbig = gradient_errors(out["g"][0], g64)
+    _say(f"[limits] {name}: irr worst err/tol {worst:.3g}, bright rel {rel:.2e}, masked {int(mask.sum())} "
+         f"(flipped {n_flip} of {n_marg} marginal); non-monotone rays {int(s['n_nonmonotone'])}; gradient "
+         f"{eg:.2e}, per component {per:.2e} over {nbig}")
+
+
+def _single_ray(kind, seed):
+    if kind == "collimated":
+        p = W.collimated_problem(1, 4, 3, jitter=1, seed=seed, R=6.0, z=30.0)
+    else:
+        p = W.point_problem(1, 4, 3, seed=seed, R=60.0, z=100.0)
+    Pz = W.random_heights(4, 4, seed, spread=0.3)
+    return p, Pz, W.target_mixture(p, seed, 3, 3)
+
+
+def test_single_ray_designs_match_the_oracle():
+    """Designs of one ray (one knot span, a 3 x 3 detector), alone and batched with a full-size design: the
+    image, loss and every gradient component against the oracle, and the batched plan equal to the separate
+    ones bit for bit."""
+    cases = [_single_ray(k, s) for k, s in (("collimated", 31), ("point", 32), ("point", 33))]
+    big = W.c1()
+    probs = [c[0] for c in cases] + big.problems
+    wl = W.Workload("single rays", probs, [c[1] for c in cases] + big.Pz, [c[2] for c in cases] + big.targets)
+    plan, out = _run(wl)
+    for d, (p, Pz, T) in enumerate(cases):
+        _, one = _run(W.Workload("one", [p], [Pz], [T]))
+        np.testing.assert_array_equal(out["irr"][d], one["irr"][0], err_msg=f"design {d}")
+        np.testing.assert_array_equal(out["g"][d], one["g"][0], err_msg=f"design {d}")
+        I64, st64 = O.forward(p, Pz)
+        assert st64["n_rays"] == 1 and out["stats"][d]["n_traced"] == 1
+        assert st64["n_marginal"] == 0
+        assert int(out["stats"][d]["n_hit"]) == st64["n_hit"] == 1, (d, st64)
+        np.testing.assert_allclose(out["irr"][d], I64, rtol=1e-4, atol=1e-4 * I64.max(), err_msg=f"design {d}")
+        L64, g64, _, _ = O.grad(p, Pz, T)
+        assert abs(out["loss"][d] - L64) <= 1e-4 * L64, (d, out["loss"][d], L64)
+        assert np.abs(g64).max() > 0
+        assert_gradient(out["g"][d], g64, what=f"single ray {d}")
+    _say(f"[limits] single rays: losses {out['loss'][:3].tolist()}")
