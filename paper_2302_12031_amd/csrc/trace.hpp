@@ -32,6 +32,25 @@ __device__ __forceinline__ float rcpf(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ double rcpd(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rcp_any(float x) { return rcpf(x); }
 __device__ __forceinline__ double rcp_any(double x) { return rcpd(x); }
+// Square root by the hardware instruction alone (within one ulp for the normal, non-negative arguments it gets
+// here: direction cosines and their squares), without the correction steps that round sqrtf correctly; those
+// cost a dozen instructions per call, three calls per ray.
+__device__ __forceinline__ float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// sin(pi r) and cos(pi r) for |r| <= 0.29 by their Taylor series about 0, through r^9 and r^10: the first
+// omitted terms, (pi r)^11 / 11! and (pi r)^12 / 12!, stay below 1e-8, a sixth of an ulp of the results.
+// Horner in r^2, a third of the instructions of the general sincospif with its own range reduction.
+constexpr double PI_D = 3.14159265358979323846;
+__device__ __forceinline__ void sincospi_reduced(float r, float& s, float& c) {
+    constexpr double p2 = PI_D * PI_D;
+    constexpr float s1 = (float)PI_D, s3 = (float)(-PI_D * p2 / 6.0), s5 = (float)(PI_D * p2 * p2 / 120.0),
+                    s7 = (float)(-PI_D * p2 * p2 * p2 / 5040.0), s9 = (float)(PI_D * p2 * p2 * p2 * p2 / 362880.0);
+    constexpr float c2 = (float)(-p2 / 2.0), c4 = (float)(p2 * p2 / 24.0), c6 = (float)(-p2 * p2 * p2 / 720.0),
+                    c8 = (float)(p2 * p2 * p2 * p2 / 40320.0), c10 = (float)(-p2 * p2 * p2 * p2 * p2 / 3628800.0);
+    const float r2 = r * r;
+    s = r * fmaf(fmaf(fmaf(fmaf(s9, r2, s7), r2, s5), r2, s3), r2, s1);
+    c = fmaf(fmaf(fmaf(fmaf(fmaf(c10, r2, c8), r2, c6), r2, c4), r2, c2), r2, 1.0f);
+}
 
 // SplitMix64 (Steele, Lea & Flood 2014) in counter form: output `index` of the sequence whose state starts
 // at state0 = mix(seed + stream * gamma).
@@ -282,7 +301,8 @@ __device__ __forceinline__ void sample_azimuth(int k, float xi, int S, float inv
     const int n = (int)rintf(4.0f * (float)k * inv_S);
     const float r = fmaf(2.0f * xi, inv_S, (float)(4 * k - n * S) * (0.5f * inv_S));
     float sr, cr;
-    sincospif(r, &sr, &cr);
+    if (S >= 64) sincospi_reduced(r, sr, cr);  // |r| < 1/4 + 2/S
+    else sincospif(r, &sr, &cr);
     const bool odd = (n & 1) != 0;
     const float a = odd ? cr : sr, b = odd ? sr : cr;
     s = (n & 2) ? -a : a;
@@ -335,7 +355,7 @@ __device__ __forceinline__ RayIn ray_entry(const DesignDev& D, int e, int ku, in
     float a = ((float)kv + x2) * D.inv_gv;
     float ao = a * D.omc;
     float cphi = 1.0f - ao;
-    float sphi = sqrtf(ao * (2.0f - ao));
+    float sphi = sqrt_hw(ao * (2.0f - ao));
     float px = D.pos_x, py = D.pos_y;
     if (D.kind == 2) {
         int ix = e / D.emit_ny, iy = e - ix * D.emit_ny;
@@ -356,7 +376,7 @@ __device__ __forceinline__ RayIn ray_entry(const DesignDev& D, int e, int ku, in
     float k = 1.0f - eta * eta * sphi * sphi;
     r.dx = eta * cth * sphi;
     r.dy = eta * sth * sphi;
-    r.dz = sqrtf(k);
+    r.dz = sqrt_hw(k);
     float w = D.w0;
     if (D.fresnel) {  // Schlick with the air-side cosine
         float m = 1.0f - cphi, m2 = m * m;
@@ -558,7 +578,7 @@ __device__ __forceinline__ RayIn ray_entry_ff(const DesignDev& D, const BoundsDe
         float sth, cth;
         sample_azimuth(ku, x1, D.grid_u, D.inv_gu, sth, cth);
         const float ao = ((float)kv + x2) * D.inv_gv * D.omc;
-        const float cphi = 1.0f - ao, sphi = sqrtf(ao * (2.0f - ao));
+        const float cphi = 1.0f - ao, sphi = sqrt_hw(ao * (2.0f - ao));
         float px = D.pos_x, py = D.pos_y;
         if (D.kind == 2) {
             int ix = e / D.emit_ny, iy = e - ix * D.emit_ny;
@@ -678,7 +698,7 @@ __device__ __forceinline__ RayIn ray_entry_ff(const DesignDev& D, const BoundsDe
     const float eta = rcpf(D.n_lens);
     const float c = H.d0x * nx + H.d0y * ny + H.d0z * nz;
     const float k = 1.0f - eta * eta * (1.0f - c * c);
-    const float beta = sqrtf(k) - eta * c;
+    const float beta = sqrt_hw(k) - eta * c;
     r.dx = eta * H.d0x + beta * nx;
     r.dy = eta * H.d0y + beta * ny;
     r.dz = eta * H.d0z + beta * nz;
@@ -892,7 +912,7 @@ __device__ __forceinline__ ExitState exit_face(const DesignDev& D, float qx, flo
         E.status = ST_TIR;
         return E;
     }
-    E.sk = sqrtf(k);
+    E.sk = sqrt_hw(k);
     E.beta = E.sk - n * E.c;
     E.ex = n * dx + E.beta * E.nxh;
     E.ey = n * dy + E.beta * E.nyh;
@@ -1322,7 +1342,7 @@ __device__ __forceinline__ bool trace_adjoint(const DesignDev& D, const BoundsDe
         const float mx = -Si.hx * inv_i, my = -Si.hy * inv_i, mz = inv_i;
         const float eta = rcpf(D.n_lens);
         const float ci = EH.d0x * mx + EH.d0y * my + EH.d0z * mz;
-        const float ski = sqrtf(fmaxf(1.0f - eta * eta * (1.0f - ci * ci), 1e-30f));
+        const float ski = sqrt_hw(fmaxf(1.0f - eta * eta * (1.0f - ci * ci), 1e-30f));
         const float betai = ski - eta * ci;
         float cib = (dbx * mx + dby * my + dbz * mz) * (eta * eta * ci / ski - eta);
         if (D.fresnel) {
