@@ -130,6 +130,33 @@ def test_per_ray_parity_full_size(name):
          f"(x throw), status mismatches on marginal rays {int((gpu[~clear, 0] != ref[~clear, 0]).sum())}")
 
 
+@pytest.mark.parametrize("strata", [63, 64, 65, 128])
+@pytest.mark.parametrize("faces", ["plano", "two faces"])
+def test_per_ray_parity_at_few_azimuth_strata(strata, faces):
+    """Every ray of the point source at few azimuth strata, where the reduced azimuth reaches its widest range
+    (|r| < 1/4 + 2/S half turns): from S = 64 on the kernels take sin and cos from their Taylor series, below it
+    from the general sincospi.  Landings against the oracle at the full-size bar."""
+    wl = W.c3(strata)
+    if faces == "two faces":
+        wl = W.with_entry_freeform(wl)
+    p, Pz = wl.problems[0], wl.Pz[0]
+    plan = ffrt.Plan(wl.problems)
+    ids = np.arange(wl.num_rays, dtype=np.int64)
+    gpu = plan.trace_rays(0, plan.pack_cp([Pz]), ids).cpu().numpy()
+    ref = O.trace_rays(p, Pz, ids)
+    clear = ref[:, 7] == 0
+    assert (gpu[clear, 0] == ref[clear, 0]).all()
+    hit = clear & (ref[:, 0] == O.HIT)
+    assert hit.sum() > 0.8 * len(ids)
+    scale = p.detector.z_screen * (1.0 + np.abs(ref[hit, 1:3]).max(1, keepdims=True) / p.detector.z_screen)
+    dxy = np.abs(gpu[hit, 1:3] - ref[hit, 1:3]) / scale
+    assert dxy.max() <= 2e-5, dxy.max()
+    assert np.median(dxy) <= 5e-7, np.median(dxy)
+    np.testing.assert_allclose(gpu[hit, 3], ref[hit, 3], rtol=2e-5)
+    _say(f"[per-ray] {faces}, {strata}^2 strata: {hit.sum()} hits, landing err max {dxy.max():.2e} median "
+         f"{np.median(dxy):.2e} (x throw)")
+
+
 def test_batched_plan_matches_separate_plans():
     full = W.c5()
     sel = [0, 1, 2, 3, 5, 8]
