@@ -51,7 +51,8 @@ typedef enum {
 
 /* Lens (sec. 2.1 - 2.1.2).  n_u = n_1 + 1 and n_v = n_2 + 1 control points, degrees p, q.  The aperture is
  * [-r_x, r_x] x [-r_y, r_y]; the flat entry face is z = z_in; delta_min is the minimal thickness used by
- * the constraint count (P^z >= z_in + delta_min).
+ * the constraint count (P^z >= z_in + delta_min).  A face holds at most 4096 control points and 64 knot spans
+ * along each axis (n_u - p <= 64, n_v - q <= 64); ffrt_plan_create returns FFRT_E_ARG beyond that.
  * entry_freeform = 1 makes the entry face a second B-spline height field on the same knots (the paper's
  * proposal for extended sources, sec. 3.3 and the conclusion): the design's control heights are then
  * 2 n_u n_v floats, the exit net followed by the entry net, and both are optimised.  Point-source rays meet
