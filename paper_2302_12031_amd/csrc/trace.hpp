@@ -430,11 +430,15 @@ __device__ RootOut intersect(const DesignDev& D, const BoundsDev& B, const float
     float pad = 4e-6f * (1.0f + fabsf(B.zmax - r.oz)) * inv_dz;
     float t_lo = fmaxf(0.0f, (B.zmin - r.oz) * inv_dz - pad);
     float t_hi = (B.zmax - r.oz) * inv_dz + pad;
+    // where the ray leaves the aperture prism, needed only when that happens before the bracket's top: the ray
+    // starts inside the prism, which is convex, so a point inside at t_hi keeps the whole bracket inside
     float t_ap = INFINITY;
-    if (r.dx > 0.0f) t_ap = fminf(t_ap, (D.r_x - r.ox) * rcpf(r.dx));
-    if (r.dx < 0.0f) t_ap = fminf(t_ap, (-D.r_x - r.ox) * rcpf(r.dx));
-    if (r.dy > 0.0f) t_ap = fminf(t_ap, (D.r_y - r.oy) * rcpf(r.dy));
-    if (r.dy < 0.0f) t_ap = fminf(t_ap, (-D.r_y - r.oy) * rcpf(r.dy));
+    if (!(fabsf(r.ox + t_hi * r.dx) < D.r_x && fabsf(r.oy + t_hi * r.dy) < D.r_y)) {
+        if (r.dx > 0.0f) t_ap = fminf(t_ap, (D.r_x - r.ox) * rcpf(r.dx));
+        if (r.dx < 0.0f) t_ap = fminf(t_ap, (-D.r_x - r.ox) * rcpf(r.dx));
+        if (r.dy > 0.0f) t_ap = fminf(t_ap, (D.r_y - r.oy) * rcpf(r.dy));
+        if (r.dy < 0.0f) t_ap = fminf(t_ap, (-D.r_y - r.oy) * rcpf(r.dy));
+    }
     float t_end = fminf(t_hi, t_ap);
     if (t_end < t_lo) {
         R.status = ST_SIDE_WALL;
@@ -802,11 +806,15 @@ __device__ MeshRoot intersect_mesh(const DesignDev& D, const BoundsDev& B, const
     const float pad = 4e-6f * (1.0f + fabsf(B.zmax - r.oz)) * inv_dz;
     const float t_lo = fmaxf(0.0f, (B.zmin - r.oz) * inv_dz - pad);
     const float t_hi = (B.zmax - r.oz) * inv_dz + pad;
+    // where the ray leaves the aperture prism, needed only when that happens before the bracket's top: the ray
+    // starts inside the prism, which is convex, so a point inside at t_hi keeps the whole bracket inside
     float t_ap = INFINITY;
-    if (r.dx > 0.0f) t_ap = fminf(t_ap, (D.r_x - r.ox) * rcpf(r.dx));
-    if (r.dx < 0.0f) t_ap = fminf(t_ap, (-D.r_x - r.ox) * rcpf(r.dx));
-    if (r.dy > 0.0f) t_ap = fminf(t_ap, (D.r_y - r.oy) * rcpf(r.dy));
-    if (r.dy < 0.0f) t_ap = fminf(t_ap, (-D.r_y - r.oy) * rcpf(r.dy));
+    if (!(fabsf(r.ox + t_hi * r.dx) < D.r_x && fabsf(r.oy + t_hi * r.dy) < D.r_y)) {
+        if (r.dx > 0.0f) t_ap = fminf(t_ap, (D.r_x - r.ox) * rcpf(r.dx));
+        if (r.dx < 0.0f) t_ap = fminf(t_ap, (-D.r_x - r.ox) * rcpf(r.dx));
+        if (r.dy > 0.0f) t_ap = fminf(t_ap, (D.r_y - r.oy) * rcpf(r.dy));
+        if (r.dy < 0.0f) t_ap = fminf(t_ap, (-D.r_y - r.oy) * rcpf(r.dy));
+    }
     const float t_end = fminf(t_hi, t_ap);
     if (t_end < t_lo) return R;
     const int NK = D.nsu * D.mesh_u, NL = D.nsv * D.mesh_v;
@@ -937,14 +945,16 @@ __device__ __forceinline__ ExitState exit_face(const DesignDev& D, float qx, flo
 // ------------------------------------------------------------------------------------------------
 // Gaussian reconstruction filter along one axis (sec. 2.3, filter eq.):
 //   f_i = exp(-alpha ((X - c_i)/w)^2) - exp(-alpha (nu/2)^2) inside the support, c_i = (i + 1/2) w - R,
-// window = the NU pixels centred on the landing pixel i0, pixels outside the grid excluded, normalised.
+// window = the NU pixels centred on the landing pixel i0, pixels outside the grid excluded, normalised (with
+// NORM = false the weights stay unnormalised and their sum goes to *Sout, so that a caller normalising the
+// product of two axes takes one reciprocal instead of two).
 // F[m] is the weight of pixel i0 - (NU-1)/2 + m; dF[m] = dF/dX.  With box (the simplest reconstruction of
 // sec. 2.3, the indicator of the pixel) the window holds the landing pixel alone, with weight 1 and no
 // derivative.
 // ------------------------------------------------------------------------------------------------
-template <int NU, bool DERIV>
+template <int NU, bool DERIV, bool NORM = true>
 __device__ __forceinline__ int filter_axis(float X, float R, float w, float inv_w, int n, float alpha,
-                                           float edge, float* F, float* dF, bool box) {
+                                           float edge, float* F, float* dF, bool box, float* Sout = nullptr) {
     constexpr int H = (NU - 1) / 2;
     int i0 = (int)floorf((X + R) * inv_w);
     i0 = min(max(i0, 0), n - 1);
@@ -954,6 +964,7 @@ __device__ __forceinline__ int filter_axis(float X, float R, float w, float inv_
             F[m] = m == H ? 1.0f : 0.0f;
             if constexpr (DERIV) dF[m] = 0.0f;
         }
+        if constexpr (!NORM) *Sout = 1.0f;
         return i0;
     }
     float c0 = ((float)i0 + 0.5f) * w - R;
@@ -976,6 +987,10 @@ __device__ __forceinline__ int filter_axis(float X, float R, float w, float inv_
             F[m] = (i >= 0) && (i < n) ? fmaxf(e - edge, 0.0f) : 0.0f;
         }
         S += F[m];
+    }
+    if constexpr (!NORM) {
+        *Sout = S;
+        return i0;
     }
     float invS = rcpf(S);
 #pragma unroll
@@ -2281,20 +2296,19 @@ __device__ __forceinline__ void forward_body(TraceArgs A) {
                     if (W[r] == 0.0f) continue;
                     float xr = X[r], yr = Y[r];
                     if (npass > 1) asm volatile("" : "+v"(xr), "+v"(yr));
-                    float Fx[NU], Fy[NU];
-                    const int di =
-                        filter_axis<NU, false>(xr, D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr, D.box) -
-                        H - ai;
-                    const int dj =
-                        filter_axis<NU, false>(yr, D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr, D.box) -
-                        H - aj;
+                    float Fx[NU], Fy[NU], Sx, Sy;
+                    const int di = filter_axis<NU, false, false>(xr, D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x,
+                                                                 Fx, nullptr, D.box, &Sx) - H - ai;
+                    const int dj = filter_axis<NU, false, false>(yr, D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y,
+                                                                 Fy, nullptr, D.box, &Sy) - H - aj;
+                    const float Wn = W[r] * rcpf(Sx * Sy);
                     if (di > SLACK || dj > SLACK) {
 #pragma unroll
                         for (int a = 0; a < NU; ++a) {
                             if (!in_slab(ai + di + a)) continue;
 #pragma unroll
                             for (int bb = 0; bb < NU; ++bb) {
-                                const float v = W[r] * Fx[a] * Fy[bb];
+                                const float v = Wn * Fx[a] * Fy[bb];
                                 if (v != 0.0f)
                                     splat_add<TSH>(use_tile, mytile, tw, r0, jlo, D.fx_scale, img, D.ny, ai + di + a,
                                                    aj + dj + bb, v);
@@ -2306,7 +2320,7 @@ __device__ __forceinline__ void forward_body(TraceArgs A) {
                     used_c = max(used_c, dj);
                     // add the NU x NU window at offset (di, dj) in [0, SLACK]^2 without indexing registers
                     // dynamically
-                    const float wr = W[r] * wsc;
+                    const float wr = Wn * wsc;
                     float fx[WN], fy[WN];
 #pragma unroll
                     for (int k = 0; k < WN; ++k) {
@@ -2351,17 +2365,18 @@ __device__ __forceinline__ void forward_body(TraceArgs A) {
                     if (W[r] == 0.0f) continue;
                     float xr = X[r], yr = Y[r];
                     if (npass > 1) asm volatile("" : "+v"(xr), "+v"(yr));
-                    float Fx[NU], Fy[NU];
-                    const int i0 =
-                        filter_axis<NU, false>(xr, D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x, Fx, nullptr, D.box);
-                    const int j0 =
-                        filter_axis<NU, false>(yr, D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y, Fy, nullptr, D.box);
+                    float Fx[NU], Fy[NU], Sx, Sy;
+                    const int i0 = filter_axis<NU, false, false>(xr, D.Rx, D.wx, D.inv_wx, D.nx, D.alpha, D.edge_x,
+                                                                 Fx, nullptr, D.box, &Sx);
+                    const int j0 = filter_axis<NU, false, false>(yr, D.Ry, D.wy, D.inv_wy, D.ny, D.alpha, D.edge_y,
+                                                                 Fy, nullptr, D.box, &Sy);
+                    const float Wn = W[r] * rcpf(Sx * Sy);
                     if (use_tile) {
                         // the tile holds every row and column of the window (pixels off the image get zero
                         // weights, which the flush skips): nine adds without a test, rows outside the slab aside.
                         // Tile offsets fit 24-bit products; the weights are >= 0, so adding one half and
                         // truncating rounds them to the nearest unit.
-                        const float wr = W[r] * (D.fx_scale * (1.0f / (float)(1 << TSH)));
+                        const float wr = Wn * (D.fx_scale * (1.0f / (float)(1 << TSH)));
                         const int base = __mul24(i0 - H - r0, tw) + (j0 - H - jlo);
 #pragma unroll
                         for (int a = 0; a < NU; ++a) {
@@ -2384,7 +2399,7 @@ __device__ __forceinline__ void forward_body(TraceArgs A) {
                             const int j = j0 + bb - H;
                             if (j < 0 || j >= D.ny) continue;
                             splat_add<TSH>(false, mytile, tw, r0, jlo, D.fx_scale, img, D.ny, i, j,
-                                           W[r] * Fx[a] * Fy[bb]);
+                                           Wn * Fx[a] * Fy[bb]);
                         }
                     }
                 }
