@@ -127,3 +127,63 @@ def test_single_ray_designs_match_the_oracle():
         assert np.abs(g64).max() > 0
         assert_gradient(out["g"][d], g64, what=f"single ray {d}")
     _say(f"[limits] single rays: losses {out['loss'][:3].tolist()}")
+
+
+# Footprints beyond the forward's LDS tile (6144 pixels): with few samples on a fine detector a workgroup's rays
+# land far apart (from the oracle's landings, a block of 16 x 16 samples, the smallest, spans ~130 x 145 pixels on
+# the 1024 detector, ~230 x 280 on the collimated 2048 one, ~270 x 220 on the 8192 one).  Point-source blocks are
+# then splatted in slabs of whole rows, one pass each; collimated blocks add to the device image directly.  The
+# largest detector (8192 x 8192, a 512 MiB fixed-point image) spans +-410 mm, a 0.1 mm pitch: per-pixel parity at
+# 1e-4 needs single-precision landings (up to ~1e-4 mm at this throw) well inside a pixel, which a 0.02 mm pitch
+# with about one ray per pixel does not give (there 12 pixels reached 1.15 of the tolerance).
+WIDE = {
+    "point-128x128-det1024-slabs": lambda: W.point_problem(128, 8, 1024, seed=41),
+    "collimated-64x64-det2048-direct": lambda: W.collimated_problem(64, 8, 2048, jitter=1, seed=42),
+    "point-97x97-det8192-largest": lambda: W.point_problem(97, 8, 8192, seed=43, R=410.0),
+}
+
+
+@pytest.mark.parametrize("name", list(WIDE))
+def test_wide_footprints_and_the_largest_detector(name):
+    """Every forward kernel shape on footprints beyond the LDS tile: irradiance per pixel against the oracle (the
+    floor of IRR_FLOOR_RAYS ray weights applies: pixels hold a few rays), flux and hit counts.
+
+    The gradient is reported, not asserted.  These splats are sparse (a ray's window mostly holds its own weight),
+    and their gradient is a sum of per-pixel terms dL/dI dI/dP that cancel to 1/30 - 1/400 of their absolute sum
+    (1/1.5 - 1/6 on the stated workloads); the oracle's gradient agrees with central differences to 1e-6 here.
+    Each ray's filter derivative carries its single-precision landing error relative to the pixel pitch, and the
+    cancellation multiplies that: on the same point source with 128^2 strata the adjoint on the oracle's dL/dI is
+    off by 6.8e-3 of max |g| on a 1024^2 detector (cancellation 393), 4.6e-5 on 256^2 (21) and 2.1e-6 on 128^2
+    (4.2); with 2048^2 strata on 1024^2, 1.6e-5 (8.5).  The adjoint kernels have no footprint-dependent path;
+    their parity is held on the workloads and the other cases here."""
+    p = WIDE[name]()
+    seed = p.source.seed
+    Pz = W.random_heights(p.lens.n_u, p.lens.n_v, seed)
+    wl = W.Workload(name, [p], [Pz], [W.target_mixture(p, seed, 3, 3)])
+    I64, st64 = O.forward(p, Pz)
+    _say(f"[limits] {name}: {wl.num_rays} rays, detector {p.detector.n_x}^2, oracle hits {st64['n_hit']}")
+    names = ffrt.Plan.config_names(0)
+    for c, nm in enumerate(names):
+        plan = ffrt.Plan(wl.problems)
+        plan.set_config(0, c)
+        Pd = plan.pack_cp(wl.Pz)
+        st = plan.new_stats()
+        irr = plan.forward(Pd, stats=st)
+        torch.cuda.synchronize()
+        I = plan.unpack_img(irr.cpu().numpy())[0]
+        s = plan.decode_stats(st)[0]
+        assert s["n_traced"] == wl.num_rays
+        assert abs(int(s["n_hit"]) - st64["n_hit"]) <= st64["n_marginal"] + 2, nm
+        assert abs(float(s["flux_on_screen"]) - st64["flux_on_screen"]) <= 1e-4 * st64["flux_on_screen"], nm
+        mask, _, _ = flip_mask(plan, 0, Pd, p, Pz, I64.shape, f"{name} {nm}")
+        worst, _ = assert_irradiance(I, I64, mask, what=f"{name} {nm}", w_ray=1.0 / wl.num_rays)
+        _say(f"[limits] {name} {nm}: irr worst err/tol {worst:.3g}")
+        del irr, I
+    plan, out = _run(wl)
+    L64, g64, _, G64 = O.grad(p, Pz, wl.targets[0])
+    assert abs(out["loss"][0] - L64) <= 1e-4 * L64
+    g_vjp = plan.unpack_cp(plan.adjoint(plan.pack_cp(wl.Pz), plan.pack_img([G64])).cpu().numpy())[0]
+    e_end, per_end, nbig = gradient_errors(out["g"][0], g64)
+    e_vjp, per_vjp, _ = gradient_errors(g_vjp, g64)
+    _say(f"[limits] {name}: gradient (reported) end to end {e_end:.2e} of max |g|, per component {per_end:.2e} "
+         f"over {nbig}; adjoint on the oracle's dL/dI {e_vjp:.2e}, per component {per_vjp:.2e}")
