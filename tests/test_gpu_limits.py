@@ -150,7 +150,7 @@ def test_wide_footprints_and_the_largest_detector(name):
 
     The gradient is reported, not asserted.  These splats are sparse (a ray's window mostly holds its own weight),
     and their gradient is a sum of per-pixel terms dL/dI dI/dP that cancel to 1/30 - 1/400 of their absolute sum
-    (1/1.5 - 1/6 on C1 and on the C3 geometry at 512^2 strata); on the first two cases the oracle's gradient agrees with central
+    (1/1.5 - 1/6.3 on the workloads C1 - C4); on the first two cases the oracle's gradient agrees with central
     differences (h = 1e-7) to 2e-6 of max |g| on its six largest components.
     Each ray's filter derivative carries its single-precision landing error relative to the pixel pitch, and the
     cancellation multiplies that: on the same point source with 128^2 strata the adjoint on the oracle's dL/dI is
